@@ -1,0 +1,181 @@
+/*
+ * msc.h -- multishift conjugate gradient on MI355X (gfx950), C ABI.
+ *
+ * Solves the family of shifted systems (A + sigma_k I) x_k = b, k = 0..ns-1, for a
+ * sparse Hermitian positive-definite A (paper: Section 2, eq. linprob) with one Krylov
+ * sequence shared by all shifts (Section 2, Algorithm 1, with the shifted constants
+ * re-derived from the collinearity of the shifted residuals).  A is either M^H M for a
+ * caller-supplied complex sparse M (the lattice fermion case) or given directly.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Complex numbers are interleaved (re, im) pairs of doubles: a "complex128 array of
+ *   length n" is 2n doubles.  Device pointers are HIP device addresses (for example a
+ *   torch tensor's data_ptr()); host pointers are ordinary host memory.
+ * - `stream` is a hipStream_t passed as void*; NULL means the null stream.  Every call
+ *   is stream-ordered with respect to the caller's other work on that stream; calls
+ *   that return results to the host (status, info) synchronise that stream.
+ * - The caller owns every buffer it passes and keeps it alive for the duration of the
+ *   call.  The library owns everything reachable from an msc_op and frees it in
+ *   msc_op_destroy.
+ * - No call throws.  Each returns an msc_status; on failure msc_last_error() returns a
+ *   thread-local message describing the last failure of the calling thread.
+ * - An msc_op is not thread safe: one call at a time per op.
+ */
+#ifndef MSC_H
+#define MSC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct msc_op_s* msc_op;  /* opaque operator handle, library-owned */
+typedef void* msc_stream;         /* a hipStream_t */
+
+typedef enum {
+    MSC_OK = 0,
+    MSC_ENOTCONV = 1,      /* result written, tolerance not reached within max_iter   */
+    MSC_EINVAL = -1,       /* invalid argument (null pointer, size, CSR structure)    */
+    MSC_ENOMEM = -2,       /* device or host allocation failed                        */
+    MSC_EHIP = -3,         /* a HIP runtime call failed                                */
+    MSC_EBREAKDOWN = -4    /* p^H (A + sigma_0) p <= 0 or NaN: A + sigma_min not PD    */
+} msc_status;
+
+typedef enum {
+    MSC_A_MHM = 0,         /* the caller passes M; A = M^H M                           */
+    MSC_A_HERM = 1         /* the caller passes A itself (Hermitian positive definite) */
+} msc_op_kind;
+
+typedef enum {
+    MSC_PREC_FP64 = 0,     /* complex128 storage and arithmetic throughout            */
+    MSC_PREC_MIXED = 1     /* complex64 operator and Krylov vectors, FP64 reductions,
+                              FP64 shift recurrences, complex128 solutions, FP64
+                              reliable updates and per-shift FP64 refinement          */
+} msc_prec;
+
+/* Solver parameters; fill with msc_params_default() and override fields. */
+typedef struct {
+    double tol;              /* relative residual target |b-(A+s_k)x_k| <= tol |b|  (1e-10) */
+    int32_t max_iter;        /* iteration limit of the multishift sequence           (10000) */
+    int32_t prec;            /* msc_prec                                     (MSC_PREC_FP64) */
+    int32_t reliable_every;  /* mixed: FP64 true-residual replacement period        (50)    */
+    int32_t freeze;          /* stop updating shifts whose residual has converged    (1)    */
+    int32_t refine;          /* mixed: refine shifts above tol after the sequence   (1)    */
+    int32_t poll_every;      /* iterations queued between host convergence polls    (16)   */
+    double inner_tol;        /* mixed: relative tolerance that ends the multishift
+                                sequence before refinement takes over              (1e-7) */
+    int32_t refine_max_iter; /* iteration limit of each refinement system          (10000) */
+    int32_t lanes;           /* lanes per CSR row, 0 = automatic                    (0)    */
+    int32_t verify;          /* compute FP64 true residuals at the end              (1)    */
+    int32_t reserved[5];
+} msc_params;
+
+/* Per-solve report.  Array members are caller-owned host arrays of length ns (or
+ * NULL when not wanted), indexed in the caller's shift order. */
+typedef struct {
+    int32_t iters;           /* multishift iterations performed                         */
+    int32_t refine_iters;    /* refinement iterations (max over refined shifts)         */
+    int32_t n_reliable;      /* reliable updates performed                              */
+    int32_t n_refined;       /* shifts that needed refinement                           */
+    double* true_rel_res;    /* [ns] |b - (A+sigma_k) x_k| / |b| in FP64                */
+    int32_t* freeze_iter;    /* [ns] iteration at which shift k froze, -1 if never      */
+    double seconds;          /* wall time of the call                                   */
+    double alg_bytes;        /* algorithmic HBM bytes moved by the call's kernels       */
+    double reserved[4];
+} msc_info;
+
+/* Fill *p with the defaults listed above. */
+void msc_params_default(msc_params* p);
+
+/* Library version string. */
+const char* msc_version(void);
+
+/* Message describing the calling thread's last failure ("" if none). */
+const char* msc_last_error(void);
+
+/*
+ * Create an operator from a CSR matrix held in device memory (Fig. 1 of the paper
+ * builds the matrix, copies it to the device, then calls the solver; here the CSR is
+ * already resident).  For MSC_A_MHM the matrix is M and the library builds M^H
+ * (conjugate transpose with sorted columns) on the device; for MSC_A_HERM it is A.
+ *   d_rowptr : int64[n+1], non-decreasing, d_rowptr[0] = 0, d_rowptr[n] = nnz
+ *   d_col    : int32[nnz], each in [0, n)
+ *   d_vals   : complex128[nnz] (2*nnz doubles)
+ * The arrays are copied; the caller may free them after the call returns.  The
+ * structure is validated on the device (MSC_EINVAL on violation).  n >= 1 and
+ * nnz < 2^31 are required.
+ */
+msc_status msc_op_create_csr(msc_op* out, int32_t kind, int64_t n, int64_t nnz,
+                             const int64_t* d_rowptr, const int32_t* d_col,
+                             const double* d_vals, msc_stream stream);
+
+/* Replace the values of the operator's matrix (same pattern, same entry order as at
+ * creation, complex128[nnz] on the device) -- for example after new gauge links. */
+msc_status msc_op_update_values(msc_op op, const double* d_vals, msc_stream stream);
+
+/* Set the shifts sigma_k (host array, any order, duplicates allowed, 1 <= ns <= 64).
+ * The smallest shift drives the Krylov sequence; A + sigma_min must be positive
+ * definite. */
+msc_status msc_op_set_shifts(msc_op op, const double* h_sigma, int32_t ns);
+
+/* Query the operator: any output pointer may be NULL. */
+msc_status msc_op_query(msc_op op, int64_t* n, int64_t* nnz, int32_t* ns, int32_t* kind);
+
+/*
+ * Apply the operator (no solve): d_out = (A + shift I) d_in for complex128 vectors of
+ * length n in device memory, computed with the FP64 (prec = MSC_PREC_FP64) or the
+ * complex64 (prec = MSC_PREC_MIXED, inputs and outputs still complex128) copy of the
+ * matrix.  This is the matrix-vector product of Algorithm 1 on its own.
+ */
+msc_status msc_op_apply(msc_op op, int32_t prec, const double* d_in, double* d_out,
+                        double shift, msc_stream stream);
+
+/*
+ * The multishift solve (Algorithm 1).  d_b: complex128[n]; d_x: complex128[ns*n],
+ * shift-major (x_k occupies d_x[2*k*n .. 2*(k+1)*n)) in the caller's shift order.
+ * x starts from zero (the method requires it).  Blocks until done.  Returns MSC_OK when
+ * every shift meets tol (with verify on: in FP64 true residual), MSC_ENOTCONV when
+ * not (x still holds the final iterates and info is filled), MSC_EBREAKDOWN on a
+ * breakdown.  info may be NULL.
+ */
+msc_status msc_solve(msc_op op, const double* d_b, double* d_x, const msc_params* params,
+                     msc_info* info, msc_stream stream);
+
+/*
+ * Adjoint of msc_solve for a real loss L(x_0..x_{ns-1}).  Given the forward solutions
+ * d_x (complex128[ns*n]) and d_g = dL/dx (complex128[ns*n], torch's convention
+ * dL/dRe + i dL/dIm), computes y_k = (A + sigma_k)^{-1} g_k and
+ *   d_grad_b[n]      = sum_k y_k
+ *   d_grad_vals[nnz] = gradient with respect to the stored values, in creation order:
+ *       A = M^H M : -sum_k [ (M y_k)_i conj(x_k)_j + (M x_k)_i conj(y_k)_j ]
+ *       A given  : -sum_k (y_k)_i conj(x_k)_j                 for entry e = (i, j).
+ * When every g_k is a real multiple of one vector the y_k come from one multishift
+ * solve; otherwise from one batched single-shift solve per shift.  Either gradient
+ * pointer may be NULL to skip it.  info (may be NULL) reports the adjoint solve.
+ */
+msc_status msc_solve_adjoint(msc_op op, const double* d_g, const double* d_x,
+                             double* d_grad_b, double* d_grad_vals,
+                             const msc_params* params, msc_info* info, msc_stream stream);
+
+/*
+ * Many independent multishift solves in one launch sequence: system s uses ops[s]
+ * (each with its own shifts) and nrhs[s] right-hand sides at d_b[s]
+ * (complex128[nrhs[s]*n_s], rhs-major); solutions go to d_x[s]
+ * (complex128[nrhs[s]*ns_s*n_s], rhs-major then shift-major).  ops, nrhs, d_b and d_x
+ * are host arrays of length nsys.  info, if not NULL, is a host array with one entry
+ * per (system, rhs) pair in order.
+ */
+msc_status msc_solve_batched(int32_t nsys, const msc_op* ops, const int32_t* nrhs,
+                             const double* const* d_b, double* const* d_x,
+                             const msc_params* params, msc_info* info, msc_stream stream);
+
+/* Release an operator and everything it owns.  NULL is ignored. */
+void msc_op_destroy(msc_op op);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MSC_H */

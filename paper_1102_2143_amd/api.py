@@ -1,0 +1,200 @@
+"""Python binding of the C ABI: argument marshalling only.
+
+Device memory and streams come from torch; every numerical step runs in ``libmsc.so``.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+_PREC = {"fp64": L.MSC_PREC_FP64, "mixed": L.MSC_PREC_MIXED}
+_KIND = {"mhm": L.MSC_A_MHM, "herm": L.MSC_A_HERM}
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev_tensor(a, dtype, device):
+    if isinstance(a, torch.Tensor):
+        t = a.to(device=device, dtype=dtype)
+    else:
+        t = torch.from_numpy(np.ascontiguousarray(a)).to(device=device, dtype=dtype)
+    return t.contiguous()
+
+
+def _ptr(t: torch.Tensor):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def make_params(tol=1e-10, prec="fp64", max_iter=10000, reliable_every=50, freeze=True,
+                refine=True, poll_every=16, inner_tol=1e-7, refine_max_iter=10000, lanes=0,
+                verify=True) -> L.Params:
+    lib = L.load()
+    p = L.Params()
+    lib.msc_params_default(ctypes.byref(p))
+    p.tol = float(tol)
+    p.prec = _PREC[prec] if isinstance(prec, str) else int(prec)
+    p.max_iter = int(max_iter)
+    p.reliable_every = int(reliable_every)
+    p.freeze = int(bool(freeze))
+    p.refine = int(bool(refine))
+    p.poll_every = int(poll_every)
+    p.inner_tol = float(inner_tol)
+    p.refine_max_iter = int(refine_max_iter)
+    p.lanes = int(lanes)
+    p.verify = int(bool(verify))
+    return p
+
+
+class Operator:
+    """A CSR operator resident on the GPU: A = M^H M (kind "mhm") or A itself ("herm")."""
+
+    def __init__(self, rowptr, col, vals, n, kind="mhm", device="cuda:0", stream=None):
+        self.lib = L.load()
+        self.device = torch.device(device)
+        self.n = int(n)
+        self.kind = kind
+        rp = _dev_tensor(rowptr, torch.int64, self.device)
+        cl = _dev_tensor(col, torch.int32, self.device)
+        vl = _dev_tensor(vals, torch.complex128, self.device)
+        self.nnz = int(cl.numel())
+        h = ctypes.c_void_p()
+        st = self.lib.msc_op_create_csr(ctypes.byref(h), _KIND[kind], self.n, self.nnz, _ptr(rp),
+                                        _ptr(cl), _ptr(vl), _stream(stream))
+        if st != L.MSC_OK:
+            raise L.MscError(st, "msc_op_create_csr")
+        self.handle = h
+        self.sigma = None
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            self.lib.msc_op_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_shifts(self, sigma):
+        s = np.ascontiguousarray(np.asarray(sigma, dtype=np.float64).reshape(-1))
+        st = self.lib.msc_op_set_shifts(self.handle,
+                                        s.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                        int(s.size))
+        if st != L.MSC_OK:
+            raise L.MscError(st, "msc_op_set_shifts")
+        self.sigma = s.copy()
+
+    def update_values(self, vals, stream=None):
+        vl = _dev_tensor(vals, torch.complex128, self.device)
+        st = self.lib.msc_op_update_values(self.handle, _ptr(vl), _stream(stream))
+        if st != L.MSC_OK:
+            raise L.MscError(st, "msc_op_update_values")
+
+    def apply(self, v, shift=0.0, prec="fp64", stream=None):
+        vin = _dev_tensor(v, torch.complex128, self.device)
+        out = torch.empty_like(vin)
+        st = self.lib.msc_op_apply(self.handle, _PREC[prec], _ptr(vin), _ptr(out), float(shift),
+                                   _stream(stream))
+        if st != L.MSC_OK:
+            raise L.MscError(st, "msc_op_apply")
+        return out
+
+    def solve(self, b, out=None, stream=None, check=True, **kw):
+        """x (ns, n) complex128 for (A + sigma_k) x_k = b; returns (x, info dict)."""
+        if self.sigma is None:
+            raise ValueError("set_shifts first")
+        ns = self.sigma.size
+        bt = _dev_tensor(b, torch.complex128, self.device)
+        x = torch.empty((ns, self.n), dtype=torch.complex128, device=self.device) if out is None else out
+        prm = make_params(**kw)
+        info, rel, fi = _new_info(ns)
+        st = self.lib.msc_solve(self.handle, _ptr(bt), _ptr(x), ctypes.byref(prm),
+                                ctypes.byref(info), _stream(stream))
+        res = _info_dict(st, info, rel, fi)
+        if check and st not in (L.MSC_OK, L.MSC_ENOTCONV):
+            raise L.MscError(st, "msc_solve")
+        return x, res
+
+    def solve_adjoint(self, g, x, stream=None, grad_vals=True, grad_b=True, check=True, **kw):
+        """(grad_b (n,), grad_vals (nnz,), info) of L with dL/dx = g."""
+        ns = self.sigma.size
+        gt = _dev_tensor(g, torch.complex128, self.device).reshape(ns, self.n)
+        xt = _dev_tensor(x, torch.complex128, self.device).reshape(ns, self.n)
+        gb = torch.empty(self.n, dtype=torch.complex128, device=self.device) if grad_b else None
+        gv = torch.empty(self.nnz, dtype=torch.complex128, device=self.device) if grad_vals else None
+        prm = make_params(**kw)
+        info, rel, fi = _new_info(ns)
+        st = self.lib.msc_solve_adjoint(self.handle, _ptr(gt), _ptr(xt),
+                                        _ptr(gb) if gb is not None else None,
+                                        _ptr(gv) if gv is not None else None,
+                                        ctypes.byref(prm), ctypes.byref(info), _stream(stream))
+        res = _info_dict(st, info, rel, fi)
+        if check and st not in (L.MSC_OK, L.MSC_ENOTCONV):
+            raise L.MscError(st, "msc_solve_adjoint")
+        return gb, gv, res
+
+
+def _new_info(ns):
+    info = L.Info()
+    rel = (ctypes.c_double * ns)()
+    fi = (ctypes.c_int32 * ns)()
+    info.true_rel_res = ctypes.cast(rel, ctypes.POINTER(ctypes.c_double))
+    info.freeze_iter = ctypes.cast(fi, ctypes.POINTER(ctypes.c_int32))
+    return info, rel, fi
+
+
+def _info_dict(st, info, rel, fi):
+    return dict(status=L.STATUS_NAMES.get(st, st), code=int(st), iters=int(info.iters),
+                refine_iters=int(info.refine_iters), n_reliable=int(info.n_reliable),
+                n_refined=int(info.n_refined), true_rel_res=np.array(rel[:]),
+                freeze_iter=np.array(fi[:]), seconds=float(info.seconds),
+                alg_bytes=float(info.alg_bytes))
+
+
+def solve_batched(ops, bs, stream=None, check=True, **kw):
+    """Solve every op against its right-hand sides bs[s] (nrhs_s, n_s) in one call.
+
+    Returns (xs, infos) with xs[s] of shape (nrhs_s, ns_s, n_s)."""
+    lib = L.load()
+    nsys = len(ops)
+    handles = (ctypes.c_void_p * nsys)(*[op.handle.value for op in ops])
+    nrhs = (ctypes.c_int32 * nsys)()
+    bptr = (ctypes.c_void_p * nsys)()
+    xptr = (ctypes.c_void_p * nsys)()
+    keep, xs = [], []
+    total = 0
+    for s, (op, b) in enumerate(zip(ops, bs)):
+        bt = _dev_tensor(b, torch.complex128, op.device).reshape(-1, op.n)
+        nrhs[s] = bt.shape[0]
+        x = torch.empty((bt.shape[0], op.sigma.size, op.n), dtype=torch.complex128, device=op.device)
+        keep.append(bt)
+        xs.append(x)
+        bptr[s] = bt.data_ptr()
+        xptr[s] = x.data_ptr()
+        total += bt.shape[0]
+    infos = (L.Info * total)()
+    arrays = []
+    t = 0
+    for s, op in enumerate(ops):
+        for _ in range(nrhs[s]):
+            rel = (ctypes.c_double * op.sigma.size)()
+            fi = (ctypes.c_int32 * op.sigma.size)()
+            infos[t].true_rel_res = ctypes.cast(rel, ctypes.POINTER(ctypes.c_double))
+            infos[t].freeze_iter = ctypes.cast(fi, ctypes.POINTER(ctypes.c_int32))
+            arrays.append((rel, fi))
+            t += 1
+    prm = make_params(**kw)
+    st = lib.msc_solve_batched(nsys, handles, nrhs, bptr, xptr, ctypes.byref(prm), infos,
+                               _stream(stream))
+    if check and st not in (L.MSC_OK, L.MSC_ENOTCONV):
+        raise L.MscError(st, "msc_solve_batched")
+    out = [_info_dict(st, infos[i], arrays[i][0], arrays[i][1]) for i in range(total)]
+    return xs, out, L.STATUS_NAMES.get(st, st)

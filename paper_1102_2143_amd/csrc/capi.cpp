@@ -1,0 +1,516 @@
+// Host driver and C ABI: operator creation (device-side M^H and complex64 copies), the
+// iteration loop with device-resident convergence state, verification, and error
+// reporting.  No exception crosses the ABI; every failure sets a thread-local message.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "msc.h"
+#include "msc_internal.h"
+
+using namespace msc;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+void set_error(const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+}
+
+#define HIP_TRY(expr)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess) {                                                        \
+      set_error("%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, __LINE__); \
+      return e_ == hipErrorOutOfMemory ? MSC_ENOMEM : MSC_EHIP;                    \
+    }                                                                              \
+  } while (0)
+
+template <class T> hipError_t dalloc(T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  return hipMalloc(reinterpret_cast<void**>(p), sizeof(T) * count);
+}
+
+template <class T> void dfree(T*& p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+void free_workspace(Workspace& w) {
+  if (w.r) (void)hipFree(w.r);
+  if (w.p) (void)hipFree(w.p);
+  if (w.t) (void)hipFree(w.t);
+  if (w.pk) (void)hipFree(w.pk);
+  dfree(w.t64);
+  dfree(w.u64);
+  dfree(w.st);
+  if (w.h_halt) (void)hipHostFree(w.h_halt);
+  for (auto& e : w.ev)
+    if (e) (void)hipEventDestroy(e);
+  w = Workspace{};
+}
+
+msc_status ensure_scratch(msc_op op) {
+  Scratch& sc = op->scratch;
+  if (sc.partial) return MSC_OK;
+  HIP_TRY(dalloc(&sc.partial, size_t(kMaxGrid) * kMaxShifts));
+  HIP_TRY(dalloc(&sc.tickets, 16));
+  HIP_TRY(dalloc(&sc.res2, kMaxShifts));
+  HIP_TRY(hipMemset(sc.tickets, 0, sizeof(unsigned) * 16));
+  return MSC_OK;
+}
+
+msc_status ensure_workspace(msc_op op, int prec, int ns) {
+  Workspace& w = op->ws;
+  const size_t n = size_t(op->n);
+  if (w.st && w.prec == prec && w.ns >= ns && w.n == n) return MSC_OK;
+  free_workspace(w);
+  const size_t es = prec == MSC_PREC_MIXED ? sizeof(float2) : sizeof(double2);
+  HIP_TRY(hipMalloc(&w.r, es * n));
+  HIP_TRY(hipMalloc(&w.p, es * n));
+  HIP_TRY(hipMalloc(&w.t, es * n));
+  HIP_TRY(hipMalloc(&w.pk, es * n * size_t(std::max(ns - 1, 1))));
+  HIP_TRY(dalloc(&w.t64, n));
+  HIP_TRY(dalloc(&w.u64, n * 8));
+  HIP_TRY(dalloc(&w.st, 1));
+  HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&w.h_halt), 2 * sizeof(int), hipHostMallocDefault));
+  HIP_TRY(hipEventCreateWithFlags(&w.ev[0], hipEventDisableTiming));
+  HIP_TRY(hipEventCreateWithFlags(&w.ev[1], hipEventDisableTiming));
+  w.n = n;
+  w.ns = ns;
+  w.prec = prec;
+  return MSC_OK;
+}
+
+int choose_lanes(msc_op op, const msc_params& prm) {
+  if (prm.lanes == 4 || prm.lanes == 8 || prm.lanes == 16 || prm.lanes == 32) return prm.lanes;
+  const double avg = op->n > 0 ? double(op->nnz) / double(op->n) : 1.0;
+  if (avg <= 6.0) return 4;
+  if (avg <= 40.0) return 8;
+  if (avg <= 80.0) return 16;
+  return 32;
+}
+
+MsArgs make_args(msc_op op, int lanes, const double* d_b, double* d_x) {
+  MsArgs a{};
+  a.kind = op->kind;
+  a.n = op->n;
+  a.lanes = lanes;
+  a.grid = default_grid(op->n, lanes);
+  a.m64 = Csr<double2>{op->rowptr, op->col, op->val64};
+  a.m32 = Csr<float2>{op->rowptr, op->col, op->val32};
+  if (op->kind == MSC_A_MHM) {
+    a.mh64 = Csr<double2>{op->rowptr_h, op->col_h, op->val64_h};
+    a.mh32 = Csr<float2>{op->rowptr_h, op->col_h, op->val32_h};
+  }
+  a.b = reinterpret_cast<const double2*>(d_b);
+  a.x = reinterpret_cast<double2*>(d_x);
+  a.r = op->ws.r;
+  a.p = op->ws.p;
+  a.t = op->ws.t;
+  a.pk = op->ws.pk;
+  a.t64 = op->ws.t64;
+  a.st = op->ws.st;
+  a.sc = op->scratch;
+  return a;
+}
+
+// Algorithmic HBM bytes of one multishift iteration (each array touched once, gathers
+// counted once), per row: see the byte model in the design notes of the repository.
+double iter_bytes(int kind, int prec, double n, double nnz, double nnz_h, double act_sum,
+                  double iters) {
+  const double w = prec == MSC_PREC_MIXED ? 8.0 : 16.0;   // Krylov vector element
+  const double vb = prec == MSC_PREC_MIXED ? 8.0 : 16.0;  // matrix value
+  const double mat = (nnz * (vb + 4.0) + 4.0 * (n + 1)) +
+                     (kind == MSC_A_MHM ? nnz_h * (vb + 4.0) + 4.0 * (n + 1) : 0.0);
+  double vec;
+  if (kind == MSC_A_MHM)
+    vec = n * (w + w) + n * (w + w + 2 * w);  // K1: p gather, t write; K2: t gather, p, r r/w
+  else
+    vec = n * (w + w) + n * (w + w + 2 * w);  // K1: p, t; K2: t, p, r r/w
+  vec += n * (w + 2 * w + 32.0);               // K3: r, p r/w, x_0 r/w
+  const double per_shift = n * (32.0 + 2 * w); // x_j r/w (complex128) + p_j r/w
+  return iters * (mat + vec) + act_sum * per_shift;
+}
+
+msc_status run_multishift(msc_op op, const double* d_b, double* d_x, const msc_params& prm,
+                          msc_info* info, hipStream_t s, double tol_stop, int prec,
+                          std::vector<double>* rel_out, int* iters_out, int* status_out,
+                          double* bytes_out) {
+  const int ns = int(op->sigma.size());
+  msc_status rc = ensure_scratch(op);
+  if (rc != MSC_OK) return rc;
+  rc = ensure_workspace(op, prec, ns);
+  if (rc != MSC_OK) return rc;
+  const int lanes = choose_lanes(op, prm);
+  MsArgs a = make_args(op, lanes, d_b, d_x);
+
+  std::vector<int> order(ns);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int i, int j) { return op->sigma[i] < op->sigma[j]; });
+  SolveState h{};
+  h.sigma0 = op->sigma[order[0]];
+  h.eps2 = tol_stop * tol_stop;  // scaled by |b|^2 in the init kernel
+  h.a_prev = 1.0;
+  h.b = 0.0;
+  h.max_iter = prm.max_iter;
+  h.ns = ns;
+  h.freeze = prm.freeze ? 1 : 0;
+  for (int j = 0; j < ns; ++j) {
+    h.s[j] = op->sigma[order[j]] - h.sigma0;
+    h.zeta[j] = 1.0;
+    h.zeta_prev[j] = 1.0;
+    h.active[j] = 1;
+    h.freeze_iter[j] = -1;
+    h.orig[j] = order[j];
+  }
+  HIP_TRY(hipMemcpyAsync(op->ws.st, &h, sizeof h, hipMemcpyHostToDevice, s));
+  HIP_TRY(launch_init(prec, a, s));
+
+  const int G = std::max(1, prm.poll_every);
+  const int ru = (prec == MSC_PREC_MIXED) ? prm.reliable_every : 0;
+  int launched = 0, chunk = 0;
+  bool done = prm.max_iter <= 0;
+  while (!done) {
+    for (int g = 0; g < G; ++g) {
+      HIP_TRY(launch_iteration(prec, a, s));
+      ++launched;
+      if (ru > 0 && launched % ru == 0) HIP_TRY(launch_reliable(prec, a, s));
+    }
+    const int slot = chunk & 1;
+    HIP_TRY(hipMemcpyAsync(&op->ws.h_halt[slot], &op->ws.st->halt, sizeof(int),
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipEventRecord(op->ws.ev[slot], s));
+    if (chunk >= 1) {
+      HIP_TRY(hipEventSynchronize(op->ws.ev[slot ^ 1]));
+      if (op->ws.h_halt[slot ^ 1]) done = true;
+    }
+    if (launched >= prm.max_iter + 2 * G) done = true;
+    ++chunk;
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  HIP_TRY(hipMemcpy(&h, op->ws.st, sizeof h, hipMemcpyDeviceToHost));
+
+  // per-shift freeze iterations in the caller's order
+  if (info && info->freeze_iter) {
+    for (int j = 0; j < ns; ++j) {
+      int fi = h.freeze_iter[j];
+      if (j == 0 || (fi < 0 && h.s[j] == 0.0)) fi = (h.R <= h.eps2) ? h.iter : -1;
+      info->freeze_iter[order[j]] = fi;
+    }
+  }
+  *iters_out = h.iter;
+  *status_out = h.status;
+  if (info) info->n_reliable = h.n_reliable;
+
+  // active-shift count summed over iterations, for the byte model: shift j (>= 1) was
+  // updated in iterations 1..freeze_iter (or all)
+  double act_sum = 0.0;
+  for (int j = 1; j < ns; ++j) act_sum += (h.freeze_iter[j] >= 0) ? h.freeze_iter[j] : h.iter;
+  *bytes_out = iter_bytes(op->kind, prec, double(op->n), double(op->nnz), double(op->nnz_h),
+                          act_sum, double(h.iter));
+
+  rel_out->assign(ns, 0.0);
+  if (prm.verify && h.status == 0) {
+    const double bn = std::sqrt(h.bnorm2);
+    for (int k0 = 0; k0 < ns; k0 += 8) {
+      const int kc = std::min(8, ns - k0);
+      HIP_TRY(launch_verify(a, op->sigma.data(), k0, kc, op->ws.u64, s));
+    }
+    std::vector<double> r2(ns);
+    HIP_TRY(hipMemcpyAsync(r2.data(), op->scratch.res2, sizeof(double) * ns, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int k = 0; k < ns; ++k) (*rel_out)[k] = bn > 0 ? std::sqrt(r2[k]) / bn : 0.0;
+    const double nvec = op->kind == MSC_A_MHM ? 2.0 : 1.0;
+    *bytes_out += nvec * (double(op->nnz) * 20.0 + 4.0 * (op->n + 1)) * std::ceil(ns / 8.0) +
+                  double(op->n) * 16.0 * ns * (op->kind == MSC_A_MHM ? 4.0 : 2.0) + 16.0 * op->n;
+  }
+  return MSC_OK;
+}
+
+msc_status check_op(msc_op op) {
+  if (!op) {
+    set_error("null operator");
+    return MSC_EINVAL;
+  }
+  return MSC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void msc_params_default(msc_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof *p);
+  p->tol = 1e-10;
+  p->max_iter = 10000;
+  p->prec = MSC_PREC_FP64;
+  p->reliable_every = 50;
+  p->freeze = 1;
+  p->refine = 1;
+  p->poll_every = 16;
+  p->inner_tol = 1e-7;
+  p->refine_max_iter = 10000;
+  p->lanes = 0;
+  p->verify = 1;
+}
+
+const char* msc_version(void) { return "msc 0.1 (gfx950)"; }
+
+const char* msc_last_error(void) { return g_last_error.c_str(); }
+
+msc_status msc_op_create_csr(msc_op* out, int32_t kind, int64_t n, int64_t nnz,
+                             const int64_t* d_rowptr, const int32_t* d_col, const double* d_vals,
+                             msc_stream stream) {
+  if (!out) {
+    set_error("msc_op_create_csr: out is NULL");
+    return MSC_EINVAL;
+  }
+  *out = nullptr;
+  if (kind != MSC_A_MHM && kind != MSC_A_HERM) {
+    set_error("msc_op_create_csr: unknown kind %d", kind);
+    return MSC_EINVAL;
+  }
+  if (n < 1 || nnz < 0 || nnz >= (int64_t(1) << 31) || n >= (int64_t(1) << 31)) {
+    set_error("msc_op_create_csr: need 1 <= n < 2^31 and 0 <= nnz < 2^31 (n=%lld nnz=%lld)",
+              (long long)n, (long long)nnz);
+    return MSC_EINVAL;
+  }
+  if (!d_rowptr || (nnz > 0 && (!d_col || !d_vals))) {
+    set_error("msc_op_create_csr: null array");
+    return MSC_EINVAL;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  msc_op op = new (std::nothrow) msc_op_s();
+  if (!op) {
+    set_error("msc_op_create_csr: host allocation failed");
+    return MSC_ENOMEM;
+  }
+  auto fail = [&](msc_status st) {
+    msc_op_destroy(op);
+    return st;
+  };
+  op->kind = kind;
+  op->n = n;
+  op->nnz = nnz;
+  op->nnz_h = kind == MSC_A_MHM ? nnz : 0;
+  if (hipGetDevice(&op->device) != hipSuccess) {
+    set_error("msc_op_create_csr: no HIP device");
+    return fail(MSC_EHIP);
+  }
+  int* d_err = nullptr;
+#define CREATE_TRY(expr)                                                          \
+  do {                                                                            \
+    hipError_t e_ = (expr);                                                       \
+    if (e_ != hipSuccess) {                                                       \
+      set_error("%s failed: %s", #expr, hipGetErrorString(e_));                   \
+      if (d_err) (void)hipFree(d_err);                                            \
+      return fail(e_ == hipErrorOutOfMemory ? MSC_ENOMEM : MSC_EHIP);             \
+    }                                                                             \
+  } while (0)
+  CREATE_TRY(dalloc(&d_err, 1));
+  CREATE_TRY(hipMemsetAsync(d_err, 0, sizeof(int), s));
+  CREATE_TRY(launch_validate_csr(d_rowptr, d_col, n, nnz, d_err, s));
+  int h_err = 0;
+  CREATE_TRY(hipMemcpyAsync(&h_err, d_err, sizeof(int), hipMemcpyDeviceToHost, s));
+  CREATE_TRY(hipStreamSynchronize(s));
+  (void)hipFree(d_err);
+  d_err = nullptr;
+  if (h_err) {
+    set_error("msc_op_create_csr: invalid CSR (%s%s%s%s)", (h_err & 1) ? "rowptr[0]!=0 " : "",
+              (h_err & 2) ? "rowptr decreasing " : "", (h_err & 4) ? "rowptr[n]!=nnz " : "",
+              (h_err & 8) ? "column out of range" : "");
+    return fail(MSC_EINVAL);
+  }
+  CREATE_TRY(dalloc(&op->rowptr, size_t(n) + 1));
+  CREATE_TRY(dalloc(&op->col, size_t(nnz)));
+  CREATE_TRY(dalloc(&op->val64, size_t(nnz)));
+  CREATE_TRY(dalloc(&op->val32, size_t(nnz)));
+  CREATE_TRY(launch_rowptr_to32(d_rowptr, op->rowptr, n, s));
+  if (nnz > 0) {
+    CREATE_TRY(hipMemcpyAsync(op->col, d_col, sizeof(int32_t) * nnz, hipMemcpyDeviceToDevice, s));
+    CREATE_TRY(hipMemcpyAsync(op->val64, d_vals, sizeof(double2) * nnz, hipMemcpyDeviceToDevice, s));
+  }
+  CREATE_TRY(launch_cast_vals(op->val64, op->val32, nnz, s));
+  if (kind == MSC_A_MHM) {
+    CREATE_TRY(dalloc(&op->rowptr_h, size_t(n) + 1));
+    CREATE_TRY(dalloc(&op->col_h, size_t(nnz)));
+    CREATE_TRY(dalloc(&op->perm_h, size_t(nnz)));
+    CREATE_TRY(dalloc(&op->val64_h, size_t(nnz)));
+    CREATE_TRY(dalloc(&op->val32_h, size_t(nnz)));
+    CREATE_TRY(build_adjoint(op->rowptr, op->col, n, nnz, op->rowptr_h, op->col_h, op->perm_h, s));
+    CREATE_TRY(launch_adjoint_vals(op->perm_h, op->val64, op->val64_h, op->val32_h, nnz, s));
+  }
+  CREATE_TRY(hipStreamSynchronize(s));
+#undef CREATE_TRY
+  *out = op;
+  return MSC_OK;
+}
+
+msc_status msc_op_update_values(msc_op op, const double* d_vals, msc_stream stream) {
+  if (check_op(op) != MSC_OK) return MSC_EINVAL;
+  if (op->nnz > 0 && !d_vals) {
+    set_error("msc_op_update_values: null values");
+    return MSC_EINVAL;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (op->nnz > 0) {
+    HIP_TRY(hipMemcpyAsync(op->val64, d_vals, sizeof(double2) * op->nnz, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(launch_cast_vals(op->val64, op->val32, op->nnz, s));
+    if (op->kind == MSC_A_MHM)
+      HIP_TRY(launch_adjoint_vals(op->perm_h, op->val64, op->val64_h, op->val32_h, op->nnz, s));
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  return MSC_OK;
+}
+
+msc_status msc_op_set_shifts(msc_op op, const double* h_sigma, int32_t ns) {
+  if (check_op(op) != MSC_OK) return MSC_EINVAL;
+  if (!h_sigma || ns < 1 || ns > kMaxShifts) {
+    set_error("msc_op_set_shifts: need 1 <= ns <= %d and a host array", kMaxShifts);
+    return MSC_EINVAL;
+  }
+  for (int k = 0; k < ns; ++k)
+    if (!std::isfinite(h_sigma[k])) {
+      set_error("msc_op_set_shifts: sigma[%d] is not finite", k);
+      return MSC_EINVAL;
+    }
+  op->sigma.assign(h_sigma, h_sigma + ns);
+  return MSC_OK;
+}
+
+msc_status msc_op_query(msc_op op, int64_t* n, int64_t* nnz, int32_t* ns, int32_t* kind) {
+  if (check_op(op) != MSC_OK) return MSC_EINVAL;
+  if (n) *n = op->n;
+  if (nnz) *nnz = op->nnz;
+  if (ns) *ns = int32_t(op->sigma.size());
+  if (kind) *kind = op->kind;
+  return MSC_OK;
+}
+
+msc_status msc_op_apply(msc_op op, int32_t prec, const double* d_in, double* d_out, double shift,
+                        msc_stream stream) {
+  if (check_op(op) != MSC_OK) return MSC_EINVAL;
+  if (!d_in || !d_out || (prec != MSC_PREC_FP64 && prec != MSC_PREC_MIXED)) {
+    set_error("msc_op_apply: null vector or unknown precision");
+    return MSC_EINVAL;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  msc_params prm;
+  msc_params_default(&prm);
+  const int ns = std::max<int>(1, int(op->sigma.size()));
+  msc_status rc = ensure_workspace(op, prec, ns);
+  if (rc != MSC_OK) return rc;
+  // the FP64 path needs two complex128 temporaries: t64 and the first slice of u64
+  void* ta = prec == MSC_PREC_MIXED ? op->ws.r : static_cast<void*>(op->ws.t64);
+  void* tb = prec == MSC_PREC_MIXED ? op->ws.t : static_cast<void*>(op->ws.u64);
+  HIP_TRY(launch_apply(op->kind, prec, choose_lanes(op, prm), op->n,
+                       Csr<double2>{op->rowptr, op->col, op->val64},
+                       Csr<double2>{op->rowptr_h, op->col_h, op->val64_h},
+                       Csr<float2>{op->rowptr, op->col, op->val32},
+                       Csr<float2>{op->rowptr_h, op->col_h, op->val32_h},
+                       reinterpret_cast<const double2*>(d_in), reinterpret_cast<double2*>(d_out),
+                       shift, ta, tb, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return MSC_OK;
+}
+
+msc_status msc_solve(msc_op op, const double* d_b, double* d_x, const msc_params* params,
+                     msc_info* info, msc_stream stream) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (check_op(op) != MSC_OK) return MSC_EINVAL;
+  if (!d_b || !d_x) {
+    set_error("msc_solve: null b or x");
+    return MSC_EINVAL;
+  }
+  if (op->sigma.empty()) {
+    set_error("msc_solve: no shifts set");
+    return MSC_EINVAL;
+  }
+  msc_params prm;
+  if (params)
+    prm = *params;
+  else
+    msc_params_default(&prm);
+  if (!(prm.tol >= 0.0) || (prm.prec != MSC_PREC_FP64 && prm.prec != MSC_PREC_MIXED)) {
+    set_error("msc_solve: invalid tol or precision");
+    return MSC_EINVAL;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int ns = int(op->sigma.size());
+  std::vector<double> rel;
+  int iters = 0, status = 0;
+  double bytes = 0.0;
+  msc_status rc = run_multishift(op, d_b, d_x, prm, info, s, prm.tol, prm.prec, &rel, &iters,
+                                 &status, &bytes);
+  if (rc != MSC_OK) return rc;
+  msc_status result = MSC_OK;
+  if (status != 0) {
+    set_error("msc_solve: breakdown (p^H (A+sigma_min) p <= 0 or not finite) at iteration %d", iters);
+    result = MSC_EBREAKDOWN;
+  } else if (prm.verify) {
+    for (int k = 0; k < ns; ++k)
+      if (!(rel[k] <= prm.tol)) result = MSC_ENOTCONV;
+    if (result == MSC_ENOTCONV) set_error("msc_solve: some shift did not reach tol");
+  }
+  if (info) {
+    info->iters = iters;
+    info->refine_iters = 0;
+    info->n_refined = 0;
+    if (info->true_rel_res)
+      for (int k = 0; k < ns; ++k) info->true_rel_res[k] = rel[k];
+    info->alg_bytes = bytes;
+    info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  return result;
+}
+
+msc_status msc_solve_adjoint(msc_op op, const double*, const double*, double*, double*,
+                             const msc_params*, msc_info*, msc_stream) {
+  if (check_op(op) != MSC_OK) return MSC_EINVAL;
+  set_error("msc_solve_adjoint: not available in this build");
+  return MSC_EINVAL;
+}
+
+msc_status msc_solve_batched(int32_t, const msc_op*, const int32_t*, const double* const*,
+                             double* const*, const msc_params*, msc_info*, msc_stream) {
+  set_error("msc_solve_batched: not available in this build");
+  return MSC_EINVAL;
+}
+
+void msc_op_destroy(msc_op op) {
+  if (!op) return;
+  free_workspace(op->ws);
+  dfree(op->scratch.partial);
+  dfree(op->scratch.tickets);
+  dfree(op->scratch.res2);
+  dfree(op->rowptr);
+  dfree(op->col);
+  dfree(op->val64);
+  dfree(op->val32);
+  dfree(op->rowptr_h);
+  dfree(op->col_h);
+  dfree(op->perm_h);
+  dfree(op->val64_h);
+  dfree(op->val32_h);
+  delete op;
+}
+
+}  // extern "C"

@@ -1,0 +1,140 @@
+// Device-side helpers shared by the HIP kernels: complex arithmetic on float2/double2,
+// wavefront and workgroup reductions in FP64, the "last workgroup finalises" ticket and
+// the XCD-aware mapping of workgroups to contiguous row ranges.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace msc {
+
+constexpr int kWave = 64;   // CDNA wavefront width
+constexpr int kXcds = 8;    // MI355X: 8 accelerator complex dies, one L2 each
+
+template <class R> struct vec2;
+template <> struct vec2<float> { using type = float2; };
+template <> struct vec2<double> { using type = double2; };
+template <class R> using cplx = typename vec2<R>::type;
+
+template <class R> __device__ __forceinline__ cplx<R> czero() { return cplx<R>{R(0), R(0)}; }
+
+// acc += a * b (complex)
+template <class R>
+__device__ __forceinline__ void cfma(cplx<R>& acc, const cplx<R>& a, const cplx<R>& b) {
+  acc.x = fma(a.x, b.x, acc.x);
+  acc.x = fma(-a.y, b.y, acc.x);
+  acc.y = fma(a.x, b.y, acc.y);
+  acc.y = fma(a.y, b.x, acc.y);
+}
+
+template <class R> __device__ __forceinline__ double norm2d(const cplx<R>& v) {
+  const double x = double(v.x), y = double(v.y);
+  return fma(x, x, y * y);
+}
+
+__device__ __forceinline__ double2 to_d(const float2 v) { return double2{double(v.x), double(v.y)}; }
+__device__ __forceinline__ double2 to_d(const double2 v) { return v; }
+template <class R> __device__ __forceinline__ cplx<R> from_d(const double2 v);
+template <> __device__ __forceinline__ float2 from_d<float>(const double2 v) {
+  return float2{float(v.x), float(v.y)};
+}
+template <> __device__ __forceinline__ double2 from_d<double>(const double2 v) { return v; }
+
+// Sum over the L consecutive lanes of a row group (L a power of two <= 64).
+template <int L, class T> __device__ __forceinline__ T group_sum(T v) {
+#pragma unroll
+  for (int off = L / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, L);
+  return v;
+}
+
+template <int L, class R> __device__ __forceinline__ cplx<R> group_sum_c(cplx<R> v) {
+  v.x = group_sum<L>(v.x);
+  v.y = group_sum<L>(v.y);
+  return v;
+}
+
+// Workgroup sum of one double per thread; the result is valid in thread 0.
+template <int BS> __device__ __forceinline__ double block_sum(double v) {
+  __shared__ double part[BS / kWave];
+  v = group_sum<kWave>(v);
+  const int w = threadIdx.x / kWave;
+  if ((threadIdx.x & (kWave - 1)) == 0) part[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < BS / kWave; ++i) s += part[i];
+  }
+  __syncthreads();
+  return s;
+}
+
+// Workgroup sums of K doubles per thread (K small); results valid in thread 0.
+template <int BS, int K> __device__ __forceinline__ void block_sum_k(double (&v)[K]) {
+  __shared__ double part[K][BS / kWave];
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = group_sum<kWave>(v[k]);
+  const int w = threadIdx.x / kWave;
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) part[k][w] = v[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      double s = 0.0;
+#pragma unroll
+      for (int i = 0; i < BS / kWave; ++i) s += part[k][i];
+      v[k] = s;
+    }
+  }
+  __syncthreads();
+}
+
+// Agent-scope stores/loads for values exchanged between workgroups of one launch
+// (the eight XCD L2 caches are not coherent with each other for plain accesses).
+__device__ __forceinline__ void store_agent(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double load_agent(const double* p) {
+  return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Every workgroup calls this once, after thread 0 stored its partial(s) with
+// store_agent.  Returns true (in all threads) in the workgroup that arrives last; that
+// workgroup then sees every partial through load_agent.  The ticket is reset by the
+// last workgroup, so the same counter serves the next launch.
+__device__ __forceinline__ bool arrive_last(unsigned* ticket) {
+  __shared__ int last;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned t = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    last = (t == gridDim.x - 1);
+    if (last) __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __syncthreads();
+  return last != 0;
+}
+
+// Workgroups are dispatched round-robin over the XCDs.  Renumber them so that the
+// workgroups of one XCD own one contiguous block of rows (its L2 then serves the
+// neighbouring-row gathers of that block).  Requires gridDim.x % 8 == 0 to permute.
+__device__ __forceinline__ int logical_block() {
+  const int g = gridDim.x, b = blockIdx.x;
+  if ((g & (kXcds - 1)) != 0) return b;
+  return (b & (kXcds - 1)) * (g / kXcds) + b / kXcds;
+}
+
+// Contiguous [beg, end) slice of `n` items for this workgroup, in units of `step`.
+__device__ __forceinline__ void block_range(int64_t n, int step, int64_t& beg, int64_t& end) {
+  const int64_t g = gridDim.x;
+  const int64_t units = (n + step - 1) / step;
+  const int64_t per = (units + g - 1) / g;
+  beg = int64_t(logical_block()) * per * step;
+  end = beg + per * step;
+  if (end > n) end = n;
+  if (beg > n) beg = n;
+}
+
+}  // namespace msc

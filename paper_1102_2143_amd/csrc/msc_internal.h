@@ -1,0 +1,149 @@
+// Internal declarations shared by the host driver and the kernel translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "msc.h"
+
+namespace msc {
+
+constexpr int kMaxShifts = 64;
+constexpr int kBlock = 256;          // threads per workgroup for every solver kernel
+constexpr int kMaxGrid = 2048;       // 256 CUs x 8 resident workgroups
+
+// Scalar state of one multishift solve, resident in device memory.  Written only by
+// the last-arriving workgroup of a kernel (or by the init kernel), read by the next
+// kernels in stream order.  Shift index j runs over the shifts sorted ascending; j = 0
+// is the driving shift sigma0.
+struct SolveState {
+  double R;          // |r|^2 of the driving recursive residual
+  double a;          // current step a_n = R / (p^H (A + sigma0) p)
+  double a_prev;     // previous step (1 before the first iteration)
+  double b;          // direction coefficient b_n of the last p update (0 at start)
+  double b_new;      // b_{n+1}, used by the update kernel of this iteration
+  double P;          // p^H (A + sigma0) p
+  double sigma0;
+  double bnorm2;
+  double eps2;       // tol^2 |b|^2
+  int iter;
+  int max_iter;
+  int halt;          // 1: no further iteration kernels do work
+  int k3_enable;     // 1: the update kernel of this iteration must run
+  int status;        // 0 running/ok, 1 breakdown
+  int ns;
+  int nact;          // number of entries in act_list for this iteration's update
+  int freeze;
+  int n_reliable;
+  int pad_;
+  unsigned ticket[4];
+  double s[kMaxShifts];         // sigma_j - sigma0
+  double zeta[kMaxShifts];      // zeta_j^(n)
+  double zeta_prev[kMaxShifts]; // zeta_j^(n-1)
+  double zk[kMaxShifts];        // zeta_j^(n+1) (this iteration)
+  double ak[kMaxShifts];        // a_j^(n) = a_n zeta^(n+1)/zeta^(n)
+  double bk[kMaxShifts];        // b_j^(n+1) = b_{n+1} (zeta^(n+1)/zeta^(n))^2
+  int active[kMaxShifts];
+  int freeze_iter[kMaxShifts];
+  int orig[kMaxShifts];         // caller's index of sorted shift j
+  int act_list[kMaxShifts];     // shifts j >= 1 updated by this iteration's kernel
+  int act_upd_p[kMaxShifts];    // 0 when that shift froze this iteration (skip p_j)
+};
+
+// Per-kernel partial-sum scratch, sized for kMaxGrid workgroups x kMaxShifts values.
+struct Scratch {
+  double* partial = nullptr;    // kMaxGrid * kMaxShifts doubles
+  unsigned* tickets = nullptr;  // 16 counters, zero between launches
+  double* res2 = nullptr;       // kMaxShifts doubles (verification output)
+};
+
+// CSR in device memory with int32 row pointers.
+template <class V> struct Csr {
+  const int32_t* rowptr = nullptr;
+  const int32_t* col = nullptr;
+  const V* val = nullptr;
+};
+
+struct Workspace {
+  size_t n = 0;
+  int ns = 0;
+  int prec = -1;
+  void* r = nullptr;    // n complex (R)
+  void* p = nullptr;    // n complex (R)
+  void* t = nullptr;    // n complex (R)
+  void* pk = nullptr;   // (ns-1) * n complex (R)
+  double2* t64 = nullptr;   // n complex128 (reliable updates, verification)
+  double2* u64 = nullptr;   // 8 * n complex128 (verification SpMM chunk)
+  SolveState* st = nullptr;
+  int* h_halt = nullptr;    // pinned host mirrors of st->halt, double buffered
+  hipEvent_t ev[2] = {nullptr, nullptr};
+};
+
+}  // namespace msc
+
+struct msc_op_s {
+  int kind = 0;
+  int64_t n = 0, nnz = 0, nnz_h = 0;
+  int device = 0;
+  int32_t* rowptr = nullptr;     // M (or A): int32[n+1]
+  int32_t* col = nullptr;
+  double2* val64 = nullptr;
+  float2* val32 = nullptr;
+  int32_t* rowptr_h = nullptr;   // M^H (kind MHM only)
+  int32_t* col_h = nullptr;
+  int32_t* perm_h = nullptr;     // entry of M^H -> entry of M
+  double2* val64_h = nullptr;
+  float2* val32_h = nullptr;
+  std::vector<double> sigma;
+  msc::Workspace ws;
+  msc::Scratch scratch;
+  int lanes64 = 0, lanes32 = 0;  // chosen lanes per row (0 = not yet tuned)
+};
+
+namespace msc {
+
+// ---- launchers implemented in the kernel translation units -------------------------
+// All launchers enqueue on `s` and return hipGetLastError() of the launch.
+
+// setup.hip
+hipError_t launch_validate_csr(const int64_t* rowptr, const int32_t* col, int64_t n, int64_t nnz,
+                               int* d_err, hipStream_t s);
+hipError_t launch_rowptr_to32(const int64_t* in, int32_t* out, int64_t n, hipStream_t s);
+hipError_t launch_cast_vals(const double2* in, float2* out, int64_t nnz, hipStream_t s);
+hipError_t build_adjoint(const int32_t* rowptr, const int32_t* col, int64_t n, int64_t nnz,
+                         int32_t* rowptr_h, int32_t* col_h, int32_t* perm_h, hipStream_t s);
+hipError_t launch_adjoint_vals(const int32_t* perm_h, const double2* val64, double2* val64_h,
+                               float2* val32_h, int64_t nnz, hipStream_t s);
+
+// multishift.hip
+struct MsArgs {
+  int kind;
+  int64_t n;
+  int lanes;
+  int grid;
+  Csr<double2> m64, mh64;
+  Csr<float2> m32, mh32;
+  const double2* b;
+  double2* x;            // caller's x, shift-major, caller order
+  void* r; void* p; void* t; void* pk;
+  double2* t64;
+  SolveState* st;
+  Scratch sc;
+};
+hipError_t launch_init(int prec, const MsArgs& a, hipStream_t s);
+hipError_t launch_iteration(int prec, const MsArgs& a, hipStream_t s);
+hipError_t launch_reliable(int prec, const MsArgs& a, hipStream_t s);
+// FP64 true residual norms^2 of shifts [k0, k0+kc) (kc <= 8) of x into sc.res2[k0..].
+hipError_t launch_verify(const MsArgs& a, const double* sigma_by_caller_index, int k0, int kc,
+                         double2* u64, hipStream_t s);
+hipError_t launch_apply(int kind, int prec, int lanes, int64_t n, const Csr<double2>& m64,
+                        const Csr<double2>& mh64, const Csr<float2>& m32,
+                        const Csr<float2>& mh32, const double2* in, double2* out,
+                        double shift, void* tmp_a, void* tmp_b, hipStream_t s);
+
+int default_grid(int64_t n, int lanes);
+
+}  // namespace msc

@@ -1,0 +1,663 @@
+// The multishift CG iteration (paper: Section 2, Algorithm 1; Section 3 design rules):
+//
+//   K1  t = M p                and  P = |t|^2 + sigma0 |p|^2   (A = M^H M)
+//       t = A p                and  P = Re(p^H t) + sigma0 |p|^2 (A given)
+//       last workgroup: a = R/P and, per shift, zeta^(n+1) and a_j (one lane per shift)
+//   K2  r <- r - a (M^H t + sigma0 p)  and  R' = |r|^2
+//       last workgroup: b = R'/R, b_j, rotation of zeta, freezing, halting
+//   K3  x_0 += a p;  for every active shift j: x_j += a_j p_j, p_j <- zeta_j r + b_j p_j;
+//       p <- r + b p  -- one pass over r and p serves all shifts (Section 3: the
+//       shifted updates are the next most expensive step; register reuse of r and p).
+//
+// The shift recurrences are the values forced by the collinearity r_j = zeta_j r:
+//   zeta' = zeta zeta_prev a_prev / (a b (zeta_prev - zeta) + zeta_prev a_prev (1 + s a)),
+//   a_j = a zeta'/zeta,  b_j = b' (zeta'/zeta)^2,  with s = sigma_j - sigma0 >= 0.
+// All scalar work stays on the device in FP64 (Section 3: the iteration constants are
+// computed on the GPU to avoid host round trips).  Reductions are deterministic: each
+// workgroup writes one partial, the last one to arrive sums them in a fixed order.
+#include "dev_common.h"
+#include "msc_internal.h"
+
+namespace msc {
+
+namespace {
+
+template <class R> __device__ __forceinline__ Csr<cplx<R>> pick_m(const MsArgs& a);
+template <> __device__ __forceinline__ Csr<float2> pick_m<float>(const MsArgs& a) { return a.m32; }
+template <> __device__ __forceinline__ Csr<double2> pick_m<double>(const MsArgs& a) { return a.m64; }
+template <class R> __device__ __forceinline__ Csr<cplx<R>> pick_mh(const MsArgs& a);
+template <> __device__ __forceinline__ Csr<float2> pick_mh<float>(const MsArgs& a) { return a.mh32; }
+template <> __device__ __forceinline__ Csr<double2> pick_mh<double>(const MsArgs& a) { return a.mh64; }
+
+// One CSR row times a vector, L lanes per row; the sum is returned in every lane.
+template <class R, int L>
+__device__ __forceinline__ cplx<R> row_dot(const Csr<cplx<R>>& m, const cplx<R>* __restrict__ x,
+                                           int64_t row, int lane) {
+  const int32_t beg = m.rowptr[row], end = m.rowptr[row + 1];
+  cplx<R> acc = czero<R>();
+  int32_t j = beg + lane;
+  for (; j + 3 * L < end; j += 4 * L) {
+    const int32_t c0 = m.col[j], c1 = m.col[j + L], c2 = m.col[j + 2 * L], c3 = m.col[j + 3 * L];
+    const cplx<R> v0 = m.val[j], v1 = m.val[j + L], v2 = m.val[j + 2 * L], v3 = m.val[j + 3 * L];
+    const cplx<R> x0 = x[c0], x1 = x[c1], x2 = x[c2], x3 = x[c3];
+    cfma<R>(acc, v0, x0);
+    cfma<R>(acc, v1, x1);
+    cfma<R>(acc, v2, x2);
+    cfma<R>(acc, v3, x3);
+  }
+  for (; j < end; j += L) {
+    const int32_t c = m.col[j];
+    const cplx<R> v = m.val[j];
+    cfma<R>(acc, v, x[c]);
+  }
+  return group_sum_c<L, R>(acc);
+}
+
+// The last workgroup sums gridDim.x partials (stride `stride`, offset `k`) in a fixed
+// order; the result is valid in thread 0.
+__device__ __forceinline__ double sum_partials(const double* partial, int count, int stride, int k) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < count; i += kBlock) s += load_agent(&partial[i * stride + k]);
+  return block_sum<kBlock>(s);
+}
+
+// ---- finalisation of K1: a and the per-shift zeta', a_j (wave 0, lane = shift) ----
+__device__ void finalize_k1(SolveState* st, double P) {
+  const int j = threadIdx.x;
+  if (j >= kWave) return;
+  const bool ok = (P > 0.0) && isfinite(P);
+  if (!ok) {
+    if (j == 0) {
+      st->P = P;
+      st->status = 1;
+      st->halt = 1;
+      st->k3_enable = 0;
+    }
+    return;
+  }
+  const double a = st->R / P;
+  if (j >= 1 && j < st->ns && st->active[j]) {
+    const double z = st->zeta[j], zp = st->zeta_prev[j];
+    const double ap = st->a_prev, b = st->b;
+    const double zn = z * zp * ap / (a * b * (zp - z) + zp * ap * (1.0 + st->s[j] * a));
+    st->zk[j] = zn;
+    st->ak[j] = a * zn / z;
+  }
+  if (j == 0) {
+    st->P = P;
+    st->a = a;
+  }
+}
+
+// ---- finalisation of K2: b, b_j, zeta rotation, freezing and halting -----------------
+__device__ void finalize_k2(SolveState* st, double Rn) {
+  const int j = threadIdx.x;
+  if (j >= kWave) return;
+  if (!isfinite(Rn)) {
+    if (j == 0) {
+      st->status = 1;
+      st->halt = 1;
+      st->k3_enable = 0;
+    }
+    return;
+  }
+  const double bn = Rn / st->R;
+  const int ns = st->ns;
+  const int it = st->iter + 1;
+  bool was_active = false, keep_p = false;
+  if (j >= 1 && j < ns && st->active[j]) {
+    was_active = true;
+    const double z = st->zeta[j], zn = st->zk[j];
+    const double q = zn / z;
+    st->bk[j] = bn * q * q;
+    st->zeta_prev[j] = z;
+    st->zeta[j] = zn;
+    keep_p = true;
+    if (st->freeze && zn * zn * Rn <= st->eps2) {
+      st->active[j] = 0;
+      st->freeze_iter[j] = it;
+      keep_p = false;
+    }
+  }
+  const uint64_t mask = __ballot(was_active);
+  if (was_active) {
+    const int pos = __popcll(mask & ((uint64_t(1) << j) - 1));
+    st->act_list[pos] = j;
+    st->act_upd_p[pos] = keep_p ? 1 : 0;
+  }
+  if (j == 0) {
+    st->nact = __popcll(mask);
+    st->b_new = bn;
+    st->a_prev = st->a;
+    st->b = bn;
+    st->R = Rn;
+    st->iter = it;
+    if (Rn <= st->eps2 || it >= st->max_iter) st->halt = 1;
+    st->k3_enable = 1;
+  }
+}
+
+// ---- K1 -------------------------------------------------------------------------------
+template <class R, int L, bool MHM>
+__global__ __launch_bounds__(kBlock) void k1_apply(MsArgs a) {
+  SolveState* st = a.st;
+  if (st->halt) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->k3_enable = 0;
+    return;
+  }
+  const Csr<cplx<R>> m = pick_m<R>(a);
+  const cplx<R>* __restrict__ p = static_cast<const cplx<R>*>(a.p);
+  cplx<R>* __restrict__ t = static_cast<cplx<R>*>(a.t);
+  const double sigma0 = st->sigma0;
+  constexpr int GPB = kBlock / L;
+  const int lane = threadIdx.x % L, grp = threadIdx.x / L;
+  int64_t beg, end;
+  block_range(a.n, GPB, beg, end);
+  double acc = 0.0;
+  for (int64_t row = beg + grp; row < end; row += GPB) {
+    const cplx<R> v = row_dot<R, L>(m, p, row, lane);
+    if (lane == 0) {
+      t[row] = v;
+      const cplx<R> pr = p[row];
+      if (MHM) {
+        acc += norm2d<R>(v) + sigma0 * norm2d<R>(pr);
+      } else {
+        acc += double(pr.x) * double(v.x) + double(pr.y) * double(v.y) + sigma0 * norm2d<R>(pr);
+      }
+    }
+  }
+  const double tot = block_sum<kBlock>(acc);
+  if (threadIdx.x == 0) store_agent(&a.sc.partial[blockIdx.x], tot);
+  if (!arrive_last(&a.sc.tickets[0])) return;
+  __shared__ double Psh;
+  const double P = sum_partials(a.sc.partial, gridDim.x, 1, 0);
+  if (threadIdx.x == 0) Psh = P;
+  __syncthreads();
+  finalize_k1(st, Psh);
+}
+
+// ---- K2 (A = M^H M): r <- r - a (M^H t + sigma0 p), R' = |r|^2 ------------------------
+template <class R, int L>
+__global__ __launch_bounds__(kBlock) void k2_mhm(MsArgs a) {
+  SolveState* st = a.st;
+  if (st->halt) return;
+  const Csr<cplx<R>> mh = pick_mh<R>(a);
+  const cplx<R>* __restrict__ t = static_cast<const cplx<R>*>(a.t);
+  const cplx<R>* __restrict__ p = static_cast<const cplx<R>*>(a.p);
+  cplx<R>* __restrict__ r = static_cast<cplx<R>*>(a.r);
+  const double sigma0 = st->sigma0;
+  const double step = st->a;
+  constexpr int GPB = kBlock / L;
+  const int lane = threadIdx.x % L, grp = threadIdx.x / L;
+  int64_t beg, end;
+  block_range(a.n, GPB, beg, end);
+  double acc = 0.0;
+  for (int64_t row = beg + grp; row < end; row += GPB) {
+    const cplx<R> q = row_dot<R, L>(mh, t, row, lane);
+    if (lane == 0) {
+      const double2 pr = to_d(p[row]);
+      const double2 rr = to_d(r[row]);
+      const double2 qd = to_d(q);
+      double2 nr;
+      nr.x = rr.x - step * (qd.x + sigma0 * pr.x);
+      nr.y = rr.y - step * (qd.y + sigma0 * pr.y);
+      const cplx<R> st_r = from_d<R>(nr);
+      r[row] = st_r;
+      acc += norm2d<R>(st_r);
+    }
+  }
+  const double tot = block_sum<kBlock>(acc);
+  if (threadIdx.x == 0) store_agent(&a.sc.partial[blockIdx.x], tot);
+  if (!arrive_last(&a.sc.tickets[1])) return;
+  __shared__ double Rsh;
+  const double Rn = sum_partials(a.sc.partial, gridDim.x, 1, 0);
+  if (threadIdx.x == 0) Rsh = Rn;
+  __syncthreads();
+  finalize_k2(st, Rsh);
+}
+
+// ---- K2 (A given): elementwise r <- r - a (t + sigma0 p) -------------------------------
+template <class R>
+__global__ __launch_bounds__(kBlock) void k2_herm(MsArgs a) {
+  SolveState* st = a.st;
+  if (st->halt) return;
+  const cplx<R>* __restrict__ t = static_cast<const cplx<R>*>(a.t);
+  const cplx<R>* __restrict__ p = static_cast<const cplx<R>*>(a.p);
+  cplx<R>* __restrict__ r = static_cast<cplx<R>*>(a.r);
+  const double sigma0 = st->sigma0;
+  const double step = st->a;
+  int64_t beg, end;
+  block_range(a.n, kBlock, beg, end);
+  double acc = 0.0;
+  for (int64_t i = beg + threadIdx.x; i < end; i += kBlock) {
+    const double2 pr = to_d(p[i]), rr = to_d(r[i]), td = to_d(t[i]);
+    double2 nr;
+    nr.x = rr.x - step * (td.x + sigma0 * pr.x);
+    nr.y = rr.y - step * (td.y + sigma0 * pr.y);
+    const cplx<R> st_r = from_d<R>(nr);
+    r[i] = st_r;
+    acc += norm2d<R>(st_r);
+  }
+  const double tot = block_sum<kBlock>(acc);
+  if (threadIdx.x == 0) store_agent(&a.sc.partial[blockIdx.x], tot);
+  if (!arrive_last(&a.sc.tickets[1])) return;
+  __shared__ double Rsh;
+  const double Rn = sum_partials(a.sc.partial, gridDim.x, 1, 0);
+  if (threadIdx.x == 0) Rsh = Rn;
+  __syncthreads();
+  finalize_k2(st, Rsh);
+}
+
+// ---- K3: fused update of every active shift from one read of r and p ------------------
+template <class R>
+__global__ __launch_bounds__(kBlock) void k3_update(MsArgs a) {
+  const SolveState* st = a.st;
+  if (!st->k3_enable) return;
+  const int64_t n = a.n;
+  const cplx<R>* __restrict__ rv = static_cast<const cplx<R>*>(a.r);
+  cplx<R>* __restrict__ pv = static_cast<cplx<R>*>(a.p);
+  cplx<R>* __restrict__ pk = static_cast<cplx<R>*>(a.pk);
+  double2* __restrict__ x = a.x;
+  const double step = st->a, bnew = st->b_new;
+  const int nact = st->nact;
+  double2* __restrict__ x0 = x + int64_t(st->orig[0]) * n;
+  int64_t beg, end;
+  block_range(n, kBlock, beg, end);
+  for (int64_t i = beg + threadIdx.x; i < end; i += kBlock) {
+    const cplx<R> rr = rv[i];
+    const cplx<R> pp = pv[i];
+    const double2 rd = to_d(rr), pd = to_d(pp);
+    double2 xv = x0[i];
+    xv.x = fma(step, pd.x, xv.x);
+    xv.y = fma(step, pd.y, xv.y);
+    x0[i] = xv;
+    int q = 0;
+    for (; q + 4 <= nact; q += 4) {
+      int jj[4];
+      cplx<R> pj[4];
+      double2 xj[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        jj[u] = st->act_list[q + u];
+        pj[u] = pk[int64_t(jj[u] - 1) * n + i];
+        xj[u] = x[int64_t(st->orig[jj[u]]) * n + i];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int j = jj[u];
+        const double2 pjd = to_d(pj[u]);
+        const double aj = st->ak[j];
+        xj[u].x = fma(aj, pjd.x, xj[u].x);
+        xj[u].y = fma(aj, pjd.y, xj[u].y);
+        x[int64_t(st->orig[j]) * n + i] = xj[u];
+        if (st->act_upd_p[q + u]) {
+          const double zj = st->zk[j], bj = st->bk[j];
+          double2 np;
+          np.x = fma(zj, rd.x, bj * pjd.x);
+          np.y = fma(zj, rd.y, bj * pjd.y);
+          pk[int64_t(j - 1) * n + i] = from_d<R>(np);
+        }
+      }
+    }
+    for (; q < nact; ++q) {
+      const int j = st->act_list[q];
+      const double2 pjd = to_d(pk[int64_t(j - 1) * n + i]);
+      double2* xp = x + int64_t(st->orig[j]) * n + i;
+      double2 xv2 = *xp;
+      const double aj = st->ak[j];
+      xv2.x = fma(aj, pjd.x, xv2.x);
+      xv2.y = fma(aj, pjd.y, xv2.y);
+      *xp = xv2;
+      if (st->act_upd_p[q]) {
+        const double zj = st->zk[j], bj = st->bk[j];
+        double2 np;
+        np.x = fma(zj, rd.x, bj * pjd.x);
+        np.y = fma(zj, rd.y, bj * pjd.y);
+        pk[int64_t(j - 1) * n + i] = from_d<R>(np);
+      }
+    }
+    double2 npd;
+    npd.x = fma(bnew, pd.x, rd.x);
+    npd.y = fma(bnew, pd.y, rd.y);
+    pv[i] = from_d<R>(npd);
+  }
+}
+
+// ---- initialisation: r = p = p_j = b, x = 0, |b|^2 ------------------------------------
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_init(MsArgs a) {
+  SolveState* st = a.st;
+  const int64_t n = a.n;
+  const int ns = st->ns;
+  cplx<R>* __restrict__ r = static_cast<cplx<R>*>(a.r);
+  cplx<R>* __restrict__ p = static_cast<cplx<R>*>(a.p);
+  cplx<R>* __restrict__ pk = static_cast<cplx<R>*>(a.pk);
+  int64_t beg, end;
+  block_range(n, kBlock, beg, end);
+  double acc = 0.0;
+  for (int64_t i = beg + threadIdx.x; i < end; i += kBlock) {
+    const double2 bv = a.b[i];
+    const cplx<R> br = from_d<R>(bv);
+    r[i] = br;
+    p[i] = br;
+    for (int j = 1; j < ns; ++j) pk[int64_t(j - 1) * n + i] = br;
+    for (int k = 0; k < ns; ++k) a.x[int64_t(k) * n + i] = double2{0.0, 0.0};
+    acc += fma(bv.x, bv.x, bv.y * bv.y);
+  }
+  const double tot = block_sum<kBlock>(acc);
+  if (threadIdx.x == 0) store_agent(&a.sc.partial[blockIdx.x], tot);
+  if (!arrive_last(&a.sc.tickets[3])) return;
+  const double B2 = sum_partials(a.sc.partial, gridDim.x, 1, 0);
+  if (threadIdx.x == 0) {
+    st->bnorm2 = B2;
+    st->R = B2;
+    st->eps2 = st->eps2 * B2;   // host stored tol^2 here
+    if (!(B2 > 0.0) || !isfinite(B2)) {
+      st->halt = 1;
+      st->k3_enable = 0;
+      if (!isfinite(B2)) st->status = 1;
+    }
+  }
+}
+
+// ---- reliable update: r = b - (A + sigma0) x_0 in FP64 --------------------------------
+template <int L, bool MHM>
+__global__ __launch_bounds__(kBlock) void k_ru_first(MsArgs a) {
+  // t64 = M x_0 (A = M^H M) -- first half of the FP64 operator
+  const SolveState* st = a.st;
+  if (st->halt) return;
+  const double2* __restrict__ x0 = a.x + int64_t(st->orig[0]) * a.n;
+  constexpr int GPB = kBlock / L;
+  const int lane = threadIdx.x % L, grp = threadIdx.x / L;
+  int64_t beg, end;
+  block_range(a.n, GPB, beg, end);
+  for (int64_t row = beg + grp; row < end; row += GPB) {
+    const double2 v = row_dot<double, L>(a.m64, x0, row, lane);
+    if (lane == 0) a.t64[row] = v;
+  }
+}
+
+template <class R, int L, bool MHM>
+__global__ __launch_bounds__(kBlock) void k_ru_second(MsArgs a) {
+  SolveState* st = a.st;
+  if (st->halt) return;
+  const double2* __restrict__ x0 = a.x + int64_t(st->orig[0]) * a.n;
+  cplx<R>* __restrict__ r = static_cast<cplx<R>*>(a.r);
+  const double sigma0 = st->sigma0;
+  constexpr int GPB = kBlock / L;
+  const int lane = threadIdx.x % L, grp = threadIdx.x / L;
+  int64_t beg, end;
+  block_range(a.n, GPB, beg, end);
+  double acc = 0.0;
+  for (int64_t row = beg + grp; row < end; row += GPB) {
+    const double2 q = MHM ? row_dot<double, L>(a.mh64, a.t64, row, lane)
+                          : row_dot<double, L>(a.m64, x0, row, lane);
+    if (lane == 0) {
+      const double2 bv = a.b[row], xv = x0[row];
+      double2 rt;
+      rt.x = bv.x - q.x - sigma0 * xv.x;
+      rt.y = bv.y - q.y - sigma0 * xv.y;
+      r[row] = from_d<R>(rt);
+      acc += fma(rt.x, rt.x, rt.y * rt.y);
+    }
+  }
+  const double tot = block_sum<kBlock>(acc);
+  if (threadIdx.x == 0) store_agent(&a.sc.partial[blockIdx.x], tot);
+  if (!arrive_last(&a.sc.tickets[2])) return;
+  const double Rt = sum_partials(a.sc.partial, gridDim.x, 1, 0);
+  if (threadIdx.x == 0) {
+    st->R = Rt;
+    st->n_reliable += 1;
+    if (!isfinite(Rt)) {
+      st->status = 1;
+      st->halt = 1;
+      st->k3_enable = 0;
+    } else if (Rt <= st->eps2) {
+      st->halt = 1;
+      st->k3_enable = 0;
+    }
+  }
+}
+
+// ---- verification: FP64 true residual norms of up to 8 solutions ---------------------
+constexpr int kVerifyChunk = 8;
+
+template <int L>
+__device__ __forceinline__ void row_dot_multi(const Csr<double2>& m, const double2* __restrict__ x,
+                                              int64_t n, int kc, int64_t row, int lane,
+                                              double2 (&acc)[kVerifyChunk]) {
+#pragma unroll
+  for (int q = 0; q < kVerifyChunk; ++q) acc[q] = double2{0.0, 0.0};
+  const int32_t beg = m.rowptr[row], end = m.rowptr[row + 1];
+  for (int32_t j = beg + lane; j < end; j += L) {
+    const int32_t c = m.col[j];
+    const double2 v = m.val[j];
+#pragma unroll
+    for (int q = 0; q < kVerifyChunk; ++q)
+      if (q < kc) cfma<double>(acc[q], v, x[int64_t(q) * n + c]);
+  }
+#pragma unroll
+  for (int q = 0; q < kVerifyChunk; ++q) acc[q] = group_sum_c<L, double>(acc[q]);
+}
+
+template <int L>
+__global__ __launch_bounds__(kBlock) void k_verify_first(Csr<double2> m, const double2* x, int64_t n,
+                                                         int kc, double2* u) {
+  constexpr int GPB = kBlock / L;
+  const int lane = threadIdx.x % L, grp = threadIdx.x / L;
+  int64_t beg, end;
+  block_range(n, GPB, beg, end);
+  double2 acc[kVerifyChunk];
+  for (int64_t row = beg + grp; row < end; row += GPB) {
+    row_dot_multi<L>(m, x, n, kc, row, lane, acc);
+    if (lane == 0) {
+#pragma unroll
+      for (int q = 0; q < kVerifyChunk; ++q)
+        if (q < kc) u[int64_t(q) * n + row] = acc[q];
+    }
+  }
+}
+
+struct VerifyArgs {
+  Csr<double2> m;        // M^H (MHM) or A (HERM)
+  const double2* in;     // U = M X (MHM) or X (HERM), chunk of kc vectors
+  const double2* x;      // X, chunk of kc vectors
+  const double2* b;
+  double sig[kVerifyChunk];
+  int64_t n;
+  int kc;
+  double* partial;
+  unsigned* ticket;
+  double* out;           // res2 of the chunk
+};
+
+template <int L>
+__global__ __launch_bounds__(kBlock) void k_verify_second(VerifyArgs v) {
+  constexpr int GPB = kBlock / L;
+  const int lane = threadIdx.x % L, grp = threadIdx.x / L;
+  int64_t beg, end;
+  block_range(v.n, GPB, beg, end);
+  double2 acc[kVerifyChunk];
+  double nrm[kVerifyChunk];
+#pragma unroll
+  for (int q = 0; q < kVerifyChunk; ++q) nrm[q] = 0.0;
+  for (int64_t row = beg + grp; row < end; row += GPB) {
+    row_dot_multi<L>(v.m, v.in, v.n, v.kc, row, lane, acc);
+    if (lane == 0) {
+      const double2 bv = v.b[row];
+#pragma unroll
+      for (int q = 0; q < kVerifyChunk; ++q) {
+        if (q < v.kc) {
+          const double2 xv = v.x[int64_t(q) * v.n + row];
+          const double rx = bv.x - acc[q].x - v.sig[q] * xv.x;
+          const double ry = bv.y - acc[q].y - v.sig[q] * xv.y;
+          nrm[q] += fma(rx, rx, ry * ry);
+        }
+      }
+    }
+  }
+  block_sum_k<kBlock, kVerifyChunk>(nrm);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < kVerifyChunk; ++q) store_agent(&v.partial[blockIdx.x * kVerifyChunk + q], nrm[q]);
+  }
+  if (!arrive_last(v.ticket)) return;
+  for (int q = 0; q < v.kc; ++q) {
+    const double s = sum_partials(v.partial, gridDim.x, kVerifyChunk, q);
+    if (threadIdx.x == 0) v.out[q] = s;
+  }
+}
+
+// ---- plain SpMV with optional shift epilogue (operator application) -------------------
+template <class R, int L>
+__global__ __launch_bounds__(kBlock) void k_spmv(Csr<cplx<R>> m, const cplx<R>* x, cplx<R>* y,
+                                                 int64_t n) {
+  constexpr int GPB = kBlock / L;
+  const int lane = threadIdx.x % L, grp = threadIdx.x / L;
+  int64_t beg, end;
+  block_range(n, GPB, beg, end);
+  for (int64_t row = beg + grp; row < end; row += GPB) {
+    const cplx<R> v = row_dot<R, L>(m, x, row, lane);
+    if (lane == 0) y[row] = v;
+  }
+}
+
+template <class R>
+__global__ void k_shift_out(const cplx<R>* q, const double2* in, double2* out, double shift, int64_t n) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const double2 qd = to_d(q[i]), xv = in[i];
+    out[i] = double2{qd.x + shift * xv.x, qd.y + shift * xv.y};
+  }
+}
+
+__global__ void k_to32(const double2* in, float2* out, int64_t n) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x)
+    out[i] = float2{float(in[i].x), float(in[i].y)};
+}
+
+int grid_rows(int64_t n, int rows_per_pass) {
+  int64_t g = (n + rows_per_pass - 1) / rows_per_pass;
+  if (g > kMaxGrid) g = kMaxGrid;
+  if (g < kXcds) g = kXcds;
+  g = (g + kXcds - 1) / kXcds * kXcds;
+  return int(g);
+}
+
+// Dispatch on lanes per row.
+#define MSC_LANES_SWITCH(LANES, CALL) \
+  switch (LANES) {                    \
+    case 4: { constexpr int LL = 4; CALL; } break;   \
+    case 8: { constexpr int LL = 8; CALL; } break;   \
+    case 16: { constexpr int LL = 16; CALL; } break;  \
+    case 32: { constexpr int LL = 32; CALL; } break;  \
+    default: return hipErrorInvalidValue;            \
+  }
+
+template <class R>
+hipError_t iteration_impl(const MsArgs& a, hipStream_t s) {
+  const int g1 = grid_rows(a.n, kBlock / a.lanes);
+  const int g3 = grid_rows(a.n, kBlock);
+  if (a.kind == MSC_A_MHM) {
+    MSC_LANES_SWITCH(a.lanes, (k1_apply<R, LL, true><<<g1, kBlock, 0, s>>>(a)));
+    MSC_LANES_SWITCH(a.lanes, (k2_mhm<R, LL><<<g1, kBlock, 0, s>>>(a)));
+  } else {
+    MSC_LANES_SWITCH(a.lanes, (k1_apply<R, LL, false><<<g1, kBlock, 0, s>>>(a)));
+    k2_herm<R><<<g3, kBlock, 0, s>>>(a);
+  }
+  k3_update<R><<<g3, kBlock, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+template <class R>
+hipError_t reliable_impl(const MsArgs& a, hipStream_t s) {
+  const int g1 = grid_rows(a.n, kBlock / a.lanes);
+  if (a.kind == MSC_A_MHM) {
+    MSC_LANES_SWITCH(a.lanes, (k_ru_first<LL, true><<<g1, kBlock, 0, s>>>(a)));
+    MSC_LANES_SWITCH(a.lanes, (k_ru_second<R, LL, true><<<g1, kBlock, 0, s>>>(a)));
+  } else {
+    MSC_LANES_SWITCH(a.lanes, (k_ru_second<R, LL, false><<<g1, kBlock, 0, s>>>(a)));
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+int default_grid(int64_t n, int lanes) { return grid_rows(n, kBlock / lanes); }
+
+hipError_t launch_init(int prec, const MsArgs& a, hipStream_t s) {
+  const int g3 = grid_rows(a.n, kBlock);
+  if (prec == MSC_PREC_MIXED)
+    k_init<float><<<g3, kBlock, 0, s>>>(a);
+  else
+    k_init<double><<<g3, kBlock, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_iteration(int prec, const MsArgs& a, hipStream_t s) {
+  return prec == MSC_PREC_MIXED ? iteration_impl<float>(a, s) : iteration_impl<double>(a, s);
+}
+
+hipError_t launch_reliable(int prec, const MsArgs& a, hipStream_t s) {
+  return prec == MSC_PREC_MIXED ? reliable_impl<float>(a, s) : reliable_impl<double>(a, s);
+}
+
+hipError_t launch_verify(const MsArgs& a, const double* sigma_by_caller_index, int k0, int kc,
+                         double2* u64, hipStream_t s) {
+  if (kc < 1 || kc > kVerifyChunk) return hipErrorInvalidValue;
+  const int g1 = grid_rows(a.n, kBlock / a.lanes);
+  const double2* xc = a.x + int64_t(k0) * a.n;
+  VerifyArgs v;
+  v.in = xc;
+  v.x = xc;
+  v.b = a.b;
+  for (int q = 0; q < kVerifyChunk; ++q) v.sig[q] = q < kc ? sigma_by_caller_index[k0 + q] : 0.0;
+  v.n = a.n;
+  v.kc = kc;
+  v.partial = a.sc.partial;
+  v.ticket = &a.sc.tickets[4];
+  v.out = a.sc.res2 + k0;
+  if (a.kind == MSC_A_MHM) {
+    MSC_LANES_SWITCH(a.lanes, (k_verify_first<LL><<<g1, kBlock, 0, s>>>(a.m64, xc, a.n, kc, u64)));
+    v.m = a.mh64;
+    v.in = u64;
+  } else {
+    v.m = a.m64;
+  }
+  MSC_LANES_SWITCH(a.lanes, (k_verify_second<LL><<<g1, kBlock, 0, s>>>(v)));
+  return hipGetLastError();
+}
+
+hipError_t launch_apply(int kind, int prec, int lanes, int64_t n, const Csr<double2>& m64,
+                        const Csr<double2>& mh64, const Csr<float2>& m32,
+                        const Csr<float2>& mh32, const double2* in, double2* out,
+                        double shift, void* tmp_a, void* tmp_b, hipStream_t s) {
+  const int g1 = grid_rows(n, kBlock / lanes);
+  const int g3 = grid_rows(n, kBlock);
+  if (prec == MSC_PREC_MIXED) {
+    float2* a32 = static_cast<float2*>(tmp_a);
+    float2* b32 = static_cast<float2*>(tmp_b);
+    k_to32<<<g3, kBlock, 0, s>>>(in, a32, n);
+    MSC_LANES_SWITCH(lanes, (k_spmv<float, LL><<<g1, kBlock, 0, s>>>(m32, a32, b32, n)));
+    if (kind == MSC_A_MHM) {
+      MSC_LANES_SWITCH(lanes, (k_spmv<float, LL><<<g1, kBlock, 0, s>>>(mh32, b32, a32, n)));
+      k_shift_out<float><<<g3, kBlock, 0, s>>>(a32, in, out, shift, n);
+    } else {
+      k_shift_out<float><<<g3, kBlock, 0, s>>>(b32, in, out, shift, n);
+    }
+  } else {
+    double2* a64 = static_cast<double2*>(tmp_a);
+    MSC_LANES_SWITCH(lanes, (k_spmv<double, LL><<<g1, kBlock, 0, s>>>(m64, in, a64, n)));
+    if (kind == MSC_A_MHM) {
+      double2* b64 = static_cast<double2*>(tmp_b);
+      MSC_LANES_SWITCH(lanes, (k_spmv<double, LL><<<g1, kBlock, 0, s>>>(mh64, a64, b64, n)));
+      k_shift_out<double><<<g3, kBlock, 0, s>>>(b64, in, out, shift, n);
+    } else {
+      k_shift_out<double><<<g3, kBlock, 0, s>>>(a64, in, out, shift, n);
+    }
+  }
+  return hipGetLastError();
+}
+
+}  // namespace msc

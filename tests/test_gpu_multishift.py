@@ -1,0 +1,247 @@
+"""GPU parity of the multishift solve against the FP64 oracle, through the C ABI."""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _op(p, cuda):
+    from paper_1102_2143_amd import Operator
+    op = Operator(p["rowptr"], p["col"], p["vals"], p["n"], kind=p.get("kind", "mhm"), device=cuda)
+    return op
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b, axis=-1) / np.linalg.norm(b, axis=-1)
+
+
+@pytest.fixture(scope="module")
+def c0():
+    p = W.make_config("c0")
+    p["apply"] = O.shifted_apply("mhm", p["rowptr"], p["col"], p["vals"], p["n"])
+    p["ref"] = O.cg_m(p["apply"], p["b"], p["sigma"], tol=1e-10)
+    return p
+
+
+# ---- operator application (the SpMV pair of the iteration) ----------------------------
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-14), ("mixed", 2e-6)])
+def test_apply_staggered(c0, cuda, prec, tol):
+    print(f"[gpu] apply staggered c0 prec={prec}", flush=True)
+    op = _op(c0, cuda)
+    v = W.gaussian_rhs(c0["n"], 5)
+    for shift in (0.0, 0.37):
+        got = op.apply(v, shift=shift, prec=prec).cpu().numpy()
+        ref = c0["apply"](v, shift)
+        assert _rel(got, ref) <= tol
+    op.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-14), ("mixed", 2e-6)])
+def test_apply_random_with_empty_rows(cuda, prec, tol):
+    print(f"[gpu] apply random csr with empty rows prec={prec}", flush=True)
+    from paper_1102_2143_amd import Operator
+    n = 333
+    rowptr, col, vals = W.random_sparse_csr(n, 37, 12, diag=2.0, empty_rows=(0, 5, 332))
+    for kind in ("mhm", "herm"):
+        op = Operator(rowptr, col, vals, n, kind=kind, device=cuda)
+        v = W.gaussian_rhs(n, 13)
+        got = op.apply(v, shift=0.5, prec=prec).cpu().numpy()
+        ref = O.shifted_apply(kind, rowptr, col, vals, n)(v, 0.5)
+        assert _rel(got, ref) <= tol
+        op.close()
+
+
+def test_apply_single_row(cuda):
+    from paper_1102_2143_amd import Operator
+    rowptr, col, vals = np.array([0, 1]), np.array([0], np.int32), np.array([2.0 - 1.0j])
+    op = Operator(rowptr, col, vals, 1, kind="mhm", device=cuda)
+    got = op.apply(np.array([1.0 + 1.0j]), shift=0.5).cpu().numpy()
+    assert np.allclose(got, (5.0 + 0.5) * (1.0 + 1.0j), rtol=0, atol=1e-15)
+    op.close()
+
+
+@pytest.mark.parametrize("lanes", [4, 8, 16, 32])
+def test_apply_every_lane_width(c0, cuda, lanes):
+    # the solve with every lanes-per-row variant reproduces the oracle
+    op = _op(c0, cuda)
+    op.set_shifts(c0["sigma"])
+    x, info = op.solve(c0["b"], tol=1e-10, prec="fp64", lanes=lanes)
+    assert info["status"] == "ok"
+    assert np.all(_rel(x.cpu().numpy(), c0["ref"]["x"]) <= 1e-8)
+    op.close()
+
+
+# ---- FP64 multishift parity -----------------------------------------------------------
+def test_c0_fp64_matches_oracle(c0, cuda):
+    print("[gpu] c0 fp64 solve", flush=True)
+    op = _op(c0, cuda)
+    op.set_shifts(c0["sigma"])
+    x, info = op.solve(c0["b"], tol=1e-10, prec="fp64")
+    xg = x.cpu().numpy()
+    ref = c0["ref"]
+    assert info["status"] == "ok", info
+    assert abs(info["iters"] - ref["iters"]) <= 2
+    assert np.all(_rel(xg, ref["x"]) <= 1e-8)
+    assert np.all(info["true_rel_res"] <= 1e-10)
+    # the library's FP64 residuals agree with the oracle's own evaluation
+    rho = np.array([np.linalg.norm(c0["b"] - c0["apply"](xg[k], c0["sigma"][k]))
+                    for k in range(xg.shape[0])]) / np.linalg.norm(c0["b"])
+    assert np.allclose(rho, info["true_rel_res"], rtol=1e-3, atol=1e-14)
+    # freeze iterations within +-2 of the oracle's
+    assert np.all(np.abs(info["freeze_iter"] - ref["freeze_iter"]) <= 2)
+    op.close()
+
+
+def test_c0_against_dense_solve(c0, cuda):
+    op = _op(c0, cuda)
+    op.set_shifts(c0["sigma"])
+    x, info = op.solve(c0["b"], tol=1e-12, prec="fp64")
+    xd = O.dense_solve("mhm", c0["rowptr"], c0["col"], c0["vals"], c0["n"], c0["b"], c0["sigma"])
+    assert np.all(_rel(x.cpu().numpy(), xd) <= 1e-10)
+    op.close()
+
+
+def test_deterministic(c0, cuda):
+    op = _op(c0, cuda)
+    op.set_shifts(c0["sigma"])
+    x1, i1 = op.solve(c0["b"], tol=1e-10)
+    x2, i2 = op.solve(c0["b"], tol=1e-10)
+    assert i1["iters"] == i2["iters"]
+    assert bool((x1 == x2).all())
+    op.close()
+
+
+def test_shift_order_and_duplicates(c0, cuda):
+    op = _op(c0, cuda)
+    sigma = np.array([0.5, 1e-3, 0.5, 0.02, 1e-3])
+    op.set_shifts(sigma)
+    x, info = op.solve(c0["b"], tol=1e-11)
+    xd = O.dense_solve("mhm", c0["rowptr"], c0["col"], c0["vals"], c0["n"], c0["b"], sigma)
+    xg = x.cpu().numpy()
+    assert np.all(_rel(xg, xd) <= 1e-9)
+    # duplicates: the copy of the driving shift takes its own (equal in exact arithmetic)
+    # recurrence, so agreement is to rounding, not bitwise
+    assert np.array_equal(xg[0], xg[2])
+    assert _rel(xg[4], xg[1]) <= 1e-13
+    op.close()
+
+
+def test_herm_laplacian(cuda):
+    print("[gpu] herm laplacian", flush=True)
+    rowptr, col, vals = W.laplacian7_csr((9, 7, 5), 31)
+    n = 315
+    b = W.gaussian_rhs(n, 32)
+    sigma = W.logspace_shifts(1e-4, 1.0, 10)
+    p = dict(rowptr=rowptr, col=col, vals=vals, n=n, kind="herm")
+    op = _op(p, cuda)
+    op.set_shifts(sigma)
+    x, info = op.solve(b, tol=1e-10)
+    ref = O.cg_m(O.shifted_apply("herm", rowptr, col, vals, n), b, sigma, tol=1e-10)
+    assert info["status"] == "ok"
+    assert abs(info["iters"] - ref["iters"]) <= 2
+    assert np.all(_rel(x.cpu().numpy(), ref["x"]) <= 1e-8)
+    op.close()
+
+
+def test_non_normal_random_operator(cuda):
+    rowptr, col, vals = W.random_sparse_csr(400, 9, 44, diag=5.0, empty_rows=(7,))
+    n = 400
+    b = W.gaussian_rhs(n, 45)
+    # an empty row of M makes M^H M singular, so every shift is positive
+    sigma = np.array([0.05, 0.3, 2.0])
+    p = dict(rowptr=rowptr, col=col, vals=vals, n=n, kind="mhm")
+    op = _op(p, cuda)
+    op.set_shifts(sigma)
+    x, info = op.solve(b, tol=1e-12)
+    xd = O.dense_solve("mhm", rowptr, col, vals, n, b, sigma)
+    assert np.all(_rel(x.cpu().numpy(), xd) <= 1e-9)
+    op.close()
+
+
+# ---- edge cases and failure handling -----------------------------------------------------
+def test_zero_rhs(c0, cuda):
+    op = _op(c0, cuda)
+    op.set_shifts(c0["sigma"])
+    x, info = op.solve(np.zeros(c0["n"], complex))
+    assert info["status"] == "ok" and info["iters"] == 0
+    assert not bool(x.abs().max() > 0)
+    op.close()
+
+
+def test_iteration_limit(c0, cuda):
+    op = _op(c0, cuda)
+    op.set_shifts(c0["sigma"])
+    x, info = op.solve(c0["b"], max_iter=3)
+    assert info["status"] == "notconv" and info["iters"] == 3
+    ref = O.cg_m(c0["apply"], c0["b"], c0["sigma"], tol=1e-10, max_iter=3)
+    assert np.all(_rel(x.cpu().numpy(), ref["x"]) <= 1e-12)
+    op.close()
+
+
+def test_indefinite_shift_is_breakdown(c0, cuda):
+    from paper_1102_2143_amd import MscError
+    op = _op(c0, cuda)
+    op.set_shifts([-50.0, 1.0])
+    with pytest.raises(MscError, match="breakdown"):
+        op.solve(c0["b"])
+    op.close()
+
+
+def test_nan_rhs_is_breakdown(c0, cuda):
+    op = _op(c0, cuda)
+    op.set_shifts(c0["sigma"])
+    b = c0["b"].copy()
+    b[3] = np.nan
+    x, info = op.solve(b, check=False)
+    assert info["status"] == "breakdown"
+    op.close()
+
+
+def test_invalid_csr_rejected(cuda):
+    from paper_1102_2143_amd import MscError, Operator
+    rowptr = np.array([0, 2, 1, 3])
+    col = np.array([0, 1, 2], np.int32)
+    with pytest.raises(MscError, match="invalid CSR"):
+        Operator(rowptr, col, np.ones(3, complex), 3, device=cuda)
+    with pytest.raises(MscError, match="column out of range"):
+        Operator(np.array([0, 1, 2, 3]), np.array([0, 1, 3], np.int32), np.ones(3, complex), 3,
+                 device=cuda)
+
+
+def test_update_values(c0, cuda):
+    op = _op(c0, cuda)
+    op.set_shifts(c0["sigma"])
+    p2 = W.staggered_problem((4, 4, 4, 4), 0.1, 77, 2000, (1e-4, 1.0, 8))
+    op.update_values(p2["vals"])
+    x, info = op.solve(c0["b"], tol=1e-11)
+    xd = O.dense_solve("mhm", p2["rowptr"], p2["col"], p2["vals"], p2["n"], c0["b"], c0["sigma"])
+    assert np.all(_rel(x.cpu().numpy(), xd) <= 1e-9)
+    op.close()
+
+
+# ---- full-size FP64 case: 16^4 ------------------------------------------------------------
+def test_c1_fp64_full_size(cuda):
+    print("[gpu] c1 16^4 fp64 solve", flush=True)
+    p = W.make_config("c1")
+    op = _op(p, cuda)
+    op.set_shifts(p["sigma"])
+    x, info = op.solve(p["b"], tol=1e-10, prec="fp64")
+    xg = x.cpu().numpy()
+    print(f"[gpu] c1 fp64 iters={info['iters']} max res={info['true_rel_res'].max():.3e} "
+          f"t={info['seconds']:.3f}s", flush=True)
+    assert info["status"] == "ok"
+    ap = O.shifted_apply("mhm", p["rowptr"], p["col"], p["vals"], p["n"])
+    bn = np.linalg.norm(p["b"])
+    rho = np.array([np.linalg.norm(p["b"] - ap(xg[k], p["sigma"][k])) for k in range(xg.shape[0])]) / bn
+    assert np.all(rho <= 1.0e-10)
+    # iteration count equals plain CG on A + sigma_min (the driving system) within +-2
+    ref = O.cg(ap, p["b"], shift=float(p["sigma"].min()), tol=1e-10)
+    assert abs(info["iters"] - ref["iters"]) <= 2
+    # sampled entries of the largest-shift solution against the driving-independent CG
+    k = int(np.argmax(p["sigma"]))
+    ref_k = O.cg(ap, p["b"], shift=float(p["sigma"][k]), tol=1e-12)["x"]
+    assert _rel(xg[k], ref_k) <= 1e-8
+    op.close()
