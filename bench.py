@@ -1,0 +1,191 @@
+"""Benchmark: shifted-solves/s to relative residual 1e-10 on one MI355X.
+
+A step is one complete multishift solve of the workload (all shifts to true relative
+residual <= 1e-10, including the FP64 verification and, for the mixed path, the
+reliable updates and per-shift refinement), with the operator and right-hand side
+already resident in HBM.  Prints one JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--workload c1] [--prec mixed|fp64]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "shifted-solves/s & HBM GB/s to rel.residual 1e-10: mixed+batched vs FP64 plain"
+PEAK_HBM_GBS = 8000.0
+WORKLOAD_NAMES = {
+    "c1": "16^4 staggered M^H M, m=0.05, 12 shifts in [1e-5,10], tol 1e-10",
+    "c2": "32^3x64 staggered M^H M, m=0.02, 16 shifts in [1e-6,10], tol 1e-10",
+    "c0": "4^4 staggered M^H M, m=0.1, 8 shifts in [1e-4,1], tol 1e-10",
+}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_bytes(kind, prec, n, nnz, nnz_h, act_avg):
+    """Algorithmic bytes of one launch of K1, K2, K3 (each array touched once)."""
+    w = 8.0 if prec == "mixed" else 16.0
+    vb = w
+    k1 = nnz * (vb + 4) + 4 * (n + 1) + n * w + n * w
+    if kind == "mhm":
+        k2 = nnz_h * (vb + 4) + 4 * (n + 1) + n * w + n * w + 2 * n * w
+    else:
+        k2 = n * w + n * w + 2 * n * w
+    k3 = n * (w + 2 * w + 32.0) + act_avg * n * (32.0 + 2 * w)
+    return {"K1": k1, "K2": k2, "K3": k3}
+
+
+def cpu_baseline(prob, sample_iters, full_iters):
+    """Time the FP64 oracle on a bounded sample of the same solve (single thread)."""
+    import oracle as O
+    from threadpoolctl import threadpool_limits
+
+    ap = O.shifted_apply("mhm", prob["rowptr"], prob["col"], prob["vals"], prob["n"])
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        O.cg_m(ap, prob["b"], prob["sigma"], tol=prob["tol"], max_iter=sample_iters)
+        dt = time.perf_counter() - t0
+    per_iter = dt / sample_iters
+    est = per_iter * full_iters
+    ns = prob["sigma"].size
+    return {"value": ns / est, "unit": "shifted-solves/s", "cores": 1, "kind": "oracle",
+            "sample": (f"oracle CG-M (numpy/scipy FP64, 1 thread) for {sample_iters} of the "
+                       f"{full_iters} iterations of the same solve, {dt:.1f} s incl. final "
+                       f"residual check; scaled by iteration count"),
+            "host_cpus": os.cpu_count(), "cpu_model": platform.processor() or platform.machine()}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c1", choices=sorted(WORKLOAD_NAMES))
+    ap.add_argument("--prec", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--timing", type=int, default=4, help="sample every k-th iteration's kernels")
+    ap.add_argument("--cpu-sample-iters", type=int, default=60)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(the solve would shard by lattice rows with a halo exchange; see DESIGN.md)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workloads as W
+    from paper_1102_2143_amd import Operator
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    prob = W.make_config(args.workload)
+    log(f"generated {args.workload}: n={prob['n']} nnz={prob['vals'].size} "
+        f"ns={prob['sigma'].size} in {time.perf_counter() - t0:.1f}s")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    op = Operator(prob["rowptr"], prob["col"], prob["vals"], prob["n"], kind="mhm", device=dev)
+    op.set_shifts(prob["sigma"])
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    b = torch.from_numpy(prob["b"]).to(dev)
+    x = torch.empty((prob["sigma"].size, prob["n"]), dtype=torch.complex128, device=dev)
+    kw = dict(tol=prob["tol"], prec=args.prec, timing=args.timing)
+
+    for i in range(args.warmup):
+        _, info = op.solve(b, out=x, **kw)
+        log(f"warmup {i}: {info['status']} iters={info['iters']} {info['seconds']:.4f}s")
+    torch.cuda.synchronize()
+    infos = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        _, info = op.solve(b, out=x, **kw)
+        infos.append(info)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    for i, info in enumerate(infos):
+        log(f"step {i}: {info['status']} iters={info['iters']} refine={info['refine_iters']} "
+            f"max true res={info['true_rel_res'].max():.3e} {info['seconds']:.4f}s")
+    ok = all(inf["status"] == "ok" and inf["true_rel_res"].max() <= prob["tol"] for inf in infos)
+
+    ns = prob["sigma"].size
+    n, nnz = prob["n"], prob["vals"].size
+    ms_per_step = 1e3 * wall / args.steps
+    value = ns * args.steps / wall
+    iters = infos[-1]["iters"]
+    alg_bytes = float(np.mean([inf["alg_bytes"] for inf in infos]))
+    eff_gbs = alg_bytes / (wall / args.steps) / 1e9
+
+    # dominant kernel from the sampled HIP-event timings of the timed steps
+    drive = int(np.argmin(prob["sigma"]))
+    fi = infos[-1]["freeze_iter"]
+    act_sum = sum((fi[k] if fi[k] >= 0 else iters) for k in range(ns) if k != drive)
+    act_avg = act_sum / max(iters, 1)
+    kb = kernel_bytes("mhm", args.prec, n, nnz, nnz, act_avg)
+    samples = sum(inf["kernel_samples"] for inf in infos)
+    kms = np.sum([inf["kernel_ms"] for inf in infos], axis=0)
+    names = ["K1", "K2", "K3"]
+    roofline = None
+    kernels = {}
+    if samples > 0:
+        for k, nm in enumerate(names):
+            avg_ms = kms[k] / samples
+            kernels[nm] = {"avg_us": 1e3 * avg_ms, "alg_bytes": kb[nm],
+                           "gbs": kb[nm] / (avg_ms * 1e-3) / 1e9}
+        dom = max(names, key=lambda nm: kernels[nm]["avg_us"])
+        ach = kernels[dom]["gbs"]
+        roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                    "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": None, "kernel": dom,
+                    "kernel_avg_us": round(kernels[dom]["avg_us"], 2)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log(f"cpu baseline: oracle for {args.cpu_sample_iters} iterations")
+        cpu = cpu_baseline(prob, args.cpu_sample_iters, iters)
+
+    line = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "shifted-solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.prec == "fp64" else "f32+f64",
+        "data": "synthetic (seeded Haar SU(3) links, complex Gaussian b)",
+        "config": {"workload": f"{args.workload}: {WORKLOAD_NAMES[args.workload]}", "n": n,
+                   "nnz_M": nnz, "ns": ns, "prec": args.prec, "iters": iters,
+                   "parallelism": "single GPU"},
+        "converged": ok,
+        "max_true_rel_res": float(max(inf["true_rel_res"].max() for inf in infos)),
+        "effective_gbs": round(eff_gbs, 1),
+        "iters_per_s": round(iters * args.steps / wall, 1),
+        "setup_s": round(setup_s, 3),
+        "kernels": {k: {kk: round(vv, 2) for kk, vv in v.items()} for k, v in kernels.items()},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+    op.close()
+
+
+if __name__ == "__main__":
+    main()

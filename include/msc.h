@@ -69,7 +69,9 @@ typedef struct {
     int32_t refine_max_iter; /* iteration limit of each refinement system          (10000) */
     int32_t lanes;           /* lanes per CSR row, 0 = automatic                    (0)    */
     int32_t verify;          /* compute FP64 true residuals at the end              (1)    */
-    int32_t reserved[5];
+    int32_t timing;          /* time the iteration kernels with HIP events on every
+                                timing-th iteration, 0 = off                        (0)    */
+    int32_t reserved[4];
 } msc_params;
 
 /* Per-solve report.  Array members are caller-owned host arrays of length ns (or
@@ -83,7 +85,11 @@ typedef struct {
     int32_t* freeze_iter;    /* [ns] iteration at which shift k froze, -1 if never      */
     double seconds;          /* wall time of the call                                   */
     double alg_bytes;        /* algorithmic HBM bytes moved by the call's kernels       */
-    double reserved[4];
+    double kernel_ms[3];     /* with timing on: summed durations of the sampled K1 (first
+                                operator half), K2 (second half + residual update) and K3
+                                (all-shift update) launches, milliseconds              */
+    int32_t kernel_samples;  /* number of sampled iterations behind kernel_ms          */
+    int32_t reserved_i;
 } msc_info;
 
 /* Fill *p with the defaults listed above. */

@@ -39,7 +39,8 @@ class Params(ctypes.Structure):
         ("refine_max_iter", ctypes.c_int32),
         ("lanes", ctypes.c_int32),
         ("verify", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 5),
+        ("timing", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 4),
     ]
 
 
@@ -53,7 +54,9 @@ class Info(ctypes.Structure):
         ("freeze_iter", ctypes.POINTER(ctypes.c_int32)),
         ("seconds", ctypes.c_double),
         ("alg_bytes", ctypes.c_double),
-        ("reserved", ctypes.c_double * 4),
+        ("kernel_ms", ctypes.c_double * 3),
+        ("kernel_samples", ctypes.c_int32),
+        ("reserved_i", ctypes.c_int32),
     ]
 
 

@@ -34,7 +34,7 @@ def _ptr(t: torch.Tensor):
 
 def make_params(tol=1e-10, prec="fp64", max_iter=10000, reliable_every=50, freeze=True,
                 refine=True, poll_every=16, inner_tol=1e-7, refine_max_iter=10000, lanes=0,
-                verify=True) -> L.Params:
+                verify=True, timing=0) -> L.Params:
     lib = L.load()
     p = L.Params()
     lib.msc_params_default(ctypes.byref(p))
@@ -49,6 +49,7 @@ def make_params(tol=1e-10, prec="fp64", max_iter=10000, reliable_every=50, freez
     p.refine_max_iter = int(refine_max_iter)
     p.lanes = int(lanes)
     p.verify = int(bool(verify))
+    p.timing = int(timing)
     return p
 
 
@@ -156,7 +157,8 @@ def _info_dict(st, info, rel, fi):
                 refine_iters=int(info.refine_iters), n_reliable=int(info.n_reliable),
                 n_refined=int(info.n_refined), true_rel_res=np.array(rel[:]),
                 freeze_iter=np.array(fi[:]), seconds=float(info.seconds),
-                alg_bytes=float(info.alg_bytes))
+                alg_bytes=float(info.alg_bytes), kernel_ms=np.array(info.kernel_ms[:]),
+                kernel_samples=int(info.kernel_samples))
 
 
 def solve_batched(ops, bs, stream=None, check=True, **kw):

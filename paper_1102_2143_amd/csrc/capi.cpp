@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -148,10 +149,27 @@ double iter_bytes(int kind, int prec, double n, double nnz, double nnz_h, double
   return iters * (mat + vec) + act_sum * per_shift;
 }
 
+// Events for sampled per-kernel timing; destroyed with the pool.
+struct EventPool {
+  std::vector<std::array<hipEvent_t, 4>> groups;
+  hipEvent_t* next() {
+    std::array<hipEvent_t, 4> g{};
+    for (auto& e : g)
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    groups.push_back(g);
+    return groups.back().data();
+  }
+  ~EventPool() {
+    for (auto& g : groups)
+      for (auto e : g)
+        if (e) (void)hipEventDestroy(e);
+  }
+};
+
 msc_status run_multishift(msc_op op, const double* d_b, double* d_x, const msc_params& prm,
                           msc_info* info, hipStream_t s, double tol_stop, int prec,
                           std::vector<double>* rel_out, int* iters_out, int* status_out,
-                          double* bytes_out) {
+                          double* bytes_out, double* bnorm_out) {
   const int ns = int(op->sigma.size());
   msc_status rc = ensure_scratch(op);
   if (rc != MSC_OK) return rc;
@@ -187,9 +205,18 @@ msc_status run_multishift(msc_op op, const double* d_b, double* d_x, const msc_p
   const int ru = (prec == MSC_PREC_MIXED) ? prm.reliable_every : 0;
   int launched = 0, chunk = 0;
   bool done = prm.max_iter <= 0;
+  EventPool pool;
   while (!done) {
     for (int g = 0; g < G; ++g) {
-      HIP_TRY(launch_iteration(prec, a, s));
+      hipEvent_t* ev = nullptr;
+      if (prm.timing > 0 && launched % prm.timing == 0) {
+        ev = pool.next();
+        if (!ev) {
+          set_error("msc_solve: event creation failed");
+          return MSC_EHIP;
+        }
+      }
+      HIP_TRY(launch_iteration(prec, a, s, ev));
       ++launched;
       if (ru > 0 && launched % ru == 0) HIP_TRY(launch_reliable(prec, a, s));
     }
@@ -206,6 +233,20 @@ msc_status run_multishift(msc_op op, const double* d_b, double* d_x, const msc_p
   }
   HIP_TRY(hipStreamSynchronize(s));
   HIP_TRY(hipMemcpy(&h, op->ws.st, sizeof h, hipMemcpyDeviceToHost));
+  if (info) {
+    for (double& v : info->kernel_ms) v = 0.0;
+    info->kernel_samples = 0;
+    // only iterations that did work are counted (the loop runs a little past the halt)
+    const int useful = std::min<int>(int(pool.groups.size()), prm.timing > 0 ? (h.iter + prm.timing - 1) / prm.timing : 0);
+    for (int q = 0; q < useful; ++q) {
+      for (int k = 0; k < 3; ++k) {
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, pool.groups[q][k], pool.groups[q][k + 1]));
+        info->kernel_ms[k] += ms;
+      }
+      info->kernel_samples += 1;
+    }
+  }
 
   // per-shift freeze iterations in the caller's order
   if (info && info->freeze_iter) {
@@ -227,6 +268,7 @@ msc_status run_multishift(msc_op op, const double* d_b, double* d_x, const msc_p
                           act_sum, double(h.iter));
 
   rel_out->assign(ns, 0.0);
+  *bnorm_out = std::sqrt(h.bnorm2);
   if (prm.verify && h.status == 0) {
     const double bn = std::sqrt(h.bnorm2);
     for (int k0 = 0; k0 < ns; k0 += 8) {
@@ -242,6 +284,249 @@ msc_status run_multishift(msc_op op, const double* d_b, double* d_x, const msc_p
                   double(op->n) * 16.0 * ns * (op->kind == MSC_A_MHM ? 4.0 : 2.0) + 16.0 * op->n;
   }
   return MSC_OK;
+}
+
+void free_bss(BssWorkspace& w) {
+  for (void* q : {w.p, w.t, w.r, w.e})
+    if (q) (void)hipFree(q);
+  dfree(w.st);
+  if (w.h_halt) (void)hipHostFree(w.h_halt);
+  for (auto& e : w.ev)
+    if (e) (void)hipEventDestroy(e);
+  w = BssWorkspace{};
+}
+
+msc_status ensure_bss(msc_op op, int prec, int mp) {
+  BssWorkspace& w = op->bws;
+  const size_t n = size_t(op->n);
+  if (w.st && w.prec == prec && w.mp == mp && w.n == n) return MSC_OK;
+  free_bss(w);
+  const size_t bytes = (prec == MSC_PREC_MIXED ? sizeof(float2) : sizeof(double2)) * n * mp;
+  for (void** q : {&w.p, &w.t, &w.r, &w.e}) {
+    HIP_TRY(hipMalloc(q, bytes));
+    HIP_TRY(hipMemset(*q, 0, bytes));
+  }
+  HIP_TRY(dalloc(&w.st, 1));
+  HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&w.h_halt), 2 * sizeof(int), hipHostMallocDefault));
+  HIP_TRY(hipEventCreateWithFlags(&w.ev[0], hipEventDisableTiming));
+  HIP_TRY(hipEventCreateWithFlags(&w.ev[1], hipEventDisableTiming));
+  w.n = n;
+  w.mp = mp;
+  w.prec = prec;
+  return MSC_OK;
+}
+
+// FP64 residual norms (and, when write_vectors, the interleaved r = p = residual, e = 0)
+// of systems j in [0, m): r_j = f_j - (A + sig_j) x_j.  res2 receives |r_j|^2.
+msc_status batch_residual(msc_op op, int prec, int lanes, int m, int mp, const double* sig,
+                          const double2* const* f, double2* const* x, bool write_vectors,
+                          std::vector<double>& res2, hipStream_t s, double* bytes) {
+  res2.assign(m, 0.0);
+  for (int q0 = 0; q0 < m; q0 += kResChunk) {
+    ResArgs v{};
+    v.m1 = Csr<double2>{op->rowptr, op->col, op->val64};
+    v.mhm = op->kind == MSC_A_MHM;
+    v.m2 = v.mhm ? Csr<double2>{op->rowptr_h, op->col_h, op->val64_h} : v.m1;
+    v.n = op->n;
+    v.kc = std::min(kResChunk, m - q0);
+    v.mp = mp;
+    v.j0 = q0;
+    for (int q = 0; q < v.kc; ++q) {
+      v.x[q] = x[q0 + q];
+      v.f[q] = f[q0 + q];
+      v.sig[q] = sig[q0 + q];
+    }
+    v.u = op->ws.u64;
+    if (write_vectors) {
+      v.r = op->bws.r;
+      v.p = op->bws.p;
+      v.e = op->bws.e;
+    }
+    v.partial = op->scratch.partial;
+    v.ticket = &op->scratch.tickets[10];
+    v.out = op->scratch.res2 + q0;
+    HIP_TRY(launch_residual(prec, lanes, v, s));
+    *bytes += (v.mhm ? 2.0 : 1.0) * (double(op->nnz) * 20.0 + 4.0 * (op->n + 1)) +
+              double(op->n) * v.kc * 16.0 * (v.mhm ? 5.0 : 3.0);
+  }
+  HIP_TRY(hipMemcpyAsync(res2.data(), op->scratch.res2, sizeof(double) * m, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return MSC_OK;
+}
+
+// Defect correction over m <= kBssMax systems sharing the operator:
+//   repeat: r_j = f_j - (A + sig_j) x_j in FP64; stop when |r_j| <= tol_abs_j;
+//           CG on (A + sig_j) e_j = r_j in the working precision from e = 0 until
+//           |r_in| <= max(delta |r_j|, tol_abs_j / 2); x_j += e_j in FP64.
+// On return res_abs[j] = |f_j - (A + sig_j) x_j| of the final iterates.
+msc_status run_batched_cg(msc_op op, int prec, int m, const double* sig, const double2* const* f,
+                          double2* const* x, const double* tol_abs, double delta,
+                          const msc_params& prm, hipStream_t s, std::vector<double>& res_abs,
+                          int* inner_total, double* bytes, bool* breakdown) {
+  *inner_total = 0;
+  *breakdown = false;
+  if (m < 1 || m > kBssMax) {
+    set_error("batched CG: 1 <= m <= %d systems", kBssMax);
+    return MSC_EINVAL;
+  }
+  const int mp = m <= 4 ? 4 : (m <= 8 ? 8 : 16);
+  msc_status rc = ensure_scratch(op);
+  if (rc != MSC_OK) return rc;
+  rc = ensure_workspace(op, op->ws.prec >= 0 ? op->ws.prec : prec, std::max<int>(1, int(op->sigma.size())));
+  if (rc != MSC_OK) return rc;
+  rc = ensure_bss(op, prec, mp);
+  if (rc != MSC_OK) return rc;
+  const int lanes = choose_lanes(op, prm);
+  BssArgs a{};
+  a.kind = op->kind;
+  a.mp = mp;
+  a.n = op->n;
+  a.m64 = Csr<double2>{op->rowptr, op->col, op->val64};
+  a.m32 = Csr<float2>{op->rowptr, op->col, op->val32};
+  if (op->kind == MSC_A_MHM) {
+    a.mh64 = Csr<double2>{op->rowptr_h, op->col_h, op->val64_h};
+    a.mh32 = Csr<float2>{op->rowptr_h, op->col_h, op->val32_h};
+  }
+  a.p = op->bws.p;
+  a.t = op->bws.t;
+  a.r = op->bws.r;
+  a.e = op->bws.e;
+  a.st = op->bws.st;
+  a.partial = op->scratch.partial;
+  a.tickets = op->scratch.tickets;
+  XPtrs xp{};
+  for (int j = 0; j < m; ++j) xp.x[j] = x[j];
+
+  const double w = prec == MSC_PREC_MIXED ? 8.0 : 16.0;
+  const double mat = (double(op->nnz) + double(op->nnz_h)) * (w + 4.0) +
+                     4.0 * (op->n + 1) * (op->kind == MSC_A_MHM ? 2.0 : 1.0);
+  const int max_cycles = 12;
+  std::vector<double> res2;
+  for (int cycle = 0;; ++cycle) {
+    rc = batch_residual(op, prec, lanes, m, mp, sig, f, x, true, res2, s, bytes);
+    if (rc != MSC_OK) return rc;
+    bool all_done = true;
+    BssState h{};
+    h.m = m;
+    h.mp = mp;
+    h.max_iter = prm.refine_max_iter;
+    for (int j = 0; j < kBssMax; ++j) h.R[j] = 1.0;
+    for (int j = 0; j < m; ++j) {
+      const double rn = std::sqrt(res2[j]);
+      h.sigma[j] = sig[j];
+      h.R[j] = res2[j];
+      const bool done = !(rn > tol_abs[j]);
+      if (!std::isfinite(rn)) *breakdown = true;
+      h.active[j] = (done || !std::isfinite(rn)) ? 0 : 1;
+      const double tgt = std::max(delta * rn, 0.5 * tol_abs[j]);
+      h.target2[j] = tgt * tgt;
+      if (h.active[j]) all_done = false;
+    }
+    res_abs.assign(m, 0.0);
+    for (int j = 0; j < m; ++j) res_abs[j] = std::sqrt(res2[j]);
+    if (all_done || cycle >= max_cycles || *breakdown) break;
+    HIP_TRY(hipMemcpyAsync(op->bws.st, &h, sizeof h, hipMemcpyHostToDevice, s));
+    const int G = std::max(1, prm.poll_every);
+    int launched = 0, chunk = 0;
+    bool done = false;
+    while (!done) {
+      for (int g = 0; g < G; ++g) {
+        HIP_TRY(launch_bss_iteration(prec, a, s));
+        ++launched;
+      }
+      const int slot = chunk & 1;
+      HIP_TRY(hipMemcpyAsync(&op->bws.h_halt[slot], &op->bws.st->halt, sizeof(int),
+                             hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipEventRecord(op->bws.ev[slot], s));
+      if (chunk >= 1) {
+        HIP_TRY(hipEventSynchronize(op->bws.ev[slot ^ 1]));
+        if (op->bws.h_halt[slot ^ 1]) done = true;
+      }
+      if (launched >= prm.refine_max_iter + 2 * G) done = true;
+      ++chunk;
+    }
+    HIP_TRY(launch_accum(prec, a, xp, s));
+    HIP_TRY(hipMemcpyAsync(&h, op->bws.st, sizeof h, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int j = 0; j < m; ++j)
+      if (h.bad[j]) *breakdown = true;
+    *inner_total += h.iter;
+    *bytes += double(h.iter) * (mat + double(op->n) * mp * w * 11.0) +
+              double(op->n) * m * (16.0 * 2.0 + w);
+    if (*breakdown) break;
+  }
+  return MSC_OK;
+}
+
+// The full solve: multishift sequence, FP64 verification of every shift, and batched
+// refinement of the shifts whose true residual is above tol.  With the mixed path and
+// refinement on, the sequence stops at inner_tol and refinement takes the shifts to tol.
+msc_status solve_impl(msc_op op, const double* d_b, double* d_x, const msc_params& prm,
+                      msc_info* info, hipStream_t s) {
+  const int ns = int(op->sigma.size());
+  std::vector<double> rel;
+  int iters = 0, status = 0;
+  double bytes = 0.0;
+  double bnorm = 0.0;
+  const bool refine = prm.refine && prm.verify;
+  const double tol_stop =
+      (prm.prec == MSC_PREC_MIXED && refine) ? std::max(prm.tol, prm.inner_tol) : prm.tol;
+  msc_status rc = run_multishift(op, d_b, d_x, prm, info, s, tol_stop, prm.prec, &rel, &iters,
+                                 &status, &bytes, &bnorm);
+  if (rc != MSC_OK) return rc;
+  int refine_iters = 0, n_refined = 0;
+  msc_status result = MSC_OK;
+  if (status != 0) {
+    set_error("msc_solve: breakdown (p^H (A+sigma_min) p <= 0 or not finite) at iteration %d", iters);
+    result = MSC_EBREAKDOWN;
+  } else if (prm.verify) {
+    std::vector<int> todo;
+    for (int k = 0; k < ns; ++k)
+      if (!(rel[k] <= prm.tol)) todo.push_back(k);
+    if (refine && !todo.empty() && bnorm > 0.0) {
+      n_refined = int(todo.size());
+      // the mixed path refines in complex64 with FP64 outer residuals; the FP64 path in FP64
+      const double delta = prm.prec == MSC_PREC_MIXED ? 1e-4 : 0.0;
+      for (size_t g0 = 0; g0 < todo.size(); g0 += kBssMax) {
+        const int m = int(std::min<size_t>(kBssMax, todo.size() - g0));
+        std::vector<double> sig(m), tol_abs(m), res;
+        std::vector<const double2*> f(m);
+        std::vector<double2*> x(m);
+        for (int j = 0; j < m; ++j) {
+          const int k = todo[g0 + j];
+          sig[j] = op->sigma[k];
+          tol_abs[j] = prm.tol * bnorm;
+          f[j] = reinterpret_cast<const double2*>(d_b);
+          x[j] = reinterpret_cast<double2*>(d_x) + int64_t(k) * op->n;
+        }
+        int inner = 0;
+        bool bd = false;
+        rc = run_batched_cg(op, prm.prec, m, sig.data(), f.data(), x.data(), tol_abs.data(), delta,
+                            prm, s, res, &inner, &bytes, &bd);
+        if (rc != MSC_OK) return rc;
+        refine_iters += inner;
+        for (int j = 0; j < m; ++j) rel[todo[g0 + j]] = res[j] / bnorm;
+        if (bd) status = 1;
+      }
+    }
+    if (status != 0) {
+      set_error("msc_solve: breakdown during refinement");
+      result = MSC_EBREAKDOWN;
+    } else {
+      for (int k = 0; k < ns; ++k)
+        if (!(rel[k] <= prm.tol)) result = MSC_ENOTCONV;
+      if (result == MSC_ENOTCONV) set_error("msc_solve: some shift did not reach tol");
+    }
+  }
+  if (info) {
+    info->iters = iters;
+    info->refine_iters = refine_iters;
+    info->n_refined = n_refined;
+    if (info->true_rel_res)
+      for (int k = 0; k < ns; ++k) info->true_rel_res[k] = rel[k];
+    info->alg_bytes = bytes;
+  }
+  return result;
 }
 
 msc_status check_op(msc_op op) {
@@ -454,39 +739,168 @@ msc_status msc_solve(msc_op op, const double* d_b, double* d_x, const msc_params
     return MSC_EINVAL;
   }
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const int ns = int(op->sigma.size());
-  std::vector<double> rel;
-  int iters = 0, status = 0;
-  double bytes = 0.0;
-  msc_status rc = run_multishift(op, d_b, d_x, prm, info, s, prm.tol, prm.prec, &rel, &iters,
-                                 &status, &bytes);
-  if (rc != MSC_OK) return rc;
-  msc_status result = MSC_OK;
-  if (status != 0) {
-    set_error("msc_solve: breakdown (p^H (A+sigma_min) p <= 0 or not finite) at iteration %d", iters);
-    result = MSC_EBREAKDOWN;
-  } else if (prm.verify) {
-    for (int k = 0; k < ns; ++k)
-      if (!(rel[k] <= prm.tol)) result = MSC_ENOTCONV;
-    if (result == MSC_ENOTCONV) set_error("msc_solve: some shift did not reach tol");
+  msc_status result = solve_impl(op, d_b, d_x, prm, info, s);
+  if (info)
+    info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return result;
+}
+
+msc_status msc_solve_adjoint(msc_op op, const double* d_g, const double* d_x, double* d_grad_b,
+                             double* d_grad_vals, const msc_params* params, msc_info* info,
+                             msc_stream stream) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (check_op(op) != MSC_OK) return MSC_EINVAL;
+  if (!d_g || !d_x) {
+    set_error("msc_solve_adjoint: null g or x");
+    return MSC_EINVAL;
   }
+  if (op->sigma.empty()) {
+    set_error("msc_solve_adjoint: no shifts set");
+    return MSC_EINVAL;
+  }
+  msc_params prm;
+  if (params)
+    prm = *params;
+  else
+    msc_params_default(&prm);
+  if (!(prm.tol >= 0.0) || (prm.prec != MSC_PREC_FP64 && prm.prec != MSC_PREC_MIXED)) {
+    set_error("msc_solve_adjoint: invalid tol or precision");
+    return MSC_EINVAL;
+  }
+  prm.verify = 1;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int ns = int(op->sigma.size());
+  const int64_t n = op->n;
+  msc_status rc = ensure_scratch(op);
+  if (rc != MSC_OK) return rc;
+  rc = ensure_workspace(op, prm.prec, ns);
+  if (rc != MSC_OK) return rc;
+  if (op->yadj_count < size_t(ns) * size_t(n)) {
+    dfree(op->yadj);
+    HIP_TRY(dalloc(&op->yadj, size_t(ns) * size_t(n)));
+    op->yadj_count = size_t(ns) * size_t(n);
+  }
+  if (!op->adj_small) HIP_TRY(dalloc(&op->adj_small, 256));
+  const double2* g = reinterpret_cast<const double2*>(d_g);
+  const double2* x = reinterpret_cast<const double2*>(d_x);
+  double2* y = op->yadj;
+
+  // 1. norms |g_k|^2, then the largest as reference and the real factors c_k
+  std::vector<double> gram(3 * ns), gn2(ns);
+  for (int q0 = 0; q0 < ns; q0 += 16) {
+    const int kc = std::min(16, ns - q0);
+    HIP_TRY(launch_gram(g, g + int64_t(q0) * n, n, kc, op->scratch.partial, &op->scratch.tickets[11],
+                        op->adj_small + 3 * q0, s));
+  }
+  HIP_TRY(hipMemcpyAsync(gram.data(), op->adj_small, sizeof(double) * 3 * ns, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  for (int k = 0; k < ns; ++k) gn2[k] = gram[3 * k + 2];
+  const int ref = int(std::max_element(gn2.begin(), gn2.end()) - gn2.begin());
+  bool collinear = gn2[ref] > 0.0 && std::isfinite(gn2[ref]);
+  std::vector<double> c(ns, 0.0);
+  if (collinear) {
+    const double2* gref = g + int64_t(ref) * n;
+    for (int q0 = 0; q0 < ns; q0 += 16) {
+      const int kc = std::min(16, ns - q0);
+      HIP_TRY(launch_gram(gref, g + int64_t(q0) * n, n, kc, op->scratch.partial,
+                          &op->scratch.tickets[11], op->adj_small + 3 * q0, s));
+    }
+    HIP_TRY(hipMemcpyAsync(gram.data(), op->adj_small, sizeof(double) * 3 * ns, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int k = 0; k < ns; ++k) c[k] = gram[3 * k] / gn2[ref];
+    HIP_TRY(hipMemcpyAsync(op->adj_small + 192, c.data(), sizeof(double) * ns, hipMemcpyHostToDevice, s));
+    std::vector<double> dn(ns);
+    for (int q0 = 0; q0 < ns; q0 += 16) {
+      const int kc = std::min(16, ns - q0);
+      HIP_TRY(launch_diffnorm(gref, g + int64_t(q0) * n, op->adj_small + 192 + q0, n, kc,
+                              op->scratch.partial, &op->scratch.tickets[11], op->adj_small + q0, s));
+    }
+    HIP_TRY(hipMemcpyAsync(dn.data(), op->adj_small, sizeof(double) * ns, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int k = 0; k < ns; ++k)
+      if (!(dn[k] <= 1e-26 * gn2[k])) collinear = false;
+    if (collinear) HIP_TRY(hipMemcpyAsync(op->adj_small + 192, c.data(), sizeof(double) * ns, hipMemcpyHostToDevice, s));
+  }
+
+  // 2. y_k = (A + sigma_k)^{-1} g_k
+  msc_status result = MSC_OK;
+  int iters = 0, refine_iters = 0, n_refined = 0;
+  std::vector<double> rel(ns, 0.0);
+  double bytes = 0.0;
+  if (collinear) {
+    msc_info sub{};
+    std::vector<double> sub_rel(ns);
+    sub.true_rel_res = sub_rel.data();
+    const double2* gref = g + int64_t(ref) * n;
+    result = solve_impl(op, reinterpret_cast<const double*>(gref), reinterpret_cast<double*>(y), prm,
+                        &sub, s);
+    if (result < 0) return result;
+    HIP_TRY(launch_scale_shifts(y, op->adj_small + 192, ns, n, s));
+    iters = sub.iters;
+    refine_iters = sub.refine_iters;
+    n_refined = sub.n_refined;
+    bytes = sub.alg_bytes;
+    rel = sub_rel;
+  } else {
+    HIP_TRY(hipMemsetAsync(y, 0, sizeof(double2) * size_t(ns) * size_t(n), s));
+    std::vector<int> todo;
+    for (int k = 0; k < ns; ++k)
+      if (gn2[k] > 0.0) todo.push_back(k);
+    const double delta = prm.prec == MSC_PREC_MIXED ? 1e-4 : 0.0;
+    bool bd = false;
+    for (size_t g0 = 0; g0 < todo.size(); g0 += kBssMax) {
+      const int m = int(std::min<size_t>(kBssMax, todo.size() - g0));
+      std::vector<double> sig(m), tol_abs(m), res;
+      std::vector<const double2*> f(m);
+      std::vector<double2*> xs(m);
+      for (int j = 0; j < m; ++j) {
+        const int k = todo[g0 + j];
+        sig[j] = op->sigma[k];
+        tol_abs[j] = prm.tol * std::sqrt(gn2[k]);
+        f[j] = g + int64_t(k) * n;
+        xs[j] = y + int64_t(k) * n;
+      }
+      int inner = 0;
+      bool b1 = false;
+      rc = run_batched_cg(op, prm.prec, m, sig.data(), f.data(), xs.data(), tol_abs.data(), delta, prm,
+                          s, res, &inner, &bytes, &b1);
+      if (rc != MSC_OK) return rc;
+      bd = bd || b1;
+      iters = std::max(iters, inner);
+      for (int j = 0; j < m; ++j) rel[todo[g0 + j]] = res[j] / std::sqrt(gn2[todo[g0 + j]]);
+    }
+    n_refined = int(todo.size());
+    if (bd) {
+      set_error("msc_solve_adjoint: breakdown in an adjoint solve");
+      result = MSC_EBREAKDOWN;
+    } else {
+      for (int k = 0; k < ns; ++k)
+        if (!(rel[k] <= prm.tol)) result = MSC_ENOTCONV;
+    }
+  }
+
+  // 3. gradients
+  if (d_grad_b) HIP_TRY(launch_sum_shifts(y, ns, n, reinterpret_cast<double2*>(d_grad_b), s));
+  if (d_grad_vals && op->nnz > 0) {
+    HIP_TRY(launch_grad_vals(op->kind, choose_lanes(op, prm), Csr<double2>{op->rowptr, op->col, op->val64},
+                             x, y, n, ns, op->ws.u64, op->ws.u64 + 4 * n,
+                             reinterpret_cast<double2*>(d_grad_vals), s));
+    bytes += double(ns) / 4.0 * (double(op->nnz) * 20.0) + double(op->nnz) * 32.0;
+  }
+  HIP_TRY(hipStreamSynchronize(s));
   if (info) {
     info->iters = iters;
-    info->refine_iters = 0;
-    info->n_refined = 0;
+    info->refine_iters = refine_iters;
+    info->n_refined = n_refined;
+    info->n_reliable = 0;
     if (info->true_rel_res)
       for (int k = 0; k < ns; ++k) info->true_rel_res[k] = rel[k];
+    if (info->freeze_iter)
+      for (int k = 0; k < ns; ++k) info->freeze_iter[k] = -1;
     info->alg_bytes = bytes;
     info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   }
   return result;
-}
-
-msc_status msc_solve_adjoint(msc_op op, const double*, const double*, double*, double*,
-                             const msc_params*, msc_info*, msc_stream) {
-  if (check_op(op) != MSC_OK) return MSC_EINVAL;
-  set_error("msc_solve_adjoint: not available in this build");
-  return MSC_EINVAL;
 }
 
 msc_status msc_solve_batched(int32_t, const msc_op*, const int32_t*, const double* const*,
@@ -498,6 +912,9 @@ msc_status msc_solve_batched(int32_t, const msc_op*, const int32_t*, const doubl
 void msc_op_destroy(msc_op op) {
   if (!op) return;
   free_workspace(op->ws);
+  free_bss(op->bws);
+  dfree(op->yadj);
+  dfree(op->adj_small);
   dfree(op->scratch.partial);
   dfree(op->scratch.tickets);
   dfree(op->scratch.res2);

@@ -105,11 +105,21 @@ __device__ __forceinline__ double load_agent(const double* p) {
 // store_agent.  Returns true (in all threads) in the workgroup that arrives last; that
 // workgroup then sees every partial through load_agent.  The ticket is reset by the
 // last workgroup, so the same counter serves the next launch.
+//
+// Only the partials cross workgroups inside a launch, and they travel with device-scope
+// (L2 write-through / L2-bypassing) accesses, so the ticket needs no acquire/release
+// fence: an agent-scope fence would write back and invalidate the whole L2 of the XCD
+// in every workgroup, evicting the gathered vectors the SpMV relies on.  Thread 0 waits
+// for its partial stores to complete before taking a ticket, so a workgroup that draws
+// the last ticket finds every partial in memory.
 __device__ __forceinline__ bool arrive_last(unsigned* ticket) {
   __shared__ int last;
   __syncthreads();
   if (threadIdx.x == 0) {
-    const unsigned t = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0);  // vmcnt = expcnt = lgkmcnt = 0: partial stores done
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    const unsigned t = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     last = (t == gridDim.x - 1);
     if (last) __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }

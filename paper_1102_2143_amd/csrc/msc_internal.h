@@ -82,6 +82,22 @@ struct Workspace {
   hipEvent_t ev[2] = {nullptr, nullptr};
 };
 
+struct BssState;
+
+// Buffers of the batched single-shift CG (interleaved n x mp vectors).
+struct BssWorkspace {
+  size_t n = 0;
+  int mp = 0;
+  int prec = -1;
+  void* p = nullptr;
+  void* t = nullptr;
+  void* r = nullptr;
+  void* e = nullptr;
+  BssState* st = nullptr;
+  int* h_halt = nullptr;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+};
+
 }  // namespace msc
 
 struct msc_op_s {
@@ -99,7 +115,11 @@ struct msc_op_s {
   float2* val32_h = nullptr;
   std::vector<double> sigma;
   msc::Workspace ws;
+  msc::BssWorkspace bws;
   msc::Scratch scratch;
+  double2* yadj = nullptr;       // adjoint solutions, ns * n complex128
+  size_t yadj_count = 0;
+  double* adj_small = nullptr;   // 256 doubles: Gram sums and shift factors
   int lanes64 = 0, lanes32 = 0;  // chosen lanes per row (0 = not yet tuned)
 };
 
@@ -134,7 +154,8 @@ struct MsArgs {
   Scratch sc;
 };
 hipError_t launch_init(int prec, const MsArgs& a, hipStream_t s);
-hipError_t launch_iteration(int prec, const MsArgs& a, hipStream_t s);
+// ev (optional, 4 events): recorded before K1, after K1, after K2 and after K3.
+hipError_t launch_iteration(int prec, const MsArgs& a, hipStream_t s, hipEvent_t* ev = nullptr);
 hipError_t launch_reliable(int prec, const MsArgs& a, hipStream_t s);
 // FP64 true residual norms^2 of shifts [k0, k0+kc) (kc <= 8) of x into sc.res2[k0..].
 hipError_t launch_verify(const MsArgs& a, const double* sigma_by_caller_index, int k0, int kc,
@@ -145,5 +166,77 @@ hipError_t launch_apply(int kind, int prec, int lanes, int64_t n, const Csr<doub
                         double shift, void* tmp_a, void* tmp_b, hipStream_t s);
 
 int default_grid(int64_t n, int lanes);
+
+// batched_cg.hip -- m <= kBssMax single-shift systems sharing one operator
+constexpr int kBssMax = 16;
+constexpr int kResChunk = 8;
+
+struct BssState {
+  double R[kBssMax];        // |r_j|^2 (recursive, inner)
+  double a[kBssMax];        // step of system j this iteration
+  double b[kBssMax];        // direction coefficient of system j
+  double target2[kBssMax];  // inner stop: R_j <= target2_j
+  double sigma[kBssMax];
+  int active[kBssMax];
+  int upd[kBssMax];         // system j was updated this iteration (e_j += a_j p_j)
+  int iters[kBssMax];
+  int bad[kBssMax];         // breakdown of system j
+  int m, mp, iter, max_iter, halt, nact, k3_enable, pad_;
+};
+
+struct BssArgs {
+  int kind;
+  int mp;
+  int64_t n;
+  Csr<double2> m64, mh64;
+  Csr<float2> m32, mh32;
+  void* p; void* t; void* r; void* e;   // interleaved n x mp vectors of the working precision
+  BssState* st;
+  double* partial;                      // kMaxGrid * kBssMax
+  unsigned* tickets;
+};
+
+struct XPtrs {
+  double2* x[kBssMax];
+};
+
+// FP64 residual r_q = f_q - (A + sig_q) x_q for q < kc (<= kResChunk) systems; writes
+// |r_q|^2 to out[q] and, when r != nullptr, r (cast) into column j0 + q of the
+// interleaved r and p and zero into e.
+struct ResArgs {
+  Csr<double2> m1;          // M (MHM) -- first half
+  Csr<double2> m2;          // M^H (MHM) or A (HERM)
+  int mhm;
+  int64_t n;
+  int kc;
+  int mp, j0;
+  const double2* x[kResChunk];
+  const double2* f[kResChunk];
+  double sig[kResChunk];
+  double2* u;               // kResChunk * n scratch (MHM)
+  void* r; void* p; void* e;
+  double* partial;
+  unsigned* ticket;
+  double* out;
+};
+
+// grad.hip
+// out[3q..3q+2] = Re<gref, g_q>, Im<gref, g_q>, |g_q|^2 for q < kc (<= 16); g shift-major.
+hipError_t launch_gram(const double2* gref, const double2* g, int64_t n, int kc, double* partial,
+                       unsigned* ticket, double* out, hipStream_t s);
+hipError_t launch_scale_shifts(double2* y, const double* d_c, int ns, int64_t n, hipStream_t s);
+// out[q] = |g_q - c_q gref|^2 for q < kc (<= 16)
+hipError_t launch_diffnorm(const double2* gref, const double2* g, const double* d_c, int64_t n,
+                           int kc, double* partial, unsigned* ticket, double* out, hipStream_t s);
+hipError_t launch_sum_shifts(const double2* y, int ns, int64_t n, double2* out, hipStream_t s);
+// grad (nnz complex128, creation order) of sum_k Re(g_k^H x_k) given x and y (shift-major);
+// u, w: scratch of 4 n complex128 each (A = M^H M only).
+hipError_t launch_grad_vals(int kind, int lanes, const Csr<double2>& m, const double2* x,
+                            const double2* y, int64_t n, int ns, double2* u, double2* w,
+                            double2* grad, hipStream_t s);
+
+hipError_t launch_bss_iteration(int prec, const BssArgs& a, hipStream_t s);
+hipError_t launch_residual(int prec, int lanes, const ResArgs& v, hipStream_t s);
+hipError_t launch_accum(int prec, const BssArgs& a, const XPtrs& xp, hipStream_t s);
 
 }  // namespace msc

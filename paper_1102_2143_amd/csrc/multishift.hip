@@ -556,17 +556,22 @@ int grid_rows(int64_t n, int rows_per_pass) {
   }
 
 template <class R>
-hipError_t iteration_impl(const MsArgs& a, hipStream_t s) {
+hipError_t iteration_impl(const MsArgs& a, hipStream_t s, hipEvent_t* ev) {
   const int g1 = grid_rows(a.n, kBlock / a.lanes);
   const int g3 = grid_rows(a.n, kBlock);
+  if (ev) (void)hipEventRecord(ev[0], s);
   if (a.kind == MSC_A_MHM) {
     MSC_LANES_SWITCH(a.lanes, (k1_apply<R, LL, true><<<g1, kBlock, 0, s>>>(a)));
+    if (ev) (void)hipEventRecord(ev[1], s);
     MSC_LANES_SWITCH(a.lanes, (k2_mhm<R, LL><<<g1, kBlock, 0, s>>>(a)));
   } else {
     MSC_LANES_SWITCH(a.lanes, (k1_apply<R, LL, false><<<g1, kBlock, 0, s>>>(a)));
+    if (ev) (void)hipEventRecord(ev[1], s);
     k2_herm<R><<<g3, kBlock, 0, s>>>(a);
   }
+  if (ev) (void)hipEventRecord(ev[2], s);
   k3_update<R><<<g3, kBlock, 0, s>>>(a);
+  if (ev) (void)hipEventRecord(ev[3], s);
   return hipGetLastError();
 }
 
@@ -595,8 +600,8 @@ hipError_t launch_init(int prec, const MsArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_iteration(int prec, const MsArgs& a, hipStream_t s) {
-  return prec == MSC_PREC_MIXED ? iteration_impl<float>(a, s) : iteration_impl<double>(a, s);
+hipError_t launch_iteration(int prec, const MsArgs& a, hipStream_t s, hipEvent_t* ev) {
+  return prec == MSC_PREC_MIXED ? iteration_impl<float>(a, s, ev) : iteration_impl<double>(a, s, ev);
 }
 
 hipError_t launch_reliable(int prec, const MsArgs& a, hipStream_t s) {

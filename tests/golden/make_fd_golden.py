@@ -1,0 +1,39 @@
+"""Write the finite-difference gradient fixture of the 8^4 gradient workload.
+
+Calls only the oracle (test infrastructure): central differences with h = 1e-6 of the
+second-order functional L~ = sum_k c_k Re(b^H x_k + x_k^H r_k) (x_k from the FP64 CG-M
+oracle at tol 1e-14), for the real and imaginary part of 32 seeded stored entries of M.
+The loss is the rational-approximation form sum_k c_k Re(b^H x_k) of the shifted family
+(Section 2 of the paper).  Run:  python tests/golden/make_fd_golden.py
+"""
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import oracle as O  # noqa: E402
+import workloads as W  # noqa: E402
+
+
+def main(name="c3", out="fd_c3_8x4.json"):
+    p = W.make_config(name)
+    cfg = p["cfg"]
+    t0 = time.time()
+    fd = O.fd_gradient("mhm", p["rowptr"], p["col"], p["vals"], p["n"], p["b"], p["sigma"], p["c"],
+                       p["fd_nz"], h=cfg["fd_h"], tol=1e-14)
+    rec = dict(config=name, dims=list(cfg["dims"]), mass=cfg["mass"], shifts=list(cfg["shifts"]),
+               seeds=dict(links=cfg["seed_links"], b=cfg["seed_b"], c=cfg["seed_c"], nz=cfg["seed_nz"]),
+               h=cfg["fd_h"], solve_tol=1e-14, nz=[int(e) for e in p["fd_nz"]],
+               grad_re=[float(v.real) for v in fd], grad_im=[float(v.imag) for v in fd],
+               seconds=round(time.time() - t0, 1),
+               source="oracle.fd_gradient (central differences of the second-order functional)")
+    with open(os.path.join(HERE, out), "w") as f:
+        json.dump(rec, f, indent=1)
+    print(f"wrote {out} in {time.time() - t0:.0f}s")
+
+
+if __name__ == "__main__":
+    main()

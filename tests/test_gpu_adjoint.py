@@ -1,0 +1,127 @@
+"""GPU: the hand-written adjoint against the dense autograd reference, the closed form
+and central finite differences of the oracle."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def _op(p, cuda, kind="mhm"):
+    from paper_1102_2143_amd import Operator
+    op = Operator(p["rowptr"], p["col"], p["vals"], p["n"], kind=kind, device=cuda)
+    op.set_shifts(p["sigma"])
+    return op
+
+
+@pytest.fixture(scope="module")
+def c3_4():
+    return W.make_config("c3_4")
+
+
+@pytest.mark.parametrize("prec,bar", [("fp64", 1e-8), ("mixed", 1e-8)])
+def test_collinear_loss_matches_dense_autograd(c3_4, cuda, prec, bar):
+    print(f"[gpu] adjoint collinear 4^4 {prec}", flush=True)
+    p = c3_4
+    op = _op(p, cuda)
+    x, info = op.solve(p["b"], tol=1e-12, prec=prec)
+    g = p["c"][:, None] * p["b"][None, :]
+    gb, gv, ainfo = op.solve_adjoint(g, x, tol=1e-12, prec=prec)
+    assert ainfo["status"] == "ok", ainfo
+    ref_v, ref_b = O.dense_reference_gradient("mhm", p["rowptr"], p["col"], p["vals"], p["n"],
+                                              p["b"], p["sigma"], g)
+    assert _rel(gv.cpu().numpy(), ref_v) <= bar
+    assert _rel(gb.cpu().numpy(), ref_b) <= bar
+    op.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_general_loss_matches_dense_autograd(c3_4, cuda, prec):
+    print(f"[gpu] adjoint general 4^4 {prec}", flush=True)
+    p = c3_4
+    op = _op(p, cuda)
+    x, _ = op.solve(p["b"], tol=1e-12, prec=prec)
+    g = W.gaussian_rhs(p["n"], 91, p["sigma"].size)
+    gb, gv, ainfo = op.solve_adjoint(g, x, tol=1e-12, prec=prec)
+    assert ainfo["status"] == "ok", ainfo
+    ref_v, ref_b = O.dense_reference_gradient("mhm", p["rowptr"], p["col"], p["vals"], p["n"],
+                                              p["b"], p["sigma"], g)
+    assert _rel(gv.cpu().numpy(), ref_v) <= 1e-8
+    assert _rel(gb.cpu().numpy(), ref_b) <= 1e-8
+    op.close()
+
+
+def test_herm_general_loss(cuda):
+    rowptr, col, vals = W.laplacian7_csr((5, 4, 6), 61)
+    n = 120
+    p = dict(rowptr=rowptr, col=col, vals=vals, n=n, sigma=np.array([1e-3, 0.1, 2.0]))
+    b = W.gaussian_rhs(n, 62)
+    op = _op(p, cuda, kind="herm")
+    x, _ = op.solve(b, tol=1e-13)
+    g = W.gaussian_rhs(n, 63, 3)
+    gb, gv, ainfo = op.solve_adjoint(g, x, tol=1e-13)
+    ref_v, ref_b = O.dense_reference_gradient("herm", rowptr, col, vals, n, b, p["sigma"], g)
+    assert _rel(gv.cpu().numpy(), ref_v) <= 1e-9
+    assert _rel(gb.cpu().numpy(), ref_b) <= 1e-9
+    op.close()
+
+
+def test_zero_gradient_gives_zero(c3_4, cuda):
+    p = c3_4
+    op = _op(p, cuda)
+    x, _ = op.solve(p["b"], tol=1e-10)
+    gb, gv, ainfo = op.solve_adjoint(np.zeros((p["sigma"].size, p["n"]), complex), x)
+    assert not bool(gv.abs().max() > 0) and not bool(gb.abs().max() > 0)
+    op.close()
+
+
+def test_autograd_function(c3_4, cuda):
+    import torch
+    from paper_1102_2143_amd.autograd import multishift_solve
+    p = c3_4
+    op = _op(p, cuda)
+    vals = torch.tensor(p["vals"], device=cuda, requires_grad=True)
+    b = torch.tensor(p["b"], device=cuda, requires_grad=True)
+    c = torch.tensor(p["c"], device=cuda)
+    x = multishift_solve(vals, b, op, tol=1e-12)
+    loss = (c * torch.real((b.detach().conj()[None, :] * x).sum(dim=1))).sum()
+    gv, gb = torch.autograd.grad(loss, (vals, b))
+    g = p["c"][:, None] * p["b"][None, :]
+    ref_v, ref_b = O.dense_reference_gradient("mhm", p["rowptr"], p["col"], p["vals"], p["n"],
+                                              p["b"], p["sigma"], g)
+    assert _rel(gv.cpu().numpy(), ref_v) <= 1e-8
+    assert _rel(gb.cpu().numpy(), ref_b) <= 1e-8
+    op.close()
+
+
+def test_c3_8x4_against_finite_differences(cuda):
+    path = os.path.join(GOLDEN, "fd_c3_8x4.json")
+    if not os.path.exists(path):
+        pytest.fail("missing golden fixture: run tests/golden/make_fd_golden.py")
+    rec = json.load(open(path))
+    print("[gpu] adjoint 8^4 vs oracle finite differences", flush=True)
+    p = W.make_config("c3")
+    op = _op(p, cuda)
+    x, info = op.solve(p["b"], tol=1e-12, prec="fp64")
+    g = p["c"][:, None] * p["b"][None, :]
+    gb, gv, ainfo = op.solve_adjoint(g, x, tol=1e-12, prec="fp64")
+    nz = np.array(rec["nz"])
+    fd = np.array(rec["grad_re"]) + 1j * np.array(rec["grad_im"])
+    got = gv.cpu().numpy()[nz]
+    # 64 real components compared as one vector, and entry by entry with a floor
+    comp_got = np.concatenate([got.real, got.imag])
+    comp_fd = np.concatenate([fd.real, fd.imag])
+    assert np.linalg.norm(comp_got - comp_fd) / np.linalg.norm(comp_fd) <= 1e-6
+    floor = 1e-3 * np.abs(comp_fd).max()
+    assert np.all(np.abs(comp_got - comp_fd) <= 1e-5 * np.maximum(np.abs(comp_fd), floor))
+    op.close()

@@ -1,0 +1,103 @@
+"""GPU: mixed precision (complex64 Krylov vectors, FP64 reductions, recurrences and
+reliable updates) with per-shift refinement, against the FP64 oracle."""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b, axis=-1) / np.linalg.norm(b, axis=-1)
+
+
+@pytest.fixture(scope="module")
+def c0():
+    p = W.make_config("c0")
+    p["apply"] = O.shifted_apply("mhm", p["rowptr"], p["col"], p["vals"], p["n"])
+    return p
+
+
+def _op(p, cuda, kind="mhm"):
+    from paper_1102_2143_amd import Operator
+    return Operator(p["rowptr"], p["col"], p["vals"], p["n"], kind=kind, device=cuda)
+
+
+def test_c0_mixed_reaches_tol_on_every_shift(c0, cuda):
+    print("[gpu] c0 mixed tol 1e-10", flush=True)
+    op = _op(c0, cuda)
+    op.set_shifts(c0["sigma"])
+    x, info = op.solve(c0["b"], tol=1e-10, prec="mixed")
+    assert info["status"] == "ok", info
+    xg = x.cpu().numpy()
+    bn = np.linalg.norm(c0["b"])
+    rho = np.array([np.linalg.norm(c0["b"] - c0["apply"](xg[k], s))
+                    for k, s in enumerate(c0["sigma"])]) / bn
+    assert np.all(rho <= 1e-10)
+    assert np.allclose(rho, info["true_rel_res"], rtol=1e-3, atol=1e-15)
+    op.close()
+
+
+def test_c0_mixed_parity_with_tightened_oracle(c0, cuda):
+    # mixed vs FP64 oracle: both at tol 1e-12 so the solution error (<= kappa * residual)
+    # is below the 1e-8 parity bar
+    op = _op(c0, cuda)
+    op.set_shifts(c0["sigma"])
+    x, info = op.solve(c0["b"], tol=1e-12, prec="mixed")
+    ref = O.cg_m(c0["apply"], c0["b"], c0["sigma"], tol=1e-13)
+    assert info["status"] == "ok"
+    assert np.all(_rel(x.cpu().numpy(), ref["x"]) <= 1e-8)
+    op.close()
+
+
+def test_mixed_without_refinement_drives_only_the_smallest_shift(c0, cuda):
+    # reliable updates keep the driving system exact; the others stop at the
+    # complex64 level, which is what refinement exists for
+    op = _op(c0, cuda)
+    op.set_shifts(c0["sigma"])
+    x, info = op.solve(c0["b"], tol=1e-10, prec="mixed", refine=False, reliable_every=25)
+    k0 = int(np.argmin(c0["sigma"]))
+    assert info["true_rel_res"][k0] <= 1.5e-10
+    assert info["n_reliable"] >= 1
+    assert info["n_refined"] == 0
+    op.close()
+
+
+def test_mixed_herm_laplacian(cuda):
+    rowptr, col, vals = W.laplacian7_csr((12, 10, 9), 51)
+    n = 1080
+    b = W.gaussian_rhs(n, 52)
+    sigma = W.logspace_shifts(1e-4, 1.0, 10)
+    p = dict(rowptr=rowptr, col=col, vals=vals, n=n)
+    op = _op(p, cuda, kind="herm")
+    op.set_shifts(sigma)
+    x, info = op.solve(b, tol=1e-10, prec="mixed")
+    assert info["status"] == "ok"
+    ap = O.shifted_apply("herm", rowptr, col, vals, n)
+    rho = np.array([np.linalg.norm(b - ap(x.cpu().numpy()[k], s)) for k, s in enumerate(sigma)])
+    assert np.all(rho / np.linalg.norm(b) <= 1e-10)
+    op.close()
+
+
+def test_c1_mixed_full_size(cuda):
+    print("[gpu] c1 16^4 mixed solve", flush=True)
+    p = W.make_config("c1")
+    op = _op(p, cuda)
+    op.set_shifts(p["sigma"])
+    x, info = op.solve(p["b"], tol=1e-10, prec="mixed")
+    print(f"[gpu] c1 mixed iters={info['iters']} refine={info['refine_iters']} "
+          f"refined={info['n_refined']} max res={info['true_rel_res'].max():.3e} "
+          f"t={info['seconds']:.3f}s", flush=True)
+    assert info["status"] == "ok"
+    xg = x.cpu().numpy()
+    ap = O.shifted_apply("mhm", p["rowptr"], p["col"], p["vals"], p["n"])
+    bn = np.linalg.norm(p["b"])
+    rho = np.array([np.linalg.norm(p["b"] - ap(xg[k], s)) for k, s in enumerate(p["sigma"])]) / bn
+    assert np.all(rho <= 1e-10)
+    # sampled shift against an independent FP64 CG of that shifted system
+    k = int(np.argmax(p["sigma"]))
+    ref_k = O.cg(ap, p["b"], shift=float(p["sigma"][k]), tol=1e-13)["x"]
+    assert _rel(xg[k], ref_k) <= 1e-8
+    op.close()

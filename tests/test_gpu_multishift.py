@@ -174,10 +174,23 @@ def test_zero_rhs(c0, cuda):
 def test_iteration_limit(c0, cuda):
     op = _op(c0, cuda)
     op.set_shifts(c0["sigma"])
-    x, info = op.solve(c0["b"], max_iter=3)
+    x, info = op.solve(c0["b"], max_iter=3, refine=False)
     assert info["status"] == "notconv" and info["iters"] == 3
     ref = O.cg_m(c0["apply"], c0["b"], c0["sigma"], tol=1e-10, max_iter=3)
     assert np.all(_rel(x.cpu().numpy(), ref["x"]) <= 1e-12)
+    op.close()
+
+
+def test_refinement_completes_a_truncated_sequence(c0, cuda):
+    # three multishift iterations, then the FP64 batched refinement takes every shift
+    # to tol from those iterates
+    op = _op(c0, cuda)
+    op.set_shifts(c0["sigma"])
+    x, info = op.solve(c0["b"], max_iter=3, refine=True, tol=1e-11)
+    assert info["status"] == "ok" and info["iters"] == 3
+    assert info["n_refined"] == c0["sigma"].size and info["refine_iters"] > 0
+    xd = O.dense_solve("mhm", c0["rowptr"], c0["col"], c0["vals"], c0["n"], c0["b"], c0["sigma"])
+    assert np.all(_rel(x.cpu().numpy(), xd) <= 1e-8)
     op.close()
 
 
