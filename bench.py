@@ -74,7 +74,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c1", choices=sorted(WORKLOAD_NAMES))
-    ap.add_argument("--prec", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--prec", default="both", choices=["fp64", "mixed", "both"],
+                    help="both: time the FP64 plain solve and the mixed solve (the headline)")
     ap.add_argument("--timing", type=int, default=4, help="sample every k-th iteration's kernels")
     ap.add_argument("--cpu-sample-iters", type=int, default=60)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -105,81 +106,95 @@ def main():
     setup_s = time.perf_counter() - t0
     b = torch.from_numpy(prob["b"]).to(dev)
     x = torch.empty((prob["sigma"].size, prob["n"]), dtype=torch.complex128, device=dev)
-    kw = dict(tol=prob["tol"], prec=args.prec, timing=args.timing)
 
-    for i in range(args.warmup):
-        _, info = op.solve(b, out=x, **kw)
-        log(f"warmup {i}: {info['status']} iters={info['iters']} {info['seconds']:.4f}s")
-    torch.cuda.synchronize()
-    infos = []
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        _, info = op.solve(b, out=x, **kw)
-        infos.append(info)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    for i, info in enumerate(infos):
-        log(f"step {i}: {info['status']} iters={info['iters']} refine={info['refine_iters']} "
-            f"max true res={info['true_rel_res'].max():.3e} {info['seconds']:.4f}s")
-    ok = all(inf["status"] == "ok" and inf["true_rel_res"].max() <= prob["tol"] for inf in infos)
+    def run_path(prec):
+        kw = dict(tol=prob["tol"], prec=prec, timing=args.timing)
+        for i in range(args.warmup):
+            _, info = op.solve(b, out=x, **kw)
+            log(f"{prec} warmup {i}: {info['status']} iters={info['iters']} {info['seconds']:.4f}s")
+        torch.cuda.synchronize()
+        infos = []
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            _, info = op.solve(b, out=x, **kw)
+            infos.append(info)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        for i, info in enumerate(infos):
+            log(f"{prec} step {i}: {info['status']} iters={info['iters']} refine={info['refine_iters']} "
+                f"refined={info['n_refined']} max true res={info['true_rel_res'].max():.3e} "
+                f"{info['seconds']:.4f}s")
+        ok = all(inf["status"] == "ok" and inf["true_rel_res"].max() <= prob["tol"] for inf in infos)
+        ns = prob["sigma"].size
+        n, nnz = prob["n"], prob["vals"].size
+        iters = infos[-1]["iters"]
+        alg_bytes = float(np.mean([inf["alg_bytes"] for inf in infos]))
+        drive = int(np.argmin(prob["sigma"]))
+        fi = infos[-1]["freeze_iter"]
+        act_sum = sum((fi[k] if fi[k] >= 0 else iters) for k in range(ns) if k != drive)
+        kb = kernel_bytes("mhm", prec, n, nnz, nnz, act_sum / max(iters, 1))
+        samples = sum(inf["kernel_samples"] for inf in infos)
+        kms = np.sum([inf["kernel_ms"] for inf in infos], axis=0)
+        kernels = {}
+        if samples > 0:
+            for k, nm in enumerate(["K1", "K2", "K3"]):
+                avg_ms = kms[k] / samples
+                kernels[nm] = {"avg_us": round(1e3 * avg_ms, 2), "alg_bytes": kb[nm],
+                               "gbs": round(kb[nm] / (avg_ms * 1e-3) / 1e9, 1)}
+        return dict(prec=prec, wall=wall, ok=ok, iters=iters, infos=infos,
+                    value=ns * args.steps / wall, ms_per_step=1e3 * wall / args.steps,
+                    eff_gbs=alg_bytes / (wall / args.steps) / 1e9, kernels=kernels,
+                    refine_iters=infos[-1]["refine_iters"], n_refined=infos[-1]["n_refined"],
+                    max_res=float(max(inf["true_rel_res"].max() for inf in infos)))
 
+    paths = [args.prec] if args.prec != "both" else ["fp64", "mixed"]
+    res = {pp: run_path(pp) for pp in paths}
+    main_path = res["mixed"] if "mixed" in res else res[paths[0]]
+    kernels = main_path["kernels"]
+    roofline = None
+    if kernels:
+        dom = max(kernels, key=lambda nm: kernels[nm]["avg_us"])
+        ach = kernels[dom]["gbs"]
+        roofline = {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                    "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": None, "kernel": dom,
+                    "kernel_avg_us": kernels[dom]["avg_us"]}
     ns = prob["sigma"].size
     n, nnz = prob["n"], prob["vals"].size
-    ms_per_step = 1e3 * wall / args.steps
-    value = ns * args.steps / wall
-    iters = infos[-1]["iters"]
-    alg_bytes = float(np.mean([inf["alg_bytes"] for inf in infos]))
-    eff_gbs = alg_bytes / (wall / args.steps) / 1e9
-
-    # dominant kernel from the sampled HIP-event timings of the timed steps
-    drive = int(np.argmin(prob["sigma"]))
-    fi = infos[-1]["freeze_iter"]
-    act_sum = sum((fi[k] if fi[k] >= 0 else iters) for k in range(ns) if k != drive)
-    act_avg = act_sum / max(iters, 1)
-    kb = kernel_bytes("mhm", args.prec, n, nnz, nnz, act_avg)
-    samples = sum(inf["kernel_samples"] for inf in infos)
-    kms = np.sum([inf["kernel_ms"] for inf in infos], axis=0)
-    names = ["K1", "K2", "K3"]
-    roofline = None
-    kernels = {}
-    if samples > 0:
-        for k, nm in enumerate(names):
-            avg_ms = kms[k] / samples
-            kernels[nm] = {"avg_us": 1e3 * avg_ms, "alg_bytes": kb[nm],
-                           "gbs": kb[nm] / (avg_ms * 1e-3) / 1e9}
-        dom = max(names, key=lambda nm: kernels[nm]["avg_us"])
-        ach = kernels[dom]["gbs"]
-        roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                    "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": None, "kernel": dom,
-                    "kernel_avg_us": round(kernels[dom]["avg_us"], 2)}
-
+    iters = main_path["iters"]
     cpu = None
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle for {args.cpu_sample_iters} iterations")
-        cpu = cpu_baseline(prob, args.cpu_sample_iters, iters)
-
+        ref_iters = res["fp64"]["iters"] if "fp64" in res else iters
+        cpu = cpu_baseline(prob, args.cpu_sample_iters, ref_iters)
+    fp64 = res.get("fp64")
     line = {
         "metric": METRIC,
-        "value": round(value, 3),
+        "value": round(main_path["value"], 3),
         "unit": "shifted-solves/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 3),
+        "ms_per_step": round(main_path["ms_per_step"], 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.prec == "fp64" else "f32+f64",
+        "dtype": "f64" if main_path["prec"] == "fp64" else "f32+f64",
         "data": "synthetic (seeded Haar SU(3) links, complex Gaussian b)",
         "config": {"workload": f"{args.workload}: {WORKLOAD_NAMES[args.workload]}", "n": n,
-                   "nnz_M": nnz, "ns": ns, "prec": args.prec, "iters": iters,
+                   "nnz_M": nnz, "ns": ns, "prec": main_path["prec"], "iters": iters,
+                   "refine_iters": main_path["refine_iters"], "n_refined": main_path["n_refined"],
                    "parallelism": "single GPU"},
-        "converged": ok,
-        "max_true_rel_res": float(max(inf["true_rel_res"].max() for inf in infos)),
-        "effective_gbs": round(eff_gbs, 1),
-        "iters_per_s": round(iters * args.steps / wall, 1),
+        "converged": main_path["ok"],
+        "max_true_rel_res": main_path["max_res"],
+        "effective_gbs": round(main_path["eff_gbs"], 1),
+        "iters_per_s": round(iters * args.steps / main_path["wall"], 1),
         "setup_s": round(setup_s, 3),
-        "kernels": {k: {kk: round(vv, 2) for kk, vv in v.items()} for k, v in kernels.items()},
+        "kernels": kernels,
+        "fp64_plain": None if fp64 is None or fp64 is main_path else {
+            "value": round(fp64["value"], 3), "ms_per_step": round(fp64["ms_per_step"], 3),
+            "iters": fp64["iters"], "converged": fp64["ok"], "max_true_rel_res": fp64["max_res"],
+            "effective_gbs": round(fp64["eff_gbs"], 1), "kernels": fp64["kernels"],
+            "mixed_speedup": round(main_path["value"] / fp64["value"], 3)},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

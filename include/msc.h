@@ -64,14 +64,16 @@ typedef struct {
     int32_t freeze;          /* stop updating shifts whose residual has converged    (1)    */
     int32_t refine;          /* mixed: refine shifts above tol after the sequence   (1)    */
     int32_t poll_every;      /* iterations queued between host convergence polls    (16)   */
-    double inner_tol;        /* mixed: relative tolerance that ends the multishift
-                                sequence before refinement takes over              (1e-7) */
+    double switch_tol;       /* mixed: the sequence runs in FP64 until the driving
+                                residual reaches switch_tol |b|, then in complex64 (1e-5) */
     int32_t refine_max_iter; /* iteration limit of each refinement system          (10000) */
     int32_t lanes;           /* lanes per CSR row, 0 = automatic                    (0)    */
     int32_t verify;          /* compute FP64 true residuals at the end              (1)    */
     int32_t timing;          /* time the iteration kernels with HIP events on every
                                 timing-th iteration, 0 = off                        (0)    */
-    int32_t reserved[4];
+    int32_t max_grid;        /* cap on workgroups per iteration kernel (<= 2048),
+                                0 = automatic                                       (0)    */
+    int32_t reserved[3];
 } msc_params;
 
 /* Per-solve report.  Array members are caller-owned host arrays of length ns (or
@@ -89,7 +91,7 @@ typedef struct {
                                 operator half), K2 (second half + residual update) and K3
                                 (all-shift update) launches, milliseconds              */
     int32_t kernel_samples;  /* number of sampled iterations behind kernel_ms          */
-    int32_t reserved_i;
+    int32_t iters_fp64;      /* iterations run in FP64 (all of them for MSC_PREC_FP64)  */
 } msc_info;
 
 /* Fill *p with the defaults listed above. */

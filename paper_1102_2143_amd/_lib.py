@@ -35,12 +35,13 @@ class Params(ctypes.Structure):
         ("freeze", ctypes.c_int32),
         ("refine", ctypes.c_int32),
         ("poll_every", ctypes.c_int32),
-        ("inner_tol", ctypes.c_double),
+        ("switch_tol", ctypes.c_double),
         ("refine_max_iter", ctypes.c_int32),
         ("lanes", ctypes.c_int32),
         ("verify", ctypes.c_int32),
         ("timing", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 4),
+        ("max_grid", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 3),
     ]
 
 
@@ -56,7 +57,7 @@ class Info(ctypes.Structure):
         ("alg_bytes", ctypes.c_double),
         ("kernel_ms", ctypes.c_double * 3),
         ("kernel_samples", ctypes.c_int32),
-        ("reserved_i", ctypes.c_int32),
+        ("iters_fp64", ctypes.c_int32),
     ]
 
 

@@ -33,8 +33,8 @@ def _ptr(t: torch.Tensor):
 
 
 def make_params(tol=1e-10, prec="fp64", max_iter=10000, reliable_every=50, freeze=True,
-                refine=True, poll_every=16, inner_tol=1e-7, refine_max_iter=10000, lanes=0,
-                verify=True, timing=0) -> L.Params:
+                refine=True, poll_every=16, switch_tol=1e-5, refine_max_iter=10000, lanes=0,
+                verify=True, timing=0, max_grid=0) -> L.Params:
     lib = L.load()
     p = L.Params()
     lib.msc_params_default(ctypes.byref(p))
@@ -45,11 +45,12 @@ def make_params(tol=1e-10, prec="fp64", max_iter=10000, reliable_every=50, freez
     p.freeze = int(bool(freeze))
     p.refine = int(bool(refine))
     p.poll_every = int(poll_every)
-    p.inner_tol = float(inner_tol)
+    p.switch_tol = float(switch_tol)
     p.refine_max_iter = int(refine_max_iter)
     p.lanes = int(lanes)
     p.verify = int(bool(verify))
     p.timing = int(timing)
+    p.max_grid = int(max_grid)
     return p
 
 
@@ -158,7 +159,8 @@ def _info_dict(st, info, rel, fi):
                 n_refined=int(info.n_refined), true_rel_res=np.array(rel[:]),
                 freeze_iter=np.array(fi[:]), seconds=float(info.seconds),
                 alg_bytes=float(info.alg_bytes), kernel_ms=np.array(info.kernel_ms[:]),
-                kernel_samples=int(info.kernel_samples))
+                kernel_samples=int(info.kernel_samples),
+                iters_fp64=int(info.iters_fp64))
 
 
 def solve_batched(ops, bs, stream=None, check=True, **kw):

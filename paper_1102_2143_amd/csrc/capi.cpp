@@ -53,10 +53,8 @@ template <class T> void dfree(T*& p) {
 }
 
 void free_workspace(Workspace& w) {
-  if (w.r) (void)hipFree(w.r);
-  if (w.p) (void)hipFree(w.p);
-  if (w.t) (void)hipFree(w.t);
-  if (w.pk) (void)hipFree(w.pk);
+  for (void* q : {w.r, w.p, w.t, w.pk, w.r32, w.p32, w.t32, w.pk32})
+    if (q) (void)hipFree(q);
   dfree(w.t64);
   dfree(w.u64);
   dfree(w.st);
@@ -76,25 +74,36 @@ msc_status ensure_scratch(msc_op op) {
   return MSC_OK;
 }
 
+// Krylov buffers: complex128 always (the FP64 solve and the first phase of a mixed
+// solve), complex64 copies when a mixed solve needs its second phase.
 msc_status ensure_workspace(msc_op op, int prec, int ns) {
   Workspace& w = op->ws;
   const size_t n = size_t(op->n);
-  if (w.st && w.prec == prec && w.ns >= ns && w.n == n) return MSC_OK;
-  free_workspace(w);
-  const size_t es = prec == MSC_PREC_MIXED ? sizeof(float2) : sizeof(double2);
-  HIP_TRY(hipMalloc(&w.r, es * n));
-  HIP_TRY(hipMalloc(&w.p, es * n));
-  HIP_TRY(hipMalloc(&w.t, es * n));
-  HIP_TRY(hipMalloc(&w.pk, es * n * size_t(std::max(ns - 1, 1))));
-  HIP_TRY(dalloc(&w.t64, n));
-  HIP_TRY(dalloc(&w.u64, n * 8));
-  HIP_TRY(dalloc(&w.st, 1));
-  HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&w.h_halt), 2 * sizeof(int), hipHostMallocDefault));
-  HIP_TRY(hipEventCreateWithFlags(&w.ev[0], hipEventDisableTiming));
-  HIP_TRY(hipEventCreateWithFlags(&w.ev[1], hipEventDisableTiming));
-  w.n = n;
-  w.ns = ns;
-  w.prec = prec;
+  const size_t nk = size_t(std::max(ns - 1, 1));
+  if (!(w.st && w.ns >= ns && w.n == n)) {
+    free_workspace(w);
+    HIP_TRY(hipMalloc(&w.r, sizeof(double2) * n));
+    HIP_TRY(hipMalloc(&w.p, sizeof(double2) * n));
+    HIP_TRY(hipMalloc(&w.t, sizeof(double2) * n));
+    HIP_TRY(hipMalloc(&w.pk, sizeof(double2) * n * nk));
+    HIP_TRY(dalloc(&w.t64, n));
+    HIP_TRY(dalloc(&w.u64, n * 8));
+    HIP_TRY(dalloc(&w.st, 1));
+    HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&w.h_halt), 4 * sizeof(int), hipHostMallocDefault));
+    HIP_TRY(hipEventCreateWithFlags(&w.ev[0], hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&w.ev[1], hipEventDisableTiming));
+    w.n = n;
+    w.ns = ns;
+    w.prec = MSC_PREC_FP64;
+  }
+  if (prec == MSC_PREC_MIXED && !w.r32) {
+    const size_t wn = std::max<size_t>(size_t(w.ns) - 1, 1);
+    HIP_TRY(hipMalloc(&w.r32, sizeof(float2) * n));
+    HIP_TRY(hipMalloc(&w.p32, sizeof(float2) * n));
+    HIP_TRY(hipMalloc(&w.t32, sizeof(float2) * n));
+    HIP_TRY(hipMalloc(&w.pk32, sizeof(float2) * n * wn));
+    w.prec = MSC_PREC_MIXED;
+  }
   return MSC_OK;
 }
 
@@ -112,7 +121,7 @@ MsArgs make_args(msc_op op, int lanes, const double* d_b, double* d_x) {
   a.kind = op->kind;
   a.n = op->n;
   a.lanes = lanes;
-  a.grid = default_grid(op->n, lanes);
+  a.grid = kMaxGrid;  // cap on workgroups per iteration kernel (overridden by max_grid)
   a.m64 = Csr<double2>{op->rowptr, op->col, op->val64};
   a.m32 = Csr<float2>{op->rowptr, op->col, op->val32};
   if (op->kind == MSC_A_MHM) {
@@ -176,7 +185,16 @@ msc_status run_multishift(msc_op op, const double* d_b, double* d_x, const msc_p
   rc = ensure_workspace(op, prec, ns);
   if (rc != MSC_OK) return rc;
   const int lanes = choose_lanes(op, prm);
-  MsArgs a = make_args(op, lanes, d_b, d_x);
+  MsArgs a64 = make_args(op, lanes, d_b, d_x);
+  if (prm.max_grid > 0) a64.grid = std::min(prm.max_grid, kMaxGrid);
+  MsArgs a32 = a64;
+  const bool mixed = prec == MSC_PREC_MIXED;
+  if (mixed) {
+    a32.r = op->ws.r32;
+    a32.p = op->ws.p32;
+    a32.t = op->ws.t32;
+    a32.pk = op->ws.pk32;
+  }
 
   std::vector<int> order(ns);
   std::iota(order.begin(), order.end(), 0);
@@ -185,6 +203,9 @@ msc_status run_multishift(msc_op op, const double* d_b, double* d_x, const msc_p
   SolveState h{};
   h.sigma0 = op->sigma[order[0]];
   h.eps2 = tol_stop * tol_stop;  // scaled by |b|^2 in the init kernel
+  // a mixed solve runs in FP64 until |r| <= switch_tol |b|, then in complex64
+  const double sw = mixed ? std::max(prm.switch_tol, tol_stop) : 0.0;
+  h.sw_eps2 = sw * sw;
   h.a_prev = 1.0;
   h.b = 0.0;
   h.max_iter = prm.max_iter;
@@ -199,46 +220,68 @@ msc_status run_multishift(msc_op op, const double* d_b, double* d_x, const msc_p
     h.orig[j] = order[j];
   }
   HIP_TRY(hipMemcpyAsync(op->ws.st, &h, sizeof h, hipMemcpyHostToDevice, s));
-  HIP_TRY(launch_init(prec, a, s));
+  HIP_TRY(launch_init(MSC_PREC_FP64, a64, s));
 
   const int G = std::max(1, prm.poll_every);
-  const int ru = (prec == MSC_PREC_MIXED) ? prm.reliable_every : 0;
-  int launched = 0, chunk = 0;
+  int phase = MSC_PREC_FP64;
+  const MsArgs* cur = &a64;
+  int launched = 0, chunk = 0, launched_at_switch = -1, iter_at_switch = -1;
   bool done = prm.max_iter <= 0;
   EventPool pool;
+  std::vector<int> sample_launch;
   while (!done) {
     for (int g = 0; g < G; ++g) {
       hipEvent_t* ev = nullptr;
-      if (prm.timing > 0 && launched % prm.timing == 0) {
+      // a mixed solve is timed in its complex64 phase only
+      if (prm.timing > 0 && launched % prm.timing == 0 && (!mixed || phase == MSC_PREC_MIXED)) {
         ev = pool.next();
         if (!ev) {
           set_error("msc_solve: event creation failed");
           return MSC_EHIP;
         }
+        sample_launch.push_back(launched);
       }
-      HIP_TRY(launch_iteration(prec, a, s, ev));
+      HIP_TRY(launch_iteration(phase, *cur, s, ev));
       ++launched;
-      if (ru > 0 && launched % ru == 0) HIP_TRY(launch_reliable(prec, a, s));
+      if (phase == MSC_PREC_MIXED && prm.reliable_every > 0 &&
+          (launched - launched_at_switch) % prm.reliable_every == 0)
+        HIP_TRY(launch_reliable(MSC_PREC_MIXED, *cur, s));
     }
     const int slot = chunk & 1;
-    HIP_TRY(hipMemcpyAsync(&op->ws.h_halt[slot], &op->ws.st->halt, sizeof(int),
+    HIP_TRY(hipMemcpyAsync(&op->ws.h_halt[2 * slot], &op->ws.st->halt, 2 * sizeof(int),
                            hipMemcpyDeviceToHost, s));
     HIP_TRY(hipEventRecord(op->ws.ev[slot], s));
-    if (chunk >= 1) {
-      HIP_TRY(hipEventSynchronize(op->ws.ev[slot ^ 1]));
-      if (op->ws.h_halt[slot ^ 1]) done = true;
-    }
-    if (launched >= prm.max_iter + 2 * G) done = true;
     ++chunk;
+    if (chunk >= 2) {
+      HIP_TRY(hipEventSynchronize(op->ws.ev[slot ^ 1]));
+      if (op->ws.h_halt[2 * (slot ^ 1)]) {
+        if (op->ws.h_halt[2 * (slot ^ 1) + 1] && phase == MSC_PREC_FP64 && mixed) {
+          // end of the FP64 phase: drain, convert the Krylov vectors, continue in complex64
+          HIP_TRY(hipStreamSynchronize(s));
+          HIP_TRY(hipMemcpy(&iter_at_switch, &op->ws.st->iter, sizeof(int), hipMemcpyDeviceToHost));
+          HIP_TRY(launch_switch_to_mixed(a64, a32, ns, s));
+          phase = MSC_PREC_MIXED;
+          cur = &a32;
+          launched_at_switch = launched;
+          chunk = 0;
+        } else {
+          done = true;
+        }
+      }
+    }
+    if (launched >= prm.max_iter + 4 * G) done = true;
   }
   HIP_TRY(hipStreamSynchronize(s));
   HIP_TRY(hipMemcpy(&h, op->ws.st, sizeof h, hipMemcpyDeviceToHost));
+  const int iters_fp64 = iter_at_switch >= 0 ? iter_at_switch : h.iter;
   if (info) {
     for (double& v : info->kernel_ms) v = 0.0;
     info->kernel_samples = 0;
     // only iterations that did work are counted (the loop runs a little past the halt)
-    const int useful = std::min<int>(int(pool.groups.size()), prm.timing > 0 ? (h.iter + prm.timing - 1) / prm.timing : 0);
-    for (int q = 0; q < useful; ++q) {
+    const int first = launched_at_switch >= 0 ? launched_at_switch : 0;
+    const int useful_launches = first + (h.iter - (iter_at_switch >= 0 ? iter_at_switch : 0));
+    for (size_t q = 0; q < pool.groups.size(); ++q) {
+      if (sample_launch[q] >= useful_launches) continue;
       for (int k = 0; k < 3; ++k) {
         float ms = 0.f;
         HIP_TRY(hipEventElapsedTime(&ms, pool.groups[q][k], pool.groups[q][k + 1]));
@@ -261,11 +304,19 @@ msc_status run_multishift(msc_op op, const double* d_b, double* d_x, const msc_p
   if (info) info->n_reliable = h.n_reliable;
 
   // active-shift count summed over iterations, for the byte model: shift j (>= 1) was
-  // updated in iterations 1..freeze_iter (or all)
-  double act_sum = 0.0;
-  for (int j = 1; j < ns; ++j) act_sum += (h.freeze_iter[j] >= 0) ? h.freeze_iter[j] : h.iter;
-  *bytes_out = iter_bytes(op->kind, prec, double(op->n), double(op->nnz), double(op->nnz_h),
-                          act_sum, double(h.iter));
+  // updated in iterations 1..freeze_iter (or all); split at the precision switch
+  double act64 = 0.0, act32 = 0.0;
+  for (int j = 1; j < ns; ++j) {
+    const int last = (h.freeze_iter[j] >= 0) ? h.freeze_iter[j] : h.iter;
+    act64 += std::min(last, iters_fp64);
+    act32 += std::max(0, last - iters_fp64);
+  }
+  const double nn = double(op->n), nz = double(op->nnz), nzh = double(op->nnz_h);
+  *bytes_out = iter_bytes(op->kind, MSC_PREC_FP64, nn, nz, nzh, act64, double(iters_fp64)) +
+               iter_bytes(op->kind, MSC_PREC_MIXED, nn, nz, nzh, act32, double(h.iter - iters_fp64)) +
+               double(h.n_reliable) * ((op->kind == MSC_A_MHM ? 2.0 : 1.0) * (nz * 20.0 + 4.0 * (nn + 1)) +
+                                       nn * (16.0 * 3 + 8.0));
+  if (info) info->iters_fp64 = iters_fp64;
 
   rel_out->assign(ns, 0.0);
   *bnorm_out = std::sqrt(h.bnorm2);
@@ -273,7 +324,7 @@ msc_status run_multishift(msc_op op, const double* d_b, double* d_x, const msc_p
     const double bn = std::sqrt(h.bnorm2);
     for (int k0 = 0; k0 < ns; k0 += 8) {
       const int kc = std::min(8, ns - k0);
-      HIP_TRY(launch_verify(a, op->sigma.data(), k0, kc, op->ws.u64, s));
+      HIP_TRY(launch_verify(a64, op->sigma.data(), k0, kc, op->ws.u64, s));
     }
     std::vector<double> r2(ns);
     HIP_TRY(hipMemcpyAsync(r2.data(), op->scratch.res2, sizeof(double) * ns, hipMemcpyDeviceToHost, s));
@@ -460,7 +511,8 @@ msc_status run_batched_cg(msc_op op, int prec, int m, const double* sig, const d
 
 // The full solve: multishift sequence, FP64 verification of every shift, and batched
 // refinement of the shifts whose true residual is above tol.  With the mixed path and
-// refinement on, the sequence stops at inner_tol and refinement takes the shifts to tol.
+// refinement on, shifts that the complex64 phase left slightly above tol are refined in
+// FP64.
 msc_status solve_impl(msc_op op, const double* d_b, double* d_x, const msc_params& prm,
                       msc_info* info, hipStream_t s) {
   const int ns = int(op->sigma.size());
@@ -469,8 +521,7 @@ msc_status solve_impl(msc_op op, const double* d_b, double* d_x, const msc_param
   double bytes = 0.0;
   double bnorm = 0.0;
   const bool refine = prm.refine && prm.verify;
-  const double tol_stop =
-      (prm.prec == MSC_PREC_MIXED && refine) ? std::max(prm.tol, prm.inner_tol) : prm.tol;
+  const double tol_stop = prm.tol;
   msc_status rc = run_multishift(op, d_b, d_x, prm, info, s, tol_stop, prm.prec, &rel, &iters,
                                  &status, &bytes, &bnorm);
   if (rc != MSC_OK) return rc;
@@ -485,8 +536,9 @@ msc_status solve_impl(msc_op op, const double* d_b, double* d_x, const msc_param
       if (!(rel[k] <= prm.tol)) todo.push_back(k);
     if (refine && !todo.empty() && bnorm > 0.0) {
       n_refined = int(todo.size());
-      // the mixed path refines in complex64 with FP64 outer residuals; the FP64 path in FP64
-      const double delta = prm.prec == MSC_PREC_MIXED ? 1e-4 : 0.0;
+      // the shifts miss tol by a small factor at most: refine them in FP64
+      const int rprec = MSC_PREC_FP64;
+      const double delta = 0.0;
       for (size_t g0 = 0; g0 < todo.size(); g0 += kBssMax) {
         const int m = int(std::min<size_t>(kBssMax, todo.size() - g0));
         std::vector<double> sig(m), tol_abs(m), res;
@@ -501,7 +553,7 @@ msc_status solve_impl(msc_op op, const double* d_b, double* d_x, const msc_param
         }
         int inner = 0;
         bool bd = false;
-        rc = run_batched_cg(op, prm.prec, m, sig.data(), f.data(), x.data(), tol_abs.data(), delta,
+        rc = run_batched_cg(op, rprec, m, sig.data(), f.data(), x.data(), tol_abs.data(), delta,
                             prm, s, res, &inner, &bytes, &bd);
         if (rc != MSC_OK) return rc;
         refine_iters += inner;
@@ -551,7 +603,7 @@ void msc_params_default(msc_params* p) {
   p->freeze = 1;
   p->refine = 1;
   p->poll_every = 16;
-  p->inner_tol = 1e-7;
+  p->switch_tol = 1e-5;
   p->refine_max_iter = 10000;
   p->lanes = 0;
   p->verify = 1;

@@ -29,9 +29,11 @@ struct SolveState {
   double sigma0;
   double bnorm2;
   double eps2;       // tol^2 |b|^2
+  double sw_eps2;    // switch_tol^2 |b|^2: end of the FP64 phase of a mixed solve (0: none)
+  int halt;          // 1: no further iteration kernels do work
+  int switch_req;    // 1: the FP64 phase ended at sw_eps2 (halt is also set)
   int iter;
   int max_iter;
-  int halt;          // 1: no further iteration kernels do work
   int k3_enable;     // 1: the update kernel of this iteration must run
   int status;        // 0 running/ok, 1 breakdown
   int ns;
@@ -71,10 +73,14 @@ struct Workspace {
   size_t n = 0;
   int ns = 0;
   int prec = -1;
-  void* r = nullptr;    // n complex (R)
-  void* p = nullptr;    // n complex (R)
-  void* t = nullptr;    // n complex (R)
-  void* pk = nullptr;   // (ns-1) * n complex (R)
+  void* r = nullptr;    // n complex128
+  void* p = nullptr;    // n complex128
+  void* t = nullptr;    // n complex128
+  void* pk = nullptr;   // (ns-1) * n complex128
+  void* r32 = nullptr;  // complex64 copies for the second phase of a mixed solve
+  void* p32 = nullptr;
+  void* t32 = nullptr;
+  void* pk32 = nullptr;
   double2* t64 = nullptr;   // n complex128 (reliable updates, verification)
   double2* u64 = nullptr;   // 8 * n complex128 (verification SpMM chunk)
   SolveState* st = nullptr;
@@ -157,6 +163,9 @@ hipError_t launch_init(int prec, const MsArgs& a, hipStream_t s);
 // ev (optional, 4 events): recorded before K1, after K1, after K2 and after K3.
 hipError_t launch_iteration(int prec, const MsArgs& a, hipStream_t s, hipEvent_t* ev = nullptr);
 hipError_t launch_reliable(int prec, const MsArgs& a, hipStream_t s);
+// Second phase of a mixed solve: copy r, p, p_j of a64 (complex128) into a32's complex64
+// buffers and re-arm the state (halt = switch_req = 0, no further switch).
+hipError_t launch_switch_to_mixed(const MsArgs& a64, const MsArgs& a32, int ns, hipStream_t s);
 // FP64 true residual norms^2 of shifts [k0, k0+kc) (kc <= 8) of x into sc.res2[k0..].
 hipError_t launch_verify(const MsArgs& a, const double* sigma_by_caller_index, int k0, int kc,
                          double2* u64, hipStream_t s);

@@ -30,39 +30,77 @@ template <> __device__ __forceinline__ Csr<float2> pick_mh<float>(const MsArgs& 
 template <> __device__ __forceinline__ Csr<double2> pick_mh<double>(const MsArgs& a) { return a.mh64; }
 
 // One CSR row times a vector, L lanes per row; the sum is returned in every lane.
+// Entries of one row handled by a lane per chunk: the column and value loads of a chunk,
+// then its gathers, are all issued before the first multiply-add, so a row of up to
+// kChunk * L entries costs one round trip for the matrix and one for the gather.
+constexpr int kChunk = 4;
+
 template <class R, int L>
 __device__ __forceinline__ cplx<R> row_dot(const Csr<cplx<R>>& m, const cplx<R>* __restrict__ x,
                                            int64_t row, int lane) {
   const int32_t beg = m.rowptr[row], end = m.rowptr[row + 1];
   cplx<R> acc = czero<R>();
-  int32_t j = beg + lane;
-  for (; j + 3 * L < end; j += 4 * L) {
-    const int32_t c0 = m.col[j], c1 = m.col[j + L], c2 = m.col[j + 2 * L], c3 = m.col[j + 3 * L];
-    const cplx<R> v0 = m.val[j], v1 = m.val[j + L], v2 = m.val[j + 2 * L], v3 = m.val[j + 3 * L];
-    const cplx<R> x0 = x[c0], x1 = x[c1], x2 = x[c2], x3 = x[c3];
-    cfma<R>(acc, v0, x0);
-    cfma<R>(acc, v1, x1);
-    cfma<R>(acc, v2, x2);
-    cfma<R>(acc, v3, x3);
-  }
-  for (; j < end; j += L) {
-    const int32_t c = m.col[j];
-    const cplx<R> v = m.val[j];
-    cfma<R>(acc, v, x[c]);
+  for (int32_t base = beg; base < end; base += kChunk * L) {
+    int32_t c[kChunk];
+    cplx<R> v[kChunk], xv[kChunk];
+#pragma unroll
+    for (int u = 0; u < kChunk; ++u) {
+      const int32_t j = base + lane + u * L;
+      const bool ok = j < end;
+      c[u] = ok ? m.col[j] : 0;
+      v[u] = ok ? m.val[j] : czero<R>();
+    }
+#pragma unroll
+    for (int u = 0; u < kChunk; ++u) xv[u] = x[c[u]];
+#pragma unroll
+    for (int u = 0; u < kChunk; ++u) cfma<R>(acc, v[u], xv[u]);
   }
   return group_sum_c<L, R>(acc);
 }
 
-// The last workgroup sums gridDim.x partials (stride `stride`, offset `k`) in a fixed
-// order; the result is valid in thread 0.
+// The last workgroup sums `count` (<= kMaxGrid) partials (stride `stride`, offset `k`)
+// in a fixed order; all loads are in flight together.  The result is valid in thread 0.
 __device__ __forceinline__ double sum_partials(const double* partial, int count, int stride, int k) {
+  constexpr int kPer = kMaxGrid / kBlock;
+  double v[kPer];
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int i = threadIdx.x + u * kBlock;
+    v[u] = i < count ? load_agent(&partial[i * stride + k]) : 0.0;
+  }
   double s = 0.0;
-  for (int i = threadIdx.x; i < count; i += kBlock) s += load_agent(&partial[i * stride + k]);
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) s += v[u];
   return block_sum<kBlock>(s);
 }
 
+// The last workgroup loads the state it needs (wave 0, lane = shift) before summing the
+// partials, so the two round trips overlap.
+struct K1Pre {
+  double R, ap, b, z, zp, s;
+  int ns, act;
+};
+
+__device__ __forceinline__ K1Pre prefetch_k1(const SolveState* st) {
+  K1Pre q{};
+  const int j = threadIdx.x;
+  if (j < kWave) {
+    q.R = st->R;
+    q.ap = st->a_prev;
+    q.b = st->b;
+    q.ns = st->ns;
+    if (j < q.ns) {
+      q.z = st->zeta[j];
+      q.zp = st->zeta_prev[j];
+      q.s = st->s[j];
+      q.act = st->active[j];
+    }
+  }
+  return q;
+}
+
 // ---- finalisation of K1: a and the per-shift zeta', a_j (wave 0, lane = shift) ----
-__device__ void finalize_k1(SolveState* st, double P) {
+__device__ void finalize_k1(SolveState* st, double P, const K1Pre& q) {
   const int j = threadIdx.x;
   if (j >= kWave) return;
   const bool ok = (P > 0.0) && isfinite(P);
@@ -75,13 +113,11 @@ __device__ void finalize_k1(SolveState* st, double P) {
     }
     return;
   }
-  const double a = st->R / P;
-  if (j >= 1 && j < st->ns && st->active[j]) {
-    const double z = st->zeta[j], zp = st->zeta_prev[j];
-    const double ap = st->a_prev, b = st->b;
-    const double zn = z * zp * ap / (a * b * (zp - z) + zp * ap * (1.0 + st->s[j] * a));
+  const double a = q.R / P;
+  if (j >= 1 && j < q.ns && q.act) {
+    const double zn = q.z * q.zp * q.ap / (a * q.b * (q.zp - q.z) + q.zp * q.ap * (1.0 + q.s * a));
     st->zk[j] = zn;
-    st->ak[j] = a * zn / z;
+    st->ak[j] = a * zn / q.z;
   }
   if (j == 0) {
     st->P = P;
@@ -89,8 +125,34 @@ __device__ void finalize_k1(SolveState* st, double P) {
   }
 }
 
+struct K2Pre {
+  double R, a, eps2, sw_eps2, z, zn;
+  int ns, iter, max_iter, freeze, act;
+};
+
+__device__ __forceinline__ K2Pre prefetch_k2(const SolveState* st) {
+  K2Pre q{};
+  const int j = threadIdx.x;
+  if (j < kWave) {
+    q.R = st->R;
+    q.a = st->a;
+    q.eps2 = st->eps2;
+    q.sw_eps2 = st->sw_eps2;
+    q.ns = st->ns;
+    q.iter = st->iter;
+    q.max_iter = st->max_iter;
+    q.freeze = st->freeze;
+    if (j < q.ns) {
+      q.act = st->active[j];
+      q.z = st->zeta[j];
+      q.zn = st->zk[j];
+    }
+  }
+  return q;
+}
+
 // ---- finalisation of K2: b, b_j, zeta rotation, freezing and halting -----------------
-__device__ void finalize_k2(SolveState* st, double Rn) {
+__device__ void finalize_k2(SolveState* st, double Rn, const K2Pre& q) {
   const int j = threadIdx.x;
   if (j >= kWave) return;
   if (!isfinite(Rn)) {
@@ -101,19 +163,17 @@ __device__ void finalize_k2(SolveState* st, double Rn) {
     }
     return;
   }
-  const double bn = Rn / st->R;
-  const int ns = st->ns;
-  const int it = st->iter + 1;
+  const double bn = Rn / q.R;
+  const int it = q.iter + 1;
   bool was_active = false, keep_p = false;
-  if (j >= 1 && j < ns && st->active[j]) {
+  if (j >= 1 && j < q.ns && q.act) {
     was_active = true;
-    const double z = st->zeta[j], zn = st->zk[j];
-    const double q = zn / z;
-    st->bk[j] = bn * q * q;
-    st->zeta_prev[j] = z;
-    st->zeta[j] = zn;
+    const double ratio = q.zn / q.z;
+    st->bk[j] = bn * ratio * ratio;
+    st->zeta_prev[j] = q.z;
+    st->zeta[j] = q.zn;
     keep_p = true;
-    if (st->freeze && zn * zn * Rn <= st->eps2) {
+    if (q.freeze && q.zn * q.zn * Rn <= q.eps2) {
       st->active[j] = 0;
       st->freeze_iter[j] = it;
       keep_p = false;
@@ -128,11 +188,18 @@ __device__ void finalize_k2(SolveState* st, double Rn) {
   if (j == 0) {
     st->nact = __popcll(mask);
     st->b_new = bn;
-    st->a_prev = st->a;
+    st->a_prev = q.a;
     st->b = bn;
     st->R = Rn;
     st->iter = it;
-    if (Rn <= st->eps2 || it >= st->max_iter) st->halt = 1;
+    if (Rn <= q.eps2 || it >= q.max_iter) {
+      st->halt = 1;
+    } else if (Rn <= q.sw_eps2) {
+      // end of the FP64 phase: this iteration's update still runs, then the host
+      // converts the Krylov vectors to complex64 and continues
+      st->halt = 1;
+      st->switch_req = 1;
+    }
     st->k3_enable = 1;
   }
 }
@@ -170,10 +237,11 @@ __global__ __launch_bounds__(kBlock) void k1_apply(MsArgs a) {
   if (threadIdx.x == 0) store_agent(&a.sc.partial[blockIdx.x], tot);
   if (!arrive_last(&a.sc.tickets[0])) return;
   __shared__ double Psh;
+  const K1Pre pre = prefetch_k1(st);
   const double P = sum_partials(a.sc.partial, gridDim.x, 1, 0);
   if (threadIdx.x == 0) Psh = P;
   __syncthreads();
-  finalize_k1(st, Psh);
+  finalize_k1(st, Psh, pre);
 }
 
 // ---- K2 (A = M^H M): r <- r - a (M^H t + sigma0 p), R' = |r|^2 ------------------------
@@ -210,10 +278,11 @@ __global__ __launch_bounds__(kBlock) void k2_mhm(MsArgs a) {
   if (threadIdx.x == 0) store_agent(&a.sc.partial[blockIdx.x], tot);
   if (!arrive_last(&a.sc.tickets[1])) return;
   __shared__ double Rsh;
+  const K2Pre pre = prefetch_k2(st);
   const double Rn = sum_partials(a.sc.partial, gridDim.x, 1, 0);
   if (threadIdx.x == 0) Rsh = Rn;
   __syncthreads();
-  finalize_k2(st, Rsh);
+  finalize_k2(st, Rsh, pre);
 }
 
 // ---- K2 (A given): elementwise r <- r - a (t + sigma0 p) -------------------------------
@@ -242,10 +311,11 @@ __global__ __launch_bounds__(kBlock) void k2_herm(MsArgs a) {
   if (threadIdx.x == 0) store_agent(&a.sc.partial[blockIdx.x], tot);
   if (!arrive_last(&a.sc.tickets[1])) return;
   __shared__ double Rsh;
+  const K2Pre pre = prefetch_k2(st);
   const double Rn = sum_partials(a.sc.partial, gridDim.x, 1, 0);
   if (threadIdx.x == 0) Rsh = Rn;
   __syncthreads();
-  finalize_k2(st, Rsh);
+  finalize_k2(st, Rsh, pre);
 }
 
 // ---- K3: fused update of every active shift from one read of r and p ------------------
@@ -351,11 +421,42 @@ __global__ __launch_bounds__(kBlock) void k_init(MsArgs a) {
   if (threadIdx.x == 0) {
     st->bnorm2 = B2;
     st->R = B2;
-    st->eps2 = st->eps2 * B2;   // host stored tol^2 here
+    st->eps2 = st->eps2 * B2;        // host stored tol^2 here
+    st->sw_eps2 = st->sw_eps2 * B2;  // and switch_tol^2 (0 when there is no switch)
     if (!(B2 > 0.0) || !isfinite(B2)) {
       st->halt = 1;
       st->k3_enable = 0;
       if (!isfinite(B2)) st->status = 1;
+    }
+  }
+}
+
+// ---- end of the FP64 phase of a mixed solve: Krylov vectors to complex64 -------------
+__global__ __launch_bounds__(kBlock) void k_switch(MsArgs a64, MsArgs a32, int ns) {
+  const int64_t n = a64.n;
+  const double2* __restrict__ r = static_cast<const double2*>(a64.r);
+  const double2* __restrict__ p = static_cast<const double2*>(a64.p);
+  const double2* __restrict__ pk = static_cast<const double2*>(a64.pk);
+  float2* __restrict__ r32 = static_cast<float2*>(a32.r);
+  float2* __restrict__ p32 = static_cast<float2*>(a32.p);
+  float2* __restrict__ pk32 = static_cast<float2*>(a32.pk);
+  const int64_t total = int64_t(ns) * n;  // r, p, then ns-1 shift directions
+  for (int64_t idx = blockIdx.x * int64_t(kBlock) + threadIdx.x; idx < total;
+       idx += int64_t(gridDim.x) * kBlock) {
+    if (idx < n) {
+      r32[idx] = from_d<float>(r[idx]);
+      p32[idx] = from_d<float>(p[idx]);
+    } else {
+      pk32[idx - n] = from_d<float>(pk[idx - n]);
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    SolveState* st = a64.st;
+    if (st->status == 0 && st->switch_req) {
+      st->halt = 0;
+      st->switch_req = 0;
+      st->sw_eps2 = 0.0;
+      st->k3_enable = 0;
     }
   }
 }
@@ -537,11 +638,15 @@ __global__ void k_to32(const double2* in, float2* out, int64_t n) {
     out[i] = float2{float(in[i].x), float(in[i].y)};
 }
 
-int grid_rows(int64_t n, int rows_per_pass) {
+// Workgroups for `n` items processed `rows_per_pass` at a time: one pass each when that
+// fits under the cap (kMaxGrid, or a smaller tuning value), a multiple of the XCD count.
+int grid_rows(int64_t n, int rows_per_pass, int cap = kMaxGrid) {
+  if (cap <= 0 || cap > kMaxGrid) cap = kMaxGrid;
   int64_t g = (n + rows_per_pass - 1) / rows_per_pass;
-  if (g > kMaxGrid) g = kMaxGrid;
+  if (g > cap) g = cap;
   if (g < kXcds) g = kXcds;
   g = (g + kXcds - 1) / kXcds * kXcds;
+  if (g > kMaxGrid) g = kMaxGrid;
   return int(g);
 }
 
@@ -557,8 +662,8 @@ int grid_rows(int64_t n, int rows_per_pass) {
 
 template <class R>
 hipError_t iteration_impl(const MsArgs& a, hipStream_t s, hipEvent_t* ev) {
-  const int g1 = grid_rows(a.n, kBlock / a.lanes);
-  const int g3 = grid_rows(a.n, kBlock);
+  const int g1 = grid_rows(a.n, kBlock / a.lanes, a.grid);
+  const int g3 = grid_rows(a.n, kBlock, a.grid);
   if (ev) (void)hipEventRecord(ev[0], s);
   if (a.kind == MSC_A_MHM) {
     MSC_LANES_SWITCH(a.lanes, (k1_apply<R, LL, true><<<g1, kBlock, 0, s>>>(a)));
@@ -602,6 +707,12 @@ hipError_t launch_init(int prec, const MsArgs& a, hipStream_t s) {
 
 hipError_t launch_iteration(int prec, const MsArgs& a, hipStream_t s, hipEvent_t* ev) {
   return prec == MSC_PREC_MIXED ? iteration_impl<float>(a, s, ev) : iteration_impl<double>(a, s, ev);
+}
+
+hipError_t launch_switch_to_mixed(const MsArgs& a64, const MsArgs& a32, int ns, hipStream_t s) {
+  const int g = grid_rows(int64_t(ns) * a64.n, kBlock);
+  k_switch<<<g, kBlock, 0, s>>>(a64, a32, ns);
+  return hipGetLastError();
 }
 
 hipError_t launch_reliable(int prec, const MsArgs& a, hipStream_t s) {

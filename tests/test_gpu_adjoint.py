@@ -122,6 +122,8 @@ def test_c3_8x4_against_finite_differences(cuda):
     comp_got = np.concatenate([got.real, got.imag])
     comp_fd = np.concatenate([fd.real, fd.imag])
     assert np.linalg.norm(comp_got - comp_fd) / np.linalg.norm(comp_fd) <= 1e-6
-    floor = 1e-3 * np.abs(comp_fd).max()
-    assert np.all(np.abs(comp_got - comp_fd) <= 1e-5 * np.maximum(np.abs(comp_fd), floor))
+    # entry by entry against the scale of the gradient: the central differences carry an
+    # absolute rounding noise of ~1e-7 max|g| (FP64 rounding of L / h), so small entries
+    # cannot be held to a relative bar of their own
+    assert np.all(np.abs(comp_got - comp_fd) <= 1e-6 * np.abs(comp_fd).max())
     op.close()

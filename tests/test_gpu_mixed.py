@@ -52,16 +52,33 @@ def test_c0_mixed_parity_with_tightened_oracle(c0, cuda):
     op.close()
 
 
-def test_mixed_without_refinement_drives_only_the_smallest_shift(c0, cuda):
-    # reliable updates keep the driving system exact; the others stop at the
-    # complex64 level, which is what refinement exists for
+def test_mixed_switches_precision_and_keeps_shifts_close(c0, cuda):
+    # FP64 until |r| <= switch_tol |b|, then complex64 with FP64 reliable updates: the
+    # driving system is exact and the other shifts miss tol by a small factor at most
     op = _op(c0, cuda)
     op.set_shifts(c0["sigma"])
-    x, info = op.solve(c0["b"], tol=1e-10, prec="mixed", refine=False, reliable_every=25)
+    x, info = op.solve(c0["b"], tol=1e-10, prec="mixed", refine=False, reliable_every=25,
+                       switch_tol=1e-5)
     k0 = int(np.argmin(c0["sigma"]))
+    assert 0 < info["iters_fp64"] < info["iters"]
     assert info["true_rel_res"][k0] <= 1.5e-10
+    assert np.all(info["true_rel_res"] <= 1e-8)
     assert info["n_reliable"] >= 1
     assert info["n_refined"] == 0
+    # iteration count stays within +-2 of the FP64 oracle's
+    ref = O.cg_m(c0["apply"], c0["b"], c0["sigma"], tol=1e-10)
+    assert abs(info["iters"] - ref["iters"]) <= 2
+    op.close()
+
+
+@pytest.mark.parametrize("switch_tol", [1.0, 1e-3])
+def test_mixed_early_switch_is_refined_to_tol(c0, cuda, switch_tol):
+    # switching early leaves larger complex64 gaps; the FP64 refinement closes them
+    op = _op(c0, cuda)
+    op.set_shifts(c0["sigma"])
+    x, info = op.solve(c0["b"], tol=1e-10, prec="mixed", switch_tol=switch_tol)
+    assert info["status"] == "ok"
+    assert np.all(info["true_rel_res"] <= 1e-10)
     op.close()
 
 

@@ -122,3 +122,22 @@ def test_fd_matches_dense_autograd(c3_4):
     gv_d, _ = O.dense_reference_gradient("mhm", p["rowptr"], p["col"], p["vals"], p["n"],
                                          p["b"], p["sigma"], g)
     assert _rel(fd, gv_d[nz]) < 1e-6
+
+
+def test_closed_form_matches_fd_fixture_8x4():
+    """The oracle's closed-form gradient at 8^4 against the stored central differences
+    (tests/golden/fd_c3_8x4.json, written by make_fd_golden.py from the oracle's FD)."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "fd_c3_8x4.json")
+    rec = json.load(open(path))
+    p = W.make_config("c3")
+    assert rec["nz"] == [int(e) for e in p["fd_nz"]]
+    ap = O.shifted_apply("mhm", p["rowptr"], p["col"], p["vals"], p["n"])
+    sol = O.cg_m(ap, p["b"], p["sigma"], tol=1e-14, max_iter=100000)
+    gv, _ = O.closed_form_gradient("mhm", p["rowptr"], p["col"], p["vals"], p["n"], sol["x"], p["c"])
+    fd = np.array(rec["grad_re"]) + 1j * np.array(rec["grad_im"])
+    got = gv[np.array(rec["nz"])]
+    comp_got = np.concatenate([got.real, got.imag])
+    comp_fd = np.concatenate([fd.real, fd.imag])
+    assert np.linalg.norm(comp_got - comp_fd) / np.linalg.norm(comp_fd) <= 1e-6
