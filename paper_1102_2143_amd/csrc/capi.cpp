@@ -10,7 +10,10 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <numeric>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -581,6 +584,402 @@ msc_status solve_impl(msc_op op, const double* d_b, double* d_x, const msc_param
   return result;
 }
 
+// ---- batched solves --------------------------------------------------------------------
+
+// Chosen lanes per row of a batch, keyed by (systems, total rows, total entries).
+struct TuneKey {
+  int64_t nsys, rows, nnz;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(nsys, rows, nnz) < std::tie(o.nsys, o.rows, o.nnz);
+  }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, int> g_tune_cache;
+
+struct BatchRun {
+  int nsys = 0, rr = 1, nchunks = 0, lanes = 8, grid = 8;
+  const msc_op* ops = nullptr;
+  const int32_t* nrhs = nullptr;
+  const double* const* d_b = nullptr;
+  double* const* d_x = nullptr;
+  std::vector<BatchSys> sys;
+  std::vector<int4> chunks;
+  std::vector<BatchState> hst;
+  void* pool = nullptr;
+  BatchSys* d_sys = nullptr;
+  int4* d_chunks = nullptr;
+  BatchState* d_st = nullptr;
+  unsigned* d_tickets = nullptr;
+  int* d_active = nullptr;
+  int* h_poll = nullptr;
+  hipStream_t sint = nullptr;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  hipEvent_t ev_sync = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  int replays = 0, n_reliable_launches = 0;
+
+  ~BatchRun() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (sint) (void)hipStreamSynchronize(sint);
+    for (auto e : ev)
+      if (e) (void)hipEventDestroy(e);
+    if (ev_sync) (void)hipEventDestroy(ev_sync);
+    if (sint) (void)hipStreamDestroy(sint);
+    if (h_poll) (void)hipHostFree(h_poll);
+    if (pool) (void)hipFree(pool);
+  }
+
+  msc_status setup(int nsys_, const msc_op* ops_, const int32_t* nrhs_, const double* const* b_,
+                   double* const* x_, int rr_, const msc_params& prm) {
+    nsys = nsys_;
+    ops = ops_;
+    nrhs = nrhs_;
+    d_b = b_;
+    d_x = x_;
+    rr = rr_;
+    // sizes of the pool
+    auto align = [](size_t v) { return (v + 255) / 256 * 256; };
+    size_t bytes = 0;
+    std::vector<size_t> off(nsys);
+    for (int s = 0; s < nsys; ++s) {
+      const size_t n = size_t(ops[s]->n), nk = std::max<size_t>(ops[s]->sigma.size() - 1, 1);
+      const size_t nch = (n + kBatchChunkRows - 1) / kBatchChunkRows;
+      off[s] = bytes;
+      bytes += 4 * align(sizeof(double2) * n * rr) + align(sizeof(double2) * n * rr * nk) +
+               3 * align(sizeof(float2) * n * rr) + align(sizeof(float2) * n * rr * nk) +
+               align(sizeof(double) * nch * kBatchMaxRhs);
+      for (size_t c = 0; c < nch; ++c) {
+        const int64_t r0 = int64_t(c) * kBatchChunkRows;
+        const int64_t r1 = std::min<int64_t>(r0 + kBatchChunkRows, int64_t(n));
+        chunks.push_back(int4{s, int(r0), int(r1), int(c)});
+      }
+    }
+    nchunks = int(chunks.size());
+    const size_t off_sys = bytes;
+    bytes += align(sizeof(BatchSys) * nsys);
+    const size_t off_ch = bytes;
+    bytes += align(sizeof(int4) * nchunks);
+    const size_t off_st = bytes;
+    bytes += align(sizeof(BatchState) * nsys);
+    const size_t off_tk = bytes;
+    bytes += align(sizeof(unsigned) * 8 * nsys);
+    const size_t off_act = bytes;
+    bytes += 256;
+    HIP_TRY(hipMalloc(&pool, bytes));
+    char* base = static_cast<char*>(pool);
+    d_sys = reinterpret_cast<BatchSys*>(base + off_sys);
+    d_chunks = reinterpret_cast<int4*>(base + off_ch);
+    d_st = reinterpret_cast<BatchState*>(base + off_st);
+    d_tickets = reinterpret_cast<unsigned*>(base + off_tk);
+    d_active = reinterpret_cast<int*>(base + off_act);
+    sys.resize(nsys);
+    hst.assign(nsys, BatchState{});
+    const double sw = prm.prec == MSC_PREC_MIXED ? std::max(prm.switch_tol, prm.tol) : 0.0;
+    for (int s = 0; s < nsys; ++s) {
+      const msc_op op = ops[s];
+      const size_t n = size_t(op->n), nk = std::max<size_t>(op->sigma.size() - 1, 1);
+      char* p = base + off[s];
+      auto take = [&](size_t b) {
+        char* q = p;
+        p += align(b);
+        return q;
+      };
+      BatchSys& S = sys[s];
+      S.kind = op->kind;
+      S.n = op->n;
+      S.nchunks = int((n + kBatchChunkRows - 1) / kBatchChunkRows);
+      S.m64 = Csr<double2>{op->rowptr, op->col, op->val64};
+      S.m32 = Csr<float2>{op->rowptr, op->col, op->val32};
+      if (op->kind == MSC_A_MHM) {
+        S.mh64 = Csr<double2>{op->rowptr_h, op->col_h, op->val64_h};
+        S.mh32 = Csr<float2>{op->rowptr_h, op->col_h, op->val32_h};
+      }
+      S.b = reinterpret_cast<const double2*>(d_b[s]);
+      S.x = reinterpret_cast<double2*>(d_x[s]);
+      S.r64 = reinterpret_cast<double2*>(take(sizeof(double2) * n * rr));
+      S.p64 = reinterpret_cast<double2*>(take(sizeof(double2) * n * rr));
+      S.t64 = reinterpret_cast<double2*>(take(sizeof(double2) * n * rr));
+      S.u64 = reinterpret_cast<double2*>(take(sizeof(double2) * n * rr));
+      S.pk64 = reinterpret_cast<double2*>(take(sizeof(double2) * n * rr * nk));
+      S.r32 = reinterpret_cast<float2*>(take(sizeof(float2) * n * rr));
+      S.p32 = reinterpret_cast<float2*>(take(sizeof(float2) * n * rr));
+      S.t32 = reinterpret_cast<float2*>(take(sizeof(float2) * n * rr));
+      S.pk32 = reinterpret_cast<float2*>(take(sizeof(float2) * n * rr * nk));
+      S.partial = reinterpret_cast<double*>(take(sizeof(double) * S.nchunks * kBatchMaxRhs));
+      S.tickets = d_tickets + 8 * s;
+      S.st = d_st + s;
+      // scalar state: shifts sorted ascending, the smallest drives
+      const int ns = int(op->sigma.size());
+      std::vector<int> order(ns);
+      std::iota(order.begin(), order.end(), 0);
+      std::stable_sort(order.begin(), order.end(),
+                       [&](int i, int j) { return op->sigma[i] < op->sigma[j]; });
+      BatchState& h = hst[s];
+      h.sigma0 = op->sigma[order[0]];
+      h.ns = ns;
+      h.nrhs = nrhs[s];
+      h.max_iter = prm.max_iter;
+      h.iters_fp64 = -1;
+      for (int k = 0; k < ns; ++k) {
+        h.s[k] = op->sigma[order[k]] - h.sigma0;
+        h.orig[k] = order[k];
+      }
+      for (int q = 0; q < kBatchMaxRhs; ++q) {
+        h.eps2[q] = prm.tol * prm.tol;
+        h.sw_eps2[q] = sw * sw;
+        h.a_prev[q] = 1.0;
+        h.b[q] = 0.0;
+        h.R[q] = 1.0;
+        for (int k = 0; k < kBatchMaxShifts; ++k) {
+          const int lk = q * kBatchMaxShifts + k;
+          h.zeta[lk] = h.zeta_prev[lk] = 1.0;
+          h.active[lk] = (q < nrhs[s] && k >= 1 && k < ns) ? 1 : 0;
+          h.freeze_iter[lk] = -1;
+        }
+      }
+    }
+    HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&h_poll), 4 * sizeof(int), hipHostMallocDefault));
+    HIP_TRY(hipStreamCreateWithFlags(&sint, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&ev_sync, hipEventDisableTiming));
+    return MSC_OK;
+  }
+
+  BatchArgs args() const {
+    BatchArgs a{};
+    a.sys = d_sys;
+    a.chunks = d_chunks;
+    a.nchunks = nchunks;
+    a.nsys = nsys;
+    a.grid = grid;
+    a.lanes = lanes;
+    a.rr = rr;
+    a.active_systems = d_active;
+    return a;
+  }
+
+  // upload the descriptors and the initial state, then r = p = p_k = b, x = 0
+  msc_status reset(hipStream_t s) {
+    HIP_TRY(hipMemcpyAsync(d_sys, sys.data(), sizeof(BatchSys) * nsys, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(d_chunks, chunks.data(), sizeof(int4) * nchunks, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(d_st, hst.data(), sizeof(BatchState) * nsys, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemsetAsync(d_tickets, 0, sizeof(unsigned) * 8 * nsys, s));
+    HIP_TRY(hipMemcpyAsync(d_active, &nsys, sizeof(int), hipMemcpyHostToDevice, s));
+    HIP_TRY(launch_batch_init(args(), s));
+    return MSC_OK;
+  }
+
+  // Lanes per row (rows per wavefront = 64 / lanes): measured on this batch when the
+  // caller leaves it open, over a few iterations of each candidate; cached per shape.
+  msc_status tune(const msc_params& prm) {
+    if (prm.lanes == 4 || prm.lanes == 8 || prm.lanes == 16) {
+      lanes = prm.lanes;
+      return MSC_OK;
+    }
+    TuneKey key{nsys, 0, 0};
+    for (int s = 0; s < nsys; ++s) {
+      key.rows += ops[s]->n;
+      key.nnz += ops[s]->nnz;
+    }
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      auto it = g_tune_cache.find(key);
+      if (it != g_tune_cache.end()) {
+        lanes = it->second;
+        return MSC_OK;
+      }
+    }
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    float best = 1e30f;
+    int best_l = 8;
+    for (int cand : {4, 8, 16}) {
+      lanes = cand;
+      msc_status rc = reset(sint);
+      if (rc != MSC_OK) return rc;
+      HIP_TRY(launch_batch_iteration(args(), sint));  // warm-up
+      HIP_TRY(hipEventRecord(e0, sint));
+      for (int i = 0; i < 4; ++i) HIP_TRY(launch_batch_iteration(args(), sint));
+      HIP_TRY(hipEventRecord(e1, sint));
+      HIP_TRY(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best) {
+        best = ms;
+        best_l = cand;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    lanes = best_l;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = lanes;
+    return MSC_OK;
+  }
+
+  msc_status solve(const msc_params& prm, hipStream_t user) {
+    grid = std::max(8, std::min(nchunks, kMaxGrid));
+    // order the internal stream after the caller's prior work
+    HIP_TRY(hipEventRecord(ev_sync, user));
+    HIP_TRY(hipStreamWaitEvent(sint, ev_sync, 0));
+    msc_status rc = tune(prm);
+    if (rc != MSC_OK) return rc;
+    rc = reset(sint);
+    if (rc != MSC_OK) return rc;
+    // G iterations captured once, replayed until every system has finished
+    const int G = std::max(1, prm.poll_every);
+    HIP_TRY(hipStreamBeginCapture(sint, hipStreamCaptureModeThreadLocal));
+    for (int g = 0; g < G; ++g) {
+      hipError_t e = launch_batch_iteration(args(), sint);
+      if (e != hipSuccess) {
+        hipGraph_t tmp = nullptr;
+        (void)hipStreamEndCapture(sint, &tmp);
+        if (tmp) (void)hipGraphDestroy(tmp);
+        set_error("batched iteration capture failed: %s", hipGetErrorString(e));
+        return MSC_EHIP;
+      }
+    }
+    HIP_TRY(hipStreamEndCapture(sint, &graph));
+    HIP_TRY(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+    const int ru_every = (prm.prec == MSC_PREC_MIXED && prm.reliable_every > 0)
+                             ? std::max(1, prm.reliable_every / G) : 0;
+    const int max_replays = (prm.max_iter + G - 1) / G + 4;
+    int chunk = 0;
+    bool done = false;
+    while (!done) {
+      HIP_TRY(hipGraphLaunch(gexec, sint));
+      ++replays;
+      if (ru_every > 0 && replays % ru_every == 0) {
+        HIP_TRY(launch_batch_reliable(args(), sint));
+        ++n_reliable_launches;
+      }
+      const int slot = chunk & 1;
+      HIP_TRY(hipMemcpyAsync(&h_poll[slot], d_active, sizeof(int), hipMemcpyDeviceToHost, sint));
+      HIP_TRY(hipEventRecord(ev[slot], sint));
+      ++chunk;
+      if (chunk >= 2) {
+        HIP_TRY(hipEventSynchronize(ev[slot ^ 1]));
+        if (h_poll[slot ^ 1] <= 0) done = true;
+      }
+      if (replays >= max_replays) done = true;
+    }
+    HIP_TRY(hipStreamSynchronize(sint));
+    HIP_TRY(hipMemcpy(hst.data(), d_st, sizeof(BatchState) * nsys, hipMemcpyDeviceToHost));
+    return MSC_OK;
+  }
+
+  msc_status finish(const msc_params& prm, msc_info* info, hipStream_t user,
+                    std::chrono::steady_clock::time_point t0) {
+    msc_status result = MSC_OK;
+    int t = 0;
+    for (int s = 0; s < nsys; ++s) {
+      const msc_op op = ops[s];
+      const int ns = int(op->sigma.size());
+      const int64_t n = op->n;
+      msc_status rc = ensure_scratch(op);
+      if (rc != MSC_OK) return rc;
+      rc = ensure_workspace(op, MSC_PREC_FP64, ns);
+      if (rc != MSC_OK) return rc;
+      const BatchState& h = hst[s];
+      for (int q = 0; q < nrhs[s]; ++q, ++t) {
+        const double* bq = d_b[s] + 2 * int64_t(q) * n;
+        double* xq = d_x[s] + 2 * int64_t(q) * ns * n;
+        std::vector<double> rel(ns, 0.0);
+        const double bn = std::sqrt(h.bnorm2[q]);
+        int refine_iters = 0, n_refined = 0;
+        bool bd = h.status[q] != 0;
+        if (!bd && prm.verify) {
+          MsArgs a = make_args(op, choose_lanes(op, prm), bq, xq);
+          for (int k0 = 0; k0 < ns; k0 += 8) {
+            HIP_TRY(launch_verify(a, op->sigma.data(), k0, std::min(8, ns - k0), op->ws.u64, sint));
+          }
+          std::vector<double> r2(ns);
+          HIP_TRY(hipMemcpyAsync(r2.data(), op->scratch.res2, sizeof(double) * ns, hipMemcpyDeviceToHost, sint));
+          HIP_TRY(hipStreamSynchronize(sint));
+          std::vector<int> todo;
+          for (int k = 0; k < ns; ++k) {
+            rel[k] = bn > 0 ? std::sqrt(r2[k]) / bn : 0.0;
+            if (!(rel[k] <= prm.tol)) todo.push_back(k);
+          }
+          if (prm.refine && !todo.empty() && bn > 0) {
+            n_refined = int(todo.size());
+            std::vector<double> sig(todo.size()), tol_abs(todo.size()), res;
+            std::vector<const double2*> f(todo.size());
+            std::vector<double2*> xs(todo.size());
+            for (size_t j = 0; j < todo.size(); ++j) {
+              sig[j] = op->sigma[todo[j]];
+              tol_abs[j] = prm.tol * bn;
+              f[j] = reinterpret_cast<const double2*>(bq);
+              xs[j] = reinterpret_cast<double2*>(xq) + int64_t(todo[j]) * n;
+            }
+            double bytes = 0.0;
+            bool b1 = false;
+            rc = run_batched_cg(op, MSC_PREC_FP64, int(todo.size()), sig.data(), f.data(), xs.data(),
+                                tol_abs.data(), 0.0, prm, sint, res, &refine_iters, &bytes, &b1);
+            if (rc != MSC_OK) return rc;
+            bd = bd || b1;
+            for (size_t j = 0; j < todo.size(); ++j) rel[todo[j]] = res[j] / bn;
+          }
+        }
+        if (bd) {
+          result = MSC_EBREAKDOWN;
+          set_error("msc_solve_batched: breakdown in system %d rhs %d", s, q);
+        } else if (prm.verify) {
+          for (int k = 0; k < ns; ++k)
+            if (!(rel[k] <= prm.tol) && result == MSC_OK) {
+              result = MSC_ENOTCONV;
+              set_error("msc_solve_batched: system %d rhs %d did not reach tol", s, q);
+            }
+        }
+        if (info) {
+          msc_info& I = info[t];
+          I.iters = h.iter[q];
+          I.refine_iters = refine_iters;
+          I.n_refined = n_refined;
+          I.n_reliable = h.n_reliable;
+          I.iters_fp64 = h.iters_fp64 >= 0 ? h.iters_fp64 : h.iter[q];
+          if (I.true_rel_res)
+            for (int k = 0; k < ns; ++k) I.true_rel_res[k] = rel[k];
+          if (I.freeze_iter)
+            for (int k = 0; k < ns; ++k) {
+              const int fi = h.freeze_iter[q * kBatchMaxShifts + k];
+              I.freeze_iter[h.orig[k]] = (k == 0 || fi < 0) ? h.iter[q] : fi;
+            }
+          for (double& v : I.kernel_ms) v = 0.0;
+          I.kernel_samples = 0;
+          // algorithmic bytes: this system's share, matrix read once for all its rhs
+          double act64 = 0.0, act32 = 0.0;
+          const int it = h.iter[q], i64 = std::min(I.iters_fp64, it);
+          for (int k = 1; k < ns; ++k) {
+            const int fi = h.freeze_iter[q * kBatchMaxShifts + k];
+            const int last = fi >= 0 ? fi : it;
+            act64 += std::min(last, i64);
+            act32 += std::max(0, last - i64);
+          }
+          const double nn = double(n), nz = double(op->nnz), nzh = double(op->nnz_h);
+          I.alg_bytes = (iter_bytes(op->kind, MSC_PREC_FP64, nn, nz, nzh, act64, i64) +
+                         iter_bytes(op->kind, MSC_PREC_MIXED, nn, nz, nzh, act32, it - i64)) /
+                            1.0 -
+                        (double(nrhs[s]) - 1.0) / double(nrhs[s]) *
+                            ((nz + nzh) * 20.0 * i64 + (nz + nzh) * 12.0 * (it - i64));
+          I.seconds = 0.0;
+        }
+      }
+    }
+    HIP_TRY(hipEventRecord(ev_sync, sint));
+    HIP_TRY(hipStreamWaitEvent(user, ev_sync, 0));
+    HIP_TRY(hipStreamSynchronize(sint));
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (info)
+      for (int i = 0; i < t; ++i) info[i].seconds = secs;
+    return result;
+  }
+};
+
 msc_status check_op(msc_op op) {
   if (!op) {
     set_error("null operator");
@@ -955,10 +1354,42 @@ msc_status msc_solve_adjoint(msc_op op, const double* d_g, const double* d_x, do
   return result;
 }
 
-msc_status msc_solve_batched(int32_t, const msc_op*, const int32_t*, const double* const*,
-                             double* const*, const msc_params*, msc_info*, msc_stream) {
-  set_error("msc_solve_batched: not available in this build");
-  return MSC_EINVAL;
+msc_status msc_solve_batched(int32_t nsys, const msc_op* ops, const int32_t* nrhs,
+                             const double* const* d_b, double* const* d_x,
+                             const msc_params* params, msc_info* info, msc_stream stream) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (nsys < 1 || !ops || !nrhs || !d_b || !d_x) {
+    set_error("msc_solve_batched: need nsys >= 1 and non-null host arrays");
+    return MSC_EINVAL;
+  }
+  msc_params prm;
+  if (params)
+    prm = *params;
+  else
+    msc_params_default(&prm);
+  if (!(prm.tol >= 0.0) || (prm.prec != MSC_PREC_FP64 && prm.prec != MSC_PREC_MIXED)) {
+    set_error("msc_solve_batched: invalid tol or precision");
+    return MSC_EINVAL;
+  }
+  int rr = 1, max_nrhs = 0;
+  for (int s = 0; s < nsys; ++s) {
+    const msc_op op = ops[s];
+    if (!op || op->sigma.empty() || int(op->sigma.size()) > kBatchMaxShifts || nrhs[s] < 1 ||
+        nrhs[s] > kBatchMaxRhs || !d_b[s] || !d_x[s]) {
+      set_error("msc_solve_batched: system %d: need an operator with 1..%d shifts, 1..%d "
+                "right-hand sides and non-null b and x", s, kBatchMaxShifts, kBatchMaxRhs);
+      return MSC_EINVAL;
+    }
+    max_nrhs = std::max(max_nrhs, int(nrhs[s]));
+  }
+  while (rr < max_nrhs) rr *= 2;
+  hipStream_t user = static_cast<hipStream_t>(stream);
+  BatchRun run;
+  msc_status rc = run.setup(nsys, ops, nrhs, d_b, d_x, rr, prm);
+  if (rc != MSC_OK) return rc;
+  rc = run.solve(prm, user);
+  if (rc != MSC_OK) return rc;
+  return run.finish(prm, info, user, t0);
 }
 
 void msc_op_destroy(msc_op op) {

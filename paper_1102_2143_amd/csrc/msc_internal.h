@@ -229,6 +229,59 @@ struct ResArgs {
   double* out;
 };
 
+// batched_ms.hip -- many independent multishift solves per launch
+constexpr int kBatchMaxRhs = 4;
+constexpr int kBatchMaxShifts = 16;
+constexpr int kBatchChunkRows = 256;
+
+struct BatchState {
+  // per right-hand side q
+  double R[kBatchMaxRhs], a[kBatchMaxRhs], a_prev[kBatchMaxRhs], b[kBatchMaxRhs];
+  double b_new[kBatchMaxRhs], bnorm2[kBatchMaxRhs], eps2[kBatchMaxRhs], sw_eps2[kBatchMaxRhs];
+  int iter[kBatchMaxRhs], halt[kBatchMaxRhs], status[kBatchMaxRhs], x0_upd[kBatchMaxRhs];
+  // per (q, sorted shift k), index q * 16 + k
+  double zeta[kBatchMaxRhs * kBatchMaxShifts], zeta_prev[kBatchMaxRhs * kBatchMaxShifts];
+  double zk[kBatchMaxRhs * kBatchMaxShifts], ak[kBatchMaxRhs * kBatchMaxShifts];
+  double bk[kBatchMaxRhs * kBatchMaxShifts];
+  int active[kBatchMaxRhs * kBatchMaxShifts], freeze_iter[kBatchMaxRhs * kBatchMaxShifts];
+  int upd_p[kBatchMaxRhs * kBatchMaxShifts], upd_x[kBatchMaxRhs * kBatchMaxShifts];
+  // per system
+  double s[kBatchMaxShifts];
+  int orig[kBatchMaxShifts];
+  double sigma0;
+  int ns, nrhs, phase32, switch_pending, done, k3_enable, max_iter, n_reliable, iters_fp64, pad_;
+};
+
+struct BatchSys {
+  int kind;
+  int nchunks;            // chunks of this system (its partial array has 4 slots each)
+  int64_t n;
+  Csr<double2> m64, mh64;
+  Csr<float2> m32, mh32;
+  const double2* b;       // nrhs * n (rhs-major)
+  double2* x;             // nrhs * ns * n (rhs-major, shift-major, caller order)
+  double2 *r64, *p64, *t64, *pk64, *u64;   // rhs-interleaved n x RR; pk: (ns-1) blocks
+  float2 *r32, *p32, *t32, *pk32;
+  BatchState* st;
+  double* partial;
+  unsigned* tickets;      // 8 counters
+};
+
+struct BatchArgs {
+  const BatchSys* sys;
+  const int4* chunks;     // (system, row0, row1, chunk index within the system)
+  int nchunks;
+  int nsys;
+  int grid;
+  int lanes;
+  int rr;                 // right-hand sides per system, padded (1, 2 or 4)
+  int* active_systems;
+};
+
+hipError_t launch_batch_init(const BatchArgs& a, hipStream_t s);
+hipError_t launch_batch_iteration(const BatchArgs& a, hipStream_t s);
+hipError_t launch_batch_reliable(const BatchArgs& a, hipStream_t s);
+
 // grad.hip
 // out[3q..3q+2] = Re<gref, g_q>, Im<gref, g_q>, |g_q|^2 for q < kc (<= 16); g shift-major.
 hipError_t launch_gram(const double2* gref, const double2* g, int64_t n, int kc, double* partial,
