@@ -79,6 +79,9 @@ def main():
     ap.add_argument("--timing", type=int, default=4, help="sample every k-th iteration's kernels")
     ap.add_argument("--cpu-sample-iters", type=int, default=60)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="copy this many MiB once before timing (a kernel of known traffic "
+                         "that calibrates FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -106,6 +109,13 @@ def main():
     setup_s = time.perf_counter() - t0
     b = torch.from_numpy(prob["b"]).to(dev)
     x = torch.empty((prob["sigma"].size, prob["n"]), dtype=torch.complex128, device=dev)
+    if args.copy_probe_mb > 0:
+        src = torch.ones(args.copy_probe_mb << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy probe: {args.copy_probe_mb} MiB read + {args.copy_probe_mb} MiB written")
+        del src, dst
 
     def run_path(prec):
         kw = dict(tol=prob["tol"], prec=prec, timing=args.timing)

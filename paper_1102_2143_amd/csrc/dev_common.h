@@ -112,7 +112,7 @@ __device__ __forceinline__ double load_agent(const double* p) {
 // in every workgroup, evicting the gathered vectors the SpMV relies on.  Thread 0 waits
 // for its partial stores to complete before taking a ticket, so a workgroup that draws
 // the last ticket finds every partial in memory.
-__device__ __forceinline__ bool arrive_last(unsigned* ticket) {
+__device__ __forceinline__ bool arrive_last(unsigned* ticket, unsigned arrivals) {
   __shared__ int last;
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -120,7 +120,7 @@ __device__ __forceinline__ bool arrive_last(unsigned* ticket) {
     __builtin_amdgcn_s_waitcnt(0);  // vmcnt = expcnt = lgkmcnt = 0: partial stores done
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
     const unsigned t = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    last = (t == gridDim.x - 1);
+    last = (t == arrivals - 1);
     if (last) __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   __syncthreads();

@@ -235,7 +235,7 @@ __global__ __launch_bounds__(kBlock) void k1_apply(MsArgs a) {
   }
   const double tot = block_sum<kBlock>(acc);
   if (threadIdx.x == 0) store_agent(&a.sc.partial[blockIdx.x], tot);
-  if (!arrive_last(&a.sc.tickets[0])) return;
+  if (!arrive_last(&a.sc.tickets[0], gridDim.x)) return;
   __shared__ double Psh;
   const K1Pre pre = prefetch_k1(st);
   const double P = sum_partials(a.sc.partial, gridDim.x, 1, 0);
@@ -276,7 +276,7 @@ __global__ __launch_bounds__(kBlock) void k2_mhm(MsArgs a) {
   }
   const double tot = block_sum<kBlock>(acc);
   if (threadIdx.x == 0) store_agent(&a.sc.partial[blockIdx.x], tot);
-  if (!arrive_last(&a.sc.tickets[1])) return;
+  if (!arrive_last(&a.sc.tickets[1], gridDim.x)) return;
   __shared__ double Rsh;
   const K2Pre pre = prefetch_k2(st);
   const double Rn = sum_partials(a.sc.partial, gridDim.x, 1, 0);
@@ -309,7 +309,7 @@ __global__ __launch_bounds__(kBlock) void k2_herm(MsArgs a) {
   }
   const double tot = block_sum<kBlock>(acc);
   if (threadIdx.x == 0) store_agent(&a.sc.partial[blockIdx.x], tot);
-  if (!arrive_last(&a.sc.tickets[1])) return;
+  if (!arrive_last(&a.sc.tickets[1], gridDim.x)) return;
   __shared__ double Rsh;
   const K2Pre pre = prefetch_k2(st);
   const double Rn = sum_partials(a.sc.partial, gridDim.x, 1, 0);
@@ -416,7 +416,7 @@ __global__ __launch_bounds__(kBlock) void k_init(MsArgs a) {
   }
   const double tot = block_sum<kBlock>(acc);
   if (threadIdx.x == 0) store_agent(&a.sc.partial[blockIdx.x], tot);
-  if (!arrive_last(&a.sc.tickets[3])) return;
+  if (!arrive_last(&a.sc.tickets[3], gridDim.x)) return;
   const double B2 = sum_partials(a.sc.partial, gridDim.x, 1, 0);
   if (threadIdx.x == 0) {
     st->bnorm2 = B2;
@@ -504,7 +504,7 @@ __global__ __launch_bounds__(kBlock) void k_ru_second(MsArgs a) {
   }
   const double tot = block_sum<kBlock>(acc);
   if (threadIdx.x == 0) store_agent(&a.sc.partial[blockIdx.x], tot);
-  if (!arrive_last(&a.sc.tickets[2])) return;
+  if (!arrive_last(&a.sc.tickets[2], gridDim.x)) return;
   const double Rt = sum_partials(a.sc.partial, gridDim.x, 1, 0);
   if (threadIdx.x == 0) {
     st->R = Rt;
@@ -602,7 +602,7 @@ __global__ __launch_bounds__(kBlock) void k_verify_second(VerifyArgs v) {
 #pragma unroll
     for (int q = 0; q < kVerifyChunk; ++q) store_agent(&v.partial[blockIdx.x * kVerifyChunk + q], nrm[q]);
   }
-  if (!arrive_last(v.ticket)) return;
+  if (!arrive_last(v.ticket, gridDim.x)) return;
   for (int q = 0; q < v.kc; ++q) {
     const double s = sum_partials(v.partial, gridDim.x, kVerifyChunk, q);
     if (threadIdx.x == 0) v.out[q] = s;
