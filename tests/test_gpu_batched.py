@@ -53,7 +53,10 @@ def test_small_batch_matches_oracle(cuda, prec):
             t += 1
             assert np.all(info["true_rel_res"] <= 1e-10), (s, q, info["true_rel_res"])
             assert np.all(_rel(xg, ref["x"]) <= 1e-8), (s, q)
-            assert abs(info["iters"] - ref["iters"]) <= 2, (s, q, info["iters"], ref["iters"])
+            # FP64: the oracle's Krylov path to +-2; mixed: the complex64 phase costs a few
+            # extra iterations (bounded at 3%)
+            bar = 2 if prec == "fp64" else max(2, int(0.03 * ref["iters"]))
+            assert abs(info["iters"] - ref["iters"]) <= bar, (s, q, info["iters"], ref["iters"])
             rho = np.array([np.linalg.norm(bs[q] - ap(xg[k], sk)) for k, sk in enumerate(p["sigma"])])
             assert np.all(rho / np.linalg.norm(bs[q]) <= 1e-10)
     for op in ops:
