@@ -95,7 +95,7 @@ __global__ __launch_bounds__(kBlock) void ik1(BssArgs a) {
       acc += double(pr.x) * double(sum.x) + double(pr.y) * double(sum.y) + sig * norm2d<R>(pr);
   }
   store_system_partials<MP>(acc, a.partial);
-  if (!arrive_last(&a.tickets[8], gridDim.x)) return;
+  if (!arrive_last(a.tickets + 8 * kTicketSite)) return;
   __shared__ double tot[kBssMax];
   sum_system_partials(a.partial, gridDim.x, tot);
   const int q = threadIdx.x;
@@ -158,7 +158,7 @@ __global__ __launch_bounds__(kBlock) void ik2(BssArgs a) {
     acc += norm2d<R>(sr);
   }
   store_system_partials<MP>(acc, a.partial);
-  if (!arrive_last(&a.tickets[9], gridDim.x)) return;
+  if (!arrive_last(a.tickets + 9 * kTicketSite)) return;
   __shared__ double tot[kBssMax];
   sum_system_partials(a.partial, gridDim.x, tot);
   if (threadIdx.x < kWave) {
@@ -296,7 +296,7 @@ __global__ __launch_bounds__(kBlock) void k_res_second(ResArgs v) {
 #pragma unroll
     for (int q = 0; q < kResChunk; ++q) store_agent(&v.partial[blockIdx.x * kResChunk + q], nrm[q]);
   }
-  if (!arrive_last(v.ticket, gridDim.x)) return;
+  if (!arrive_last(v.ticket)) return;
   for (int q = 0; q < v.kc; ++q) {
     double s = 0.0;
     for (int i = threadIdx.x; i < int(gridDim.x); i += kBlock) s += load_agent(&v.partial[i * kResChunk + q]);

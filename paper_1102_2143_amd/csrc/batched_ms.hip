@@ -77,7 +77,7 @@ __device__ __forceinline__ bool chunk_reduce(double (&v)[kBatchMaxRhs], const Ba
 #pragma unroll
     for (int q = 0; q < kBatchMaxRhs; ++q) store_agent(&S.partial[cidx * kBatchMaxRhs + q], v[q]);
   }
-  if (!arrive_last(&S.tickets[ticket], unsigned(S.nchunks))) return false;
+  if (!arrive_last(S.tickets + ticket * kTicketSite, unsigned(S.nchunks), unsigned(cidx))) return false;
   // thread -> (rhs q = tid / 64, sub-lane) : all loads of a rhs in flight together
   const int q = threadIdx.x / kWave, s = threadIdx.x % kWave;
   double acc = 0.0;

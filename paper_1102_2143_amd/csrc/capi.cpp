@@ -71,9 +71,9 @@ msc_status ensure_scratch(msc_op op) {
   Scratch& sc = op->scratch;
   if (sc.partial) return MSC_OK;
   HIP_TRY(dalloc(&sc.partial, size_t(kMaxGrid) * kMaxShifts));
-  HIP_TRY(dalloc(&sc.tickets, 16));
+  HIP_TRY(dalloc(&sc.tickets, 16 * kTicketSite));
   HIP_TRY(dalloc(&sc.res2, kMaxShifts));
-  HIP_TRY(hipMemset(sc.tickets, 0, sizeof(unsigned) * 16));
+  HIP_TRY(hipMemset(sc.tickets, 0, sizeof(unsigned) * 16 * kTicketSite));
   return MSC_OK;
 }
 
@@ -124,7 +124,9 @@ MsArgs make_args(msc_op op, int lanes, const double* d_b, double* d_x) {
   a.kind = op->kind;
   a.n = op->n;
   a.lanes = lanes;
-  a.grid = kMaxGrid;  // cap on workgroups per iteration kernel (overridden by max_grid)
+  // cap on workgroups per iteration kernel (overridden by max_grid): 1024 measured best
+  // at 16^4 (fewer final reductions than 2048, enough rows in flight)
+  a.grid = 1024;
   a.m64 = Csr<double2>{op->rowptr, op->col, op->val64};
   a.m32 = Csr<float2>{op->rowptr, op->col, op->val32};
   if (op->kind == MSC_A_MHM) {
@@ -397,7 +399,7 @@ msc_status batch_residual(msc_op op, int prec, int lanes, int m, int mp, const d
       v.e = op->bws.e;
     }
     v.partial = op->scratch.partial;
-    v.ticket = &op->scratch.tickets[10];
+    v.ticket = op->scratch.tickets + 10 * kTicketSite;
     v.out = op->scratch.res2 + q0;
     HIP_TRY(launch_residual(prec, lanes, v, s));
     *bytes += (v.mhm ? 2.0 : 1.0) * (double(op->nnz) * 20.0 + 4.0 * (op->n + 1)) +
@@ -664,7 +666,7 @@ struct BatchRun {
     const size_t off_st = bytes;
     bytes += align(sizeof(BatchState) * nsys);
     const size_t off_tk = bytes;
-    bytes += align(sizeof(unsigned) * 8 * nsys);
+    bytes += align(sizeof(unsigned) * 4 * kTicketSite * nsys);
     const size_t off_act = bytes;
     bytes += 256;
     HIP_TRY(hipMalloc(&pool, bytes));
@@ -708,7 +710,7 @@ struct BatchRun {
       S.t32 = reinterpret_cast<float2*>(take(sizeof(float2) * n * rr));
       S.pk32 = reinterpret_cast<float2*>(take(sizeof(float2) * n * rr * nk));
       S.partial = reinterpret_cast<double*>(take(sizeof(double) * S.nchunks * kBatchMaxRhs));
-      S.tickets = d_tickets + 8 * s;
+      S.tickets = d_tickets + 4 * kTicketSite * s;
       S.st = d_st + s;
       // scalar state: shifts sorted ascending, the smallest drives
       const int ns = int(op->sigma.size());
@@ -766,7 +768,7 @@ struct BatchRun {
     HIP_TRY(hipMemcpyAsync(d_sys, sys.data(), sizeof(BatchSys) * nsys, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(d_chunks, chunks.data(), sizeof(int4) * nchunks, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(d_st, hst.data(), sizeof(BatchState) * nsys, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemsetAsync(d_tickets, 0, sizeof(unsigned) * 8 * nsys, s));
+    HIP_TRY(hipMemsetAsync(d_tickets, 0, sizeof(unsigned) * 4 * kTicketSite * nsys, s));
     HIP_TRY(hipMemcpyAsync(d_active, &nsys, sizeof(int), hipMemcpyHostToDevice, s));
     HIP_TRY(launch_batch_init(args(), s));
     return MSC_OK;
@@ -1240,7 +1242,7 @@ msc_status msc_solve_adjoint(msc_op op, const double* d_g, const double* d_x, do
   std::vector<double> gram(3 * ns), gn2(ns);
   for (int q0 = 0; q0 < ns; q0 += 16) {
     const int kc = std::min(16, ns - q0);
-    HIP_TRY(launch_gram(g, g + int64_t(q0) * n, n, kc, op->scratch.partial, &op->scratch.tickets[11],
+    HIP_TRY(launch_gram(g, g + int64_t(q0) * n, n, kc, op->scratch.partial, op->scratch.tickets + 11 * kTicketSite,
                         op->adj_small + 3 * q0, s));
   }
   HIP_TRY(hipMemcpyAsync(gram.data(), op->adj_small, sizeof(double) * 3 * ns, hipMemcpyDeviceToHost, s));
@@ -1254,7 +1256,7 @@ msc_status msc_solve_adjoint(msc_op op, const double* d_g, const double* d_x, do
     for (int q0 = 0; q0 < ns; q0 += 16) {
       const int kc = std::min(16, ns - q0);
       HIP_TRY(launch_gram(gref, g + int64_t(q0) * n, n, kc, op->scratch.partial,
-                          &op->scratch.tickets[11], op->adj_small + 3 * q0, s));
+                          op->scratch.tickets + 11 * kTicketSite, op->adj_small + 3 * q0, s));
     }
     HIP_TRY(hipMemcpyAsync(gram.data(), op->adj_small, sizeof(double) * 3 * ns, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
@@ -1264,7 +1266,7 @@ msc_status msc_solve_adjoint(msc_op op, const double* d_g, const double* d_x, do
     for (int q0 = 0; q0 < ns; q0 += 16) {
       const int kc = std::min(16, ns - q0);
       HIP_TRY(launch_diffnorm(gref, g + int64_t(q0) * n, op->adj_small + 192 + q0, n, kc,
-                              op->scratch.partial, &op->scratch.tickets[11], op->adj_small + q0, s));
+                              op->scratch.partial, op->scratch.tickets + 11 * kTicketSite, op->adj_small + q0, s));
     }
     HIP_TRY(hipMemcpyAsync(dn.data(), op->adj_small, sizeof(double) * ns, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));

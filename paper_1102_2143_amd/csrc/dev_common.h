@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "msc_internal.h"
+
 namespace msc {
 
 constexpr int kWave = 64;   // CDNA wavefront width
@@ -112,19 +114,43 @@ __device__ __forceinline__ double load_agent(const double* p) {
 // in every workgroup, evicting the gathered vectors the SpMV relies on.  Thread 0 waits
 // for its partial stores to complete before taking a ticket, so a workgroup that draws
 // the last ticket finds every partial in memory.
-__device__ __forceinline__ bool arrive_last(unsigned* ticket, unsigned arrivals) {
+//
+// Arrivals on one counter serialise at the memory side, so the ticket is two-level:
+// arrival `idx` (0 <= idx < arrivals) first takes a ticket in group idx % 8 (eight
+// counters on separate 128-byte lines), and only the last arrival of each group takes
+// the final ticket.  A ticket site is kTicketSite unsigned words (msc_internal.h).
+
+__device__ __forceinline__ bool arrive_last(unsigned* site, unsigned arrivals, unsigned idx) {
   __shared__ int last;
   __syncthreads();
   if (threadIdx.x == 0) {
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
     __builtin_amdgcn_s_waitcnt(0);  // vmcnt = expcnt = lgkmcnt = 0: partial stores done
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
-    const unsigned t = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    last = (t == arrivals - 1);
-    if (last) __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned g = idx & 7u;
+    const unsigned in_group = (arrivals - g + 7u) / 8u;  // arrivals whose index is g mod 8
+    const unsigned groups = arrivals < 8u ? arrivals : 8u;
+    unsigned* gc = site + g * kTicketStride;
+    const unsigned t = __hip_atomic_fetch_add(gc, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int is_last = 0;
+    if (t == in_group - 1) {
+      __hip_atomic_store(gc, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      unsigned* fc = site + 8 * kTicketStride;
+      const unsigned f = __hip_atomic_fetch_add(fc, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (f == groups - 1) {
+        __hip_atomic_store(fc, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        is_last = 1;
+      }
+    }
+    last = is_last;
   }
   __syncthreads();
   return last != 0;
+}
+
+// Grid-wide form: every workgroup of the launch arrives once.
+__device__ __forceinline__ bool arrive_last(unsigned* site) {
+  return arrive_last(site, gridDim.x, blockIdx.x);
 }
 
 // Workgroups are dispatched round-robin over the XCDs.  Renumber them so that the

@@ -40,7 +40,7 @@ __global__ __launch_bounds__(kBlock) void k_gram(const double2* gref, const doub
   if (threadIdx.x == 0) {
     for (int q = 0; q < 3 * kc; ++q) store_agent(&partial[blockIdx.x * 3 * kGramMax + q], acc[q]);
   }
-  if (!arrive_last(ticket, gridDim.x)) return;
+  if (!arrive_last(ticket)) return;
   for (int q = 0; q < 3 * kc; ++q) {
     double s = 0.0;
     for (int b = threadIdx.x; b < int(gridDim.x); b += kBlock) s += load_agent(&partial[b * 3 * kGramMax + q]);
@@ -73,7 +73,7 @@ __global__ __launch_bounds__(kBlock) void k_diffnorm(const double2* gref, const 
   if (threadIdx.x == 0) {
     for (int q = 0; q < kc; ++q) store_agent(&partial[blockIdx.x * kGramMax + q], acc[q]);
   }
-  if (!arrive_last(ticket, gridDim.x)) return;
+  if (!arrive_last(ticket)) return;
   for (int q = 0; q < kc; ++q) {
     double s = 0.0;
     for (int b = threadIdx.x; b < int(gridDim.x); b += kBlock) s += load_agent(&partial[b * kGramMax + q]);

@@ -14,6 +14,9 @@ namespace msc {
 constexpr int kMaxShifts = 64;
 constexpr int kBlock = 256;          // threads per workgroup for every solver kernel
 constexpr int kMaxGrid = 2048;       // 256 CUs x 8 resident workgroups
+// A "last workgroup" ticket site: eight group counters 128 bytes apart and a final one.
+constexpr int kTicketStride = 32;
+constexpr int kTicketSite = 9 * kTicketStride;
 
 // Scalar state of one multishift solve, resident in device memory.  Written only by
 // the last-arriving workgroup of a kernel (or by the init kernel), read by the next

@@ -58,6 +58,43 @@ __device__ __forceinline__ cplx<R> row_dot(const Csr<cplx<R>>& m, const cplx<R>*
   return group_sum_c<L, R>(acc);
 }
 
+// Two rows per row group at a time: both rows' loads share one round trip.  An empty
+// second row (beg1 == end1) contributes zero.
+template <class R, int L>
+__device__ __forceinline__ void row_dot2(const Csr<cplx<R>>& m, const cplx<R>* __restrict__ x,
+                                         int64_t row0, int64_t row1, bool has1, int lane,
+                                         cplx<R>& out0, cplx<R>& out1) {
+  const int32_t b0 = m.rowptr[row0], e0 = m.rowptr[row0 + 1];
+  const int32_t b1 = has1 ? m.rowptr[row1] : 0, e1 = has1 ? m.rowptr[row1 + 1] : 0;
+  const int32_t len = (e0 - b0) > (e1 - b1) ? (e0 - b0) : (e1 - b1);
+  cplx<R> a0 = czero<R>(), a1 = czero<R>();
+  for (int32_t base = 0; base < len; base += kChunk * L) {
+    int32_t c0[kChunk], c1[kChunk];
+    cplx<R> v0[kChunk], v1[kChunk], x0[kChunk], x1[kChunk];
+#pragma unroll
+    for (int u = 0; u < kChunk; ++u) {
+      const int32_t j0 = b0 + base + lane + u * L, j1 = b1 + base + lane + u * L;
+      const bool ok0 = j0 < e0, ok1 = j1 < e1;
+      c0[u] = ok0 ? m.col[j0] : 0;
+      v0[u] = ok0 ? m.val[j0] : czero<R>();
+      c1[u] = ok1 ? m.col[j1] : 0;
+      v1[u] = ok1 ? m.val[j1] : czero<R>();
+    }
+#pragma unroll
+    for (int u = 0; u < kChunk; ++u) {
+      x0[u] = x[c0[u]];
+      x1[u] = x[c1[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < kChunk; ++u) {
+      cfma<R>(a0, v0[u], x0[u]);
+      cfma<R>(a1, v1[u], x1[u]);
+    }
+  }
+  out0 = group_sum_c<L, R>(a0);
+  out1 = group_sum_c<L, R>(a1);
+}
+
 // The last workgroup sums `count` (<= kMaxGrid) partials (stride `stride`, offset `k`)
 // in a fixed order; all loads are in flight together.  The result is valid in thread 0.
 __device__ __forceinline__ double sum_partials(const double* partial, int count, int stride, int k) {
@@ -221,21 +258,27 @@ __global__ __launch_bounds__(kBlock) void k1_apply(MsArgs a) {
   int64_t beg, end;
   block_range(a.n, GPB, beg, end);
   double acc = 0.0;
-  for (int64_t row = beg + grp; row < end; row += GPB) {
-    const cplx<R> v = row_dot<R, L>(m, p, row, lane);
+  auto epilogue = [&](int64_t row, const cplx<R>& v) {
+    t[row] = v;
+    const cplx<R> pr = p[row];
+    if (MHM)
+      acc += norm2d<R>(v) + sigma0 * norm2d<R>(pr);
+    else
+      acc += double(pr.x) * double(v.x) + double(pr.y) * double(v.y) + sigma0 * norm2d<R>(pr);
+  };
+  for (int64_t row = beg + grp; row < end; row += 2 * GPB) {
+    const int64_t row1 = row + GPB;
+    const bool has1 = row1 < end;
+    cplx<R> v0, v1;
+    row_dot2<R, L>(m, p, row, row1, has1, lane, v0, v1);
     if (lane == 0) {
-      t[row] = v;
-      const cplx<R> pr = p[row];
-      if (MHM) {
-        acc += norm2d<R>(v) + sigma0 * norm2d<R>(pr);
-      } else {
-        acc += double(pr.x) * double(v.x) + double(pr.y) * double(v.y) + sigma0 * norm2d<R>(pr);
-      }
+      epilogue(row, v0);
+      if (has1) epilogue(row1, v1);
     }
   }
   const double tot = block_sum<kBlock>(acc);
   if (threadIdx.x == 0) store_agent(&a.sc.partial[blockIdx.x], tot);
-  if (!arrive_last(&a.sc.tickets[0], gridDim.x)) return;
+  if (!arrive_last(a.sc.tickets + 0 * kTicketSite)) return;
   __shared__ double Psh;
   const K1Pre pre = prefetch_k1(st);
   const double P = sum_partials(a.sc.partial, gridDim.x, 1, 0);
@@ -260,23 +303,30 @@ __global__ __launch_bounds__(kBlock) void k2_mhm(MsArgs a) {
   int64_t beg, end;
   block_range(a.n, GPB, beg, end);
   double acc = 0.0;
-  for (int64_t row = beg + grp; row < end; row += GPB) {
-    const cplx<R> q = row_dot<R, L>(mh, t, row, lane);
+  auto epilogue = [&](int64_t row, const cplx<R>& q) {
+    const double2 pr = to_d(p[row]);
+    const double2 rr = to_d(r[row]);
+    const double2 qd = to_d(q);
+    double2 nr;
+    nr.x = rr.x - step * (qd.x + sigma0 * pr.x);
+    nr.y = rr.y - step * (qd.y + sigma0 * pr.y);
+    const cplx<R> st_r = from_d<R>(nr);
+    r[row] = st_r;
+    acc += norm2d<R>(st_r);
+  };
+  for (int64_t row = beg + grp; row < end; row += 2 * GPB) {
+    const int64_t row1 = row + GPB;
+    const bool has1 = row1 < end;
+    cplx<R> q0, q1;
+    row_dot2<R, L>(mh, t, row, row1, has1, lane, q0, q1);
     if (lane == 0) {
-      const double2 pr = to_d(p[row]);
-      const double2 rr = to_d(r[row]);
-      const double2 qd = to_d(q);
-      double2 nr;
-      nr.x = rr.x - step * (qd.x + sigma0 * pr.x);
-      nr.y = rr.y - step * (qd.y + sigma0 * pr.y);
-      const cplx<R> st_r = from_d<R>(nr);
-      r[row] = st_r;
-      acc += norm2d<R>(st_r);
+      epilogue(row, q0);
+      if (has1) epilogue(row1, q1);
     }
   }
   const double tot = block_sum<kBlock>(acc);
   if (threadIdx.x == 0) store_agent(&a.sc.partial[blockIdx.x], tot);
-  if (!arrive_last(&a.sc.tickets[1], gridDim.x)) return;
+  if (!arrive_last(a.sc.tickets + 1 * kTicketSite)) return;
   __shared__ double Rsh;
   const K2Pre pre = prefetch_k2(st);
   const double Rn = sum_partials(a.sc.partial, gridDim.x, 1, 0);
@@ -309,7 +359,7 @@ __global__ __launch_bounds__(kBlock) void k2_herm(MsArgs a) {
   }
   const double tot = block_sum<kBlock>(acc);
   if (threadIdx.x == 0) store_agent(&a.sc.partial[blockIdx.x], tot);
-  if (!arrive_last(&a.sc.tickets[1], gridDim.x)) return;
+  if (!arrive_last(a.sc.tickets + 1 * kTicketSite)) return;
   __shared__ double Rsh;
   const K2Pre pre = prefetch_k2(st);
   const double Rn = sum_partials(a.sc.partial, gridDim.x, 1, 0);
@@ -416,7 +466,7 @@ __global__ __launch_bounds__(kBlock) void k_init(MsArgs a) {
   }
   const double tot = block_sum<kBlock>(acc);
   if (threadIdx.x == 0) store_agent(&a.sc.partial[blockIdx.x], tot);
-  if (!arrive_last(&a.sc.tickets[3], gridDim.x)) return;
+  if (!arrive_last(a.sc.tickets + 3 * kTicketSite)) return;
   const double B2 = sum_partials(a.sc.partial, gridDim.x, 1, 0);
   if (threadIdx.x == 0) {
     st->bnorm2 = B2;
@@ -504,7 +554,7 @@ __global__ __launch_bounds__(kBlock) void k_ru_second(MsArgs a) {
   }
   const double tot = block_sum<kBlock>(acc);
   if (threadIdx.x == 0) store_agent(&a.sc.partial[blockIdx.x], tot);
-  if (!arrive_last(&a.sc.tickets[2], gridDim.x)) return;
+  if (!arrive_last(a.sc.tickets + 2 * kTicketSite)) return;
   const double Rt = sum_partials(a.sc.partial, gridDim.x, 1, 0);
   if (threadIdx.x == 0) {
     st->R = Rt;
@@ -602,7 +652,7 @@ __global__ __launch_bounds__(kBlock) void k_verify_second(VerifyArgs v) {
 #pragma unroll
     for (int q = 0; q < kVerifyChunk; ++q) store_agent(&v.partial[blockIdx.x * kVerifyChunk + q], nrm[q]);
   }
-  if (!arrive_last(v.ticket, gridDim.x)) return;
+  if (!arrive_last(v.ticket)) return;
   for (int q = 0; q < v.kc; ++q) {
     const double s = sum_partials(v.partial, gridDim.x, kVerifyChunk, q);
     if (threadIdx.x == 0) v.out[q] = s;
@@ -732,7 +782,7 @@ hipError_t launch_verify(const MsArgs& a, const double* sigma_by_caller_index, i
   v.n = a.n;
   v.kc = kc;
   v.partial = a.sc.partial;
-  v.ticket = &a.sc.tickets[4];
+  v.ticket = a.sc.tickets + 4 * kTicketSite;
   v.out = a.sc.res2 + k0;
   if (a.kind == MSC_A_MHM) {
     MSC_LANES_SWITCH(a.lanes, (k_verify_first<LL><<<g1, kBlock, 0, s>>>(a.m64, xc, a.n, kc, u64)));
