@@ -85,7 +85,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(the solve would shard by lattice rows with a halo exchange; see DESIGN.md)",
+              "(the solve would shard by lattice rows with a halo exchange)",
               file=sys.stderr)
         sys.exit(2)
 

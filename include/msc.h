@@ -55,6 +55,16 @@ typedef enum {
                               reliable updates and per-shift FP64 refinement          */
 } msc_prec;
 
+/* Matrix storage read by the SpMVs of the multishift iteration.  At creation the
+ * library also builds a sliced ELLPACK copy (64-row slices, one row per lane, diagonal
+ * held apart) when its padding stays below half the entry count; AUTO uses it when it
+ * exists, SELL requires it (MSC_EINVAL otherwise), CSR forces the CSR kernels. */
+typedef enum {
+    MSC_FORMAT_AUTO = 0,
+    MSC_FORMAT_CSR = 1,
+    MSC_FORMAT_SELL = 2
+} msc_format;
+
 /* Solver parameters; fill with msc_params_default() and override fields. */
 typedef struct {
     double tol;              /* relative residual target |b-(A+s_k)x_k| <= tol |b|  (1e-10) */
@@ -73,7 +83,8 @@ typedef struct {
                                 timing-th iteration, 0 = off                        (0)    */
     int32_t max_grid;        /* cap on workgroups per iteration kernel (<= 2048),
                                 0 = automatic                                       (0)    */
-    int32_t reserved[3];
+    int32_t format;          /* msc_format: matrix copy the iteration SpMVs read     (0)    */
+    int32_t reserved[2];
 } msc_params;
 
 /* Per-solve report.  Array members are caller-owned host arrays of length ns (or

@@ -16,6 +16,7 @@ LIB_PATH = os.environ.get("MSC_LIB", os.path.join(HERE, "libmsc.so"))
 MSC_OK, MSC_ENOTCONV, MSC_EINVAL, MSC_ENOMEM, MSC_EHIP, MSC_EBREAKDOWN = 0, 1, -1, -2, -3, -4
 MSC_A_MHM, MSC_A_HERM = 0, 1
 MSC_PREC_FP64, MSC_PREC_MIXED = 0, 1
+MSC_FORMAT_AUTO, MSC_FORMAT_CSR, MSC_FORMAT_SELL = 0, 1, 2
 
 STATUS_NAMES = {0: "ok", 1: "notconv", -1: "einval", -2: "enomem", -3: "ehip", -4: "breakdown"}
 
@@ -41,7 +42,8 @@ class Params(ctypes.Structure):
         ("verify", ctypes.c_int32),
         ("timing", ctypes.c_int32),
         ("max_grid", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 3),
+        ("format", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 2),
     ]
 
 

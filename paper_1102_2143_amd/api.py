@@ -13,6 +13,7 @@ from . import _lib as L
 
 _PREC = {"fp64": L.MSC_PREC_FP64, "mixed": L.MSC_PREC_MIXED}
 _KIND = {"mhm": L.MSC_A_MHM, "herm": L.MSC_A_HERM}
+_FORMAT = {"auto": L.MSC_FORMAT_AUTO, "csr": L.MSC_FORMAT_CSR, "sell": L.MSC_FORMAT_SELL}
 
 
 def _stream(stream=None):
@@ -34,7 +35,7 @@ def _ptr(t: torch.Tensor):
 
 def make_params(tol=1e-10, prec="fp64", max_iter=10000, reliable_every=50, freeze=True,
                 refine=True, poll_every=16, switch_tol=1e-5, refine_max_iter=10000, lanes=0,
-                verify=True, timing=0, max_grid=0) -> L.Params:
+                verify=True, timing=0, max_grid=0, format="auto") -> L.Params:
     lib = L.load()
     p = L.Params()
     lib.msc_params_default(ctypes.byref(p))
@@ -51,6 +52,7 @@ def make_params(tol=1e-10, prec="fp64", max_iter=10000, reliable_every=50, freez
     p.verify = int(bool(verify))
     p.timing = int(timing)
     p.max_grid = int(max_grid)
+    p.format = _FORMAT[format] if isinstance(format, str) else int(format)
     return p
 
 

@@ -133,6 +133,18 @@ MsArgs make_args(msc_op op, int lanes, const double* d_b, double* d_x) {
     a.mh64 = Csr<double2>{op->rowptr_h, op->col_h, op->val64_h};
     a.mh32 = Csr<float2>{op->rowptr_h, op->col_h, op->val32_h};
   }
+  a.sell = op->sell ? 1 : 0;
+  if (op->sell) {
+    const SellStore& sm = op->sell_m;
+    a.nslices = sm.nslices;
+    a.s64 = Sell<double2>{sm.cptr, sm.col, sm.val64, sm.diag64, sm.wp};
+    a.s32 = Sell<float2>{sm.cptr, sm.col, sm.val32, sm.diag32, sm.wp};
+    if (op->kind == MSC_A_MHM) {
+      const SellStore& sh = op->sell_mh;
+      a.sh64 = Sell<double2>{sh.cptr, sh.col, sh.val64, sh.diag64, sh.wp};
+      a.sh32 = Sell<float2>{sh.cptr, sh.col, sh.val32, sh.diag32, sh.wp};
+    }
+  }
   a.b = reinterpret_cast<const double2*>(d_b);
   a.x = reinterpret_cast<double2*>(d_x);
   a.r = op->ws.r;
@@ -165,9 +177,9 @@ double iter_bytes(int kind, int prec, double n, double nnz, double nnz_h, double
 
 // Events for sampled per-kernel timing; destroyed with the pool.
 struct EventPool {
-  std::vector<std::array<hipEvent_t, 4>> groups;
+  std::vector<std::array<hipEvent_t, 6>> groups;
   hipEvent_t* next() {
-    std::array<hipEvent_t, 4> g{};
+    std::array<hipEvent_t, 6> g{};
     for (auto& e : g)
       if (hipEventCreate(&e) != hipSuccess) return nullptr;
     groups.push_back(g);
@@ -190,8 +202,15 @@ msc_status run_multishift(msc_op op, const double* d_b, double* d_x, const msc_p
   rc = ensure_workspace(op, prec, ns);
   if (rc != MSC_OK) return rc;
   const int lanes = choose_lanes(op, prm);
+  if (prm.format < MSC_FORMAT_AUTO || prm.format > MSC_FORMAT_SELL ||
+      (prm.format == MSC_FORMAT_SELL && !op->sell)) {
+    set_error("msc_solve: format %d unavailable (sliced ELLPACK copy %s)", prm.format,
+              op->sell ? "built" : "not built: padding too large");
+    return MSC_EINVAL;
+  }
   MsArgs a64 = make_args(op, lanes, d_b, d_x);
   if (prm.max_grid > 0) a64.grid = std::min(prm.max_grid, kMaxGrid);
+  if (prm.format == MSC_FORMAT_CSR) a64.sell = 0;
   MsArgs a32 = a64;
   const bool mixed = prec == MSC_PREC_MIXED;
   if (mixed) {
@@ -289,7 +308,7 @@ msc_status run_multishift(msc_op op, const double* d_b, double* d_x, const msc_p
       if (sample_launch[q] >= useful_launches) continue;
       for (int k = 0; k < 3; ++k) {
         float ms = 0.f;
-        HIP_TRY(hipEventElapsedTime(&ms, pool.groups[q][k], pool.groups[q][k + 1]));
+        HIP_TRY(hipEventElapsedTime(&ms, pool.groups[q][2 * k], pool.groups[q][2 * k + 1]));
         info->kernel_ms[k] += ms;
       }
       info->kernel_samples += 1;
@@ -1096,6 +1115,16 @@ msc_status msc_op_create_csr(msc_op* out, int32_t kind, int64_t n, int64_t nnz,
     CREATE_TRY(build_adjoint(op->rowptr, op->col, n, nnz, op->rowptr_h, op->col_h, op->perm_h, s));
     CREATE_TRY(launch_adjoint_vals(op->perm_h, op->val64, op->val64_h, op->val32_h, nnz, s));
   }
+  // sliced ELLPACK copies for the iteration SpMVs, when their padding is small
+  bool built_m = false, built_mh = kind != MSC_A_MHM;
+  CREATE_TRY(build_sell(op->rowptr, op->col, op->val64, n, nnz, op->sell_m, &built_m, s));
+  if (built_m && kind == MSC_A_MHM)
+    CREATE_TRY(build_sell(op->rowptr_h, op->col_h, op->val64_h, n, nnz, op->sell_mh, &built_mh, s));
+  op->sell = built_m && built_mh;
+  if (!op->sell) {
+    free_sell(op->sell_m);
+    free_sell(op->sell_mh);
+  }
   CREATE_TRY(hipStreamSynchronize(s));
 #undef CREATE_TRY
   *out = op;
@@ -1114,6 +1143,11 @@ msc_status msc_op_update_values(msc_op op, const double* d_vals, msc_stream stre
     HIP_TRY(launch_cast_vals(op->val64, op->val32, op->nnz, s));
     if (op->kind == MSC_A_MHM)
       HIP_TRY(launch_adjoint_vals(op->perm_h, op->val64, op->val64_h, op->val32_h, op->nnz, s));
+    if (op->sell) {
+      HIP_TRY(refill_sell(op->rowptr, op->col, op->val64, op->n, op->sell_m, s));
+      if (op->kind == MSC_A_MHM)
+        HIP_TRY(refill_sell(op->rowptr_h, op->col_h, op->val64_h, op->n, op->sell_mh, s));
+    }
   }
   HIP_TRY(hipStreamSynchronize(s));
   return MSC_OK;
@@ -1412,6 +1446,8 @@ void msc_op_destroy(msc_op op) {
   dfree(op->perm_h);
   dfree(op->val64_h);
   dfree(op->val32_h);
+  free_sell(op->sell_m);
+  free_sell(op->sell_mh);
   delete op;
 }
 

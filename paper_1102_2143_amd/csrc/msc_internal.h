@@ -72,6 +72,35 @@ template <class V> struct Csr {
   const V* val = nullptr;
 };
 
+// Sliced ELLPACK copy of a CSR matrix for the iteration SpMVs: slices of kSlice rows
+// (one wavefront, one row per lane), the diagonal held apart in `diag`, the off-diagonal
+// entries of a slice stored by pairs.  Entry k of lane l of slice s sits at
+//   (cptr[s] + k / 2) * 2 kSlice + 2 l + (k % 2),
+// so a lane reads two entries with one load and a wavefront reads whole cache lines;
+// cptr[s + 1] - cptr[s] is the slice's width in pairs.  Padding entries hold 0 and a
+// valid column.
+constexpr int kSlice = 64;
+template <class V> struct Sell {
+  const int32_t* cptr = nullptr;  // nslices + 1
+  const int32_t* col = nullptr;
+  const V* val = nullptr;
+  const V* diag = nullptr;        // n
+  int32_t wp = 0;                 // > 0: every slice is wp pairs wide (cptr[s] = s wp)
+};
+
+// Device buffers of one sliced ELLPACK matrix (both value precisions share the columns).
+struct SellStore {
+  int64_t nslices = 0;
+  int64_t pairs = 0;              // total pairs of all slices
+  int32_t wp = 0;                 // common width in pairs when all slices agree, else 0
+  int32_t* cptr = nullptr;
+  int32_t* col = nullptr;
+  double2* val64 = nullptr;
+  float2* val32 = nullptr;
+  double2* diag64 = nullptr;
+  float2* diag32 = nullptr;
+};
+
 struct Workspace {
   size_t n = 0;
   int ns = 0;
@@ -130,6 +159,8 @@ struct msc_op_s {
   size_t yadj_count = 0;
   double* adj_small = nullptr;   // 256 doubles: Gram sums and shift factors
   int lanes64 = 0, lanes32 = 0;  // chosen lanes per row (0 = not yet tuned)
+  bool sell = false;             // sliced ELLPACK copies built (M, and M^H for kind MHM)
+  msc::SellStore sell_m, sell_mh;
 };
 
 namespace msc {
@@ -146,6 +177,14 @@ hipError_t build_adjoint(const int32_t* rowptr, const int32_t* col, int64_t n, i
                          int32_t* rowptr_h, int32_t* col_h, int32_t* perm_h, hipStream_t s);
 hipError_t launch_adjoint_vals(const int32_t* perm_h, const double2* val64, double2* val64_h,
                                float2* val32_h, int64_t nnz, hipStream_t s);
+// Build the sliced ELLPACK copy of a CSR matrix into `out` when its padding stays small
+// (slots <= 1.5 nnz + 2 kSlice per slice); *built tells whether it was.  Synchronises `s`.
+hipError_t build_sell(const int32_t* rowptr, const int32_t* col, const double2* val64, int64_t n,
+                      int64_t nnz, SellStore& out, bool* built, hipStream_t s);
+// Rewrite the values (and diagonal) of a built copy from the CSR values.
+hipError_t refill_sell(const int32_t* rowptr, const int32_t* col, const double2* val64, int64_t n,
+                       const SellStore& out, hipStream_t s);
+void free_sell(SellStore& out);
 
 // multishift.hip
 struct MsArgs {
@@ -155,6 +194,10 @@ struct MsArgs {
   int grid;
   Csr<double2> m64, mh64;
   Csr<float2> m32, mh32;
+  int sell;              // K1/K2 read the sliced ELLPACK copies below
+  int64_t nslices;
+  Sell<double2> s64, sh64;
+  Sell<float2> s32, sh32;
   const double2* b;
   double2* x;            // caller's x, shift-major, caller order
   void* r; void* p; void* t; void* pk;
@@ -163,7 +206,7 @@ struct MsArgs {
   Scratch sc;
 };
 hipError_t launch_init(int prec, const MsArgs& a, hipStream_t s);
-// ev (optional, 4 events): recorded before K1, after K1, after K2 and after K3.
+// ev (optional, 6 events): start/stop pairs attached to the K1, K2 and K3 dispatches.
 hipError_t launch_iteration(int prec, const MsArgs& a, hipStream_t s, hipEvent_t* ev = nullptr);
 hipError_t launch_reliable(int prec, const MsArgs& a, hipStream_t s);
 // Second phase of a mixed solve: copy r, p, p_j of a64 (complex128) into a32's complex64
@@ -261,6 +304,10 @@ struct BatchSys {
   int64_t n;
   Csr<double2> m64, mh64;
   Csr<float2> m32, mh32;
+  int sell;              // K1/K2 read the sliced ELLPACK copies below
+  int64_t nslices;
+  Sell<double2> s64, sh64;
+  Sell<float2> s32, sh32;
   const double2* b;       // nrhs * n (rhs-major)
   double2* x;             // nrhs * ns * n (rhs-major, shift-major, caller order)
   double2 *r64, *p64, *t64, *pk64, *u64;   // rhs-interleaved n x RR; pk: (ns-1) blocks

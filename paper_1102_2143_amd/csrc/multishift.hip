@@ -15,6 +15,8 @@
 // All scalar work stays on the device in FP64 (Section 3: the iteration constants are
 // computed on the GPU to avoid host round trips).  Reductions are deterministic: each
 // workgroup writes one partial, the last one to arrive sums them in a fixed order.
+#include <hip/hip_ext.h>
+
 #include "dev_common.h"
 #include "msc_internal.h"
 
@@ -28,6 +30,106 @@ template <> __device__ __forceinline__ Csr<double2> pick_m<double>(const MsArgs&
 template <class R> __device__ __forceinline__ Csr<cplx<R>> pick_mh(const MsArgs& a);
 template <> __device__ __forceinline__ Csr<float2> pick_mh<float>(const MsArgs& a) { return a.mh32; }
 template <> __device__ __forceinline__ Csr<double2> pick_mh<double>(const MsArgs& a) { return a.mh64; }
+
+template <class R> __device__ __forceinline__ Sell<cplx<R>> pick_sm(const MsArgs& a);
+template <> __device__ __forceinline__ Sell<float2> pick_sm<float>(const MsArgs& a) { return a.s32; }
+template <> __device__ __forceinline__ Sell<double2> pick_sm<double>(const MsArgs& a) { return a.s64; }
+template <class R> __device__ __forceinline__ Sell<cplx<R>> pick_shm(const MsArgs& a);
+template <> __device__ __forceinline__ Sell<float2> pick_shm<float>(const MsArgs& a) { return a.sh32; }
+template <> __device__ __forceinline__ Sell<double2> pick_shm<double>(const MsArgs& a) { return a.sh64; }
+
+// Entries 2q and 2q+1 of one lane (pair index q counts kSlice pairs per slice column).
+__device__ __forceinline__ void load_pair(const float2* __restrict__ v, int64_t q, float2& e0,
+                                          float2& e1) {
+  const float4 w = reinterpret_cast<const float4*>(v)[q];
+  e0 = float2{w.x, w.y};
+  e1 = float2{w.z, w.w};
+}
+__device__ __forceinline__ void load_pair(const double2* __restrict__ v, int64_t q, double2& e0,
+                                          double2& e1) {
+  e0 = v[2 * q];
+  e1 = v[2 * q + 1];
+}
+
+// Pairs per round trip of the sliced ELLPACK row product (register budget: complex64
+// keeps a 24-entry staggered row in flight at once, complex128 half of it).
+template <class R> constexpr int sell_kp();
+template <> constexpr int sell_kp<float>() { return 12; }
+template <> constexpr int sell_kp<double>() { return 6; }
+
+// Column and value loads of KP pairs starting at pair column c (np < KP: only the first
+// np pairs exist; the rest read as zero).
+template <class R, int KP, bool FULL>
+__device__ __forceinline__ void sell_load(const Sell<cplx<R>>& m, int32_t c, int np, int lane,
+                                          int2 (&cc)[KP], cplx<R> (&v)[2 * KP]) {
+  const int2* __restrict__ colp = reinterpret_cast<const int2*>(m.col);
+#pragma unroll
+  for (int u = 0; u < KP; ++u) {
+    if (FULL || u < np) {
+      const int64_t q = int64_t(c + u) * kSlice + lane;
+      cc[u] = colp[q];
+      load_pair(m.val, q, v[2 * u], v[2 * u + 1]);
+    } else {
+      cc[u] = int2{0, 0};
+      v[2 * u] = v[2 * u + 1] = czero<R>();
+    }
+  }
+}
+
+template <class R, int KP, bool FULL>
+__device__ __forceinline__ void sell_gather_fma(const cplx<R>* __restrict__ x, int np,
+                                                const int2 (&cc)[KP], const cplx<R> (&v)[2 * KP],
+                                                cplx<R>& acc) {
+  cplx<R> xv[2 * KP];
+#pragma unroll
+  for (int u = 0; u < KP; ++u) {
+    if (FULL || u < np) {
+      xv[2 * u] = x[cc[u].x];
+      xv[2 * u + 1] = x[cc[u].y];
+    } else {
+      xv[2 * u] = xv[2 * u + 1] = czero<R>();
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < 2 * KP; ++u) cfma<R>(acc, v[u], xv[u]);
+}
+
+// Slice offsets are read through the scalar cache: the address is wavefront-uniform and
+// the array is never written while a solve runs.
+__device__ __forceinline__ int32_t load_uniform(const int32_t* p, int64_t i) {
+  using cptr_t = const __attribute__((address_space(4))) int32_t*;
+  return ((cptr_t)p)[i];
+}
+
+// Off-diagonal part of the product of one sliced ELLPACK row per lane with x; slice `sl`
+// is wavefront-uniform.  Pairs go KP at a time: a chunk's column and value loads, then
+// its gathers, are all issued before its first multiply-add.
+template <class R>
+__device__ __forceinline__ cplx<R> sell_row(const Sell<cplx<R>>& m, const cplx<R>* __restrict__ x,
+                                            int64_t sl, int lane) {
+  constexpr int KP = sell_kp<R>();
+  int32_t c, c1;
+  if (m.wp > 0) {
+    c = int32_t(sl) * m.wp;
+    c1 = c + m.wp;
+  } else {
+    c = load_uniform(m.cptr, sl);
+    c1 = load_uniform(m.cptr, sl + 1);
+  }
+  cplx<R> acc = czero<R>();
+  int2 cc[KP];
+  cplx<R> v[2 * KP];
+  for (; c + KP <= c1; c += KP) {
+    sell_load<R, KP, true>(m, c, KP, lane, cc, v);
+    sell_gather_fma<R, KP, true>(x, KP, cc, v, acc);
+  }
+  if (c < c1) {
+    const int np = c1 - c;
+    sell_load<R, KP, false>(m, c, np, lane, cc, v);
+    sell_gather_fma<R, KP, false>(x, np, cc, v, acc);
+  }
+  return acc;
+}
 
 // One CSR row times a vector, L lanes per row; the sum is returned in every lane.
 // Entries of one row handled by a lane per chunk: the column and value loads of a chunk,
@@ -241,6 +343,32 @@ __device__ void finalize_k2(SolveState* st, double Rn, const K2Pre& q) {
   }
 }
 
+// Workgroup partial of P (K1) or R' (K2), the ticket, and the finalisation by the last
+// workgroup to arrive.
+__device__ __forceinline__ void finish_k1(const MsArgs& a, double acc) {
+  const double tot = block_sum<kBlock>(acc);
+  if (threadIdx.x == 0) store_agent(&a.sc.partial[blockIdx.x], tot);
+  if (!arrive_last(a.sc.tickets + 0 * kTicketSite)) return;
+  __shared__ double Psh;
+  const K1Pre pre = prefetch_k1(a.st);
+  const double P = sum_partials(a.sc.partial, gridDim.x, 1, 0);
+  if (threadIdx.x == 0) Psh = P;
+  __syncthreads();
+  finalize_k1(a.st, Psh, pre);
+}
+
+__device__ __forceinline__ void finish_k2(const MsArgs& a, double acc) {
+  const double tot = block_sum<kBlock>(acc);
+  if (threadIdx.x == 0) store_agent(&a.sc.partial[blockIdx.x], tot);
+  if (!arrive_last(a.sc.tickets + 1 * kTicketSite)) return;
+  __shared__ double Rsh;
+  const K2Pre pre = prefetch_k2(a.st);
+  const double Rn = sum_partials(a.sc.partial, gridDim.x, 1, 0);
+  if (threadIdx.x == 0) Rsh = Rn;
+  __syncthreads();
+  finalize_k2(a.st, Rsh, pre);
+}
+
 // ---- K1 -------------------------------------------------------------------------------
 template <class R, int L, bool MHM>
 __global__ __launch_bounds__(kBlock) void k1_apply(MsArgs a) {
@@ -276,15 +404,7 @@ __global__ __launch_bounds__(kBlock) void k1_apply(MsArgs a) {
       if (has1) epilogue(row1, v1);
     }
   }
-  const double tot = block_sum<kBlock>(acc);
-  if (threadIdx.x == 0) store_agent(&a.sc.partial[blockIdx.x], tot);
-  if (!arrive_last(a.sc.tickets + 0 * kTicketSite)) return;
-  __shared__ double Psh;
-  const K1Pre pre = prefetch_k1(st);
-  const double P = sum_partials(a.sc.partial, gridDim.x, 1, 0);
-  if (threadIdx.x == 0) Psh = P;
-  __syncthreads();
-  finalize_k1(st, Psh, pre);
+  finish_k1(a, acc);
 }
 
 // ---- K2 (A = M^H M): r <- r - a (M^H t + sigma0 p), R' = |r|^2 ------------------------
@@ -324,15 +444,85 @@ __global__ __launch_bounds__(kBlock) void k2_mhm(MsArgs a) {
       if (has1) epilogue(row1, q1);
     }
   }
-  const double tot = block_sum<kBlock>(acc);
-  if (threadIdx.x == 0) store_agent(&a.sc.partial[blockIdx.x], tot);
-  if (!arrive_last(a.sc.tickets + 1 * kTicketSite)) return;
-  __shared__ double Rsh;
-  const K2Pre pre = prefetch_k2(st);
-  const double Rn = sum_partials(a.sc.partial, gridDim.x, 1, 0);
-  if (threadIdx.x == 0) Rsh = Rn;
-  __syncthreads();
-  finalize_k2(st, Rsh, pre);
+  finish_k2(a, acc);
+}
+
+// ---- K1 and K2 on the sliced ELLPACK copies: one row per lane, one slice per wave ----
+template <class R, bool MHM>
+__global__ __launch_bounds__(kBlock) void k1_sell(MsArgs a) {
+  SolveState* st = a.st;
+  if (st->halt) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->k3_enable = 0;
+    return;
+  }
+  const Sell<cplx<R>> m = pick_sm<R>(a);
+  const cplx<R>* __restrict__ p = static_cast<const cplx<R>*>(a.p);
+  cplx<R>* __restrict__ t = static_cast<cplx<R>*>(a.t);
+  const double sigma0 = st->sigma0;
+  constexpr int SPB = kBlock / kSlice;
+  const int lane = threadIdx.x % kSlice;
+  const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x / kSlice));
+  int64_t beg, end;
+  block_range(a.nslices, SPB, beg, end);
+  double acc = 0.0;
+  for (int64_t sl = beg + wv; sl < end; sl += SPB) {
+    const int64_t row = sl * kSlice + lane;
+    const bool live = row < a.n;
+    const int64_t rr = live ? row : a.n - 1;  // lanes past n read a valid row, unused
+    const cplx<R> pr = p[rr];
+    const cplx<R> d = m.diag[rr];
+    cplx<R> v = sell_row<R>(m, p, sl, lane);
+    cfma<R>(v, d, pr);
+    if (live) {
+      t[row] = v;
+      if (MHM)
+        acc += norm2d<R>(v) + sigma0 * norm2d<R>(pr);
+      else
+        acc += double(pr.x) * double(v.x) + double(pr.y) * double(v.y) + sigma0 * norm2d<R>(pr);
+    }
+  }
+  finish_k1(a, acc);
+}
+
+template <class R>
+__global__ __launch_bounds__(kBlock) void k2_sell(MsArgs a) {
+  SolveState* st = a.st;
+  if (st->halt) return;
+  const Sell<cplx<R>> mh = pick_shm<R>(a);
+  const cplx<R>* __restrict__ t = static_cast<const cplx<R>*>(a.t);
+  const cplx<R>* __restrict__ p = static_cast<const cplx<R>*>(a.p);
+  cplx<R>* __restrict__ r = static_cast<cplx<R>*>(a.r);
+  const double sigma0 = st->sigma0;
+  const double step = st->a;
+  constexpr int SPB = kBlock / kSlice;
+  const int lane = threadIdx.x % kSlice;
+  const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x / kSlice));
+  int64_t beg, end;
+  block_range(a.nslices, SPB, beg, end);
+  double acc = 0.0;
+  for (int64_t sl = beg + wv; sl < end; sl += SPB) {
+    const int64_t row = sl * kSlice + lane;
+    const bool live = row < a.n;
+    const int64_t rr = live ? row : a.n - 1;  // lanes past n read a valid row, unused
+    const cplx<R> tr = t[rr];
+    const cplx<R> d = mh.diag[rr];
+    const cplx<R> pv = p[rr];
+    const cplx<R> rv = r[rr];
+    cplx<R> q = sell_row<R>(mh, t, sl, lane);
+    cfma<R>(q, d, tr);
+    if (live) {
+      const double2 pr = to_d(pv);
+      const double2 rr = to_d(rv);
+      const double2 qd = to_d(q);
+      double2 nr;
+      nr.x = rr.x - step * (qd.x + sigma0 * pr.x);
+      nr.y = rr.y - step * (qd.y + sigma0 * pr.y);
+      const cplx<R> st_r = from_d<R>(nr);
+      r[row] = st_r;
+      acc += norm2d<R>(st_r);
+    }
+  }
+  finish_k2(a, acc);
 }
 
 // ---- K2 (A given): elementwise r <- r - a (t + sigma0 p) -------------------------------
@@ -357,15 +547,7 @@ __global__ __launch_bounds__(kBlock) void k2_herm(MsArgs a) {
     r[i] = st_r;
     acc += norm2d<R>(st_r);
   }
-  const double tot = block_sum<kBlock>(acc);
-  if (threadIdx.x == 0) store_agent(&a.sc.partial[blockIdx.x], tot);
-  if (!arrive_last(a.sc.tickets + 1 * kTicketSite)) return;
-  __shared__ double Rsh;
-  const K2Pre pre = prefetch_k2(st);
-  const double Rn = sum_partials(a.sc.partial, gridDim.x, 1, 0);
-  if (threadIdx.x == 0) Rsh = Rn;
-  __syncthreads();
-  finalize_k2(st, Rsh, pre);
+  finish_k2(a, acc);
 }
 
 // ---- K3: fused update of every active shift from one read of r and p ------------------
@@ -710,23 +892,37 @@ int grid_rows(int64_t n, int rows_per_pass, int cap = kMaxGrid) {
     default: return hipErrorInvalidValue;            \
   }
 
+// Launch one kernel of an iteration.  With `ev`, the start/stop events of pair `k` are
+// attached to the dispatch itself (their timestamps are the kernel's own begin and
+// end), so the elapsed time excludes the queue gap between kernels.
+template <class K>
+void launch_timed(K kern, int grid, hipStream_t s, hipEvent_t* ev, int k, const MsArgs& a) {
+  if (ev)
+    hipExtLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), 0, s, ev[2 * k], ev[2 * k + 1], 0, a);
+  else
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), 0, s, a);
+}
+
 template <class R>
 hipError_t iteration_impl(const MsArgs& a, hipStream_t s, hipEvent_t* ev) {
   const int g1 = grid_rows(a.n, kBlock / a.lanes, a.grid);
   const int g3 = grid_rows(a.n, kBlock, a.grid);
-  if (ev) (void)hipEventRecord(ev[0], s);
-  if (a.kind == MSC_A_MHM) {
-    MSC_LANES_SWITCH(a.lanes, (k1_apply<R, LL, true><<<g1, kBlock, 0, s>>>(a)));
-    if (ev) (void)hipEventRecord(ev[1], s);
-    MSC_LANES_SWITCH(a.lanes, (k2_mhm<R, LL><<<g1, kBlock, 0, s>>>(a)));
+  if (a.sell) {
+    if (a.kind == MSC_A_MHM) {
+      launch_timed(k1_sell<R, true>, g3, s, ev, 0, a);
+      launch_timed(k2_sell<R>, g3, s, ev, 1, a);
+    } else {
+      launch_timed(k1_sell<R, false>, g3, s, ev, 0, a);
+      launch_timed(k2_herm<R>, g3, s, ev, 1, a);
+    }
+  } else if (a.kind == MSC_A_MHM) {
+    MSC_LANES_SWITCH(a.lanes, (launch_timed(k1_apply<R, LL, true>, g1, s, ev, 0, a)));
+    MSC_LANES_SWITCH(a.lanes, (launch_timed(k2_mhm<R, LL>, g1, s, ev, 1, a)));
   } else {
-    MSC_LANES_SWITCH(a.lanes, (k1_apply<R, LL, false><<<g1, kBlock, 0, s>>>(a)));
-    if (ev) (void)hipEventRecord(ev[1], s);
-    k2_herm<R><<<g3, kBlock, 0, s>>>(a);
+    MSC_LANES_SWITCH(a.lanes, (launch_timed(k1_apply<R, LL, false>, g1, s, ev, 0, a)));
+    launch_timed(k2_herm<R>, g3, s, ev, 1, a);
   }
-  if (ev) (void)hipEventRecord(ev[2], s);
-  k3_update<R><<<g3, kBlock, 0, s>>>(a);
-  if (ev) (void)hipEventRecord(ev[3], s);
+  launch_timed(k3_update<R>, g3, s, ev, 2, a);
   return hipGetLastError();
 }
 

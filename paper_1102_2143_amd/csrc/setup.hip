@@ -1,6 +1,9 @@
 // Operator set-up on the device: CSR validation, index and value conversions, and the
 // conjugate transpose M^H (counting sort by column, then a per-row sort so the result
-// is deterministic).  Runs once per operator; not on the iteration path.
+// is deterministic), and the sliced ELLPACK copies the iteration SpMVs read.  Runs once
+// per operator (the values again after an update); not on the iteration path.
+#include <vector>
+
 #include "dev_common.h"
 #include "msc_internal.h"
 
@@ -174,6 +177,66 @@ __global__ void k_adjoint_vals(const int32_t* __restrict__ perm_h, const double2
   }
 }
 
+// ---- sliced ELLPACK copy ------------------------------------------------------------
+// One thread per row slot of a slice (slots past n belong to the last, partial slice).
+// Pairs of off-diagonal entries each slice needs: the wavefront maximum of its rows.
+__global__ void k_sell_pairs(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                             int64_t n, int64_t nslices, int32_t* __restrict__ pairs) {
+  const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  int cnt = 0;
+  if (i < n)
+    for (int32_t e = rowptr[i]; e < rowptr[i + 1]; ++e) cnt += col[e] != int32_t(i);
+#pragma unroll
+  for (int off = kSlice / 2; off > 0; off >>= 1) {
+    const int o = __shfl_xor(cnt, off, kSlice);
+    cnt = o > cnt ? o : cnt;
+  }
+  const int64_t sl = i / kSlice;
+  if ((i % kSlice) == 0 && sl < nslices) pairs[sl] = (cnt + 1) / 2;
+}
+
+// Scatter each row into its slice: off-diagonal entries in CSR order, padding with the
+// row's own column and value 0, diagonal entries summed into diag.
+__global__ void k_sell_fill(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                            const double2* __restrict__ val, int64_t n, int64_t nslices,
+                            const int32_t* __restrict__ cptr, int32_t* __restrict__ scol,
+                            double2* __restrict__ sv64, float2* __restrict__ sv32,
+                            double2* __restrict__ d64, float2* __restrict__ d32) {
+  const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  const int64_t sl = i / kSlice;
+  if (sl >= nslices) return;
+  const int lane = int(i % kSlice);
+  const int64_t base = int64_t(cptr[sl]) * (2 * kSlice) + 2 * lane;
+  const int width = 2 * (cptr[sl + 1] - cptr[sl]);
+  int k = 0;
+  if (i < n) {
+    double2 d{0.0, 0.0};
+    for (int32_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+      const int32_t c = col[e];
+      const double2 v = val[e];
+      if (c == int32_t(i)) {
+        d.x += v.x;
+        d.y += v.y;
+        continue;
+      }
+      const int64_t at = base + int64_t(k >> 1) * (2 * kSlice) + (k & 1);
+      scol[at] = c;
+      sv64[at] = v;
+      sv32[at] = float2{float(v.x), float(v.y)};
+      ++k;
+    }
+    d64[i] = d;
+    d32[i] = float2{float(d.x), float(d.y)};
+  }
+  const int32_t pad = i < n ? int32_t(i) : 0;
+  for (; k < width; ++k) {
+    const int64_t at = base + int64_t(k >> 1) * (2 * kSlice) + (k & 1);
+    scol[at] = pad;
+    sv64[at] = double2{0.0, 0.0};
+    sv32[at] = float2{0.f, 0.f};
+  }
+}
+
 }  // namespace
 
 hipError_t launch_validate_csr(const int64_t* rowptr, const int32_t* col, int64_t n, int64_t nnz,
@@ -229,6 +292,74 @@ hipError_t launch_adjoint_vals(const int32_t* perm_h, const double2* val64, doub
   if (nnz > 0)
     k_adjoint_vals<<<blocks_for(nnz), kSetupBlock, 0, s>>>(perm_h, val64, val64_h, val32_h, nnz);
   return hipGetLastError();
+}
+
+void free_sell(SellStore& m) {
+  for (void* q : {static_cast<void*>(m.cptr), static_cast<void*>(m.col), static_cast<void*>(m.val64),
+                  static_cast<void*>(m.val32), static_cast<void*>(m.diag64),
+                  static_cast<void*>(m.diag32)})
+    if (q) (void)hipFree(q);
+  m = SellStore{};
+}
+
+hipError_t refill_sell(const int32_t* rowptr, const int32_t* col, const double2* val64, int64_t n,
+                       const SellStore& m, hipStream_t s) {
+  const int64_t slots = m.nslices * kSlice;
+  k_sell_fill<<<dim3(unsigned((slots + kSetupBlock - 1) / kSetupBlock)), kSetupBlock, 0, s>>>(
+      rowptr, col, val64, n, m.nslices, m.cptr, m.col, m.val64, m.val32, m.diag64, m.diag32);
+  return hipGetLastError();
+}
+
+hipError_t build_sell(const int32_t* rowptr, const int32_t* col, const double2* val64, int64_t n,
+                      int64_t nnz, SellStore& m, bool* built, hipStream_t s) {
+  *built = false;
+  free_sell(m);
+  const int64_t nslices = (n + kSlice - 1) / kSlice;
+  const int64_t slots = nslices * kSlice;
+  const unsigned blocks = unsigned((slots + kSetupBlock - 1) / kSetupBlock);
+  int32_t* pairs = nullptr;
+  hipError_t e = hipMalloc(&pairs, sizeof(int32_t) * nslices);
+  if (e != hipSuccess) return e;
+  k_sell_pairs<<<dim3(blocks), kSetupBlock, 0, s>>>(rowptr, col, n, nslices, pairs);
+  std::vector<int32_t> h(size_t(nslices) + 1, 0);
+  e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(h.data() + 1, pairs, sizeof(int32_t) * nslices,
+                                          hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(pairs);
+  if (e != hipSuccess) return e;
+  int64_t total = 0;
+  bool uniform = true;
+  for (int64_t q = 1; q <= nslices; ++q) {
+    uniform = uniform && h[q] == h[1];
+    total += h[q];
+    if (total >= (int64_t(1) << 31)) return hipSuccess;  // offsets would not fit: keep CSR
+    h[q] = int32_t(total);
+  }
+  const double sell_slots = double(total) * 2.0 * kSlice;
+  if (sell_slots > 1.5 * double(nnz) + 2.0 * kSlice * double(nslices)) return hipSuccess;
+  m.nslices = nslices;
+  m.pairs = total;
+  m.wp = uniform ? h[1] : 0;
+  const size_t cells = size_t(total) * 2 * kSlice;
+  if ((e = hipMalloc(&m.cptr, sizeof(int32_t) * (nslices + 1))) != hipSuccess ||
+      (e = hipMalloc(&m.col, sizeof(int32_t) * (cells ? cells : 1))) != hipSuccess ||
+      (e = hipMalloc(&m.val64, sizeof(double2) * (cells ? cells : 1))) != hipSuccess ||
+      (e = hipMalloc(&m.val32, sizeof(float2) * (cells ? cells : 1))) != hipSuccess ||
+      (e = hipMalloc(&m.diag64, sizeof(double2) * n)) != hipSuccess ||
+      (e = hipMalloc(&m.diag32, sizeof(float2) * n)) != hipSuccess) {
+    free_sell(m);
+    return e;
+  }
+  e = hipMemcpyAsync(m.cptr, h.data(), sizeof(int32_t) * (nslices + 1), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = refill_sell(rowptr, col, val64, n, m, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    free_sell(m);
+    return e;
+  }
+  *built = true;
+  return hipSuccess;
 }
 
 }  // namespace msc

@@ -129,8 +129,10 @@ def test_shift_order_and_duplicates(c0, cuda):
     op.close()
 
 
-def test_herm_laplacian(cuda):
-    print("[gpu] herm laplacian", flush=True)
+@pytest.mark.parametrize("fmt", ["auto", "csr", "sell"])
+def test_herm_laplacian(cuda, fmt):
+    # 315 rows: four full 64-row slices and a partial one; boundary rows are shorter
+    print(f"[gpu] herm laplacian {fmt}", flush=True)
     rowptr, col, vals = W.laplacian7_csr((9, 7, 5), 31)
     n = 315
     b = W.gaussian_rhs(n, 32)
@@ -138,7 +140,7 @@ def test_herm_laplacian(cuda):
     p = dict(rowptr=rowptr, col=col, vals=vals, n=n, kind="herm")
     op = _op(p, cuda)
     op.set_shifts(sigma)
-    x, info = op.solve(b, tol=1e-10)
+    x, info = op.solve(b, tol=1e-10, format=fmt)
     ref = O.cg_m(O.shifted_apply("herm", rowptr, col, vals, n), b, sigma, tol=1e-10)
     assert info["status"] == "ok"
     assert abs(info["iters"] - ref["iters"]) <= 2
@@ -146,7 +148,8 @@ def test_herm_laplacian(cuda):
     op.close()
 
 
-def test_non_normal_random_operator(cuda):
+@pytest.mark.parametrize("fmt", ["auto", "csr"])
+def test_non_normal_random_operator(cuda, fmt):
     rowptr, col, vals = W.random_sparse_csr(400, 9, 44, diag=5.0, empty_rows=(7,))
     n = 400
     b = W.gaussian_rhs(n, 45)
@@ -155,7 +158,7 @@ def test_non_normal_random_operator(cuda):
     p = dict(rowptr=rowptr, col=col, vals=vals, n=n, kind="mhm")
     op = _op(p, cuda)
     op.set_shifts(sigma)
-    x, info = op.solve(b, tol=1e-12)
+    x, info = op.solve(b, tol=1e-12, format=fmt)
     xd = O.dense_solve("mhm", rowptr, col, vals, n, b, sigma)
     assert np.all(_rel(x.cpu().numpy(), xd) <= 1e-9)
     op.close()
@@ -224,14 +227,97 @@ def test_invalid_csr_rejected(cuda):
                  device=cuda)
 
 
-def test_update_values(c0, cuda):
+@pytest.mark.parametrize("fmt", ["csr", "sell"])
+def test_update_values(c0, cuda, fmt):
+    # new values reach both the CSR arrays and the sliced ELLPACK copies
     op = _op(c0, cuda)
     op.set_shifts(c0["sigma"])
     p2 = W.staggered_problem((4, 4, 4, 4), 0.1, 77, 2000, (1e-4, 1.0, 8))
     op.update_values(p2["vals"])
-    x, info = op.solve(c0["b"], tol=1e-11)
+    x, info = op.solve(c0["b"], tol=1e-11, format=fmt)
     xd = O.dense_solve("mhm", p2["rowptr"], p2["col"], p2["vals"], p2["n"], c0["b"], c0["sigma"])
     assert np.all(_rel(x.cpu().numpy(), xd) <= 1e-9)
+    op.close()
+
+
+# ---- matrix formats of the iteration SpMVs ------------------------------------------------
+@pytest.mark.parametrize("fmt", ["csr", "sell"])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_c0_both_formats_match_oracle(c0, cuda, fmt, prec):
+    print(f"[gpu] c0 {prec} format={fmt}", flush=True)
+    op = _op(c0, cuda)
+    op.set_shifts(c0["sigma"])
+    x, info = op.solve(c0["b"], tol=1e-10, prec=prec, format=fmt)
+    ref = c0["ref"]
+    assert info["status"] == "ok", info
+    if prec == "fp64":
+        assert abs(info["iters"] - ref["iters"]) <= 2
+        assert np.all(_rel(x.cpu().numpy(), ref["x"]) <= 1e-8)
+    else:
+        assert info["iters"] <= 1.03 * ref["iters"] + 2
+    assert np.all(info["true_rel_res"] <= 1e-10)
+    op.close()
+
+
+def test_sell_partial_last_slice(cuda):
+    # 6x6x6x4 sites: 2592 rows = 40 full slices and a half one
+    print("[gpu] 6^3x4 staggered, partial slice", flush=True)
+    p = W.staggered_problem((6, 6, 6, 4), 0.1, 91, 92, (1e-3, 1.0, 6))
+    assert p["n"] % 64 != 0
+    ap = O.shifted_apply("mhm", p["rowptr"], p["col"], p["vals"], p["n"])
+    ref = O.cg_m(ap, p["b"], p["sigma"], tol=1e-10)
+    op = _op(p, cuda)
+    op.set_shifts(p["sigma"])
+    for prec in ("fp64", "mixed"):
+        x, info = op.solve(p["b"], tol=1e-10, prec=prec, format="sell")
+        assert info["status"] == "ok"
+        assert np.all(info["true_rel_res"] <= 1e-10)
+        if prec == "fp64":
+            assert abs(info["iters"] - ref["iters"]) <= 2
+            assert np.all(_rel(x.cpu().numpy(), ref["x"]) <= 1e-8)
+    op.close()
+
+
+def test_sell_refused_when_padding_is_large(cuda):
+    # one 60-entry row per 64-row slice, every other row holds only its diagonal: the
+    # sliced copy would be ~30x the entry count, so it is not built and format="sell"
+    # is an error while "auto" falls back to CSR
+    from paper_1102_2143_amd import MscError
+    n = 640
+    rows = []
+    rng = np.random.default_rng(5)
+    for i in range(n):
+        if i % 64 == 0:
+            cols = np.sort(rng.choice(n, 60, replace=False))
+            cols = np.union1d(cols, [i])
+        else:
+            cols = np.array([i])
+        rows.append(cols)
+    rowptr = np.zeros(n + 1, np.int64)
+    rowptr[1:] = np.cumsum([len(c) for c in rows])
+    col = np.concatenate(rows).astype(np.int32)
+    vals = rng.standard_normal(len(col)) * 0.1 + 0j
+    vals[[rowptr[i] + int(np.searchsorted(rows[i], i)) for i in range(n)]] = 3.0
+    b = W.gaussian_rhs(n, 6)
+    sigma = np.array([0.01, 0.5])
+    op = _op(dict(rowptr=rowptr, col=col, vals=vals, n=n), cuda)
+    op.set_shifts(sigma)
+    with pytest.raises(MscError):
+        op.solve(b, format="sell")
+    x, info = op.solve(b, tol=1e-12, format="auto")
+    xd = O.dense_solve("mhm", rowptr, col, vals, n, b, sigma)
+    assert np.all(_rel(x.cpu().numpy(), xd) <= 1e-9)
+    op.close()
+
+
+def test_kernel_timing_samples(c0, cuda):
+    # timing attaches start/stop events to sampled K1/K2/K3 dispatches
+    op = _op(c0, cuda)
+    op.set_shifts(c0["sigma"])
+    x, info = op.solve(c0["b"], tol=1e-10, timing=4)
+    assert info["status"] == "ok"
+    assert info["kernel_samples"] > 0
+    assert np.all(info["kernel_ms"] > 0)
     op.close()
 
 
