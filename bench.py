@@ -31,6 +31,35 @@ WORKLOAD_NAMES = {
 }
 
 
+# HBM traffic per launch comes from rocprofv3 counter runs of this same script
+# (FETCH_SIZE and WRITE_SIZE, KiB per dispatch, scaled by the calibration against a copy
+# kernel of known size); it is reported only while the kernel sources are unchanged since.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+KERNEL_NAMES = {("mixed", "K1"): "k1_sell<float, true>", ("mixed", "K2"): "k2_sell<float>",
+                ("mixed", "K3"): "k3_update<float>", ("fp64", "K1"): "k1_sell<double, true>",
+                ("fp64", "K2"): "k2_sell<double>", ("fp64", "K3"): "k3_update<double>"}
+
+
+def measured_traffic(workload, prec, kernel):
+    """(bytes per launch, kernel name) from the committed counter summary, or (None, name)."""
+    import hashlib
+    name = KERNEL_NAMES.get((prec, kernel))
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            data = json.load(fh)
+        h = hashlib.sha256()
+        for rel in data["kernel_sources"]:
+            with open(os.path.join(ROOT, rel), "rb") as fh:
+                h.update(fh.read())
+        if h.hexdigest() != data["kernel_source_sha256"]:
+            return None, name
+        ent = data["workloads"][workload][name]
+        return 1024.0 * (ent["fetch_kib"] * data["fetch_scale"]
+                         + ent["write_kib"] * data["write_scale"]), name
+    except (OSError, KeyError, ValueError):
+        return None, name
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -165,8 +194,12 @@ def main():
     if kernels:
         dom = max(kernels, key=lambda nm: kernels[nm]["avg_us"])
         ach = kernels[dom]["gbs"]
+        traffic, kname = measured_traffic(args.workload, main_path["prec"], dom)
         roofline = {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                    "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": None, "kernel": dom,
+                    "frac": round(ach / PEAK_HBM_GBS, 4),
+                    "traffic": None if traffic is None else round(traffic),
+                    "kernel": dom, "kernel_name": kname,
+                    "alg_bytes": kernels[dom]["alg_bytes"],
                     "kernel_avg_us": kernels[dom]["avg_us"]}
     ns = prob["sigma"].size
     n, nnz = prob["n"], prob["vals"].size
