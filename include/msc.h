@@ -75,7 +75,7 @@ typedef struct {
     int32_t refine;          /* mixed: refine shifts above tol after the sequence   (1)    */
     int32_t poll_every;      /* iterations queued between host convergence polls    (16)   */
     double switch_tol;       /* mixed: the sequence runs in FP64 until the driving
-                                residual reaches switch_tol |b|, then in complex64 (1e-5) */
+                                residual reaches switch_tol |b|, then in complex64 (3e-5) */
     int32_t refine_max_iter; /* iteration limit of each refinement system          (10000) */
     int32_t lanes;           /* lanes per CSR row, 0 = automatic                    (0)    */
     int32_t verify;          /* compute FP64 true residuals at the end              (1)    */
@@ -84,7 +84,9 @@ typedef struct {
     int32_t max_grid;        /* cap on workgroups per iteration kernel (<= 2048),
                                 0 = automatic                                       (0)    */
     int32_t format;          /* msc_format: matrix copy the iteration SpMVs read     (0)    */
-    int32_t reserved[2];
+    double mixed_margin;     /* mixed: the sequence runs until its recursive residuals
+                                reach mixed_margin * tol (0 < margin <= 1), so that the
+                                complex64 drift leaves few shifts above tol     (0.7)  */
 } msc_params;
 
 /* Per-solve report.  Array members are caller-owned host arrays of length ns (or

@@ -43,7 +43,7 @@ class Params(ctypes.Structure):
         ("timing", ctypes.c_int32),
         ("max_grid", ctypes.c_int32),
         ("format", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 2),
+        ("mixed_margin", ctypes.c_double),
     ]
 
 

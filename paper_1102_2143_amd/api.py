@@ -34,8 +34,8 @@ def _ptr(t: torch.Tensor):
 
 
 def make_params(tol=1e-10, prec="fp64", max_iter=10000, reliable_every=50, freeze=True,
-                refine=True, poll_every=16, switch_tol=1e-5, refine_max_iter=10000, lanes=0,
-                verify=True, timing=0, max_grid=0, format="auto") -> L.Params:
+                refine=True, poll_every=16, switch_tol=None, refine_max_iter=10000, lanes=0,
+                verify=True, timing=0, max_grid=0, format="auto", mixed_margin=None) -> L.Params:
     lib = L.load()
     p = L.Params()
     lib.msc_params_default(ctypes.byref(p))
@@ -46,13 +46,16 @@ def make_params(tol=1e-10, prec="fp64", max_iter=10000, reliable_every=50, freez
     p.freeze = int(bool(freeze))
     p.refine = int(bool(refine))
     p.poll_every = int(poll_every)
-    p.switch_tol = float(switch_tol)
+    if switch_tol is not None:
+        p.switch_tol = float(switch_tol)
     p.refine_max_iter = int(refine_max_iter)
     p.lanes = int(lanes)
     p.verify = int(bool(verify))
     p.timing = int(timing)
     p.max_grid = int(max_grid)
     p.format = _FORMAT[format] if isinstance(format, str) else int(format)
+    if mixed_margin is not None:
+        p.mixed_margin = float(mixed_margin)
     return p
 
 

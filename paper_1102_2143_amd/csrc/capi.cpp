@@ -545,7 +545,7 @@ msc_status solve_impl(msc_op op, const double* d_b, double* d_x, const msc_param
   double bytes = 0.0;
   double bnorm = 0.0;
   const bool refine = prm.refine && prm.verify;
-  const double tol_stop = prm.tol;
+  const double tol_stop = prm.prec == MSC_PREC_MIXED ? prm.tol * prm.mixed_margin : prm.tol;
   msc_status rc = run_multishift(op, d_b, d_x, prm, info, s, tol_stop, prm.prec, &rel, &iters,
                                  &status, &bytes, &bnorm);
   if (rc != MSC_OK) return rc;
@@ -748,7 +748,8 @@ struct BatchRun {
         h.orig[k] = order[k];
       }
       for (int q = 0; q < kBatchMaxRhs; ++q) {
-        h.eps2[q] = prm.tol * prm.tol;
+        const double ts = prm.prec == MSC_PREC_MIXED ? prm.tol * prm.mixed_margin : prm.tol;
+        h.eps2[q] = ts * ts;
         h.sw_eps2[q] = sw * sw;
         h.a_prev[q] = 1.0;
         h.b[q] = 0.0;
@@ -1023,10 +1024,11 @@ void msc_params_default(msc_params* p) {
   p->freeze = 1;
   p->refine = 1;
   p->poll_every = 16;
-  p->switch_tol = 1e-5;
+  p->switch_tol = 3e-5;
   p->refine_max_iter = 10000;
   p->lanes = 0;
   p->verify = 1;
+  p->mixed_margin = 0.7;
 }
 
 const char* msc_version(void) { return "msc 0.1 (gfx950)"; }
@@ -1221,8 +1223,9 @@ msc_status msc_solve(msc_op op, const double* d_b, double* d_x, const msc_params
     prm = *params;
   else
     msc_params_default(&prm);
-  if (!(prm.tol >= 0.0) || (prm.prec != MSC_PREC_FP64 && prm.prec != MSC_PREC_MIXED)) {
-    set_error("msc_solve: invalid tol or precision");
+  if (!(prm.tol >= 0.0) || (prm.prec != MSC_PREC_FP64 && prm.prec != MSC_PREC_MIXED) ||
+      !(prm.mixed_margin > 0.0 && prm.mixed_margin <= 1.0)) {
+    set_error("msc_solve: invalid tol, precision or mixed_margin");
     return MSC_EINVAL;
   }
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -1250,8 +1253,9 @@ msc_status msc_solve_adjoint(msc_op op, const double* d_g, const double* d_x, do
     prm = *params;
   else
     msc_params_default(&prm);
-  if (!(prm.tol >= 0.0) || (prm.prec != MSC_PREC_FP64 && prm.prec != MSC_PREC_MIXED)) {
-    set_error("msc_solve_adjoint: invalid tol or precision");
+  if (!(prm.tol >= 0.0) || (prm.prec != MSC_PREC_FP64 && prm.prec != MSC_PREC_MIXED) ||
+      !(prm.mixed_margin > 0.0 && prm.mixed_margin <= 1.0)) {
+    set_error("msc_solve_adjoint: invalid tol, precision or mixed_margin");
     return MSC_EINVAL;
   }
   prm.verify = 1;
@@ -1403,8 +1407,9 @@ msc_status msc_solve_batched(int32_t nsys, const msc_op* ops, const int32_t* nrh
     prm = *params;
   else
     msc_params_default(&prm);
-  if (!(prm.tol >= 0.0) || (prm.prec != MSC_PREC_FP64 && prm.prec != MSC_PREC_MIXED)) {
-    set_error("msc_solve_batched: invalid tol or precision");
+  if (!(prm.tol >= 0.0) || (prm.prec != MSC_PREC_FP64 && prm.prec != MSC_PREC_MIXED) ||
+      !(prm.mixed_margin > 0.0 && prm.mixed_margin <= 1.0)) {
+    set_error("msc_solve_batched: invalid tol, precision or mixed_margin");
     return MSC_EINVAL;
   }
   int rr = 1, max_nrhs = 0;

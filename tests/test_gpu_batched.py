@@ -47,7 +47,9 @@ def test_small_batch_matches_oracle(cuda, prec):
         ap = O.shifted_apply(p["kind"], p["rowptr"], p["col"], p["vals"], p["n"])
         bs = np.atleast_2d(p["b"])
         for q in range(bs.shape[0]):
-            ref = O.cg_m(ap, bs[q], p["sigma"], tol=1e-10)
+            # the mixed sequence runs to mixed_margin * tol (default 0.7): its Krylov path
+            # is compared with the oracle's at that tolerance
+            ref = O.cg_m(ap, bs[q], p["sigma"], tol=1e-10 * (0.7 if prec == "mixed" else 1.0))
             xg = xs[s][q].cpu().numpy()
             info = infos[t]
             t += 1

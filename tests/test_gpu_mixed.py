@@ -58,7 +58,7 @@ def test_mixed_switches_precision_and_keeps_shifts_close(c0, cuda):
     op = _op(c0, cuda)
     op.set_shifts(c0["sigma"])
     x, info = op.solve(c0["b"], tol=1e-10, prec="mixed", refine=False, reliable_every=25,
-                       switch_tol=1e-5)
+                       switch_tol=1e-5, mixed_margin=1.0)
     k0 = int(np.argmin(c0["sigma"]))
     assert 0 < info["iters_fp64"] < info["iters"]
     assert info["true_rel_res"][k0] <= 1.5e-10
@@ -69,6 +69,25 @@ def test_mixed_switches_precision_and_keeps_shifts_close(c0, cuda):
     # the FP64 path is held to +-2 (test_gpu_multishift)
     ref = O.cg_m(c0["apply"], c0["b"], c0["sigma"], tol=1e-10)
     assert abs(info["iters"] - ref["iters"]) <= max(2, int(0.03 * ref["iters"]))
+    op.close()
+
+
+def test_mixed_margin_trades_iterations_for_residual(c0, cuda):
+    # a sequence driven to margin * tol leaves smaller true residuals for a few more
+    # iterations; margins outside (0, 1] are rejected
+    from paper_1102_2143_amd import MscError
+    op = _op(c0, cuda)
+    op.set_shifts(c0["sigma"])
+    _, i1 = op.solve(c0["b"], tol=1e-10, prec="mixed", refine=False, mixed_margin=1.0,
+                     switch_tol=1e-3)
+    _, i5 = op.solve(c0["b"], tol=1e-10, prec="mixed", refine=False, mixed_margin=0.5,
+                     switch_tol=1e-3)
+    assert i5["iters"] >= i1["iters"]
+    assert i5["true_rel_res"].max() < i1["true_rel_res"].max()
+    assert i5["true_rel_res"][int(np.argmin(c0["sigma"]))] <= 0.75e-10
+    for bad in (0.0, 1.5):
+        with pytest.raises(MscError):
+            op.solve(c0["b"], prec="mixed", mixed_margin=bad)
     op.close()
 
 

@@ -254,7 +254,9 @@ def test_c0_both_formats_match_oracle(c0, cuda, fmt, prec):
         assert abs(info["iters"] - ref["iters"]) <= 2
         assert np.all(_rel(x.cpu().numpy(), ref["x"]) <= 1e-8)
     else:
-        assert info["iters"] <= 1.03 * ref["iters"] + 2
+        # the mixed sequence runs to 0.7 tol (default mixed_margin)
+        ref7 = O.cg_m(c0["apply"], c0["b"], c0["sigma"], tol=0.7e-10)
+        assert info["iters"] <= 1.03 * ref7["iters"] + 2
     assert np.all(info["true_rel_res"] <= 1e-10)
     op.close()
 

@@ -41,7 +41,7 @@ def test_params_default_and_struct_layout():
     lib.msc_params_default(ctypes.byref(p))
     assert p.tol == 1e-10 and p.max_iter == 10000 and p.reliable_every == 50
     assert p.poll_every == 16 and p.verify == 1
-    assert ctypes.sizeof(_lib.Params) == 72  # int32 max_grid took one reserved slot
+    assert ctypes.sizeof(_lib.Params) == 72  # max_grid, format and mixed_margin took the reserved slots
     assert ctypes.sizeof(_lib.Info) == 80
 
 
