@@ -237,18 +237,19 @@ msc_status run_multishift(msc_op op, const double* d_b, double* d_x, const msc_p
   h.freeze = prm.freeze ? 1 : 0;
   for (int j = 0; j < ns; ++j) {
     h.s[j] = op->sigma[order[j]] - h.sigma0;
-    h.zeta[j] = 1.0;
+    h.rot[0].zeta[j] = 1.0;
     h.zeta_prev[j] = 1.0;
-    h.active[j] = 1;
+    h.rot[0].active[j] = 1;
     h.freeze_iter[j] = -1;
     h.orig[j] = order[j];
   }
   HIP_TRY(hipMemcpyAsync(op->ws.st, &h, sizeof h, hipMemcpyHostToDevice, s));
+  a64.par = a32.par = 0;
   HIP_TRY(launch_init(MSC_PREC_FP64, a64, s));
 
   const int G = std::max(1, prm.poll_every);
   int phase = MSC_PREC_FP64;
-  const MsArgs* cur = &a64;
+  MsArgs* cur = &a64;
   int launched = 0, chunk = 0, launched_at_switch = -1, iter_at_switch = -1;
   bool done = prm.max_iter <= 0;
   EventPool pool;
@@ -265,15 +266,19 @@ msc_status run_multishift(msc_op op, const double* d_b, double* d_x, const msc_p
         }
         sample_launch.push_back(launched);
       }
+      // iteration `launched` reads the state rot[launched & 1] and writes the other one
+      cur->par = launched & 1;
       HIP_TRY(launch_iteration(phase, *cur, s, ev));
       ++launched;
+      cur->par = launched & 1;
       if (phase == MSC_PREC_MIXED && prm.reliable_every > 0 &&
           (launched - launched_at_switch) % prm.reliable_every == 0)
         HIP_TRY(launch_reliable(MSC_PREC_MIXED, *cur, s));
     }
     const int slot = chunk & 1;
-    HIP_TRY(hipMemcpyAsync(&op->ws.h_halt[2 * slot], &op->ws.st->halt, 2 * sizeof(int),
-                           hipMemcpyDeviceToHost, s));
+    // halt and switch_req of the state the next iteration would start from
+    HIP_TRY(hipMemcpyAsync(&op->ws.h_halt[2 * slot], &op->ws.st->rot[launched & 1].halt,
+                           2 * sizeof(int), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipEventRecord(op->ws.ev[slot], s));
     ++chunk;
     if (chunk >= 2) {
@@ -282,7 +287,9 @@ msc_status run_multishift(msc_op op, const double* d_b, double* d_x, const msc_p
         if (op->ws.h_halt[2 * (slot ^ 1) + 1] && phase == MSC_PREC_FP64 && mixed) {
           // end of the FP64 phase: drain, convert the Krylov vectors, continue in complex64
           HIP_TRY(hipStreamSynchronize(s));
-          HIP_TRY(hipMemcpy(&iter_at_switch, &op->ws.st->iter, sizeof(int), hipMemcpyDeviceToHost));
+          HIP_TRY(hipMemcpy(&iter_at_switch, &op->ws.st->rot[launched & 1].iter, sizeof(int),
+                            hipMemcpyDeviceToHost));
+          a64.par = a32.par = launched & 1;
           HIP_TRY(launch_switch_to_mixed(a64, a32, ns, s));
           phase = MSC_PREC_MIXED;
           cur = &a32;
@@ -297,13 +304,14 @@ msc_status run_multishift(msc_op op, const double* d_b, double* d_x, const msc_p
   }
   HIP_TRY(hipStreamSynchronize(s));
   HIP_TRY(hipMemcpy(&h, op->ws.st, sizeof h, hipMemcpyDeviceToHost));
-  const int iters_fp64 = iter_at_switch >= 0 ? iter_at_switch : h.iter;
+  const RotState& fin = h.rot[launched & 1];  // state after the last launched iteration
+  const int iters_fp64 = iter_at_switch >= 0 ? iter_at_switch : fin.iter;
   if (info) {
     for (double& v : info->kernel_ms) v = 0.0;
     info->kernel_samples = 0;
     // only iterations that did work are counted (the loop runs a little past the halt)
     const int first = launched_at_switch >= 0 ? launched_at_switch : 0;
-    const int useful_launches = first + (h.iter - (iter_at_switch >= 0 ? iter_at_switch : 0));
+    const int useful_launches = first + (fin.iter - (iter_at_switch >= 0 ? iter_at_switch : 0));
     for (size_t q = 0; q < pool.groups.size(); ++q) {
       if (sample_launch[q] >= useful_launches) continue;
       for (int k = 0; k < 3; ++k) {
@@ -319,32 +327,32 @@ msc_status run_multishift(msc_op op, const double* d_b, double* d_x, const msc_p
   if (info && info->freeze_iter) {
     for (int j = 0; j < ns; ++j) {
       int fi = h.freeze_iter[j];
-      if (j == 0 || (fi < 0 && h.s[j] == 0.0)) fi = (h.R <= h.eps2) ? h.iter : -1;
+      if (j == 0 || (fi < 0 && h.s[j] == 0.0)) fi = (fin.R <= h.eps2) ? fin.iter : -1;
       info->freeze_iter[order[j]] = fi;
     }
   }
-  *iters_out = h.iter;
-  *status_out = h.status;
+  *iters_out = fin.iter;
+  *status_out = fin.status;
   if (info) info->n_reliable = h.n_reliable;
 
   // active-shift count summed over iterations, for the byte model: shift j (>= 1) was
   // updated in iterations 1..freeze_iter (or all); split at the precision switch
   double act64 = 0.0, act32 = 0.0;
   for (int j = 1; j < ns; ++j) {
-    const int last = (h.freeze_iter[j] >= 0) ? h.freeze_iter[j] : h.iter;
+    const int last = (h.freeze_iter[j] >= 0) ? h.freeze_iter[j] : fin.iter;
     act64 += std::min(last, iters_fp64);
     act32 += std::max(0, last - iters_fp64);
   }
   const double nn = double(op->n), nz = double(op->nnz), nzh = double(op->nnz_h);
   *bytes_out = iter_bytes(op->kind, MSC_PREC_FP64, nn, nz, nzh, act64, double(iters_fp64)) +
-               iter_bytes(op->kind, MSC_PREC_MIXED, nn, nz, nzh, act32, double(h.iter - iters_fp64)) +
+               iter_bytes(op->kind, MSC_PREC_MIXED, nn, nz, nzh, act32, double(fin.iter - iters_fp64)) +
                double(h.n_reliable) * ((op->kind == MSC_A_MHM ? 2.0 : 1.0) * (nz * 20.0 + 4.0 * (nn + 1)) +
                                        nn * (16.0 * 3 + 8.0));
   if (info) info->iters_fp64 = iters_fp64;
 
   rel_out->assign(ns, 0.0);
   *bnorm_out = std::sqrt(h.bnorm2);
-  if (prm.verify && h.status == 0) {
+  if (prm.verify && fin.status == 0) {
     const double bn = std::sqrt(h.bnorm2);
     for (int k0 = 0; k0 < ns; k0 += 8) {
       const int kc = std::min(8, ns - k0);

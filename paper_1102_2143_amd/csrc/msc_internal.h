@@ -18,44 +18,47 @@ constexpr int kMaxGrid = 2048;       // 256 CUs x 8 resident workgroups
 constexpr int kTicketStride = 32;
 constexpr int kTicketSite = 9 * kTicketStride;
 
-// Scalar state of one multishift solve, resident in device memory.  Written only by
-// the last-arriving workgroup of a kernel (or by the init kernel), read by the next
-// kernels in stream order.  Shift index j runs over the shifts sorted ascending; j = 0
-// is the driving shift sigma0.
+// Scalar state of one multishift solve, resident in device memory.  Shift index j runs
+// over the shifts sorted ascending; j = 0 is the driving shift sigma0.
+//
+// No kernel of an iteration waits for its own reduction: each workgroup stores a partial
+// sum and the workgroups of the next kernel add the partials up themselves, in one fixed
+// order, so they all obtain the same value.  Workgroup 0 of K2 then stores the step
+// constants of the iteration for K3, and workgroup 0 of K3 stores the state of the next
+// iteration.  What every workgroup of K3 reads while its workgroup 0 writes the next
+// values is kept twice (RotState), indexed by the parity of the iteration.
+struct RotState {
+  double R;                    // |r|^2 of the driving recursive residual
+  int iter;                    // iterations completed
+  int halt;                    // 1: the kernels of this iteration do no work
+  int switch_req;              // 1: halted because the FP64 phase of a mixed solve ended
+  int status;                  // 0 running/ok, 1 breakdown
+  double zeta[kMaxShifts];     // zeta_j^(n)
+  int active[kMaxShifts];      // shift j still updated
+};
+
 struct SolveState {
-  double R;          // |r|^2 of the driving recursive residual
-  double a;          // current step a_n = R / (p^H (A + sigma0) p)
-  double a_prev;     // previous step (1 before the first iteration)
-  double b;          // direction coefficient b_n of the last p update (0 at start)
-  double b_new;      // b_{n+1}, used by the update kernel of this iteration
-  double P;          // p^H (A + sigma0) p
+  double a;          // a_n = R / (p^H (A + sigma0) p)      (K2, workgroup 0)
+  double a_prev;     // a_{n-1} (1 before the first iteration)
+  double b;          // b_{n-1}, last direction coefficient (0 at start)
+  double P;          // p^H (A + sigma0) p                  (K2, workgroup 0)
   double sigma0;
   double bnorm2;
-  double eps2;       // tol^2 |b|^2
+  double eps2;       // (mixed_margin) tol^2 |b|^2
   double sw_eps2;    // switch_tol^2 |b|^2: end of the FP64 phase of a mixed solve (0: none)
-  int halt;          // 1: no further iteration kernels do work
-  int switch_req;    // 1: the FP64 phase ended at sw_eps2 (halt is also set)
-  int iter;
   int max_iter;
-  int k3_enable;     // 1: the update kernel of this iteration must run
-  int status;        // 0 running/ok, 1 breakdown
   int ns;
-  int nact;          // number of entries in act_list for this iteration's update
   int freeze;
   int n_reliable;
+  int kstatus;       // 1: K2 of the current iteration found p^H (A + sigma0) p <= 0
   int pad_;
-  unsigned ticket[4];
   double s[kMaxShifts];         // sigma_j - sigma0
-  double zeta[kMaxShifts];      // zeta_j^(n)
   double zeta_prev[kMaxShifts]; // zeta_j^(n-1)
-  double zk[kMaxShifts];        // zeta_j^(n+1) (this iteration)
-  double ak[kMaxShifts];        // a_j^(n) = a_n zeta^(n+1)/zeta^(n)
-  double bk[kMaxShifts];        // b_j^(n+1) = b_{n+1} (zeta^(n+1)/zeta^(n))^2
-  int active[kMaxShifts];
+  double zk[kMaxShifts];        // zeta_j^(n+1) of the current iteration (K2 -> K3)
+  double ak[kMaxShifts];        // a_j^(n) = a_n zeta^(n+1)/zeta^(n)          (K2 -> K3)
   int freeze_iter[kMaxShifts];
   int orig[kMaxShifts];         // caller's index of sorted shift j
-  int act_list[kMaxShifts];     // shifts j >= 1 updated by this iteration's kernel
-  int act_upd_p[kMaxShifts];    // 0 when that shift froze this iteration (skip p_j)
+  RotState rot[2];              // rot[par]: state at the start of an iteration of parity par
 };
 
 // Per-kernel partial-sum scratch, sized for kMaxGrid workgroups x kMaxShifts values.
@@ -194,6 +197,8 @@ struct MsArgs {
   int grid;
   Csr<double2> m64, mh64;
   Csr<float2> m32, mh32;
+  int par;               // parity of the iteration: its state is st->rot[par]
+  int gk1, gk2;          // workgroups of this iteration's K1 and K2 (partials to sum)
   int sell;              // K1/K2 read the sliced ELLPACK copies below
   int64_t nslices;
   Sell<double2> s64, sh64;
@@ -304,10 +309,6 @@ struct BatchSys {
   int64_t n;
   Csr<double2> m64, mh64;
   Csr<float2> m32, mh32;
-  int sell;              // K1/K2 read the sliced ELLPACK copies below
-  int64_t nslices;
-  Sell<double2> s64, sh64;
-  Sell<float2> s32, sh32;
   const double2* b;       // nrhs * n (rhs-major)
   double2* x;             // nrhs * ns * n (rhs-major, shift-major, caller order)
   double2 *r64, *p64, *t64, *pk64, *u64;   // rhs-interleaved n x RR; pk: (ns-1) blocks

@@ -240,170 +240,168 @@ __device__ __forceinline__ double sum_partials(const double* partial, int count,
   return block_sum<kBlock>(s);
 }
 
-// The last workgroup loads the state it needs (wave 0, lane = shift) before summing the
-// partials, so the two round trips overlap.
-struct K1Pre {
-  double R, ap, b, z, zp, s;
-  int ns, act;
-};
-
-__device__ __forceinline__ K1Pre prefetch_k1(const SolveState* st) {
-  K1Pre q{};
-  const int j = threadIdx.x;
-  if (j < kWave) {
-    q.R = st->R;
-    q.ap = st->a_prev;
-    q.b = st->b;
-    q.ns = st->ns;
-    if (j < q.ns) {
-      q.z = st->zeta[j];
-      q.zp = st->zeta_prev[j];
-      q.s = st->s[j];
-      q.act = st->active[j];
-    }
-  }
-  return q;
+// ---- the iteration's reductions ------------------------------------------------------
+// K1 stores one partial of P per workgroup in region 0, K2 one partial of R' in region 1;
+// the workgroups of the next kernel each add all of them up in the same order.
+__device__ __forceinline__ double* region(const MsArgs& a, int k) {
+  return a.sc.partial + k * kMaxGrid;
 }
 
-// ---- finalisation of K1: a and the per-shift zeta', a_j (wave 0, lane = shift) ----
-__device__ void finalize_k1(SolveState* st, double P, const K1Pre& q) {
-  const int j = threadIdx.x;
-  if (j >= kWave) return;
+__device__ __forceinline__ void store_partial(double* reg, double acc) {
+  const double tot = block_sum<kBlock>(acc);
+  if (threadIdx.x == 0) store_agent(&reg[blockIdx.x], tot);
+}
+
+// Sum of `count` partials, identical in every thread of every workgroup that calls it.
+__device__ __forceinline__ double all_sum(const double* reg, int count) {
+  __shared__ double total;
+  const double v = sum_partials(reg, count, 1, 0);
+  if (threadIdx.x == 0) total = v;
+  __syncthreads();
+  return total;
+}
+
+// K2 prologue: a = R / P.  Workgroup 0 also stores a, P and, for every active shift j
+// (wave 0, lane j), zeta_j^(n+1) = zeta zeta_- a_- / (a b (zeta_- - zeta) + zeta_- a_-
+// (1 + s_j a)) and a_j = a zeta_j^(n+1) / zeta_j for K3; a breakdown (P <= 0 or not
+// finite) is flagged for K3 instead.  Returns false on breakdown.
+__device__ bool k2_step(const MsArgs& a, double& step) {
+  SolveState* st = a.st;
+  const RotState& rs = st->rot[a.par];
+  const double P = all_sum(region(a, 0), a.gk1);
   const bool ok = (P > 0.0) && isfinite(P);
-  if (!ok) {
-    if (j == 0) {
-      st->P = P;
-      st->status = 1;
-      st->halt = 1;
-      st->k3_enable = 0;
+  step = ok ? rs.R / P : 0.0;
+  if (blockIdx.x == 0 && threadIdx.x < kWave) {
+    const int j = threadIdx.x;
+    if (!ok) {
+      if (j == 0) {
+        st->P = P;
+        st->kstatus = 1;
+      }
+    } else {
+      if (j >= 1 && j < st->ns && rs.active[j]) {
+        const double z = rs.zeta[j], zp = st->zeta_prev[j], ap = st->a_prev, b = st->b;
+        const double zn = z * zp * ap / (step * b * (zp - z) + zp * ap * (1.0 + st->s[j] * step));
+        st->zk[j] = zn;
+        st->ak[j] = step * zn / z;
+      }
+      if (j == 0) {
+        st->P = P;
+        st->a = step;
+      }
     }
-    return;
   }
-  const double a = q.R / P;
-  if (j >= 1 && j < q.ns && q.act) {
-    const double zn = q.z * q.zp * q.ap / (a * q.b * (q.zp - q.z) + q.zp * q.ap * (1.0 + q.s * a));
-    st->zk[j] = zn;
-    st->ak[j] = a * zn / q.z;
-  }
-  if (j == 0) {
-    st->P = P;
-    st->a = a;
-  }
+  return ok;
 }
 
-struct K2Pre {
-  double R, a, eps2, sw_eps2, z, zn;
-  int ns, iter, max_iter, freeze, act;
+// K3 prologue, shared through LDS: R' and b = R'/R, and per shift j the coefficients of
+// its update, whether it freezes now (zeta_j^(n+1)^2 R' <= eps2), and the list of shifts
+// this iteration updates.
+struct K3Plan {
+  double bn;
+  double bk[kMaxShifts];
+  double zk[kMaxShifts];
+  double ak[kMaxShifts];
+  int list[kMaxShifts];
+  int upd_p[kMaxShifts];
+  int nact;
+  int ok;
 };
 
-__device__ __forceinline__ K2Pre prefetch_k2(const SolveState* st) {
-  K2Pre q{};
-  const int j = threadIdx.x;
-  if (j < kWave) {
-    q.R = st->R;
-    q.a = st->a;
-    q.eps2 = st->eps2;
-    q.sw_eps2 = st->sw_eps2;
-    q.ns = st->ns;
-    q.iter = st->iter;
-    q.max_iter = st->max_iter;
-    q.freeze = st->freeze;
-    if (j < q.ns) {
-      q.act = st->active[j];
-      q.z = st->zeta[j];
-      q.zn = st->zk[j];
+__device__ void k3_plan(const MsArgs& a, K3Plan& pl) {
+  SolveState* st = a.st;
+  const RotState& rs = st->rot[a.par];
+  const double Rn = all_sum(region(a, 1), a.gk2);
+  if (threadIdx.x < kWave) {
+    const int j = threadIdx.x;
+    const bool ok = isfinite(Rn) && st->kstatus == 0;
+    const double bn = Rn / rs.R;
+    const bool act = ok && j >= 1 && j < st->ns && rs.active[j];
+    bool freeze_now = false;
+    double zn = 0.0;
+    if (act) {
+      zn = st->zk[j];
+      const double ratio = zn / rs.zeta[j];
+      pl.bk[j] = bn * ratio * ratio;
+      pl.zk[j] = zn;
+      pl.ak[j] = st->ak[j];
+      freeze_now = st->freeze && zn * zn * Rn <= st->eps2;
+    }
+    const uint64_t mask = __ballot(act);
+    if (act) {
+      const int pos = __popcll(mask & ((uint64_t(1) << j) - 1));
+      pl.list[pos] = j;
+      pl.upd_p[pos] = freeze_now ? 0 : 1;
+    }
+    if (j == 0) {
+      pl.bn = bn;
+      pl.nact = __popcll(mask);
+      pl.ok = ok ? 1 : 0;
+    }
+    // workgroup 0 writes the state of the next iteration (other workgroups read only
+    // rot[par] and what K2 stored)
+    if (blockIdx.x == 0) {
+      RotState& nx = st->rot[a.par ^ 1];
+      const int it = rs.iter + 1;
+      if (j < st->ns) {
+        nx.zeta[j] = act ? zn : rs.zeta[j];
+        nx.active[j] = act ? (freeze_now ? 0 : 1) : rs.active[j];
+      }
+      if (act) {
+        st->zeta_prev[j] = rs.zeta[j];
+        if (freeze_now) st->freeze_iter[j] = it;
+      }
+      if (j == 0) {
+        if (!ok) {
+          nx.R = rs.R;
+          nx.iter = rs.iter;
+          nx.halt = 1;
+          nx.switch_req = 0;
+          nx.status = 1;
+        } else {
+          nx.R = Rn;
+          nx.iter = it;
+          nx.status = 0;
+          st->b = bn;
+          st->a_prev = st->a;
+          const bool done = Rn <= st->eps2 || it >= st->max_iter;
+          // the FP64 phase of a mixed solve ends here: this iteration's update still runs,
+          // then the host converts the Krylov vectors to complex64 and continues
+          const bool sw = !done && Rn <= st->sw_eps2;
+          nx.halt = (done || sw) ? 1 : 0;
+          nx.switch_req = sw ? 1 : 0;
+        }
+      }
     }
   }
-  return q;
+  __syncthreads();
 }
 
-// ---- finalisation of K2: b, b_j, zeta rotation, freezing and halting -----------------
-__device__ void finalize_k2(SolveState* st, double Rn, const K2Pre& q) {
+// A halted iteration carries its state over to the next one (workgroup 0 of K3).
+__device__ void carry_state(const MsArgs& a) {
+  if (blockIdx.x != 0) return;
+  SolveState* st = a.st;
+  const RotState& rs = st->rot[a.par];
+  RotState& nx = st->rot[a.par ^ 1];
   const int j = threadIdx.x;
-  if (j >= kWave) return;
-  if (!isfinite(Rn)) {
-    if (j == 0) {
-      st->status = 1;
-      st->halt = 1;
-      st->k3_enable = 0;
-    }
-    return;
-  }
-  const double bn = Rn / q.R;
-  const int it = q.iter + 1;
-  bool was_active = false, keep_p = false;
-  if (j >= 1 && j < q.ns && q.act) {
-    was_active = true;
-    const double ratio = q.zn / q.z;
-    st->bk[j] = bn * ratio * ratio;
-    st->zeta_prev[j] = q.z;
-    st->zeta[j] = q.zn;
-    keep_p = true;
-    if (q.freeze && q.zn * q.zn * Rn <= q.eps2) {
-      st->active[j] = 0;
-      st->freeze_iter[j] = it;
-      keep_p = false;
-    }
-  }
-  const uint64_t mask = __ballot(was_active);
-  if (was_active) {
-    const int pos = __popcll(mask & ((uint64_t(1) << j) - 1));
-    st->act_list[pos] = j;
-    st->act_upd_p[pos] = keep_p ? 1 : 0;
+  if (j < kMaxShifts) {
+    nx.zeta[j] = rs.zeta[j];
+    nx.active[j] = rs.active[j];
   }
   if (j == 0) {
-    st->nact = __popcll(mask);
-    st->b_new = bn;
-    st->a_prev = q.a;
-    st->b = bn;
-    st->R = Rn;
-    st->iter = it;
-    if (Rn <= q.eps2 || it >= q.max_iter) {
-      st->halt = 1;
-    } else if (Rn <= q.sw_eps2) {
-      // end of the FP64 phase: this iteration's update still runs, then the host
-      // converts the Krylov vectors to complex64 and continues
-      st->halt = 1;
-      st->switch_req = 1;
-    }
-    st->k3_enable = 1;
+    nx.R = rs.R;
+    nx.iter = rs.iter;
+    nx.halt = 1;
+    nx.switch_req = rs.switch_req;
+    nx.status = rs.status;
   }
-}
-
-// Workgroup partial of P (K1) or R' (K2), the ticket, and the finalisation by the last
-// workgroup to arrive.
-__device__ __forceinline__ void finish_k1(const MsArgs& a, double acc) {
-  const double tot = block_sum<kBlock>(acc);
-  if (threadIdx.x == 0) store_agent(&a.sc.partial[blockIdx.x], tot);
-  if (!arrive_last(a.sc.tickets + 0 * kTicketSite)) return;
-  __shared__ double Psh;
-  const K1Pre pre = prefetch_k1(a.st);
-  const double P = sum_partials(a.sc.partial, gridDim.x, 1, 0);
-  if (threadIdx.x == 0) Psh = P;
-  __syncthreads();
-  finalize_k1(a.st, Psh, pre);
-}
-
-__device__ __forceinline__ void finish_k2(const MsArgs& a, double acc) {
-  const double tot = block_sum<kBlock>(acc);
-  if (threadIdx.x == 0) store_agent(&a.sc.partial[blockIdx.x], tot);
-  if (!arrive_last(a.sc.tickets + 1 * kTicketSite)) return;
-  __shared__ double Rsh;
-  const K2Pre pre = prefetch_k2(a.st);
-  const double Rn = sum_partials(a.sc.partial, gridDim.x, 1, 0);
-  if (threadIdx.x == 0) Rsh = Rn;
-  __syncthreads();
-  finalize_k2(a.st, Rsh, pre);
 }
 
 // ---- K1 -------------------------------------------------------------------------------
 template <class R, int L, bool MHM>
 __global__ __launch_bounds__(kBlock) void k1_apply(MsArgs a) {
-  SolveState* st = a.st;
-  if (st->halt) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) st->k3_enable = 0;
-    return;
-  }
+  const SolveState* st = a.st;
+  if (st->rot[a.par].halt) return;
   const Csr<cplx<R>> m = pick_m<R>(a);
   const cplx<R>* __restrict__ p = static_cast<const cplx<R>*>(a.p);
   cplx<R>* __restrict__ t = static_cast<cplx<R>*>(a.t);
@@ -431,20 +429,21 @@ __global__ __launch_bounds__(kBlock) void k1_apply(MsArgs a) {
       if (has1) epilogue(row1, v1);
     }
   }
-  finish_k1(a, acc);
+  store_partial(region(a, 0), acc);
 }
 
 // ---- K2 (A = M^H M): r <- r - a (M^H t + sigma0 p), R' = |r|^2 ------------------------
 template <class R, int L>
 __global__ __launch_bounds__(kBlock) void k2_mhm(MsArgs a) {
-  SolveState* st = a.st;
-  if (st->halt) return;
+  const SolveState* st = a.st;
+  if (st->rot[a.par].halt) return;
+  double step;
+  if (!k2_step(a, step)) return;  // breakdown: every workgroup sees the same P
   const Csr<cplx<R>> mh = pick_mh<R>(a);
   const cplx<R>* __restrict__ t = static_cast<const cplx<R>*>(a.t);
   const cplx<R>* __restrict__ p = static_cast<const cplx<R>*>(a.p);
   cplx<R>* __restrict__ r = static_cast<cplx<R>*>(a.r);
   const double sigma0 = st->sigma0;
-  const double step = st->a;
   constexpr int GPB = kBlock / L;
   const int lane = threadIdx.x % L, grp = threadIdx.x / L;
   int64_t beg, end;
@@ -471,17 +470,14 @@ __global__ __launch_bounds__(kBlock) void k2_mhm(MsArgs a) {
       if (has1) epilogue(row1, q1);
     }
   }
-  finish_k2(a, acc);
+  store_partial(region(a, 1), acc);
 }
 
 // ---- K1 and K2 on the sliced ELLPACK copies: one row per lane, one slice per wave ----
 template <class R, bool MHM>
 __global__ __launch_bounds__(kBlock) void k1_sell(MsArgs a) {
-  SolveState* st = a.st;
-  if (st->halt) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) st->k3_enable = 0;
-    return;
-  }
+  const SolveState* st = a.st;
+  if (st->rot[a.par].halt) return;
   const Sell<cplx<R>> m = pick_sm<R>(a);
   const cplx<R>* __restrict__ p = static_cast<const cplx<R>*>(a.p);
   cplx<R>* __restrict__ t = static_cast<cplx<R>*>(a.t);
@@ -508,19 +504,20 @@ __global__ __launch_bounds__(kBlock) void k1_sell(MsArgs a) {
         acc += double(pr.x) * double(v.x) + double(pr.y) * double(v.y) + sigma0 * norm2d<R>(pr);
     }
   }
-  finish_k1(a, acc);
+  store_partial(region(a, 0), acc);
 }
 
 template <class R>
 __global__ __launch_bounds__(kBlock) void k2_sell(MsArgs a) {
-  SolveState* st = a.st;
-  if (st->halt) return;
+  const SolveState* st = a.st;
+  if (st->rot[a.par].halt) return;
+  double step;
+  if (!k2_step(a, step)) return;  // breakdown: every workgroup sees the same P
   const Sell<cplx<R>> mh = pick_shm<R>(a);
   const cplx<R>* __restrict__ t = static_cast<const cplx<R>*>(a.t);
   const cplx<R>* __restrict__ p = static_cast<const cplx<R>*>(a.p);
   cplx<R>* __restrict__ r = static_cast<cplx<R>*>(a.r);
   const double sigma0 = st->sigma0;
-  const double step = st->a;
   constexpr int SPB = kBlock / kSlice;
   const int lane = threadIdx.x % kSlice;
   const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x / kSlice));
@@ -549,19 +546,20 @@ __global__ __launch_bounds__(kBlock) void k2_sell(MsArgs a) {
       acc += norm2d<R>(st_r);
     }
   }
-  finish_k2(a, acc);
+  store_partial(region(a, 1), acc);
 }
 
 // ---- K2 (A given): elementwise r <- r - a (t + sigma0 p) -------------------------------
 template <class R>
 __global__ __launch_bounds__(kBlock) void k2_herm(MsArgs a) {
-  SolveState* st = a.st;
-  if (st->halt) return;
+  const SolveState* st = a.st;
+  if (st->rot[a.par].halt) return;
+  double step;
+  if (!k2_step(a, step)) return;  // breakdown: every workgroup sees the same P
   const cplx<R>* __restrict__ t = static_cast<const cplx<R>*>(a.t);
   const cplx<R>* __restrict__ p = static_cast<const cplx<R>*>(a.p);
   cplx<R>* __restrict__ r = static_cast<cplx<R>*>(a.r);
   const double sigma0 = st->sigma0;
-  const double step = st->a;
   int64_t beg, end;
   block_range(a.n, kBlock, beg, end);
   double acc = 0.0;
@@ -574,21 +572,29 @@ __global__ __launch_bounds__(kBlock) void k2_herm(MsArgs a) {
     r[i] = st_r;
     acc += norm2d<R>(st_r);
   }
-  finish_k2(a, acc);
+  store_partial(region(a, 1), acc);
 }
 
 // ---- K3: fused update of every active shift from one read of r and p ------------------
+// x_0 += a p; for each active shift j: x_j += a_j p_j, p_j <- zeta_j^(n+1) r + b_j p_j
+// (skipped when j freezes now); p <- r + b p.
 template <class R>
 __global__ __launch_bounds__(kBlock) void k3_update(MsArgs a) {
   const SolveState* st = a.st;
-  if (!st->k3_enable) return;
+  if (st->rot[a.par].halt) {
+    carry_state(a);
+    return;
+  }
+  __shared__ K3Plan pl;
+  k3_plan(a, pl);
+  if (!pl.ok) return;
   const int64_t n = a.n;
   const cplx<R>* __restrict__ rv = static_cast<const cplx<R>*>(a.r);
   cplx<R>* __restrict__ pv = static_cast<cplx<R>*>(a.p);
   cplx<R>* __restrict__ pk = static_cast<cplx<R>*>(a.pk);
   double2* __restrict__ x = a.x;
-  const double step = st->a, bnew = st->b_new;
-  const int nact = st->nact;
+  const double step = st->a, bnew = pl.bn;
+  const int nact = pl.nact;
   double2* __restrict__ x0 = x + int64_t(st->orig[0]) * n;
   int64_t beg, end;
   block_range(n, kBlock, beg, end);
@@ -607,7 +613,7 @@ __global__ __launch_bounds__(kBlock) void k3_update(MsArgs a) {
       double2 xj[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        jj[u] = st->act_list[q + u];
+        jj[u] = pl.list[q + u];
         pj[u] = pk[int64_t(jj[u] - 1) * n + i];
         xj[u] = x[int64_t(st->orig[jj[u]]) * n + i];
       }
@@ -615,12 +621,12 @@ __global__ __launch_bounds__(kBlock) void k3_update(MsArgs a) {
       for (int u = 0; u < 4; ++u) {
         const int j = jj[u];
         const double2 pjd = to_d(pj[u]);
-        const double aj = st->ak[j];
+        const double aj = pl.ak[j];
         xj[u].x = fma(aj, pjd.x, xj[u].x);
         xj[u].y = fma(aj, pjd.y, xj[u].y);
         x[int64_t(st->orig[j]) * n + i] = xj[u];
-        if (st->act_upd_p[q + u]) {
-          const double zj = st->zk[j], bj = st->bk[j];
+        if (pl.upd_p[q + u]) {
+          const double zj = pl.zk[j], bj = pl.bk[j];
           double2 np;
           np.x = fma(zj, rd.x, bj * pjd.x);
           np.y = fma(zj, rd.y, bj * pjd.y);
@@ -629,16 +635,16 @@ __global__ __launch_bounds__(kBlock) void k3_update(MsArgs a) {
       }
     }
     for (; q < nact; ++q) {
-      const int j = st->act_list[q];
+      const int j = pl.list[q];
       const double2 pjd = to_d(pk[int64_t(j - 1) * n + i]);
       double2* xp = x + int64_t(st->orig[j]) * n + i;
       double2 xv2 = *xp;
-      const double aj = st->ak[j];
+      const double aj = pl.ak[j];
       xv2.x = fma(aj, pjd.x, xv2.x);
       xv2.y = fma(aj, pjd.y, xv2.y);
       *xp = xv2;
-      if (st->act_upd_p[q]) {
-        const double zj = st->zk[j], bj = st->bk[j];
+      if (pl.upd_p[q]) {
+        const double zj = pl.zk[j], bj = pl.bk[j];
         double2 np;
         np.x = fma(zj, rd.x, bj * pjd.x);
         np.y = fma(zj, rd.y, bj * pjd.y);
@@ -678,14 +684,14 @@ __global__ __launch_bounds__(kBlock) void k_init(MsArgs a) {
   if (!arrive_last(a.sc.tickets + 3 * kTicketSite)) return;
   const double B2 = sum_partials(a.sc.partial, gridDim.x, 1, 0);
   if (threadIdx.x == 0) {
+    RotState& r0 = st->rot[a.par];
     st->bnorm2 = B2;
-    st->R = B2;
+    r0.R = B2;
     st->eps2 = st->eps2 * B2;        // host stored tol^2 here
     st->sw_eps2 = st->sw_eps2 * B2;  // and switch_tol^2 (0 when there is no switch)
     if (!(B2 > 0.0) || !isfinite(B2)) {
-      st->halt = 1;
-      st->k3_enable = 0;
-      if (!isfinite(B2)) st->status = 1;
+      r0.halt = 1;
+      if (!isfinite(B2)) r0.status = 1;
     }
   }
 }
@@ -711,11 +717,11 @@ __global__ __launch_bounds__(kBlock) void k_switch(MsArgs a64, MsArgs a32, int n
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     SolveState* st = a64.st;
-    if (st->status == 0 && st->switch_req) {
-      st->halt = 0;
-      st->switch_req = 0;
+    RotState& rs = st->rot[a64.par];
+    if (rs.status == 0 && rs.switch_req) {
+      rs.halt = 0;
+      rs.switch_req = 0;
       st->sw_eps2 = 0.0;
-      st->k3_enable = 0;
     }
   }
 }
@@ -725,7 +731,7 @@ template <int L, bool MHM>
 __global__ __launch_bounds__(kBlock) void k_ru_first(MsArgs a) {
   // t64 = M x_0 (A = M^H M) -- first half of the FP64 operator
   const SolveState* st = a.st;
-  if (st->halt) return;
+  if (st->rot[a.par].halt) return;
   const double2* __restrict__ x0 = a.x + int64_t(st->orig[0]) * a.n;
   constexpr int GPB = kBlock / L;
   const int lane = threadIdx.x % L, grp = threadIdx.x / L;
@@ -740,7 +746,7 @@ __global__ __launch_bounds__(kBlock) void k_ru_first(MsArgs a) {
 template <class R, int L, bool MHM>
 __global__ __launch_bounds__(kBlock) void k_ru_second(MsArgs a) {
   SolveState* st = a.st;
-  if (st->halt) return;
+  if (st->rot[a.par].halt) return;
   const double2* __restrict__ x0 = a.x + int64_t(st->orig[0]) * a.n;
   cplx<R>* __restrict__ r = static_cast<cplx<R>*>(a.r);
   const double sigma0 = st->sigma0;
@@ -766,15 +772,14 @@ __global__ __launch_bounds__(kBlock) void k_ru_second(MsArgs a) {
   if (!arrive_last(a.sc.tickets + 2 * kTicketSite)) return;
   const double Rt = sum_partials(a.sc.partial, gridDim.x, 1, 0);
   if (threadIdx.x == 0) {
-    st->R = Rt;
+    RotState& rs = st->rot[a.par];
+    rs.R = Rt;
     st->n_reliable += 1;
     if (!isfinite(Rt)) {
-      st->status = 1;
-      st->halt = 1;
-      st->k3_enable = 0;
+      rs.status = 1;
+      rs.halt = 1;
     } else if (Rt <= st->eps2) {
-      st->halt = 1;
-      st->k3_enable = 0;
+      rs.halt = 1;
     }
   }
 }
@@ -931,9 +936,17 @@ void launch_timed(K kern, int grid, hipStream_t s, hipEvent_t* ev, int k, const 
 }
 
 template <class R>
-hipError_t iteration_impl(const MsArgs& a, hipStream_t s, hipEvent_t* ev) {
-  const int g1 = grid_rows(a.n, kBlock / a.lanes, a.grid);
-  const int g3 = grid_rows(a.n, kBlock, a.grid);
+hipError_t iteration_impl(const MsArgs& args, hipStream_t s, hipEvent_t* ev) {
+  const int g1 = grid_rows(args.n, kBlock / args.lanes, args.grid);
+  const int g3 = grid_rows(args.n, kBlock, args.grid);
+  MsArgs a = args;
+  // workgroups of K1 and K2, whose partials K2 and K3 add up
+  if (a.sell) {
+    a.gk1 = a.gk2 = g3;
+  } else {
+    a.gk1 = g1;
+    a.gk2 = a.kind == MSC_A_MHM ? g1 : g3;
+  }
   if (a.sell) {
     if (a.kind == MSC_A_MHM) {
       launch_timed(k1_sell<R, true>, g3, s, ev, 0, a);
