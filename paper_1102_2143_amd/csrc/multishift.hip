@@ -252,11 +252,30 @@ __device__ __forceinline__ void store_partial(double* reg, double acc) {
   if (threadIdx.x == 0) store_agent(&reg[blockIdx.x], tot);
 }
 
-// Sum of `count` partials, identical in every thread of every workgroup that calls it.
-__device__ __forceinline__ double all_sum(const double* reg, int count) {
+// Partials are loaded early (four per thread, covering grids of up to 1024 workgroups)
+// so their round trip overlaps the caller's own first loads; the sum is identical in
+// every thread of every workgroup that forms it.
+constexpr int kEarly = 4;
+struct Early {
+  double v[kEarly];
+};
+
+__device__ __forceinline__ void load_early(const double* reg, int count, Early& e) {
+#pragma unroll
+  for (int u = 0; u < kEarly; ++u) {
+    const int i = threadIdx.x + u * kBlock;
+    e.v[u] = i < count ? load_agent(&reg[i]) : 0.0;
+  }
+}
+
+__device__ __forceinline__ double all_sum(const double* reg, int count, const Early& e) {
   __shared__ double total;
-  const double v = sum_partials(reg, count, 1, 0);
-  if (threadIdx.x == 0) total = v;
+  double s = 0.0;
+#pragma unroll
+  for (int u = 0; u < kEarly; ++u) s += e.v[u];
+  for (int i = threadIdx.x + kEarly * kBlock; i < count; i += kBlock) s += load_agent(&reg[i]);
+  s = block_sum<kBlock>(s);
+  if (threadIdx.x == 0) total = s;
   __syncthreads();
   return total;
 }
@@ -265,23 +284,33 @@ __device__ __forceinline__ double all_sum(const double* reg, int count) {
 // (wave 0, lane j), zeta_j^(n+1) = zeta zeta_- a_- / (a b (zeta_- - zeta) + zeta_- a_-
 // (1 + s_j a)) and a_j = a zeta_j^(n+1) / zeta_j for K3; a breakdown (P <= 0 or not
 // finite) is flagged for K3 instead.  Returns false on breakdown.
-__device__ bool k2_step(const MsArgs& a, double& step) {
+__device__ bool k2_step(const MsArgs& a, const Early& e, double& step) {
   SolveState* st = a.st;
   const RotState& rs = st->rot[a.par];
-  const double P = all_sum(region(a, 0), a.gk1);
+  const int j = threadIdx.x;
+  const bool lead = blockIdx.x == 0 && j < kWave;
+  // workgroup 0, lane j: shift j's state, loaded before the partial sum
+  double z = 1.0, zp = 1.0, sj = 0.0;
+  int act = 0;
+  if (lead && j >= 1 && j < st->ns) {
+    act = rs.active[j];
+    z = rs.zeta[j];
+    zp = st->zeta_prev[j];
+    sj = st->s[j];
+  }
+  const double ap = st->a_prev, b = st->b, R = rs.R;
+  const double P = all_sum(region(a, 0), a.gk1, e);
   const bool ok = (P > 0.0) && isfinite(P);
-  step = ok ? rs.R / P : 0.0;
-  if (blockIdx.x == 0 && threadIdx.x < kWave) {
-    const int j = threadIdx.x;
+  step = ok ? R / P : 0.0;
+  if (lead) {
     if (!ok) {
       if (j == 0) {
         st->P = P;
         st->kstatus = 1;
       }
     } else {
-      if (j >= 1 && j < st->ns && rs.active[j]) {
-        const double z = rs.zeta[j], zp = st->zeta_prev[j], ap = st->a_prev, b = st->b;
-        const double zn = z * zp * ap / (step * b * (zp - z) + zp * ap * (1.0 + st->s[j] * step));
+      if (act) {
+        const double zn = z * zp * ap / (step * b * (zp - z) + zp * ap * (1.0 + sj * step));
         st->zk[j] = zn;
         st->ak[j] = step * zn / z;
       }
@@ -308,24 +337,33 @@ struct K3Plan {
   int ok;
 };
 
-__device__ void k3_plan(const MsArgs& a, K3Plan& pl) {
+__device__ void k3_plan(const MsArgs& a, const Early& e, K3Plan& pl) {
   SolveState* st = a.st;
   const RotState& rs = st->rot[a.par];
-  const double Rn = all_sum(region(a, 1), a.gk2);
-  if (threadIdx.x < kWave) {
-    const int j = threadIdx.x;
-    const bool ok = isfinite(Rn) && st->kstatus == 0;
-    const double bn = Rn / rs.R;
-    const bool act = ok && j >= 1 && j < st->ns && rs.active[j];
+  const int j = threadIdx.x;
+  // wave 0, lane j: shift j's state, loaded before the partial sum
+  int act0 = 0;
+  double z = 1.0, zn = 0.0, akj = 0.0;
+  if (j >= 1 && j < kWave && j < st->ns) {
+    act0 = rs.active[j];
+    z = rs.zeta[j];
+    zn = st->zk[j];
+    akj = st->ak[j];
+  }
+  const double R = rs.R, eps2 = st->eps2;
+  const int kst = st->kstatus, frz = st->freeze;
+  const double Rn = all_sum(region(a, 1), a.gk2, e);
+  if (j < kWave) {
+    const bool ok = isfinite(Rn) && kst == 0;
+    const double bn = Rn / R;
+    const bool act = ok && act0;
     bool freeze_now = false;
-    double zn = 0.0;
     if (act) {
-      zn = st->zk[j];
-      const double ratio = zn / rs.zeta[j];
+      const double ratio = zn / z;
       pl.bk[j] = bn * ratio * ratio;
       pl.zk[j] = zn;
-      pl.ak[j] = st->ak[j];
-      freeze_now = st->freeze && zn * zn * Rn <= st->eps2;
+      pl.ak[j] = akj;
+      freeze_now = frz && zn * zn * Rn <= eps2;
     }
     const uint64_t mask = __ballot(act);
     if (act) {
@@ -348,12 +386,12 @@ __device__ void k3_plan(const MsArgs& a, K3Plan& pl) {
         nx.active[j] = act ? (freeze_now ? 0 : 1) : rs.active[j];
       }
       if (act) {
-        st->zeta_prev[j] = rs.zeta[j];
+        st->zeta_prev[j] = z;
         if (freeze_now) st->freeze_iter[j] = it;
       }
       if (j == 0) {
         if (!ok) {
-          nx.R = rs.R;
+          nx.R = R;
           nx.iter = rs.iter;
           nx.halt = 1;
           nx.switch_req = 0;
@@ -364,7 +402,7 @@ __device__ void k3_plan(const MsArgs& a, K3Plan& pl) {
           nx.status = 0;
           st->b = bn;
           st->a_prev = st->a;
-          const bool done = Rn <= st->eps2 || it >= st->max_iter;
+          const bool done = Rn <= eps2 || it >= st->max_iter;
           // the FP64 phase of a mixed solve ends here: this iteration's update still runs,
           // then the host converts the Krylov vectors to complex64 and continues
           const bool sw = !done && Rn <= st->sw_eps2;
@@ -437,8 +475,10 @@ template <class R, int L>
 __global__ __launch_bounds__(kBlock) void k2_mhm(MsArgs a) {
   const SolveState* st = a.st;
   if (st->rot[a.par].halt) return;
+  Early e;
+  load_early(region(a, 0), a.gk1, e);
   double step;
-  if (!k2_step(a, step)) return;  // breakdown: every workgroup sees the same P
+  if (!k2_step(a, e, step)) return;  // breakdown: every workgroup sees the same P
   const Csr<cplx<R>> mh = pick_mh<R>(a);
   const cplx<R>* __restrict__ t = static_cast<const cplx<R>*>(a.t);
   const cplx<R>* __restrict__ p = static_cast<const cplx<R>*>(a.p);
@@ -511,8 +551,8 @@ template <class R>
 __global__ __launch_bounds__(kBlock) void k2_sell(MsArgs a) {
   const SolveState* st = a.st;
   if (st->rot[a.par].halt) return;
-  double step;
-  if (!k2_step(a, step)) return;  // breakdown: every workgroup sees the same P
+  Early e;
+  load_early(region(a, 0), a.gk1, e);
   const Sell<cplx<R>> mh = pick_shm<R>(a);
   const cplx<R>* __restrict__ t = static_cast<const cplx<R>*>(a.t);
   const cplx<R>* __restrict__ p = static_cast<const cplx<R>*>(a.p);
@@ -524,28 +564,44 @@ __global__ __launch_bounds__(kBlock) void k2_sell(MsArgs a) {
   int64_t beg, end;
   block_range(a.nslices, SPB, beg, end);
   double acc = 0.0;
-  for (int64_t sl = beg + wv; sl < end; sl += SPB) {
+  double step = 0.0;
+  // q = M^H t for one slice, with the row operands of the epilogue
+  struct Row {
+    cplx<R> q, p, r;
+  };
+  auto product = [&](int64_t sl) {
     const int64_t row = sl * kSlice + lane;
-    const bool live = row < a.n;
-    const int64_t rr = live ? row : a.n - 1;  // lanes past n read a valid row, unused
+    const int64_t rr = row < a.n ? row : a.n - 1;  // lanes past n read a valid row, unused
     const cplx<R> tr = t[rr];
     const cplx<R> d = mh.diag[rr];
-    const cplx<R> pv = p[rr];
-    const cplx<R> rv = r[rr];
-    cplx<R> q = sell_row<R>(mh, t, sl, lane);
-    cfma<R>(q, d, tr);
-    if (live) {
-      const double2 pr = to_d(pv);
-      const double2 rr = to_d(rv);
-      const double2 qd = to_d(q);
-      double2 nr;
-      nr.x = rr.x - step * (qd.x + sigma0 * pr.x);
-      nr.y = rr.y - step * (qd.y + sigma0 * pr.y);
-      const cplx<R> st_r = from_d<R>(nr);
-      r[row] = st_r;
-      acc += norm2d<R>(st_r);
-    }
-  }
+    Row o;
+    o.p = p[rr];
+    o.r = r[rr];
+    o.q = sell_row<R>(mh, t, sl, lane);
+    cfma<R>(o.q, d, tr);
+    return o;
+  };
+  auto epilogue = [&](int64_t sl, const Row& o) {
+    const int64_t row = sl * kSlice + lane;
+    if (row >= a.n) return;
+    const double2 pr = to_d(o.p);
+    const double2 rr = to_d(o.r);
+    const double2 qd = to_d(o.q);
+    double2 nr;
+    nr.x = rr.x - step * (qd.x + sigma0 * pr.x);
+    nr.y = rr.y - step * (qd.y + sigma0 * pr.y);
+    const cplx<R> st_r = from_d<R>(nr);
+    r[row] = st_r;
+    acc += norm2d<R>(st_r);
+  };
+  // the first slice's product runs while P's partials are on their way
+  int64_t sl = beg + wv;
+  const bool has0 = sl < end;
+  Row first{};
+  if (has0) first = product(sl);
+  if (!k2_step(a, e, step)) return;  // breakdown: every workgroup sees the same P
+  if (has0) epilogue(sl, first);
+  for (sl += SPB; sl < end; sl += SPB) epilogue(sl, product(sl));
   store_partial(region(a, 1), acc);
 }
 
@@ -554,8 +610,10 @@ template <class R>
 __global__ __launch_bounds__(kBlock) void k2_herm(MsArgs a) {
   const SolveState* st = a.st;
   if (st->rot[a.par].halt) return;
+  Early e;
+  load_early(region(a, 0), a.gk1, e);
   double step;
-  if (!k2_step(a, step)) return;  // breakdown: every workgroup sees the same P
+  if (!k2_step(a, e, step)) return;  // breakdown: every workgroup sees the same P
   const cplx<R>* __restrict__ t = static_cast<const cplx<R>*>(a.t);
   const cplx<R>* __restrict__ p = static_cast<const cplx<R>*>(a.p);
   cplx<R>* __restrict__ r = static_cast<cplx<R>*>(a.r);
@@ -585,24 +643,33 @@ __global__ __launch_bounds__(kBlock) void k3_update(MsArgs a) {
     carry_state(a);
     return;
   }
-  __shared__ K3Plan pl;
-  k3_plan(a, pl);
-  if (!pl.ok) return;
+  Early e;
+  load_early(region(a, 1), a.gk2, e);
   const int64_t n = a.n;
   const cplx<R>* __restrict__ rv = static_cast<const cplx<R>*>(a.r);
   cplx<R>* __restrict__ pv = static_cast<cplx<R>*>(a.p);
   cplx<R>* __restrict__ pk = static_cast<cplx<R>*>(a.pk);
   double2* __restrict__ x = a.x;
-  const double step = st->a, bnew = pl.bn;
-  const int nact = pl.nact;
   double2* __restrict__ x0 = x + int64_t(st->orig[0]) * n;
   int64_t beg, end;
   block_range(n, kBlock, beg, end);
-  for (int64_t i = beg + threadIdx.x; i < end; i += kBlock) {
-    const cplx<R> rr = rv[i];
-    const cplx<R> pp = pv[i];
+  // this thread's first row is read while R' is being summed
+  const int64_t i0 = beg + threadIdx.x;
+  const int64_t ic = i0 < end ? i0 : n - 1;
+  cplx<R> r_first = rv[ic], p_first = pv[ic];
+  double2 x_first = x0[ic];
+  const double step = st->a;
+  __shared__ K3Plan pl;
+  k3_plan(a, e, pl);
+  if (!pl.ok) return;
+  const double bnew = pl.bn;
+  const int nact = pl.nact;
+  for (int64_t i = i0; i < end; i += kBlock) {
+    const bool first = i == i0;
+    const cplx<R> rr = first ? r_first : rv[i];
+    const cplx<R> pp = first ? p_first : pv[i];
     const double2 rd = to_d(rr), pd = to_d(pp);
-    double2 xv = x0[i];
+    double2 xv = first ? x_first : x0[i];
     xv.x = fma(step, pd.x, xv.x);
     xv.y = fma(step, pd.y, xv.y);
     x0[i] = xv;
