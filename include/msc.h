@@ -100,9 +100,11 @@ typedef struct {
     int32_t* freeze_iter;    /* [ns] iteration at which shift k froze, -1 if never      */
     double seconds;          /* wall time of the call                                   */
     double alg_bytes;        /* algorithmic HBM bytes moved by the call's kernels       */
-    double kernel_ms[3];     /* with timing on: summed durations of the sampled K1 (first
-                                operator half), K2 (second half + residual update) and K3
-                                (all-shift update) launches, milliseconds              */
+    double kernel_ms[3];     /* with timing on: summed durations of the sampled launches,
+                                milliseconds: [0] the head (the previous iteration's
+                                all-shift update fused with the first operator half),
+                                [1] K2 (second half + residual update), [2] the separate
+                                all-shift update kernel of the CSR path (0 otherwise)  */
     int32_t kernel_samples;  /* number of sampled iterations behind kernel_ms          */
     int32_t iters_fp64;      /* iterations run in FP64 (all of them for MSC_PREC_FP64)  */
 } msc_info;

@@ -56,7 +56,7 @@ template <class T> void dfree(T*& p) {
 }
 
 void free_workspace(Workspace& w) {
-  for (void* q : {w.r, w.p, w.t, w.pk, w.r32, w.p32, w.t32, w.pk32})
+  for (void* q : {w.r, w.p[0], w.p[1], w.t, w.pk, w.r32, w.p32[0], w.p32[1], w.t32, w.pk32})
     if (q) (void)hipFree(q);
   dfree(w.t64);
   dfree(w.u64);
@@ -86,7 +86,8 @@ msc_status ensure_workspace(msc_op op, int prec, int ns) {
   if (!(w.st && w.ns >= ns && w.n == n)) {
     free_workspace(w);
     HIP_TRY(hipMalloc(&w.r, sizeof(double2) * n));
-    HIP_TRY(hipMalloc(&w.p, sizeof(double2) * n));
+    HIP_TRY(hipMalloc(&w.p[0], sizeof(double2) * n));
+    HIP_TRY(hipMalloc(&w.p[1], sizeof(double2) * n));
     HIP_TRY(hipMalloc(&w.t, sizeof(double2) * n));
     HIP_TRY(hipMalloc(&w.pk, sizeof(double2) * n * nk));
     HIP_TRY(dalloc(&w.t64, n));
@@ -102,7 +103,8 @@ msc_status ensure_workspace(msc_op op, int prec, int ns) {
   if (prec == MSC_PREC_MIXED && !w.r32) {
     const size_t wn = std::max<size_t>(size_t(w.ns) - 1, 1);
     HIP_TRY(hipMalloc(&w.r32, sizeof(float2) * n));
-    HIP_TRY(hipMalloc(&w.p32, sizeof(float2) * n));
+    HIP_TRY(hipMalloc(&w.p32[0], sizeof(float2) * n));
+    HIP_TRY(hipMalloc(&w.p32[1], sizeof(float2) * n));
     HIP_TRY(hipMalloc(&w.t32, sizeof(float2) * n));
     HIP_TRY(hipMalloc(&w.pk32, sizeof(float2) * n * wn));
     w.prec = MSC_PREC_MIXED;
@@ -148,7 +150,8 @@ MsArgs make_args(msc_op op, int lanes, const double* d_b, double* d_x) {
   a.b = reinterpret_cast<const double2*>(d_b);
   a.x = reinterpret_cast<double2*>(d_x);
   a.r = op->ws.r;
-  a.p = op->ws.p;
+  a.pb[0] = op->ws.p[0];
+  a.pb[1] = op->ws.p[1];
   a.t = op->ws.t;
   a.pk = op->ws.pk;
   a.t64 = op->ws.t64;
@@ -215,7 +218,8 @@ msc_status run_multishift(msc_op op, const double* d_b, double* d_x, const msc_p
   const bool mixed = prec == MSC_PREC_MIXED;
   if (mixed) {
     a32.r = op->ws.r32;
-    a32.p = op->ws.p32;
+    a32.pb[0] = op->ws.p32[0];
+    a32.pb[1] = op->ws.p32[1];
     a32.t = op->ws.t32;
     a32.pk = op->ws.pk32;
   }
@@ -266,14 +270,15 @@ msc_status run_multishift(msc_op op, const double* d_b, double* d_x, const msc_p
         }
         sample_launch.push_back(launched);
       }
-      // iteration `launched` reads the state rot[launched & 1] and writes the other one
+      // iteration `launched` starts from the state rot[launched & 1]; in the complex64
+      // phase every reliable_every-th iteration recomputes r in FP64 after its head has
+      // brought x up to date
       cur->par = launched & 1;
-      HIP_TRY(launch_iteration(phase, *cur, s, ev));
+      const int since = launched - launched_at_switch;
+      const bool ru = phase == MSC_PREC_MIXED && prm.reliable_every > 0 && since > 0 &&
+                      since % prm.reliable_every == 0;
+      HIP_TRY(launch_iteration(phase, *cur, s, ev, ru));
       ++launched;
-      cur->par = launched & 1;
-      if (phase == MSC_PREC_MIXED && prm.reliable_every > 0 &&
-          (launched - launched_at_switch) % prm.reliable_every == 0)
-        HIP_TRY(launch_reliable(MSC_PREC_MIXED, *cur, s));
     }
     const int slot = chunk & 1;
     // halt and switch_req of the state the next iteration would start from
@@ -312,9 +317,11 @@ msc_status run_multishift(msc_op op, const double* d_b, double* d_x, const msc_p
     // only iterations that did work are counted (the loop runs a little past the halt)
     const int first = launched_at_switch >= 0 ? launched_at_switch : 0;
     const int useful_launches = first + (fin.iter - (iter_at_switch >= 0 ? iter_at_switch : 0));
+    // slot 2 (the separate update kernel) exists on the CSR path only
+    const int slots = a64.sell ? 2 : 3;
     for (size_t q = 0; q < pool.groups.size(); ++q) {
       if (sample_launch[q] >= useful_launches) continue;
-      for (int k = 0; k < 3; ++k) {
+      for (int k = 0; k < slots; ++k) {
         float ms = 0.f;
         HIP_TRY(hipEventElapsedTime(&ms, pool.groups[q][2 * k], pool.groups[q][2 * k + 1]));
         info->kernel_ms[k] += ms;

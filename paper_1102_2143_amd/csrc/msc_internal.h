@@ -21,18 +21,23 @@ constexpr int kTicketSite = 9 * kTicketStride;
 // Scalar state of one multishift solve, resident in device memory.  Shift index j runs
 // over the shifts sorted ascending; j = 0 is the driving shift sigma0.
 //
-// No kernel of an iteration waits for its own reduction: each workgroup stores a partial
-// sum and the workgroups of the next kernel add the partials up themselves, in one fixed
-// order, so they all obtain the same value.  Workgroup 0 of K2 then stores the step
-// constants of the iteration for K3, and workgroup 0 of K3 stores the state of the next
-// iteration.  What every workgroup of K3 reads while its workgroup 0 writes the next
-// values is kept twice (RotState), indexed by the parity of the iteration.
+// An iteration is a head kernel, which first applies the previous iteration's update
+// (x, p_j, p) and then computes t = M p (K1), followed by K2.  No kernel waits for its
+// own reduction: each workgroup stores a partial sum and the workgroups of the next
+// kernel add the partials up themselves, in one fixed order, so they all obtain the same
+// value.  Workgroup 0 of K2 stores the step constants for the next head; workgroup 0 of
+// the head stores the state the rest of the iteration and the next head start from.
+// What every head workgroup reads while its workgroup 0 writes the successor values is
+// kept twice (RotState): the head of an iteration of parity par reads rot[par] and
+// writes rot[par ^ 1], which K2 and the reliable update then use.
 struct RotState {
   double R;                    // |r|^2 of the driving recursive residual
   int iter;                    // iterations completed
   int halt;                    // 1: the kernels of this iteration do no work
   int switch_req;              // 1: halted because the FP64 phase of a mixed solve ended
   int status;                  // 0 running/ok, 1 breakdown
+  int pending;                 // 1: the previous K2's r awaits its update of x, p_j and p
+  int pcur;                    // which of the two direction buffers holds p
   double zeta[kMaxShifts];     // zeta_j^(n)
   int active[kMaxShifts];      // shift j still updated
 };
@@ -50,12 +55,12 @@ struct SolveState {
   int ns;
   int freeze;
   int n_reliable;
-  int kstatus;       // 1: K2 of the current iteration found p^H (A + sigma0) p <= 0
+  int kstatus;       // 1: a K2 found p^H (A + sigma0) p <= 0
   int pad_;
   double s[kMaxShifts];         // sigma_j - sigma0
   double zeta_prev[kMaxShifts]; // zeta_j^(n-1)
-  double zk[kMaxShifts];        // zeta_j^(n+1) of the current iteration (K2 -> K3)
-  double ak[kMaxShifts];        // a_j^(n) = a_n zeta^(n+1)/zeta^(n)          (K2 -> K3)
+  double zk[kMaxShifts];        // zeta_j^(n+1) of the current iteration (K2 -> head)
+  double ak[kMaxShifts];        // a_j^(n) = a_n zeta^(n+1)/zeta^(n)       (K2 -> head)
   int freeze_iter[kMaxShifts];
   int orig[kMaxShifts];         // caller's index of sorted shift j
   RotState rot[2];              // rot[par]: state at the start of an iteration of parity par
@@ -109,11 +114,11 @@ struct Workspace {
   int ns = 0;
   int prec = -1;
   void* r = nullptr;    // n complex128
-  void* p = nullptr;    // n complex128
+  void* p[2] = {nullptr, nullptr};    // two n complex128 direction buffers
   void* t = nullptr;    // n complex128
   void* pk = nullptr;   // (ns-1) * n complex128
   void* r32 = nullptr;  // complex64 copies for the second phase of a mixed solve
-  void* p32 = nullptr;
+  void* p32[2] = {nullptr, nullptr};
   void* t32 = nullptr;
   void* pk32 = nullptr;
   double2* t64 = nullptr;   // n complex128 (reliable updates, verification)
@@ -205,15 +210,18 @@ struct MsArgs {
   Sell<float2> s32, sh32;
   const double2* b;
   double2* x;            // caller's x, shift-major, caller order
-  void* r; void* p; void* t; void* pk;
+  void* r; void* t; void* pk;
+  void* pb[2];           // the two direction buffers (p of consecutive iterations)
   double2* t64;
   SolveState* st;
   Scratch sc;
 };
 hipError_t launch_init(int prec, const MsArgs& a, hipStream_t s);
-// ev (optional, 6 events): start/stop pairs attached to the K1, K2 and K3 dispatches.
-hipError_t launch_iteration(int prec, const MsArgs& a, hipStream_t s, hipEvent_t* ev = nullptr);
-hipError_t launch_reliable(int prec, const MsArgs& a, hipStream_t s);
+// One iteration of parity a.par; with `reliable`, the FP64 reliable update runs between
+// the head and K2.  ev (optional, 6 events): start/stop pairs attached to the K1 (head),
+// K2 and, on the CSR path, the separate update kernel.
+hipError_t launch_iteration(int prec, const MsArgs& a, hipStream_t s, hipEvent_t* ev = nullptr,
+                            bool reliable = false);
 // Second phase of a mixed solve: copy r, p, p_j of a64 (complex128) into a32's complex64
 // buffers and re-arm the state (halt = switch_req = 0, no further switch).
 hipError_t launch_switch_to_mixed(const MsArgs& a64, const MsArgs& a32, int ns, hipStream_t s);

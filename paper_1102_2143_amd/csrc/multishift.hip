@@ -158,6 +158,80 @@ __device__ __forceinline__ cplx<R> sell_row(const Sell<cplx<R>>& m, const cplx<R
   return acc;
 }
 
+// The next direction r + b p, formed in FP64 and rounded once; a lane that gathers p'
+// at a neighbouring row forms the same bits as the row's owner stores.
+template <class R>
+__device__ __forceinline__ cplx<R> next_dir(double b, const cplx<R>& r, const cplx<R>& p) {
+  const double2 rd = to_d(r), pd = to_d(p);
+  double2 v;
+  v.x = fma(b, pd.x, rd.x);
+  v.y = fma(b, pd.y, rd.y);
+  return from_d<R>(v);
+}
+
+// Pairs per round trip when each entry gathers two vectors (MSC_SELL_KPN32 / 64).
+#ifndef MSC_SELL_KPN32
+#define MSC_SELL_KPN32 4
+#endif
+#ifndef MSC_SELL_KPN64
+#define MSC_SELL_KPN64 2
+#endif
+template <class R> constexpr int sell_kp_next();
+template <> constexpr int sell_kp_next<float>() { return MSC_SELL_KPN32; }
+template <> constexpr int sell_kp_next<double>() { return MSC_SELL_KPN64; }
+
+template <class R, int KP, bool FULL>
+__device__ __forceinline__ void sell_gather2_fma(const cplx<R>* __restrict__ r,
+                                                 const cplx<R>* __restrict__ p, double b, int np,
+                                                 const int2 (&cc)[KP], const cplx<R> (&v)[2 * KP],
+                                                 cplx<R>& acc) {
+  cplx<R> xr[2 * KP], xp[2 * KP];
+#pragma unroll
+  for (int u = 0; u < KP; ++u) {
+    if (FULL || u < np) {
+      xr[2 * u] = r[cc[u].x];
+      xp[2 * u] = p[cc[u].x];
+      xr[2 * u + 1] = r[cc[u].y];
+      xp[2 * u + 1] = p[cc[u].y];
+    } else {
+      xr[2 * u] = xr[2 * u + 1] = xp[2 * u] = xp[2 * u + 1] = czero<R>();
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < 2 * KP; ++u) cfma<R>(acc, v[u], next_dir<R>(b, xr[u], xp[u]));
+}
+
+// Off-diagonal part of one sliced ELLPACK row per lane times p' = r + b p, with p' formed
+// at each gathered column.
+template <class R>
+__device__ __forceinline__ cplx<R> sell_row_next(const Sell<cplx<R>>& m,
+                                                 const cplx<R>* __restrict__ r,
+                                                 const cplx<R>* __restrict__ p, double b,
+                                                 int64_t sl, int lane) {
+  constexpr int KP = sell_kp_next<R>();
+  int32_t c, c1;
+  if (m.wp > 0) {
+    c = int32_t(sl) * m.wp;
+    c1 = c + m.wp;
+  } else {
+    c = load_uniform(m.cptr, sl);
+    c1 = load_uniform(m.cptr, sl + 1);
+  }
+  cplx<R> acc = czero<R>();
+  int2 cc[KP];
+  cplx<R> v[2 * KP];
+  for (; c + KP <= c1; c += KP) {
+    sell_load<R, KP, true>(m, c, KP, lane, cc, v);
+    sell_gather2_fma<R, KP, true>(r, p, b, KP, cc, v, acc);
+  }
+  if (c < c1) {
+    const int np = c1 - c;
+    sell_load<R, KP, false>(m, c, np, lane, cc, v);
+    sell_gather2_fma<R, KP, false>(r, p, b, np, cc, v, acc);
+  }
+  return acc;
+}
+
 // One CSR row times a vector, L lanes per row; the sum is returned in every lane.
 // Entries of one row handled by a lane per chunk: the column and value loads of a chunk,
 // then its gathers, are all issued before the first multiply-add, so a row of up to
@@ -282,11 +356,12 @@ __device__ __forceinline__ double all_sum(const double* reg, int count, const Ea
 
 // K2 prologue: a = R / P.  Workgroup 0 also stores a, P and, for every active shift j
 // (wave 0, lane j), zeta_j^(n+1) = zeta zeta_- a_- / (a b (zeta_- - zeta) + zeta_- a_-
-// (1 + s_j a)) and a_j = a zeta_j^(n+1) / zeta_j for K3; a breakdown (P <= 0 or not
-// finite) is flagged for K3 instead.  Returns false on breakdown.
+// (1 + s_j a)) and a_j = a zeta_j^(n+1) / zeta_j for the next head, and marks the update
+// pending; a breakdown (P <= 0 or not finite) is flagged instead.  Returns false on
+// breakdown.  The iteration's state is the one its head wrote, rot[par ^ 1].
 __device__ bool k2_step(const MsArgs& a, const Early& e, double& step) {
   SolveState* st = a.st;
-  const RotState& rs = st->rot[a.par];
+  RotState& rs = st->rot[a.par ^ 1];
   const int j = threadIdx.x;
   const bool lead = blockIdx.x == 0 && j < kWave;
   // workgroup 0, lane j: shift j's state, loaded before the partial sum
@@ -303,6 +378,7 @@ __device__ bool k2_step(const MsArgs& a, const Early& e, double& step) {
   const bool ok = (P > 0.0) && isfinite(P);
   step = ok ? R / P : 0.0;
   if (lead) {
+    if (j == 0) rs.pending = 1;
     if (!ok) {
       if (j == 0) {
         st->P = P;
@@ -323,28 +399,33 @@ __device__ bool k2_step(const MsArgs& a, const Early& e, double& step) {
   return ok;
 }
 
-// K3 prologue, shared through LDS: R' and b = R'/R, and per shift j the coefficients of
-// its update, whether it freezes now (zeta_j^(n+1)^2 R' <= eps2), and the list of shifts
-// this iteration updates.
-struct K3Plan {
-  double bn;
+// Head prologue, shared through LDS.  When the previous K2 left its update pending:
+// R' (from K2's partials) and b = R'/R, and per shift j the coefficients of its update,
+// whether it freezes now (zeta_j^(n+1)^2 R' <= eps2), and the list of shifts to update.
+// Workgroup 0 writes the state the rest of the iteration and the next head start from.
+struct Plan {
+  double bn;                 // b of p <- r + b p (0: p is current, nothing pending)
   double bk[kMaxShifts];
   double zk[kMaxShifts];
   double ak[kMaxShifts];
   int list[kMaxShifts];
   int upd_p[kMaxShifts];
   int nact;
-  int ok;
+  int pending;               // the update runs in this head
+  int ok;                    // 0: breakdown, the head stops
+  int spmv;                  // 1: this head also computes t = M p
 };
 
-__device__ void k3_plan(const MsArgs& a, const Early& e, K3Plan& pl) {
+__device__ void head_plan(const MsArgs& a, const Early& e, Plan& pl) {
   SolveState* st = a.st;
   const RotState& rs = st->rot[a.par];
+  RotState& nx = st->rot[a.par ^ 1];
   const int j = threadIdx.x;
+  const int pending = rs.pending;
   // wave 0, lane j: shift j's state, loaded before the partial sum
   int act0 = 0;
   double z = 1.0, zn = 0.0, akj = 0.0;
-  if (j >= 1 && j < kWave && j < st->ns) {
+  if (pending && j >= 1 && j < kWave && j < st->ns) {
     act0 = rs.active[j];
     z = rs.zeta[j];
     zn = st->zk[j];
@@ -352,11 +433,11 @@ __device__ void k3_plan(const MsArgs& a, const Early& e, K3Plan& pl) {
   }
   const double R = rs.R, eps2 = st->eps2;
   const int kst = st->kstatus, frz = st->freeze;
-  const double Rn = all_sum(region(a, 1), a.gk2, e);
+  const double Rn = pending ? all_sum(region(a, 1), a.gk2, e) : R;
   if (j < kWave) {
-    const bool ok = isfinite(Rn) && kst == 0;
-    const double bn = Rn / R;
-    const bool act = ok && act0;
+    const bool ok = !pending || (isfinite(Rn) && kst == 0);
+    const double bn = pending ? Rn / R : 0.0;
+    const bool act = pending && ok && act0;
     bool freeze_now = false;
     if (act) {
       const double ratio = zn / z;
@@ -371,16 +452,19 @@ __device__ void k3_plan(const MsArgs& a, const Early& e, K3Plan& pl) {
       pl.list[pos] = j;
       pl.upd_p[pos] = freeze_now ? 0 : 1;
     }
+    const int it = pending ? rs.iter + 1 : rs.iter;
+    const bool done = pending && (Rn <= eps2 || it >= st->max_iter);
+    // the FP64 phase of a mixed solve ends here: the update still runs, then the host
+    // converts the Krylov vectors to complex64 and continues
+    const bool sw = pending && !done && Rn <= st->sw_eps2;
     if (j == 0) {
       pl.bn = bn;
       pl.nact = __popcll(mask);
+      pl.pending = pending;
       pl.ok = ok ? 1 : 0;
+      pl.spmv = (ok && !done && !sw) ? 1 : 0;
     }
-    // workgroup 0 writes the state of the next iteration (other workgroups read only
-    // rot[par] and what K2 stored)
     if (blockIdx.x == 0) {
-      RotState& nx = st->rot[a.par ^ 1];
-      const int it = rs.iter + 1;
       if (j < st->ns) {
         nx.zeta[j] = act ? zn : rs.zeta[j];
         nx.active[j] = act ? (freeze_now ? 0 : 1) : rs.active[j];
@@ -390,24 +474,25 @@ __device__ void k3_plan(const MsArgs& a, const Early& e, K3Plan& pl) {
         if (freeze_now) st->freeze_iter[j] = it;
       }
       if (j == 0) {
+        nx.pending = 0;
         if (!ok) {
           nx.R = R;
           nx.iter = rs.iter;
           nx.halt = 1;
           nx.switch_req = 0;
           nx.status = 1;
+          nx.pcur = rs.pcur;
         } else {
           nx.R = Rn;
           nx.iter = it;
           nx.status = 0;
-          st->b = bn;
-          st->a_prev = st->a;
-          const bool done = Rn <= eps2 || it >= st->max_iter;
-          // the FP64 phase of a mixed solve ends here: this iteration's update still runs,
-          // then the host converts the Krylov vectors to complex64 and continues
-          const bool sw = !done && Rn <= st->sw_eps2;
           nx.halt = (done || sw) ? 1 : 0;
           nx.switch_req = sw ? 1 : 0;
+          nx.pcur = pending ? rs.pcur ^ 1 : rs.pcur;
+          if (pending) {
+            st->b = bn;
+            st->a_prev = st->a;
+          }
         }
       }
     }
@@ -415,7 +500,7 @@ __device__ void k3_plan(const MsArgs& a, const Early& e, K3Plan& pl) {
   __syncthreads();
 }
 
-// A halted iteration carries its state over to the next one (workgroup 0 of K3).
+// A halted iteration carries its state over to the next one (head, workgroup 0).
 __device__ void carry_state(const MsArgs& a) {
   if (blockIdx.x != 0) return;
   SolveState* st = a.st;
@@ -432,16 +517,195 @@ __device__ void carry_state(const MsArgs& a) {
     nx.halt = 1;
     nx.switch_req = rs.switch_req;
     nx.status = rs.status;
+    nx.pending = rs.pending;
+    nx.pcur = rs.pcur;
   }
+}
+
+// The pending update of row i: x_0 += a p, x_j += a_j p_j for the listed shifts, p_j <-
+// zeta_j^(n+1) r + b_j p_j (unless j freezes now), and the new direction r + b p, which
+// is stored in the other direction buffer and returned.  rr, pp, x0v: the row's r, p
+// and x_0 (already loaded).
+template <class R>
+__device__ __forceinline__ cplx<R> update_row(const MsArgs& a, const Plan& pl, double step,
+                                              int64_t i, const cplx<R>& rr, const cplx<R>& pp,
+                                              double2 x0v, double2* __restrict__ x0,
+                                              cplx<R>* __restrict__ pnew) {
+  const SolveState* st = a.st;
+  const int64_t n = a.n;
+  cplx<R>* __restrict__ pk = static_cast<cplx<R>*>(a.pk);
+  double2* __restrict__ x = a.x;
+  const double2 rd = to_d(rr), pd = to_d(pp);
+  x0v.x = fma(step, pd.x, x0v.x);
+  x0v.y = fma(step, pd.y, x0v.y);
+  x0[i] = x0v;
+  const int nact = pl.nact;
+  int q = 0;
+  for (; q + 4 <= nact; q += 4) {
+    int jj[4];
+    cplx<R> pj[4];
+    double2 xj[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      jj[u] = pl.list[q + u];
+      pj[u] = pk[int64_t(jj[u] - 1) * n + i];
+      xj[u] = x[int64_t(st->orig[jj[u]]) * n + i];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int j = jj[u];
+      const double2 pjd = to_d(pj[u]);
+      const double aj = pl.ak[j];
+      xj[u].x = fma(aj, pjd.x, xj[u].x);
+      xj[u].y = fma(aj, pjd.y, xj[u].y);
+      x[int64_t(st->orig[j]) * n + i] = xj[u];
+      if (pl.upd_p[q + u]) {
+        const double zj = pl.zk[j], bj = pl.bk[j];
+        double2 np;
+        np.x = fma(zj, rd.x, bj * pjd.x);
+        np.y = fma(zj, rd.y, bj * pjd.y);
+        pk[int64_t(j - 1) * n + i] = from_d<R>(np);
+      }
+    }
+  }
+  for (; q < nact; ++q) {
+    const int j = pl.list[q];
+    const double2 pjd = to_d(pk[int64_t(j - 1) * n + i]);
+    double2* xp = x + int64_t(st->orig[j]) * n + i;
+    double2 xv2 = *xp;
+    const double aj = pl.ak[j];
+    xv2.x = fma(aj, pjd.x, xv2.x);
+    xv2.y = fma(aj, pjd.y, xv2.y);
+    *xp = xv2;
+    if (pl.upd_p[q]) {
+      const double zj = pl.zk[j], bj = pl.bk[j];
+      double2 np;
+      np.x = fma(zj, rd.x, bj * pjd.x);
+      np.y = fma(zj, rd.y, bj * pjd.y);
+      pk[int64_t(j - 1) * n + i] = from_d<R>(np);
+    }
+  }
+  const cplx<R> np = next_dir<R>(pl.bn, rr, pp);
+  pnew[i] = np;
+  return np;
+}
+
+// ---- head on the CSR path: the pending update only (K1 follows as its own kernel) -----
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_update(MsArgs a) {
+  const SolveState* st = a.st;
+  const RotState& rs = st->rot[a.par];
+  if (rs.halt) {
+    carry_state(a);
+    return;
+  }
+  Early e;
+  if (rs.pending) load_early(region(a, 1), a.gk2, e);
+  const int pc = rs.pcur;
+  const int64_t n = a.n;
+  const cplx<R>* __restrict__ rv = static_cast<const cplx<R>*>(a.r);
+  const cplx<R>* __restrict__ pv = static_cast<const cplx<R>*>(a.pb[pc]);
+  cplx<R>* __restrict__ pnew = static_cast<cplx<R>*>(a.pb[pc ^ 1]);
+  double2* __restrict__ x0 = a.x + int64_t(st->orig[0]) * n;
+  int64_t beg, end;
+  block_range(n, kBlock, beg, end);
+  // this thread's first row is read while R' is being summed
+  const int64_t i0 = beg + threadIdx.x;
+  const int64_t ic = i0 < end ? i0 : n - 1;
+  const cplx<R> r_first = rv[ic], p_first = pv[ic];
+  const double2 x_first = x0[ic];
+  const double step = st->a;
+  __shared__ Plan pl;
+  head_plan(a, e, pl);
+  if (!pl.ok || !pl.pending) return;
+  for (int64_t i = i0; i < end; i += kBlock) {
+    const bool first = i == i0;
+    update_row<R>(a, pl, step, i, first ? r_first : rv[i], first ? p_first : pv[i],
+                  first ? x_first : x0[i], x0, pnew);
+  }
+}
+
+// ---- head on the sliced ELLPACK path: pending update fused with K1 -------------------
+// One row per lane, one slice per wave.  With an update pending, the lane first updates
+// its own row (x, p_j, and p' = r + b p stored in the other buffer), then t = M p' takes
+// p' at the gathered columns from r and the old p, rounded exactly as the owning lane
+// rounds it; P = |t|^2 + sigma0 |p'|^2 (A = M^H M) or Re p'^H t + sigma0 |p'|^2.
+template <class R, bool MHM>
+__global__ __launch_bounds__(kBlock) void k1_fused(MsArgs a) {
+  const SolveState* st = a.st;
+  const RotState& rs = st->rot[a.par];
+  if (rs.halt) {
+    carry_state(a);
+    return;
+  }
+  const int pending = rs.pending;
+  Early e;
+  if (pending) load_early(region(a, 1), a.gk2, e);
+  const int pc = rs.pcur;
+  const Sell<cplx<R>> m = pick_sm<R>(a);
+  const cplx<R>* __restrict__ rv = static_cast<const cplx<R>*>(a.r);
+  const cplx<R>* __restrict__ pv = static_cast<const cplx<R>*>(a.pb[pc]);
+  cplx<R>* __restrict__ pnew = static_cast<cplx<R>*>(a.pb[pc ^ 1]);
+  cplx<R>* __restrict__ t = static_cast<cplx<R>*>(a.t);
+  double2* __restrict__ x0 = a.x + int64_t(st->orig[0]) * a.n;
+  const double sigma0 = st->sigma0;
+  const double step = st->a;
+  constexpr int SPB = kBlock / kSlice;
+  const int lane = threadIdx.x % kSlice;
+  const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x / kSlice));
+  int64_t beg, end;
+  block_range(a.nslices, SPB, beg, end);
+  // the first slice's own row is read while R' is being summed
+  const int64_t sl0 = beg + wv;
+  const int64_t row0 = sl0 * kSlice + lane;
+  const int64_t rc = (sl0 < end && row0 < a.n) ? row0 : a.n - 1;
+  const cplx<R> r_first = rv[rc], p_first = pv[rc];
+  const double2 x_first = x0[rc];
+  __shared__ Plan pl;
+  head_plan(a, e, pl);
+  if (!pl.ok) return;
+  const bool upd = pl.pending != 0;
+  const double bn = pl.bn;
+  double acc = 0.0;
+  for (int64_t sl = sl0; sl < end; sl += SPB) {
+    const int64_t row = sl * kSlice + lane;
+    const bool live = row < a.n;
+    const int64_t rr = live ? row : a.n - 1;  // lanes past n read a valid row, unused
+    const bool first = sl == sl0;
+    const cplx<R> r_i = first ? r_first : rv[rr];
+    const cplx<R> p_i = first ? p_first : pv[rr];
+    cplx<R> p_row = p_i;
+    if (upd) {
+      if (live)
+        p_row = update_row<R>(a, pl, step, row, r_i, p_i, first ? x_first : x0[rr], x0, pnew);
+      else
+        p_row = next_dir<R>(bn, r_i, p_i);
+    }
+    if (!pl.spmv) continue;
+    const cplx<R> d = m.diag[rr];
+    // without a pending update p' = p: the same product with r := p and b = 0 (exact)
+    cplx<R> v = sell_row_next<R>(m, upd ? rv : pv, pv, bn, sl, lane);
+    cfma<R>(v, d, p_row);
+    if (live) {
+      t[row] = v;
+      if (MHM)
+        acc += norm2d<R>(v) + sigma0 * norm2d<R>(p_row);
+      else
+        acc += double(p_row.x) * double(v.x) + double(p_row.y) * double(v.y) +
+               sigma0 * norm2d<R>(p_row);
+    }
+  }
+  if (pl.spmv) store_partial(region(a, 0), acc);
 }
 
 // ---- K1 -------------------------------------------------------------------------------
 template <class R, int L, bool MHM>
 __global__ __launch_bounds__(kBlock) void k1_apply(MsArgs a) {
   const SolveState* st = a.st;
-  if (st->rot[a.par].halt) return;
+  const RotState& ns = st->rot[a.par ^ 1];  // written by this iteration's head
+  if (ns.halt) return;
   const Csr<cplx<R>> m = pick_m<R>(a);
-  const cplx<R>* __restrict__ p = static_cast<const cplx<R>*>(a.p);
+  const cplx<R>* __restrict__ p = static_cast<const cplx<R>*>(a.pb[ns.pcur]);
   cplx<R>* __restrict__ t = static_cast<cplx<R>*>(a.t);
   const double sigma0 = st->sigma0;
   constexpr int GPB = kBlock / L;
@@ -474,14 +738,15 @@ __global__ __launch_bounds__(kBlock) void k1_apply(MsArgs a) {
 template <class R, int L>
 __global__ __launch_bounds__(kBlock) void k2_mhm(MsArgs a) {
   const SolveState* st = a.st;
-  if (st->rot[a.par].halt) return;
+  const RotState& ns = st->rot[a.par ^ 1];  // written by this iteration's head
+  if (ns.halt) return;
   Early e;
   load_early(region(a, 0), a.gk1, e);
   double step;
   if (!k2_step(a, e, step)) return;  // breakdown: every workgroup sees the same P
   const Csr<cplx<R>> mh = pick_mh<R>(a);
   const cplx<R>* __restrict__ t = static_cast<const cplx<R>*>(a.t);
-  const cplx<R>* __restrict__ p = static_cast<const cplx<R>*>(a.p);
+  const cplx<R>* __restrict__ p = static_cast<const cplx<R>*>(a.pb[ns.pcur]);
   cplx<R>* __restrict__ r = static_cast<cplx<R>*>(a.r);
   const double sigma0 = st->sigma0;
   constexpr int GPB = kBlock / L;
@@ -513,49 +778,17 @@ __global__ __launch_bounds__(kBlock) void k2_mhm(MsArgs a) {
   store_partial(region(a, 1), acc);
 }
 
-// ---- K1 and K2 on the sliced ELLPACK copies: one row per lane, one slice per wave ----
-template <class R, bool MHM>
-__global__ __launch_bounds__(kBlock) void k1_sell(MsArgs a) {
-  const SolveState* st = a.st;
-  if (st->rot[a.par].halt) return;
-  const Sell<cplx<R>> m = pick_sm<R>(a);
-  const cplx<R>* __restrict__ p = static_cast<const cplx<R>*>(a.p);
-  cplx<R>* __restrict__ t = static_cast<cplx<R>*>(a.t);
-  const double sigma0 = st->sigma0;
-  constexpr int SPB = kBlock / kSlice;
-  const int lane = threadIdx.x % kSlice;
-  const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x / kSlice));
-  int64_t beg, end;
-  block_range(a.nslices, SPB, beg, end);
-  double acc = 0.0;
-  for (int64_t sl = beg + wv; sl < end; sl += SPB) {
-    const int64_t row = sl * kSlice + lane;
-    const bool live = row < a.n;
-    const int64_t rr = live ? row : a.n - 1;  // lanes past n read a valid row, unused
-    const cplx<R> pr = p[rr];
-    const cplx<R> d = m.diag[rr];
-    cplx<R> v = sell_row<R>(m, p, sl, lane);
-    cfma<R>(v, d, pr);
-    if (live) {
-      t[row] = v;
-      if (MHM)
-        acc += norm2d<R>(v) + sigma0 * norm2d<R>(pr);
-      else
-        acc += double(pr.x) * double(v.x) + double(pr.y) * double(v.y) + sigma0 * norm2d<R>(pr);
-    }
-  }
-  store_partial(region(a, 0), acc);
-}
-
+// ---- K2 on the sliced ELLPACK copy of M^H: one row per lane, one slice per wave ------
 template <class R>
 __global__ __launch_bounds__(kBlock) void k2_sell(MsArgs a) {
   const SolveState* st = a.st;
-  if (st->rot[a.par].halt) return;
+  const RotState& ns = st->rot[a.par ^ 1];  // written by this iteration's head
+  if (ns.halt) return;
   Early e;
   load_early(region(a, 0), a.gk1, e);
   const Sell<cplx<R>> mh = pick_shm<R>(a);
   const cplx<R>* __restrict__ t = static_cast<const cplx<R>*>(a.t);
-  const cplx<R>* __restrict__ p = static_cast<const cplx<R>*>(a.p);
+  const cplx<R>* __restrict__ p = static_cast<const cplx<R>*>(a.pb[ns.pcur]);
   cplx<R>* __restrict__ r = static_cast<cplx<R>*>(a.r);
   const double sigma0 = st->sigma0;
   constexpr int SPB = kBlock / kSlice;
@@ -609,13 +842,14 @@ __global__ __launch_bounds__(kBlock) void k2_sell(MsArgs a) {
 template <class R>
 __global__ __launch_bounds__(kBlock) void k2_herm(MsArgs a) {
   const SolveState* st = a.st;
-  if (st->rot[a.par].halt) return;
+  const RotState& ns = st->rot[a.par ^ 1];  // written by this iteration's head
+  if (ns.halt) return;
   Early e;
   load_early(region(a, 0), a.gk1, e);
   double step;
   if (!k2_step(a, e, step)) return;  // breakdown: every workgroup sees the same P
   const cplx<R>* __restrict__ t = static_cast<const cplx<R>*>(a.t);
-  const cplx<R>* __restrict__ p = static_cast<const cplx<R>*>(a.p);
+  const cplx<R>* __restrict__ p = static_cast<const cplx<R>*>(a.pb[ns.pcur]);
   cplx<R>* __restrict__ r = static_cast<cplx<R>*>(a.r);
   const double sigma0 = st->sigma0;
   int64_t beg, end;
@@ -633,98 +867,6 @@ __global__ __launch_bounds__(kBlock) void k2_herm(MsArgs a) {
   store_partial(region(a, 1), acc);
 }
 
-// ---- K3: fused update of every active shift from one read of r and p ------------------
-// x_0 += a p; for each active shift j: x_j += a_j p_j, p_j <- zeta_j^(n+1) r + b_j p_j
-// (skipped when j freezes now); p <- r + b p.
-template <class R>
-__global__ __launch_bounds__(kBlock) void k3_update(MsArgs a) {
-  const SolveState* st = a.st;
-  if (st->rot[a.par].halt) {
-    carry_state(a);
-    return;
-  }
-  Early e;
-  load_early(region(a, 1), a.gk2, e);
-  const int64_t n = a.n;
-  const cplx<R>* __restrict__ rv = static_cast<const cplx<R>*>(a.r);
-  cplx<R>* __restrict__ pv = static_cast<cplx<R>*>(a.p);
-  cplx<R>* __restrict__ pk = static_cast<cplx<R>*>(a.pk);
-  double2* __restrict__ x = a.x;
-  double2* __restrict__ x0 = x + int64_t(st->orig[0]) * n;
-  int64_t beg, end;
-  block_range(n, kBlock, beg, end);
-  // this thread's first row is read while R' is being summed
-  const int64_t i0 = beg + threadIdx.x;
-  const int64_t ic = i0 < end ? i0 : n - 1;
-  cplx<R> r_first = rv[ic], p_first = pv[ic];
-  double2 x_first = x0[ic];
-  const double step = st->a;
-  __shared__ K3Plan pl;
-  k3_plan(a, e, pl);
-  if (!pl.ok) return;
-  const double bnew = pl.bn;
-  const int nact = pl.nact;
-  for (int64_t i = i0; i < end; i += kBlock) {
-    const bool first = i == i0;
-    const cplx<R> rr = first ? r_first : rv[i];
-    const cplx<R> pp = first ? p_first : pv[i];
-    const double2 rd = to_d(rr), pd = to_d(pp);
-    double2 xv = first ? x_first : x0[i];
-    xv.x = fma(step, pd.x, xv.x);
-    xv.y = fma(step, pd.y, xv.y);
-    x0[i] = xv;
-    int q = 0;
-    for (; q + 4 <= nact; q += 4) {
-      int jj[4];
-      cplx<R> pj[4];
-      double2 xj[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        jj[u] = pl.list[q + u];
-        pj[u] = pk[int64_t(jj[u] - 1) * n + i];
-        xj[u] = x[int64_t(st->orig[jj[u]]) * n + i];
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int j = jj[u];
-        const double2 pjd = to_d(pj[u]);
-        const double aj = pl.ak[j];
-        xj[u].x = fma(aj, pjd.x, xj[u].x);
-        xj[u].y = fma(aj, pjd.y, xj[u].y);
-        x[int64_t(st->orig[j]) * n + i] = xj[u];
-        if (pl.upd_p[q + u]) {
-          const double zj = pl.zk[j], bj = pl.bk[j];
-          double2 np;
-          np.x = fma(zj, rd.x, bj * pjd.x);
-          np.y = fma(zj, rd.y, bj * pjd.y);
-          pk[int64_t(j - 1) * n + i] = from_d<R>(np);
-        }
-      }
-    }
-    for (; q < nact; ++q) {
-      const int j = pl.list[q];
-      const double2 pjd = to_d(pk[int64_t(j - 1) * n + i]);
-      double2* xp = x + int64_t(st->orig[j]) * n + i;
-      double2 xv2 = *xp;
-      const double aj = pl.ak[j];
-      xv2.x = fma(aj, pjd.x, xv2.x);
-      xv2.y = fma(aj, pjd.y, xv2.y);
-      *xp = xv2;
-      if (pl.upd_p[q]) {
-        const double zj = pl.zk[j], bj = pl.bk[j];
-        double2 np;
-        np.x = fma(zj, rd.x, bj * pjd.x);
-        np.y = fma(zj, rd.y, bj * pjd.y);
-        pk[int64_t(j - 1) * n + i] = from_d<R>(np);
-      }
-    }
-    double2 npd;
-    npd.x = fma(bnew, pd.x, rd.x);
-    npd.y = fma(bnew, pd.y, rd.y);
-    pv[i] = from_d<R>(npd);
-  }
-}
-
 // ---- initialisation: r = p = p_j = b, x = 0, |b|^2 ------------------------------------
 template <class R>
 __global__ __launch_bounds__(kBlock) void k_init(MsArgs a) {
@@ -732,7 +874,7 @@ __global__ __launch_bounds__(kBlock) void k_init(MsArgs a) {
   const int64_t n = a.n;
   const int ns = st->ns;
   cplx<R>* __restrict__ r = static_cast<cplx<R>*>(a.r);
-  cplx<R>* __restrict__ p = static_cast<cplx<R>*>(a.p);
+  cplx<R>* __restrict__ p = static_cast<cplx<R>*>(a.pb[0]);  // rot[par].pcur = 0
   cplx<R>* __restrict__ pk = static_cast<cplx<R>*>(a.pk);
   int64_t beg, end;
   block_range(n, kBlock, beg, end);
@@ -766,11 +908,12 @@ __global__ __launch_bounds__(kBlock) void k_init(MsArgs a) {
 // ---- end of the FP64 phase of a mixed solve: Krylov vectors to complex64 -------------
 __global__ __launch_bounds__(kBlock) void k_switch(MsArgs a64, MsArgs a32, int ns) {
   const int64_t n = a64.n;
+  const int pc = a64.st->rot[a64.par].pcur;  // the direction buffer in use carries over
   const double2* __restrict__ r = static_cast<const double2*>(a64.r);
-  const double2* __restrict__ p = static_cast<const double2*>(a64.p);
+  const double2* __restrict__ p = static_cast<const double2*>(a64.pb[pc]);
   const double2* __restrict__ pk = static_cast<const double2*>(a64.pk);
   float2* __restrict__ r32 = static_cast<float2*>(a32.r);
-  float2* __restrict__ p32 = static_cast<float2*>(a32.p);
+  float2* __restrict__ p32 = static_cast<float2*>(a32.pb[pc]);
   float2* __restrict__ pk32 = static_cast<float2*>(a32.pk);
   const int64_t total = int64_t(ns) * n;  // r, p, then ns-1 shift directions
   for (int64_t idx = blockIdx.x * int64_t(kBlock) + threadIdx.x; idx < total;
@@ -793,12 +936,13 @@ __global__ __launch_bounds__(kBlock) void k_switch(MsArgs a64, MsArgs a32, int n
   }
 }
 
-// ---- reliable update: r = b - (A + sigma0) x_0 in FP64 --------------------------------
+// ---- reliable update: r = b - (A + sigma0) x_0 in FP64, between the head and K2 ----------
 template <int L, bool MHM>
 __global__ __launch_bounds__(kBlock) void k_ru_first(MsArgs a) {
   // t64 = M x_0 (A = M^H M) -- first half of the FP64 operator
   const SolveState* st = a.st;
-  if (st->rot[a.par].halt) return;
+  const RotState& ns = st->rot[a.par ^ 1];  // written by this iteration's head
+  if (ns.halt) return;
   const double2* __restrict__ x0 = a.x + int64_t(st->orig[0]) * a.n;
   constexpr int GPB = kBlock / L;
   const int lane = threadIdx.x % L, grp = threadIdx.x / L;
@@ -813,7 +957,7 @@ __global__ __launch_bounds__(kBlock) void k_ru_first(MsArgs a) {
 template <class R, int L, bool MHM>
 __global__ __launch_bounds__(kBlock) void k_ru_second(MsArgs a) {
   SolveState* st = a.st;
-  if (st->rot[a.par].halt) return;
+  if (st->rot[a.par ^ 1].halt) return;
   const double2* __restrict__ x0 = a.x + int64_t(st->orig[0]) * a.n;
   cplx<R>* __restrict__ r = static_cast<cplx<R>*>(a.r);
   const double sigma0 = st->sigma0;
@@ -834,12 +978,14 @@ __global__ __launch_bounds__(kBlock) void k_ru_second(MsArgs a) {
       acc += fma(rt.x, rt.x, rt.y * rt.y);
     }
   }
+  // region 2: the head's partials in region 0 still wait for K2
+  double* reg = region(a, 2);
   const double tot = block_sum<kBlock>(acc);
-  if (threadIdx.x == 0) store_agent(&a.sc.partial[blockIdx.x], tot);
+  if (threadIdx.x == 0) store_agent(&reg[blockIdx.x], tot);
   if (!arrive_last(a.sc.tickets + 2 * kTicketSite)) return;
-  const double Rt = sum_partials(a.sc.partial, gridDim.x, 1, 0);
+  const double Rt = sum_partials(reg, gridDim.x, 1, 0);
   if (threadIdx.x == 0) {
-    RotState& rs = st->rot[a.par];
+    RotState& rs = st->rot[a.par ^ 1];
     rs.R = Rt;
     st->n_reliable += 1;
     if (!isfinite(Rt)) {
@@ -1003,37 +1149,6 @@ void launch_timed(K kern, int grid, hipStream_t s, hipEvent_t* ev, int k, const 
 }
 
 template <class R>
-hipError_t iteration_impl(const MsArgs& args, hipStream_t s, hipEvent_t* ev) {
-  const int g1 = grid_rows(args.n, kBlock / args.lanes, args.grid);
-  const int g3 = grid_rows(args.n, kBlock, args.grid);
-  MsArgs a = args;
-  // workgroups of K1 and K2, whose partials K2 and K3 add up
-  if (a.sell) {
-    a.gk1 = a.gk2 = g3;
-  } else {
-    a.gk1 = g1;
-    a.gk2 = a.kind == MSC_A_MHM ? g1 : g3;
-  }
-  if (a.sell) {
-    if (a.kind == MSC_A_MHM) {
-      launch_timed(k1_sell<R, true>, g3, s, ev, 0, a);
-      launch_timed(k2_sell<R>, g3, s, ev, 1, a);
-    } else {
-      launch_timed(k1_sell<R, false>, g3, s, ev, 0, a);
-      launch_timed(k2_herm<R>, g3, s, ev, 1, a);
-    }
-  } else if (a.kind == MSC_A_MHM) {
-    MSC_LANES_SWITCH(a.lanes, (launch_timed(k1_apply<R, LL, true>, g1, s, ev, 0, a)));
-    MSC_LANES_SWITCH(a.lanes, (launch_timed(k2_mhm<R, LL>, g1, s, ev, 1, a)));
-  } else {
-    MSC_LANES_SWITCH(a.lanes, (launch_timed(k1_apply<R, LL, false>, g1, s, ev, 0, a)));
-    launch_timed(k2_herm<R>, g3, s, ev, 1, a);
-  }
-  launch_timed(k3_update<R>, g3, s, ev, 2, a);
-  return hipGetLastError();
-}
-
-template <class R>
 hipError_t reliable_impl(const MsArgs& a, hipStream_t s) {
   const int g1 = grid_rows(a.n, kBlock / a.lanes);
   if (a.kind == MSC_A_MHM) {
@@ -1041,6 +1156,50 @@ hipError_t reliable_impl(const MsArgs& a, hipStream_t s) {
     MSC_LANES_SWITCH(a.lanes, (k_ru_second<R, LL, true><<<g1, kBlock, 0, s>>>(a)));
   } else {
     MSC_LANES_SWITCH(a.lanes, (k_ru_second<R, LL, false><<<g1, kBlock, 0, s>>>(a)));
+  }
+  return hipGetLastError();
+}
+
+// One iteration: the head (pending update fused with K1 on the sliced ELLPACK path; a
+// separate update kernel followed by the CSR K1 otherwise), the optional reliable
+// update, then K2.
+template <class R>
+hipError_t iteration_impl(const MsArgs& args, hipStream_t s, hipEvent_t* ev, bool reliable) {
+  const int g1 = grid_rows(args.n, kBlock / args.lanes, args.grid);
+  const int g3 = grid_rows(args.n, kBlock, args.grid);
+  MsArgs a = args;
+  // workgroups of K1 and K2, whose partials K2 and the next head add up
+  if (a.sell) {
+    a.gk1 = a.gk2 = g3;
+  } else {
+    a.gk1 = g1;
+    a.gk2 = a.kind == MSC_A_MHM ? g1 : g3;
+  }
+  if (a.sell) {
+    if (a.kind == MSC_A_MHM)
+      launch_timed(k1_fused<R, true>, g3, s, ev, 0, a);
+    else
+      launch_timed(k1_fused<R, false>, g3, s, ev, 0, a);
+  } else {
+    launch_timed(k_update<R>, g3, s, ev, 2, a);
+    if (a.kind == MSC_A_MHM) {
+      MSC_LANES_SWITCH(a.lanes, (launch_timed(k1_apply<R, LL, true>, g1, s, ev, 0, a)));
+    } else {
+      MSC_LANES_SWITCH(a.lanes, (launch_timed(k1_apply<R, LL, false>, g1, s, ev, 0, a)));
+    }
+  }
+  if (reliable) {
+    const hipError_t e = reliable_impl<R>(a, s);
+    if (e != hipSuccess) return e;
+  }
+  if (a.kind == MSC_A_MHM) {
+    if (a.sell) {
+      launch_timed(k2_sell<R>, g3, s, ev, 1, a);
+    } else {
+      MSC_LANES_SWITCH(a.lanes, (launch_timed(k2_mhm<R, LL>, g1, s, ev, 1, a)));
+    }
+  } else {
+    launch_timed(k2_herm<R>, g3, s, ev, 1, a);
   }
   return hipGetLastError();
 }
@@ -1058,18 +1217,16 @@ hipError_t launch_init(int prec, const MsArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_iteration(int prec, const MsArgs& a, hipStream_t s, hipEvent_t* ev) {
-  return prec == MSC_PREC_MIXED ? iteration_impl<float>(a, s, ev) : iteration_impl<double>(a, s, ev);
+hipError_t launch_iteration(int prec, const MsArgs& a, hipStream_t s, hipEvent_t* ev,
+                            bool reliable) {
+  return prec == MSC_PREC_MIXED ? iteration_impl<float>(a, s, ev, reliable)
+                                : iteration_impl<double>(a, s, ev, reliable);
 }
 
 hipError_t launch_switch_to_mixed(const MsArgs& a64, const MsArgs& a32, int ns, hipStream_t s) {
   const int g = grid_rows(int64_t(ns) * a64.n, kBlock);
   k_switch<<<g, kBlock, 0, s>>>(a64, a32, ns);
   return hipGetLastError();
-}
-
-hipError_t launch_reliable(int prec, const MsArgs& a, hipStream_t s) {
-  return prec == MSC_PREC_MIXED ? reliable_impl<float>(a, s) : reliable_impl<double>(a, s);
 }
 
 hipError_t launch_verify(const MsArgs& a, const double* sigma_by_caller_index, int k0, int kc,

@@ -312,14 +312,21 @@ def test_sell_refused_when_padding_is_large(cuda):
     op.close()
 
 
-def test_kernel_timing_samples(c0, cuda):
-    # timing attaches start/stop events to sampled K1/K2/K3 dispatches
+@pytest.mark.parametrize("fmt", ["sell", "csr"])
+def test_kernel_timing_samples(c0, cuda, fmt):
+    # timing attaches start/stop events to the sampled dispatches: the head and K2 on the
+    # sliced ELLPACK path (the update runs inside the head), K1, K2 and the separate
+    # update kernel on the CSR path
     op = _op(c0, cuda)
     op.set_shifts(c0["sigma"])
-    x, info = op.solve(c0["b"], tol=1e-10, timing=4)
+    x, info = op.solve(c0["b"], tol=1e-10, timing=4, format=fmt)
     assert info["status"] == "ok"
     assert info["kernel_samples"] > 0
-    assert np.all(info["kernel_ms"] > 0)
+    assert np.all(info["kernel_ms"][:2] > 0)
+    if fmt == "sell":
+        assert info["kernel_ms"][2] == 0
+    else:
+        assert info["kernel_ms"][2] > 0
     op.close()
 
 
