@@ -63,23 +63,6 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_bytes(kind, prec, n, nnz, nnz_h, act_avg):
-    """Algorithmic bytes of one launch (each array touched once, gathers counted once).
-
-    K1: t = M p; K2: r <- r - a (M^H t + sigma0 p); K3: the all-shift update.  The head
-    kernel of the sliced-ELLPACK path runs K3 and then K1 on the new p, reading the old p
-    once for both."""
-    w = 8.0 if prec == "mixed" else 16.0
-    vb = w
-    k1 = nnz * (vb + 4) + 4 * (n + 1) + n * w + n * w
-    if kind == "mhm":
-        k2 = nnz_h * (vb + 4) + 4 * (n + 1) + n * w + n * w + 2 * n * w
-    else:
-        k2 = n * w + n * w + 2 * n * w
-    k3 = n * (w + 2 * w + 32.0) + act_avg * n * (32.0 + 2 * w)
-    return {"K1": k1, "K2": k2, "K3": k3, "head": k1 + k3 - n * w}
-
-
 def cpu_baseline(prob, sample_iters, full_iters):
     """Time the FP64 oracle on a bounded sample of the same solve (single thread)."""
     import oracle as O
@@ -173,20 +156,19 @@ def main():
         n, nnz = prob["n"], prob["vals"].size
         iters = infos[-1]["iters"]
         alg_bytes = float(np.mean([inf["alg_bytes"] for inf in infos]))
-        drive = int(np.argmin(prob["sigma"]))
-        fi = infos[-1]["freeze_iter"]
-        act_sum = sum((fi[k] if fi[k] >= 0 else iters) for k in range(ns) if k != drive)
-        kb = kernel_bytes("mhm", prec, n, nnz, nnz, act_sum / max(iters, 1))
         samples = sum(inf["kernel_samples"] for inf in infos)
         kms = np.sum([inf["kernel_ms"] for inf in infos], axis=0)
+        kby = np.sum([inf["kernel_bytes"] for inf in infos], axis=0)
         kernels = {}
         if samples > 0:
-            # slot 2 (a separate K3) is empty when the update is fused into the head
+            # slot 2 (a separate update kernel) is empty when the update is fused into the head
             names = ["head", "K2"] if kms[2] == 0 else ["K1", "K2", "K3"]
             for k, nm in enumerate(names):
-                avg_ms = kms[k] / samples
-                kernels[nm] = {"avg_us": round(1e3 * avg_ms, 2), "alg_bytes": kb[nm],
-                               "gbs": round(kb[nm] / (avg_ms * 1e-3) / 1e9, 1)}
+                # algorithmic bytes of the sampled launches (the library counts the shifts
+                # active at each sampled iteration) over their measured durations
+                kernels[nm] = {"avg_us": round(1e3 * kms[k] / samples, 2),
+                               "alg_bytes": round(kby[k] / samples),
+                               "gbs": round(kby[k] / (kms[k] * 1e-3) / 1e9, 1)}
         return dict(prec=prec, wall=wall, ok=ok, iters=iters, infos=infos,
                     value=ns * args.steps / wall, ms_per_step=1e3 * wall / args.steps,
                     eff_gbs=alg_bytes / (wall / args.steps) / 1e9, kernels=kernels,

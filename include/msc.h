@@ -107,6 +107,9 @@ typedef struct {
                                 all-shift update kernel of the CSR path (0 otherwise)  */
     int32_t kernel_samples;  /* number of sampled iterations behind kernel_ms          */
     int32_t iters_fp64;      /* iterations run in FP64 (all of them for MSC_PREC_FP64)  */
+    double kernel_bytes[3];  /* algorithmic HBM bytes of the same sampled launches, summed
+                                like kernel_ms (each array touched once, gathers once;
+                                the head's depends on the shifts active at its iteration) */
 } msc_info;
 
 /* Fill *p with the defaults listed above. */

@@ -60,6 +60,7 @@ class Info(ctypes.Structure):
         ("kernel_ms", ctypes.c_double * 3),
         ("kernel_samples", ctypes.c_int32),
         ("iters_fp64", ctypes.c_int32),
+        ("kernel_bytes", ctypes.c_double * 3),
     ]
 
 

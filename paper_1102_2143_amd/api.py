@@ -165,6 +165,7 @@ def _info_dict(st, info, rel, fi):
                 freeze_iter=np.array(fi[:]), seconds=float(info.seconds),
                 alg_bytes=float(info.alg_bytes), kernel_ms=np.array(info.kernel_ms[:]),
                 kernel_samples=int(info.kernel_samples),
+                kernel_bytes=np.array(info.kernel_bytes[:]),
                 iters_fp64=int(info.iters_fp64))
 
 

@@ -162,6 +162,23 @@ MsArgs make_args(msc_op op, int lanes, const double* d_b, double* d_x) {
 
 // Algorithmic HBM bytes of one multishift iteration (each array touched once, gathers
 // counted once), per row: see the byte model in the design notes of the repository.
+// Algorithmic bytes of one launch: K1 (t = M p), K2 (r <- r - a (M^H t + sigma0 p)), the
+// all-shift update with `act` active shifts, and the head that fuses the update with K1
+// (the old p is read once for both).
+struct KernelBytes {
+  double k1, k2, upd, head;
+};
+KernelBytes kernel_bytes(int kind, int prec, double n, double nnz, double nnz_h, double act,
+                         bool pending) {
+  const double w = prec == MSC_PREC_MIXED ? 8.0 : 16.0;
+  KernelBytes b{};
+  b.k1 = nnz * (w + 4.0) + 4.0 * (n + 1) + 2.0 * n * w;
+  b.k2 = (kind == MSC_A_MHM ? nnz_h * (w + 4.0) + 4.0 * (n + 1) + n * w : n * w) + 3.0 * n * w;
+  b.upd = pending ? n * (3.0 * w + 32.0) + act * n * (32.0 + 2.0 * w) : 0.0;
+  b.head = b.k1 + (pending ? b.upd - n * w : 0.0);
+  return b;
+}
+
 double iter_bytes(int kind, int prec, double n, double nnz, double nnz_h, double act_sum,
                   double iters) {
   const double w = prec == MSC_PREC_MIXED ? 8.0 : 16.0;   // Krylov vector element
@@ -313,19 +330,36 @@ msc_status run_multishift(msc_op op, const double* d_b, double* d_x, const msc_p
   const int iters_fp64 = iter_at_switch >= 0 ? iter_at_switch : fin.iter;
   if (info) {
     for (double& v : info->kernel_ms) v = 0.0;
+    for (double& v : info->kernel_bytes) v = 0.0;
     info->kernel_samples = 0;
     // only iterations that did work are counted (the loop runs a little past the halt)
     const int first = launched_at_switch >= 0 ? launched_at_switch : 0;
     const int useful_launches = first + (fin.iter - (iter_at_switch >= 0 ? iter_at_switch : 0));
     // slot 2 (the separate update kernel) exists on the CSR path only
     const int slots = a64.sell ? 2 : 3;
+    const double nn = double(op->n), nz = double(op->nnz), nzh = double(op->nnz_h);
     for (size_t q = 0; q < pool.groups.size(); ++q) {
-      if (sample_launch[q] >= useful_launches) continue;
+      const int L = sample_launch[q];
+      if (L >= useful_launches) continue;
       for (int k = 0; k < slots; ++k) {
         float ms = 0.f;
         HIP_TRY(hipEventElapsedTime(&ms, pool.groups[q][2 * k], pool.groups[q][2 * k + 1]));
         info->kernel_ms[k] += ms;
       }
+      // iterations completed before this launch's head, and the shifts its update touched
+      const bool ph32 = launched_at_switch >= 0 && L >= launched_at_switch;
+      const int done_before = ph32 ? iter_at_switch + (L - launched_at_switch) : L;
+      const bool pending = !(L == 0 || (ph32 && L == launched_at_switch));
+      int act = 0;
+      for (int j = 1; j < ns; ++j) {
+        const int last = h.freeze_iter[j] >= 0 ? h.freeze_iter[j] : fin.iter;
+        if (last >= done_before + 1) ++act;
+      }
+      const KernelBytes kb = kernel_bytes(op->kind, ph32 ? MSC_PREC_MIXED : prec, nn, nz, nzh,
+                                          double(act), pending);
+      info->kernel_bytes[0] += a64.sell ? kb.head : kb.k1;
+      info->kernel_bytes[1] += kb.k2;
+      if (!a64.sell) info->kernel_bytes[2] += kb.upd;
       info->kernel_samples += 1;
     }
   }
@@ -355,6 +389,8 @@ msc_status run_multishift(msc_op op, const double* d_b, double* d_x, const msc_p
                iter_bytes(op->kind, MSC_PREC_MIXED, nn, nz, nzh, act32, double(fin.iter - iters_fp64)) +
                double(h.n_reliable) * ((op->kind == MSC_A_MHM ? 2.0 : 1.0) * (nz * 20.0 + 4.0 * (nn + 1)) +
                                        nn * (16.0 * 3 + 8.0));
+  // the fused head reads the old direction once for the update and the product
+  if (a64.sell) *bytes_out -= nn * (16.0 * iters_fp64 + 8.0 * (fin.iter - iters_fp64));
   if (info) info->iters_fp64 = iters_fp64;
 
   rel_out->assign(ns, 0.0);

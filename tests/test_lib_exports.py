@@ -42,7 +42,7 @@ def test_params_default_and_struct_layout():
     assert p.tol == 1e-10 and p.max_iter == 10000 and p.reliable_every == 50
     assert p.poll_every == 16 and p.verify == 1
     assert ctypes.sizeof(_lib.Params) == 72  # max_grid, format and mixed_margin took the reserved slots
-    assert ctypes.sizeof(_lib.Info) == 80
+    assert ctypes.sizeof(_lib.Info) == 104  # kernel_bytes[3] appended
 
 
 def test_null_arguments_are_rejected_without_gpu_work():
