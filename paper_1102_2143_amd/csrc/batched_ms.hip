@@ -14,6 +14,7 @@
 
 #include "dev_common.h"
 #include "msc_internal.h"
+#include "sell_load.h"
 
 namespace msc {
 
@@ -68,6 +69,86 @@ __device__ __forceinline__ void row_dot_rhs(const Csr<cplx<R>>& m, const cplx<R>
   for (int q = 0; q < RR; ++q) acc[q] = group_sum_c<L, R>(acc[q]);
 }
 
+template <class R> __device__ __forceinline__ Sell<cplx<R>> sell1(const BatchSys& S);
+template <> __device__ __forceinline__ Sell<double2> sell1<double>(const BatchSys& S) { return S.s64; }
+template <> __device__ __forceinline__ Sell<float2> sell1<float>(const BatchSys& S) { return S.s32; }
+template <class R> __device__ __forceinline__ Sell<cplx<R>> sell2(const BatchSys& S);
+template <> __device__ __forceinline__ Sell<double2> sell2<double>(const BatchSys& S) { return S.sh64; }
+template <> __device__ __forceinline__ Sell<float2> sell2<float>(const BatchSys& S) { return S.sh32; }
+
+// The RR interleaved values of column c, loaded 16 bytes at a time.
+template <class R, int RR>
+__device__ __forceinline__ void load_rhs(const cplx<R>* __restrict__ x, int64_t c, cplx<R> (&o)[RR]) {
+  if constexpr (std::is_same<R, float>::value && RR % 2 == 0) {
+    const f32x4* v = reinterpret_cast<const f32x4*>(x + c * RR);
+#pragma unroll
+    for (int h = 0; h < RR / 2; ++h) {
+      const f32x4 w = v[h];
+      o[2 * h] = float2{w.x, w.y};
+      o[2 * h + 1] = float2{w.z, w.w};
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < RR; ++q) o[q] = x[c * RR + q];
+  }
+}
+
+// Pairs per round trip of the RR-rhs product (register budget ~ 120 VGPRs).
+template <class R, int RR> constexpr int kp_rhs() {
+  return std::is_same<R, float>::value ? (RR >= 4 ? 2 : 4) : (RR >= 4 ? 1 : 2);
+}
+
+template <class R, int RR, int KP, bool FULL>
+__device__ __forceinline__ void gather_rhs_fma(const cplx<R>* __restrict__ x, int np,
+                                               const int2 (&cc)[KP], const cplx<R> (&v)[2 * KP],
+                                               cplx<R> (&acc)[RR]) {
+  cplx<R> xs[2 * KP][RR];
+#pragma unroll
+  for (int u = 0; u < KP; ++u) {
+    if (FULL || u < np) {
+      load_rhs<R, RR>(x, cc[u].x, xs[2 * u]);
+      load_rhs<R, RR>(x, cc[u].y, xs[2 * u + 1]);
+    } else {
+#pragma unroll
+      for (int q = 0; q < RR; ++q) xs[2 * u][q] = xs[2 * u + 1][q] = czero<R>();
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < 2 * KP; ++u) {
+#pragma unroll
+    for (int q = 0; q < RR; ++q) cfma<R>(acc[q], v[u], xs[u][q]);
+  }
+}
+
+// Off-diagonal part of one sliced ELLPACK row per lane times the RR interleaved vectors
+// of x (slice `sl` wavefront-uniform); one read of the matrix row serves every rhs.
+template <class R, int RR>
+__device__ __forceinline__ void sell_row_rhs(const Sell<cplx<R>>& m, const cplx<R>* __restrict__ x,
+                                             int64_t sl, int lane, cplx<R> (&acc)[RR]) {
+  constexpr int KP = kp_rhs<R, RR>();
+#pragma unroll
+  for (int q = 0; q < RR; ++q) acc[q] = czero<R>();
+  int32_t c, c1;
+  if (m.wp > 0) {
+    c = int32_t(sl) * m.wp;
+    c1 = c + m.wp;
+  } else {
+    c = load_uniform(m.cptr, sl);
+    c1 = load_uniform(m.cptr, sl + 1);
+  }
+  int2 cc[KP];
+  cplx<R> v[2 * KP];
+  for (; c + KP <= c1; c += KP) {
+    sell_load<R, KP, true>(m, c, KP, lane, cc, v);
+    gather_rhs_fma<R, RR, KP, true>(x, KP, cc, v, acc);
+  }
+  if (c < c1) {
+    const int np = c1 - c;
+    sell_load<R, KP, false>(m, c, np, lane, cc, v);
+    gather_rhs_fma<R, RR, KP, false>(x, np, cc, v, acc);
+  }
+}
+
 // Per-rhs workgroup partials of a chunk: store, take the system's ticket; true in the
 // last chunk of the system, which then holds the per-rhs totals in tot[].
 __device__ __forceinline__ bool chunk_reduce(double (&v)[kBatchMaxRhs], const BatchSys& S, int cidx,
@@ -96,19 +177,43 @@ __device__ void bk1_chunk(const BatchSys& S, BatchState* st, const int4& ch) {
   cplx<R>* __restrict__ t = vec_t<R>(S);
   const double s0 = st->sigma0;
   const bool mhm = S.kind == MSC_A_MHM;
-  constexpr int GPB = kBlock / L;
-  const int lane = threadIdx.x % L, grp = threadIdx.x / L;
   double acc[kBatchMaxRhs] = {0.0, 0.0, 0.0, 0.0};
-  for (int64_t row = ch.y + grp; row < ch.z; row += GPB) {
-    cplx<R> v[RR];
-    row_dot_rhs<R, L, RR>(m, p, row, lane, v);
-    if (lane == 0) {
+  auto epilogue = [&](int64_t row, const cplx<R> (&v)[RR], const cplx<R> (&pr)[RR]) {
 #pragma unroll
-      for (int q = 0; q < RR; ++q) {
-        t[row * RR + q] = v[q];
-        const cplx<R> pr = p[row * RR + q];
-        acc[q] += (mhm ? norm2d<R>(v[q]) : double(pr.x) * double(v[q].x) + double(pr.y) * double(v[q].y)) +
-                  s0 * norm2d<R>(pr);
+    for (int q = 0; q < RR; ++q) {
+      t[row * RR + q] = v[q];
+      acc[q] += (mhm ? norm2d<R>(v[q])
+                     : double(pr[q].x) * double(v[q].x) + double(pr[q].y) * double(v[q].y)) +
+                s0 * norm2d<R>(pr[q]);
+    }
+  };
+  if (S.sell) {
+    // one row per lane: the chunk's four slices, one per wave
+    const Sell<cplx<R>> ms = sell1<R>(S);
+    const int lane = threadIdx.x % kSlice;
+    const int64_t sl = ch.y / kSlice + __builtin_amdgcn_readfirstlane(int(threadIdx.x / kSlice));
+    if (sl * kSlice < ch.z) {
+      const int64_t row = sl * kSlice + lane;
+      const int64_t rr = row < ch.z ? row : ch.z - 1;
+      cplx<R> pr[RR], v[RR];
+      load_rhs<R, RR>(p, rr, pr);
+      const cplx<R> d = ms.diag[rr];
+      sell_row_rhs<R, RR>(ms, p, sl, lane, v);
+#pragma unroll
+      for (int q = 0; q < RR; ++q) cfma<R>(v[q], d, pr[q]);
+      if (row < ch.z) epilogue(row, v, pr);
+    }
+  } else {
+    constexpr int GPB = kBlock / L;
+    const int lane = threadIdx.x % L, grp = threadIdx.x / L;
+    for (int64_t row = ch.y + grp; row < ch.z; row += GPB) {
+      cplx<R> v[RR];
+      row_dot_rhs<R, L, RR>(m, p, row, lane, v);
+      if (lane == 0) {
+        cplx<R> pr[RR];
+#pragma unroll
+        for (int q = 0; q < RR; ++q) pr[q] = p[row * RR + q];
+        epilogue(row, v, pr);
       }
     }
   }
@@ -153,26 +258,45 @@ __device__ void bk2_chunk(const BatchSys& S, BatchState* st, const int4& ch, int
   double step[RR];
 #pragma unroll
   for (int q = 0; q < RR; ++q) step[q] = (q < st->nrhs && !st->halt[q]) ? st->a[q] : 0.0;
-  constexpr int GPB = kBlock / L;
-  const int lane = threadIdx.x % L, grp = threadIdx.x / L;
   double acc[kBatchMaxRhs] = {0.0, 0.0, 0.0, 0.0};
-  for (int64_t row = ch.y + grp; row < ch.z; row += GPB) {
-    cplx<R> qv[RR];
-    if (mhm) {
-      row_dot_rhs<R, L, RR>(mat2<R>(S), t, row, lane, qv);
-    } else {
+  auto epilogue = [&](int64_t row, const cplx<R> (&qv)[RR]) {
 #pragma unroll
-      for (int q = 0; q < RR; ++q) qv[q] = t[row * RR + q];
+    for (int q = 0; q < RR; ++q) {
+      const double2 pr = to_d(p[row * RR + q]), rr = to_d(r[row * RR + q]), qd = to_d(qv[q]);
+      const double2 nr{rr.x - step[q] * (qd.x + s0 * pr.x), rr.y - step[q] * (qd.y + s0 * pr.y)};
+      const cplx<R> sr = from_d<R>(nr);
+      r[row * RR + q] = sr;
+      acc[q] += norm2d<R>(sr);
     }
-    if (lane == 0) {
+  };
+  if (S.sell && mhm) {
+    // one row per lane: the chunk's four slices, one per wave
+    const Sell<cplx<R>> ms = sell2<R>(S);
+    const int lane = threadIdx.x % kSlice;
+    const int64_t sl = ch.y / kSlice + __builtin_amdgcn_readfirstlane(int(threadIdx.x / kSlice));
+    if (sl * kSlice < ch.z) {
+      const int64_t row = sl * kSlice + lane;
+      const int64_t rr = row < ch.z ? row : ch.z - 1;
+      cplx<R> tr[RR], qv[RR];
+      load_rhs<R, RR>(t, rr, tr);
+      const cplx<R> d = ms.diag[rr];
+      sell_row_rhs<R, RR>(ms, t, sl, lane, qv);
 #pragma unroll
-      for (int q = 0; q < RR; ++q) {
-        const double2 pr = to_d(p[row * RR + q]), rr = to_d(r[row * RR + q]), qd = to_d(qv[q]);
-        const double2 nr{rr.x - step[q] * (qd.x + s0 * pr.x), rr.y - step[q] * (qd.y + s0 * pr.y)};
-        const cplx<R> sr = from_d<R>(nr);
-        r[row * RR + q] = sr;
-        acc[q] += norm2d<R>(sr);
+      for (int q = 0; q < RR; ++q) cfma<R>(qv[q], d, tr[q]);
+      if (row < ch.z) epilogue(row, qv);
+    }
+  } else {
+    constexpr int GPB = kBlock / L;
+    const int lane = threadIdx.x % L, grp = threadIdx.x / L;
+    for (int64_t row = ch.y + grp; row < ch.z; row += GPB) {
+      cplx<R> qv[RR];
+      if (mhm) {
+        row_dot_rhs<R, L, RR>(mat2<R>(S), t, row, lane, qv);
+      } else {
+#pragma unroll
+        for (int q = 0; q < RR; ++q) qv[q] = t[row * RR + q];
       }
+      if (lane == 0) epilogue(row, qv);
     }
   }
   __shared__ double tot[kBatchMaxRhs];
@@ -271,11 +395,15 @@ __device__ void bk3_chunk(const BatchSys& S, const BatchState* st, const int4& c
       xv.x = fma(a, pd.x, xv.x);
       xv.y = fma(a, pd.y, xv.y);
       *x0 = xv;
+      constexpr bool same = std::is_same<R, W>::value;
       for (int k = 1; k < ns; ++k) {
         const int lk = q * kBatchMaxShifts + k;
+        const bool ux = st->upd_x[lk];
+        // a frozen shift is left alone, except on the switching iteration (copied over)
+        if (same && !ux) continue;
         const int64_t pidx = int64_t(k - 1) * n * RR + idx;
         const double2 pj = to_d(pk[pidx]);
-        if (st->upd_x[lk]) {
+        if (ux) {
           double2* xp = S.x + (int64_t(q) * ns + st->orig[k]) * n + i;
           double2 xk = *xp;
           const double aj = st->ak[lk];
@@ -286,7 +414,7 @@ __device__ void bk3_chunk(const BatchSys& S, const BatchState* st, const int4& c
         if (st->upd_p[lk]) {
           const double zj = st->zk[lk], bj = st->bk[lk];
           pkw[pidx] = from_d<W>(double2{fma(zj, rd.x, bj * pj.x), fma(zj, rd.y, bj * pj.y)});
-        } else if (!std::is_same<R, W>::value) {
+        } else if (!same) {
           pkw[pidx] = from_d<W>(pj);
         }
       }

@@ -768,6 +768,17 @@ struct BatchRun {
         S.mh64 = Csr<double2>{op->rowptr_h, op->col_h, op->val64_h};
         S.mh32 = Csr<float2>{op->rowptr_h, op->col_h, op->val32_h};
       }
+      S.sell = (op->sell && prm.format != MSC_FORMAT_CSR) ? 1 : 0;
+      if (S.sell) {
+        const SellStore& sm = op->sell_m;
+        S.s64 = Sell<double2>{sm.cptr, sm.col, sm.val64, sm.diag64, sm.wp};
+        S.s32 = Sell<float2>{sm.cptr, sm.col, sm.val32, sm.diag32, sm.wp};
+        if (op->kind == MSC_A_MHM) {
+          const SellStore& sh = op->sell_mh;
+          S.sh64 = Sell<double2>{sh.cptr, sh.col, sh.val64, sh.diag64, sh.wp};
+          S.sh32 = Sell<float2>{sh.cptr, sh.col, sh.val32, sh.diag32, sh.wp};
+        }
+      }
       S.b = reinterpret_cast<const double2*>(d_b[s]);
       S.x = reinterpret_cast<double2*>(d_x[s]);
       S.r64 = reinterpret_cast<double2*>(take(sizeof(double2) * n * rr));

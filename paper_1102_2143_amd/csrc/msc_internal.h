@@ -317,6 +317,9 @@ struct BatchSys {
   int64_t n;
   Csr<double2> m64, mh64;
   Csr<float2> m32, mh32;
+  int sell;               // the SpMVs read the system's sliced ELLPACK copies below
+  Sell<double2> s64, sh64;
+  Sell<float2> s32, sh32;
   const double2* b;       // nrhs * n (rhs-major)
   double2* x;             // nrhs * ns * n (rhs-major, shift-major, caller order)
   double2 *r64, *p64, *t64, *pk64, *u64;   // rhs-interleaved n x RR; pk: (ns-1) blocks

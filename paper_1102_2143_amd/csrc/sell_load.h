@@ -1,0 +1,69 @@
+// Loads of the sliced ELLPACK layout (see Sell in msc_internal.h), shared by the
+// single-system and the batched kernels.
+#pragma once
+
+#include "dev_common.h"
+#include "msc_internal.h"
+
+namespace msc {
+
+// MSC_SELL_NT: stream the matrix with non-temporal loads (1) or ordinary loads (0; measured
+// faster on MI355X at 16^4 and for the FP64 kernels at 32^3x64).
+#ifndef MSC_SELL_NT
+#define MSC_SELL_NT 0
+#endif
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef int i32x2 __attribute__((ext_vector_type(2)));
+
+template <class T> __device__ __forceinline__ T stream_load(const T* p) {
+  if (MSC_SELL_NT) return __builtin_nontemporal_load(p);
+  return *p;
+}
+
+// Entries 2q and 2q+1 of one lane (pair index q counts kSlice pairs per slice column).
+__device__ __forceinline__ void load_pair(const float2* __restrict__ v, int64_t q, float2& e0,
+                                          float2& e1) {
+  const f32x4 w = stream_load(reinterpret_cast<const f32x4*>(v) + q);
+  e0 = float2{w.x, w.y};
+  e1 = float2{w.z, w.w};
+}
+__device__ __forceinline__ void load_pair(const double2* __restrict__ v, int64_t q, double2& e0,
+                                          double2& e1) {
+  const f64x2 a = stream_load(reinterpret_cast<const f64x2*>(v) + 2 * q);
+  const f64x2 b = stream_load(reinterpret_cast<const f64x2*>(v) + 2 * q + 1);
+  e0 = double2{a.x, a.y};
+  e1 = double2{b.x, b.y};
+}
+__device__ __forceinline__ int2 load_cols(const int32_t* __restrict__ col, int64_t q) {
+  const i32x2 c = stream_load(reinterpret_cast<const i32x2*>(col) + q);
+  return int2{c.x, c.y};
+}
+
+// Column and value loads of KP pairs starting at pair column c (np < KP: only the first
+// np pairs exist; the rest read as zero).
+template <class R, int KP, bool FULL>
+__device__ __forceinline__ void sell_load(const Sell<cplx<R>>& m, int32_t c, int np, int lane,
+                                          int2 (&cc)[KP], cplx<R> (&v)[2 * KP]) {
+#pragma unroll
+  for (int u = 0; u < KP; ++u) {
+    if (FULL || u < np) {
+      const int64_t q = int64_t(c + u) * kSlice + lane;
+      cc[u] = load_cols(m.col, q);
+      load_pair(m.val, q, v[2 * u], v[2 * u + 1]);
+    } else {
+      cc[u] = int2{0, 0};
+      v[2 * u] = v[2 * u + 1] = czero<R>();
+    }
+  }
+}
+
+// Slice offsets are read through the scalar cache: the address is wavefront-uniform and
+// the array is never written while a solve runs.
+__device__ __forceinline__ int32_t load_uniform(const int32_t* p, int64_t i) {
+  using cptr_t = const __attribute__((address_space(4))) int32_t*;
+  return ((cptr_t)p)[i];
+}
+
+}  // namespace msc

@@ -34,13 +34,16 @@ def _ops(systems, cuda):
     return ops
 
 
-@pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_small_batch_matches_oracle(cuda, prec):
-    print(f"[gpu] batched small {prec}", flush=True)
+@pytest.mark.parametrize("prec,fmt", [("fp64", "auto"), ("mixed", "auto"), ("fp64", "csr"),
+                                      ("mixed", "csr")])
+def test_small_batch_matches_oracle(cuda, prec, fmt):
+    # "auto": the SpMVs read each system's sliced ELLPACK copy; "csr": the CSR kernels
+    print(f"[gpu] batched small {prec} {fmt}", flush=True)
     from paper_1102_2143_amd import solve_batched
     systems = _small_batch()
     ops = _ops(systems, cuda)
-    xs, infos, status = solve_batched(ops, [p["b"] for p in systems], tol=1e-10, prec=prec)
+    xs, infos, status = solve_batched(ops, [p["b"] for p in systems], tol=1e-10, prec=prec,
+                                      format=fmt)
     assert status == "ok", [i["status"] for i in infos]
     t = 0
     for s, p in enumerate(systems):
