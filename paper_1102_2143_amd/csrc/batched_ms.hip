@@ -370,8 +370,40 @@ __device__ void bk2_chunk(const BatchSys& S, BatchState* st, const int4& ch, int
 }
 
 // ---- BK3: x_q += a_q p_q, shifted updates, p_q <- r_q + b_q p_q --------------------------
+// The update's per-(rhs, shift) coefficients, staged in LDS once per chunk so the loop
+// over shifts issues its vector loads without first waiting on the scalar state.
+struct K3Coef {
+  double ak[kQK], zk[kQK], bk[kQK];
+  int upd_x[kQK], upd_p[kQK];
+  int orig[kBatchMaxShifts];
+  double a[kBatchMaxRhs], bnew[kBatchMaxRhs];
+  int x0_upd[kBatchMaxRhs];
+  int nrhs, ns;
+};
+
 template <class R, class W, int RR>
 __device__ void bk3_chunk(const BatchSys& S, const BatchState* st, const int4& ch) {
+  __shared__ K3Coef cf;
+  const int tid = threadIdx.x;
+  __syncthreads();  // the previous chunk of this workgroup is done with cf
+  if (tid < kQK) {
+    cf.ak[tid] = st->ak[tid];
+    cf.zk[tid] = st->zk[tid];
+    cf.bk[tid] = st->bk[tid];
+    cf.upd_x[tid] = st->upd_x[tid];
+    cf.upd_p[tid] = st->upd_p[tid];
+  }
+  if (tid < kBatchMaxShifts) cf.orig[tid] = st->orig[tid];
+  if (tid < kBatchMaxRhs) {
+    cf.a[tid] = st->a[tid];
+    cf.bnew[tid] = st->b_new[tid];
+    cf.x0_upd[tid] = st->x0_upd[tid];
+  }
+  if (tid == 0) {
+    cf.nrhs = st->nrhs;
+    cf.ns = st->ns;
+  }
+  __syncthreads();
   const cplx<R>* __restrict__ r = vec_r<R>(S);
   cplx<R>* __restrict__ p = vec_p<R>(S);
   cplx<R>* __restrict__ pk = vec_pk<R>(S);
@@ -380,45 +412,58 @@ __device__ void bk3_chunk(const BatchSys& S, const BatchState* st, const int4& c
   cplx<W>* __restrict__ rw = vec_r<W>(S);
   cplx<W>* __restrict__ pkw = vec_pk<W>(S);
   const int64_t n = S.n;
-  const int ns = st->ns;
+  const int ns = cf.ns;
   const int64_t rows = ch.z - ch.y;
-  for (int64_t e = threadIdx.x; e < rows * RR; e += kBlock) {
+  for (int64_t e = tid; e < rows * RR; e += kBlock) {
     const int64_t i = ch.y + e / RR;
     const int q = int(e % RR);
     const int64_t idx = i * RR + q;
     const double2 rd = to_d(r[idx]);
     const double2 pd = to_d(p[idx]);
-    if (q < st->nrhs && st->x0_upd[q]) {
-      double2* x0 = S.x + (int64_t(q) * ns + st->orig[0]) * n + i;
-      const double a = st->a[q];
+    if (q < cf.nrhs && cf.x0_upd[q]) {
+      double2* x0 = S.x + (int64_t(q) * ns + cf.orig[0]) * n + i;
+      const double a = cf.a[q];
       double2 xv = *x0;
       xv.x = fma(a, pd.x, xv.x);
       xv.y = fma(a, pd.y, xv.y);
       *x0 = xv;
       constexpr bool same = std::is_same<R, W>::value;
-      for (int k = 1; k < ns; ++k) {
-        const int lk = q * kBatchMaxShifts + k;
-        const bool ux = st->upd_x[lk];
-        // a frozen shift is left alone, except on the switching iteration (copied over)
-        if (same && !ux) continue;
-        const int64_t pidx = int64_t(k - 1) * n * RR + idx;
-        const double2 pj = to_d(pk[pidx]);
-        if (ux) {
-          double2* xp = S.x + (int64_t(q) * ns + st->orig[k]) * n + i;
-          double2 xk = *xp;
-          const double aj = st->ak[lk];
-          xk.x = fma(aj, pj.x, xk.x);
-          xk.y = fma(aj, pj.y, xk.y);
-          *xp = xk;
+      // two shifts at a time, their loads issued before either store (x_k and p_k of
+      // different shifts share one array each, so the compiler cannot reorder); frozen
+      // shifts are skipped except on the switching iteration, which copies them
+      for (int k0 = 1; k0 < ns; k0 += 2) {
+        double2 pj[2], xk[2];
+        bool ux[2], ld[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const int k = k0 + u;
+          const int lk = q * kBatchMaxShifts + k;
+          ux[u] = k < ns && cf.upd_x[lk];
+          ld[u] = k < ns && (ux[u] || !same);
+          if (ld[u]) pj[u] = to_d(pk[int64_t(k - 1) * n * RR + idx]);
+          if (ux[u]) xk[u] = S.x[(int64_t(q) * ns + cf.orig[k]) * n + i];
         }
-        if (st->upd_p[lk]) {
-          const double zj = st->zk[lk], bj = st->bk[lk];
-          pkw[pidx] = from_d<W>(double2{fma(zj, rd.x, bj * pj.x), fma(zj, rd.y, bj * pj.y)});
-        } else if (!same) {
-          pkw[pidx] = from_d<W>(pj);
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const int k = k0 + u;
+          if (!ld[u]) continue;
+          const int lk = q * kBatchMaxShifts + k;
+          const int64_t pidx = int64_t(k - 1) * n * RR + idx;
+          if (ux[u]) {
+            const double aj = cf.ak[lk];
+            xk[u].x = fma(aj, pj[u].x, xk[u].x);
+            xk[u].y = fma(aj, pj[u].y, xk[u].y);
+            S.x[(int64_t(q) * ns + cf.orig[k]) * n + i] = xk[u];
+          }
+          if (cf.upd_p[lk]) {
+            const double zj = cf.zk[lk], bj = cf.bk[lk];
+            pkw[pidx] = from_d<W>(double2{fma(zj, rd.x, bj * pj[u].x), fma(zj, rd.y, bj * pj[u].y)});
+          } else if (!same) {
+            pkw[pidx] = from_d<W>(pj[u]);
+          }
         }
       }
-      const double bq = st->b_new[q];
+      const double bq = cf.bnew[q];
       pw[idx] = from_d<W>(double2{fma(bq, pd.x, rd.x), fma(bq, pd.y, rd.y)});
     } else if (!std::is_same<R, W>::value) {
       pw[idx] = from_d<W>(pd);
