@@ -959,15 +959,45 @@ struct BatchRun {
   msc_status finish(const msc_params& prm, msc_info* info, hipStream_t user,
                     std::chrono::steady_clock::time_point t0) {
     msc_status result = MSC_OK;
+    // every (system, rhs) verification is queued first, each writing its own slot, and
+    // read back with one copy
+    int total = 0;
+    for (int s = 0; s < nsys; ++s) total += nrhs[s];
+    double* d_res2 = nullptr;
+    std::vector<double> r2all(size_t(total) * kMaxShifts, 0.0);
+    struct Res2Guard {
+      double*& p;
+      ~Res2Guard() { dfree(p); }
+    } res2_guard{d_res2};
+    if (prm.verify) {
+      HIP_TRY(dalloc(&d_res2, size_t(total) * kMaxShifts));
+      int t = 0;
+      for (int s = 0; s < nsys; ++s) {
+        const msc_op op = ops[s];
+        const int ns = int(op->sigma.size());
+        const int64_t n = op->n;
+        msc_status rc = ensure_scratch(op);
+        if (rc != MSC_OK) return rc;
+        rc = ensure_workspace(op, MSC_PREC_FP64, ns);
+        if (rc != MSC_OK) return rc;
+        for (int q = 0; q < nrhs[s]; ++q, ++t) {
+          if (hst[s].status[q] != 0) continue;
+          MsArgs a = make_args(op, choose_lanes(op, prm), d_b[s] + 2 * int64_t(q) * n,
+                               d_x[s] + 2 * int64_t(q) * ns * n);
+          a.sc.res2 = d_res2 + size_t(t) * kMaxShifts;
+          for (int k0 = 0; k0 < ns; k0 += 8)
+            HIP_TRY(launch_verify(a, op->sigma.data(), k0, std::min(8, ns - k0), op->ws.u64, sint));
+        }
+      }
+      HIP_TRY(hipMemcpyAsync(r2all.data(), d_res2, sizeof(double) * r2all.size(),
+                             hipMemcpyDeviceToHost, sint));
+      HIP_TRY(hipStreamSynchronize(sint));
+    }
     int t = 0;
     for (int s = 0; s < nsys; ++s) {
       const msc_op op = ops[s];
       const int ns = int(op->sigma.size());
       const int64_t n = op->n;
-      msc_status rc = ensure_scratch(op);
-      if (rc != MSC_OK) return rc;
-      rc = ensure_workspace(op, MSC_PREC_FP64, ns);
-      if (rc != MSC_OK) return rc;
       const BatchState& h = hst[s];
       for (int q = 0; q < nrhs[s]; ++q, ++t) {
         const double* bq = d_b[s] + 2 * int64_t(q) * n;
@@ -977,13 +1007,7 @@ struct BatchRun {
         int refine_iters = 0, n_refined = 0;
         bool bd = h.status[q] != 0;
         if (!bd && prm.verify) {
-          MsArgs a = make_args(op, choose_lanes(op, prm), bq, xq);
-          for (int k0 = 0; k0 < ns; k0 += 8) {
-            HIP_TRY(launch_verify(a, op->sigma.data(), k0, std::min(8, ns - k0), op->ws.u64, sint));
-          }
-          std::vector<double> r2(ns);
-          HIP_TRY(hipMemcpyAsync(r2.data(), op->scratch.res2, sizeof(double) * ns, hipMemcpyDeviceToHost, sint));
-          HIP_TRY(hipStreamSynchronize(sint));
+          const double* r2 = r2all.data() + size_t(t) * kMaxShifts;
           std::vector<int> todo;
           for (int k = 0; k < ns; ++k) {
             rel[k] = bn > 0 ? std::sqrt(r2[k]) / bn : 0.0;
@@ -1002,7 +1026,7 @@ struct BatchRun {
             }
             double bytes = 0.0;
             bool b1 = false;
-            rc = run_batched_cg(op, MSC_PREC_FP64, int(todo.size()), sig.data(), f.data(), xs.data(),
+            const msc_status rc = run_batched_cg(op, MSC_PREC_FP64, int(todo.size()), sig.data(), f.data(), xs.data(),
                                 tol_abs.data(), 0.0, prm, sint, res, &refine_iters, &bytes, &b1);
             if (rc != MSC_OK) return rc;
             bd = bd || b1;
