@@ -63,6 +63,45 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def batched_line(args, dev):
+    """The 64-system batch (4 rhs x 10 shifts each) solved in one batched call, mixed and
+    FP64: shifted-solves/s and effective GB/s (algorithmic bytes / wall time)."""
+    import torch
+    import workloads as W
+    from paper_1102_2143_amd import Operator, solve_batched
+
+    systems = W.make_config("c4")["systems"]
+    ops = []
+    for p in systems:
+        op = Operator(p["rowptr"], p["col"], p["vals"], p["n"], kind=p["kind"], device=dev)
+        op.set_shifts(p["sigma"])
+        ops.append(op)
+    bs = [torch.from_numpy(np.ascontiguousarray(p["b"])).to(dev) for p in systems]
+    count = sum(np.atleast_2d(p["b"]).shape[0] * p["sigma"].size for p in systems)
+    out = {"workload": "c4: 48 staggered (4^4..12^4) + 16 Laplacian 32^3 systems, 4 rhs, "
+                       "10 shifts each, tol 1e-10", "shifted_solves": int(count)}
+    for prec in ("mixed", "fp64"):
+        for _ in range(args.warmup):
+            solve_batched(ops, bs, tol=1e-10, prec=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ok = True
+        for _ in range(args.steps):
+            _, infos, status = solve_batched(ops, bs, tol=1e-10, prec=prec)
+            ok = ok and status == "ok" and all(i["true_rel_res"].max() <= 1e-10 for i in infos)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / args.steps
+        ab = sum(i["alg_bytes"] for i in infos)
+        out[prec] = {"ms_per_step": round(1e3 * wall, 3), "value": round(count / wall, 1),
+                     "effective_gbs": round(ab / wall / 1e9, 1), "converged": bool(ok),
+                     "max_iters": max(i["iters"] for i in infos)}
+        log(f"batched {prec}: {1e3 * wall:.1f} ms per batch, ok={ok}")
+    out["mixed_speedup"] = round(out["fp64"]["ms_per_step"] / out["mixed"]["ms_per_step"], 3)
+    for op in ops:
+        op.close()
+    return out
+
+
 def cpu_baseline(prob, sample_iters, full_iters):
     """Time the FP64 oracle on a bounded sample of the same solve (single thread)."""
     import oracle as O
@@ -96,6 +135,8 @@ def main():
                          "(every 64th perturbs the solve time by < 0.5 %%; every 4th by ~7 %%)")
     ap.add_argument("--cpu-sample-iters", type=int, default=60)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the 64-system batched solve reported beside the main line")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="copy this many MiB once before timing (a kernel of known traffic "
                          "that calibrates FETCH_SIZE / WRITE_SIZE counters)")
@@ -229,6 +270,7 @@ def main():
             "mixed_speedup": round(main_path["value"] / fp64["value"], 3)},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "batched": None if args.no_batch else batched_line(args, dev),
     }
     print(json.dumps(line), flush=True)
     op.close()
