@@ -93,9 +93,17 @@ __device__ __forceinline__ void load_rhs(const cplx<R>* __restrict__ x, int64_t 
   }
 }
 
-// Pairs per round trip of the RR-rhs product (register budget ~ 120 VGPRs).
+// Pairs per round trip of the RR-rhs product (MSC_BATCH_KP32 / MSC_BATCH_KP64 at four
+// right-hand sides, twice that for fewer).
+#ifndef MSC_BATCH_KP32
+#define MSC_BATCH_KP32 4
+#endif
+#ifndef MSC_BATCH_KP64
+#define MSC_BATCH_KP64 2
+#endif
 template <class R, int RR> constexpr int kp_rhs() {
-  return std::is_same<R, float>::value ? (RR >= 4 ? 2 : 4) : (RR >= 4 ? 1 : 2);
+  return std::is_same<R, float>::value ? (RR >= 4 ? MSC_BATCH_KP32 : 2 * MSC_BATCH_KP32)
+                                       : (RR >= 4 ? MSC_BATCH_KP64 : 2 * MSC_BATCH_KP64);
 }
 
 template <class R, int RR, int KP, bool FULL>
