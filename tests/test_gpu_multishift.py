@@ -280,6 +280,26 @@ def test_sell_partial_last_slice(cuda):
     op.close()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_diagonal_operator(cuda, prec):
+    # M diagonal: every slice of the sliced copy is zero pairs wide, and the solution is
+    # known in closed form, x_k = b / (|d|^2 + sigma_k)
+    n = 200
+    rng = np.random.default_rng(8)
+    d = rng.uniform(0.5, 2.0, n) * np.exp(1j * rng.uniform(0, 2 * np.pi, n))
+    rowptr = np.arange(n + 1, dtype=np.int64)
+    col = np.arange(n, dtype=np.int32)
+    b = W.gaussian_rhs(n, 9)
+    sigma = np.array([0.0, 0.1, 1.0])
+    op = _op(dict(rowptr=rowptr, col=col, vals=d, n=n), cuda)
+    op.set_shifts(sigma)
+    x, info = op.solve(b, tol=1e-12, prec=prec, format="sell")
+    assert info["status"] == "ok"
+    exact = b[None, :] / (np.abs(d)[None, :] ** 2 + sigma[:, None])
+    assert np.all(_rel(x.cpu().numpy(), exact) <= 1e-10)
+    op.close()
+
+
 def test_sell_refused_when_padding_is_large(cuda):
     # one 60-entry row per 64-row slice, every other row holds only its diagonal: the
     # sliced copy would be ~30x the entry count, so it is not built and format="sell"
