@@ -768,8 +768,8 @@ struct BatchRun {
         S.mh64 = Csr<double2>{op->rowptr_h, op->col_h, op->val64_h};
         S.mh32 = Csr<float2>{op->rowptr_h, op->col_h, op->val32_h};
       }
-      S.sell = (op->sell && prm.format != MSC_FORMAT_CSR) ? 1 : 0;
-      if (S.sell) {
+      S.sell = 0;  // chosen by tune()
+      if (op->sell) {
         const SellStore& sm = op->sell_m;
         S.s64 = Sell<double2>{sm.cptr, sm.col, sm.val64, sm.diag64, sm.wp};
         S.s32 = Sell<float2>{sm.cptr, sm.col, sm.val32, sm.diag32, sm.wp};
@@ -856,11 +856,29 @@ struct BatchRun {
     return MSC_OK;
   }
 
-  // Lanes per row (rows per wavefront = 64 / lanes): measured on this batch when the
-  // caller leaves it open, over a few iterations of each candidate; cached per shape.
+  // SpMV layout of the batch, measured on this batch over a few iterations of each
+  // candidate and cached per shape: the sliced ELLPACK copies (one row per lane, 64 rows
+  // per wavefront; systems without a copy use CSR) or CSR throughout with 4, 8 or 16
+  // lanes per row (16, 8 or 4 rows per wavefront).  msc_params.format / lanes narrow the
+  // candidates.
   msc_status tune(const msc_params& prm) {
-    if (prm.lanes == 4 || prm.lanes == 8 || prm.lanes == 16) {
-      lanes = prm.lanes;
+    const bool fixed_lanes = prm.lanes == 4 || prm.lanes == 8 || prm.lanes == 16;
+    bool any_sell = false;
+    for (int s = 0; s < nsys; ++s) any_sell = any_sell || ops[s]->sell;
+    std::vector<std::pair<bool, int>> cands;  // (sliced ELLPACK where built, lanes)
+    if (any_sell && prm.format != MSC_FORMAT_CSR) cands.push_back({true, fixed_lanes ? prm.lanes : 8});
+    if (prm.format != MSC_FORMAT_SELL || !any_sell) {
+      if (fixed_lanes)
+        cands.push_back({false, prm.lanes});
+      else
+        for (int l : {4, 8, 16}) cands.push_back({false, l});
+    }
+    auto apply = [&](bool sell, int l) {
+      lanes = l;
+      for (int s = 0; s < nsys; ++s) sys[s].sell = (sell && ops[s]->sell) ? 1 : 0;
+    };
+    if (cands.size() == 1) {
+      apply(cands[0].first, cands[0].second);
       return MSC_OK;
     }
     TuneKey key{nsys, 0, 0};
@@ -868,11 +886,12 @@ struct BatchRun {
       key.rows += ops[s]->n;
       key.nnz += ops[s]->nnz;
     }
+    key.nsys += int64_t(prm.format) << 32;
     {
       std::lock_guard<std::mutex> lk(g_tune_mu);
       auto it = g_tune_cache.find(key);
       if (it != g_tune_cache.end()) {
-        lanes = it->second;
+        apply((it->second & 256) != 0, it->second & 255);
         return MSC_OK;
       }
     }
@@ -880,9 +899,9 @@ struct BatchRun {
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     float best = 1e30f;
-    int best_l = 8;
-    for (int cand : {4, 8, 16}) {
-      lanes = cand;
+    std::pair<bool, int> best_c = cands[0];
+    for (const auto& c : cands) {
+      apply(c.first, c.second);
       msc_status rc = reset(sint);
       if (rc != MSC_OK) return rc;
       HIP_TRY(launch_batch_iteration(args(), sint));  // warm-up
@@ -894,14 +913,14 @@ struct BatchRun {
       HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
       if (ms < best) {
         best = ms;
-        best_l = cand;
+        best_c = c;
       }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    lanes = best_l;
+    apply(best_c.first, best_c.second);
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune_cache[key] = lanes;
+    g_tune_cache[key] = best_c.second | (best_c.first ? 256 : 0);
     return MSC_OK;
   }
 

@@ -74,8 +74,10 @@ def test_batch_result_is_independent_of_companions(cuda):
     from paper_1102_2143_amd import solve_batched
     systems = _small_batch()
     ops = _ops(systems, cuda)
-    xs_all, _, st1 = solve_batched(ops, [p["b"] for p in systems], tol=1e-10, prec="fp64", lanes=8)
-    xs_one, _, st2 = solve_batched([ops[2]], [systems[2]["b"]], tol=1e-10, prec="fp64", lanes=8)
+    xs_all, _, st1 = solve_batched(ops, [p["b"] for p in systems], tol=1e-10, prec="fp64", lanes=8,
+                                    format="sell")
+    xs_one, _, st2 = solve_batched([ops[2]], [systems[2]["b"]], tol=1e-10, prec="fp64", lanes=8,
+                                    format="sell")
     assert st1 == "ok" and st2 == "ok"
     assert bool((xs_all[2] == xs_one[0]).all())
     for op in ops:
