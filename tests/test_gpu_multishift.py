@@ -184,6 +184,27 @@ def test_iteration_limit(c0, cuda):
     op.close()
 
 
+@pytest.mark.parametrize("fmt", ["sell", "csr"])
+def test_iteration_limit_in_the_complex64_phase(c0, cuda, fmt):
+    # the limit falls after the switch to complex64: the sequence stops there, and every
+    # shift's residual is as small as the oracle's after as many iterations (up to the
+    # complex64 rounding of the unconverged iterates)
+    op = _op(c0, cuda)
+    op.set_shifts(c0["sigma"])
+    x, info = op.solve(c0["b"], max_iter=60, refine=False, prec="mixed", switch_tol=0.3,
+                       format=fmt)
+    assert info["status"] == "notconv" and info["iters"] == 60
+    assert 0 < info["iters_fp64"] < 60
+    ref = O.cg_m(c0["apply"], c0["b"], c0["sigma"], tol=1e-10, max_iter=60)
+    xg = x.cpu().numpy()
+    bn = np.linalg.norm(c0["b"])
+    rho_g = np.array([np.linalg.norm(c0["b"] - c0["apply"](xg[k], s)) for k, s in enumerate(c0["sigma"])]) / bn
+    rho_o = np.array([np.linalg.norm(c0["b"] - c0["apply"](ref["x"][k], s)) for k, s in enumerate(c0["sigma"])]) / bn
+    assert np.all(rho_g <= 2.0 * rho_o + 1e-6), (rho_g, rho_o)
+    assert np.all(rho_o <= 2.0 * rho_g + 1e-6), (rho_g, rho_o)
+    op.close()
+
+
 def test_refinement_completes_a_truncated_sequence(c0, cuda):
     # three multishift iterations, then the FP64 batched refinement takes every shift
     # to tol from those iterates
