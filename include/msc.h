@@ -57,12 +57,17 @@ typedef enum {
 
 /* Matrix storage read by the SpMVs of the multishift iteration.  At creation the
  * library also builds a sliced ELLPACK copy (64-row slices, one row per lane, diagonal
- * held apart) when its padding stays below half the entry count; AUTO uses it when it
- * exists, SELL requires it (MSC_EINVAL otherwise), CSR forces the CSR kernels. */
+ * held apart) when its padding stays below half the entry count, and gives it 16-bit
+ * column offsets (from a 32-bit base per slice column and entry position) when every
+ * such column's entries span less than 65536 columns.  AUTO uses the copy when it
+ * exists, with the narrow columns when they exist; SELL requires the copy (MSC_EINVAL
+ * otherwise) and reads the narrow columns when they exist; SELL32 requires the copy and
+ * reads its 32-bit columns; CSR forces the CSR kernels. */
 typedef enum {
     MSC_FORMAT_AUTO = 0,
     MSC_FORMAT_CSR = 1,
-    MSC_FORMAT_SELL = 2
+    MSC_FORMAT_SELL = 2,
+    MSC_FORMAT_SELL32 = 3
 } msc_format;
 
 /* Solver parameters; fill with msc_params_default() and override fields. */
@@ -148,6 +153,12 @@ msc_status msc_op_set_shifts(msc_op op, const double* h_sigma, int32_t ns);
 
 /* Query the operator: any output pointer may be NULL. */
 msc_status msc_op_query(msc_op op, int64_t* n, int64_t* nnz, int32_t* ns, int32_t* kind);
+
+/* Storage the operator holds besides its CSR matrix (see msc_format): *sell = 1 when the
+ * sliced ELLPACK copy was built; *narrow has bit 0 set when the copy of the operator's
+ * matrix has 16-bit column offsets and, for MSC_A_MHM, bit 1 when the copy of M^H has
+ * them.  Either pointer may be NULL. */
+msc_status msc_op_storage(msc_op op, int32_t* sell, int32_t* narrow);
 
 /*
  * Apply the operator (no solve): d_out = (A + shift I) d_in for complex128 vectors of

@@ -16,13 +16,14 @@ LIB_PATH = os.environ.get("MSC_LIB", os.path.join(HERE, "libmsc.so"))
 MSC_OK, MSC_ENOTCONV, MSC_EINVAL, MSC_ENOMEM, MSC_EHIP, MSC_EBREAKDOWN = 0, 1, -1, -2, -3, -4
 MSC_A_MHM, MSC_A_HERM = 0, 1
 MSC_PREC_FP64, MSC_PREC_MIXED = 0, 1
-MSC_FORMAT_AUTO, MSC_FORMAT_CSR, MSC_FORMAT_SELL = 0, 1, 2
+MSC_FORMAT_AUTO, MSC_FORMAT_CSR, MSC_FORMAT_SELL, MSC_FORMAT_SELL32 = 0, 1, 2, 3
 
 STATUS_NAMES = {0: "ok", 1: "notconv", -1: "einval", -2: "enomem", -3: "ehip", -4: "breakdown"}
 
 EXPORTED = (
     "msc_params_default", "msc_version", "msc_last_error", "msc_op_create_csr",
-    "msc_op_update_values", "msc_op_set_shifts", "msc_op_query", "msc_op_apply", "msc_solve",
+    "msc_op_update_values", "msc_op_set_shifts", "msc_op_query", "msc_op_storage", "msc_op_apply",
+    "msc_solve",
     "msc_solve_adjoint", "msc_solve_batched", "msc_op_destroy",
 )
 
@@ -91,6 +92,8 @@ def load():
     lib.msc_op_query.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64),
                                  ctypes.POINTER(i32), ctypes.POINTER(i32)]
     lib.msc_op_query.restype = i32
+    lib.msc_op_storage.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    lib.msc_op_storage.restype = i32
     lib.msc_op_apply.argtypes = [vp, i32, vp, vp, dbl, vp]
     lib.msc_op_apply.restype = i32
     lib.msc_solve.argtypes = [vp, vp, vp, ctypes.POINTER(Params), ctypes.POINTER(Info), vp]

@@ -13,7 +13,8 @@ from . import _lib as L
 
 _PREC = {"fp64": L.MSC_PREC_FP64, "mixed": L.MSC_PREC_MIXED}
 _KIND = {"mhm": L.MSC_A_MHM, "herm": L.MSC_A_HERM}
-_FORMAT = {"auto": L.MSC_FORMAT_AUTO, "csr": L.MSC_FORMAT_CSR, "sell": L.MSC_FORMAT_SELL}
+_FORMAT = {"auto": L.MSC_FORMAT_AUTO, "csr": L.MSC_FORMAT_CSR, "sell": L.MSC_FORMAT_SELL,
+           "sell32": L.MSC_FORMAT_SELL32}
 
 
 def _stream(stream=None):
@@ -98,6 +99,16 @@ class Operator:
         if st != L.MSC_OK:
             raise L.MscError(st, "msc_op_set_shifts")
         self.sigma = s.copy()
+
+    def storage(self):
+        """{"sell": sliced ELLPACK copy built, "narrow": (matrix, M^H) copies with 16-bit
+        column offsets}."""
+        sell, narrow = ctypes.c_int32(), ctypes.c_int32()
+        st = self.lib.msc_op_storage(self.handle, ctypes.byref(sell), ctypes.byref(narrow))
+        if st != L.MSC_OK:
+            raise L.MscError(st, "msc_op_storage")
+        return {"sell": bool(sell.value),
+                "narrow": (bool(narrow.value & 1), bool(narrow.value & 2))}
 
     def update_values(self, vals, stream=None):
         vl = _dev_tensor(vals, torch.complex128, self.device)

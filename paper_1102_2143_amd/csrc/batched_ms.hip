@@ -130,9 +130,10 @@ __device__ __forceinline__ void gather_rhs_fma(const cplx<R>* __restrict__ x, in
 
 // Off-diagonal part of one sliced ELLPACK row per lane times the RR interleaved vectors
 // of x (slice `sl` wavefront-uniform); one read of the matrix row serves every rhs.
-template <class R, int RR>
-__device__ __forceinline__ void sell_row_rhs(const Sell<cplx<R>>& m, const cplx<R>* __restrict__ x,
-                                             int64_t sl, int lane, cplx<R> (&acc)[RR]) {
+template <class R, int RR, bool NARROW>
+__device__ __forceinline__ void sell_row_rhs_cols(const Sell<cplx<R>>& m,
+                                                  const cplx<R>* __restrict__ x, int64_t sl,
+                                                  int lane, cplx<R> (&acc)[RR]) {
   constexpr int KP = kp_rhs<R, RR>();
 #pragma unroll
   for (int q = 0; q < RR; ++q) acc[q] = czero<R>();
@@ -147,14 +148,22 @@ __device__ __forceinline__ void sell_row_rhs(const Sell<cplx<R>>& m, const cplx<
   int2 cc[KP];
   cplx<R> v[2 * KP];
   for (; c + KP <= c1; c += KP) {
-    sell_load<R, KP, true>(m, c, KP, lane, cc, v);
+    sell_load<R, KP, true, NARROW>(m, c, KP, lane, cc, v);
     gather_rhs_fma<R, RR, KP, true>(x, KP, cc, v, acc);
   }
   if (c < c1) {
     const int np = c1 - c;
-    sell_load<R, KP, false>(m, c, np, lane, cc, v);
+    sell_load<R, KP, false, NARROW>(m, c, np, lane, cc, v);
     gather_rhs_fma<R, RR, KP, false>(x, np, cc, v, acc);
   }
+}
+template <class R, int RR>
+__device__ __forceinline__ void sell_row_rhs(const Sell<cplx<R>>& m, const cplx<R>* __restrict__ x,
+                                             int64_t sl, int lane, cplx<R> (&acc)[RR]) {
+  if (m.col16)
+    sell_row_rhs_cols<R, RR, true>(m, x, sl, lane, acc);
+  else
+    sell_row_rhs_cols<R, RR, false>(m, x, sl, lane, acc);
 }
 
 // Per-rhs workgroup partials of a chunk: store, take the system's ticket; true in the

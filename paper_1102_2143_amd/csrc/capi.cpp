@@ -121,6 +121,24 @@ int choose_lanes(msc_op op, const msc_params& prm) {
   return 32;
 }
 
+// View of a sliced ELLPACK copy with one value precision; narrow columns when the copy
+// has them and `narrow` asks for them.
+template <class V>
+Sell<V> sell_view(const SellStore& m, const V* val, const V* diag, bool narrow) {
+  Sell<V> v{m.cptr, m.col, val, diag, m.wp};
+  if (narrow && m.col16) {
+    v.col16 = m.col16;
+    v.cbase = m.cbase;
+  }
+  return v;
+}
+
+// Bytes per column index of the matrix copy an SpMV reads (CSR and 32-bit sliced
+// ELLPACK: 4, narrow sliced ELLPACK: 2, the per-column bases being negligible).
+template <class V> double index_bytes(bool sell, const Sell<V>& m) {
+  return sell && m.col16 ? 2.0 : 4.0;
+}
+
 MsArgs make_args(msc_op op, int lanes, const double* d_b, double* d_x) {
   MsArgs a{};
   a.kind = op->kind;
@@ -139,12 +157,12 @@ MsArgs make_args(msc_op op, int lanes, const double* d_b, double* d_x) {
   if (op->sell) {
     const SellStore& sm = op->sell_m;
     a.nslices = sm.nslices;
-    a.s64 = Sell<double2>{sm.cptr, sm.col, sm.val64, sm.diag64, sm.wp};
-    a.s32 = Sell<float2>{sm.cptr, sm.col, sm.val32, sm.diag32, sm.wp};
+    a.s64 = sell_view(sm, sm.val64, sm.diag64, true);
+    a.s32 = sell_view(sm, sm.val32, sm.diag32, true);
     if (op->kind == MSC_A_MHM) {
       const SellStore& sh = op->sell_mh;
-      a.sh64 = Sell<double2>{sh.cptr, sh.col, sh.val64, sh.diag64, sh.wp};
-      a.sh32 = Sell<float2>{sh.cptr, sh.col, sh.val32, sh.diag32, sh.wp};
+      a.sh64 = sell_view(sh, sh.val64, sh.diag64, true);
+      a.sh32 = sell_view(sh, sh.val32, sh.diag32, true);
     }
   }
   a.b = reinterpret_cast<const double2*>(d_b);
@@ -168,23 +186,25 @@ MsArgs make_args(msc_op op, int lanes, const double* d_b, double* d_x) {
 struct KernelBytes {
   double k1, k2, upd, head;
 };
+// launch with `act` active shifts; ib / ibh: bytes per column index of the copies of the
+// operator's matrix and of M^H that the SpMVs read.
 KernelBytes kernel_bytes(int kind, int prec, double n, double nnz, double nnz_h, double act,
-                         bool pending) {
+                         bool pending, double ib, double ibh) {
   const double w = prec == MSC_PREC_MIXED ? 8.0 : 16.0;
   KernelBytes b{};
-  b.k1 = nnz * (w + 4.0) + 4.0 * (n + 1) + 2.0 * n * w;
-  b.k2 = (kind == MSC_A_MHM ? nnz_h * (w + 4.0) + 4.0 * (n + 1) + n * w : n * w) + 3.0 * n * w;
+  b.k1 = nnz * (w + ib) + 4.0 * (n + 1) + 2.0 * n * w;
+  b.k2 = (kind == MSC_A_MHM ? nnz_h * (w + ibh) + 4.0 * (n + 1) + n * w : n * w) + 3.0 * n * w;
   b.upd = pending ? n * (3.0 * w + 32.0) + act * n * (32.0 + 2.0 * w) : 0.0;
   b.head = b.k1 + (pending ? b.upd - n * w : 0.0);
   return b;
 }
 
 double iter_bytes(int kind, int prec, double n, double nnz, double nnz_h, double act_sum,
-                  double iters) {
+                  double iters, double ib, double ibh) {
   const double w = prec == MSC_PREC_MIXED ? 8.0 : 16.0;   // Krylov vector element
   const double vb = prec == MSC_PREC_MIXED ? 8.0 : 16.0;  // matrix value
-  const double mat = (nnz * (vb + 4.0) + 4.0 * (n + 1)) +
-                     (kind == MSC_A_MHM ? nnz_h * (vb + 4.0) + 4.0 * (n + 1) : 0.0);
+  const double mat = (nnz * (vb + ib) + 4.0 * (n + 1)) +
+                     (kind == MSC_A_MHM ? nnz_h * (vb + ibh) + 4.0 * (n + 1) : 0.0);
   double vec;
   if (kind == MSC_A_MHM)
     vec = n * (w + w) + n * (w + w + 2 * w);  // K1: p gather, t write; K2: t gather, p, r r/w
@@ -222,8 +242,8 @@ msc_status run_multishift(msc_op op, const double* d_b, double* d_x, const msc_p
   rc = ensure_workspace(op, prec, ns);
   if (rc != MSC_OK) return rc;
   const int lanes = choose_lanes(op, prm);
-  if (prm.format < MSC_FORMAT_AUTO || prm.format > MSC_FORMAT_SELL ||
-      (prm.format == MSC_FORMAT_SELL && !op->sell)) {
+  if (prm.format < MSC_FORMAT_AUTO || prm.format > MSC_FORMAT_SELL32 ||
+      ((prm.format == MSC_FORMAT_SELL || prm.format == MSC_FORMAT_SELL32) && !op->sell)) {
     set_error("msc_solve: format %d unavailable (sliced ELLPACK copy %s)", prm.format,
               op->sell ? "built" : "not built: padding too large");
     return MSC_EINVAL;
@@ -231,6 +251,16 @@ msc_status run_multishift(msc_op op, const double* d_b, double* d_x, const msc_p
   MsArgs a64 = make_args(op, lanes, d_b, d_x);
   if (prm.max_grid > 0) a64.grid = std::min(prm.max_grid, kMaxGrid);
   if (prm.format == MSC_FORMAT_CSR) a64.sell = 0;
+  if (prm.format == MSC_FORMAT_SELL32 && op->sell) {
+    const SellStore &sm = op->sell_m, &sh = op->sell_mh;
+    a64.s64 = sell_view(sm, sm.val64, sm.diag64, false);
+    a64.s32 = sell_view(sm, sm.val32, sm.diag32, false);
+    if (op->kind == MSC_A_MHM) {
+      a64.sh64 = sell_view(sh, sh.val64, sh.diag64, false);
+      a64.sh32 = sell_view(sh, sh.val32, sh.diag32, false);
+    }
+  }
+  const double ib = index_bytes(a64.sell, a64.s64), ibh = index_bytes(a64.sell, a64.sh64);
   MsArgs a32 = a64;
   const bool mixed = prec == MSC_PREC_MIXED;
   if (mixed) {
@@ -356,7 +386,7 @@ msc_status run_multishift(msc_op op, const double* d_b, double* d_x, const msc_p
         if (last >= done_before + 1) ++act;
       }
       const KernelBytes kb = kernel_bytes(op->kind, ph32 ? MSC_PREC_MIXED : prec, nn, nz, nzh,
-                                          double(act), pending);
+                                          double(act), pending, ib, ibh);
       info->kernel_bytes[0] += a64.sell ? kb.head : kb.k1;
       info->kernel_bytes[1] += kb.k2;
       if (!a64.sell) info->kernel_bytes[2] += kb.upd;
@@ -385,8 +415,9 @@ msc_status run_multishift(msc_op op, const double* d_b, double* d_x, const msc_p
     act32 += std::max(0, last - iters_fp64);
   }
   const double nn = double(op->n), nz = double(op->nnz), nzh = double(op->nnz_h);
-  *bytes_out = iter_bytes(op->kind, MSC_PREC_FP64, nn, nz, nzh, act64, double(iters_fp64)) +
-               iter_bytes(op->kind, MSC_PREC_MIXED, nn, nz, nzh, act32, double(fin.iter - iters_fp64)) +
+  *bytes_out = iter_bytes(op->kind, MSC_PREC_FP64, nn, nz, nzh, act64, double(iters_fp64), ib, ibh) +
+               iter_bytes(op->kind, MSC_PREC_MIXED, nn, nz, nzh, act32,
+                          double(fin.iter - iters_fp64), ib, ibh) +
                double(h.n_reliable) * ((op->kind == MSC_A_MHM ? 2.0 : 1.0) * (nz * 20.0 + 4.0 * (nn + 1)) +
                                        nn * (16.0 * 3 + 8.0));
   // the fused head reads the old direction once for the update and the product
@@ -771,12 +802,13 @@ struct BatchRun {
       S.sell = 0;  // chosen by tune()
       if (op->sell) {
         const SellStore& sm = op->sell_m;
-        S.s64 = Sell<double2>{sm.cptr, sm.col, sm.val64, sm.diag64, sm.wp};
-        S.s32 = Sell<float2>{sm.cptr, sm.col, sm.val32, sm.diag32, sm.wp};
+        const bool narrow = prm.format != MSC_FORMAT_SELL32;
+        S.s64 = sell_view(sm, sm.val64, sm.diag64, narrow);
+        S.s32 = sell_view(sm, sm.val32, sm.diag32, narrow);
         if (op->kind == MSC_A_MHM) {
           const SellStore& sh = op->sell_mh;
-          S.sh64 = Sell<double2>{sh.cptr, sh.col, sh.val64, sh.diag64, sh.wp};
-          S.sh32 = Sell<float2>{sh.cptr, sh.col, sh.val32, sh.diag32, sh.wp};
+          S.sh64 = sell_view(sh, sh.val64, sh.diag64, narrow);
+          S.sh32 = sell_view(sh, sh.val32, sh.diag32, narrow);
         }
       }
       S.b = reinterpret_cast<const double2*>(d_b[s]);
@@ -867,7 +899,7 @@ struct BatchRun {
     for (int s = 0; s < nsys; ++s) any_sell = any_sell || ops[s]->sell;
     std::vector<std::pair<bool, int>> cands;  // (sliced ELLPACK where built, lanes)
     if (any_sell && prm.format != MSC_FORMAT_CSR) cands.push_back({true, fixed_lanes ? prm.lanes : 8});
-    if (prm.format != MSC_FORMAT_SELL || !any_sell) {
+    if ((prm.format != MSC_FORMAT_SELL && prm.format != MSC_FORMAT_SELL32) || !any_sell) {
       if (fixed_lanes)
         cands.push_back({false, prm.lanes});
       else
@@ -1088,11 +1120,13 @@ struct BatchRun {
             act32 += std::max(0, last - i64);
           }
           const double nn = double(n), nz = double(op->nnz), nzh = double(op->nnz_h);
-          I.alg_bytes = (iter_bytes(op->kind, MSC_PREC_FP64, nn, nz, nzh, act64, i64) +
-                         iter_bytes(op->kind, MSC_PREC_MIXED, nn, nz, nzh, act32, it - i64)) /
-                            1.0 -
+          const double ib = index_bytes(sys[s].sell, sys[s].s64);
+          const double ibh = index_bytes(sys[s].sell, sys[s].sh64);
+          I.alg_bytes = iter_bytes(op->kind, MSC_PREC_FP64, nn, nz, nzh, act64, i64, ib, ibh) +
+                        iter_bytes(op->kind, MSC_PREC_MIXED, nn, nz, nzh, act32, it - i64, ib, ibh) -
                         (double(nrhs[s]) - 1.0) / double(nrhs[s]) *
-                            ((nz + nzh) * 20.0 * i64 + (nz + nzh) * 12.0 * (it - i64));
+                            ((nz * (16.0 + ib) + nzh * (16.0 + ibh)) * i64 +
+                             (nz * (8.0 + ib) + nzh * (8.0 + ibh)) * (it - i64));
           I.seconds = 0.0;
         }
       }
@@ -1281,6 +1315,15 @@ msc_status msc_op_query(msc_op op, int64_t* n, int64_t* nnz, int32_t* ns, int32_
   if (nnz) *nnz = op->nnz;
   if (ns) *ns = int32_t(op->sigma.size());
   if (kind) *kind = op->kind;
+  return MSC_OK;
+}
+
+msc_status msc_op_storage(msc_op op, int32_t* sell, int32_t* narrow) {
+  if (check_op(op) != MSC_OK) return MSC_EINVAL;
+  if (sell) *sell = op->sell ? 1 : 0;
+  if (narrow)
+    *narrow = (op->sell && op->sell_m.col16 ? 1 : 0) |
+              (op->sell && op->kind == MSC_A_MHM && op->sell_mh.col16 ? 2 : 0);
   return MSC_OK;
 }
 
@@ -1513,8 +1556,9 @@ msc_status msc_solve_batched(int32_t nsys, const msc_op* ops, const int32_t* nrh
   else
     msc_params_default(&prm);
   if (!(prm.tol >= 0.0) || (prm.prec != MSC_PREC_FP64 && prm.prec != MSC_PREC_MIXED) ||
-      !(prm.mixed_margin > 0.0 && prm.mixed_margin <= 1.0)) {
-    set_error("msc_solve_batched: invalid tol, precision or mixed_margin");
+      !(prm.mixed_margin > 0.0 && prm.mixed_margin <= 1.0) ||
+      prm.format < MSC_FORMAT_AUTO || prm.format > MSC_FORMAT_SELL32) {
+    set_error("msc_solve_batched: invalid tol, precision, mixed_margin or format");
     return MSC_EINVAL;
   }
   int rr = 1, max_nrhs = 0;

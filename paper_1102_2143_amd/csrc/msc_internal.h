@@ -94,6 +94,12 @@ template <class V> struct Sell {
   const V* val = nullptr;
   const V* diag = nullptr;        // n
   int32_t wp = 0;                 // > 0: every slice is wp pairs wide (cptr[s] = s wp)
+  // Narrow columns (both set, or both null: then col is read).  Entry position e of pair
+  // column c (e = 0, 1; c counts pair columns over all slices) has base cbase[2c + e];
+  // the pair of lane l holds the two 16-bit offsets from those bases, entry 0 in the low
+  // half, at col16[c kSlice + l].
+  const uint32_t* col16 = nullptr;
+  const int32_t* cbase = nullptr;
 };
 
 // Device buffers of one sliced ELLPACK matrix (both value precisions share the columns).
@@ -107,6 +113,8 @@ struct SellStore {
   float2* val32 = nullptr;
   double2* diag64 = nullptr;
   float2* diag32 = nullptr;
+  uint32_t* col16 = nullptr;      // narrow columns, when every slice column's entries span
+  int32_t* cbase = nullptr;       // less than 2^16 (else both null)
 };
 
 struct Workspace {
@@ -186,7 +194,8 @@ hipError_t build_adjoint(const int32_t* rowptr, const int32_t* col, int64_t n, i
 hipError_t launch_adjoint_vals(const int32_t* perm_h, const double2* val64, double2* val64_h,
                                float2* val32_h, int64_t nnz, hipStream_t s);
 // Build the sliced ELLPACK copy of a CSR matrix into `out` when its padding stays small
-// (slots <= 1.5 nnz + 2 kSlice per slice); *built tells whether it was.  Synchronises `s`.
+// (slots <= 1.5 nnz + 2 kSlice per slice); *built tells whether it was.  The narrow
+// columns are added when every slice column's entries span less than 2^16.  Synchronises `s`.
 hipError_t build_sell(const int32_t* rowptr, const int32_t* col, const double2* val64, int64_t n,
                       int64_t nnz, SellStore& out, bool* built, hipStream_t s);
 // Rewrite the values (and diagonal) of a built copy from the CSR values.

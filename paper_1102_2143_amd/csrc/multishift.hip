@@ -75,9 +75,10 @@ __device__ __forceinline__ void sell_gather_fma(const cplx<R>* __restrict__ x, i
 // Off-diagonal part of the product of one sliced ELLPACK row per lane with x; slice `sl`
 // is wavefront-uniform.  Pairs go KP at a time: a chunk's column and value loads, then
 // its gathers, are all issued before its first multiply-add.
-template <class R>
-__device__ __forceinline__ cplx<R> sell_row(const Sell<cplx<R>>& m, const cplx<R>* __restrict__ x,
-                                            int64_t sl, int lane) {
+template <class R, bool NARROW>
+__device__ __forceinline__ cplx<R> sell_row_cols(const Sell<cplx<R>>& m,
+                                                 const cplx<R>* __restrict__ x, int64_t sl,
+                                                 int lane) {
   constexpr int KP = sell_kp<R>();
   int32_t c, c1;
   if (m.wp > 0) {
@@ -91,15 +92,20 @@ __device__ __forceinline__ cplx<R> sell_row(const Sell<cplx<R>>& m, const cplx<R
   int2 cc[KP];
   cplx<R> v[2 * KP];
   for (; c + KP <= c1; c += KP) {
-    sell_load<R, KP, true>(m, c, KP, lane, cc, v);
+    sell_load<R, KP, true, NARROW>(m, c, KP, lane, cc, v);
     sell_gather_fma<R, KP, true>(x, KP, cc, v, acc);
   }
   if (c < c1) {
     const int np = c1 - c;
-    sell_load<R, KP, false>(m, c, np, lane, cc, v);
+    sell_load<R, KP, false, NARROW>(m, c, np, lane, cc, v);
     sell_gather_fma<R, KP, false>(x, np, cc, v, acc);
   }
   return acc;
+}
+template <class R>
+__device__ __forceinline__ cplx<R> sell_row(const Sell<cplx<R>>& m, const cplx<R>* __restrict__ x,
+                                            int64_t sl, int lane) {
+  return m.col16 ? sell_row_cols<R, true>(m, x, sl, lane) : sell_row_cols<R, false>(m, x, sl, lane);
 }
 
 // The next direction r + b p, formed in FP64 and rounded once; a lane that gathers p'
@@ -147,11 +153,11 @@ __device__ __forceinline__ void sell_gather2_fma(const cplx<R>* __restrict__ r,
 
 // Off-diagonal part of one sliced ELLPACK row per lane times p' = r + b p, with p' formed
 // at each gathered column.
-template <class R>
-__device__ __forceinline__ cplx<R> sell_row_next(const Sell<cplx<R>>& m,
-                                                 const cplx<R>* __restrict__ r,
-                                                 const cplx<R>* __restrict__ p, double b,
-                                                 int64_t sl, int lane) {
+template <class R, bool NARROW>
+__device__ __forceinline__ cplx<R> sell_row_next_cols(const Sell<cplx<R>>& m,
+                                                      const cplx<R>* __restrict__ r,
+                                                      const cplx<R>* __restrict__ p, double b,
+                                                      int64_t sl, int lane) {
   constexpr int KP = sell_kp_next<R>();
   int32_t c, c1;
   if (m.wp > 0) {
@@ -165,15 +171,23 @@ __device__ __forceinline__ cplx<R> sell_row_next(const Sell<cplx<R>>& m,
   int2 cc[KP];
   cplx<R> v[2 * KP];
   for (; c + KP <= c1; c += KP) {
-    sell_load<R, KP, true>(m, c, KP, lane, cc, v);
+    sell_load<R, KP, true, NARROW>(m, c, KP, lane, cc, v);
     sell_gather2_fma<R, KP, true>(r, p, b, KP, cc, v, acc);
   }
   if (c < c1) {
     const int np = c1 - c;
-    sell_load<R, KP, false>(m, c, np, lane, cc, v);
+    sell_load<R, KP, false, NARROW>(m, c, np, lane, cc, v);
     sell_gather2_fma<R, KP, false>(r, p, b, np, cc, v, acc);
   }
   return acc;
+}
+template <class R>
+__device__ __forceinline__ cplx<R> sell_row_next(const Sell<cplx<R>>& m,
+                                                 const cplx<R>* __restrict__ r,
+                                                 const cplx<R>* __restrict__ p, double b,
+                                                 int64_t sl, int lane) {
+  return m.col16 ? sell_row_next_cols<R, true>(m, r, p, b, sl, lane)
+                 : sell_row_next_cols<R, false>(m, r, p, b, sl, lane);
 }
 
 // One CSR row times a vector, L lanes per row; the sum is returned in every lane.

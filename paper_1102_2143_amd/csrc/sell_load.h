@@ -41,29 +41,41 @@ __device__ __forceinline__ int2 load_cols(const int32_t* __restrict__ col, int64
   return int2{c.x, c.y};
 }
 
+// Slice offsets and column bases are read through the scalar cache: the address is
+// wavefront-uniform and the arrays are never written while a solve runs.
+__device__ __forceinline__ int32_t load_uniform(const int32_t* p, int64_t i) {
+  using cptr_t = const __attribute__((address_space(4))) int32_t*;
+  return ((cptr_t)p)[i];
+}
+
+// Columns of pair q = c kSlice + lane (c wavefront-uniform): 32-bit, or (NARROW) the two
+// 16-bit offsets added to the pair column's bases.
+template <bool NARROW, class V>
+__device__ __forceinline__ int2 sell_cols(const Sell<V>& m, int32_t c, int64_t q) {
+  if (NARROW) {
+    const uint32_t w = stream_load(m.col16 + q);
+    return int2{load_uniform(m.cbase, 2 * int64_t(c)) + int32_t(w & 0xffffu),
+                load_uniform(m.cbase, 2 * int64_t(c) + 1) + int32_t(w >> 16)};
+  }
+  return load_cols(m.col, q);
+}
+
 // Column and value loads of KP pairs starting at pair column c (np < KP: only the first
 // np pairs exist; the rest read as zero).
-template <class R, int KP, bool FULL>
+template <class R, int KP, bool FULL, bool NARROW>
 __device__ __forceinline__ void sell_load(const Sell<cplx<R>>& m, int32_t c, int np, int lane,
                                           int2 (&cc)[KP], cplx<R> (&v)[2 * KP]) {
 #pragma unroll
   for (int u = 0; u < KP; ++u) {
     if (FULL || u < np) {
       const int64_t q = int64_t(c + u) * kSlice + lane;
-      cc[u] = load_cols(m.col, q);
+      cc[u] = sell_cols<NARROW>(m, c + u, q);
       load_pair(m.val, q, v[2 * u], v[2 * u + 1]);
     } else {
       cc[u] = int2{0, 0};
       v[2 * u] = v[2 * u + 1] = czero<R>();
     }
   }
-}
-
-// Slice offsets are read through the scalar cache: the address is wavefront-uniform and
-// the array is never written while a solve runs.
-__device__ __forceinline__ int32_t load_uniform(const int32_t* p, int64_t i) {
-  using cptr_t = const __attribute__((address_space(4))) int32_t*;
-  return ((cptr_t)p)[i];
 }
 
 }  // namespace msc

@@ -228,12 +228,45 @@ __global__ void k_sell_fill(const int32_t* __restrict__ rowptr, const int32_t* _
     d64[i] = d;
     d32[i] = float2{float(d.x), float(d.y)};
   }
-  const int32_t pad = i < n ? int32_t(i) : 0;
+  // padding points at the row itself (slots past n: at the last row), so that it stays
+  // inside the column span of its neighbours
+  const int32_t pad = int32_t(i < n ? i : n - 1);
   for (; k < width; ++k) {
     const int64_t at = base + int64_t(k >> 1) * (2 * kSlice) + (k & 1);
     scol[at] = pad;
     sv64[at] = double2{0.0, 0.0};
     sv32[at] = float2{0.f, 0.f};
+  }
+}
+
+// Narrow columns of a built copy: one wavefront per slice.  For each pair column and
+// entry position the wavefront minimum is the base and each lane keeps its 16-bit offset;
+// *wide is set when some span reaches 2^16 (the narrow copy is then unusable).
+__global__ void __launch_bounds__(kSlice) k_sell_narrow(const int32_t* __restrict__ cptr,
+                                                      const int32_t* __restrict__ scol,
+                                                      uint32_t* __restrict__ col16,
+                                                      int32_t* __restrict__ cbase,
+                                                      int* __restrict__ wide) {
+  const int64_t sl = blockIdx.x;
+  const int lane = int(threadIdx.x);
+  const int32_t c1 = cptr[sl + 1];
+  for (int32_t c = cptr[sl]; c < c1; ++c) {
+    const int64_t q = int64_t(c) * kSlice + lane;
+    const int32_t e0 = scol[2 * q], e1 = scol[2 * q + 1];
+    int32_t lo0 = e0, hi0 = e0, lo1 = e1, hi1 = e1;
+#pragma unroll
+    for (int off = kSlice / 2; off > 0; off >>= 1) {
+      lo0 = min(lo0, __shfl_xor(lo0, off, kSlice));
+      hi0 = max(hi0, __shfl_xor(hi0, off, kSlice));
+      lo1 = min(lo1, __shfl_xor(lo1, off, kSlice));
+      hi1 = max(hi1, __shfl_xor(hi1, off, kSlice));
+    }
+    if (lane == 0 && (hi0 - lo0 > 0xffff || hi1 - lo1 > 0xffff)) *wide = 1;
+    col16[q] = uint32_t(e0 - lo0) | (uint32_t(e1 - lo1) << 16);
+    if (lane == 0) {
+      cbase[2 * int64_t(c)] = lo0;
+      cbase[2 * int64_t(c) + 1] = lo1;
+    }
   }
 }
 
@@ -297,7 +330,8 @@ hipError_t launch_adjoint_vals(const int32_t* perm_h, const double2* val64, doub
 void free_sell(SellStore& m) {
   for (void* q : {static_cast<void*>(m.cptr), static_cast<void*>(m.col), static_cast<void*>(m.val64),
                   static_cast<void*>(m.val32), static_cast<void*>(m.diag64),
-                  static_cast<void*>(m.diag32)})
+                  static_cast<void*>(m.diag32), static_cast<void*>(m.col16),
+                  static_cast<void*>(m.cbase)})
     if (q) (void)hipFree(q);
   m = SellStore{};
 }
@@ -359,6 +393,37 @@ hipError_t build_sell(const int32_t* rowptr, const int32_t* col, const double2* 
     return e;
   }
   *built = true;
+  if (total == 0) return hipSuccess;
+  // narrow columns: kept only when every span fits
+  int* wide = nullptr;
+  if ((e = hipMalloc(&m.col16, sizeof(uint32_t) * total * kSlice)) != hipSuccess ||
+      (e = hipMalloc(&m.cbase, sizeof(int32_t) * 2 * total)) != hipSuccess ||
+      (e = hipMalloc(&wide, sizeof(int))) != hipSuccess) {
+    if (wide) (void)hipFree(wide);
+    free_sell(m);
+    *built = false;
+    return e;
+  }
+  int h_wide = 0;
+  e = hipMemsetAsync(wide, 0, sizeof(int), s);
+  if (e == hipSuccess) {
+    k_sell_narrow<<<dim3(unsigned(nslices)), kSlice, 0, s>>>(m.cptr, m.col, m.col16, m.cbase, wide);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(&h_wide, wide, sizeof(int), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(wide);
+  if (e != hipSuccess) {
+    free_sell(m);
+    *built = false;
+    return e;
+  }
+  if (h_wide) {
+    (void)hipFree(m.col16);
+    (void)hipFree(m.cbase);
+    m.col16 = nullptr;
+    m.cbase = nullptr;
+  }
   return hipSuccess;
 }
 

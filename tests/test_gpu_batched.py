@@ -35,9 +35,10 @@ def _ops(systems, cuda):
 
 
 @pytest.mark.parametrize("prec,fmt", [("fp64", "auto"), ("mixed", "auto"), ("fp64", "csr"),
-                                      ("mixed", "csr")])
+                                      ("mixed", "csr"), ("fp64", "sell32"), ("mixed", "sell32")])
 def test_small_batch_matches_oracle(cuda, prec, fmt):
-    # "auto": the SpMVs read each system's sliced ELLPACK copy; "csr": the CSR kernels
+    # "auto": the SpMVs read each system's sliced ELLPACK copy (16-bit column offsets);
+    # "sell32": the same copy with its 32-bit columns; "csr": the CSR kernels
     print(f"[gpu] batched small {prec} {fmt}", flush=True)
     from paper_1102_2143_amd import solve_batched
     systems = _small_batch()
@@ -80,6 +81,12 @@ def test_batch_result_is_independent_of_companions(cuda):
                                     format="sell")
     assert st1 == "ok" and st2 == "ok"
     assert bool((xs_all[2] == xs_one[0]).all())
+    # the 32-bit and the 16-bit columns name the same entries: the same bits
+    xs_w, _, st3 = solve_batched(ops, [p["b"] for p in systems], tol=1e-10, prec="fp64", lanes=8,
+                                 format="sell32")
+    assert st3 == "ok"
+    for a, b in zip(xs_all, xs_w):
+        assert bool((a == b).all())
     for op in ops:
         op.close()
 

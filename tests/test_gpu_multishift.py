@@ -129,7 +129,7 @@ def test_shift_order_and_duplicates(c0, cuda):
     op.close()
 
 
-@pytest.mark.parametrize("fmt", ["auto", "csr", "sell"])
+@pytest.mark.parametrize("fmt", ["auto", "csr", "sell", "sell32"])
 def test_herm_laplacian(cuda, fmt):
     # 315 rows: four full 64-row slices and a partial one; boundary rows are shorter
     print(f"[gpu] herm laplacian {fmt}", flush=True)
@@ -248,7 +248,7 @@ def test_invalid_csr_rejected(cuda):
                  device=cuda)
 
 
-@pytest.mark.parametrize("fmt", ["csr", "sell"])
+@pytest.mark.parametrize("fmt", ["csr", "sell", "sell32"])
 def test_update_values(c0, cuda, fmt):
     # new values reach both the CSR arrays and the sliced ELLPACK copies
     op = _op(c0, cuda)
@@ -262,7 +262,7 @@ def test_update_values(c0, cuda, fmt):
 
 
 # ---- matrix formats of the iteration SpMVs ------------------------------------------------
-@pytest.mark.parametrize("fmt", ["csr", "sell"])
+@pytest.mark.parametrize("fmt", ["csr", "sell", "sell32"])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_c0_both_formats_match_oracle(c0, cuda, fmt, prec):
     print(f"[gpu] c0 {prec} format={fmt}", flush=True)
@@ -279,6 +279,73 @@ def test_c0_both_formats_match_oracle(c0, cuda, fmt, prec):
         ref7 = O.cg_m(c0["apply"], c0["b"], c0["sigma"], tol=0.7e-10)
         assert info["iters"] <= 1.03 * ref7["iters"] + 2
     assert np.all(info["true_rel_res"] <= 1e-10)
+    op.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_narrow_and_wide_columns_agree_bitwise(c0, cuda, prec):
+    # the lattice's slice columns span a few hundred columns, so both copies get 16-bit
+    # offsets; they name the same entries as the 32-bit columns, so the solves agree in
+    # every bit, and the sampled kernels' byte counts differ by 2 bytes per entry read
+    op = _op(c0, cuda)
+    assert op.storage() == {"sell": True, "narrow": (True, True)}
+    op.set_shifts(c0["sigma"])
+    x16, i16 = op.solve(c0["b"], tol=1e-10, prec=prec, format="sell", timing=8)
+    x32, i32 = op.solve(c0["b"], tol=1e-10, prec=prec, format="sell32", timing=8)
+    assert i16["status"] == "ok" and i32["status"] == "ok"
+    assert bool((x16 == x32).all())
+    assert i16["iters"] == i32["iters"] and i16["kernel_samples"] == i32["kernel_samples"]
+    nnz = len(c0["col"])  # M and M^H hold the same number of entries
+    for k in range(2):  # the head reads M, K2 reads M^H
+        saved = i32["kernel_bytes"][k] - i16["kernel_bytes"][k]
+        assert saved == pytest.approx(2.0 * nnz * i16["kernel_samples"], rel=1e-12)
+    op.close()
+
+
+def _chain_problem(n, far, seed):
+    # M: diagonal d_i plus one off-diagonal entry per row at column i + 1 (the last row
+    # has none), except row 0, whose entry sits at column `far`.  Lanes 1..63 of the first
+    # slice reach columns 2..64, so its first slice column spans far - 2 columns.
+    rng = np.random.default_rng(seed)
+    d = rng.uniform(2.0, 3.0, n) * np.exp(1j * rng.uniform(0, 2 * np.pi, n))
+    e = rng.uniform(0.2, 0.8, n - 1) * np.exp(1j * rng.uniform(0, 2 * np.pi, n - 1))
+    counts = np.full(n, 2, np.int64)
+    counts[-1] = 1
+    rowptr = np.zeros(n + 1, np.int64)
+    rowptr[1:] = np.cumsum(counts)
+    col = np.empty(rowptr[-1], np.int32)
+    vals = np.empty(rowptr[-1], np.complex128)
+    i = np.arange(n - 1)
+    col[rowptr[i]] = i
+    col[rowptr[i] + 1] = i + 1
+    col[1] = far
+    vals[rowptr[i]] = d[:-1]
+    vals[rowptr[i] + 1] = e
+    col[-1] = n - 1
+    vals[-1] = d[-1]
+    return dict(rowptr=rowptr, col=col, vals=vals, n=n, kind="mhm",
+                b=W.gaussian_rhs(n, seed + 1), sigma=np.array([0.0, 0.3, 3.0]))
+
+
+@pytest.mark.parametrize("far,narrow", [(65537, True), (65538, False)])
+def test_narrow_columns_at_the_span_limit(cuda, far, narrow):
+    # a slice column spanning 65535 columns still takes 16-bit offsets, one spanning
+    # 65536 keeps the copy on 32-bit columns; both solve to the oracle's answer
+    print(f"[gpu] chain operator, far column {far}", flush=True)
+    p = _chain_problem(66000, far, 17)
+    op = _op(p, cuda)
+    st = op.storage()
+    assert st["sell"] and st["narrow"][0] == narrow
+    op.set_shifts(p["sigma"])
+    ap = O.shifted_apply("mhm", p["rowptr"], p["col"], p["vals"], p["n"])
+    ref = O.cg_m(ap, p["b"], p["sigma"], tol=1e-12)
+    xs = {}
+    for fmt in ("sell", "sell32"):
+        xs[fmt], info = op.solve(p["b"], tol=1e-12, format=fmt)
+        assert info["status"] == "ok"
+        assert abs(info["iters"] - ref["iters"]) <= 2
+        assert np.all(_rel(xs[fmt].cpu().numpy(), ref["x"]) <= 1e-9)
+    assert bool((xs["sell"] == xs["sell32"]).all())
     op.close()
 
 
@@ -353,7 +420,7 @@ def test_sell_refused_when_padding_is_large(cuda):
     op.close()
 
 
-@pytest.mark.parametrize("fmt", ["sell", "csr"])
+@pytest.mark.parametrize("fmt", ["sell", "sell32", "csr"])
 def test_kernel_timing_samples(c0, cuda, fmt):
     # timing attaches start/stop events to the sampled dispatches: the head and K2 on the
     # sliced ELLPACK path (the update runs inside the head), K1, K2 and the separate
@@ -364,7 +431,7 @@ def test_kernel_timing_samples(c0, cuda, fmt):
     assert info["status"] == "ok"
     assert info["kernel_samples"] > 0
     assert np.all(info["kernel_ms"][:2] > 0)
-    if fmt == "sell":
+    if fmt != "csr":
         assert info["kernel_ms"][2] == 0
     else:
         assert info["kernel_ms"][2] > 0
