@@ -11,8 +11,11 @@
 // An outer defect-correction cycle recomputes f_j - (A + sigma_j) x_j in FP64 (the
 // multi-vector kernels below), the inner CG runs in the working precision from e = 0,
 // and x_j += e_j is accumulated in FP64.
+#include <type_traits>
+
 #include "dev_common.h"
 #include "msc_internal.h"
+#include "sell_load.h"
 
 namespace msc {
 
@@ -55,6 +58,61 @@ __device__ __forceinline__ void sum_system_partials(const double* partial, int c
   __syncthreads();
 }
 
+// After the partials of IK1 are stored: the last workgroup forms a_j = R_j / P_j.
+__device__ void ik1_finish(const BssArgs& a) {
+  BssState* st = a.st;
+  if (!arrive_last(a.tickets + 8 * kTicketSite)) return;
+  __shared__ double tot[kBssMax];
+  sum_system_partials(a.partial, gridDim.x, tot);
+  const int q = threadIdx.x;
+  if (q < st->m && st->active[q]) {
+    const double P = tot[q];
+    if (P > 0.0 && isfinite(P)) {
+      st->a[q] = st->R[q] / P;
+    } else {
+      st->a[q] = 0.0;
+      st->active[q] = 0;
+      st->bad[q] = 1;
+    }
+  }
+}
+
+// After the partials of IK2 are stored: the last workgroup forms b_j and R_j, retires
+// converged systems and decides whether the batch halts.
+__device__ void ik2_finish(const BssArgs& a) {
+  BssState* st = a.st;
+  if (!arrive_last(a.tickets + 9 * kTicketSite)) return;
+  __shared__ double tot[kBssMax];
+  sum_system_partials(a.partial, gridDim.x, tot);
+  if (threadIdx.x < kWave) {
+    const int qq = threadIdx.x;
+    bool upd = false, act = false;
+    if (qq < st->m && st->active[qq]) {
+      const double Rn = tot[qq];
+      upd = true;
+      if (!isfinite(Rn)) {
+        st->bad[qq] = 1;
+        st->active[qq] = 0;
+        upd = false;
+      } else {
+        st->b[qq] = Rn / st->R[qq];
+        st->R[qq] = Rn;
+        st->iters[qq] += 1;
+        if (Rn <= st->target2[qq]) st->active[qq] = 0;
+        act = st->active[qq] != 0;
+      }
+    }
+    if (qq < kBssMax) st->upd[qq] = upd ? 1 : 0;
+    const uint64_t am = __ballot(act);
+    if (qq == 0) {
+      st->iter += 1;
+      st->nact = __popcll(am);
+      if (st->nact == 0 || st->iter >= st->max_iter) st->halt = 1;
+      st->k3_enable = 1;
+    }
+  }
+}
+
 // ---- IK1: t_j = A1 p_j and P_j = p_j^H (A + sigma_j) p_j ----------------------------
 template <class R, int MP, bool MHM>
 __global__ __launch_bounds__(kBlock) void ik1(BssArgs a) {
@@ -95,20 +153,7 @@ __global__ __launch_bounds__(kBlock) void ik1(BssArgs a) {
       acc += double(pr.x) * double(sum.x) + double(pr.y) * double(sum.y) + sig * norm2d<R>(pr);
   }
   store_system_partials<MP>(acc, a.partial);
-  if (!arrive_last(a.tickets + 8 * kTicketSite)) return;
-  __shared__ double tot[kBssMax];
-  sum_system_partials(a.partial, gridDim.x, tot);
-  const int q = threadIdx.x;
-  if (q < st->m && st->active[q]) {
-    const double P = tot[q];
-    if (P > 0.0 && isfinite(P)) {
-      st->a[q] = st->R[q] / P;
-    } else {
-      st->a[q] = 0.0;
-      st->active[q] = 0;
-      st->bad[q] = 1;
-    }
-  }
+  ik1_finish(a);
 }
 
 // ---- IK2: r_j <- r_j - a_j (A2 t_j + sigma_j p_j), R_j = |r_j|^2 ----------------------
@@ -158,36 +203,132 @@ __global__ __launch_bounds__(kBlock) void ik2(BssArgs a) {
     acc += norm2d<R>(sr);
   }
   store_system_partials<MP>(acc, a.partial);
-  if (!arrive_last(a.tickets + 9 * kTicketSite)) return;
-  __shared__ double tot[kBssMax];
-  sum_system_partials(a.partial, gridDim.x, tot);
-  if (threadIdx.x < kWave) {
-    const int qq = threadIdx.x;
-    bool upd = false, act = false;
-    if (qq < st->m && st->active[qq]) {
-      const double Rn = tot[qq];
-      upd = true;
-      if (!isfinite(Rn)) {
-        st->bad[qq] = 1;
-        st->active[qq] = 0;
-        upd = false;
-      } else {
-        st->b[qq] = Rn / st->R[qq];
-        st->R[qq] = Rn;
-        st->iters[qq] += 1;
-        if (Rn <= st->target2[qq]) st->active[qq] = 0;
-        act = st->active[qq] != 0;
+  ik2_finish(a);
+}
+
+// ---- IK1 and IK2 on the sliced ELLPACK copies: one row per lane, every system of the
+// batch per lane (one read of the matrix row serves all of them) ----------------------
+// Pairs per round trip: the MP gathered values of 2 KP entries stay within the budget.
+template <class R, int MP> constexpr int kp_bss() {
+  return std::is_same<R, float>::value ? (MP <= 4 ? 4 : (MP == 8 ? 2 : 1))
+                                       : (MP <= 4 ? 2 : 1);
+}
+template <class R> __device__ __forceinline__ Sell<cplx<R>> pick_s(const BssArgs& a, bool second);
+template <> __device__ __forceinline__ Sell<float2> pick_s<float>(const BssArgs& a, bool second) {
+  return second ? a.sh32 : a.s32;
+}
+template <> __device__ __forceinline__ Sell<double2> pick_s<double>(const BssArgs& a, bool second) {
+  return second ? a.sh64 : a.s64;
+}
+
+// Per-system workgroup sums of MP doubles per thread, stored as the workgroup's partials.
+template <int MP>
+__device__ __forceinline__ void store_rr_partials(double (&v)[MP], double* partial) {
+  block_sum_k<kBlock, MP>(v);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < MP; ++q) store_agent(&partial[blockIdx.x * kBssMax + q], v[q]);
+  }
+}
+
+template <class R, int MP, bool MHM>
+__global__ __launch_bounds__(kBlock) void ik1s(BssArgs a) {
+  BssState* st = a.st;
+  if (st->halt) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->k3_enable = 0;
+    return;
+  }
+  const Sell<cplx<R>> m = pick_s<R>(a, false);
+  const cplx<R>* __restrict__ p = static_cast<const cplx<R>*>(a.p);
+  cplx<R>* __restrict__ t = static_cast<cplx<R>*>(a.t);
+  constexpr int SPB = kBlock / kSlice;
+  const int lane = threadIdx.x % kSlice;
+  const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x / kSlice));
+  double sig[MP], acc[MP];
+#pragma unroll
+  for (int q = 0; q < MP; ++q) {
+    sig[q] = st->sigma[q];
+    acc[q] = 0.0;
+  }
+  int64_t beg, end;
+  block_range(a.nslices, SPB, beg, end);
+  for (int64_t sl = beg + wv; sl < end; sl += SPB) {
+    const int64_t row = sl * kSlice + lane;
+    const bool live = row < a.n;
+    const int64_t rr = live ? row : a.n - 1;  // lanes past n read a valid row, unused
+    cplx<R> v[MP], pr[MP];
+    sell_row_rhs<R, MP, kp_bss<R, MP>()>(m, p, sl, lane, v);
+    load_rhs<R, MP>(p, rr, pr);
+    const cplx<R> d = m.diag[rr];
+    if (live) {
+#pragma unroll
+      for (int q = 0; q < MP; ++q) {
+        cfma<R>(v[q], d, pr[q]);
+        t[row * MP + q] = v[q];
+        if (MHM)
+          acc[q] += norm2d<R>(v[q]) + sig[q] * norm2d<R>(pr[q]);
+        else
+          acc[q] += double(pr[q].x) * double(v[q].x) + double(pr[q].y) * double(v[q].y) +
+                    sig[q] * norm2d<R>(pr[q]);
       }
     }
-    if (qq < kBssMax) st->upd[qq] = upd ? 1 : 0;
-    const uint64_t am = __ballot(act);
-    if (qq == 0) {
-      st->iter += 1;
-      st->nact = __popcll(am);
-      if (st->nact == 0 || st->iter >= st->max_iter) st->halt = 1;
-      st->k3_enable = 1;
+  }
+  store_rr_partials<MP>(acc, a.partial);
+  ik1_finish(a);
+}
+
+template <class R, int MP, bool MHM>
+__global__ __launch_bounds__(kBlock) void ik2s(BssArgs a) {
+  BssState* st = a.st;
+  if (st->halt) return;
+  const cplx<R>* __restrict__ t = static_cast<const cplx<R>*>(a.t);
+  const cplx<R>* __restrict__ p = static_cast<const cplx<R>*>(a.p);
+  cplx<R>* __restrict__ r = static_cast<cplx<R>*>(a.r);
+  constexpr int SPB = kBlock / kSlice;
+  const int lane = threadIdx.x % kSlice;
+  const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x / kSlice));
+  double sig[MP], step[MP], acc[MP];
+#pragma unroll
+  for (int q = 0; q < MP; ++q) {
+    sig[q] = st->sigma[q];
+    step[q] = st->active[q] ? st->a[q] : 0.0;
+    acc[q] = 0.0;
+  }
+  int64_t beg, end;
+  block_range(a.nslices, SPB, beg, end);
+  for (int64_t sl = beg + wv; sl < end; sl += SPB) {
+    const int64_t row = sl * kSlice + lane;
+    const bool live = row < a.n;
+    const int64_t rr = live ? row : a.n - 1;
+    cplx<R> v[MP], pr[MP], rv[MP];
+    if (MHM) {
+      const Sell<cplx<R>> mh = pick_s<R>(a, true);
+      cplx<R> tr[MP];
+      sell_row_rhs<R, MP, kp_bss<R, MP>()>(mh, t, sl, lane, v);
+      load_rhs<R, MP>(t, rr, tr);
+      const cplx<R> d = mh.diag[rr];
+#pragma unroll
+      for (int q = 0; q < MP; ++q) cfma<R>(v[q], d, tr[q]);
+    } else {
+      load_rhs<R, MP>(t, rr, v);
+    }
+    load_rhs<R, MP>(p, rr, pr);
+    load_rhs<R, MP>(r, rr, rv);
+    if (live) {
+#pragma unroll
+      for (int q = 0; q < MP; ++q) {
+        const double2 qd = to_d(v[q]), pd = to_d(pr[q]), rd = to_d(rv[q]);
+        double2 nr;
+        nr.x = rd.x - step[q] * (qd.x + sig[q] * pd.x);
+        nr.y = rd.y - step[q] * (qd.y + sig[q] * pd.y);
+        const cplx<R> sr = from_d<R>(nr);
+        r[row * MP + q] = sr;
+        acc[q] += norm2d<R>(sr);
+      }
     }
   }
+  store_rr_partials<MP>(acc, a.partial);
+  ik2_finish(a);
 }
 
 // ---- IK3: e_j += a_j p_j; p_j <- r_j + b_j p_j (elementwise over the batch) --------------
@@ -350,7 +491,16 @@ template <class R>
 hipError_t bss_iteration_impl(const BssArgs& a, hipStream_t s) {
   const int g1 = grid_for(a.n, kBlock / a.mp);
   const int g3 = grid_for(a.n * a.mp, kBlock);
-  if (a.kind == MSC_A_MHM) {
+  if (a.sell) {
+    const int gs = grid_for(a.nslices, kBlock / kSlice);
+    if (a.kind == MSC_A_MHM) {
+      MSC_MP_SWITCH(a.mp, (ik1s<R, MPP, true><<<gs, kBlock, 0, s>>>(a)));
+      MSC_MP_SWITCH(a.mp, (ik2s<R, MPP, true><<<gs, kBlock, 0, s>>>(a)));
+    } else {
+      MSC_MP_SWITCH(a.mp, (ik1s<R, MPP, false><<<gs, kBlock, 0, s>>>(a)));
+      MSC_MP_SWITCH(a.mp, (ik2s<R, MPP, false><<<gs, kBlock, 0, s>>>(a)));
+    }
+  } else if (a.kind == MSC_A_MHM) {
     MSC_MP_SWITCH(a.mp, (ik1<R, MPP, true><<<g1, kBlock, 0, s>>>(a)));
     MSC_MP_SWITCH(a.mp, (ik2<R, MPP, true><<<g1, kBlock, 0, s>>>(a)));
   } else {

@@ -76,23 +76,6 @@ template <class R> __device__ __forceinline__ Sell<cplx<R>> sell2(const BatchSys
 template <> __device__ __forceinline__ Sell<double2> sell2<double>(const BatchSys& S) { return S.sh64; }
 template <> __device__ __forceinline__ Sell<float2> sell2<float>(const BatchSys& S) { return S.sh32; }
 
-// The RR interleaved values of column c, loaded 16 bytes at a time.
-template <class R, int RR>
-__device__ __forceinline__ void load_rhs(const cplx<R>* __restrict__ x, int64_t c, cplx<R> (&o)[RR]) {
-  if constexpr (std::is_same<R, float>::value && RR % 2 == 0) {
-    const f32x4* v = reinterpret_cast<const f32x4*>(x + c * RR);
-#pragma unroll
-    for (int h = 0; h < RR / 2; ++h) {
-      const f32x4 w = v[h];
-      o[2 * h] = float2{w.x, w.y};
-      o[2 * h + 1] = float2{w.z, w.w};
-    }
-  } else {
-#pragma unroll
-    for (int q = 0; q < RR; ++q) o[q] = x[c * RR + q];
-  }
-}
-
 // Pairs per round trip of the RR-rhs product (MSC_BATCH_KP32 / MSC_BATCH_KP64 at four
 // right-hand sides, twice that for fewer).
 #ifndef MSC_BATCH_KP32
@@ -104,66 +87,6 @@ __device__ __forceinline__ void load_rhs(const cplx<R>* __restrict__ x, int64_t 
 template <class R, int RR> constexpr int kp_rhs() {
   return std::is_same<R, float>::value ? (RR >= 4 ? MSC_BATCH_KP32 : 2 * MSC_BATCH_KP32)
                                        : (RR >= 4 ? MSC_BATCH_KP64 : 2 * MSC_BATCH_KP64);
-}
-
-template <class R, int RR, int KP, bool FULL>
-__device__ __forceinline__ void gather_rhs_fma(const cplx<R>* __restrict__ x, int np,
-                                               const int2 (&cc)[KP], const cplx<R> (&v)[2 * KP],
-                                               cplx<R> (&acc)[RR]) {
-  cplx<R> xs[2 * KP][RR];
-#pragma unroll
-  for (int u = 0; u < KP; ++u) {
-    if (FULL || u < np) {
-      load_rhs<R, RR>(x, cc[u].x, xs[2 * u]);
-      load_rhs<R, RR>(x, cc[u].y, xs[2 * u + 1]);
-    } else {
-#pragma unroll
-      for (int q = 0; q < RR; ++q) xs[2 * u][q] = xs[2 * u + 1][q] = czero<R>();
-    }
-  }
-#pragma unroll
-  for (int u = 0; u < 2 * KP; ++u) {
-#pragma unroll
-    for (int q = 0; q < RR; ++q) cfma<R>(acc[q], v[u], xs[u][q]);
-  }
-}
-
-// Off-diagonal part of one sliced ELLPACK row per lane times the RR interleaved vectors
-// of x (slice `sl` wavefront-uniform); one read of the matrix row serves every rhs.
-template <class R, int RR, bool NARROW>
-__device__ __forceinline__ void sell_row_rhs_cols(const Sell<cplx<R>>& m,
-                                                  const cplx<R>* __restrict__ x, int64_t sl,
-                                                  int lane, cplx<R> (&acc)[RR]) {
-  constexpr int KP = kp_rhs<R, RR>();
-#pragma unroll
-  for (int q = 0; q < RR; ++q) acc[q] = czero<R>();
-  int32_t c, c1;
-  if (m.wp > 0) {
-    c = int32_t(sl) * m.wp;
-    c1 = c + m.wp;
-  } else {
-    c = load_uniform(m.cptr, sl);
-    c1 = load_uniform(m.cptr, sl + 1);
-  }
-  int2 cc[KP];
-  cplx<R> v[2 * KP];
-  for (; c + KP <= c1; c += KP) {
-    sell_load<R, KP, true, NARROW>(m, c, KP, lane, cc, v);
-    gather_rhs_fma<R, RR, KP, true>(x, KP, cc, v, acc);
-  }
-  if (c < c1) {
-    const int np = c1 - c;
-    sell_load<R, KP, false, NARROW>(m, c, np, lane, cc, v);
-    gather_rhs_fma<R, RR, KP, false>(x, np, cc, v, acc);
-  }
-}
-template <class R, int RR>
-__device__ __forceinline__ void sell_row_rhs(const Sell<cplx<R>>& m, const cplx<R>* __restrict__ x,
-                                             int64_t sl, int lane, cplx<R> (&acc)[RR]) {
-  if (m.col16)
-    sell_row_rhs_cols<R, RR, true>(m, x, sl, lane, acc);
-  else
-    sell_row_rhs_cols<R, RR, false>(m, x, sl, lane, acc);
 }
 
 // Per-rhs workgroup partials of a chunk: store, take the system's ticket; true in the
@@ -215,7 +138,7 @@ __device__ void bk1_chunk(const BatchSys& S, BatchState* st, const int4& ch) {
       cplx<R> pr[RR], v[RR];
       load_rhs<R, RR>(p, rr, pr);
       const cplx<R> d = ms.diag[rr];
-      sell_row_rhs<R, RR>(ms, p, sl, lane, v);
+      sell_row_rhs<R, RR, kp_rhs<R, RR>()>(ms, p, sl, lane, v);
 #pragma unroll
       for (int q = 0; q < RR; ++q) cfma<R>(v[q], d, pr[q]);
       if (row < ch.z) epilogue(row, v, pr);
@@ -297,7 +220,7 @@ __device__ void bk2_chunk(const BatchSys& S, BatchState* st, const int4& ch, int
       cplx<R> tr[RR], qv[RR];
       load_rhs<R, RR>(t, rr, tr);
       const cplx<R> d = ms.diag[rr];
-      sell_row_rhs<R, RR>(ms, t, sl, lane, qv);
+      sell_row_rhs<R, RR, kp_rhs<R, RR>()>(ms, t, sl, lane, qv);
 #pragma unroll
       for (int q = 0; q < RR; ++q) cfma<R>(qv[q], d, tr[q]);
       if (row < ch.z) epilogue(row, qv);

@@ -544,6 +544,20 @@ msc_status run_batched_cg(msc_op op, int prec, int m, const double* sig, const d
     a.mh64 = Csr<double2>{op->rowptr_h, op->col_h, op->val64_h};
     a.mh32 = Csr<float2>{op->rowptr_h, op->col_h, op->val32_h};
   }
+  // the SpMVs read the sliced ELLPACK copies where they exist (as the multishift does),
+  // up to 8 systems (16 gathered FP64 values per entry exceed the register budget)
+  a.sell = op->sell && prm.format != MSC_FORMAT_CSR && mp <= 8 ? 1 : 0;
+  if (a.sell) {
+    const bool narrow = prm.format != MSC_FORMAT_SELL32;
+    const SellStore &sm = op->sell_m, &sh = op->sell_mh;
+    a.nslices = sm.nslices;
+    a.s64 = sell_view(sm, sm.val64, sm.diag64, narrow);
+    a.s32 = sell_view(sm, sm.val32, sm.diag32, narrow);
+    if (op->kind == MSC_A_MHM) {
+      a.sh64 = sell_view(sh, sh.val64, sh.diag64, narrow);
+      a.sh32 = sell_view(sh, sh.val32, sh.diag32, narrow);
+    }
+  }
   a.p = op->bws.p;
   a.t = op->bws.t;
   a.r = op->bws.r;
@@ -555,7 +569,8 @@ msc_status run_batched_cg(msc_op op, int prec, int m, const double* sig, const d
   for (int j = 0; j < m; ++j) xp.x[j] = x[j];
 
   const double w = prec == MSC_PREC_MIXED ? 8.0 : 16.0;
-  const double mat = (double(op->nnz) + double(op->nnz_h)) * (w + 4.0) +
+  const double mat = double(op->nnz) * (w + index_bytes(a.sell, a.s64)) +
+                     double(op->nnz_h) * (w + index_bytes(a.sell, a.sh64)) +
                      4.0 * (op->n + 1) * (op->kind == MSC_A_MHM ? 2.0 : 1.0);
   const int max_cycles = 12;
   std::vector<double> res2;
@@ -583,11 +598,15 @@ msc_status run_batched_cg(msc_op op, int prec, int m, const double* sig, const d
     for (int j = 0; j < m; ++j) res_abs[j] = std::sqrt(res2[j]);
     if (all_done || cycle >= max_cycles || *breakdown) break;
     HIP_TRY(hipMemcpyAsync(op->bws.st, &h, sizeof h, hipMemcpyHostToDevice, s));
+    // chunks of 2, 4, 8, ... iterations up to poll_every: a correction solve often needs
+    // only a few iterations, and the halt flag of a chunk is read after the next one is
+    // queued
     const int G = std::max(1, prm.poll_every);
     int launched = 0, chunk = 0;
     bool done = false;
     while (!done) {
-      for (int g = 0; g < G; ++g) {
+      const int cg = std::min(G, 2 << std::min(chunk, 20));
+      for (int g = 0; g < cg; ++g) {
         HIP_TRY(launch_bss_iteration(prec, a, s));
         ++launched;
       }

@@ -267,6 +267,10 @@ struct BssArgs {
   int64_t n;
   Csr<double2> m64, mh64;
   Csr<float2> m32, mh32;
+  int sell;                             // 1: the SpMVs read the sliced ELLPACK copies
+  int64_t nslices;
+  Sell<double2> s64, sh64;
+  Sell<float2> s32, sh32;
   void* p; void* t; void* r; void* e;   // interleaved n x mp vectors of the working precision
   BssState* st;
   double* partial;                      // kMaxGrid * kBssMax

@@ -17,6 +17,8 @@
 // workgroup writes one partial, the last one to arrive sums them in a fixed order.
 #include <hip/hip_ext.h>
 
+#include <type_traits>
+
 #include "dev_common.h"
 #include "msc_internal.h"
 #include "sell_load.h"
@@ -361,12 +363,21 @@ __device__ bool k2_step(const MsArgs& a, const Early& e, double& step) {
 // R' (from K2's partials) and b = R'/R, and per shift j the coefficients of its update,
 // whether it freezes now (zeta_j^(n+1)^2 R' <= eps2), and the list of shifts to update.
 // Workgroup 0 writes the state the rest of the iteration and the next head start from.
+// Shifts whose x_j and p_j loads the head's update issues together (MSC_UPD_GROUP).
+#ifndef MSC_UPD_GROUP
+#define MSC_UPD_GROUP 4
+#endif
+constexpr int kUpdGroup = MSC_UPD_GROUP;
+
 struct Plan {
   double bn;                 // b of p <- r + b p (0: p is current, nothing pending)
+  // the shifts updated by this head, in list order: coefficients, the element offsets of
+  // x_j (the caller's order) and of p_j, and whether p_j is updated (0: j freezes now)
   double bk[kMaxShifts];
   double zk[kMaxShifts];
   double ak[kMaxShifts];
-  int list[kMaxShifts];
+  int64_t xo[kMaxShifts];
+  int64_t po[kMaxShifts];
   int upd_p[kMaxShifts];
   int nact;
   int pending;               // the update runs in this head
@@ -381,13 +392,14 @@ __device__ void head_plan(const MsArgs& a, const Early& e, Plan& pl) {
   const int j = threadIdx.x;
   const int pending = rs.pending;
   // wave 0, lane j: shift j's state, loaded before the partial sum
-  int act0 = 0;
+  int act0 = 0, origj = 0;
   double z = 1.0, zn = 0.0, akj = 0.0;
   if (pending && j >= 1 && j < kWave && j < st->ns) {
     act0 = rs.active[j];
     z = rs.zeta[j];
     zn = st->zk[j];
     akj = st->ak[j];
+    origj = st->orig[j];
   }
   const double R = rs.R, eps2 = st->eps2;
   const int kst = st->kstatus, frz = st->freeze;
@@ -396,18 +408,16 @@ __device__ void head_plan(const MsArgs& a, const Early& e, Plan& pl) {
     const bool ok = !pending || (isfinite(Rn) && kst == 0);
     const double bn = pending ? Rn / R : 0.0;
     const bool act = pending && ok && act0;
-    bool freeze_now = false;
-    if (act) {
-      const double ratio = zn / z;
-      pl.bk[j] = bn * ratio * ratio;
-      pl.zk[j] = zn;
-      pl.ak[j] = akj;
-      freeze_now = frz && zn * zn * Rn <= eps2;
-    }
+    const bool freeze_now = act && frz && zn * zn * Rn <= eps2;
     const uint64_t mask = __ballot(act);
     if (act) {
       const int pos = __popcll(mask & ((uint64_t(1) << j) - 1));
-      pl.list[pos] = j;
+      const double ratio = zn / z;
+      pl.bk[pos] = bn * ratio * ratio;
+      pl.zk[pos] = zn;
+      pl.ak[pos] = akj;
+      pl.xo[pos] = int64_t(origj) * a.n;
+      pl.po[pos] = int64_t(j - 1) * a.n;
       pl.upd_p[pos] = freeze_now ? 0 : 1;
     }
     const int it = pending ? rs.iter + 1 : rs.iter;
@@ -489,60 +499,46 @@ __device__ __forceinline__ cplx<R> update_row(const MsArgs& a, const Plan& pl, d
                                               int64_t i, const cplx<R>& rr, const cplx<R>& pp,
                                               double2 x0v, double2* __restrict__ x0,
                                               cplx<R>* __restrict__ pnew) {
-  const SolveState* st = a.st;
-  const int64_t n = a.n;
   cplx<R>* __restrict__ pk = static_cast<cplx<R>*>(a.pk);
   double2* __restrict__ x = a.x;
   const double2 rd = to_d(rr), pd = to_d(pp);
   x0v.x = fma(step, pd.x, x0v.x);
   x0v.y = fma(step, pd.y, x0v.y);
   x0[i] = x0v;
+  // shifts in groups of MSC_UPD_GROUP: a group's loads are all issued before its first
+  // store; a last, partial group is masked
   const int nact = pl.nact;
-  int q = 0;
-  for (; q + 4 <= nact; q += 4) {
-    int jj[4];
-    cplx<R> pj[4];
-    double2 xj[4];
+  auto group = [&](int q, int m, auto full) {
+    cplx<R> pj[kUpdGroup];
+    double2 xj[kUpdGroup];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      jj[u] = pl.list[q + u];
-      pj[u] = pk[int64_t(jj[u] - 1) * n + i];
-      xj[u] = x[int64_t(st->orig[jj[u]]) * n + i];
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int j = jj[u];
-      const double2 pjd = to_d(pj[u]);
-      const double aj = pl.ak[j];
-      xj[u].x = fma(aj, pjd.x, xj[u].x);
-      xj[u].y = fma(aj, pjd.y, xj[u].y);
-      x[int64_t(st->orig[j]) * n + i] = xj[u];
-      if (pl.upd_p[q + u]) {
-        const double zj = pl.zk[j], bj = pl.bk[j];
-        double2 np;
-        np.x = fma(zj, rd.x, bj * pjd.x);
-        np.y = fma(zj, rd.y, bj * pjd.y);
-        pk[int64_t(j - 1) * n + i] = from_d<R>(np);
+    for (int u = 0; u < kUpdGroup; ++u) {
+      if (decltype(full)::value || u < m) {
+        pj[u] = pk[pl.po[q + u] + i];
+        xj[u] = x[pl.xo[q + u] + i];
       }
     }
-  }
-  for (; q < nact; ++q) {
-    const int j = pl.list[q];
-    const double2 pjd = to_d(pk[int64_t(j - 1) * n + i]);
-    double2* xp = x + int64_t(st->orig[j]) * n + i;
-    double2 xv2 = *xp;
-    const double aj = pl.ak[j];
-    xv2.x = fma(aj, pjd.x, xv2.x);
-    xv2.y = fma(aj, pjd.y, xv2.y);
-    *xp = xv2;
-    if (pl.upd_p[q]) {
-      const double zj = pl.zk[j], bj = pl.bk[j];
-      double2 np;
-      np.x = fma(zj, rd.x, bj * pjd.x);
-      np.y = fma(zj, rd.y, bj * pjd.y);
-      pk[int64_t(j - 1) * n + i] = from_d<R>(np);
+#pragma unroll
+    for (int u = 0; u < kUpdGroup; ++u) {
+      if (decltype(full)::value || u < m) {
+        const double2 pjd = to_d(pj[u]);
+        const double aj = pl.ak[q + u];
+        xj[u].x = fma(aj, pjd.x, xj[u].x);
+        xj[u].y = fma(aj, pjd.y, xj[u].y);
+        x[pl.xo[q + u] + i] = xj[u];
+        if (pl.upd_p[q + u]) {
+          const double zj = pl.zk[q + u], bj = pl.bk[q + u];
+          double2 np;
+          np.x = fma(zj, rd.x, bj * pjd.x);
+          np.y = fma(zj, rd.y, bj * pjd.y);
+          pk[pl.po[q + u] + i] = from_d<R>(np);
+        }
+      }
     }
-  }
+  };
+  int q = 0;
+  for (; q + kUpdGroup <= nact; q += kUpdGroup) group(q, kUpdGroup, std::true_type{});
+  if (q < nact) group(q, nact - q, std::false_type{});
   const cplx<R> np = next_dir<R>(pl.bn, rr, pp);
   pnew[i] = np;
   return np;

@@ -2,6 +2,8 @@
 // single-system and the batched kernels.
 #pragma once
 
+#include <type_traits>
+
 #include "dev_common.h"
 #include "msc_internal.h"
 
@@ -76,6 +78,84 @@ __device__ __forceinline__ void sell_load(const Sell<cplx<R>>& m, int32_t c, int
       v[2 * u] = v[2 * u + 1] = czero<R>();
     }
   }
+}
+
+// ---- several right-hand sides interleaved, v[i RR + q] ----------------------------------
+
+// The RR interleaved values of column c, loaded 16 bytes at a time.
+template <class R, int RR>
+__device__ __forceinline__ void load_rhs(const cplx<R>* __restrict__ x, int64_t c, cplx<R> (&o)[RR]) {
+  if constexpr (std::is_same<R, float>::value && RR % 2 == 0) {
+    const f32x4* v = reinterpret_cast<const f32x4*>(x + c * RR);
+#pragma unroll
+    for (int h = 0; h < RR / 2; ++h) {
+      const f32x4 w = v[h];
+      o[2 * h] = float2{w.x, w.y};
+      o[2 * h + 1] = float2{w.z, w.w};
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < RR; ++q) o[q] = x[c * RR + q];
+  }
+}
+
+template <class R, int RR, int KP, bool FULL>
+__device__ __forceinline__ void gather_rhs_fma(const cplx<R>* __restrict__ x, int np,
+                                               const int2 (&cc)[KP], const cplx<R> (&v)[2 * KP],
+                                               cplx<R> (&acc)[RR]) {
+  cplx<R> xs[2 * KP][RR];
+#pragma unroll
+  for (int u = 0; u < KP; ++u) {
+    if (FULL || u < np) {
+      load_rhs<R, RR>(x, cc[u].x, xs[2 * u]);
+      load_rhs<R, RR>(x, cc[u].y, xs[2 * u + 1]);
+    } else {
+#pragma unroll
+      for (int q = 0; q < RR; ++q) xs[2 * u][q] = xs[2 * u + 1][q] = czero<R>();
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < 2 * KP; ++u) {
+#pragma unroll
+    for (int q = 0; q < RR; ++q) cfma<R>(acc[q], v[u], xs[u][q]);
+  }
+}
+
+// Off-diagonal part of one sliced ELLPACK row per lane times the RR interleaved vectors
+// of x (slice `sl` wavefront-uniform); one read of the matrix row serves every rhs.
+template <class R, int RR, int KP, bool NARROW>
+__device__ __forceinline__ void sell_row_rhs_cols(const Sell<cplx<R>>& m,
+                                                  const cplx<R>* __restrict__ x, int64_t sl,
+                                                  int lane, cplx<R> (&acc)[RR]) {
+#pragma unroll
+  for (int q = 0; q < RR; ++q) acc[q] = czero<R>();
+  int32_t c, c1;
+  if (m.wp > 0) {
+    c = int32_t(sl) * m.wp;
+    c1 = c + m.wp;
+  } else {
+    c = load_uniform(m.cptr, sl);
+    c1 = load_uniform(m.cptr, sl + 1);
+  }
+  int2 cc[KP];
+  cplx<R> v[2 * KP];
+  for (; c + KP <= c1; c += KP) {
+    sell_load<R, KP, true, NARROW>(m, c, KP, lane, cc, v);
+    gather_rhs_fma<R, RR, KP, true>(x, KP, cc, v, acc);
+  }
+  if (c < c1) {
+    const int np = c1 - c;
+    sell_load<R, KP, false, NARROW>(m, c, np, lane, cc, v);
+    gather_rhs_fma<R, RR, KP, false>(x, np, cc, v, acc);
+  }
+}
+template <class R, int RR, int KP>
+__device__ __forceinline__ void sell_row_rhs(const Sell<cplx<R>>& m, const cplx<R>* __restrict__ x,
+                                             int64_t sl, int lane, cplx<R> (&acc)[RR]) {
+  if (m.col16)
+    sell_row_rhs_cols<R, RR, KP, true>(m, x, sl, lane, acc);
+  else
+    sell_row_rhs_cols<R, RR, KP, false>(m, x, sl, lane, acc);
 }
 
 }  // namespace msc

@@ -61,15 +61,17 @@ def test_general_loss_matches_dense_autograd(c3_4, cuda, prec):
     op.close()
 
 
-def test_herm_general_loss(cuda):
+@pytest.mark.parametrize("fmt", ["auto", "csr"])
+def test_herm_general_loss(cuda, fmt):
+    # three shifts: the adjoint's batched CG reads the sliced copy ("auto") or CSR
     rowptr, col, vals = W.laplacian7_csr((5, 4, 6), 61)
     n = 120
     p = dict(rowptr=rowptr, col=col, vals=vals, n=n, sigma=np.array([1e-3, 0.1, 2.0]))
     b = W.gaussian_rhs(n, 62)
     op = _op(p, cuda, kind="herm")
-    x, _ = op.solve(b, tol=1e-13)
+    x, _ = op.solve(b, tol=1e-13, format=fmt)
     g = W.gaussian_rhs(n, 63, 3)
-    gb, gv, ainfo = op.solve_adjoint(g, x, tol=1e-13)
+    gb, gv, ainfo = op.solve_adjoint(g, x, tol=1e-13, format=fmt)
     ref_v, ref_b = O.dense_reference_gradient("herm", rowptr, col, vals, n, b, p["sigma"], g)
     assert _rel(gv.cpu().numpy(), ref_v) <= 1e-9
     assert _rel(gb.cpu().numpy(), ref_b) <= 1e-9

@@ -91,14 +91,21 @@ def test_mixed_margin_trades_iterations_for_residual(c0, cuda):
     op.close()
 
 
+@pytest.mark.parametrize("fmt", ["auto", "csr"])
 @pytest.mark.parametrize("switch_tol", [1.0, 1e-3])
-def test_mixed_early_switch_is_refined_to_tol(c0, cuda, switch_tol):
-    # switching early leaves larger complex64 gaps; the FP64 refinement closes them
+def test_mixed_early_switch_is_refined_to_tol(c0, cuda, switch_tol, fmt):
+    # switching early leaves larger complex64 gaps; the FP64 refinement (a batched CG on
+    # the sliced ELLPACK copies, or on CSR) closes them
     op = _op(c0, cuda)
     op.set_shifts(c0["sigma"])
-    x, info = op.solve(c0["b"], tol=1e-10, prec="mixed", switch_tol=switch_tol)
+    x, info = op.solve(c0["b"], tol=1e-10, prec="mixed", switch_tol=switch_tol, format=fmt)
     assert info["status"] == "ok"
     assert np.all(info["true_rel_res"] <= 1e-10)
+    if switch_tol == 1.0:
+        assert info["n_refined"] > 0 and info["refine_iters"] > 0
+    rho = np.array([np.linalg.norm(c0["b"] - c0["apply"](x.cpu().numpy()[k], s))
+                    for k, s in enumerate(c0["sigma"])])
+    assert np.all(rho / np.linalg.norm(c0["b"]) <= 1e-10)
     op.close()
 
 
