@@ -394,6 +394,49 @@ __global__ __launch_bounds__(kBlock) void k_res_first(ResArgs v) {
   }
 }
 
+// Per-system norms: workgroup partials, then the last workgroup's totals in out[0..kc).
+__device__ void res_finish(const ResArgs& v, double (&nrm)[kResChunk]) {
+  block_sum_k<kBlock, kResChunk>(nrm);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < kResChunk; ++q) store_agent(&v.partial[blockIdx.x * kResChunk + q], nrm[q]);
+  }
+  if (!arrive_last(v.ticket)) return;
+  for (int q = 0; q < v.kc; ++q) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < int(gridDim.x); i += kBlock) s += load_agent(&v.partial[i * kResChunk + q]);
+    s = block_sum<kBlock>(s);
+    if (threadIdx.x == 0) v.out[q] = s;
+  }
+}
+
+// Row `row`'s residuals from the products acc_q = (A x_q)[row]: norms, and the
+// interleaved r = p = residual, e = 0 when r is set.
+template <class R>
+__device__ __forceinline__ void res_row(const ResArgs& v, int64_t row, const double2 (&acc)[kResChunk],
+                                        double (&nrm)[kResChunk]) {
+  cplx<R>* __restrict__ r = static_cast<cplx<R>*>(v.r);
+  cplx<R>* __restrict__ p = static_cast<cplx<R>*>(v.p);
+  cplx<R>* __restrict__ e = static_cast<cplx<R>*>(v.e);
+#pragma unroll
+  for (int q = 0; q < kResChunk; ++q) {
+    if (q < v.kc) {
+      const double2 fv = v.f[q][row], xv = v.x[q][row];
+      double2 rt;
+      rt.x = fv.x - acc[q].x - v.sig[q] * xv.x;
+      rt.y = fv.y - acc[q].y - v.sig[q] * xv.y;
+      nrm[q] += fma(rt.x, rt.x, rt.y * rt.y);
+      if (r) {
+        const int64_t idx = row * v.mp + v.j0 + q;
+        const cplx<R> rc = from_d<R>(rt);
+        r[idx] = rc;
+        p[idx] = rc;
+        e[idx] = czero<R>();
+      }
+    }
+  }
+}
+
 template <class R, int L>
 __global__ __launch_bounds__(kBlock) void k_res_second(ResArgs v) {
   constexpr int GPB = kBlock / L;
@@ -407,43 +450,67 @@ __global__ __launch_bounds__(kBlock) void k_res_second(ResArgs v) {
   const double2* in[kResChunk];
 #pragma unroll
   for (int q = 0; q < kResChunk; ++q) in[q] = v.mhm ? v.u + int64_t(q) * v.n : v.x[q];
-  cplx<R>* __restrict__ r = static_cast<cplx<R>*>(v.r);
-  cplx<R>* __restrict__ p = static_cast<cplx<R>*>(v.p);
-  cplx<R>* __restrict__ e = static_cast<cplx<R>*>(v.e);
   for (int64_t row = beg + grp; row < end; row += GPB) {
     row_dot_ptrs<L>(v.m2, in, v.kc, row, lane, acc);
-    if (lane == 0) {
+    if (lane == 0) res_row<R>(v, row, acc, nrm);
+  }
+  res_finish(v, nrm);
+}
+
+// The same two steps on the sliced ELLPACK copies: one row per lane.
+__global__ __launch_bounds__(kBlock) void k_res_first_s(ResArgs v) {
+  constexpr int SPB = kBlock / kSlice;
+  const int lane = threadIdx.x % kSlice;
+  const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x / kSlice));
+  const double2* xs[kResChunk];
 #pragma unroll
-      for (int q = 0; q < kResChunk; ++q) {
-        if (q < v.kc) {
-          const double2 fv = v.f[q][row], xv = v.x[q][row];
-          double2 rt;
-          rt.x = fv.x - acc[q].x - v.sig[q] * xv.x;
-          rt.y = fv.y - acc[q].y - v.sig[q] * xv.y;
-          nrm[q] += fma(rt.x, rt.x, rt.y * rt.y);
-          if (r) {
-            const int64_t idx = row * v.mp + v.j0 + q;
-            const cplx<R> rc = from_d<R>(rt);
-            r[idx] = rc;
-            p[idx] = rc;
-            e[idx] = czero<R>();
-          }
-        }
+  for (int q = 0; q < kResChunk; ++q) xs[q] = v.x[q < v.kc ? q : 0];
+  int64_t beg, end;
+  block_range(v.nslices, SPB, beg, end);
+  for (int64_t sl = beg + wv; sl < end; sl += SPB) {
+    const int64_t row = sl * kSlice + lane;
+    const int64_t rr = row < v.n ? row : v.n - 1;
+    double2 acc[kResChunk];
+    sell_row_multi<double, kResChunk, 1>(v.s1, xs, v.kc, sl, lane, acc);
+    const double2 d = v.s1.diag[rr];
+#pragma unroll
+    for (int q = 0; q < kResChunk; ++q) {
+      if (q < v.kc) {
+        cfma<double>(acc[q], d, xs[q][rr]);
+        if (row < v.n) v.u[int64_t(q) * v.n + row] = acc[q];
       }
     }
   }
-  block_sum_k<kBlock, kResChunk>(nrm);
-  if (threadIdx.x == 0) {
+}
+
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_res_second_s(ResArgs v) {
+  constexpr int SPB = kBlock / kSlice;
+  const int lane = threadIdx.x % kSlice;
+  const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x / kSlice));
+  const double2* in[kResChunk];
 #pragma unroll
-    for (int q = 0; q < kResChunk; ++q) store_agent(&v.partial[blockIdx.x * kResChunk + q], nrm[q]);
+  for (int q = 0; q < kResChunk; ++q) {
+    const int qq = q < v.kc ? q : 0;
+    in[q] = v.mhm ? v.u + int64_t(qq) * v.n : v.x[qq];
   }
-  if (!arrive_last(v.ticket)) return;
-  for (int q = 0; q < v.kc; ++q) {
-    double s = 0.0;
-    for (int i = threadIdx.x; i < int(gridDim.x); i += kBlock) s += load_agent(&v.partial[i * kResChunk + q]);
-    s = block_sum<kBlock>(s);
-    if (threadIdx.x == 0) v.out[q] = s;
+  double nrm[kResChunk];
+#pragma unroll
+  for (int q = 0; q < kResChunk; ++q) nrm[q] = 0.0;
+  int64_t beg, end;
+  block_range(v.nslices, SPB, beg, end);
+  for (int64_t sl = beg + wv; sl < end; sl += SPB) {
+    const int64_t row = sl * kSlice + lane;
+    const int64_t rr = row < v.n ? row : v.n - 1;
+    double2 acc[kResChunk];
+    sell_row_multi<double, kResChunk, 1>(v.s2, in, v.kc, sl, lane, acc);
+    const double2 d = v.s2.diag[rr];
+#pragma unroll
+    for (int q = 0; q < kResChunk; ++q)
+      if (q < v.kc) cfma<double>(acc[q], d, in[q][rr]);
+    if (row < v.n) res_row<R>(v, row, acc, nrm);
   }
+  res_finish(v, nrm);
 }
 
 // x_j += e_j (FP64 accumulation of the correction)
@@ -519,6 +586,15 @@ hipError_t launch_bss_iteration(int prec, const BssArgs& a, hipStream_t s) {
 
 hipError_t launch_residual(int prec, int lanes, const ResArgs& v, hipStream_t s) {
   if (v.kc < 1 || v.kc > kResChunk) return hipErrorInvalidValue;
+  if (v.sell) {
+    const int gs = grid_for(v.nslices, kBlock / kSlice);
+    if (v.mhm) k_res_first_s<<<gs, kBlock, 0, s>>>(v);
+    if (prec == MSC_PREC_MIXED)
+      k_res_second_s<float><<<gs, kBlock, 0, s>>>(v);
+    else
+      k_res_second_s<double><<<gs, kBlock, 0, s>>>(v);
+    return hipGetLastError();
+  }
   const int g1 = grid_for(v.n, kBlock / lanes);
   if (v.mhm) MSC_L_SWITCH(lanes, (k_res_first<LL><<<g1, kBlock, 0, s>>>(v)));
   if (prec == MSC_PREC_MIXED) {

@@ -418,7 +418,8 @@ msc_status run_multishift(msc_op op, const double* d_b, double* d_x, const msc_p
   *bytes_out = iter_bytes(op->kind, MSC_PREC_FP64, nn, nz, nzh, act64, double(iters_fp64), ib, ibh) +
                iter_bytes(op->kind, MSC_PREC_MIXED, nn, nz, nzh, act32,
                           double(fin.iter - iters_fp64), ib, ibh) +
-               double(h.n_reliable) * ((op->kind == MSC_A_MHM ? 2.0 : 1.0) * (nz * 20.0 + 4.0 * (nn + 1)) +
+               double(h.n_reliable) * (nz * (16.0 + ib) + nzh * (16.0 + ibh) +
+                                       4.0 * (nn + 1) * (op->kind == MSC_A_MHM ? 2.0 : 1.0) +
                                        nn * (16.0 * 3 + 8.0));
   // the fused head reads the old direction once for the update and the product
   if (a64.sell) *bytes_out -= nn * (16.0 * iters_fp64 + 8.0 * (fin.iter - iters_fp64));
@@ -437,7 +438,7 @@ msc_status run_multishift(msc_op op, const double* d_b, double* d_x, const msc_p
     HIP_TRY(hipStreamSynchronize(s));
     for (int k = 0; k < ns; ++k) (*rel_out)[k] = bn > 0 ? std::sqrt(r2[k]) / bn : 0.0;
     const double nvec = op->kind == MSC_A_MHM ? 2.0 : 1.0;
-    *bytes_out += nvec * (double(op->nnz) * 20.0 + 4.0 * (op->n + 1)) * std::ceil(ns / 8.0) +
+    *bytes_out += (nz * (16.0 + ib) + nzh * (16.0 + ibh) + nvec * 4.0 * (nn + 1)) * std::ceil(ns / 8.0) +
                   double(op->n) * 16.0 * ns * (op->kind == MSC_A_MHM ? 4.0 : 2.0) + 16.0 * op->n;
   }
   return MSC_OK;
@@ -477,13 +478,22 @@ msc_status ensure_bss(msc_op op, int prec, int mp) {
 // of systems j in [0, m): r_j = f_j - (A + sig_j) x_j.  res2 receives |r_j|^2.
 msc_status batch_residual(msc_op op, int prec, int lanes, int m, int mp, const double* sig,
                           const double2* const* f, double2* const* x, bool write_vectors,
-                          std::vector<double>& res2, hipStream_t s, double* bytes) {
+                          std::vector<double>& res2, hipStream_t s, double* bytes,
+                          const msc_params& prm) {
   res2.assign(m, 0.0);
   for (int q0 = 0; q0 < m; q0 += kResChunk) {
     ResArgs v{};
     v.m1 = Csr<double2>{op->rowptr, op->col, op->val64};
     v.mhm = op->kind == MSC_A_MHM;
     v.m2 = v.mhm ? Csr<double2>{op->rowptr_h, op->col_h, op->val64_h} : v.m1;
+    v.sell = op->sell && prm.format != MSC_FORMAT_CSR ? 1 : 0;
+    if (v.sell) {
+      const bool narrow = prm.format != MSC_FORMAT_SELL32;
+      const SellStore &sm = op->sell_m, &sh = op->sell_mh;
+      v.nslices = sm.nslices;
+      v.s1 = sell_view(sm, sm.val64, sm.diag64, narrow);
+      v.s2 = v.mhm ? sell_view(sh, sh.val64, sh.diag64, narrow) : v.s1;
+    }
     v.n = op->n;
     v.kc = std::min(kResChunk, m - q0);
     v.mp = mp;
@@ -503,7 +513,9 @@ msc_status batch_residual(msc_op op, int prec, int lanes, int m, int mp, const d
     v.ticket = op->scratch.tickets + 10 * kTicketSite;
     v.out = op->scratch.res2 + q0;
     HIP_TRY(launch_residual(prec, lanes, v, s));
-    *bytes += (v.mhm ? 2.0 : 1.0) * (double(op->nnz) * 20.0 + 4.0 * (op->n + 1)) +
+    const double ib = index_bytes(v.sell, v.s1), ibh = v.mhm ? index_bytes(v.sell, v.s2) : 0.0;
+    *bytes += double(op->nnz) * (16.0 + ib) + (v.mhm ? double(op->nnz) * (16.0 + ibh) : 0.0) +
+              (v.mhm ? 2.0 : 1.0) * 4.0 * (op->n + 1) +
               double(op->n) * v.kc * 16.0 * (v.mhm ? 5.0 : 3.0);
   }
   HIP_TRY(hipMemcpyAsync(res2.data(), op->scratch.res2, sizeof(double) * m, hipMemcpyDeviceToHost, s));
@@ -575,7 +587,7 @@ msc_status run_batched_cg(msc_op op, int prec, int m, const double* sig, const d
   const int max_cycles = 12;
   std::vector<double> res2;
   for (int cycle = 0;; ++cycle) {
-    rc = batch_residual(op, prec, lanes, m, mp, sig, f, x, true, res2, s, bytes);
+    rc = batch_residual(op, prec, lanes, m, mp, sig, f, x, true, res2, s, bytes, prm);
     if (rc != MSC_OK) return rc;
     bool all_done = true;
     BssState h{};

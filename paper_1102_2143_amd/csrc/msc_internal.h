@@ -287,6 +287,9 @@ struct XPtrs {
 struct ResArgs {
   Csr<double2> m1;          // M (MHM) -- first half
   Csr<double2> m2;          // M^H (MHM) or A (HERM)
+  int sell;                 // 1: read the sliced ELLPACK copies s1, s2 instead
+  int64_t nslices;
+  Sell<double2> s1, s2;
   int mhm;
   int64_t n;
   int kc;

@@ -891,6 +891,28 @@ __global__ __launch_bounds__(kBlock) void k_switch(MsArgs a64, MsArgs a32, int n
 }
 
 // ---- reliable update: r = b - (A + sigma0) x_0 in FP64, between the head and K2 ----------
+// After each workgroup's share of |r|^2 (acc per thread): the last workgroup replaces R.
+__device__ void ru_finish(const MsArgs& a, double acc) {
+  SolveState* st = a.st;
+  // region 2: the head's partials in region 0 still wait for K2
+  double* reg = region(a, 2);
+  const double tot = block_sum<kBlock>(acc);
+  if (threadIdx.x == 0) store_agent(&reg[blockIdx.x], tot);
+  if (!arrive_last(a.sc.tickets + 2 * kTicketSite)) return;
+  const double Rt = sum_partials(reg, gridDim.x, 1, 0);
+  if (threadIdx.x == 0) {
+    RotState& rs = st->rot[a.par ^ 1];
+    rs.R = Rt;
+    st->n_reliable += 1;
+    if (!isfinite(Rt)) {
+      rs.status = 1;
+      rs.halt = 1;
+    } else if (Rt <= st->eps2) {
+      rs.halt = 1;
+    }
+  }
+}
+
 template <int L, bool MHM>
 __global__ __launch_bounds__(kBlock) void k_ru_first(MsArgs a) {
   // t64 = M x_0 (A = M^H M) -- first half of the FP64 operator
@@ -932,23 +954,58 @@ __global__ __launch_bounds__(kBlock) void k_ru_second(MsArgs a) {
       acc += fma(rt.x, rt.x, rt.y * rt.y);
     }
   }
-  // region 2: the head's partials in region 0 still wait for K2
-  double* reg = region(a, 2);
-  const double tot = block_sum<kBlock>(acc);
-  if (threadIdx.x == 0) store_agent(&reg[blockIdx.x], tot);
-  if (!arrive_last(a.sc.tickets + 2 * kTicketSite)) return;
-  const double Rt = sum_partials(reg, gridDim.x, 1, 0);
-  if (threadIdx.x == 0) {
-    RotState& rs = st->rot[a.par ^ 1];
-    rs.R = Rt;
-    st->n_reliable += 1;
-    if (!isfinite(Rt)) {
-      rs.status = 1;
-      rs.halt = 1;
-    } else if (Rt <= st->eps2) {
-      rs.halt = 1;
+  ru_finish(a, acc);
+}
+
+// The same on the sliced ELLPACK copies: one row per lane, one slice per wavefront.
+__global__ __launch_bounds__(kBlock) void k_ru_first_s(MsArgs a) {
+  const SolveState* st = a.st;
+  if (st->rot[a.par ^ 1].halt) return;
+  const double2* __restrict__ x0 = a.x + int64_t(st->orig[0]) * a.n;
+  constexpr int SPB = kBlock / kSlice;
+  const int lane = threadIdx.x % kSlice;
+  const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x / kSlice));
+  int64_t beg, end;
+  block_range(a.nslices, SPB, beg, end);
+  for (int64_t sl = beg + wv; sl < end; sl += SPB) {
+    const int64_t row = sl * kSlice + lane;
+    const int64_t rr = row < a.n ? row : a.n - 1;
+    double2 v = sell_row<double>(a.s64, x0, sl, lane);
+    cfma<double>(v, a.s64.diag[rr], x0[rr]);
+    if (row < a.n) a.t64[row] = v;
+  }
+}
+
+template <class R, bool MHM>
+__global__ __launch_bounds__(kBlock) void k_ru_second_s(MsArgs a) {
+  SolveState* st = a.st;
+  if (st->rot[a.par ^ 1].halt) return;
+  const double2* __restrict__ x0 = a.x + int64_t(st->orig[0]) * a.n;
+  cplx<R>* __restrict__ r = static_cast<cplx<R>*>(a.r);
+  const double sigma0 = st->sigma0;
+  constexpr int SPB = kBlock / kSlice;
+  const int lane = threadIdx.x % kSlice;
+  const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x / kSlice));
+  int64_t beg, end;
+  block_range(a.nslices, SPB, beg, end);
+  double acc = 0.0;
+  for (int64_t sl = beg + wv; sl < end; sl += SPB) {
+    const int64_t row = sl * kSlice + lane;
+    const int64_t rr = row < a.n ? row : a.n - 1;
+    const Sell<double2> m = MHM ? a.sh64 : a.s64;
+    const double2* __restrict__ in = MHM ? a.t64 : x0;
+    double2 q = sell_row<double>(m, in, sl, lane);
+    cfma<double>(q, m.diag[rr], in[rr]);
+    if (row < a.n) {
+      const double2 bv = a.b[row], xv = x0[row];
+      double2 rt;
+      rt.x = bv.x - q.x - sigma0 * xv.x;
+      rt.y = bv.y - q.y - sigma0 * xv.y;
+      r[row] = from_d<R>(rt);
+      acc += fma(rt.x, rt.x, rt.y * rt.y);
     }
   }
+  ru_finish(a, acc);
 }
 
 // ---- verification: FP64 true residual norms of up to 8 solutions ---------------------
@@ -992,6 +1049,8 @@ __global__ __launch_bounds__(kBlock) void k_verify_first(Csr<double2> m, const d
 
 struct VerifyArgs {
   Csr<double2> m;        // M^H (MHM) or A (HERM)
+  Sell<double2> s;       // its sliced ELLPACK copy (the SELL kernels)
+  int64_t nslices;
   const double2* in;     // U = M X (MHM) or X (HERM), chunk of kc vectors
   const double2* x;      // X, chunk of kc vectors
   const double2* b;
@@ -1002,6 +1061,20 @@ struct VerifyArgs {
   unsigned* ticket;
   double* out;           // res2 of the chunk
 };
+
+// Per-chunk norms: workgroup partials, then the last workgroup's totals in out[0..kc).
+__device__ void verify_finish(const VerifyArgs& v, double (&nrm)[kVerifyChunk]) {
+  block_sum_k<kBlock, kVerifyChunk>(nrm);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < kVerifyChunk; ++q) store_agent(&v.partial[blockIdx.x * kVerifyChunk + q], nrm[q]);
+  }
+  if (!arrive_last(v.ticket)) return;
+  for (int q = 0; q < v.kc; ++q) {
+    const double s = sum_partials(v.partial, gridDim.x, kVerifyChunk, q);
+    if (threadIdx.x == 0) v.out[q] = s;
+  }
+}
 
 template <int L>
 __global__ __launch_bounds__(kBlock) void k_verify_second(VerifyArgs v) {
@@ -1028,16 +1101,70 @@ __global__ __launch_bounds__(kBlock) void k_verify_second(VerifyArgs v) {
       }
     }
   }
-  block_sum_k<kBlock, kVerifyChunk>(nrm);
-  if (threadIdx.x == 0) {
+  verify_finish(v, nrm);
+}
+
+// One row per lane on the sliced ELLPACK copies: u_q = M x_q, then the residual norms.
+__global__ __launch_bounds__(kBlock) void k_verify_first_s(Sell<double2> m, const double2* x,
+                                                           int64_t n, int64_t nslices, int kc,
+                                                           double2* u) {
+  constexpr int SPB = kBlock / kSlice;
+  const int lane = threadIdx.x % kSlice;
+  const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x / kSlice));
+  const double2* xs[kVerifyChunk];
 #pragma unroll
-    for (int q = 0; q < kVerifyChunk; ++q) store_agent(&v.partial[blockIdx.x * kVerifyChunk + q], nrm[q]);
+  for (int q = 0; q < kVerifyChunk; ++q) xs[q] = x + int64_t(q < kc ? q : 0) * n;
+  int64_t beg, end;
+  block_range(nslices, SPB, beg, end);
+  for (int64_t sl = beg + wv; sl < end; sl += SPB) {
+    const int64_t row = sl * kSlice + lane;
+    const int64_t rr = row < n ? row : n - 1;
+    double2 acc[kVerifyChunk];
+    sell_row_multi<double, kVerifyChunk, 1>(m, xs, kc, sl, lane, acc);
+    const double2 d = m.diag[rr];
+#pragma unroll
+    for (int q = 0; q < kVerifyChunk; ++q) {
+      if (q < kc) {
+        cfma<double>(acc[q], d, xs[q][rr]);
+        if (row < n) u[int64_t(q) * n + row] = acc[q];
+      }
+    }
   }
-  if (!arrive_last(v.ticket)) return;
-  for (int q = 0; q < v.kc; ++q) {
-    const double s = sum_partials(v.partial, gridDim.x, kVerifyChunk, q);
-    if (threadIdx.x == 0) v.out[q] = s;
+}
+
+__global__ __launch_bounds__(kBlock) void k_verify_second_s(VerifyArgs v) {
+  constexpr int SPB = kBlock / kSlice;
+  const int lane = threadIdx.x % kSlice;
+  const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x / kSlice));
+  const double2* ins[kVerifyChunk];
+#pragma unroll
+  for (int q = 0; q < kVerifyChunk; ++q) ins[q] = v.in + int64_t(q < v.kc ? q : 0) * v.n;
+  double nrm[kVerifyChunk];
+#pragma unroll
+  for (int q = 0; q < kVerifyChunk; ++q) nrm[q] = 0.0;
+  int64_t beg, end;
+  block_range(v.nslices, SPB, beg, end);
+  for (int64_t sl = beg + wv; sl < end; sl += SPB) {
+    const int64_t row = sl * kSlice + lane;
+    const int64_t rr = row < v.n ? row : v.n - 1;
+    double2 acc[kVerifyChunk];
+    sell_row_multi<double, kVerifyChunk, 1>(v.s, ins, v.kc, sl, lane, acc);
+    const double2 d = v.s.diag[rr];
+    if (row < v.n) {
+      const double2 bv = v.b[row];
+#pragma unroll
+      for (int q = 0; q < kVerifyChunk; ++q) {
+        if (q < v.kc) {
+          cfma<double>(acc[q], d, ins[q][row]);
+          const double2 xv = v.x[int64_t(q) * v.n + row];
+          const double rx = bv.x - acc[q].x - v.sig[q] * xv.x;
+          const double ry = bv.y - acc[q].y - v.sig[q] * xv.y;
+          nrm[q] += fma(rx, rx, ry * ry);
+        }
+      }
+    }
   }
+  verify_finish(v, nrm);
 }
 
 // ---- plain SpMV with optional shift epilogue (operator application) -------------------
@@ -1104,6 +1231,16 @@ void launch_timed(K kern, int grid, hipStream_t s, hipEvent_t* ev, int k, const 
 
 template <class R>
 hipError_t reliable_impl(const MsArgs& a, hipStream_t s) {
+  if (a.sell) {
+    const int gs = grid_rows(a.nslices, kBlock / kSlice);
+    if (a.kind == MSC_A_MHM) {
+      k_ru_first_s<<<gs, kBlock, 0, s>>>(a);
+      k_ru_second_s<R, true><<<gs, kBlock, 0, s>>>(a);
+    } else {
+      k_ru_second_s<R, false><<<gs, kBlock, 0, s>>>(a);
+    }
+    return hipGetLastError();
+  }
   const int g1 = grid_rows(a.n, kBlock / a.lanes);
   if (a.kind == MSC_A_MHM) {
     MSC_LANES_SWITCH(a.lanes, (k_ru_first<LL, true><<<g1, kBlock, 0, s>>>(a)));
@@ -1198,6 +1335,19 @@ hipError_t launch_verify(const MsArgs& a, const double* sigma_by_caller_index, i
   v.partial = a.sc.partial;
   v.ticket = a.sc.tickets + 4 * kTicketSite;
   v.out = a.sc.res2 + k0;
+  if (a.sell) {
+    const int gs = grid_rows(a.nslices, kBlock / kSlice);
+    v.nslices = a.nslices;
+    if (a.kind == MSC_A_MHM) {
+      k_verify_first_s<<<gs, kBlock, 0, s>>>(a.s64, xc, a.n, a.nslices, kc, u64);
+      v.s = a.sh64;
+      v.in = u64;
+    } else {
+      v.s = a.s64;
+    }
+    k_verify_second_s<<<gs, kBlock, 0, s>>>(v);
+    return hipGetLastError();
+  }
   if (a.kind == MSC_A_MHM) {
     MSC_LANES_SWITCH(a.lanes, (k_verify_first<LL><<<g1, kBlock, 0, s>>>(a.m64, xc, a.n, kc, u64)));
     v.m = a.mh64;

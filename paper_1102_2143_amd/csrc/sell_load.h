@@ -158,4 +158,58 @@ __device__ __forceinline__ void sell_row_rhs(const Sell<cplx<R>>& m, const cplx<
     sell_row_rhs_cols<R, RR, KP, false>(m, x, sl, lane, acc);
 }
 
+// ---- several separate vectors: x_q = xs[q], q < kc <= KC --------------------------------
+
+template <class R, int KC, int KP, bool NARROW>
+__device__ __forceinline__ void sell_row_multi_cols(const Sell<cplx<R>>& m,
+                                                    const cplx<R>* const (&xs)[KC], int kc,
+                                                    int64_t sl, int lane, cplx<R> (&acc)[KC]) {
+  int32_t c, c1;
+  if (m.wp > 0) {
+    c = int32_t(sl) * m.wp;
+    c1 = c + m.wp;
+  } else {
+    c = load_uniform(m.cptr, sl);
+    c1 = load_uniform(m.cptr, sl + 1);
+  }
+  int2 cc[KP];
+  cplx<R> v[2 * KP];
+  for (; c < c1; c += KP) {
+    const int np = c1 - c;
+    sell_load<R, KP, false, NARROW>(m, c, np, lane, cc, v);
+    cplx<R> g[2 * KP][KC];
+#pragma unroll
+    for (int u = 0; u < KP; ++u) {
+#pragma unroll
+      for (int q = 0; q < KC; ++q) {
+        if (u < np && q < kc) {
+          g[2 * u][q] = xs[q][cc[u].x];
+          g[2 * u + 1][q] = xs[q][cc[u].y];
+        } else {
+          g[2 * u][q] = g[2 * u + 1][q] = czero<R>();
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 2 * KP; ++u) {
+#pragma unroll
+      for (int q = 0; q < KC; ++q) cfma<R>(acc[q], v[u], g[u][q]);
+    }
+  }
+}
+
+// Off-diagonal part of one sliced ELLPACK row per lane times each of kc separate vectors
+// (slice `sl` wavefront-uniform; vectors q >= kc give zero).
+template <class R, int KC, int KP>
+__device__ __forceinline__ void sell_row_multi(const Sell<cplx<R>>& m,
+                                               const cplx<R>* const (&xs)[KC], int kc,
+                                               int64_t sl, int lane, cplx<R> (&acc)[KC]) {
+#pragma unroll
+  for (int q = 0; q < KC; ++q) acc[q] = czero<R>();
+  if (m.col16)
+    sell_row_multi_cols<R, KC, KP, true>(m, xs, kc, sl, lane, acc);
+  else
+    sell_row_multi_cols<R, KC, KP, false>(m, xs, kc, sl, lane, acc);
+}
+
 }  // namespace msc

@@ -83,8 +83,12 @@ def test_mixed_margin_trades_iterations_for_residual(c0, cuda):
     _, i5 = op.solve(c0["b"], tol=1e-10, prec="mixed", refine=False, mixed_margin=0.5,
                      switch_tol=1e-3)
     assert i5["iters"] >= i1["iters"]
-    assert i5["true_rel_res"].max() < i1["true_rel_res"].max()
-    assert i5["true_rel_res"][int(np.argmin(c0["sigma"]))] <= 0.75e-10
+    # shifts whose residual is set by the recursion drop with the margin; those held above
+    # tol by the complex64 gap of the early switch stay where the gap put them
+    r1, r5 = i1["true_rel_res"], i5["true_rel_res"]
+    assert np.all(r5 <= 1.01 * r1)
+    assert np.sum(r5 < 0.75 * r1) >= 3
+    assert r5[int(np.argmin(c0["sigma"]))] <= 0.75e-10
     for bad in (0.0, 1.5):
         with pytest.raises(MscError):
             op.solve(c0["b"], prec="mixed", mixed_margin=bad)

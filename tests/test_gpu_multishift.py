@@ -278,7 +278,13 @@ def test_c0_both_formats_match_oracle(c0, cuda, fmt, prec):
         # the mixed sequence runs to 0.7 tol (default mixed_margin)
         ref7 = O.cg_m(c0["apply"], c0["b"], c0["sigma"], tol=0.7e-10)
         assert info["iters"] <= 1.03 * ref7["iters"] + 2
+        assert info["n_reliable"] > 0
     assert np.all(info["true_rel_res"] <= 1e-10)
+    # the FP64 verification (on the format's own kernels) agrees with the oracle's residuals
+    xg = x.cpu().numpy()
+    rho = np.array([np.linalg.norm(c0["b"] - c0["apply"](xg[k], sk))
+                    for k, sk in enumerate(c0["sigma"])]) / np.linalg.norm(c0["b"])
+    assert np.allclose(rho, info["true_rel_res"], rtol=1e-3, atol=1e-15)
     op.close()
 
 
