@@ -92,6 +92,11 @@ typedef struct {
     double mixed_margin;     /* mixed: the sequence runs until its recursive residuals
                                 reach mixed_margin * tol (0 < margin <= 1), so that the
                                 complex64 drift leaves few shifts above tol     (0.7)  */
+    int32_t two_step;        /* 1: every other iteration defers its all-shift update and
+                                the next applies both steps in one pass over x_k and p_k
+                                (same recurrences, half the traffic of those vectors);
+                                0: one step per iteration                        (1)    */
+    int32_t reserved;        /* must be 0                                        (0)    */
 } msc_params;
 
 /* Per-solve report.  Array members are caller-owned host arrays of length ns (or

@@ -56,7 +56,8 @@ template <class T> void dfree(T*& p) {
 }
 
 void free_workspace(Workspace& w) {
-  for (void* q : {w.r, w.p[0], w.p[1], w.t, w.pk, w.r32, w.p32[0], w.p32[1], w.t32, w.pk32})
+  for (void* q : {w.r, w.p[0], w.p[1], w.t, w.pk, w.r32, w.p32[0], w.p32[1], w.t32, w.pk32,
+                  w.rprev})
     if (q) (void)hipFree(q);
   dfree(w.t64);
   dfree(w.u64);
@@ -92,6 +93,7 @@ msc_status ensure_workspace(msc_op op, int prec, int ns) {
     HIP_TRY(hipMalloc(&w.pk, sizeof(double2) * n * nk));
     HIP_TRY(dalloc(&w.t64, n));
     HIP_TRY(dalloc(&w.u64, n * 8));
+    HIP_TRY(hipMalloc(&w.rprev, sizeof(double2) * n));
     HIP_TRY(dalloc(&w.st, 1));
     HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&w.h_halt), 4 * sizeof(int), hipHostMallocDefault));
     HIP_TRY(hipEventCreateWithFlags(&w.ev[0], hipEventDisableTiming));
@@ -172,6 +174,9 @@ MsArgs make_args(msc_op op, int lanes, const double* d_b, double* d_x) {
   a.pb[1] = op->ws.p[1];
   a.t = op->ws.t;
   a.pk = op->ws.pk;
+  a.rprev = op->ws.rprev;  // complex64 use in the second phase of a mixed solve
+  a.defer_ok = 0;
+  a.sample = -1;
   a.t64 = op->ws.t64;
   a.st = op->ws.st;
   a.sc = op->scratch;
@@ -188,19 +193,24 @@ struct KernelBytes {
 };
 // launch with `act` active shifts; ib / ibh: bytes per column index of the copies of the
 // operator's matrix and of M^H that the SpMVs read.
+// `mode` is the head's update mode (0: one step; 1: deferred, r kept; 2: two steps, the
+// kept r read back).
 KernelBytes kernel_bytes(int kind, int prec, double n, double nnz, double nnz_h, double act,
-                         bool pending, double ib, double ibh) {
+                         bool pending, double ib, double ibh, int mode) {
   const double w = prec == MSC_PREC_MIXED ? 8.0 : 16.0;
   KernelBytes b{};
   b.k1 = nnz * (w + ib) + 4.0 * (n + 1) + 2.0 * n * w;
   b.k2 = (kind == MSC_A_MHM ? nnz_h * (w + ibh) + 4.0 * (n + 1) + n * w : n * w) + 3.0 * n * w;
-  b.upd = pending ? n * (3.0 * w + 32.0) + act * n * (32.0 + 2.0 * w) : 0.0;
+  b.upd = pending ? n * (3.0 * w + 32.0) + act * n * (32.0 + 2.0 * w) + (mode != 0 ? n * w : 0.0)
+                  : 0.0;
   b.head = b.k1 + (pending ? b.upd - n * w : 0.0);
   return b;
 }
 
+// act_sum: x_j/p_j row-vector updates performed (shifts listed, summed over the heads);
+// kept: heads that kept r for a deferred step or read it back.
 double iter_bytes(int kind, int prec, double n, double nnz, double nnz_h, double act_sum,
-                  double iters, double ib, double ibh) {
+                  double iters, double ib, double ibh, double kept) {
   const double w = prec == MSC_PREC_MIXED ? 8.0 : 16.0;   // Krylov vector element
   const double vb = prec == MSC_PREC_MIXED ? 8.0 : 16.0;  // matrix value
   const double mat = (nnz * (vb + ib) + 4.0 * (n + 1)) +
@@ -212,7 +222,7 @@ double iter_bytes(int kind, int prec, double n, double nnz, double nnz_h, double
     vec = n * (w + w) + n * (w + w + 2 * w);  // K1: p, t; K2: t, p, r r/w
   vec += n * (w + 2 * w + 32.0);               // K3: r, p r/w, x_0 r/w
   const double per_shift = n * (32.0 + 2 * w); // x_j r/w (complex128) + p_j r/w
-  return iters * (mat + vec) + act_sum * per_shift;
+  return iters * (mat + vec) + act_sum * per_shift + kept * n * w;
 }
 
 // Events for sampled per-kernel timing; destroyed with the pool.
@@ -308,13 +318,17 @@ msc_status run_multishift(msc_op op, const double* d_b, double* d_x, const msc_p
   while (!done) {
     for (int g = 0; g < G; ++g) {
       hipEvent_t* ev = nullptr;
-      // a mixed solve is timed in its complex64 phase only
-      if (prm.timing > 0 && launched % prm.timing == 0 && (!mixed || phase == MSC_PREC_MIXED)) {
+      cur->sample = -1;
+      // a mixed solve is timed in its complex64 phase only; consecutive launches are
+      // sampled in pairs (a deferring head and the one that applies two steps)
+      if (prm.timing > 0 && launched % prm.timing < 2 && (!mixed || phase == MSC_PREC_MIXED) &&
+          int(sample_launch.size()) < kMaxSamples) {
         ev = pool.next();
         if (!ev) {
           set_error("msc_solve: event creation failed");
           return MSC_EHIP;
         }
+        cur->sample = int(sample_launch.size());
         sample_launch.push_back(launched);
       }
       // iteration `launched` starts from the state rot[launched & 1]; in the complex64
@@ -324,6 +338,9 @@ msc_status run_multishift(msc_op op, const double* d_b, double* d_x, const msc_p
       const int since = launched - launched_at_switch;
       const bool ru = phase == MSC_PREC_MIXED && prm.reliable_every > 0 && since > 0 &&
                       since % prm.reliable_every == 0;
+      // a head followed by a reliable update applies its own step (the update may halt
+      // the sequence before the next head)
+      cur->defer_ok = (prm.two_step && !ru) ? 1 : 0;
       HIP_TRY(launch_iteration(phase, *cur, s, ev, ru));
       ++launched;
     }
@@ -376,17 +393,12 @@ msc_status run_multishift(msc_op op, const double* d_b, double* d_x, const msc_p
         HIP_TRY(hipEventElapsedTime(&ms, pool.groups[q][2 * k], pool.groups[q][2 * k + 1]));
         info->kernel_ms[k] += ms;
       }
-      // iterations completed before this launch's head, and the shifts its update touched
+      // the head's update mode and the shifts it listed, as recorded by the head itself
       const bool ph32 = launched_at_switch >= 0 && L >= launched_at_switch;
-      const int done_before = ph32 ? iter_at_switch + (L - launched_at_switch) : L;
       const bool pending = !(L == 0 || (ph32 && L == launched_at_switch));
-      int act = 0;
-      for (int j = 1; j < ns; ++j) {
-        const int last = h.freeze_iter[j] >= 0 ? h.freeze_iter[j] : fin.iter;
-        if (last >= done_before + 1) ++act;
-      }
+      const int mode = h.smp_mode[q], act = h.smp_nact[q];
       const KernelBytes kb = kernel_bytes(op->kind, ph32 ? MSC_PREC_MIXED : prec, nn, nz, nzh,
-                                          double(act), pending, ib, ibh);
+                                          double(act), pending, ib, ibh, mode);
       info->kernel_bytes[0] += a64.sell ? kb.head : kb.k1;
       info->kernel_bytes[1] += kb.k2;
       if (!a64.sell) info->kernel_bytes[2] += kb.upd;
@@ -406,18 +418,14 @@ msc_status run_multishift(msc_op op, const double* d_b, double* d_x, const msc_p
   *status_out = fin.status;
   if (info) info->n_reliable = h.n_reliable;
 
-  // active-shift count summed over iterations, for the byte model: shift j (>= 1) was
-  // updated in iterations 1..freeze_iter (or all); split at the precision switch
-  double act64 = 0.0, act32 = 0.0;
-  for (int j = 1; j < ns; ++j) {
-    const int last = (h.freeze_iter[j] >= 0) ? h.freeze_iter[j] : fin.iter;
-    act64 += std::min(last, iters_fp64);
-    act32 += std::max(0, last - iters_fp64);
-  }
+  // shift-vector updates and kept-r passes counted by the heads, per phase
+  const double act64 = h.n_shift_upd[0], act32 = h.n_shift_upd[1];
+  const double kept64 = h.n_defer[0] + h.n_two[0], kept32 = h.n_defer[1] + h.n_two[1];
   const double nn = double(op->n), nz = double(op->nnz), nzh = double(op->nnz_h);
-  *bytes_out = iter_bytes(op->kind, MSC_PREC_FP64, nn, nz, nzh, act64, double(iters_fp64), ib, ibh) +
+  *bytes_out = iter_bytes(op->kind, MSC_PREC_FP64, nn, nz, nzh, act64, double(iters_fp64), ib, ibh,
+                          kept64) +
                iter_bytes(op->kind, MSC_PREC_MIXED, nn, nz, nzh, act32,
-                          double(fin.iter - iters_fp64), ib, ibh) +
+                          double(fin.iter - iters_fp64), ib, ibh, kept32) +
                double(h.n_reliable) * (nz * (16.0 + ib) + nzh * (16.0 + ibh) +
                                        4.0 * (nn + 1) * (op->kind == MSC_A_MHM ? 2.0 : 1.0) +
                                        nn * (16.0 * 3 + 8.0));
@@ -1153,8 +1161,9 @@ struct BatchRun {
           const double nn = double(n), nz = double(op->nnz), nzh = double(op->nnz_h);
           const double ib = index_bytes(sys[s].sell, sys[s].s64);
           const double ibh = index_bytes(sys[s].sell, sys[s].sh64);
-          I.alg_bytes = iter_bytes(op->kind, MSC_PREC_FP64, nn, nz, nzh, act64, i64, ib, ibh) +
-                        iter_bytes(op->kind, MSC_PREC_MIXED, nn, nz, nzh, act32, it - i64, ib, ibh) -
+          I.alg_bytes = iter_bytes(op->kind, MSC_PREC_FP64, nn, nz, nzh, act64, i64, ib, ibh, 0.0) +
+                        iter_bytes(op->kind, MSC_PREC_MIXED, nn, nz, nzh, act32, it - i64, ib, ibh,
+                                   0.0) -
                         (double(nrhs[s]) - 1.0) / double(nrhs[s]) *
                             ((nz * (16.0 + ib) + nzh * (16.0 + ibh)) * i64 +
                              (nz * (8.0 + ib) + nzh * (8.0 + ibh)) * (it - i64));
@@ -1199,6 +1208,7 @@ void msc_params_default(msc_params* p) {
   p->lanes = 0;
   p->verify = 1;
   p->mixed_margin = 0.7;
+  p->two_step = 1;
 }
 
 const char* msc_version(void) { return "msc 0.1 (gfx950)"; }
@@ -1403,8 +1413,9 @@ msc_status msc_solve(msc_op op, const double* d_b, double* d_x, const msc_params
   else
     msc_params_default(&prm);
   if (!(prm.tol >= 0.0) || (prm.prec != MSC_PREC_FP64 && prm.prec != MSC_PREC_MIXED) ||
-      !(prm.mixed_margin > 0.0 && prm.mixed_margin <= 1.0)) {
-    set_error("msc_solve: invalid tol, precision or mixed_margin");
+      !(prm.mixed_margin > 0.0 && prm.mixed_margin <= 1.0) ||
+      (prm.two_step != 0 && prm.two_step != 1) || prm.reserved != 0) {
+    set_error("msc_solve: invalid tol, precision, mixed_margin, two_step or reserved");
     return MSC_EINVAL;
   }
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -1433,8 +1444,9 @@ msc_status msc_solve_adjoint(msc_op op, const double* d_g, const double* d_x, do
   else
     msc_params_default(&prm);
   if (!(prm.tol >= 0.0) || (prm.prec != MSC_PREC_FP64 && prm.prec != MSC_PREC_MIXED) ||
-      !(prm.mixed_margin > 0.0 && prm.mixed_margin <= 1.0)) {
-    set_error("msc_solve_adjoint: invalid tol, precision or mixed_margin");
+      !(prm.mixed_margin > 0.0 && prm.mixed_margin <= 1.0) ||
+      (prm.two_step != 0 && prm.two_step != 1) || prm.reserved != 0) {
+    set_error("msc_solve_adjoint: invalid tol, precision, mixed_margin, two_step or reserved");
     return MSC_EINVAL;
   }
   prm.verify = 1;
@@ -1588,8 +1600,10 @@ msc_status msc_solve_batched(int32_t nsys, const msc_op* ops, const int32_t* nrh
     msc_params_default(&prm);
   if (!(prm.tol >= 0.0) || (prm.prec != MSC_PREC_FP64 && prm.prec != MSC_PREC_MIXED) ||
       !(prm.mixed_margin > 0.0 && prm.mixed_margin <= 1.0) ||
-      prm.format < MSC_FORMAT_AUTO || prm.format > MSC_FORMAT_SELL32) {
-    set_error("msc_solve_batched: invalid tol, precision, mixed_margin or format");
+      prm.format < MSC_FORMAT_AUTO || prm.format > MSC_FORMAT_SELL32 ||
+      (prm.two_step != 0 && prm.two_step != 1) || prm.reserved != 0) {
+    set_error("msc_solve_batched: invalid tol, precision, mixed_margin, format, two_step or "
+              "reserved");
     return MSC_EINVAL;
   }
   int rr = 1, max_nrhs = 0;

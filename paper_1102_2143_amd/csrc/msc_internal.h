@@ -38,9 +38,14 @@ struct RotState {
   int status;                  // 0 running/ok, 1 breakdown
   int pending;                 // 1: the previous K2's r awaits its update of x, p_j and p
   int pcur;                    // which of the two direction buffers holds p
+  int defer;                   // 1: the head that wrote this state left its all-shift
+                               // update to the next head (SolveState::d_*)
   double zeta[kMaxShifts];     // zeta_j^(n)
   int active[kMaxShifts];      // shift j still updated
 };
+
+// Head launches whose update mode is recorded for the byte model of sampled timings.
+constexpr int kMaxSamples = 256;
 
 struct SolveState {
   double a;          // a_n = R / (p^H (A + sigma0) p)      (K2, workgroup 0)
@@ -64,6 +69,22 @@ struct SolveState {
   int freeze_iter[kMaxShifts];
   int orig[kMaxShifts];         // caller's index of sorted shift j
   RotState rot[2];              // rot[par]: state at the start of an iteration of parity par
+  // the all-shift update step a head deferred to the next one: a_j, zeta_j^(n+1), b_j of
+  // that step, whether shift j took part and whether it updated p_j (did not freeze)
+  double d_a[kMaxShifts];
+  double d_z[kMaxShifts];
+  double d_b[kMaxShifts];
+  int d_act[kMaxShifts];
+  int d_upd[kMaxShifts];
+  // per sampled head launch (MsArgs::sample): its update mode (Plan) and shifts listed
+  int smp_mode[kMaxSamples];
+  int smp_nact[kMaxSamples];
+  // per phase (0: FP64, 1: complex64): x_j/p_j row updates performed (in units of n
+  // rows), heads that deferred their update, heads that applied two steps
+  int n_shift_upd[2];
+  int n_defer[2];
+  int n_two[2];
+  int pad2_[2];
 };
 
 // Per-kernel partial-sum scratch, sized for kMaxGrid workgroups x kMaxShifts values.
@@ -130,6 +151,8 @@ struct Workspace {
   void* t32 = nullptr;
   void* pk32 = nullptr;
   double2* t64 = nullptr;   // n complex128 (reliable updates, verification)
+  void* rprev = nullptr;    // n complex128 (complex64 in the second phase): r kept by a
+                            // head that defers its all-shift update
   double2* u64 = nullptr;   // 8 * n complex128 (verification SpMM chunk)
   SolveState* st = nullptr;
   int* h_halt = nullptr;    // pinned host mirrors of st->halt, double buffered
@@ -221,6 +244,9 @@ struct MsArgs {
   double2* x;            // caller's x, shift-major, caller order
   void* r; void* t; void* pk;
   void* pb[2];           // the two direction buffers (p of consecutive iterations)
+  void* rprev;           // r kept by a head that defers its all-shift update
+  int defer_ok;          // 1: this launch's head may defer its all-shift update
+  int sample;            // slot of SolveState::smp_* for this head, -1: not sampled
   double2* t64;
   SolveState* st;
   Scratch sc;

@@ -371,35 +371,56 @@ constexpr int kUpdGroup = MSC_UPD_GROUP;
 
 struct Plan {
   double bn;                 // b of p <- r + b p (0: p is current, nothing pending)
-  // the shifts updated by this head, in list order: coefficients, the element offsets of
-  // x_j (the caller's order) and of p_j, and whether p_j is updated (0: j freezes now)
-  double bk[kMaxShifts];
-  double zk[kMaxShifts];
-  double ak[kMaxShifts];
+  // the shifts this head updates, in list order: x_j += cx_p p_j + cx_r r0 and, where pw,
+  // p_j <- cp_p p_j + cp_r0 r0 + cp_r1 r (r: the current residual; r0: the one a deferring
+  // head kept), with the element offsets of x_j (the caller's order) and of p_j
+  double cx_p[kMaxShifts];
+  double cx_r[kMaxShifts];
+  double cp_p[kMaxShifts];
+  double cp_r0[kMaxShifts];
+  double cp_r1[kMaxShifts];
   int64_t xo[kMaxShifts];
   int64_t po[kMaxShifts];
-  int upd_p[kMaxShifts];
+  int pw[kMaxShifts];
   int nact;
+  int mode;                  // 0: one step; 1: deferred (r kept, shifts untouched);
+                             // 2: the deferred step and this one together
   int pending;               // the update runs in this head
   int ok;                    // 0: breakdown, the head stops
   int spmv;                  // 1: this head also computes t = M p
 };
 
+// Two consecutive steps A, B of shift j combine into one pass over its vectors:
+//   x += a_A p + a_B p',  p' = zeta_A r0 + b_A p,  p'' = zeta_B r + b_B p'
+// so x += (a_A + a_B b_A) p + a_B zeta_A r0 and p'' = b_B b_A p + b_B zeta_A r0 + zeta_B r;
+// a shift that froze at A takes only x += a_A p, one that freezes at B ends with p'.
+template <class T>
 __device__ void head_plan(const MsArgs& a, const Early& e, Plan& pl) {
+  constexpr int ph = sizeof(T) == 4 ? 1 : 0;  // phase: 0 FP64, 1 complex64
   SolveState* st = a.st;
   const RotState& rs = st->rot[a.par];
   RotState& nx = st->rot[a.par ^ 1];
   const int j = threadIdx.x;
   const int pending = rs.pending;
+  const int two = rs.defer;
   // wave 0, lane j: shift j's state, loaded before the partial sum
-  int act0 = 0, origj = 0;
-  double z = 1.0, zn = 0.0, akj = 0.0;
-  if (pending && j >= 1 && j < kWave && j < st->ns) {
-    act0 = rs.active[j];
-    z = rs.zeta[j];
-    zn = st->zk[j];
-    akj = st->ak[j];
-    origj = st->orig[j];
+  int act0 = 0, origj = 0, dact = 0, dupd = 0;
+  double z = 1.0, zn = 0.0, akj = 0.0, da = 0.0, dz = 0.0, db = 0.0;
+  if (j >= 1 && j < kWave && j < st->ns) {
+    if (pending) {
+      act0 = rs.active[j];
+      z = rs.zeta[j];
+      zn = st->zk[j];
+      akj = st->ak[j];
+    }
+    if (pending || two) origj = st->orig[j];
+    if (two) {
+      dact = st->d_act[j];
+      dupd = st->d_upd[j];
+      da = st->d_a[j];
+      dz = st->d_z[j];
+      db = st->d_b[j];
+    }
   }
   const double R = rs.R, eps2 = st->eps2;
   const int kst = st->kstatus, frz = st->freeze;
@@ -409,33 +430,75 @@ __device__ void head_plan(const MsArgs& a, const Early& e, Plan& pl) {
     const double bn = pending ? Rn / R : 0.0;
     const bool act = pending && ok && act0;
     const bool freeze_now = act && frz && zn * zn * Rn <= eps2;
-    const uint64_t mask = __ballot(act);
-    if (act) {
-      const int pos = __popcll(mask & ((uint64_t(1) << j) - 1));
-      const double ratio = zn / z;
-      pl.bk[pos] = bn * ratio * ratio;
-      pl.zk[pos] = zn;
-      pl.ak[pos] = akj;
-      pl.xo[pos] = int64_t(origj) * a.n;
-      pl.po[pos] = int64_t(j - 1) * a.n;
-      pl.upd_p[pos] = freeze_now ? 0 : 1;
-    }
+    const double ratio = act ? zn / z : 0.0;
+    const double bk = bn * ratio * ratio;
     const int it = pending ? rs.iter + 1 : rs.iter;
     const bool done = pending && (Rn <= eps2 || it >= st->max_iter);
     // the FP64 phase of a mixed solve ends here: the update still runs, then the host
     // converts the Krylov vectors to complex64 and continues
     const bool sw = pending && !done && Rn <= st->sw_eps2;
+    const bool cont = ok && !done && !sw;
+    // a head defers only when the iteration continues and nothing is deferred yet; the
+    // head after it (or a halting one) applies both steps
+    const int mode = two ? 2 : ((pending && cont && a.defer_ok) ? 1 : 0);
+    bool listed = false, pw = false;
+    double cxp = 0.0, cxr = 0.0, cpp = 0.0, cpr0 = 0.0, cpr1 = 0.0;
+    if (mode == 0) {
+      listed = act;
+      cxp = akj;
+      cpp = bk;
+      cpr1 = zn;
+      pw = !freeze_now;
+    } else if (mode == 2) {
+      listed = dact != 0;
+      pw = dupd != 0;
+      if (act) {
+        cxp = da + akj * db;
+        cxr = akj * dz;
+      } else {
+        cxp = da;
+      }
+      if (act && !freeze_now) {
+        cpp = bk * db;
+        cpr0 = bk * dz;
+        cpr1 = zn;
+      } else {
+        cpp = db;
+        cpr0 = dz;
+      }
+    }
+    const uint64_t mask = __ballot(listed);
+    if (listed) {
+      const int pos = __popcll(mask & ((uint64_t(1) << j) - 1));
+      pl.cx_p[pos] = cxp;
+      pl.cx_r[pos] = cxr;
+      pl.cp_p[pos] = cpp;
+      pl.cp_r0[pos] = cpr0;
+      pl.cp_r1[pos] = cpr1;
+      pl.xo[pos] = int64_t(origj) * a.n;
+      pl.po[pos] = int64_t(j - 1) * a.n;
+      pl.pw[pos] = pw ? 1 : 0;
+    }
+    const int nlist = __popcll(mask);
     if (j == 0) {
       pl.bn = bn;
-      pl.nact = __popcll(mask);
+      pl.nact = nlist;
+      pl.mode = mode;
       pl.pending = pending;
       pl.ok = ok ? 1 : 0;
-      pl.spmv = (ok && !done && !sw) ? 1 : 0;
+      pl.spmv = cont ? 1 : 0;
     }
     if (blockIdx.x == 0) {
       if (j < st->ns) {
         nx.zeta[j] = act ? zn : rs.zeta[j];
         nx.active[j] = act ? (freeze_now ? 0 : 1) : rs.active[j];
+        if (mode == 1 && j >= 1) {
+          st->d_a[j] = akj;
+          st->d_z[j] = zn;
+          st->d_b[j] = bk;
+          st->d_act[j] = act ? 1 : 0;
+          st->d_upd[j] = freeze_now ? 0 : 1;
+        }
       }
       if (act) {
         st->zeta_prev[j] = z;
@@ -443,6 +506,16 @@ __device__ void head_plan(const MsArgs& a, const Early& e, Plan& pl) {
       }
       if (j == 0) {
         nx.pending = 0;
+        nx.defer = (ok && mode == 1) ? 1 : 0;
+        if (a.sample >= 0 && a.sample < kMaxSamples) {
+          st->smp_mode[a.sample] = mode;
+          st->smp_nact[a.sample] = nlist;
+        }
+        if (pending && ok) {
+          st->n_shift_upd[ph] += nlist;
+          st->n_defer[ph] += mode == 1 ? 1 : 0;
+          st->n_two[ph] += mode == 2 ? 1 : 0;
+        }
         if (!ok) {
           nx.R = R;
           nx.iter = rs.iter;
@@ -487,26 +560,32 @@ __device__ void carry_state(const MsArgs& a) {
     nx.status = rs.status;
     nx.pending = rs.pending;
     nx.pcur = rs.pcur;
+    nx.defer = rs.defer;
   }
 }
 
-// The pending update of row i: x_0 += a p, x_j += a_j p_j for the listed shifts, p_j <-
-// zeta_j^(n+1) r + b_j p_j (unless j freezes now), and the new direction r + b p, which
-// is stored in the other direction buffer and returned.  rr, pp, x0v: the row's r, p
-// and x_0 (already loaded).
+// The pending update of row i: x_0 += a p and the listed shifts' x_j and p_j as the plan
+// says (one step, or two when a deferred step is folded in, reading the kept r0; a
+// deferring head keeps r in r0 instead), then the new direction r + b p, which is stored
+// in the other direction buffer and returned.  rr, pp, x0v: the row's r, p and x_0
+// (already loaded).
 template <class R>
 __device__ __forceinline__ cplx<R> update_row(const MsArgs& a, const Plan& pl, double step,
                                               int64_t i, const cplx<R>& rr, const cplx<R>& pp,
                                               double2 x0v, double2* __restrict__ x0,
                                               cplx<R>* __restrict__ pnew) {
   cplx<R>* __restrict__ pk = static_cast<cplx<R>*>(a.pk);
+  cplx<R>* __restrict__ rprev = static_cast<cplx<R>*>(a.rprev);
   double2* __restrict__ x = a.x;
   const double2 rd = to_d(rr), pd = to_d(pp);
   x0v.x = fma(step, pd.x, x0v.x);
   x0v.y = fma(step, pd.y, x0v.y);
   x0[i] = x0v;
+  if (pl.mode == 1) rprev[i] = rr;
+  const double2 r0d = pl.mode == 2 ? to_d(rprev[i]) : double2{0.0, 0.0};
   // shifts in groups of MSC_UPD_GROUP: a group's loads are all issued before its first
-  // store; a last, partial group is masked
+  // store; a last, partial group is masked.  With cx_r = cp_r0 = 0 (one step) the fused
+  // multiply-adds round exactly as x += a p and p <- zeta r + b p.
   const int nact = pl.nact;
   auto group = [&](int q, int m, auto full) {
     cplx<R> pj[kUpdGroup];
@@ -522,15 +601,15 @@ __device__ __forceinline__ cplx<R> update_row(const MsArgs& a, const Plan& pl, d
     for (int u = 0; u < kUpdGroup; ++u) {
       if (decltype(full)::value || u < m) {
         const double2 pjd = to_d(pj[u]);
-        const double aj = pl.ak[q + u];
-        xj[u].x = fma(aj, pjd.x, xj[u].x);
-        xj[u].y = fma(aj, pjd.y, xj[u].y);
+        const double cxp = pl.cx_p[q + u], cxr = pl.cx_r[q + u];
+        xj[u].x = fma(cxp, pjd.x, fma(cxr, r0d.x, xj[u].x));
+        xj[u].y = fma(cxp, pjd.y, fma(cxr, r0d.y, xj[u].y));
         x[pl.xo[q + u] + i] = xj[u];
-        if (pl.upd_p[q + u]) {
-          const double zj = pl.zk[q + u], bj = pl.bk[q + u];
+        if (pl.pw[q + u]) {
+          const double cpp = pl.cp_p[q + u], c0 = pl.cp_r0[q + u], c1 = pl.cp_r1[q + u];
           double2 np;
-          np.x = fma(zj, rd.x, bj * pjd.x);
-          np.y = fma(zj, rd.y, bj * pjd.y);
+          np.x = fma(c1, rd.x, fma(c0, r0d.x, cpp * pjd.x));
+          np.y = fma(c1, rd.y, fma(c0, r0d.y, cpp * pjd.y));
           pk[pl.po[q + u] + i] = from_d<R>(np);
         }
       }
@@ -570,7 +649,7 @@ __global__ __launch_bounds__(kBlock) void k_update(MsArgs a) {
   const double2 x_first = x0[ic];
   const double step = st->a;
   __shared__ Plan pl;
-  head_plan(a, e, pl);
+  head_plan<R>(a, e, pl);
   if (!pl.ok || !pl.pending) return;
   for (int64_t i = i0; i < end; i += kBlock) {
     const bool first = i == i0;
@@ -616,7 +695,7 @@ __global__ __launch_bounds__(kBlock) void k1_fused(MsArgs a) {
   const cplx<R> r_first = rv[rc], p_first = pv[rc];
   const double2 x_first = x0[rc];
   __shared__ Plan pl;
-  head_plan(a, e, pl);
+  head_plan<R>(a, e, pl);
   if (!pl.ok) return;
   const bool upd = pl.pending != 0;
   const double bn = pl.bn;

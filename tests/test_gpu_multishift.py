@@ -184,24 +184,49 @@ def test_iteration_limit(c0, cuda):
     op.close()
 
 
-@pytest.mark.parametrize("fmt", ["sell", "csr"])
-def test_iteration_limit_in_the_complex64_phase(c0, cuda, fmt):
+@pytest.mark.parametrize("fmt,limit", [("sell", 60), ("sell", 61), ("csr", 60), ("csr", 61)])
+def test_iteration_limit_in_the_complex64_phase(c0, cuda, fmt, limit):
     # the limit falls after the switch to complex64: the sequence stops there, and every
     # shift's residual is as small as the oracle's after as many iterations (up to the
-    # complex64 rounding of the unconverged iterates)
+    # complex64 rounding of the unconverged iterates); an even and an odd limit end a
+    # deferred all-shift update at either point of its two-step cycle
     op = _op(c0, cuda)
     op.set_shifts(c0["sigma"])
-    x, info = op.solve(c0["b"], max_iter=60, refine=False, prec="mixed", switch_tol=0.3,
+    x, info = op.solve(c0["b"], max_iter=limit, refine=False, prec="mixed", switch_tol=0.3,
                        format=fmt)
-    assert info["status"] == "notconv" and info["iters"] == 60
-    assert 0 < info["iters_fp64"] < 60
-    ref = O.cg_m(c0["apply"], c0["b"], c0["sigma"], tol=1e-10, max_iter=60)
+    assert info["status"] == "notconv" and info["iters"] == limit
+    assert 0 < info["iters_fp64"] < limit
+    ref = O.cg_m(c0["apply"], c0["b"], c0["sigma"], tol=1e-10, max_iter=limit)
     xg = x.cpu().numpy()
     bn = np.linalg.norm(c0["b"])
     rho_g = np.array([np.linalg.norm(c0["b"] - c0["apply"](xg[k], s)) for k, s in enumerate(c0["sigma"])]) / bn
     rho_o = np.array([np.linalg.norm(c0["b"] - c0["apply"](ref["x"][k], s)) for k, s in enumerate(c0["sigma"])]) / bn
     assert np.all(rho_g <= 2.0 * rho_o + 1e-6), (rho_g, rho_o)
     assert np.all(rho_o <= 2.0 * rho_g + 1e-6), (rho_g, rho_o)
+    op.close()
+
+
+@pytest.mark.parametrize("fmt", ["sell", "csr"])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_two_step_update_matches_one_step(c0, cuda, fmt, prec):
+    # deferring every other all-shift update and applying two steps in one pass follows
+    # the same recurrences: the driving sequence, the iteration count and every freeze are
+    # identical; the shifted solutions agree to rounding (FP64) or to the complex64
+    # rounding of the shift directions (mixed), and the byte count drops
+    op = _op(c0, cuda)
+    op.set_shifts(c0["sigma"])
+    x1, i1 = op.solve(c0["b"], tol=1e-10, prec=prec, format=fmt, two_step=False)
+    x2, i2 = op.solve(c0["b"], tol=1e-10, prec=prec, format=fmt, two_step=True)
+    assert i1["status"] == "ok" and i2["status"] == "ok"
+    assert i1["iters"] == i2["iters"] and i1["iters_fp64"] == i2["iters_fp64"]
+    assert np.array_equal(i1["freeze_iter"], i2["freeze_iter"])
+    if prec == "fp64":
+        k0 = int(np.argmin(c0["sigma"]))
+        assert bool((x1[k0] == x2[k0]).all())  # the driving shift's x does not defer
+    bar = 1e-11 if prec == "fp64" else 1e-6
+    assert np.all(_rel(x2.cpu().numpy(), x1.cpu().numpy()) <= bar)
+    assert np.all(i2["true_rel_res"] <= 1e-10)
+    assert i2["alg_bytes"] < i1["alg_bytes"]
     op.close()
 
 
