@@ -84,8 +84,9 @@ typedef struct {
     int32_t refine_max_iter; /* iteration limit of each refinement system          (10000) */
     int32_t lanes;           /* lanes per CSR row, 0 = automatic                    (0)    */
     int32_t verify;          /* compute FP64 true residuals at the end              (1)    */
-    int32_t timing;          /* time the iteration kernels with HIP events on every
-                                timing-th iteration, 0 = off                        (0)    */
+    int32_t timing;          /* time the iteration kernels with HIP events on the first
+                                two of every timing iterations (complex64 phase only
+                                in a mixed solve; at most 256 samples), 0 = off    (0)    */
     int32_t max_grid;        /* cap on workgroups per iteration kernel (<= 2048),
                                 0 = automatic                                       (0)    */
     int32_t format;          /* msc_format: matrix copy the iteration SpMVs read     (0)    */

@@ -2,19 +2,26 @@
 //
 //   K1  t = M p                and  P = |t|^2 + sigma0 |p|^2   (A = M^H M)
 //       t = A p                and  P = Re(p^H t) + sigma0 |p|^2 (A given)
-//       last workgroup: a = R/P and, per shift, zeta^(n+1) and a_j (one lane per shift)
-//   K2  r <- r - a (M^H t + sigma0 p)  and  R' = |r|^2
-//       last workgroup: b = R'/R, b_j, rotation of zeta, freezing, halting
-//   K3  x_0 += a p;  for every active shift j: x_j += a_j p_j, p_j <- zeta_j r + b_j p_j;
-//       p <- r + b p  -- one pass over r and p serves all shifts (Section 3: the
-//       shifted updates are the next most expensive step; register reuse of r and p).
+//   K2  a = R/P and, per shift, zeta^(n+1) and a_j (one lane per shift);
+//       r <- r - a (M^H t + sigma0 p)  and  R' = |r|^2
+//   K3  b = R'/R, b_j, rotation of zeta, freezing, halting;  x_0 += a p;  for every
+//       active shift j: x_j += a_j p_j, p_j <- zeta_j r + b_j p_j;  p <- r + b p  -- one
+//       pass over r and p serves all shifts (Section 3: the shifted updates are the next
+//       most expensive step; register reuse of r and p).
+//
+// On the sliced ELLPACK path an iteration is two kernels: the head (K3 of the previous
+// iteration, then K1 on the new direction, formed at each gathered column) and K2.
+// Every other head may defer the shifted part of K3; the next one applies both steps in
+// one pass over x_j and p_j.
 //
 // The shift recurrences are the values forced by the collinearity r_j = zeta_j r:
 //   zeta' = zeta zeta_prev a_prev / (a b (zeta_prev - zeta) + zeta_prev a_prev (1 + s a)),
 //   a_j = a zeta'/zeta,  b_j = b' (zeta'/zeta)^2,  with s = sigma_j - sigma0 >= 0.
 // All scalar work stays on the device in FP64 (Section 3: the iteration constants are
 // computed on the GPU to avoid host round trips).  Reductions are deterministic: each
-// workgroup writes one partial, the last one to arrive sums them in a fixed order.
+// workgroup writes one partial, and every workgroup of the consuming kernel sums them in
+// one fixed order (set-up, reliable update and verification: the last workgroup to
+// arrive does).
 #include <hip/hip_ext.h>
 
 #include <type_traits>
