@@ -107,7 +107,10 @@ __device__ void ik2_finish(const BssArgs& a) {
     if (qq == 0) {
       st->iter += 1;
       st->nact = __popcll(am);
-      if (st->nact == 0 || st->iter >= st->max_iter) st->halt = 1;
+      if (st->nact == 0 || st->iter >= st->max_iter) {
+        st->halt = 1;
+        store_host_flag(a.hflag, 1);
+      }
       st->k3_enable = 1;
     }
   }

@@ -95,7 +95,9 @@ msc_status ensure_workspace(msc_op op, int prec, int ns) {
     HIP_TRY(dalloc(&w.u64, n * 8));
     HIP_TRY(hipMalloc(&w.rprev, sizeof(double2) * n));
     HIP_TRY(dalloc(&w.st, 1));
-    HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&w.h_halt), 4 * sizeof(int), hipHostMallocDefault));
+    HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&w.h_halt), 4 * sizeof(int),
+                          hipHostMallocMapped | hipHostMallocCoherent));
+    HIP_TRY(hipHostGetDevicePointer(reinterpret_cast<void**>(&w.d_halt), w.h_halt, 0));
     HIP_TRY(hipEventCreateWithFlags(&w.ev[0], hipEventDisableTiming));
     HIP_TRY(hipEventCreateWithFlags(&w.ev[1], hipEventDisableTiming));
     w.n = n;
@@ -175,6 +177,7 @@ MsArgs make_args(msc_op op, int lanes, const double* d_b, double* d_x) {
   a.t = op->ws.t;
   a.pk = op->ws.pk;
   a.rprev = op->ws.rprev;  // complex64 use in the second phase of a mixed solve
+  a.hflag = op->ws.d_halt;
   a.defer_ok = 0;
   a.sample = -1;
   a.t64 = op->ws.t64;
@@ -305,6 +308,7 @@ msc_status run_multishift(msc_op op, const double* d_b, double* d_x, const msc_p
     h.orig[j] = order[j];
   }
   HIP_TRY(hipMemcpyAsync(op->ws.st, &h, sizeof h, hipMemcpyHostToDevice, s));
+  __atomic_store_n(op->ws.h_halt, 0, __ATOMIC_RELEASE);  // no kernel of this op is in flight
   a64.par = a32.par = 0;
   HIP_TRY(launch_init(MSC_PREC_FP64, a64, s));
 
@@ -345,17 +349,18 @@ msc_status run_multishift(msc_op op, const double* d_b, double* d_x, const msc_p
       ++launched;
     }
     const int slot = chunk & 1;
-    // halt and switch_req of the state the next iteration would start from
-    HIP_TRY(hipMemcpyAsync(&op->ws.h_halt[2 * slot], &op->ws.st->rot[launched & 1].halt,
-                           2 * sizeof(int), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipEventRecord(op->ws.ev[slot], s));
     ++chunk;
     if (chunk >= 2) {
       HIP_TRY(hipEventSynchronize(op->ws.ev[slot ^ 1]));
-      if (op->ws.h_halt[2 * (slot ^ 1)]) {
-        if (op->ws.h_halt[2 * (slot ^ 1) + 1] && phase == MSC_PREC_FP64 && mixed) {
+      // halt | switch_req << 1 of the newest state a head has written: at least as recent
+      // as the end of that chunk (within a phase the halt only ever gets set)
+      const int f = __atomic_load_n(op->ws.h_halt, __ATOMIC_ACQUIRE);
+      if (f & 1) {
+        if ((f & 2) && phase == MSC_PREC_FP64 && mixed) {
           // end of the FP64 phase: drain, convert the Krylov vectors, continue in complex64
           HIP_TRY(hipStreamSynchronize(s));
+          __atomic_store_n(op->ws.h_halt, 0, __ATOMIC_RELEASE);
           HIP_TRY(hipMemcpy(&iter_at_switch, &op->ws.st->rot[launched & 1].iter, sizeof(int),
                             hipMemcpyDeviceToHost));
           a64.par = a32.par = launched & 1;
@@ -473,7 +478,9 @@ msc_status ensure_bss(msc_op op, int prec, int mp) {
     HIP_TRY(hipMemset(*q, 0, bytes));
   }
   HIP_TRY(dalloc(&w.st, 1));
-  HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&w.h_halt), 2 * sizeof(int), hipHostMallocDefault));
+  HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&w.h_halt), 2 * sizeof(int),
+                        hipHostMallocMapped | hipHostMallocCoherent));
+  HIP_TRY(hipHostGetDevicePointer(reinterpret_cast<void**>(&w.d_halt), w.h_halt, 0));
   HIP_TRY(hipEventCreateWithFlags(&w.ev[0], hipEventDisableTiming));
   HIP_TRY(hipEventCreateWithFlags(&w.ev[1], hipEventDisableTiming));
   w.n = n;
@@ -585,6 +592,7 @@ msc_status run_batched_cg(msc_op op, int prec, int m, const double* sig, const d
   a.st = op->bws.st;
   a.partial = op->scratch.partial;
   a.tickets = op->scratch.tickets;
+  a.hflag = op->bws.d_halt;
   XPtrs xp{};
   for (int j = 0; j < m; ++j) xp.x[j] = x[j];
 
@@ -618,6 +626,7 @@ msc_status run_batched_cg(msc_op op, int prec, int m, const double* sig, const d
     for (int j = 0; j < m; ++j) res_abs[j] = std::sqrt(res2[j]);
     if (all_done || cycle >= max_cycles || *breakdown) break;
     HIP_TRY(hipMemcpyAsync(op->bws.st, &h, sizeof h, hipMemcpyHostToDevice, s));
+    __atomic_store_n(op->bws.h_halt, 0, __ATOMIC_RELEASE);  // the previous cycle has drained
     // chunks of 2, 4, 8, ... iterations up to poll_every: a correction solve often needs
     // only a few iterations, and the halt flag of a chunk is read after the next one is
     // queued
@@ -631,12 +640,11 @@ msc_status run_batched_cg(msc_op op, int prec, int m, const double* sig, const d
         ++launched;
       }
       const int slot = chunk & 1;
-      HIP_TRY(hipMemcpyAsync(&op->bws.h_halt[slot], &op->bws.st->halt, sizeof(int),
-                             hipMemcpyDeviceToHost, s));
       HIP_TRY(hipEventRecord(op->bws.ev[slot], s));
       if (chunk >= 1) {
         HIP_TRY(hipEventSynchronize(op->bws.ev[slot ^ 1]));
-        if (op->bws.h_halt[slot ^ 1]) done = true;
+        // set by the last IK2 once every system is done (it only ever gets set)
+        if (__atomic_load_n(op->bws.h_halt, __ATOMIC_ACQUIRE)) done = true;
       }
       if (launched >= prm.refine_max_iter + 2 * G) done = true;
       ++chunk;

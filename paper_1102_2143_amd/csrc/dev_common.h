@@ -103,6 +103,12 @@ __device__ __forceinline__ double load_agent(const double* p) {
   return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// A word in host-coherent memory that the host polls after an event: one vector store at
+// system scope (no cache maintenance; the host reads it once the kernel has completed).
+__device__ __forceinline__ void store_host_flag(int* p, int v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 // Every workgroup calls this once, after thread 0 stored its partial(s) with
 // store_agent.  Returns true (in all threads) in the workgroup that arrives last; that
 // workgroup then sees every partial through load_agent.  The ticket is reset by the

@@ -155,7 +155,8 @@ struct Workspace {
                             // head that defers its all-shift update
   double2* u64 = nullptr;   // 8 * n complex128 (verification SpMM chunk)
   SolveState* st = nullptr;
-  int* h_halt = nullptr;    // pinned host mirrors of st->halt, double buffered
+  int* h_halt = nullptr;    // host-coherent word the heads write: halt | switch_req << 1
+  int* d_halt = nullptr;    // its device address
   hipEvent_t ev[2] = {nullptr, nullptr};
 };
 
@@ -171,7 +172,8 @@ struct BssWorkspace {
   void* r = nullptr;
   void* e = nullptr;
   BssState* st = nullptr;
-  int* h_halt = nullptr;
+  int* h_halt = nullptr;    // host-coherent copy of st->halt, written by the last IK2
+  int* d_halt = nullptr;    // its device address
   hipEvent_t ev[2] = {nullptr, nullptr};
 };
 
@@ -245,6 +247,7 @@ struct MsArgs {
   void* r; void* t; void* pk;
   void* pb[2];           // the two direction buffers (p of consecutive iterations)
   void* rprev;           // r kept by a head that defers its all-shift update
+  int* hflag;            // host-coherent word: halt | switch_req << 1 of the next state
   int defer_ok;          // 1: this launch's head may defer its all-shift update
   int sample;            // slot of SolveState::smp_* for this head, -1: not sampled
   double2* t64;
@@ -301,6 +304,7 @@ struct BssArgs {
   BssState* st;
   double* partial;                      // kMaxGrid * kBssMax
   unsigned* tickets;
+  int* hflag;                           // host-coherent copy of st->halt
 };
 
 struct XPtrs {

@@ -530,6 +530,7 @@ __device__ void head_plan(const MsArgs& a, const Early& e, Plan& pl) {
           nx.switch_req = 0;
           nx.status = 1;
           nx.pcur = rs.pcur;
+          store_host_flag(a.hflag, 1);
         } else {
           nx.R = Rn;
           nx.iter = it;
@@ -537,6 +538,7 @@ __device__ void head_plan(const MsArgs& a, const Early& e, Plan& pl) {
           nx.halt = (done || sw) ? 1 : 0;
           nx.switch_req = sw ? 1 : 0;
           nx.pcur = pending ? rs.pcur ^ 1 : rs.pcur;
+          store_host_flag(a.hflag, ((done || sw) ? 1 : 0) | (sw ? 2 : 0));
           if (pending) {
             st->b = bn;
             st->a_prev = st->a;
@@ -568,6 +570,7 @@ __device__ void carry_state(const MsArgs& a) {
     nx.pending = rs.pending;
     nx.pcur = rs.pcur;
     nx.defer = rs.defer;
+    store_host_flag(a.hflag, 1 | (rs.switch_req ? 2 : 0));
   }
 }
 
@@ -993,8 +996,10 @@ __device__ void ru_finish(const MsArgs& a, double acc) {
     if (!isfinite(Rt)) {
       rs.status = 1;
       rs.halt = 1;
+      store_host_flag(a.hflag, 1);
     } else if (Rt <= st->eps2) {
       rs.halt = 1;
+      store_host_flag(a.hflag, 1);
     }
   }
 }
