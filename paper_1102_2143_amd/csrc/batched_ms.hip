@@ -189,7 +189,8 @@ __device__ void bk1_chunk(const BatchSys& S, BatchState* st, const int4& ch) {
 
 // ---- BK2: r <- r - a (A2 t + s0 p), R' = |r|^2; recurrences, freezing, halting ------------
 template <class R, int L, int RR>
-__device__ void bk2_chunk(const BatchSys& S, BatchState* st, const int4& ch, int* active_systems) {
+__device__ void bk2_chunk(const BatchSys& S, BatchState* st, const int4& ch, int* active_systems,
+                          int defer_ok) {
   const cplx<R>* __restrict__ t = vec_t<R>(S);
   const cplx<R>* __restrict__ p = vec_p<R>(S);
   cplx<R>* __restrict__ r = vec_r<R>(S);
@@ -257,12 +258,21 @@ __device__ void bk2_chunk(const BatchSys& S, BatchState* st, const int4& ch, int
   const int phase32 = st->phase32;
   const bool act = live && k >= 1 && k < ns && st->active[lk];
   const double z = act ? st->zeta[lk] : 1.0, zn = act ? st->zk[lk] : 1.0;
+  const double akq = act ? st->ak[lk] : 0.0;
+  // a step this rhs deferred in the previous BK3 (read before any lane writes the state)
+  const int twoq = q < nrhs ? st->two[q] : 0;
+  const bool dact = twoq && k >= 1 && k < ns && st->d_act[lk];
+  const bool dupd = dact && st->d_upd[lk];
+  const double da = dact ? st->d_a[lk] : 0.0, dz = dact ? st->d_z[lk] : 0.0;
+  const double db = dact ? st->d_b[lk] : 0.0;
   const double Rn = live ? tot[q] : 0.0;
   const double bn = Rn / Rq;
   bool keep_p = false;
+  double bkq = 0.0;
   if (act) {
     const double ratio = zn / z;
-    st->bk[lk] = bn * ratio * ratio;
+    bkq = bn * ratio * ratio;
+    st->bk[lk] = bkq;
     st->zeta_prev[lk] = z;
     st->zeta[lk] = zn;
     keep_p = true;
@@ -272,9 +282,8 @@ __device__ void bk2_chunk(const BatchSys& S, BatchState* st, const int4& ch, int
       keep_p = false;
     }
   }
-  st->upd_p[lk] = keep_p ? 1 : 0;
-  st->upd_x[lk] = act ? 1 : 0;
   // per right-hand side (lanes k == 0)
+  const bool halt_q = live && (!isfinite(Rn) || Rn <= eps2q || itq + 1 >= max_iter);
   bool halted_after = true, below = true;
   if (k == 0 && q < nrhs) {
     st->x0_upd[q] = live ? 1 : 0;
@@ -297,12 +306,66 @@ __device__ void bk2_chunk(const BatchSys& S, BatchState* st, const int4& ch, int
   }
   const bool all_halted = __ballot(!halted_after) == 0;
   const bool all_below = __ballot(!halted_after && !below) == 0;
+  const bool switching = !all_halted && !phase32 && all_below;
+  // BK3's mode for this rhs: apply a deferred step with this one (2), defer this one when
+  // the rhs continues and the vectors keep their precision (1), or one step (0)
+  const int mode = twoq ? 2 : ((live && !halt_q && !switching && defer_ok) ? 1 : 0);
+  bool listed = false, pw = false;
+  double cxp = 0.0, cxr = 0.0, cpp = 0.0, cpr0 = 0.0, cpr1 = 0.0;
+  if (mode == 0) {
+    listed = act;
+    pw = keep_p;
+    cxp = akq;
+    cpp = bkq;
+    cpr1 = zn;
+  } else if (mode == 2) {
+    listed = dact;
+    pw = dupd;
+    if (act) {
+      cxp = da + akq * db;
+      cxr = akq * dz;
+    } else {
+      cxp = da;
+    }
+    if (act && keep_p) {
+      cpp = bkq * db;
+      cpr0 = bkq * dz;
+      cpr1 = zn;
+    } else {
+      cpp = db;
+      cpr0 = dz;
+    }
+  }
+  st->upd_x[lk] = listed ? 1 : 0;
+  st->upd_p[lk] = pw ? 1 : 0;
+  st->cxp[lk] = cxp;
+  st->cxr[lk] = cxr;
+  st->cpp[lk] = cpp;
+  st->cpr0[lk] = cpr0;
+  st->cpr1[lk] = cpr1;
+  if (mode == 1) {
+    st->d_a[lk] = akq;
+    st->d_z[lk] = zn;
+    st->d_b[lk] = bkq;
+    st->d_act[lk] = act ? 1 : 0;
+    st->d_upd[lk] = keep_p ? 1 : 0;
+  }
+  const uint64_t lm = __ballot(listed);
+  if (k == 0 && q < nrhs) {
+    st->mode[q] = mode;
+    st->two[q] = mode == 1 ? 1 : 0;
+    if (live) {
+      const int ph = phase32 ? 1 : 0;
+      st->n_upd[q][ph] += __popcll((lm >> (q * kBatchMaxShifts)) & 0xffffull);
+      st->n_kept[q][ph] += mode != 0 ? 1 : 0;
+    }
+  }
   if (lk == 0) {
     st->k3_enable = 1;
     if (all_halted) {
       st->done = 1;
       atomicSub(active_systems, 1);
-    } else if (!phase32 && all_below) {
+    } else if (switching) {
       st->switch_pending = 1;
       st->iters_fp64 = itq + 1;
     }
@@ -313,11 +376,11 @@ __device__ void bk2_chunk(const BatchSys& S, BatchState* st, const int4& ch, int
 // The update's per-(rhs, shift) coefficients, staged in LDS once per chunk so the loop
 // over shifts issues its vector loads without first waiting on the scalar state.
 struct K3Coef {
-  double ak[kQK], zk[kQK], bk[kQK];
+  double cxp[kQK], cxr[kQK], cpp[kQK], cpr0[kQK], cpr1[kQK];
   int upd_x[kQK], upd_p[kQK];
   int orig[kBatchMaxShifts];
   double a[kBatchMaxRhs], bnew[kBatchMaxRhs];
-  int x0_upd[kBatchMaxRhs];
+  int x0_upd[kBatchMaxRhs], mode[kBatchMaxRhs];
   int nrhs, ns;
 };
 
@@ -327,9 +390,11 @@ __device__ void bk3_chunk(const BatchSys& S, const BatchState* st, const int4& c
   const int tid = threadIdx.x;
   __syncthreads();  // the previous chunk of this workgroup is done with cf
   if (tid < kQK) {
-    cf.ak[tid] = st->ak[tid];
-    cf.zk[tid] = st->zk[tid];
-    cf.bk[tid] = st->bk[tid];
+    cf.cxp[tid] = st->cxp[tid];
+    cf.cxr[tid] = st->cxr[tid];
+    cf.cpp[tid] = st->cpp[tid];
+    cf.cpr0[tid] = st->cpr0[tid];
+    cf.cpr1[tid] = st->cpr1[tid];
     cf.upd_x[tid] = st->upd_x[tid];
     cf.upd_p[tid] = st->upd_p[tid];
   }
@@ -338,6 +403,7 @@ __device__ void bk3_chunk(const BatchSys& S, const BatchState* st, const int4& c
     cf.a[tid] = st->a[tid];
     cf.bnew[tid] = st->b_new[tid];
     cf.x0_upd[tid] = st->x0_upd[tid];
+    cf.mode[tid] = st->mode[tid];
   }
   if (tid == 0) {
     cf.nrhs = st->nrhs;
@@ -351,6 +417,7 @@ __device__ void bk3_chunk(const BatchSys& S, const BatchState* st, const int4& c
   cplx<W>* __restrict__ pw = vec_p<W>(S);
   cplx<W>* __restrict__ rw = vec_r<W>(S);
   cplx<W>* __restrict__ pkw = vec_pk<W>(S);
+  cplx<R>* __restrict__ rkeep = static_cast<cplx<R>*>(S.rkeep);
   const int64_t n = S.n;
   const int ns = cf.ns;
   const int64_t rows = ch.z - ch.y;
@@ -367,6 +434,11 @@ __device__ void bk3_chunk(const BatchSys& S, const BatchState* st, const int4& c
       xv.x = fma(a, pd.x, xv.x);
       xv.y = fma(a, pd.y, xv.y);
       *x0 = xv;
+      // a deferring BK3 keeps r for the next one, which folds both steps (with
+      // cxr = cpr0 = 0 the multiply-adds round exactly as one step)
+      const int mode = cf.mode[q];
+      if (mode == 1) rkeep[idx] = r[idx];
+      const double2 r0 = mode == 2 ? to_d(rkeep[idx]) : double2{0.0, 0.0};
       constexpr bool same = std::is_same<R, W>::value;
       // two shifts at a time, their loads issued before either store (x_k and p_k of
       // different shifts share one array each, so the compiler cannot reorder); frozen
@@ -390,14 +462,15 @@ __device__ void bk3_chunk(const BatchSys& S, const BatchState* st, const int4& c
           const int lk = q * kBatchMaxShifts + k;
           const int64_t pidx = int64_t(k - 1) * n * RR + idx;
           if (ux[u]) {
-            const double aj = cf.ak[lk];
-            xk[u].x = fma(aj, pj[u].x, xk[u].x);
-            xk[u].y = fma(aj, pj[u].y, xk[u].y);
+            const double cx = cf.cxp[lk], cr = cf.cxr[lk];
+            xk[u].x = fma(cx, pj[u].x, fma(cr, r0.x, xk[u].x));
+            xk[u].y = fma(cx, pj[u].y, fma(cr, r0.y, xk[u].y));
             S.x[(int64_t(q) * ns + cf.orig[k]) * n + i] = xk[u];
           }
           if (cf.upd_p[lk]) {
-            const double zj = cf.zk[lk], bj = cf.bk[lk];
-            pkw[pidx] = from_d<W>(double2{fma(zj, rd.x, bj * pj[u].x), fma(zj, rd.y, bj * pj[u].y)});
+            const double cp = cf.cpp[lk], c0 = cf.cpr0[lk], c1 = cf.cpr1[lk];
+            pkw[pidx] = from_d<W>(double2{fma(c1, rd.x, fma(c0, r0.x, cp * pj[u].x)),
+                                          fma(c1, rd.y, fma(c0, r0.y, cp * pj[u].y))});
           } else if (!same) {
             pkw[pidx] = from_d<W>(pj[u]);
           }
@@ -557,9 +630,9 @@ __global__ __launch_bounds__(kBlock) void bk2(BatchArgs a) {
     BatchState* st = S.st;
     if (st->done) continue;
     if (st->phase32)
-      bk2_chunk<float, L, RR>(S, st, ch, a.active_systems);
+      bk2_chunk<float, L, RR>(S, st, ch, a.active_systems, a.defer_ok);
     else
-      bk2_chunk<double, L, RR>(S, st, ch, a.active_systems);
+      bk2_chunk<double, L, RR>(S, st, ch, a.active_systems, a.defer_ok);
   }
 }
 

@@ -797,7 +797,7 @@ struct BatchRun {
       const size_t n = size_t(ops[s]->n), nk = std::max<size_t>(ops[s]->sigma.size() - 1, 1);
       const size_t nch = (n + kBatchChunkRows - 1) / kBatchChunkRows;
       off[s] = bytes;
-      bytes += 4 * align(sizeof(double2) * n * rr) + align(sizeof(double2) * n * rr * nk) +
+      bytes += 5 * align(sizeof(double2) * n * rr) + align(sizeof(double2) * n * rr * nk) +
                3 * align(sizeof(float2) * n * rr) + align(sizeof(float2) * n * rr * nk) +
                align(sizeof(double) * nch * kBatchMaxRhs);
       for (size_t c = 0; c < nch; ++c) {
@@ -864,6 +864,7 @@ struct BatchRun {
       S.p64 = reinterpret_cast<double2*>(take(sizeof(double2) * n * rr));
       S.t64 = reinterpret_cast<double2*>(take(sizeof(double2) * n * rr));
       S.u64 = reinterpret_cast<double2*>(take(sizeof(double2) * n * rr));
+      S.rkeep = take(sizeof(double2) * n * rr);
       S.pk64 = reinterpret_cast<double2*>(take(sizeof(double2) * n * rr * nk));
       S.r32 = reinterpret_cast<float2*>(take(sizeof(float2) * n * rr));
       S.p32 = reinterpret_cast<float2*>(take(sizeof(float2) * n * rr));
@@ -1016,7 +1017,11 @@ struct BatchRun {
     const int G = std::max(1, prm.poll_every);
     HIP_TRY(hipStreamBeginCapture(sint, hipStreamCaptureModeThreadLocal));
     for (int g = 0; g < G; ++g) {
-      hipError_t e = launch_batch_iteration(args(), sint);
+      // BK3 may defer its shifted update except in the graph's last iteration (a reliable
+      // update or the end of the solve may follow it)
+      BatchArgs ga = args();
+      ga.defer_ok = (prm.two_step && g < G - 1) ? 1 : 0;
+      hipError_t e = launch_batch_iteration(ga, sint);
       if (e != hipSuccess) {
         hipGraph_t tmp = nullptr;
         (void)hipStreamEndCapture(sint, &tmp);
@@ -1157,21 +1162,18 @@ struct BatchRun {
             }
           for (double& v : I.kernel_ms) v = 0.0;
           I.kernel_samples = 0;
-          // algorithmic bytes: this system's share, matrix read once for all its rhs
-          double act64 = 0.0, act32 = 0.0;
+          // algorithmic bytes: this system's share, matrix read once for all its rhs; the
+          // shift-vector updates and kept-r passes as counted by BK2 per phase
           const int it = h.iter[q], i64 = std::min(I.iters_fp64, it);
-          for (int k = 1; k < ns; ++k) {
-            const int fi = h.freeze_iter[q * kBatchMaxShifts + k];
-            const int last = fi >= 0 ? fi : it;
-            act64 += std::min(last, i64);
-            act32 += std::max(0, last - i64);
-          }
+          const double act64 = h.n_upd[q][0], act32 = h.n_upd[q][1];
+          const double kept64 = h.n_kept[q][0], kept32 = h.n_kept[q][1];
           const double nn = double(n), nz = double(op->nnz), nzh = double(op->nnz_h);
           const double ib = index_bytes(sys[s].sell, sys[s].s64);
           const double ibh = index_bytes(sys[s].sell, sys[s].sh64);
-          I.alg_bytes = iter_bytes(op->kind, MSC_PREC_FP64, nn, nz, nzh, act64, i64, ib, ibh, 0.0) +
+          I.alg_bytes = iter_bytes(op->kind, MSC_PREC_FP64, nn, nz, nzh, act64, i64, ib, ibh,
+                                   kept64) +
                         iter_bytes(op->kind, MSC_PREC_MIXED, nn, nz, nzh, act32, it - i64, ib, ibh,
-                                   0.0) -
+                                   kept32) -
                         (double(nrhs[s]) - 1.0) / double(nrhs[s]) *
                             ((nz * (16.0 + ib) + nzh * (16.0 + ibh)) * i64 +
                              (nz * (8.0 + ib) + nzh * (8.0 + ibh)) * (it - i64));

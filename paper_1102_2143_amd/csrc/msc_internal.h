@@ -350,6 +350,19 @@ struct BatchState {
   double bk[kBatchMaxRhs * kBatchMaxShifts];
   int active[kBatchMaxRhs * kBatchMaxShifts], freeze_iter[kBatchMaxRhs * kBatchMaxShifts];
   int upd_p[kBatchMaxRhs * kBatchMaxShifts], upd_x[kBatchMaxRhs * kBatchMaxShifts];
+  // BK3's update of (q, k): x += cxp p_k + cxr r0 (upd_x); p_k <- cpp p_k + cpr0 r0 + cpr1 r
+  // (upd_p), r0 being the residual kept by a deferring BK3 (one step: cxr = cpr0 = 0)
+  double cxp[kBatchMaxRhs * kBatchMaxShifts], cxr[kBatchMaxRhs * kBatchMaxShifts];
+  double cpp[kBatchMaxRhs * kBatchMaxShifts], cpr0[kBatchMaxRhs * kBatchMaxShifts];
+  double cpr1[kBatchMaxRhs * kBatchMaxShifts];
+  // the step a deferring BK3 left to the next one: a_k, zeta_k', b_k, took part, updated p_k
+  double d_a[kBatchMaxRhs * kBatchMaxShifts], d_z[kBatchMaxRhs * kBatchMaxShifts];
+  double d_b[kBatchMaxRhs * kBatchMaxShifts];
+  int d_act[kBatchMaxRhs * kBatchMaxShifts], d_upd[kBatchMaxRhs * kBatchMaxShifts];
+  // per right-hand side: BK3's mode (0 one step, 1 deferred, 2 two steps), a deferred step
+  // pending, and per phase (FP64, complex64) the shift-vector updates and kept-r passes
+  int mode[kBatchMaxRhs], two[kBatchMaxRhs];
+  int n_upd[kBatchMaxRhs][2], n_kept[kBatchMaxRhs][2];
   // per system
   double s[kBatchMaxShifts];
   int orig[kBatchMaxShifts];
@@ -370,6 +383,8 @@ struct BatchSys {
   double2* x;             // nrhs * ns * n (rhs-major, shift-major, caller order)
   double2 *r64, *p64, *t64, *pk64, *u64;   // rhs-interleaved n x RR; pk: (ns-1) blocks
   float2 *r32, *p32, *t32, *pk32;
+  void* rkeep;            // n x RR: r kept by a deferring BK3 (complex128, or complex64 in
+                          // the second phase)
   BatchState* st;
   double* partial;
   unsigned* tickets;      // 8 counters
@@ -384,6 +399,7 @@ struct BatchArgs {
   int lanes;
   int rr;                 // right-hand sides per system, padded (1, 2 or 4)
   int* active_systems;
+  int defer_ok;           // 1: this iteration's BK3 may defer the shifted update
 };
 
 hipError_t launch_batch_init(const BatchArgs& a, hipStream_t s);

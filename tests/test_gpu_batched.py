@@ -91,6 +91,31 @@ def test_batch_result_is_independent_of_companions(cuda):
         op.close()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_batch_two_step_matches_one_step(cuda, prec):
+    # the batch defers every other shifted update and folds two steps into one pass: the
+    # driving sequences, iteration counts and freezes are those of one step per
+    # iteration, the solutions agree to rounding, and fewer bytes move
+    print(f"[gpu] batched two-step {prec}", flush=True)
+    from paper_1102_2143_amd import solve_batched
+    systems = _small_batch()
+    ops = _ops(systems, cuda)
+    bs = [p["b"] for p in systems]
+    x1, i1, s1 = solve_batched(ops, bs, tol=1e-10, prec=prec, two_step=False)
+    x2, i2, s2 = solve_batched(ops, bs, tol=1e-10, prec=prec, two_step=True)
+    assert s1 == "ok" and s2 == "ok"
+    for a, b in zip(i1, i2):
+        assert a["iters"] == b["iters"]
+        assert np.array_equal(a["freeze_iter"], b["freeze_iter"])
+        assert np.all(b["true_rel_res"] <= 1e-10)
+    bar = 1e-11 if prec == "fp64" else 1e-6
+    for a, b in zip(x1, x2):
+        assert np.all(_rel(b.cpu().numpy(), a.cpu().numpy()) <= bar)
+    assert sum(i["alg_bytes"] for i in i2) < sum(i["alg_bytes"] for i in i1)
+    for op in ops:
+        op.close()
+
+
 def test_batch_rejects_bad_input(cuda):
     from paper_1102_2143_amd import MscError, solve_batched
     systems = _small_batch()[:1]
