@@ -63,6 +63,52 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+# CG-M with 15 shifts on the 2-D Poisson 1000^2 matrix, ms per iteration on one Tesla T10
+# (the paper's Table 1), quoted beside the same workload here as context.
+PAPER_T10_MS_PER_ITER = {"fp64": 12.9839, "fp32": 8.82461}
+
+
+def paper_table1_line(args, dev):
+    """The paper's own benchmark workload (Table 1): the 2-D 5-point Poisson matrix on a
+    1000 x 1000 grid with 15 shifts, b = 1 as in its Fig. 1 example, ms per CG-M iteration.
+    The shifts are not given for Table 1; here they are 15 log-spaced in [1e-3, 1].  The
+    matrix is real but runs through the complex path (zero imaginary parts), so every
+    value moves twice the bytes of a real-valued solver."""
+    import torch
+    import workloads as W
+    from paper_1102_2143_amd import Operator
+
+    rowptr, col, vals = W.poisson5pt_csr(1000, 1000)
+    n = 1000 * 1000
+    op = Operator(rowptr, col, vals, n, kind="herm", device=dev)
+    sigma = W.logspace_shifts(1e-3, 1.0, 15)
+    op.set_shifts(sigma)
+    b = torch.ones(n, dtype=torch.complex128, device=dev)
+    x = torch.empty((15, n), dtype=torch.complex128, device=dev)
+    out = {"workload": "2-D Poisson 5-point 1000^2 (n = 10^6), 15 shifts log-spaced in "
+                       "[1e-3, 1], b = 1, tol 1e-5 (the paper's Table 1 workload)",
+           "paper_t10_ms_per_iter": PAPER_T10_MS_PER_ITER}
+    # fp64: FP64 throughout; complex64: the mixed path switched at the first iteration
+    # (switch_tol 1), against the paper's single-precision column
+    for name, kw in (("fp64", dict(prec="fp64")), ("complex64", dict(prec="mixed", switch_tol=1.0))):
+        kw = dict(tol=1e-5, max_iter=2000, verify=False, refine=False, **kw)
+        op.solve(b, out=x, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        iters = 0
+        for _ in range(max(1, args.steps)):
+            _, info = op.solve(b, out=x, **kw)
+            iters += info["iters"]
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / iters
+        ref = PAPER_T10_MS_PER_ITER["fp64" if name == "fp64" else "fp32"]
+        out[name] = {"ms_per_iter": round(ms, 4), "iters": info["iters"],
+                     "t10_over_mi355x": round(ref / ms, 1)}
+        log(f"paper workload {name}: {ms:.4f} ms per iteration ({info['iters']} iterations)")
+    op.close()
+    return out
+
+
 def batched_line(args, dev):
     """The 64-system batch (4 rhs x 10 shifts each) solved in one batched call, mixed and
     FP64: shifted-solves/s and effective GB/s (algorithmic bytes / wall time)."""
@@ -137,6 +183,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 64-system batched solve reported beside the main line")
+    ap.add_argument("--no-paper-workload", action="store_true",
+                    help="skip the paper's Table 1 workload (2-D Poisson) reported beside it")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="copy this many MiB once before timing (a kernel of known traffic "
                          "that calibrates FETCH_SIZE / WRITE_SIZE counters)")
@@ -271,6 +319,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "batched": None if args.no_batch else batched_line(args, dev),
+        "paper_table1": None if args.no_paper_workload else paper_table1_line(args, dev),
     }
     print(json.dumps(line), flush=True)
     op.close()

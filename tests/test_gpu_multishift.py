@@ -148,6 +148,28 @@ def test_herm_laplacian(cuda, fmt):
     op.close()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_paper_poisson_workload_small(cuda, prec):
+    # the matrix of the paper's benchmark (2-D 5-point Poisson, Dirichlet) at 30 x 24 with
+    # 15 shifts and b = 1 as in its Fig. 1 example, solved to 1e-10
+    print(f"[gpu] 2-D Poisson 30x24, 15 shifts, {prec}", flush=True)
+    rowptr, col, vals = W.poisson5pt_csr(30, 24)
+    n = 720
+    sigma = W.logspace_shifts(1e-3, 1.0, 15)
+    b = np.ones(n, dtype=np.complex128)
+    op = _op(dict(rowptr=rowptr, col=col, vals=vals, n=n, kind="herm"), cuda)
+    assert op.storage() == {"sell": True, "narrow": (True, False)}
+    op.set_shifts(sigma)
+    x, info = op.solve(b, tol=1e-10, prec=prec)
+    ref = O.cg_m(O.shifted_apply("herm", rowptr, col, vals, n), b, sigma, tol=1e-10)
+    assert info["status"] == "ok"
+    assert np.all(info["true_rel_res"] <= 1e-10)
+    if prec == "fp64":
+        assert abs(info["iters"] - ref["iters"]) <= 2
+    assert np.all(_rel(x.cpu().numpy(), ref["x"]) <= 1e-8)
+    op.close()
+
+
 @pytest.mark.parametrize("fmt", ["auto", "csr"])
 def test_non_normal_random_operator(cuda, fmt):
     rowptr, col, vals = W.random_sparse_csr(400, 9, 44, diag=5.0, empty_rows=(7,))

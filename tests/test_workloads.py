@@ -121,6 +121,26 @@ def test_laplacian7():
         assert np.all(np.diff(col[rowptr[i]:rowptr[i + 1]]) > 0)
 
 
+def test_poisson5pt_spectrum_and_structure():
+    # the 5-point Dirichlet Laplacian's eigenvalues are known in closed form:
+    # 4 - 2 cos(i pi / (nx+1)) - 2 cos(j pi / (ny+1)), i = 1..nx, j = 1..ny
+    nx, ny = 7, 5
+    rowptr, col, vals = W.poisson5pt_csr(nx, ny)
+    n = nx * ny
+    assert col.size == 5 * n - 2 * (nx + ny)
+    a = _csr(rowptr, col, vals, n).toarray()
+    assert np.all(a.imag == 0) and np.array_equal(a, a.T)
+    i = np.arange(1, nx + 1)[:, None]
+    j = np.arange(1, ny + 1)[None, :]
+    closed = np.sort((4 - 2 * np.cos(i * np.pi / (nx + 1)) - 2 * np.cos(j * np.pi / (ny + 1))).ravel())
+    assert np.allclose(np.linalg.eigvalsh(a.real), closed, rtol=0, atol=1e-12)
+    for r in range(n):
+        assert np.all(np.diff(col[rowptr[r]:rowptr[r + 1]]) > 0)
+    # the paper's size: 10^6 rows, 4,996,000 entries
+    rowptr, col, vals = W.poisson5pt_csr(1000, 1000)
+    assert rowptr[-1] == col.size == 5 * 10**6 - 4000
+
+
 def test_random_sparse_is_not_normal():
     rowptr, col, vals = W.random_sparse_csr(50, 4, 3, diag=3.0)
     m = _csr(rowptr, col, vals, 50).toarray()

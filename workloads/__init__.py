@@ -15,7 +15,8 @@ from .lattice import (
     pure_gauge_links,
     staggered_csr,
 )
-from .generic import laplacian7_csr, random_sparse_csr, gaussian_rhs, logspace_shifts
+from .generic import (laplacian7_csr, poisson5pt_csr, random_sparse_csr, gaussian_rhs,
+                      logspace_shifts)
 from .configs import CONFIGS, make_config, staggered_problem
 
 __all__ = [
@@ -29,6 +30,7 @@ __all__ = [
     "pure_gauge_links",
     "staggered_csr",
     "laplacian7_csr",
+    "poisson5pt_csr",
     "random_sparse_csr",
     "gaussian_rhs",
     "logspace_shifts",

@@ -57,6 +57,28 @@ def laplacian7_csr(dims, seed: int, diag_lo: float = 0.01, diag_hi: float = 1.0)
     return rowptr, cols[valid].astype(np.int32), np.ascontiguousarray(vals[valid])
 
 
+def poisson5pt_csr(nx: int, ny: int):
+    """2-D 5-point Poisson matrix on an nx x ny grid with Dirichlet boundaries: 4 on the
+    diagonal and -1 for each in-grid neighbour (the matrix of the paper's benchmark, a
+    1000 x 1000 grid there).  Sites are numbered ``s = x + nx*y``; columns sorted within a
+    row; stored as complex128 with zero imaginary part (real symmetric positive definite,
+    given to the solver directly as A)."""
+    nx, ny = int(nx), int(ny)
+    n = nx * ny
+    s = np.arange(n, dtype=np.int64)
+    x, y = s % nx, s // nx
+    # neighbours in column order: below (y-1), left (x-1), self, right (x+1), above (y+1)
+    cand = [(s - nx, y > 0, -1.0), (s - 1, x > 0, -1.0), (s, np.ones(n, bool), 4.0),
+            (s + 1, x < nx - 1, -1.0), (s + nx, y < ny - 1, -1.0)]
+    cols = np.stack([c for c, _, _ in cand], axis=1)
+    valid = np.stack([v for _, v, _ in cand], axis=1)
+    vals = np.broadcast_to(np.array([v for _, _, v in cand], dtype=np.complex128), cols.shape)
+    counts = valid.sum(axis=1)
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(counts, out=rowptr[1:])
+    return rowptr, cols[valid].astype(np.int32), np.ascontiguousarray(vals[valid])
+
+
 def random_sparse_csr(n: int, per_row: int, seed: int, diag: complex = 0.0, empty_rows=()):
     """Random complex sparse matrix with ``per_row`` distinct sorted columns per row.
 
