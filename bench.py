@@ -176,9 +176,9 @@ def main():
     ap.add_argument("--workload", default="c1", choices=sorted(WORKLOAD_NAMES))
     ap.add_argument("--prec", default="both", choices=["fp64", "mixed", "both"],
                     help="both: time the FP64 plain solve and the mixed solve (the headline)")
-    ap.add_argument("--timing", type=int, default=64,
-                    help="time the kernels of every k-th iteration with dispatch events "
-                         "(every 64th perturbs the solve time by < 0.5 %%; every 4th by ~7 %%)")
+    ap.add_argument("--timing", type=int, default=128,
+                    help="time the kernels of a run of consecutive iterations (one folding "
+                         "cycle of the shift update) out of every k with dispatch events")
     ap.add_argument("--cpu-sample-iters", type=int, default=60)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true",

@@ -85,18 +85,20 @@ typedef struct {
     int32_t lanes;           /* lanes per CSR row, 0 = automatic                    (0)    */
     int32_t verify;          /* compute FP64 true residuals at the end              (1)    */
     int32_t timing;          /* time the iteration kernels with HIP events on the first
-                                two of every timing iterations (complex64 phase only
-                                in a mixed solve; at most 256 samples), 0 = off    (0)    */
+                                max(2, update_steps) of every timing iterations
+                                (complex64 phase only in a mixed solve; at most 256
+                                samples), 0 = off                                  (0)    */
     int32_t max_grid;        /* cap on workgroups per iteration kernel (<= 2048),
                                 0 = automatic                                       (0)    */
     int32_t format;          /* msc_format: matrix copy the iteration SpMVs read     (0)    */
     double mixed_margin;     /* mixed: the sequence runs until its recursive residuals
                                 reach mixed_margin * tol (0 < margin <= 1), so that the
                                 complex64 drift leaves few shifts above tol     (0.7)  */
-    int32_t two_step;        /* 1: every other iteration defers its all-shift update and
-                                the next applies both steps in one pass over x_k and p_k
-                                (same recurrences, half the traffic of those vectors);
-                                0: one step per iteration                        (1)    */
+    int32_t update_steps;    /* 1..4: consecutive steps of the all-shift update folded
+                                into one pass over x_k and p_k (the heads between defer
+                                theirs); same recurrences, 1/update_steps of the traffic
+                                of those vectors. 1: one step per iteration. The batched
+                                solve folds at most 2                            (4)    */
     int32_t reserved;        /* must be 0                                        (0)    */
 } msc_params;
 

@@ -45,7 +45,7 @@ class Params(ctypes.Structure):
         ("max_grid", ctypes.c_int32),
         ("format", ctypes.c_int32),
         ("mixed_margin", ctypes.c_double),
-        ("two_step", ctypes.c_int32),
+        ("update_steps", ctypes.c_int32),
         ("reserved", ctypes.c_int32),
     ]
 

@@ -37,7 +37,7 @@ def _ptr(t: torch.Tensor):
 def make_params(tol=1e-10, prec="fp64", max_iter=10000, reliable_every=50, freeze=True,
                 refine=True, poll_every=16, switch_tol=None, refine_max_iter=10000, lanes=0,
                 verify=True, timing=0, max_grid=0, format="auto", mixed_margin=None,
-                two_step=True) -> L.Params:
+                update_steps=None) -> L.Params:
     lib = L.load()
     p = L.Params()
     lib.msc_params_default(ctypes.byref(p))
@@ -58,7 +58,8 @@ def make_params(tol=1e-10, prec="fp64", max_iter=10000, reliable_every=50, freez
     p.format = _FORMAT[format] if isinstance(format, str) else int(format)
     if mixed_margin is not None:
         p.mixed_margin = float(mixed_margin)
-    p.two_step = int(bool(two_step))
+    if update_steps is not None:
+        p.update_steps = int(update_steps)
     return p
 
 

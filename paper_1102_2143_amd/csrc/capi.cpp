@@ -57,7 +57,7 @@ template <class T> void dfree(T*& p) {
 
 void free_workspace(Workspace& w) {
   for (void* q : {w.r, w.p[0], w.p[1], w.t, w.pk, w.r32, w.p32[0], w.p32[1], w.t32, w.pk32,
-                  w.rprev})
+                  w.rkeep[0], w.rkeep[1], w.rkeep[2]})
     if (q) (void)hipFree(q);
   dfree(w.t64);
   dfree(w.u64);
@@ -93,7 +93,7 @@ msc_status ensure_workspace(msc_op op, int prec, int ns) {
     HIP_TRY(hipMalloc(&w.pk, sizeof(double2) * n * nk));
     HIP_TRY(dalloc(&w.t64, n));
     HIP_TRY(dalloc(&w.u64, n * 8));
-    HIP_TRY(hipMalloc(&w.rprev, sizeof(double2) * n));
+    for (auto& q : w.rkeep) HIP_TRY(hipMalloc(&q, sizeof(double2) * n));
     HIP_TRY(dalloc(&w.st, 1));
     HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&w.h_halt), 4 * sizeof(int),
                           hipHostMallocMapped | hipHostMallocCoherent));
@@ -176,8 +176,9 @@ MsArgs make_args(msc_op op, int lanes, const double* d_b, double* d_x) {
   a.pb[1] = op->ws.p[1];
   a.t = op->ws.t;
   a.pk = op->ws.pk;
-  a.rprev = op->ws.rprev;  // complex64 use in the second phase of a mixed solve
+  for (int k = 0; k < kMaxSteps - 1; ++k) a.rkeep[k] = op->ws.rkeep[k];  // complex64 in phase 2
   a.hflag = op->ws.d_halt;
+  a.steps = 1;
   a.defer_ok = 0;
   a.sample = -1;
   a.t64 = op->ws.t64;
@@ -196,16 +197,15 @@ struct KernelBytes {
 };
 // launch with `act` active shifts; ib / ibh: bytes per column index of the copies of the
 // operator's matrix and of M^H that the SpMVs read.
-// `mode` is the head's update mode (0: one step; 1: deferred, r kept; 2: two steps, the
-// kept r read back).
+// `kept`: residual vectors the head's update writes (a deferring head keeps r) or reads
+// back (an applying head after deferred steps).
 KernelBytes kernel_bytes(int kind, int prec, double n, double nnz, double nnz_h, double act,
-                         bool pending, double ib, double ibh, int mode) {
+                         bool pending, double ib, double ibh, int kept) {
   const double w = prec == MSC_PREC_MIXED ? 8.0 : 16.0;
   KernelBytes b{};
   b.k1 = nnz * (w + ib) + 4.0 * (n + 1) + 2.0 * n * w;
   b.k2 = (kind == MSC_A_MHM ? nnz_h * (w + ibh) + 4.0 * (n + 1) + n * w : n * w) + 3.0 * n * w;
-  b.upd = pending ? n * (3.0 * w + 32.0) + act * n * (32.0 + 2.0 * w) + (mode != 0 ? n * w : 0.0)
-                  : 0.0;
+  b.upd = pending ? n * (3.0 * w + 32.0) + act * n * (32.0 + 2.0 * w) + kept * n * w : 0.0;
   b.head = b.k1 + (pending ? b.upd - n * w : 0.0);
   return b;
 }
@@ -324,8 +324,10 @@ msc_status run_multishift(msc_op op, const double* d_b, double* d_x, const msc_p
       hipEvent_t* ev = nullptr;
       cur->sample = -1;
       // a mixed solve is timed in its complex64 phase only; consecutive launches are
-      // sampled in pairs (a deferring head and the one that applies two steps)
-      if (prm.timing > 0 && launched % prm.timing < 2 && (!mixed || phase == MSC_PREC_MIXED) &&
+      // sampled in runs as long as a folding cycle (heads that defer and the one that
+      // applies the folded steps)
+      if (prm.timing > 0 && launched % prm.timing < std::max(2, prm.update_steps) &&
+          (!mixed || phase == MSC_PREC_MIXED) &&
           int(sample_launch.size()) < kMaxSamples) {
         ev = pool.next();
         if (!ev) {
@@ -344,7 +346,8 @@ msc_status run_multishift(msc_op op, const double* d_b, double* d_x, const msc_p
                       since % prm.reliable_every == 0;
       // a head followed by a reliable update applies its own step (the update may halt
       // the sequence before the next head)
-      cur->defer_ok = (prm.two_step && !ru) ? 1 : 0;
+      cur->defer_ok = ru ? 0 : 1;
+      cur->steps = prm.update_steps;
       HIP_TRY(launch_iteration(phase, *cur, s, ev, ru));
       ++launched;
     }
@@ -401,9 +404,10 @@ msc_status run_multishift(msc_op op, const double* d_b, double* d_x, const msc_p
       // the head's update mode and the shifts it listed, as recorded by the head itself
       const bool ph32 = launched_at_switch >= 0 && L >= launched_at_switch;
       const bool pending = !(L == 0 || (ph32 && L == launched_at_switch));
-      const int mode = h.smp_mode[q], act = h.smp_nact[q];
+      const int act = h.smp_nact[q];
+      const int kept = h.smp_mode[q] == 1 ? 1 : h.smp_m[q];
       const KernelBytes kb = kernel_bytes(op->kind, ph32 ? MSC_PREC_MIXED : prec, nn, nz, nzh,
-                                          double(act), pending, ib, ibh, mode);
+                                          double(act), pending, ib, ibh, kept);
       info->kernel_bytes[0] += a64.sell ? kb.head : kb.k1;
       info->kernel_bytes[1] += kb.k2;
       if (!a64.sell) info->kernel_bytes[2] += kb.upd;
@@ -1020,7 +1024,7 @@ struct BatchRun {
       // BK3 may defer its shifted update except in the graph's last iteration (a reliable
       // update or the end of the solve may follow it)
       BatchArgs ga = args();
-      ga.defer_ok = (prm.two_step && g < G - 1) ? 1 : 0;
+      ga.defer_ok = (prm.update_steps > 1 && g < G - 1) ? 1 : 0;
       hipError_t e = launch_batch_iteration(ga, sint);
       if (e != hipSuccess) {
         hipGraph_t tmp = nullptr;
@@ -1218,7 +1222,7 @@ void msc_params_default(msc_params* p) {
   p->lanes = 0;
   p->verify = 1;
   p->mixed_margin = 0.7;
-  p->two_step = 1;
+  p->update_steps = 4;
 }
 
 const char* msc_version(void) { return "msc 0.1 (gfx950)"; }
@@ -1424,8 +1428,8 @@ msc_status msc_solve(msc_op op, const double* d_b, double* d_x, const msc_params
     msc_params_default(&prm);
   if (!(prm.tol >= 0.0) || (prm.prec != MSC_PREC_FP64 && prm.prec != MSC_PREC_MIXED) ||
       !(prm.mixed_margin > 0.0 && prm.mixed_margin <= 1.0) ||
-      (prm.two_step != 0 && prm.two_step != 1) || prm.reserved != 0) {
-    set_error("msc_solve: invalid tol, precision, mixed_margin, two_step or reserved");
+      prm.update_steps < 1 || prm.update_steps > kMaxSteps || prm.reserved != 0) {
+    set_error("msc_solve: invalid tol, precision, mixed_margin, update_steps or reserved");
     return MSC_EINVAL;
   }
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -1455,8 +1459,8 @@ msc_status msc_solve_adjoint(msc_op op, const double* d_g, const double* d_x, do
     msc_params_default(&prm);
   if (!(prm.tol >= 0.0) || (prm.prec != MSC_PREC_FP64 && prm.prec != MSC_PREC_MIXED) ||
       !(prm.mixed_margin > 0.0 && prm.mixed_margin <= 1.0) ||
-      (prm.two_step != 0 && prm.two_step != 1) || prm.reserved != 0) {
-    set_error("msc_solve_adjoint: invalid tol, precision, mixed_margin, two_step or reserved");
+      prm.update_steps < 1 || prm.update_steps > kMaxSteps || prm.reserved != 0) {
+    set_error("msc_solve_adjoint: invalid tol, precision, mixed_margin, update_steps or reserved");
     return MSC_EINVAL;
   }
   prm.verify = 1;
@@ -1611,9 +1615,9 @@ msc_status msc_solve_batched(int32_t nsys, const msc_op* ops, const int32_t* nrh
   if (!(prm.tol >= 0.0) || (prm.prec != MSC_PREC_FP64 && prm.prec != MSC_PREC_MIXED) ||
       !(prm.mixed_margin > 0.0 && prm.mixed_margin <= 1.0) ||
       prm.format < MSC_FORMAT_AUTO || prm.format > MSC_FORMAT_SELL32 ||
-      (prm.two_step != 0 && prm.two_step != 1) || prm.reserved != 0) {
-    set_error("msc_solve_batched: invalid tol, precision, mixed_margin, format, two_step or "
-              "reserved");
+      prm.update_steps < 1 || prm.update_steps > kMaxSteps || prm.reserved != 0) {
+    set_error("msc_solve_batched: invalid tol, precision, mixed_margin, format, update_steps "
+              "or reserved");
     return MSC_EINVAL;
   }
   int rr = 1, max_nrhs = 0;

@@ -38,14 +38,27 @@ struct RotState {
   int status;                  // 0 running/ok, 1 breakdown
   int pending;                 // 1: the previous K2's r awaits its update of x, p_j and p
   int pcur;                    // which of the two direction buffers holds p
-  int defer;                   // 1: the head that wrote this state left its all-shift
-                               // update to the next head (SolveState::d_*)
+  int ndef;                    // steps of the all-shift update deferred so far (their
+                               // residuals kept; SolveState::dfs)
   double zeta[kMaxShifts];     // zeta_j^(n)
   int active[kMaxShifts];      // shift j still updated
 };
 
 // Head launches whose update mode is recorded for the byte model of sampled timings.
 constexpr int kMaxSamples = 256;
+
+// Steps of the all-shift update one pass over x_j and p_j may fold together.
+constexpr int kMaxSteps = 4;
+
+// Deferred steps of shift j composed against the direction p_j at the first of them and
+// the residuals r_0..r_{m-1} the deferring heads kept: so far
+//   x_j gained cx[0] p_j + sum_k cx[k+1] r_k,  and p_j now is cp[0] p_j + sum_k cp[k+1] r_k.
+struct DeferState {
+  double cx[kMaxSteps][kMaxShifts];
+  double cp[kMaxSteps][kMaxShifts];
+  int act[kMaxShifts];          // shift j took part in a deferred step
+  int upd[kMaxShifts];          // a deferred step changed p_j
+};
 
 struct SolveState {
   double a;          // a_n = R / (p^H (A + sigma0) p)      (K2, workgroup 0)
@@ -69,16 +82,14 @@ struct SolveState {
   int freeze_iter[kMaxShifts];
   int orig[kMaxShifts];         // caller's index of sorted shift j
   RotState rot[2];              // rot[par]: state at the start of an iteration of parity par
-  // the all-shift update step a head deferred to the next one: a_j, zeta_j^(n+1), b_j of
-  // that step, whether shift j took part and whether it updated p_j (did not freeze)
-  double d_a[kMaxShifts];
-  double d_z[kMaxShifts];
-  double d_b[kMaxShifts];
-  int d_act[kMaxShifts];
-  int d_upd[kMaxShifts];
-  // per sampled head launch (MsArgs::sample): its update mode (Plan) and shifts listed
+  // the deferred steps of the all-shift update, composed (DeferState), indexed by the
+  // parity of the head that writes them
+  DeferState dfs[2];
+  // per sampled head launch (MsArgs::sample): its update mode (Plan), shifts listed and
+  // kept residuals read
   int smp_mode[kMaxSamples];
   int smp_nact[kMaxSamples];
+  int smp_m[kMaxSamples];
   // per phase (0: FP64, 1: complex64): x_j/p_j row updates performed (in units of n
   // rows), heads that deferred their update, heads that applied two steps
   int n_shift_upd[2];
@@ -151,8 +162,8 @@ struct Workspace {
   void* t32 = nullptr;
   void* pk32 = nullptr;
   double2* t64 = nullptr;   // n complex128 (reliable updates, verification)
-  void* rprev = nullptr;    // n complex128 (complex64 in the second phase): r kept by a
-                            // head that defers its all-shift update
+  void* rkeep[kMaxSteps - 1] = {nullptr, nullptr, nullptr};  // n complex128 each (complex64
+                            // in the second phase): residuals kept by deferring heads
   double2* u64 = nullptr;   // 8 * n complex128 (verification SpMM chunk)
   SolveState* st = nullptr;
   int* h_halt = nullptr;    // host-coherent word the heads write: halt | switch_req << 1
@@ -246,8 +257,9 @@ struct MsArgs {
   double2* x;            // caller's x, shift-major, caller order
   void* r; void* t; void* pk;
   void* pb[2];           // the two direction buffers (p of consecutive iterations)
-  void* rprev;           // r kept by a head that defers its all-shift update
+  void* rkeep[kMaxSteps - 1];  // residuals kept by heads that defer the all-shift update
   int* hflag;            // host-coherent word: halt | switch_req << 1 of the next state
+  int steps;             // steps of the all-shift update folded into one pass (1..kMaxSteps)
   int defer_ok;          // 1: this launch's head may defer its all-shift update
   int sample;            // slot of SolveState::smp_* for this head, -1: not sampled
   double2* t64;

@@ -378,29 +378,30 @@ constexpr int kUpdGroup = MSC_UPD_GROUP;
 
 struct Plan {
   double bn;                 // b of p <- r + b p (0: p is current, nothing pending)
-  // the shifts this head updates, in list order: x_j += cx_p p_j + cx_r r0 and, where pw,
-  // p_j <- cp_p p_j + cp_r0 r0 + cp_r1 r (r: the current residual; r0: the one a deferring
-  // head kept), with the element offsets of x_j (the caller's order) and of p_j
-  double cx_p[kMaxShifts];
-  double cx_r[kMaxShifts];
-  double cp_p[kMaxShifts];
-  double cp_r0[kMaxShifts];
-  double cp_r1[kMaxShifts];
+  // the shifts this head updates, in list order, with the element offsets of x_j (the
+  // caller's order) and of p_j:  x_j += cx[0] p_j + sum_{k<m} cx[k+1] r_k  and, where pw,
+  // p_j <- cp[0] p_j + sum_{k<m} cp[k+1] r_k + cp[m+1] r  (r_k: the residuals kept by the
+  // m heads that deferred; r: the current one; unused coefficients are 0)
+  double cx[kMaxSteps][kMaxShifts];
+  double cp[kMaxSteps + 1][kMaxShifts];
   int64_t xo[kMaxShifts];
   int64_t po[kMaxShifts];
   int pw[kMaxShifts];
   int nact;
-  int mode;                  // 0: one step; 1: deferred (r kept, shifts untouched);
-                             // 2: the deferred step and this one together
+  int mode;                  // 0: apply (the current step and m deferred ones); 1: defer
+  int m;                     // kept residuals read (mode 0)
+  int keep;                  // slot the current residual is kept in (mode 1), -1: none
   int pending;               // the update runs in this head
   int ok;                    // 0: breakdown, the head stops
   int spmv;                  // 1: this head also computes t = M p
 };
 
-// Two consecutive steps A, B of shift j combine into one pass over its vectors:
-//   x += a_A p + a_B p',  p' = zeta_A r0 + b_A p,  p'' = zeta_B r + b_B p'
-// so x += (a_A + a_B b_A) p + a_B zeta_A r0 and p'' = b_B b_A p + b_B zeta_A r0 + zeta_B r;
-// a shift that froze at A takes only x += a_A p, one that freezes at B ends with p'.
+// Consecutive steps of shift j compose: with p_j = cp[0] p + sum_k cp[k+1] r_k after the
+// deferred ones, the next step adds a_j p_j to x_j and turns p_j into
+// zeta_j' r + b_j p_j (r: that step's residual), unless j freezes there (p_j stays); a
+// frozen shift takes no further step.  A head defers (keeps its r, touches no x_j, p_j)
+// while fewer than `steps` - 1 steps are pending and its iteration continues; otherwise
+// it applies all of them in one pass.
 template <class T>
 __device__ void head_plan(const MsArgs& a, const Early& e, Plan& pl) {
   constexpr int ph = sizeof(T) == 4 ? 1 : 0;  // phase: 0 FP64, 1 complex64
@@ -409,10 +410,14 @@ __device__ void head_plan(const MsArgs& a, const Early& e, Plan& pl) {
   RotState& nx = st->rot[a.par ^ 1];
   const int j = threadIdx.x;
   const int pending = rs.pending;
-  const int two = rs.defer;
+  const int m = rs.ndef;
   // wave 0, lane j: shift j's state, loaded before the partial sum
   int act0 = 0, origj = 0, dact = 0, dupd = 0;
-  double z = 1.0, zn = 0.0, akj = 0.0, da = 0.0, dz = 0.0, db = 0.0;
+  double z = 1.0, zn = 0.0, akj = 0.0;
+  double cx[kMaxSteps + 1], cp[kMaxSteps + 1];
+#pragma unroll
+  for (int i = 0; i <= kMaxSteps; ++i) cx[i] = cp[i] = 0.0;
+  cp[0] = 1.0;
   if (j >= 1 && j < kWave && j < st->ns) {
     if (pending) {
       act0 = rs.active[j];
@@ -420,13 +425,18 @@ __device__ void head_plan(const MsArgs& a, const Early& e, Plan& pl) {
       zn = st->zk[j];
       akj = st->ak[j];
     }
-    if (pending || two) origj = st->orig[j];
-    if (two) {
-      dact = st->d_act[j];
-      dupd = st->d_upd[j];
-      da = st->d_a[j];
-      dz = st->d_z[j];
-      db = st->d_b[j];
+    if (pending || m > 0) origj = st->orig[j];
+    if (m > 0) {
+      const DeferState& d = st->dfs[a.par];
+#pragma unroll
+      for (int i = 0; i < kMaxSteps; ++i) {
+        if (i <= m) {
+          cx[i] = d.cx[i][j];
+          cp[i] = d.cp[i][j];
+        }
+      }
+      dact = d.act[j];
+      dupd = d.upd[j];
     }
   }
   const double R = rs.R, eps2 = st->eps2;
@@ -445,52 +455,42 @@ __device__ void head_plan(const MsArgs& a, const Early& e, Plan& pl) {
     // converts the Krylov vectors to complex64 and continues
     const bool sw = pending && !done && Rn <= st->sw_eps2;
     const bool cont = ok && !done && !sw;
-    // a head defers only when the iteration continues and nothing is deferred yet; the
-    // head after it (or a halting one) applies both steps
-    const int mode = two ? 2 : ((pending && cont && a.defer_ok) ? 1 : 0);
-    bool listed = false, pw = false;
-    double cxp = 0.0, cxr = 0.0, cpp = 0.0, cpr0 = 0.0, cpr1 = 0.0;
-    if (mode == 0) {
-      listed = act;
-      cxp = akj;
-      cpp = bk;
-      cpr1 = zn;
-      pw = !freeze_now;
-    } else if (mode == 2) {
-      listed = dact != 0;
-      pw = dupd != 0;
-      if (act) {
-        cxp = da + akj * db;
-        cxr = akj * dz;
-      } else {
-        cxp = da;
-      }
-      if (act && !freeze_now) {
-        cpp = bk * db;
-        cpr0 = bk * dz;
-        cpr1 = zn;
-      } else {
-        cpp = db;
-        cpr0 = dz;
-      }
+    // fold the current step into the composition
+    if (act) {
+#pragma unroll
+      for (int i = 0; i < kMaxSteps; ++i)
+        if (i <= m) cx[i] = fma(akj, cp[i], cx[i]);
     }
+    if (act && !freeze_now) {
+#pragma unroll
+      for (int i = 0; i < kMaxSteps; ++i)
+        if (i <= m) cp[i] *= bk;
+#pragma unroll
+      for (int i = 1; i <= kMaxSteps; ++i)
+        if (i == m + 1) cp[i] = zn;
+    }
+    dact = dact || act;
+    dupd = dupd || (act && !freeze_now);
+    const int mode = (pending && cont && a.defer_ok && m + 1 < a.steps) ? 1 : 0;
+    const bool listed = mode == 0 && dact;
     const uint64_t mask = __ballot(listed);
     if (listed) {
       const int pos = __popcll(mask & ((uint64_t(1) << j) - 1));
-      pl.cx_p[pos] = cxp;
-      pl.cx_r[pos] = cxr;
-      pl.cp_p[pos] = cpp;
-      pl.cp_r0[pos] = cpr0;
-      pl.cp_r1[pos] = cpr1;
+#pragma unroll
+      for (int i = 0; i < kMaxSteps; ++i) pl.cx[i][pos] = i <= m ? cx[i] : 0.0;
+#pragma unroll
+      for (int i = 0; i <= kMaxSteps; ++i) pl.cp[i][pos] = i <= m + 1 ? cp[i] : 0.0;
       pl.xo[pos] = int64_t(origj) * a.n;
       pl.po[pos] = int64_t(j - 1) * a.n;
-      pl.pw[pos] = pw ? 1 : 0;
+      pl.pw[pos] = dupd ? 1 : 0;
     }
     const int nlist = __popcll(mask);
     if (j == 0) {
       pl.bn = bn;
       pl.nact = nlist;
       pl.mode = mode;
+      pl.m = mode == 0 ? m : 0;
+      pl.keep = mode == 1 ? m : -1;
       pl.pending = pending;
       pl.ok = ok ? 1 : 0;
       pl.spmv = cont ? 1 : 0;
@@ -500,11 +500,14 @@ __device__ void head_plan(const MsArgs& a, const Early& e, Plan& pl) {
         nx.zeta[j] = act ? zn : rs.zeta[j];
         nx.active[j] = act ? (freeze_now ? 0 : 1) : rs.active[j];
         if (mode == 1 && j >= 1) {
-          st->d_a[j] = akj;
-          st->d_z[j] = zn;
-          st->d_b[j] = bk;
-          st->d_act[j] = act ? 1 : 0;
-          st->d_upd[j] = freeze_now ? 0 : 1;
+          DeferState& d = st->dfs[a.par ^ 1];
+#pragma unroll
+          for (int i = 0; i < kMaxSteps; ++i) {
+            d.cx[i][j] = i <= m ? cx[i] : 0.0;
+            d.cp[i][j] = i <= m + 1 ? cp[i] : 0.0;
+          }
+          d.act[j] = dact ? 1 : 0;
+          d.upd[j] = dupd ? 1 : 0;
         }
       }
       if (act) {
@@ -513,15 +516,16 @@ __device__ void head_plan(const MsArgs& a, const Early& e, Plan& pl) {
       }
       if (j == 0) {
         nx.pending = 0;
-        nx.defer = (ok && mode == 1) ? 1 : 0;
+        nx.ndef = (ok && mode == 1) ? m + 1 : 0;
         if (a.sample >= 0 && a.sample < kMaxSamples) {
           st->smp_mode[a.sample] = mode;
           st->smp_nact[a.sample] = nlist;
+          st->smp_m[a.sample] = mode == 0 ? m : 0;
         }
         if (pending && ok) {
           st->n_shift_upd[ph] += nlist;
           st->n_defer[ph] += mode == 1 ? 1 : 0;
-          st->n_two[ph] += mode == 2 ? 1 : 0;
+          st->n_two[ph] += mode == 0 ? m : 0;
         }
         if (!ok) {
           nx.R = R;
@@ -569,58 +573,78 @@ __device__ void carry_state(const MsArgs& a) {
     nx.status = rs.status;
     nx.pending = rs.pending;
     nx.pcur = rs.pcur;
-    nx.defer = rs.defer;
+    nx.ndef = rs.ndef;
     store_host_flag(a.hflag, 1 | (rs.switch_req ? 2 : 0));
   }
 }
 
-// The pending update of row i: x_0 += a p and the listed shifts' x_j and p_j as the plan
-// says (one step, or two when a deferred step is folded in, reading the kept r0; a
-// deferring head keeps r in r0 instead), then the new direction r + b p, which is stored
-// in the other direction buffer and returned.  rr, pp, x0v: the row's r, p and x_0
-// (already loaded).
+// The pending update of row i: x_0 += a p, then the listed shifts' x_j and p_j as the
+// plan composes them (the current step and the m deferred ones, reading the m kept
+// residuals; a deferring head keeps r instead and touches no shift), then the new
+// direction r + b p, which is stored in the other direction buffer and returned.  rr,
+// pp, x0v: the row's r, p and x_0 (already loaded).
 template <class R>
 __device__ __forceinline__ cplx<R> update_row(const MsArgs& a, const Plan& pl, double step,
                                               int64_t i, const cplx<R>& rr, const cplx<R>& pp,
                                               double2 x0v, double2* __restrict__ x0,
                                               cplx<R>* __restrict__ pnew) {
   cplx<R>* __restrict__ pk = static_cast<cplx<R>*>(a.pk);
-  cplx<R>* __restrict__ rprev = static_cast<cplx<R>*>(a.rprev);
   double2* __restrict__ x = a.x;
   const double2 rd = to_d(rr), pd = to_d(pp);
   x0v.x = fma(step, pd.x, x0v.x);
   x0v.y = fma(step, pd.y, x0v.y);
   x0[i] = x0v;
-  if (pl.mode == 1) rprev[i] = rr;
-  const double2 r0d = pl.mode == 2 ? to_d(rprev[i]) : double2{0.0, 0.0};
+  if (pl.keep >= 0) static_cast<cplx<R>*>(a.rkeep[pl.keep])[i] = rr;
+  // kept residuals (zero beyond m, where the coefficients are zero too)
+  double2 rk[kMaxSteps - 1];
+#pragma unroll
+  for (int k = 0; k < kMaxSteps - 1; ++k)
+    rk[k] = k < pl.m ? to_d(static_cast<const cplx<R>*>(a.rkeep[k])[i]) : double2{0.0, 0.0};
   // shifts in groups of MSC_UPD_GROUP: a group's loads are all issued before its first
-  // store; a last, partial group is masked.  With cx_r = cp_r0 = 0 (one step) the fused
+  // store; a last, partial group is masked.  With one step (m = 0) the fused
   // multiply-adds round exactly as x += a p and p <- zeta r + b p.
   const int nact = pl.nact;
-  auto group = [&](int q, int m, auto full) {
+  const int m = pl.m;
+  auto group = [&](int q, int cnt, auto full) {
     cplx<R> pj[kUpdGroup];
     double2 xj[kUpdGroup];
 #pragma unroll
     for (int u = 0; u < kUpdGroup; ++u) {
-      if (decltype(full)::value || u < m) {
+      if (decltype(full)::value || u < cnt) {
         pj[u] = pk[pl.po[q + u] + i];
         xj[u] = x[pl.xo[q + u] + i];
       }
     }
 #pragma unroll
     for (int u = 0; u < kUpdGroup; ++u) {
-      if (decltype(full)::value || u < m) {
+      if (decltype(full)::value || u < cnt) {
+        const int c = q + u;
         const double2 pjd = to_d(pj[u]);
-        const double cxp = pl.cx_p[q + u], cxr = pl.cx_r[q + u];
-        xj[u].x = fma(cxp, pjd.x, fma(cxr, r0d.x, xj[u].x));
-        xj[u].y = fma(cxp, pjd.y, fma(cxr, r0d.y, xj[u].y));
-        x[pl.xo[q + u] + i] = xj[u];
-        if (pl.pw[q + u]) {
-          const double cpp = pl.cp_p[q + u], c0 = pl.cp_r0[q + u], c1 = pl.cp_r1[q + u];
-          double2 np;
-          np.x = fma(c1, rd.x, fma(c0, r0d.x, cpp * pjd.x));
-          np.y = fma(c1, rd.y, fma(c0, r0d.y, cpp * pjd.y));
-          pk[pl.po[q + u] + i] = from_d<R>(np);
+        double2 xv = xj[u];
+#pragma unroll
+        for (int k = kMaxSteps - 2; k >= 0; --k) {
+          if (k < m) {
+            xv.x = fma(pl.cx[k + 1][c], rk[k].x, xv.x);
+            xv.y = fma(pl.cx[k + 1][c], rk[k].y, xv.y);
+          }
+        }
+        xv.x = fma(pl.cx[0][c], pjd.x, xv.x);
+        xv.y = fma(pl.cx[0][c], pjd.y, xv.y);
+        x[pl.xo[c] + i] = xv;
+        if (pl.pw[c]) {
+          const double c0 = pl.cp[0][c];
+          double2 np{c0 * pjd.x, c0 * pjd.y};
+#pragma unroll
+          for (int k = 0; k < kMaxSteps - 1; ++k) {
+            if (k < m) {
+              np.x = fma(pl.cp[k + 1][c], rk[k].x, np.x);
+              np.y = fma(pl.cp[k + 1][c], rk[k].y, np.y);
+            }
+          }
+          const double cr = pl.cp[m + 1][c];
+          np.x = fma(cr, rd.x, np.x);
+          np.y = fma(cr, rd.y, np.y);
+          pk[pl.po[c] + i] = from_d<R>(np);
         }
       }
     }

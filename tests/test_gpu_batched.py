@@ -92,7 +92,7 @@ def test_batch_result_is_independent_of_companions(cuda):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_batch_two_step_matches_one_step(cuda, prec):
+def test_batch_two_steps_match_one_step(cuda, prec):
     # the batch defers every other shifted update and folds two steps into one pass: the
     # driving sequences, iteration counts and freezes are those of one step per
     # iteration, the solutions agree to rounding, and fewer bytes move
@@ -101,8 +101,8 @@ def test_batch_two_step_matches_one_step(cuda, prec):
     systems = _small_batch()
     ops = _ops(systems, cuda)
     bs = [p["b"] for p in systems]
-    x1, i1, s1 = solve_batched(ops, bs, tol=1e-10, prec=prec, two_step=False)
-    x2, i2, s2 = solve_batched(ops, bs, tol=1e-10, prec=prec, two_step=True)
+    x1, i1, s1 = solve_batched(ops, bs, tol=1e-10, prec=prec, update_steps=1)
+    x2, i2, s2 = solve_batched(ops, bs, tol=1e-10, prec=prec, update_steps=2)
     assert s1 == "ok" and s2 == "ok"
     for a, b in zip(i1, i2):
         assert a["iters"] == b["iters"]

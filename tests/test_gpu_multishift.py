@@ -228,17 +228,17 @@ def test_iteration_limit_in_the_complex64_phase(c0, cuda, fmt, limit):
     op.close()
 
 
-@pytest.mark.parametrize("fmt", ["sell", "csr"])
+@pytest.mark.parametrize("fmt,steps", [("sell", 2), ("sell", 3), ("sell", 4), ("csr", 2), ("csr", 3)])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_two_step_update_matches_one_step(c0, cuda, fmt, prec):
-    # deferring every other all-shift update and applying two steps in one pass follows
-    # the same recurrences: the driving sequence, the iteration count and every freeze are
-    # identical; the shifted solutions agree to rounding (FP64) or to the complex64
-    # rounding of the shift directions (mixed), and the byte count drops
+def test_folded_update_steps_match_one_step(c0, cuda, fmt, steps, prec):
+    # folding consecutive steps of the all-shift update into one pass (the heads between
+    # defer theirs) follows the same recurrences: the driving sequence, the iteration count
+    # and every freeze are identical; the shifted solutions agree to rounding (FP64) or to
+    # the complex64 rounding of the shift directions (mixed), and fewer bytes move
     op = _op(c0, cuda)
     op.set_shifts(c0["sigma"])
-    x1, i1 = op.solve(c0["b"], tol=1e-10, prec=prec, format=fmt, two_step=False)
-    x2, i2 = op.solve(c0["b"], tol=1e-10, prec=prec, format=fmt, two_step=True)
+    x1, i1 = op.solve(c0["b"], tol=1e-10, prec=prec, format=fmt, update_steps=1)
+    x2, i2 = op.solve(c0["b"], tol=1e-10, prec=prec, format=fmt, update_steps=steps)
     assert i1["status"] == "ok" and i2["status"] == "ok"
     assert i1["iters"] == i2["iters"] and i1["iters_fp64"] == i2["iters_fp64"]
     assert np.array_equal(i1["freeze_iter"], i2["freeze_iter"])
@@ -249,6 +249,16 @@ def test_two_step_update_matches_one_step(c0, cuda, fmt, prec):
     assert np.all(_rel(x2.cpu().numpy(), x1.cpu().numpy()) <= bar)
     assert np.all(i2["true_rel_res"] <= 1e-10)
     assert i2["alg_bytes"] < i1["alg_bytes"]
+    op.close()
+
+
+def test_update_steps_out_of_range_rejected(c0, cuda):
+    from paper_1102_2143_amd import MscError
+    op = _op(c0, cuda)
+    op.set_shifts(c0["sigma"])
+    for bad in (0, 5):
+        with pytest.raises(MscError):
+            op.solve(c0["b"], update_steps=bad)
     op.close()
 
 

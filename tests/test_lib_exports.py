@@ -41,8 +41,8 @@ def test_params_default_and_struct_layout():
     lib.msc_params_default(ctypes.byref(p))
     assert p.tol == 1e-10 and p.max_iter == 10000 and p.reliable_every == 50
     assert p.poll_every == 16 and p.verify == 1
-    assert p.two_step == 1 and p.reserved == 0
-    assert ctypes.sizeof(_lib.Params) == 80  # two_step and a reserved word appended
+    assert p.update_steps == 4 and p.reserved == 0
+    assert ctypes.sizeof(_lib.Params) == 80  # update_steps and a reserved word appended
     assert ctypes.sizeof(_lib.Info) == 104  # kernel_bytes[3] appended
 
 
