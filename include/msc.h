@@ -97,8 +97,7 @@ typedef struct {
     int32_t update_steps;    /* 1..4: consecutive steps of the all-shift update folded
                                 into one pass over x_k and p_k (the heads between defer
                                 theirs); same recurrences, 1/update_steps of the traffic
-                                of those vectors. 1: one step per iteration. The batched
-                                solve folds at most 2                            (4)    */
+                                of those vectors. 1: one step per iteration    (4)    */
     int32_t reserved;        /* must be 0                                        (0)    */
 } msc_params;
 

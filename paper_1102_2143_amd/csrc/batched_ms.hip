@@ -190,7 +190,7 @@ __device__ void bk1_chunk(const BatchSys& S, BatchState* st, const int4& ch) {
 // ---- BK2: r <- r - a (A2 t + s0 p), R' = |r|^2; recurrences, freezing, halting ------------
 template <class R, int L, int RR>
 __device__ void bk2_chunk(const BatchSys& S, BatchState* st, const int4& ch, int* active_systems,
-                          int defer_ok) {
+                          int defer_ok, int steps) {
   const cplx<R>* __restrict__ t = vec_t<R>(S);
   const cplx<R>* __restrict__ p = vec_p<R>(S);
   cplx<R>* __restrict__ r = vec_r<R>(S);
@@ -259,12 +259,25 @@ __device__ void bk2_chunk(const BatchSys& S, BatchState* st, const int4& ch, int
   const bool act = live && k >= 1 && k < ns && st->active[lk];
   const double z = act ? st->zeta[lk] : 1.0, zn = act ? st->zk[lk] : 1.0;
   const double akq = act ? st->ak[lk] : 0.0;
-  // a step this rhs deferred in the previous BK3 (read before any lane writes the state)
-  const int twoq = q < nrhs ? st->two[q] : 0;
-  const bool dact = twoq && k >= 1 && k < ns && st->d_act[lk];
-  const bool dupd = dact && st->d_upd[lk];
-  const double da = dact ? st->d_a[lk] : 0.0, dz = dact ? st->d_z[lk] : 0.0;
-  const double db = dact ? st->d_b[lk] : 0.0;
+  // steps this rhs deferred in previous BK3s, composed (read before any lane writes the
+  // state): x_k gained cx[0] p_k + sum_i cx[i+1] r_i, p_k now is cp[0] p_k + sum_i cp[i+1] r_i
+  const int md = q < nrhs ? st->ndef[q] : 0;
+  double cx[kMaxSteps + 1], cp[kMaxSteps + 1];
+#pragma unroll
+  for (int i = 0; i <= kMaxSteps; ++i) cx[i] = cp[i] = 0.0;
+  cp[0] = 1.0;
+  bool dact = false, dupd = false;
+  if (md > 0 && k >= 1 && k < ns) {
+#pragma unroll
+    for (int i = 0; i < kMaxSteps; ++i) {
+      if (i <= md) {
+        cx[i] = st->dcx[i][lk];
+        cp[i] = st->dcp[i][lk];
+      }
+    }
+    dact = st->dact[lk] != 0;
+    dupd = st->dupd[lk] != 0;
+  }
   const double Rn = live ? tot[q] : 0.0;
   const double bn = Rn / Rq;
   bool keep_p = false;
@@ -307,57 +320,50 @@ __device__ void bk2_chunk(const BatchSys& S, BatchState* st, const int4& ch, int
   const bool all_halted = __ballot(!halted_after) == 0;
   const bool all_below = __ballot(!halted_after && !below) == 0;
   const bool switching = !all_halted && !phase32 && all_below;
-  // BK3's mode for this rhs: apply a deferred step with this one (2), defer this one when
-  // the rhs continues and the vectors keep their precision (1), or one step (0)
-  const int mode = twoq ? 2 : ((live && !halt_q && !switching && defer_ok) ? 1 : 0);
-  bool listed = false, pw = false;
-  double cxp = 0.0, cxr = 0.0, cpp = 0.0, cpr0 = 0.0, cpr1 = 0.0;
-  if (mode == 0) {
-    listed = act;
-    pw = keep_p;
-    cxp = akq;
-    cpp = bkq;
-    cpr1 = zn;
-  } else if (mode == 2) {
-    listed = dact;
-    pw = dupd;
-    if (act) {
-      cxp = da + akq * db;
-      cxr = akq * dz;
-    } else {
-      cxp = da;
-    }
-    if (act && keep_p) {
-      cpp = bkq * db;
-      cpr0 = bkq * dz;
-      cpr1 = zn;
-    } else {
-      cpp = db;
-      cpr0 = dz;
-    }
+  // fold this step into the composition (x_k += a_k p_k; p_k <- zeta_k' r + b_k p_k unless
+  // k freezes now); then BK3 either defers it (this rhs continues, the vectors keep their
+  // precision, fewer than `steps` - 1 steps pending) or applies every pending step
+  if (act) {
+#pragma unroll
+    for (int i = 0; i < kMaxSteps; ++i)
+      if (i <= md) cx[i] = fma(akq, cp[i], cx[i]);
   }
+  if (act && keep_p) {
+#pragma unroll
+    for (int i = 0; i < kMaxSteps; ++i)
+      if (i <= md) cp[i] *= bkq;
+#pragma unroll
+    for (int i = 1; i <= kMaxSteps; ++i)
+      if (i == md + 1) cp[i] = zn;
+  }
+  dact = dact || act;
+  dupd = dupd || (act && keep_p);
+  const bool defer = live && !halt_q && !switching && defer_ok && md + 1 < steps;
+  const bool listed = !defer && dact;
   st->upd_x[lk] = listed ? 1 : 0;
-  st->upd_p[lk] = pw ? 1 : 0;
-  st->cxp[lk] = cxp;
-  st->cxr[lk] = cxr;
-  st->cpp[lk] = cpp;
-  st->cpr0[lk] = cpr0;
-  st->cpr1[lk] = cpr1;
-  if (mode == 1) {
-    st->d_a[lk] = akq;
-    st->d_z[lk] = zn;
-    st->d_b[lk] = bkq;
-    st->d_act[lk] = act ? 1 : 0;
-    st->d_upd[lk] = keep_p ? 1 : 0;
+  st->upd_p[lk] = (listed && dupd) ? 1 : 0;
+#pragma unroll
+  for (int i = 0; i < kMaxSteps; ++i) st->cx[i][lk] = i <= md ? cx[i] : 0.0;
+#pragma unroll
+  for (int i = 0; i <= kMaxSteps; ++i) st->cp[i][lk] = i <= md + 1 ? cp[i] : 0.0;
+  if (defer) {
+#pragma unroll
+    for (int i = 0; i < kMaxSteps; ++i) {
+      st->dcx[i][lk] = i <= md ? cx[i] : 0.0;
+      st->dcp[i][lk] = i <= md + 1 ? cp[i] : 0.0;
+    }
+    st->dact[lk] = dact ? 1 : 0;
+    st->dupd[lk] = dupd ? 1 : 0;
   }
   const uint64_t lm = __ballot(listed);
   if (k == 0 && q < nrhs) {
-    st->mode[q] = mode;
-    st->two[q] = mode == 1 ? 1 : 0;
+    st->ndef[q] = defer ? md + 1 : 0;
+    st->m[q] = defer ? 0 : md;
+    st->keep[q] = defer ? md : -1;
     if (live) {
       const int ph = phase32 ? 1 : 0;
       st->n_upd[q][ph] += __popcll((lm >> (q * kBatchMaxShifts)) & 0xffffull);
-      st->n_kept[q][ph] += mode != 0 ? 1 : 0;
+      st->n_kept[q][ph] += defer ? 1 : md;
     }
   }
   if (lk == 0) {
@@ -376,11 +382,11 @@ __device__ void bk2_chunk(const BatchSys& S, BatchState* st, const int4& ch, int
 // The update's per-(rhs, shift) coefficients, staged in LDS once per chunk so the loop
 // over shifts issues its vector loads without first waiting on the scalar state.
 struct K3Coef {
-  double cxp[kQK], cxr[kQK], cpp[kQK], cpr0[kQK], cpr1[kQK];
+  double cx[kMaxSteps][kQK], cp[kMaxSteps + 1][kQK];
   int upd_x[kQK], upd_p[kQK];
   int orig[kBatchMaxShifts];
   double a[kBatchMaxRhs], bnew[kBatchMaxRhs];
-  int x0_upd[kBatchMaxRhs], mode[kBatchMaxRhs];
+  int x0_upd[kBatchMaxRhs], m[kBatchMaxRhs], keep[kBatchMaxRhs];
   int nrhs, ns;
 };
 
@@ -390,11 +396,10 @@ __device__ void bk3_chunk(const BatchSys& S, const BatchState* st, const int4& c
   const int tid = threadIdx.x;
   __syncthreads();  // the previous chunk of this workgroup is done with cf
   if (tid < kQK) {
-    cf.cxp[tid] = st->cxp[tid];
-    cf.cxr[tid] = st->cxr[tid];
-    cf.cpp[tid] = st->cpp[tid];
-    cf.cpr0[tid] = st->cpr0[tid];
-    cf.cpr1[tid] = st->cpr1[tid];
+#pragma unroll
+    for (int i = 0; i < kMaxSteps; ++i) cf.cx[i][tid] = st->cx[i][tid];
+#pragma unroll
+    for (int i = 0; i <= kMaxSteps; ++i) cf.cp[i][tid] = st->cp[i][tid];
     cf.upd_x[tid] = st->upd_x[tid];
     cf.upd_p[tid] = st->upd_p[tid];
   }
@@ -403,7 +408,8 @@ __device__ void bk3_chunk(const BatchSys& S, const BatchState* st, const int4& c
     cf.a[tid] = st->a[tid];
     cf.bnew[tid] = st->b_new[tid];
     cf.x0_upd[tid] = st->x0_upd[tid];
-    cf.mode[tid] = st->mode[tid];
+    cf.m[tid] = st->m[tid];
+    cf.keep[tid] = st->keep[tid];
   }
   if (tid == 0) {
     cf.nrhs = st->nrhs;
@@ -417,7 +423,6 @@ __device__ void bk3_chunk(const BatchSys& S, const BatchState* st, const int4& c
   cplx<W>* __restrict__ pw = vec_p<W>(S);
   cplx<W>* __restrict__ rw = vec_r<W>(S);
   cplx<W>* __restrict__ pkw = vec_pk<W>(S);
-  cplx<R>* __restrict__ rkeep = static_cast<cplx<R>*>(S.rkeep);
   const int64_t n = S.n;
   const int ns = cf.ns;
   const int64_t rows = ch.z - ch.y;
@@ -434,11 +439,14 @@ __device__ void bk3_chunk(const BatchSys& S, const BatchState* st, const int4& c
       xv.x = fma(a, pd.x, xv.x);
       xv.y = fma(a, pd.y, xv.y);
       *x0 = xv;
-      // a deferring BK3 keeps r for the next one, which folds both steps (with
-      // cxr = cpr0 = 0 the multiply-adds round exactly as one step)
-      const int mode = cf.mode[q];
-      if (mode == 1) rkeep[idx] = r[idx];
-      const double2 r0 = mode == 2 ? to_d(rkeep[idx]) : double2{0.0, 0.0};
+      // a deferring BK3 keeps r; the one that applies reads the m kept residuals (with
+      // m = 0 the multiply-adds round exactly as one step)
+      const int mq = cf.m[q], kq = cf.keep[q];
+      if (kq >= 0) static_cast<cplx<R>*>(S.rkeep[kq])[idx] = r[idx];
+      double2 rk[kMaxSteps - 1];
+#pragma unroll
+      for (int kk = 0; kk < kMaxSteps - 1; ++kk)
+        rk[kk] = kk < mq ? to_d(static_cast<const cplx<R>*>(S.rkeep[kk])[idx]) : double2{0.0, 0.0};
       constexpr bool same = std::is_same<R, W>::value;
       // two shifts at a time, their loads issued before either store (x_k and p_k of
       // different shifts share one array each, so the compiler cannot reorder); frozen
@@ -462,15 +470,32 @@ __device__ void bk3_chunk(const BatchSys& S, const BatchState* st, const int4& c
           const int lk = q * kBatchMaxShifts + k;
           const int64_t pidx = int64_t(k - 1) * n * RR + idx;
           if (ux[u]) {
-            const double cx = cf.cxp[lk], cr = cf.cxr[lk];
-            xk[u].x = fma(cx, pj[u].x, fma(cr, r0.x, xk[u].x));
-            xk[u].y = fma(cx, pj[u].y, fma(cr, r0.y, xk[u].y));
-            S.x[(int64_t(q) * ns + cf.orig[k]) * n + i] = xk[u];
+            double2 xv = xk[u];
+#pragma unroll
+            for (int kk = kMaxSteps - 2; kk >= 0; --kk) {
+              if (kk < mq) {
+                xv.x = fma(cf.cx[kk + 1][lk], rk[kk].x, xv.x);
+                xv.y = fma(cf.cx[kk + 1][lk], rk[kk].y, xv.y);
+              }
+            }
+            xv.x = fma(cf.cx[0][lk], pj[u].x, xv.x);
+            xv.y = fma(cf.cx[0][lk], pj[u].y, xv.y);
+            S.x[(int64_t(q) * ns + cf.orig[k]) * n + i] = xv;
           }
           if (cf.upd_p[lk]) {
-            const double cp = cf.cpp[lk], c0 = cf.cpr0[lk], c1 = cf.cpr1[lk];
-            pkw[pidx] = from_d<W>(double2{fma(c1, rd.x, fma(c0, r0.x, cp * pj[u].x)),
-                                          fma(c1, rd.y, fma(c0, r0.y, cp * pj[u].y))});
+            const double c0 = cf.cp[0][lk];
+            double2 np{c0 * pj[u].x, c0 * pj[u].y};
+#pragma unroll
+            for (int kk = 0; kk < kMaxSteps - 1; ++kk) {
+              if (kk < mq) {
+                np.x = fma(cf.cp[kk + 1][lk], rk[kk].x, np.x);
+                np.y = fma(cf.cp[kk + 1][lk], rk[kk].y, np.y);
+              }
+            }
+            const double cr = cf.cp[mq + 1][lk];
+            np.x = fma(cr, rd.x, np.x);
+            np.y = fma(cr, rd.y, np.y);
+            pkw[pidx] = from_d<W>(np);
           } else if (!same) {
             pkw[pidx] = from_d<W>(pj[u]);
           }
@@ -630,14 +655,14 @@ __global__ __launch_bounds__(kBlock) void bk2(BatchArgs a) {
     BatchState* st = S.st;
     if (st->done) continue;
     if (st->phase32)
-      bk2_chunk<float, L, RR>(S, st, ch, a.active_systems, a.defer_ok);
+      bk2_chunk<float, L, RR>(S, st, ch, a.active_systems, a.defer_ok, a.steps);
     else
-      bk2_chunk<double, L, RR>(S, st, ch, a.active_systems, a.defer_ok);
+      bk2_chunk<double, L, RR>(S, st, ch, a.active_systems, a.defer_ok, a.steps);
   }
 }
 
 template <int RR>
-__global__ __launch_bounds__(kBlock) void bk3(BatchArgs a) {
+__global__ __launch_bounds__(kBlock, 4) void bk3(BatchArgs a) {
   for (int c = blockIdx.x; c < a.nchunks; c += gridDim.x) {
     const int4 ch = a.chunks[c];
     const BatchSys& S = a.sys[ch.x];

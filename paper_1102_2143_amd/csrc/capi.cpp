@@ -801,7 +801,8 @@ struct BatchRun {
       const size_t n = size_t(ops[s]->n), nk = std::max<size_t>(ops[s]->sigma.size() - 1, 1);
       const size_t nch = (n + kBatchChunkRows - 1) / kBatchChunkRows;
       off[s] = bytes;
-      bytes += 5 * align(sizeof(double2) * n * rr) + align(sizeof(double2) * n * rr * nk) +
+      bytes += (4 + kMaxSteps - 1) * align(sizeof(double2) * n * rr) +
+               align(sizeof(double2) * n * rr * nk) +
                3 * align(sizeof(float2) * n * rr) + align(sizeof(float2) * n * rr * nk) +
                align(sizeof(double) * nch * kBatchMaxRhs);
       for (size_t c = 0; c < nch; ++c) {
@@ -868,7 +869,7 @@ struct BatchRun {
       S.p64 = reinterpret_cast<double2*>(take(sizeof(double2) * n * rr));
       S.t64 = reinterpret_cast<double2*>(take(sizeof(double2) * n * rr));
       S.u64 = reinterpret_cast<double2*>(take(sizeof(double2) * n * rr));
-      S.rkeep = take(sizeof(double2) * n * rr);
+      for (auto& q : S.rkeep) q = take(sizeof(double2) * n * rr);
       S.pk64 = reinterpret_cast<double2*>(take(sizeof(double2) * n * rr * nk));
       S.r32 = reinterpret_cast<float2*>(take(sizeof(float2) * n * rr));
       S.p32 = reinterpret_cast<float2*>(take(sizeof(float2) * n * rr));
@@ -1025,6 +1026,7 @@ struct BatchRun {
       // update or the end of the solve may follow it)
       BatchArgs ga = args();
       ga.defer_ok = (prm.update_steps > 1 && g < G - 1) ? 1 : 0;
+      ga.steps = prm.update_steps;
       hipError_t e = launch_batch_iteration(ga, sint);
       if (e != hipSuccess) {
         hipGraph_t tmp = nullptr;

@@ -362,18 +362,19 @@ struct BatchState {
   double bk[kBatchMaxRhs * kBatchMaxShifts];
   int active[kBatchMaxRhs * kBatchMaxShifts], freeze_iter[kBatchMaxRhs * kBatchMaxShifts];
   int upd_p[kBatchMaxRhs * kBatchMaxShifts], upd_x[kBatchMaxRhs * kBatchMaxShifts];
-  // BK3's update of (q, k): x += cxp p_k + cxr r0 (upd_x); p_k <- cpp p_k + cpr0 r0 + cpr1 r
-  // (upd_p), r0 being the residual kept by a deferring BK3 (one step: cxr = cpr0 = 0)
-  double cxp[kBatchMaxRhs * kBatchMaxShifts], cxr[kBatchMaxRhs * kBatchMaxShifts];
-  double cpp[kBatchMaxRhs * kBatchMaxShifts], cpr0[kBatchMaxRhs * kBatchMaxShifts];
-  double cpr1[kBatchMaxRhs * kBatchMaxShifts];
-  // the step a deferring BK3 left to the next one: a_k, zeta_k', b_k, took part, updated p_k
-  double d_a[kBatchMaxRhs * kBatchMaxShifts], d_z[kBatchMaxRhs * kBatchMaxShifts];
-  double d_b[kBatchMaxRhs * kBatchMaxShifts];
-  int d_act[kBatchMaxRhs * kBatchMaxShifts], d_upd[kBatchMaxRhs * kBatchMaxShifts];
-  // per right-hand side: BK3's mode (0 one step, 1 deferred, 2 two steps), a deferred step
-  // pending, and per phase (FP64, complex64) the shift-vector updates and kept-r passes
-  int mode[kBatchMaxRhs], two[kBatchMaxRhs];
+  // BK3's update of (q, k) (upd_x, upd_p): x += cx[0] p_k + sum_{i<m} cx[i+1] r_i and
+  // p_k <- cp[0] p_k + sum_{i<m} cp[i+1] r_i + cp[m+1] r, the r_i being the residuals
+  // kept by the m BK3s that deferred (one step: m = 0)
+  double cx[kMaxSteps][kBatchMaxRhs * kBatchMaxShifts];
+  double cp[kMaxSteps + 1][kBatchMaxRhs * kBatchMaxShifts];
+  // the deferred steps of (q, k) composed as in DeferState
+  double dcx[kMaxSteps][kBatchMaxRhs * kBatchMaxShifts];
+  double dcp[kMaxSteps][kBatchMaxRhs * kBatchMaxShifts];
+  int dact[kBatchMaxRhs * kBatchMaxShifts], dupd[kBatchMaxRhs * kBatchMaxShifts];
+  // per right-hand side: steps deferred so far, BK3's kept residuals to read (m) and the
+  // slot it keeps r in (-1: none), and per phase (FP64, complex64) the shift-vector
+  // updates and kept-r passes
+  int ndef[kBatchMaxRhs], m[kBatchMaxRhs], keep[kBatchMaxRhs];
   int n_upd[kBatchMaxRhs][2], n_kept[kBatchMaxRhs][2];
   // per system
   double s[kBatchMaxShifts];
@@ -395,8 +396,8 @@ struct BatchSys {
   double2* x;             // nrhs * ns * n (rhs-major, shift-major, caller order)
   double2 *r64, *p64, *t64, *pk64, *u64;   // rhs-interleaved n x RR; pk: (ns-1) blocks
   float2 *r32, *p32, *t32, *pk32;
-  void* rkeep;            // n x RR: r kept by a deferring BK3 (complex128, or complex64 in
-                          // the second phase)
+  void* rkeep[kMaxSteps - 1];  // n x RR each: residuals kept by deferring BK3s
+                               // (complex128, or complex64 in the second phase)
   BatchState* st;
   double* partial;
   unsigned* tickets;      // 8 counters
@@ -412,6 +413,7 @@ struct BatchArgs {
   int rr;                 // right-hand sides per system, padded (1, 2 or 4)
   int* active_systems;
   int defer_ok;           // 1: this iteration's BK3 may defer the shifted update
+  int steps;              // steps of the shifted update folded into one pass (1..kMaxSteps)
 };
 
 hipError_t launch_batch_init(const BatchArgs& a, hipStream_t s);

@@ -91,18 +91,19 @@ def test_batch_result_is_independent_of_companions(cuda):
         op.close()
 
 
+@pytest.mark.parametrize("steps", [2, 4])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_batch_two_steps_match_one_step(cuda, prec):
-    # the batch defers every other shifted update and folds two steps into one pass: the
+def test_batch_folded_steps_match_one_step(cuda, prec, steps):
+    # the batch defers shifted updates and folds up to `steps` of them into one pass: the
     # driving sequences, iteration counts and freezes are those of one step per
     # iteration, the solutions agree to rounding, and fewer bytes move
-    print(f"[gpu] batched two-step {prec}", flush=True)
+    print(f"[gpu] batched {steps} folded steps {prec}", flush=True)
     from paper_1102_2143_amd import solve_batched
     systems = _small_batch()
     ops = _ops(systems, cuda)
     bs = [p["b"] for p in systems]
     x1, i1, s1 = solve_batched(ops, bs, tol=1e-10, prec=prec, update_steps=1)
-    x2, i2, s2 = solve_batched(ops, bs, tol=1e-10, prec=prec, update_steps=2)
+    x2, i2, s2 = solve_batched(ops, bs, tol=1e-10, prec=prec, update_steps=steps)
     assert s1 == "ok" and s2 == "ok"
     for a, b in zip(i1, i2):
         assert a["iters"] == b["iters"]
