@@ -171,8 +171,8 @@ def cpu_baseline(prob, sample_iters, full_iters):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c1", choices=sorted(WORKLOAD_NAMES))
     ap.add_argument("--prec", default="both", choices=["fp64", "mixed", "both"],
                     help="both: time the FP64 plain solve and the mixed solve (the headline)")

@@ -206,12 +206,13 @@ def test_iteration_limit(c0, cuda):
     op.close()
 
 
-@pytest.mark.parametrize("fmt,limit", [("sell", 60), ("sell", 61), ("csr", 60), ("csr", 61)])
+@pytest.mark.parametrize("fmt,limit", [("sell", 60), ("sell", 61), ("sell", 62), ("sell", 63),
+                                       ("csr", 60), ("csr", 61)])
 def test_iteration_limit_in_the_complex64_phase(c0, cuda, fmt, limit):
     # the limit falls after the switch to complex64: the sequence stops there, and every
     # shift's residual is as small as the oracle's after as many iterations (up to the
-    # complex64 rounding of the unconverged iterates); an even and an odd limit end a
-    # deferred all-shift update at either point of its two-step cycle
+    # complex64 rounding of the unconverged iterates); consecutive limits end the
+    # sequence at every point of the folding cycle of the all-shift update
     op = _op(c0, cuda)
     op.set_shifts(c0["sigma"])
     x, info = op.solve(c0["b"], max_iter=limit, refine=False, prec="mixed", switch_tol=0.3,
