@@ -113,6 +113,23 @@ def test_mixed_early_switch_is_refined_to_tol(c0, cuda, switch_tol, fmt):
     op.close()
 
 
+@pytest.mark.parametrize("lanes", [4, 16, 32])
+def test_refinement_on_csr_at_every_lane_width(c0, cuda, lanes):
+    # an early switch leaves every shift above tol, so the FP64 refinement (residuals and
+    # batched CG on CSR with the given lanes per row) does the rest
+    op = _op(c0, cuda)
+    op.set_shifts(c0["sigma"])
+    x, info = op.solve(c0["b"], tol=1e-10, prec="mixed", switch_tol=1.0, format="csr",
+                       lanes=lanes)
+    assert info["status"] == "ok"
+    assert info["n_refined"] > 0
+    rho = np.array([np.linalg.norm(c0["b"] - c0["apply"](x.cpu().numpy()[k], s))
+                    for k, s in enumerate(c0["sigma"])]) / np.linalg.norm(c0["b"])
+    assert np.all(rho <= 1e-10)
+    assert np.allclose(rho, info["true_rel_res"], rtol=1e-3, atol=1e-15)
+    op.close()
+
+
 def test_mixed_herm_laplacian(cuda):
     rowptr, col, vals = W.laplacian7_csr((12, 10, 9), 51)
     n = 1080
