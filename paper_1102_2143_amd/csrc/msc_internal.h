@@ -91,7 +91,8 @@ struct SolveState {
   int smp_nact[kMaxSamples];
   int smp_m[kMaxSamples];
   // per phase (0: FP64, 1: complex64): x_j/p_j row updates performed (in units of n
-  // rows), heads that deferred their update, heads that applied two steps
+  // rows), heads that deferred their update, and passes over kept residuals (a deferring
+  // head writes one, an applying head reads the ones pending)
   int n_shift_upd[2];
   int n_defer[2];
   int n_two[2];

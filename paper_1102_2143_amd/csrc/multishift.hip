@@ -11,8 +11,8 @@
 //
 // On the sliced ELLPACK path an iteration is two kernels: the head (K3 of the previous
 // iteration, then K1 on the new direction, formed at each gathered column) and K2.
-// Every other head may defer the shifted part of K3; the next one applies both steps in
-// one pass over x_j and p_j.
+// A head may defer the shifted part of K3; a later one applies up to four composed steps
+// in one pass over x_j and p_j.
 //
 // The shift recurrences are the values forced by the collinearity r_j = zeta_j r:
 //   zeta' = zeta zeta_prev a_prev / (a b (zeta_prev - zeta) + zeta_prev a_prev (1 + s a)),
