@@ -37,6 +37,7 @@ WORKLOAD_NAMES = {
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
 KERNEL_NAMES = {("mixed", "head"): "k1_fused<float, true>", ("mixed", "K2"): "k2_sell<float>",
                 ("fp64", "head"): "k1_fused<double, true>", ("fp64", "K2"): "k2_sell<double>"}
+PHASE_NAMES = {"fp64": "FP64", "mixed": "complex64"}
 
 
 def measured_traffic(workload, prec, kernel):
@@ -245,19 +246,34 @@ def main():
         n, nnz = prob["n"], prob["vals"].size
         iters = infos[-1]["iters"]
         alg_bytes = float(np.mean([inf["alg_bytes"] for inf in infos]))
-        samples = sum(inf["kernel_samples"] for inf in infos)
-        kms = np.sum([inf["kernel_ms"] for inf in infos], axis=0)
-        kby = np.sum([inf["kernel_bytes"] for inf in infos], axis=0)
+        # a mixed solve reports its FP64 phase apart from its complex64 phase; each phase
+        # launches one of each iteration kernel per iteration
+        it64 = float(np.mean([inf["iters_fp64"] for inf in infos]))
+        itall = float(np.mean([inf["iters"] for inf in infos]))
+        if prec == "mixed":
+            phases = [("fp64", "fp64_kernel", it64), ("mixed", "kernel", itall - it64)]
+        else:
+            phases = [("fp64", "kernel", itall)]
         kernels = {}
-        if samples > 0:
+        for phase, key, launches in phases:
+            samples = sum(inf[key + "_samples"] for inf in infos)
+            if samples == 0:
+                continue
+            kms = np.sum([inf[key + "_ms"] for inf in infos], axis=0)
+            kby = np.sum([inf[key + "_bytes"] for inf in infos], axis=0)
             # slot 2 (a separate update kernel) is empty when the update is fused into the head
             names = ["head", "K2"] if kms[2] == 0 else ["K1", "K2", "K3"]
             for k, nm in enumerate(names):
                 # algorithmic bytes of the sampled launches (the library counts the shifts
-                # active at each sampled iteration) over their measured durations
-                kernels[nm] = {"avg_us": round(1e3 * kms[k] / samples, 2),
-                               "alg_bytes": round(kby[k] / samples),
-                               "gbs": round(kby[k] / (kms[k] * 1e-3) / 1e9, 1)}
+                # active at each sampled iteration) over their measured durations; the
+                # kernel's time per step is its average duration times the phase's launches
+                avg_us = 1e3 * kms[k] / samples
+                kernels[f"{PHASE_NAMES[phase]} {nm}"] = {
+                    "phase": phase, "kernel": nm, "avg_us": round(avg_us, 2),
+                    "alg_bytes": round(kby[k] / samples),
+                    "gbs": round(kby[k] / (kms[k] * 1e-3) / 1e9, 1),
+                    "launches_per_step": round(launches, 1),
+                    "ms_per_step": round(1e-3 * avg_us * launches, 3)}
         return dict(prec=prec, wall=wall, ok=ok, iters=iters, infos=infos,
                     value=ns * args.steps / wall, ms_per_step=1e3 * wall / args.steps,
                     eff_gbs=alg_bytes / (wall / args.steps) / 1e9, kernels=kernels,
@@ -270,15 +286,18 @@ def main():
     kernels = main_path["kernels"]
     roofline = None
     if kernels:
-        dom = max(kernels, key=lambda nm: kernels[nm]["avg_us"])
+        # the dominant kernel is the one with the most GPU time per step
+        dom = max(kernels, key=lambda nm: kernels[nm]["ms_per_step"])
         ach = kernels[dom]["gbs"]
-        traffic, kname = measured_traffic(args.workload, main_path["prec"], dom)
+        traffic, kname = measured_traffic(args.workload, kernels[dom]["phase"],
+                                          kernels[dom]["kernel"])
         roofline = {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                     "frac": round(ach / PEAK_HBM_GBS, 4),
                     "traffic": None if traffic is None else round(traffic),
                     "kernel": dom, "kernel_name": kname,
                     "alg_bytes": kernels[dom]["alg_bytes"],
-                    "kernel_avg_us": kernels[dom]["avg_us"]}
+                    "kernel_avg_us": kernels[dom]["avg_us"],
+                    "kernel_ms_per_step": kernels[dom]["ms_per_step"]}
     ns = prob["sigma"].size
     n, nnz = prob["n"], prob["vals"].size
     iters = main_path["iters"]

@@ -86,8 +86,8 @@ typedef struct {
     int32_t verify;          /* compute FP64 true residuals at the end              (1)    */
     int32_t timing;          /* time the iteration kernels with HIP events on the first
                                 max(2, update_steps) of every timing iterations
-                                (complex64 phase only in a mixed solve; at most 256
-                                samples), 0 = off                                  (0)    */
+                                (both phases of a mixed solve, reported apart; at
+                                most 256 samples), 0 = off                         (0)    */
     int32_t max_grid;        /* cap on workgroups per iteration kernel (<= 2048),
                                 0 = automatic                                       (0)    */
     int32_t format;          /* msc_format: matrix copy the iteration SpMVs read     (0)    */
@@ -122,6 +122,12 @@ typedef struct {
     double kernel_bytes[3];  /* algorithmic HBM bytes of the same sampled launches, summed
                                 like kernel_ms (each array touched once, gathers once;
                                 the head's depends on the shifts active at its iteration) */
+    double fp64_kernel_ms[3];    /* mixed solve: kernel_ms of the launches sampled in its
+                                    FP64 phase (kernel_ms holds its complex64 phase);
+                                    0 otherwise                                        */
+    double fp64_kernel_bytes[3]; /* mixed solve: kernel_bytes of the same launches       */
+    int32_t fp64_kernel_samples; /* mixed solve: sampled iterations of the FP64 phase    */
+    int32_t reserved;            /* 0                                                    */
 } msc_info;
 
 /* Fill *p with the defaults listed above. */

@@ -64,6 +64,10 @@ class Info(ctypes.Structure):
         ("kernel_samples", ctypes.c_int32),
         ("iters_fp64", ctypes.c_int32),
         ("kernel_bytes", ctypes.c_double * 3),
+        ("fp64_kernel_ms", ctypes.c_double * 3),
+        ("fp64_kernel_bytes", ctypes.c_double * 3),
+        ("fp64_kernel_samples", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 

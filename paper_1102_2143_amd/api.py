@@ -180,6 +180,9 @@ def _info_dict(st, info, rel, fi):
                 alg_bytes=float(info.alg_bytes), kernel_ms=np.array(info.kernel_ms[:]),
                 kernel_samples=int(info.kernel_samples),
                 kernel_bytes=np.array(info.kernel_bytes[:]),
+                fp64_kernel_ms=np.array(info.fp64_kernel_ms[:]),
+                fp64_kernel_samples=int(info.fp64_kernel_samples),
+                fp64_kernel_bytes=np.array(info.fp64_kernel_bytes[:]),
                 iters_fp64=int(info.iters_fp64))
 
 

@@ -245,6 +245,14 @@ struct EventPool {
   }
 };
 
+// The kernel timing fields of a report, cleared (calls that sample nothing leave them 0).
+void clear_timing(msc_info& I) {
+  for (int k = 0; k < 3; ++k)
+    I.kernel_ms[k] = I.kernel_bytes[k] = I.fp64_kernel_ms[k] = I.fp64_kernel_bytes[k] = 0.0;
+  I.kernel_samples = I.fp64_kernel_samples = 0;
+  I.reserved = 0;
+}
+
 msc_status run_multishift(msc_op op, const double* d_b, double* d_x, const msc_params& prm,
                           msc_info* info, hipStream_t s, double tol_stop, int prec,
                           std::vector<double>* rel_out, int* iters_out, int* status_out,
@@ -323,11 +331,9 @@ msc_status run_multishift(msc_op op, const double* d_b, double* d_x, const msc_p
     for (int g = 0; g < G; ++g) {
       hipEvent_t* ev = nullptr;
       cur->sample = -1;
-      // a mixed solve is timed in its complex64 phase only; consecutive launches are
-      // sampled in runs as long as a folding cycle (heads that defer and the one that
-      // applies the folded steps)
+      // consecutive launches are sampled in runs as long as a folding cycle (heads that
+      // defer and the one that applies the folded steps), in both phases of a mixed solve
       if (prm.timing > 0 && launched % prm.timing < std::max(2, prm.update_steps) &&
-          (!mixed || phase == MSC_PREC_MIXED) &&
           int(sample_launch.size()) < kMaxSamples) {
         ev = pool.next();
         if (!ev) {
@@ -384,9 +390,7 @@ msc_status run_multishift(msc_op op, const double* d_b, double* d_x, const msc_p
   const RotState& fin = h.rot[launched & 1];  // state after the last launched iteration
   const int iters_fp64 = iter_at_switch >= 0 ? iter_at_switch : fin.iter;
   if (info) {
-    for (double& v : info->kernel_ms) v = 0.0;
-    for (double& v : info->kernel_bytes) v = 0.0;
-    info->kernel_samples = 0;
+    clear_timing(*info);
     // only iterations that did work are counted (the loop runs a little past the halt)
     const int first = launched_at_switch >= 0 ? launched_at_switch : 0;
     const int useful_launches = first + (fin.iter - (iter_at_switch >= 0 ? iter_at_switch : 0));
@@ -396,22 +400,26 @@ msc_status run_multishift(msc_op op, const double* d_b, double* d_x, const msc_p
     for (size_t q = 0; q < pool.groups.size(); ++q) {
       const int L = sample_launch[q];
       if (L >= useful_launches) continue;
+      // the FP64 phase of a mixed solve is reported apart from its complex64 phase
+      const bool ph32 = launched_at_switch >= 0 && L >= launched_at_switch;
+      const bool apart = mixed && !ph32;
+      double* kms = apart ? info->fp64_kernel_ms : info->kernel_ms;
+      double* kby = apart ? info->fp64_kernel_bytes : info->kernel_bytes;
       for (int k = 0; k < slots; ++k) {
         float ms = 0.f;
         HIP_TRY(hipEventElapsedTime(&ms, pool.groups[q][2 * k], pool.groups[q][2 * k + 1]));
-        info->kernel_ms[k] += ms;
+        kms[k] += ms;
       }
       // the head's update mode and the shifts it listed, as recorded by the head itself
-      const bool ph32 = launched_at_switch >= 0 && L >= launched_at_switch;
       const bool pending = !(L == 0 || (ph32 && L == launched_at_switch));
       const int act = h.smp_nact[q];
       const int kept = h.smp_mode[q] == 1 ? 1 : h.smp_m[q];
-      const KernelBytes kb = kernel_bytes(op->kind, ph32 ? MSC_PREC_MIXED : prec, nn, nz, nzh,
-                                          double(act), pending, ib, ibh, kept);
-      info->kernel_bytes[0] += a64.sell ? kb.head : kb.k1;
-      info->kernel_bytes[1] += kb.k2;
-      if (!a64.sell) info->kernel_bytes[2] += kb.upd;
-      info->kernel_samples += 1;
+      const KernelBytes kb = kernel_bytes(op->kind, ph32 ? MSC_PREC_MIXED : MSC_PREC_FP64, nn,
+                                          nz, nzh, double(act), pending, ib, ibh, kept);
+      kby[0] += a64.sell ? kb.head : kb.k1;
+      kby[1] += kb.k2;
+      if (!a64.sell) kby[2] += kb.upd;
+      (apart ? info->fp64_kernel_samples : info->kernel_samples) += 1;
     }
   }
 
@@ -1166,8 +1174,7 @@ struct BatchRun {
               const int fi = h.freeze_iter[q * kBatchMaxShifts + k];
               I.freeze_iter[h.orig[k]] = (k == 0 || fi < 0) ? h.iter[q] : fi;
             }
-          for (double& v : I.kernel_ms) v = 0.0;
-          I.kernel_samples = 0;
+          clear_timing(I);
           // algorithmic bytes: this system's share, matrix read once for all its rhs; the
           // shift-vector updates and kept-r passes as counted by BK2 per phase
           const int it = h.iter[q], i64 = std::min(I.iters_fp64, it);
@@ -1595,6 +1602,7 @@ msc_status msc_solve_adjoint(msc_op op, const double* d_g, const double* d_x, do
       for (int k = 0; k < ns; ++k) info->true_rel_res[k] = rel[k];
     if (info->freeze_iter)
       for (int k = 0; k < ns; ++k) info->freeze_iter[k] = -1;
+    clear_timing(*info);
     info->alg_bytes = bytes;
     info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   }

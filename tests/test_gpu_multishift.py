@@ -502,6 +502,26 @@ def test_kernel_timing_samples(c0, cuda, fmt):
     op.close()
 
 
+@pytest.mark.parametrize("fmt", ["sell", "csr"])
+def test_kernel_timing_both_phases(c0, cuda, fmt):
+    # a mixed solve samples both phases and reports its FP64 phase apart; the FP64 phase's
+    # heads and K2 move more bytes per launch than the complex64 phase's; an FP64 solve
+    # leaves the FP64-phase fields empty
+    op = _op(c0, cuda)
+    op.set_shifts(c0["sigma"])
+    _, im = op.solve(c0["b"], tol=1e-10, prec="mixed", timing=4, format=fmt)
+    assert im["status"] == "ok" and 0 < im["iters_fp64"] < im["iters"]
+    assert im["kernel_samples"] > 0 and im["fp64_kernel_samples"] > 0
+    assert np.all(im["fp64_kernel_ms"][:2] > 0) and np.all(im["kernel_ms"][:2] > 0)
+    per64 = im["fp64_kernel_bytes"][1] / im["fp64_kernel_samples"]
+    per32 = im["kernel_bytes"][1] / im["kernel_samples"]
+    assert per64 > per32
+    _, i64 = op.solve(c0["b"], tol=1e-10, prec="fp64", timing=4, format=fmt)
+    assert i64["fp64_kernel_samples"] == 0 and np.all(i64["fp64_kernel_ms"] == 0)
+    assert i64["kernel_samples"] > 0
+    op.close()
+
+
 # ---- full-size FP64 case: 16^4 ------------------------------------------------------------
 def test_c1_fp64_full_size(cuda):
     print("[gpu] c1 16^4 fp64 solve", flush=True)

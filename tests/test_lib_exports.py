@@ -43,7 +43,7 @@ def test_params_default_and_struct_layout():
     assert p.poll_every == 16 and p.verify == 1
     assert p.update_steps == 4 and p.reserved == 0
     assert ctypes.sizeof(_lib.Params) == 80  # update_steps and a reserved word appended
-    assert ctypes.sizeof(_lib.Info) == 104  # kernel_bytes[3] appended
+    assert ctypes.sizeof(_lib.Info) == 160  # FP64-phase timing fields appended
 
 
 def test_null_arguments_are_rejected_without_gpu_work():
