@@ -60,6 +60,26 @@ def measured_traffic(workload, prec, kernel):
         return None, name
 
 
+def copy_ceiling(dev, nbytes, reps=20):
+    """GB/s of a device-to-device copy that reads nbytes/2 and writes nbytes/2, the mean
+    of reps copies timed with events on torch's stream (after 3 untimed ones)."""
+    import torch
+    half = max(1, int(nbytes) // 8)
+    src = torch.ones(half, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / reps
+    del src, dst
+    return 2.0 * 4.0 * half / (ms * 1e-3) / 1e9
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -186,6 +206,8 @@ def main():
                     help="skip the 64-system batched solve reported beside the main line")
     ap.add_argument("--no-paper-workload", action="store_true",
                     help="skip the paper's Table 1 workload (2-D Poisson) reported beside it")
+    ap.add_argument("--no-copy-ceiling", action="store_true",
+                    help="skip the copy-kernel ceiling beside the roofline figures")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="copy this many MiB once before timing (a kernel of known traffic "
                          "that calibrates FETCH_SIZE / WRITE_SIZE counters)")
@@ -298,6 +320,15 @@ def main():
                     "alg_bytes": kernels[dom]["alg_bytes"],
                     "kernel_avg_us": kernels[dom]["avg_us"],
                     "kernel_ms_per_step": kernels[dom]["ms_per_step"]}
+        if not args.no_copy_ceiling:
+            same = copy_ceiling(dev, kernels[dom]["alg_bytes"])
+            big = copy_ceiling(dev, 2 << 30)
+            roofline["copy_ceiling"] = {
+                "same_bytes_gbs": round(same, 1), "2GiB_gbs": round(big, 1),
+                "frac_of_same_bytes": round(ach / same, 4),
+                "note": "device-to-device copy moving the kernel's algorithmic bytes (half "
+                        "read, half written; a working set of that size stays partly in "
+                        "the last-level cache, as the kernel's does), and 2 GiB beyond it"}
     ns = prob["sigma"].size
     n, nnz = prob["n"], prob["vals"].size
     iters = main_path["iters"]

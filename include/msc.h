@@ -87,7 +87,8 @@ typedef struct {
     int32_t timing;          /* time the iteration kernels with HIP events on the first
                                 max(2, update_steps) of every timing iterations
                                 (both phases of a mixed solve, reported apart; at
-                                most 256 samples), 0 = off                         (0)    */
+                                most 256 samples, at most 128 of them in the FP64
+                                phase of a mixed solve), 0 = off                  (0)    */
     int32_t max_grid;        /* cap on workgroups per iteration kernel (<= 2048),
                                 0 = automatic                                       (0)    */
     int32_t format;          /* msc_format: matrix copy the iteration SpMVs read     (0)    */

@@ -332,9 +332,11 @@ msc_status run_multishift(msc_op op, const double* d_b, double* d_x, const msc_p
       hipEvent_t* ev = nullptr;
       cur->sample = -1;
       // consecutive launches are sampled in runs as long as a folding cycle (heads that
-      // defer and the one that applies the folded steps), in both phases of a mixed solve
+      // defer and the one that applies the folded steps), in both phases of a mixed solve;
+      // the FP64 phase of a mixed solve takes at most half of the records
+      const int cap = mixed && phase == MSC_PREC_FP64 ? kMaxSamples / 2 : kMaxSamples;
       if (prm.timing > 0 && launched % prm.timing < std::max(2, prm.update_steps) &&
-          int(sample_launch.size()) < kMaxSamples) {
+          int(sample_launch.size()) < cap) {
         ev = pool.next();
         if (!ev) {
           set_error("msc_solve: event creation failed");
@@ -400,6 +402,8 @@ msc_status run_multishift(msc_op op, const double* d_b, double* d_x, const msc_p
     for (size_t q = 0; q < pool.groups.size(); ++q) {
       const int L = sample_launch[q];
       if (L >= useful_launches) continue;
+      // FP64-phase launches between the switch request and the host's switch did no work
+      if (launched_at_switch >= 0 && L < launched_at_switch && L >= iter_at_switch) continue;
       // the FP64 phase of a mixed solve is reported apart from its complex64 phase
       const bool ph32 = launched_at_switch >= 0 && L >= launched_at_switch;
       const bool apart = mixed && !ph32;

@@ -519,6 +519,11 @@ def test_kernel_timing_both_phases(c0, cuda, fmt):
     _, i64 = op.solve(c0["b"], tol=1e-10, prec="fp64", timing=4, format=fmt)
     assert i64["fp64_kernel_samples"] == 0 and np.all(i64["fp64_kernel_ms"] == 0)
     assert i64["kernel_samples"] > 0
+    # every launch sampled: the FP64 phase stops at half of the 256 records, so the
+    # complex64 phase still gets its share
+    _, ia = op.solve(c0["b"], tol=1e-10, prec="mixed", timing=1, format=fmt)
+    assert ia["fp64_kernel_samples"] == min(ia["iters_fp64"], 128)
+    assert ia["kernel_samples"] > 0
     op.close()
 
 
