@@ -26,6 +26,7 @@ from .gradient import (
     closed_form_gradient,
     adjoint_gradient,
     fd_gradient,
+    fd_directional,
     second_order_loss,
 )
 
@@ -43,5 +44,6 @@ __all__ = [
     "closed_form_gradient",
     "adjoint_gradient",
     "fd_gradient",
+    "fd_directional",
     "second_order_loss",
 ]

@@ -148,3 +148,19 @@ def fd_gradient(kind, rowptr, col, vals, n, b, sigma, c, nz, h=1e-6, tol=1e-14,
             parts.append((loss(vp) - loss(vm)) / (2.0 * h))
         out[t] = parts[0] + 1j * parts[1]
     return out
+
+
+def fd_directional(kind, rowptr, col, vals, n, b, sigma, c, delta, h=1e-6, tol=1e-14,
+                   max_iter=100000):
+    """Central difference of L = sum_k c_k Re(b^H x_k) along a direction of all stored
+    entries: (L(v + h delta) - L(v - h delta)) / (2h), which equals
+    sum_e Re(conj(grad_e) delta_e) in the convention above, to O(h^2)."""
+    vals = np.asarray(vals, dtype=np.complex128)
+    delta = np.asarray(delta, dtype=np.complex128)
+
+    def loss(v):
+        apply = shifted_apply(kind, rowptr, col, v, n)
+        sol = cg_m(apply, b, sigma, tol=tol, max_iter=max_iter)
+        return second_order_loss(kind, rowptr, col, v, n, b, sigma, c, sol["x"])
+
+    return (loss(vals + h * delta) - loss(vals - h * delta)) / (2.0 * h)

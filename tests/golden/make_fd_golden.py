@@ -2,9 +2,11 @@
 
 Calls only the oracle (test infrastructure): central differences with h = 1e-6 of the
 second-order functional L~ = sum_k c_k Re(b^H x_k + x_k^H r_k) (x_k from the FP64 CG-M
-oracle at tol 1e-14), for the real and imaginary part of 32 seeded stored entries of M.
+oracle at tol 1e-14), for the real and imaginary part of 32 seeded stored entries of M;
+with the argument ``directional``, the 16^4 fixture: one central difference along a seeded
+direction over every stored entry.
 The loss is the rational-approximation form sum_k c_k Re(b^H x_k) of the shifted family
-(Section 2 of the paper).  Run:  python tests/golden/make_fd_golden.py
+(Section 2 of the paper).  Run:  python tests/golden/make_fd_golden.py [directional]
 """
 import json
 import os
@@ -35,5 +37,28 @@ def main(name="c3", out="fd_c3_8x4.json"):
     print(f"wrote {out} in {time.time() - t0:.0f}s")
 
 
+def main_directional(name="c3_16", out="fd_c3_16x4_dir.json"):
+    """The 16^4 gradient workload: one central difference of L~ along a seeded complex
+    Gaussian direction over every stored entry of M (two oracle solves)."""
+    p = W.make_config(name)
+    cfg = p["cfg"]
+    t0 = time.time()
+    d = O.fd_directional("mhm", p["rowptr"], p["col"], p["vals"], p["n"], p["b"], p["sigma"],
+                         p["c"], p["fd_dir"], h=cfg["fd_h"], tol=1e-14)
+    rec = dict(config=name, dims=list(cfg["dims"]), mass=cfg["mass"], shifts=list(cfg["shifts"]),
+               seeds=dict(links=cfg["seed_links"], b=cfg["seed_b"], c=cfg["seed_c"],
+                          direction=cfg["seed_dir"]),
+               h=cfg["fd_h"], solve_tol=1e-14, directional_derivative=float(d),
+               seconds=round(time.time() - t0, 1),
+               source="oracle.fd_directional (central difference of the second-order "
+                      "functional along workloads.gaussian_rhs(nnz, seed_dir))")
+    with open(os.path.join(HERE, out), "w") as f:
+        json.dump(rec, f, indent=1)
+    print(f"wrote {out} in {time.time() - t0:.0f}s")
+
+
 if __name__ == "__main__":
-    main()
+    if len(sys.argv) > 1 and sys.argv[1] == "directional":
+        main_directional()
+    else:
+        main()

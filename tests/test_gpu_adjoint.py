@@ -129,3 +129,27 @@ def test_c3_8x4_against_finite_differences(cuda):
     # cannot be held to a relative bar of their own
     assert np.all(np.abs(comp_got - comp_fd) <= 1e-6 * np.abs(comp_fd).max())
     op.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_c3_16x4_directional_derivative(cuda, prec):
+    # the 16^4 gradient workload: Re(sum conj(grad) delta) of the adjoint's gradient along
+    # the seeded direction over every stored entry, against the oracle's central
+    # difference of the loss along that direction (tests/golden/fd_c3_16x4_dir.json)
+    path = os.path.join(GOLDEN, "fd_c3_16x4_dir.json")
+    if not os.path.exists(path):
+        pytest.fail("missing golden fixture: run tests/golden/make_fd_golden.py directional")
+    rec = json.load(open(path))
+    print(f"[gpu] adjoint 16^4 {prec} vs oracle directional finite difference", flush=True)
+    p = W.make_config("c3_16")
+    op = _op(p, cuda)
+    x, info = op.solve(p["b"], tol=1e-12, prec=prec)
+    assert info["status"] == "ok", info
+    g = p["c"][:, None] * p["b"][None, :]
+    gb, gv, ainfo = op.solve_adjoint(g, x, tol=1e-12, prec=prec)
+    assert ainfo["status"] == "ok", ainfo
+    got = float(np.real(np.vdot(gv.cpu().numpy(), p["fd_dir"])))
+    fd = rec["directional_derivative"]
+    print(f"[gpu] adjoint 16^4 {prec}: {got:.12e} vs fd {fd:.12e}", flush=True)
+    assert abs(got - fd) <= 1e-6 * abs(fd)
+    op.close()

@@ -124,6 +124,40 @@ def test_fd_matches_dense_autograd(c3_4):
     assert _rel(fd, gv_d[nz]) < 1e-6
 
 
+def test_fd_directional_matches_dense_autograd(c3_4):
+    """One central difference along a random direction of every stored entry equals
+    Re(sum conj(grad) delta) of the dense autograd gradient; a wrong sign or a dropped
+    conjugate in either would show up here."""
+    p = c3_4
+    delta = W.gaussian_rhs(p["vals"].size, 6004)
+    d = O.fd_directional("mhm", p["rowptr"], p["col"], p["vals"], p["n"], p["b"], p["sigma"],
+                         p["c"], delta, h=1e-6)
+    g = p["c"][:, None] * p["b"][None, :]
+    gv_d, _ = O.dense_reference_gradient("mhm", p["rowptr"], p["col"], p["vals"], p["n"],
+                                         p["b"], p["sigma"], g)
+    ref = float(np.real(np.vdot(gv_d, delta)))
+    assert abs(d - ref) <= 1e-6 * abs(ref)
+    # the imaginary direction probes the other half of the convention
+    d_i = O.fd_directional("mhm", p["rowptr"], p["col"], p["vals"], p["n"], p["b"], p["sigma"],
+                           p["c"], 1j * delta, h=1e-6)
+    ref_i = float(np.real(np.vdot(gv_d, 1j * delta)))
+    assert abs(d_i - ref_i) <= 1e-6 * abs(ref_i)
+
+
+def test_fd_directional_fixture_16x4_matches_its_recipe():
+    """The stored 16^4 directional fixture names the seeds and step of its recipe."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                        "fd_c3_16x4_dir.json")
+    rec = json.load(open(path))
+    cfg = W.CONFIGS["c3_16"]
+    assert rec["seeds"] == dict(links=cfg["seed_links"], b=cfg["seed_b"], c=cfg["seed_c"],
+                                direction=cfg["seed_dir"])
+    assert rec["h"] == cfg["fd_h"] and rec["dims"] == list(cfg["dims"])
+    assert np.isfinite(rec["directional_derivative"])
+
+
 def test_closed_form_matches_fd_fixture_8x4():
     """The oracle's closed-form gradient at 8^4 against the stored central differences
     (tests/golden/fd_c3_8x4.json, written by make_fd_golden.py from the oracle's FD)."""

@@ -27,7 +27,8 @@ CONFIGS = {
     "c3": dict(dims=(8, 8, 8, 8), mass=0.1, shifts=(1e-4, 1.0, 10), seed_links=1003,
                seed_b=2003, seed_c=3003, seed_nz=4003, n_nz=32, fd_h=1e-6, tol=1e-10),
     "c3_16": dict(dims=(16, 16, 16, 16), mass=0.1, shifts=(1e-4, 1.0, 10), seed_links=1003,
-                  seed_b=2003, seed_c=3003, seed_nz=4003, n_nz=32, fd_h=1e-6, tol=1e-10),
+                  seed_b=2003, seed_c=3003, seed_nz=4003, n_nz=32, fd_h=1e-6, tol=1e-10,
+                  seed_dir=6003),
     "c3_4": dict(dims=(4, 4, 4, 4), mass=0.1, shifts=(1e-4, 1.0, 10), seed_links=1003,
                  seed_b=2003, seed_c=3003, seed_nz=4003, n_nz=32, fd_h=1e-6, tol=1e-10),
     "c4": dict(stag_dims=((4, 4, 4, 4), (6, 6, 6, 6), (8, 8, 8, 8), (12, 12, 12, 12)),
@@ -85,4 +86,7 @@ def make_config(name: str):
         prob["c"] = rng_c.uniform(0.0, 1.0, size=cfg["shifts"][2])
         rng_nz = np.random.default_rng(cfg["seed_nz"])
         prob["fd_nz"] = np.sort(rng_nz.choice(prob["vals"].size, size=cfg["n_nz"], replace=False))
+        if "seed_dir" in cfg:
+            # a direction over every stored entry for a directional finite difference
+            prob["fd_dir"] = gaussian_rhs(prob["vals"].size, cfg["seed_dir"])
     return prob
