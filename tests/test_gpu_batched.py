@@ -148,3 +148,35 @@ def test_c4_full_batch(cuda):
         assert np.all(rho / np.linalg.norm(p["b"][1]) <= 1e-10)
     for op in ops:
         op.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_batch_at_maximum_shifts_and_rhs(cuda, prec):
+    # 16 shifts and 4 right-hand sides, the most a batched system takes (17 shifts are
+    # rejected), beside a smaller system; every (system, rhs) against the oracle.  Mixed
+    # runs at tol 1e-12 against the oracle at 1e-13 (solution error <= kappa * residual)
+    from paper_1102_2143_amd import solve_batched, MscError
+    print(f"[gpu] batched max shifts and rhs {prec}", flush=True)
+    big = W.staggered_problem((4, 4, 4, 6), 0.1, 710, 810, (1e-4, 10.0, 16), nrhs=4)
+    small = W.staggered_problem((4, 4, 4, 4), 0.1, 711, 811, (1e-3, 1.0, 3), nrhs=1)
+    systems = [big, small]
+    ops = _ops(systems, cuda)
+    tol, otol = (1e-10, 1e-10) if prec == "fp64" else (1e-12, 1e-13)
+    xs, infos, status = solve_batched(ops, [p["b"] for p in systems], tol=tol, prec=prec)
+    assert status == "ok", [i["status"] for i in infos]
+    t = 0
+    for s, p in enumerate(systems):
+        ap = O.shifted_apply(p["kind"], p["rowptr"], p["col"], p["vals"], p["n"])
+        bs = np.atleast_2d(p["b"])
+        for q in range(bs.shape[0]):
+            ref = O.cg_m(ap, bs[q], p["sigma"], tol=otol)
+            info = infos[t]
+            t += 1
+            assert np.all(info["true_rel_res"] <= tol), (s, q, info["true_rel_res"])
+            assert np.all(_rel(xs[s][q].cpu().numpy(), ref["x"]) <= 1e-8), (s, q)
+    over = W.staggered_problem((4, 4, 4, 4), 0.1, 712, 812, (1e-4, 1.0, 17), nrhs=1)
+    op17 = _ops([over], cuda)
+    with pytest.raises(MscError):
+        solve_batched(op17, [over["b"]], tol=1e-10, prec=prec)
+    for op in ops + op17:
+        op.close()

@@ -550,3 +550,26 @@ def test_c1_fp64_full_size(cuda):
     ref_k = O.cg(ap, p["b"], shift=float(p["sigma"][k]), tol=1e-12)["x"]
     assert _rel(xg[k], ref_k) <= 1e-8
     op.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_maximum_shift_count(c0, cuda, prec):
+    # 64 shifts, the most one solve takes (65 is rejected), against the oracle: FP64 on the
+    # same Krylov path at the same tol; mixed at tol 1e-12 against the oracle at 1e-13 so
+    # that the solution error (<= kappa * residual) stays below the 1e-8 bar
+    from paper_1102_2143_amd import MscError
+    print(f"[gpu] c0 64 shifts {prec}", flush=True)
+    sigma = W.logspace_shifts(1e-4, 10.0, 64)
+    op = _op(c0, cuda)
+    op.set_shifts(sigma)
+    tol, otol = (1e-10, 1e-10) if prec == "fp64" else (1e-12, 1e-13)
+    x, info = op.solve(c0["b"], tol=tol, prec=prec)
+    assert info["status"] == "ok"
+    assert np.all(info["true_rel_res"] <= tol)
+    ref = O.cg_m(c0["apply"], c0["b"], sigma, tol=otol)
+    assert np.all(_rel(x.cpu().numpy(), ref["x"]) <= 1e-8)
+    if prec == "fp64":
+        assert abs(info["iters"] - ref["iters"]) <= 2
+    with pytest.raises(MscError):
+        op.set_shifts(W.logspace_shifts(1e-4, 10.0, 65))
+    op.close()
