@@ -60,6 +60,12 @@ def measured_traffic(workload, prec, kernel):
         return None, name
 
 
+def dominant_kernel(kernels):
+    """The kernel with the most GPU time per step: its average duration times its phase's
+    launches (a mixed solve lists its FP64-phase and complex64-phase kernels apart)."""
+    return max(kernels, key=lambda nm: kernels[nm]["ms_per_step"])
+
+
 def copy_ceiling(dev, nbytes, reps=20):
     """GB/s of a device-to-device copy that reads nbytes/2 and writes nbytes/2, the mean
     of reps copies timed with events on torch's stream (after 3 untimed ones)."""
@@ -213,7 +219,7 @@ def main():
                          "that calibrates FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
               "(the solve would shard by lattice rows with a halo exchange)",
               file=sys.stderr)
         sys.exit(2)
@@ -308,8 +314,7 @@ def main():
     kernels = main_path["kernels"]
     roofline = None
     if kernels:
-        # the dominant kernel is the one with the most GPU time per step
-        dom = max(kernels, key=lambda nm: kernels[nm]["ms_per_step"])
+        dom = dominant_kernel(kernels)
         ach = kernels[dom]["gbs"]
         traffic, kname = measured_traffic(args.workload, kernels[dom]["phase"],
                                           kernels[dom]["kernel"])

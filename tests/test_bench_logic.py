@@ -1,0 +1,48 @@
+"""Host logic of bench.py (no GPU): the roofline kernel's choice, the digest that keeps
+counter traffic tied to the kernel sources it was measured on, and the one-GPU limit."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_dominant_kernel_is_the_most_time_per_step():
+    # the complex64 head is the slowest launch, but the FP64 head runs more of them
+    kernels = {
+        "FP64 head": {"avg_us": 23.8, "ms_per_step": 6.96},
+        "FP64 K2": {"avg_us": 17.3, "ms_per_step": 5.06},
+        "complex64 head": {"avg_us": 30.0, "ms_per_step": 5.90},
+        "complex64 K2": {"avg_us": 11.9, "ms_per_step": 4.09},
+    }
+    assert bench.dominant_kernel(kernels) == "FP64 head"
+    kernels["complex64 head"]["ms_per_step"] = 7.5
+    assert bench.dominant_kernel(kernels) == "complex64 head"
+
+
+def test_traffic_is_reported_only_for_the_measured_sources(tmp_path, monkeypatch):
+    data = json.load(open(bench.TRAFFIC_FILE))
+    name = bench.KERNEL_NAMES[("fp64", "head")]
+    ent = data["workloads"]["c1"][name]
+    want = 1024.0 * (ent["fetch_kib"] * data["fetch_scale"] + ent["write_kib"] * data["write_scale"])
+    got, kname = bench.measured_traffic("c1", "fp64", "head")
+    assert kname == name and got == pytest.approx(want)
+    # a digest that no longer matches the kernel sources turns the figure off
+    data["kernel_source_sha256"] = "0" * 64
+    stale = tmp_path / "hbm_traffic.json"
+    stale.write_text(json.dumps(data))
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(stale))
+    got, kname = bench.measured_traffic("c1", "fp64", "head")
+    assert got is None and kname == name
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode != 0
+    assert "one GPU" in (r.stdout + r.stderr) or "1 GPU" in (r.stdout + r.stderr)
