@@ -206,7 +206,8 @@ def main():
     ap.add_argument("--timing", type=int, default=128,
                     help="time the kernels of a run of consecutive iterations (one folding "
                          "cycle of the shift update) out of every k with dispatch events")
-    ap.add_argument("--cpu-sample-iters", type=int, default=60)
+    ap.add_argument("--cpu-sample-iters", type=int, default=320,
+                    help="oracle iterations timed for cpu_baseline (about 10 s of one core)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 64-system batched solve reported beside the main line")
