@@ -15,7 +15,8 @@ Contents (each function cites the passage of the paper it follows):
                             closed form.
 * :mod:`oracle.gradient` -- reference gradients of L = sum_k Re(g_k^H x_k): dense
                             autograd, the closed form for g_k = c_k b, and central
-                            finite differences of a second-order functional.
+                            finite differences of a second-order functional (per
+                            stored entry, or along one direction of all of them).
 """
 from .operators import csr_matrix_of, shifted_apply, adjoint_csr
 from .cgm import cg_m
