@@ -1,0 +1,40 @@
+"""GPU: one short bench.py run in a child process, its JSON line against the contract the
+benchmark reports on (keys, units, the roofline and CPU-baseline objects)."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+pytestmark = pytest.mark.gpu
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_bench_line_keeps_the_contract(cuda):
+    print("[gpu] bench.py --steps 2 --warmup 1 (child process)", flush=True)
+    cmd = [sys.executable, os.path.join(ROOT, "bench.py"), "--steps", "2", "--warmup", "1",
+           "--no-batch", "--no-paper-workload", "--cpu-sample-iters", "10"]
+    r = subprocess.run(cmd, capture_output=True, text=True, timeout=240, cwd=ROOT)
+    assert r.returncode == 0, r.stderr[-2000:]
+    lines = [ln for ln in r.stdout.splitlines() if ln.startswith("{")]
+    assert len(lines) == 1, r.stdout[-2000:]
+    d = json.loads(lines[0])
+    for key in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step",
+                "higher_is_better", "scaling", "vs_baseline", "dtype", "data", "config",
+                "roofline", "cpu_baseline"):
+        assert key in d, key
+    assert d["n_gpus"] == 1 and d["steps"] == 2 and d["warmup"] == 1
+    assert d["unit"] == "shifted-solves/s" and d["higher_is_better"] is True
+    assert d["value"] > 0 and d["converged"] is True
+    assert d["max_true_rel_res"] <= 1e-10
+    assert "workload" in d["config"]
+    rf = d["roofline"]
+    assert rf["bound"] == "hbm" and rf["unit"] == "GB/s" and rf["peak"] == 8000.0
+    assert rf["frac"] == pytest.approx(rf["achieved"] / rf["peak"], abs=1e-4)
+    assert 0 < rf["frac"] < 1
+    assert rf["kernel"] in d["kernels"]
+    assert rf["copy_ceiling"]["same_bytes_gbs"] > 0
+    cb = d["cpu_baseline"]
+    assert cb["kind"] == "oracle" and cb["cores"] >= 1 and cb["value"] > 0
+    assert cb["unit"] == d["unit"]
