@@ -206,7 +206,7 @@ def main():
     ap.add_argument("--timing", type=int, default=128,
                     help="time the kernels of a run of consecutive iterations (one folding "
                          "cycle of the shift update) out of every k with dispatch events")
-    ap.add_argument("--cpu-sample-iters", type=int, default=320,
+    ap.add_argument("--cpu-sample-iters", type=int, default=420,
                     help="oracle iterations timed for cpu_baseline (about 10 s of one core)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true",
