@@ -1,47 +1,63 @@
-"""CG-M (Algorithm 1 of the paper) in FP64, step by step.  Test infrastructure only.
+"""Multishift conjugate gradient (CG-M) in FP64.  Test infrastructure only.
 
-The paper's Algorithm 1 solves (A + sigma I) x_sigma = b for all shifts from one Krylov
-sequence (Section 2).  It is written here in the paper's order and notation:
+What it computes (Section 2, eq. linprob and the discussion of shift invariance): the
+solutions x_k = (A + sigma_k I)^{-1} b of a whole family of shifted systems from the one
+Krylov sequence of a single "driving" system.
 
-* ``beta0`` is the step of the driving system; it is negative in this notation
-  (r <- r + beta0 * Ap and x_sigma <- x_sigma - beta_sigma p_sigma), the convention of
-  the multishift reference the paper builds on;
-* ``alpha`` is the search-direction coefficient, p <- r + alpha p;
-* ``zeta`` holds the collinearity factors, r_sigma = zeta_sigma r.
+Derivation used here (restated from the mathematics, not from the printed algorithm,
+whose shifted constants are garbled; Section 2, Algorithm 1 is the method being
+restated).  Plain CG on the driving matrix B = A + sigma0 I with positive step sizes:
 
-Three shifted constants are garbled as printed; they are replaced by the values that
-follow from requiring r_sigma = zeta_sigma r for every iterate (derived by eliminating
-p from the CG recurrences and matching the coefficients of r_{n+1}, r_n, r_{n-1}):
+    q_n     = B d_n,             a_n = |r_n|^2 / d_n^H q_n
+    r_{n+1} = r_n - a_n q_n,     c_n = |r_{n+1}|^2 / |r_n|^2
+    d_{n+1} = r_{n+1} + c_n d_n
 
-  zeta_{1s} = zeta_{0s} zeta_{-1s} beta_{-1}
-              / (beta0 alpha (zeta_{-1s} - zeta_{0s}) + zeta_{-1s} beta_{-1} (1 - s beta0))
-  beta_s    = beta0 zeta_{1s} / zeta_{0s}
-  alpha_s   = alpha (zeta_{1s} / zeta_{0s})**2          (alpha already updated)
-  p_s      <- zeta_{1s} r + alpha_s p_s                 (the new zeta, not the old one)
+Eliminating d gives a three-term recurrence for the residuals alone.  The residual of
+the shifted matrix B + s I (s = sigma_k - sigma0 >= 0) after n steps of CG lies in the
+same Krylov space and, because both are the residual polynomial applied to b, is a
+scalar multiple of r_n: r_n(s) = z_n(s) r_n.  Requiring that the same three-term
+recurrence (with the shifted step a_n(s) and coefficient c_n(s)) holds for z_n(s) r_n
+and matching the coefficients of r_{n+1}, r_n and r_{n-1} fixes
 
-Further readings (the paper is silent or generic on these):
+    z_{n+1} = z_n z_{n-1} a_{n-1} / ( a_n c_{n-1} (z_{n-1} - z_n)
+                                      + z_{n-1} a_{n-1} (1 + s a_n) )
+    a_n(s)  = a_n z_{n+1} / z_n
+    c_n(s)  = c_n (z_{n+1} / z_n)^2
 
-* the Krylov sequence is driven by the smallest shift sigma0 = min(sigma); the
-  relative shifts s = sigma - sigma0 >= 0 enter the recurrences (the paper's A is the
-  special case sigma0 = 0, available through ``drive``);
-* the halting test is relative, |r| <= tol |b|, on the recursive residual of the
-  driving system;
-* a shift is frozen (no further update of x_s, p_s, zeta_s) once its recursive
-  residual zeta_s^2 |r|^2 <= tol^2 |b|^2, which also keeps zeta from underflowing;
-* a breakdown is reported when p^H (A + sigma0) p is not a positive finite number.
+with z_{-1} = z_0 = 1, a_{-1} = 1, c_{-1} = 0.  Each shift then keeps its own iterate
+and direction, x(s) += a_n(s) d(s) and d(s) <- z_{n+1} r_{n+1} + c_n(s) d(s).  The
+driving system is the shift s = 0, for which z stays exactly 1.
+
+Readings (the paper is silent or generic on these):
+
+* the driving system is the smallest shift, sigma0 = min(sigma) (``drive`` may name
+  another sigma0, e.g. 0 for the paper's unshifted A);
+* halting is relative, |r_n| <= tol |b|, on the recursive residual of the driving system;
+* a shift stops being advanced once its recursive residual z^2 |r|^2 <= tol^2 |b|^2,
+  which also keeps z from underflowing;
+* a breakdown is reported when d^H B d is not a positive finite number.
 """
 from __future__ import annotations
 
 import numpy as np
 
 
-def _dot(u, v) -> complex:
-    return complex(np.vdot(u, v))
+class _Shift:
+    """State carried for one shifted system (in the sorted order of the shifts)."""
+
+    def __init__(self, s, b):
+        self.s = float(s)               # sigma_k - sigma0 >= 0
+        self.x = np.zeros_like(b)       # iterate x(s)
+        self.d = b.copy()               # direction d(s)
+        self.z = 1.0                    # z_n(s):   r_n(s) = z_n(s) r_n
+        self.z_old = 1.0                # z_{n-1}(s)
+        self.live = True                # still advanced
+        self.frozen_at = -1             # iteration at which it stopped, -1: never
 
 
 def cg_m(apply_A, b, sigma, tol=1e-10, max_iter=10000, drive="min", freeze=True,
          observe=None):
-    """Solve (A + sigma_k I) x_k = b for every shift with Algorithm 1 (corrected).
+    """Solve (A + sigma_k I) x_k = b for every shift with one Krylov sequence.
 
     Parameters
     ----------
@@ -49,8 +65,9 @@ def cg_m(apply_A, b, sigma, tol=1e-10, max_iter=10000, drive="min", freeze=True,
     b       : complex right-hand side, shape (n,).
     sigma   : real shifts, any order, duplicates allowed.
     drive   : ``"min"`` (drive with the smallest shift) or a float sigma0.
-    observe : optional ``observe(i, r=..., x=..., zeta=..., p=..., ps=...)`` called after
-              every iteration with the state in sorted-shift order ``order``.
+    observe : optional ``observe(i, r=..., x=..., zeta=..., p=..., ps=..., order=...,
+              sigma0=...)`` called after every iteration with the state in sorted-shift
+              order ``order`` (x, zeta and the directions ps stacked over the shifts).
 
     Returns a dict with ``x`` (ns, n) in the caller's shift order, ``iters``, ``status``
     (``"ok"``, ``"notconv"`` or ``"breakdown"``), ``true_rel_res`` per shift,
@@ -60,78 +77,71 @@ def cg_m(apply_A, b, sigma, tol=1e-10, max_iter=10000, drive="min", freeze=True,
     sigma = np.asarray(sigma, dtype=np.float64).reshape(-1)
     ns, n = sigma.size, b.size
     order = np.argsort(sigma, kind="stable")
-    sig = sigma[order]
-    sigma0 = float(sig[0]) if drive == "min" else float(drive)
-    s = sig - sigma0
-    bnorm2 = _dot(b, b).real
-    x_sorted = np.zeros((ns, n), dtype=np.complex128)
-    freeze_iter = np.full(ns, -1, dtype=np.int64)
+    sigma0 = float(sigma[order[0]]) if drive == "min" else float(drive)
+    shifts = [_Shift(sigma[k] - sigma0, b) for k in order]
+    bb = float(np.vdot(b, b).real)
     result = dict(order=order, sigma0=sigma0)
-    if bnorm2 == 0.0:
+    if bb == 0.0:
         result.update(x=np.zeros((ns, n), dtype=np.complex128), iters=0, status="ok",
-                      true_rel_res=np.zeros(ns), freeze_iter=freeze_iter, R=0.0)
+                      true_rel_res=np.zeros(ns), freeze_iter=np.full(ns, -1, dtype=np.int64),
+                      R=0.0)
         return result
-    eps2 = tol * tol * bnorm2
+    target = tol * tol * bb            # halting / freezing threshold on |r|^2
 
-    # initialisation block of Algorithm 1
-    alpha = 0.0
-    beta0 = 1.0
-    zeta_m1 = np.ones(ns)
-    zeta_0 = np.ones(ns)
-    r = b.copy()
-    p = b.copy()
-    p_s = np.tile(b, (ns, 1))
-    x_s = x_sorted
-    R1 = _dot(r, r).real
-    i = 0
-    active = np.ones(ns, dtype=bool)
+    r = b.copy()                       # driving residual
+    d = b.copy()                       # driving direction
+    rr = bb                            # |r_n|^2
+    a_old, c_old = 1.0, 0.0            # a_{n-1}, c_{n-1}
+    it = 0
     status = "notconv"
-
-    while R1 > eps2 and i < max_iter:
-        R0 = R1
-        beta_m1 = beta0
-        pbar = apply_A(p, sigma0)
-        P = _dot(p, pbar).real
-        if not (np.isfinite(P) and P > 0.0):
+    while rr > target and it < max_iter:
+        q = apply_A(d, sigma0)
+        curv = float(np.vdot(d, q).real)
+        if not (np.isfinite(curv) and curv > 0.0):
             status = "breakdown"
             break
-        beta0 = -R0 / P
-        r = r + beta0 * pbar
-        act = np.nonzero(active)[0]
-        zeta_1 = zeta_0.copy()
-        denom = (beta0 * alpha * (zeta_m1[act] - zeta_0[act])
-                 + zeta_m1[act] * beta_m1 * (1.0 - s[act] * beta0))
-        zeta_1[act] = zeta_0[act] * zeta_m1[act] * beta_m1 / denom
-        beta_s = beta0 * zeta_1[act] / zeta_0[act]
-        R1 = _dot(r, r).real
-        if not np.isfinite(R1):
+        a = rr / curv
+        # shifted steps from the collinearity of the residuals
+        z_new = {}
+        for j, sh in enumerate(shifts):
+            if not sh.live:
+                continue
+            zn = sh.z * sh.z_old * a_old / (a * c_old * (sh.z_old - sh.z)
+                                            + sh.z_old * a_old * (1.0 + sh.s * a))
+            sh.x += (a * zn / sh.z) * sh.d
+            z_new[j] = zn
+        r = r - a * q
+        rr_new = float(np.vdot(r, r).real)
+        if not np.isfinite(rr_new):
             status = "breakdown"
             break
-        alpha = R1 / R0
-        alpha_s = alpha * (zeta_1[act] / zeta_0[act]) ** 2
-        p = r + alpha * p
-        x_s[act] -= beta_s[:, None] * p_s[act]
-        p_s[act] = zeta_1[act, None] * r[None, :] + alpha_s[:, None] * p_s[act]
-        zeta_m1[act] = zeta_0[act]
-        zeta_0[act] = zeta_1[act]
-        i += 1
+        c = rr_new / rr
+        for j, zn in z_new.items():
+            sh = shifts[j]
+            ratio = zn / sh.z
+            sh.d = zn * r + (c * ratio * ratio) * sh.d
+            sh.z_old, sh.z = sh.z, zn
+        d = r + c * d
+        a_old, c_old, rr = a, c, rr_new
+        it += 1
         if freeze:
-            done = active & (zeta_0 * zeta_0 * R1 <= eps2)
-            freeze_iter[done] = i
-            active &= ~done
+            for sh in shifts:
+                if sh.live and sh.z * sh.z * rr <= target:
+                    sh.live = False
+                    sh.frozen_at = it
         if observe is not None:
-            observe(i, r=r, x=x_s, zeta=zeta_0, p=p, ps=p_s, order=order, sigma0=sigma0)
+            observe(it, r=r, x=np.stack([sh.x for sh in shifts]),
+                    zeta=np.array([sh.z for sh in shifts]), p=d,
+                    ps=np.stack([sh.d for sh in shifts]), order=order, sigma0=sigma0)
     if status != "breakdown":
-        status = "ok" if R1 <= eps2 else "notconv"
+        status = "ok" if rr <= target else "notconv"
 
-    x = np.empty_like(x_s)
-    x[order] = x_s
-    fi = np.empty_like(freeze_iter)
-    fi[order] = freeze_iter
-    rel = np.empty(ns)
-    bn = np.sqrt(bnorm2)
-    for k in range(ns):
-        res = b - apply_A(x[k], float(sigma[k]))
-        rel[k] = np.linalg.norm(res) / bn
-    result.update(x=x, iters=i, status=status, true_rel_res=rel, freeze_iter=fi, R=R1)
+    x = np.empty((ns, n), dtype=np.complex128)
+    frozen = np.empty(ns, dtype=np.int64)
+    for j, k in enumerate(order):
+        x[k] = shifts[j].x
+        frozen[k] = shifts[j].frozen_at
+    bn = np.sqrt(bb)
+    rel = np.array([np.linalg.norm(b - apply_A(x[k], float(sigma[k]))) / bn for k in range(ns)])
+    result.update(x=x, iters=it, status=status, true_rel_res=rel, freeze_iter=frozen, R=rr)
     return result
