@@ -34,6 +34,29 @@ def _ptr(t: torch.Tensor):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _numel(a) -> int:
+    """Element count of a tensor or array-like without moving it."""
+    if isinstance(a, torch.Tensor):
+        return int(a.numel())
+    return int(np.asarray(a).size)
+
+
+def _need(cond, msg):
+    # the C ABI sees raw pointers only: every length is checked here before a call
+    if not cond:
+        raise ValueError(msg)
+
+
+def _check_out(out, shape, device, what):
+    """`out` must be a contiguous complex128 tensor of `shape` on `device`."""
+    _need(isinstance(out, torch.Tensor), f"{what}: out must be a torch tensor")
+    _need(tuple(out.shape) == tuple(shape),
+          f"{what}: out has shape {tuple(out.shape)}, expected {tuple(shape)}")
+    _need(out.dtype == torch.complex128, f"{what}: out must be complex128, got {out.dtype}")
+    _need(out.device == device, f"{what}: out is on {out.device}, the operator on {device}")
+    _need(out.is_contiguous(), f"{what}: out must be contiguous")
+
+
 def make_params(tol=1e-10, prec="fp64", max_iter=10000, reliable_every=50, freeze=True,
                 refine=True, poll_every=16, switch_tol=None, refine_max_iter=10000, lanes=0,
                 verify=True, timing=0, max_grid=0, format="auto", mixed_margin=None,
@@ -67,10 +90,20 @@ class Operator:
     """A CSR operator resident on the GPU: A = M^H M (kind "mhm") or A itself ("herm")."""
 
     def __init__(self, rowptr, col, vals, n, kind="mhm", device="cuda:0", stream=None):
-        self.lib = L.load()
-        self.device = torch.device(device)
         self.n = int(n)
         self.kind = kind
+        self.sigma = None
+        self.version = 0      # bumped whenever the values or the shifts change
+        self._autograd_vals = None  # values of the last autograd forward, while current
+        self.handle = None
+        _need(kind in _KIND, f"unknown operator kind {kind!r}")
+        _need(self.n >= 1, "n must be >= 1")
+        _need(_numel(rowptr) == self.n + 1,
+              f"rowptr has {_numel(rowptr)} entries, expected n + 1 = {self.n + 1}")
+        _need(_numel(vals) == _numel(col),
+              f"vals has {_numel(vals)} entries but col has {_numel(col)}")
+        self.lib = L.load()
+        self.device = torch.device(device)
         rp = _dev_tensor(rowptr, torch.int64, self.device)
         cl = _dev_tensor(col, torch.int32, self.device)
         vl = _dev_tensor(vals, torch.complex128, self.device)
@@ -81,7 +114,6 @@ class Operator:
         if st != L.MSC_OK:
             raise L.MscError(st, "msc_op_create_csr")
         self.handle = h
-        self.sigma = None
 
     def close(self):
         if getattr(self, "handle", None) is not None and self.handle.value:
@@ -102,6 +134,7 @@ class Operator:
         if st != L.MSC_OK:
             raise L.MscError(st, "msc_op_set_shifts")
         self.sigma = s.copy()
+        self.version += 1
 
     def storage(self):
         """{"sell": sliced ELLPACK copy built, "narrow": (matrix, M^H) copies with 16-bit
@@ -114,13 +147,19 @@ class Operator:
                 "narrow": (bool(narrow.value & 1), bool(narrow.value & 2))}
 
     def update_values(self, vals, stream=None):
+        _need(_numel(vals) == self.nnz,
+              f"update_values: {_numel(vals)} values, the operator has {self.nnz} entries")
         vl = _dev_tensor(vals, torch.complex128, self.device)
         st = self.lib.msc_op_update_values(self.handle, _ptr(vl), _stream(stream))
         if st != L.MSC_OK:
             raise L.MscError(st, "msc_op_update_values")
+        self.version += 1
+        self._autograd_vals = None
 
     def apply(self, v, shift=0.0, prec="fp64", stream=None):
-        vin = _dev_tensor(v, torch.complex128, self.device)
+        _need(_numel(v) == self.n, f"apply: v has {_numel(v)} entries, expected n = {self.n}")
+        _need(prec in _PREC, f"apply: unknown precision {prec!r}")
+        vin = _dev_tensor(v, torch.complex128, self.device).reshape(-1)
         out = torch.empty_like(vin)
         st = self.lib.msc_op_apply(self.handle, _PREC[prec], _ptr(vin), _ptr(out), float(shift),
                                    _stream(stream))
@@ -133,6 +172,9 @@ class Operator:
         if self.sigma is None:
             raise ValueError("set_shifts first")
         ns = self.sigma.size
+        _need(_numel(b) == self.n, f"solve: b has {_numel(b)} entries, expected n = {self.n}")
+        if out is not None:
+            _check_out(out, (ns, self.n), self.device, "solve")
         bt = _dev_tensor(b, torch.complex128, self.device)
         x = torch.empty((ns, self.n), dtype=torch.complex128, device=self.device) if out is None else out
         prm = make_params(**kw)
@@ -146,7 +188,13 @@ class Operator:
 
     def solve_adjoint(self, g, x, stream=None, grad_vals=True, grad_b=True, check=True, **kw):
         """(grad_b (n,), grad_vals (nnz,), info) of L with dL/dx = g."""
+        if self.sigma is None:
+            raise ValueError("set_shifts first")
         ns = self.sigma.size
+        _need(_numel(g) == ns * self.n,
+              f"solve_adjoint: g has {_numel(g)} entries, expected ns * n = {ns * self.n}")
+        _need(_numel(x) == ns * self.n,
+              f"solve_adjoint: x has {_numel(x)} entries, expected ns * n = {ns * self.n}")
         gt = _dev_tensor(g, torch.complex128, self.device).reshape(ns, self.n)
         xt = _dev_tensor(x, torch.complex128, self.device).reshape(ns, self.n)
         gb = torch.empty(self.n, dtype=torch.complex128, device=self.device) if grad_b else None
@@ -190,6 +238,13 @@ def solve_batched(ops, bs, stream=None, check=True, **kw):
     """Solve every op against its right-hand sides bs[s] (nrhs_s, n_s) in one call.
 
     Returns (xs, infos) with xs[s] of shape (nrhs_s, ns_s, n_s)."""
+    _need(len(ops) == len(bs) and len(ops) >= 1,
+          "solve_batched: one right-hand-side block per operator, at least one")
+    for s, (op, b) in enumerate(zip(ops, bs)):
+        _need(op.sigma is not None, f"solve_batched: system {s} has no shifts")
+        nb = _numel(b)
+        _need(nb >= op.n and nb % op.n == 0,
+              f"solve_batched: system {s}: b has {nb} entries, not a multiple of n = {op.n}")
     lib = L.load()
     nsys = len(ops)
     handles = (ctypes.c_void_p * nsys)(*[op.handle.value for op in ops])

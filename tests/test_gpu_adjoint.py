@@ -106,6 +106,44 @@ def test_autograd_function(c3_4, cuda):
     op.close()
 
 
+def test_autograd_two_forwards_share_one_operator(c3_4, cuda):
+    # two forwards with different values (and a shift change in between) on one operator,
+    # then both backwards: each gradient belongs to its own forward's A + sigma
+    import torch
+    from paper_1102_2143_amd.autograd import multishift_solve
+    p = c3_4
+    op = _op(p, cuda)
+    c = torch.tensor(p["c"], device=cuda)
+    rng = np.random.default_rng(77)
+    vals2_np = p["vals"] * (1.0 + 0.05 * rng.standard_normal(p["vals"].size))
+    sigma2 = p["sigma"] * 1.5
+    v1 = torch.tensor(p["vals"], device=cuda, requires_grad=True)
+    v2 = torch.tensor(vals2_np, device=cuda, requires_grad=True)
+    b = torch.tensor(p["b"], device=cuda, requires_grad=True)
+
+    def loss_of(x):
+        return (c * torch.real((b.detach().conj()[None, :] * x).sum(dim=1))).sum()
+
+    x1 = multishift_solve(v1, b, op, tol=1e-12)
+    op.set_shifts(sigma2)
+    x2 = multishift_solve(v2, b, op, tol=1e-12)
+    g = p["c"][:, None] * p["b"][None, :]
+    # backward of the first forward after the second one changed values and shifts
+    gv1, gb1 = torch.autograd.grad(loss_of(x1), (v1, b))
+    ref_v1, ref_b1 = O.dense_reference_gradient("mhm", p["rowptr"], p["col"], p["vals"], p["n"],
+                                                p["b"], p["sigma"], g)
+    assert _rel(gv1.cpu().numpy(), ref_v1) <= 1e-8
+    assert _rel(gb1.cpu().numpy(), ref_b1) <= 1e-8
+    # the operator is back at the second forward's state: its backward is correct too
+    assert np.array_equal(op.sigma, sigma2)
+    gv2, gb2 = torch.autograd.grad(loss_of(x2), (v2, b))
+    ref_v2, ref_b2 = O.dense_reference_gradient("mhm", p["rowptr"], p["col"], vals2_np, p["n"],
+                                                p["b"], sigma2, g)
+    assert _rel(gv2.cpu().numpy(), ref_v2) <= 1e-8
+    assert _rel(gb2.cpu().numpy(), ref_b2) <= 1e-8
+    op.close()
+
+
 def test_c3_8x4_against_finite_differences(cuda):
     path = os.path.join(GOLDEN, "fd_c3_8x4.json")
     if not os.path.exists(path):
