@@ -5,7 +5,11 @@ residual <= 1e-10, including the FP64 verification and, for the mixed path, the
 reliable updates and per-shift refinement), with the operator and right-hand side
 already resident in HBM.  Prints one JSON line.
 
-    python bench.py [--steps K] [--warmup W] [--workload c1] [--prec mixed|fp64]
+    python bench.py [--steps K] [--warmup W] [--workload c2] [--prec mixed|fp64]
+
+The default workload is the largest single-GPU configuration, 32^3 x 64 (c2), whose
+working set is far beyond the last-level cache; 16^4 (c1), whose working set largely fits
+in the 256 MB Infinity Cache, is reported beside it as cache-resident.
 """
 from __future__ import annotations
 
@@ -175,24 +179,44 @@ def batched_line(args, dev):
     return out
 
 
+def cpu_model():
+    """The host CPU's model name from /proc/cpuinfo (else what platform reports)."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
 def cpu_baseline(prob, sample_iters, full_iters):
-    """Time the FP64 oracle on a bounded sample of the same solve (single thread)."""
+    """Time the FP64 oracle on a bounded sample of the same solve (single thread): the
+    first `sample_iters` iterations of its CG-M on the same operator, shifts and b, with
+    its own set-up (CSR and M^H) and the final residual check left out of the timing; the
+    solve's cost is the measured time per iteration times the FP64 iteration count."""
     import oracle as O
     from threadpoolctl import threadpool_limits
 
     ap = O.shifted_apply("mhm", prob["rowptr"], prob["col"], prob["vals"], prob["n"])
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
-        O.cg_m(ap, prob["b"], prob["sigma"], tol=prob["tol"], max_iter=sample_iters)
+        res = O.cg_m(ap, prob["b"], prob["sigma"], tol=prob["tol"], max_iter=sample_iters,
+                     verify=False)
         dt = time.perf_counter() - t0
-    per_iter = dt / sample_iters
+    done = max(1, res["iters"])
+    per_iter = dt / done
     est = per_iter * full_iters
     ns = prob["sigma"].size
     return {"value": ns / est, "unit": "shifted-solves/s", "cores": 1, "kind": "oracle",
-            "sample": (f"oracle CG-M (numpy/scipy FP64, 1 thread) for {sample_iters} of the "
-                       f"{full_iters} iterations of the same solve, {dt:.1f} s incl. final "
-                       f"residual check; scaled by iteration count"),
-            "host_cpus": os.cpu_count(), "cpu_model": platform.processor() or platform.machine()}
+            "sample": (f"oracle CG-M (numpy/scipy FP64, 1 thread) on the same operator, "
+                       f"shifts and b: the first {done} of the {full_iters} iterations of "
+                       f"the FP64 solve, {dt:.1f} s ({1e3 * per_iter:.0f} ms per iteration, "
+                       f"set-up and final residual check excluded), scaled to the full "
+                       f"iteration count: {est:.0f} s per solve"),
+            "s_per_iter": per_iter, "est_s_per_solve": est,
+            "host_cpus": os.cpu_count(), "cpu_model": cpu_model()}
 
 
 def main():
@@ -200,14 +224,19 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c1", choices=sorted(WORKLOAD_NAMES))
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOAD_NAMES))
     ap.add_argument("--prec", default="both", choices=["fp64", "mixed", "both"],
                     help="both: time the FP64 plain solve and the mixed solve (the headline)")
     ap.add_argument("--timing", type=int, default=128,
                     help="time the kernels of a run of consecutive iterations (one folding "
                          "cycle of the shift update) out of every k with dispatch events")
-    ap.add_argument("--cpu-sample-iters", type=int, default=420,
-                    help="oracle iterations timed for cpu_baseline (about 10 s of one core)")
+    ap.add_argument("--cpu-sample-iters", type=int, default=0,
+                    help="oracle iterations timed for cpu_baseline (0: about 10-30 s of one "
+                         "core: 8 at 32^3x64, 420 at 16^4, all at 4^4)")
+    ap.add_argument("--fp64-steps", type=int, default=5,
+                    help="timed steps of the FP64 plain comparison line (after one warm-up)")
+    ap.add_argument("--no-c1", action="store_true",
+                    help="skip the cache-resident 16^4 line reported beside the 32^3x64 one")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 64-system batched solve reported beside the main line")
@@ -253,15 +282,15 @@ def main():
         log(f"copy probe: {args.copy_probe_mb} MiB read + {args.copy_probe_mb} MiB written")
         del src, dst
 
-    def run_path(prec):
+    def run_path(prec, steps, warmup, prob=prob, op=op, b=b, x=x):
         kw = dict(tol=prob["tol"], prec=prec, timing=args.timing)
-        for i in range(args.warmup):
+        for i in range(warmup):
             _, info = op.solve(b, out=x, **kw)
             log(f"{prec} warmup {i}: {info['status']} iters={info['iters']} {info['seconds']:.4f}s")
         torch.cuda.synchronize()
         infos = []
         t0 = time.perf_counter()
-        for i in range(args.steps):
+        for i in range(steps):
             _, info = op.solve(b, out=x, **kw)
             infos.append(info)
         torch.cuda.synchronize()
@@ -304,13 +333,21 @@ def main():
                     "launches_per_step": round(launches, 1),
                     "ms_per_step": round(1e-3 * avg_us * launches, 3)}
         return dict(prec=prec, wall=wall, ok=ok, iters=iters, infos=infos,
-                    value=ns * args.steps / wall, ms_per_step=1e3 * wall / args.steps,
-                    eff_gbs=alg_bytes / (wall / args.steps) / 1e9, kernels=kernels,
+                    value=ns * steps / wall, ms_per_step=1e3 * wall / steps, steps=steps,
+                    eff_gbs=alg_bytes / (wall / steps) / 1e9, kernels=kernels,
                     refine_iters=infos[-1]["refine_iters"], n_refined=infos[-1]["n_refined"],
                     max_res=float(max(inf["true_rel_res"].max() for inf in infos)))
 
-    paths = [args.prec] if args.prec != "both" else ["fp64", "mixed"]
-    res = {pp: run_path(pp) for pp in paths}
+    # the headline path takes --steps / --warmup; the FP64 plain comparison beside it takes
+    # --fp64-steps after one warm-up
+    res = {}
+    if args.prec in ("mixed", "both"):
+        res["mixed"] = run_path("mixed", args.steps, args.warmup)
+    if args.prec in ("fp64", "both"):
+        fp64_only = args.prec == "fp64"
+        res["fp64"] = run_path("fp64", args.steps if fp64_only else args.fp64_steps,
+                               args.warmup if fp64_only else 1)
+    paths = list(res)
     main_path = res["mixed"] if "mixed" in res else res[paths[0]]
     kernels = main_path["kernels"]
     roofline = None
@@ -338,11 +375,35 @@ def main():
     ns = prob["sigma"].size
     n, nnz = prob["n"], prob["vals"].size
     iters = main_path["iters"]
+    c1_line = None
+    if args.workload == "c2" and not args.no_c1:
+        # 16^4: the working set (about 0.2 GB) largely fits the 256 MB last-level cache, so
+        # its rates are cache-resident rates, not HBM bandwidth
+        p1 = W.make_config("c1")
+        op1 = Operator(p1["rowptr"], p1["col"], p1["vals"], p1["n"], kind="mhm", device=dev)
+        op1.set_shifts(p1["sigma"])
+        b1 = torch.from_numpy(p1["b"]).to(dev)
+        x1 = torch.empty((p1["sigma"].size, p1["n"]), dtype=torch.complex128, device=dev)
+        st1 = min(args.steps, 10)
+        r1 = {pp: run_path(pp, st1, 1, prob=p1, op=op1, b=b1, x=x1) for pp in ("mixed", "fp64")}
+        c1_line = {"workload": f"c1: {WORKLOAD_NAMES['c1']}",
+                   "note": "cache-resident: the working set largely fits the 256 MB "
+                           "last-level cache; effective GB/s here is not HBM bandwidth",
+                   "steps": st1}
+        for pp, rr in r1.items():
+            c1_line[pp] = {"value": round(rr["value"], 3), "ms_per_step": round(rr["ms_per_step"], 3),
+                           "iters": rr["iters"], "converged": rr["ok"],
+                           "max_true_rel_res": rr["max_res"],
+                           "effective_gbs": round(rr["eff_gbs"], 1)}
+        c1_line["mixed_speedup"] = round(r1["mixed"]["value"] / r1["fp64"]["value"], 3)
+        op1.close()
+        del op1, b1, x1
     cpu = None
     if not args.no_cpu_baseline:
-        log(f"cpu baseline: oracle for {args.cpu_sample_iters} iterations")
+        sample = args.cpu_sample_iters or {"c2": 8, "c1": 420}.get(args.workload, 100000)
+        log(f"cpu baseline: oracle for {sample} iterations")
         ref_iters = res["fp64"]["iters"] if "fp64" in res else iters
-        cpu = cpu_baseline(prob, args.cpu_sample_iters, ref_iters)
+        cpu = cpu_baseline(prob, sample, ref_iters)
     fp64 = res.get("fp64")
     line = {
         "metric": METRIC,
@@ -369,11 +430,13 @@ def main():
         "kernels": kernels,
         "fp64_plain": None if fp64 is None or fp64 is main_path else {
             "value": round(fp64["value"], 3), "ms_per_step": round(fp64["ms_per_step"], 3),
+            "steps": fp64["steps"],
             "iters": fp64["iters"], "converged": fp64["ok"], "max_true_rel_res": fp64["max_res"],
             "effective_gbs": round(fp64["eff_gbs"], 1), "kernels": fp64["kernels"],
             "mixed_speedup": round(main_path["value"] / fp64["value"], 3)},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "c1_cache_resident": c1_line,
         "batched": None if args.no_batch else batched_line(args, dev),
         "paper_table1": None if args.no_paper_workload else paper_table1_line(args, dev),
     }

@@ -46,3 +46,16 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode != 0
     assert "one GPU" in (r.stdout + r.stderr) or "1 GPU" in (r.stdout + r.stderr)
+
+
+def test_default_workload_is_the_largest_single_gpu_configuration():
+    # 32^3 x 64 is the headline; 16^4 is reported beside it as cache-resident
+    import argparse
+    src = open(os.path.join(ROOT, "bench.py")).read()
+    assert 'ap.add_argument("--workload", default="c2"' in src
+    assert bench.WORKLOAD_NAMES["c2"].startswith("32^3x64")
+
+
+def test_cpu_model_is_read_from_the_host():
+    name = bench.cpu_model()
+    assert isinstance(name, str) and name and name != "x86_64"

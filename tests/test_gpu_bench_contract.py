@@ -12,9 +12,11 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def test_bench_line_keeps_the_contract(cuda):
-    print("[gpu] bench.py --steps 2 --warmup 1 (child process)", flush=True)
-    cmd = [sys.executable, os.path.join(ROOT, "bench.py"), "--steps", "2", "--warmup", "1",
-           "--no-batch", "--no-paper-workload", "--cpu-sample-iters", "10"]
+    # the 16^4 workload keeps this run short; the default (32^3 x 64) has the same keys
+    print("[gpu] bench.py --workload c1 --steps 2 --warmup 1 (child process)", flush=True)
+    cmd = [sys.executable, os.path.join(ROOT, "bench.py"), "--workload", "c1", "--steps", "2",
+           "--warmup", "1", "--fp64-steps", "2", "--no-batch", "--no-paper-workload",
+           "--cpu-sample-iters", "10"]
     r = subprocess.run(cmd, capture_output=True, text=True, timeout=240, cwd=ROOT)
     assert r.returncode == 0, r.stderr[-2000:]
     lines = [ln for ln in r.stdout.splitlines() if ln.startswith("{")]
@@ -28,7 +30,8 @@ def test_bench_line_keeps_the_contract(cuda):
     assert d["unit"] == "shifted-solves/s" and d["higher_is_better"] is True
     assert d["value"] > 0 and d["converged"] is True
     assert d["max_true_rel_res"] <= 1e-10
-    assert "workload" in d["config"]
+    assert d["config"]["workload"].startswith("c1:")
+    assert d["fp64_plain"]["steps"] == 2
     rf = d["roofline"]
     assert rf["bound"] == "hbm" and rf["unit"] == "GB/s" and rf["peak"] == 8000.0
     assert rf["frac"] == pytest.approx(rf["achieved"] / rf["peak"], abs=1e-4)
@@ -38,3 +41,4 @@ def test_bench_line_keeps_the_contract(cuda):
     cb = d["cpu_baseline"]
     assert cb["kind"] == "oracle" and cb["cores"] >= 1 and cb["value"] > 0
     assert cb["unit"] == d["unit"]
+    assert cb["cpu_model"] and cb["s_per_iter"] > 0
