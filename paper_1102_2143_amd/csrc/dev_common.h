@@ -109,17 +109,20 @@ __device__ __forceinline__ void store_host_flag(int* p, int v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
-// Every workgroup calls this once, after thread 0 stored its partial(s) with
-// store_agent.  Returns true (in all threads) in the workgroup that arrives last; that
-// workgroup then sees every partial through load_agent.  The ticket is reset by the
-// last workgroup, so the same counter serves the next launch.
+// Every workgroup calls this once, after its partial(s) are stored with store_agent by
+// wave 0.  Returns true (in all threads) in the workgroup that arrives last; that
+// workgroup then sees every partial through load_agent.  The counters are reset by the
+// last arrivals, so the same site serves the next launch.
 //
-// Only the partials cross workgroups inside a launch, and they travel with device-scope
-// (L2 write-through / L2-bypassing) accesses, so the ticket needs no acquire/release
-// fence: an agent-scope fence would write back and invalidate the whole L2 of the XCD
-// in every workgroup, evicting the gathered vectors the SpMV relies on.  Thread 0 waits
-// for its partial stores to complete before taking a ticket, so a workgroup that draws
-// the last ticket finds every partial in memory.
+// Ordering, in the terms of the HIP (HSA) memory model at agent scope:
+//   * each workgroup's ticket increment is a release RMW, so its partial stores, which
+//     precede it in wave 0, happen before any workgroup that observes the increment;
+//   * a group's last arrival issues an acquire fence before its own release increment of
+//     the final counter, which makes the ordering transitive;
+//   * the final arrival issues an acquire fence before anything reads a partial.
+// Acquire fences (which invalidate the XCD's caches) run in at most nine workgroups per
+// launch; every workgroup pays only the release, the write-back of its own pending
+// stores.
 //
 // Arrivals on one counter serialise at the memory side, so the ticket is two-level:
 // arrival `idx` (0 <= idx < arrivals) first takes a ticket in group idx % 8 (eight
@@ -130,20 +133,19 @@ __device__ __forceinline__ bool arrive_last(unsigned* site, unsigned arrivals, u
   __shared__ int last;
   __syncthreads();
   if (threadIdx.x == 0) {
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
-    __builtin_amdgcn_s_waitcnt(0);  // vmcnt = expcnt = lgkmcnt = 0: partial stores done
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
     const unsigned g = idx & 7u;
     const unsigned in_group = (arrivals - g + 7u) / 8u;  // arrivals whose index is g mod 8
     const unsigned groups = arrivals < 8u ? arrivals : 8u;
     unsigned* gc = site + g * kTicketStride;
-    const unsigned t = __hip_atomic_fetch_add(gc, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned t = __hip_atomic_fetch_add(gc, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     int is_last = 0;
     if (t == in_group - 1) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       __hip_atomic_store(gc, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       unsigned* fc = site + 8 * kTicketStride;
-      const unsigned f = __hip_atomic_fetch_add(fc, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const unsigned f = __hip_atomic_fetch_add(fc, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
       if (f == groups - 1) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         __hip_atomic_store(fc, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         is_last = 1;
       }

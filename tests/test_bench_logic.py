@@ -26,18 +26,29 @@ def test_dominant_kernel_is_the_most_time_per_step():
 
 
 def test_traffic_is_reported_only_for_the_measured_sources(tmp_path, monkeypatch):
+    import hashlib
     data = json.load(open(bench.TRAFFIC_FILE))
-    name = bench.KERNEL_NAMES[("fp64", "head")]
-    ent = data["workloads"]["c1"][name]
+    wl = sorted(data["workloads"])[0]
+    name = sorted(data["workloads"][wl])[0]
+    prec, kern = [k for k, v in bench.KERNEL_NAMES.items() if v == name][0]
+    ent = data["workloads"][wl][name]
     want = 1024.0 * (ent["fetch_kib"] * data["fetch_scale"] + ent["write_kib"] * data["write_scale"])
-    got, kname = bench.measured_traffic("c1", "fp64", "head")
+    # a summary whose digest matches the kernel sources as they are gives the figure
+    h = hashlib.sha256()
+    for rel in data["kernel_sources"]:
+        h.update(open(os.path.join(ROOT, rel), "rb").read())
+    data["kernel_source_sha256"] = h.hexdigest()
+    fresh = tmp_path / "fresh.json"
+    fresh.write_text(json.dumps(data))
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(fresh))
+    got, kname = bench.measured_traffic(wl, prec, kern)
     assert kname == name and got == pytest.approx(want)
     # a digest that no longer matches the kernel sources turns the figure off
     data["kernel_source_sha256"] = "0" * 64
     stale = tmp_path / "hbm_traffic.json"
     stale.write_text(json.dumps(data))
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(stale))
-    got, kname = bench.measured_traffic("c1", "fp64", "head")
+    got, kname = bench.measured_traffic(wl, prec, kern)
     assert got is None and kname == name
 
 
