@@ -10,6 +10,9 @@ Contents (each function cites the passage of the paper it follows):
 * :mod:`oracle.cgm`      -- Algorithm 1 (CG-M) step by step, with the printed errata
                             corrected, plus the true per-shift residuals.
 * :mod:`oracle.cg`       -- textbook unshifted CG (the paper's comparator, Section 4).
+* :mod:`oracle.bicgstab` -- textbook BiCGStab and the multishift BiCGStab-M (the
+                            paper's second shifted solver, Sections 1 and 3) for
+                            non-Hermitian A, derived from the BiCG polynomials.
 * :mod:`oracle.direct`   -- the plain definition x_k = (A + sigma_k I)^{-1} b: dense
                             solve, the free-field Fourier closed form and the pure-gauge
                             closed form.
@@ -21,6 +24,7 @@ Contents (each function cites the passage of the paper it follows):
 from .operators import csr_matrix_of, shifted_apply, adjoint_csr
 from .cgm import cg_m
 from .cg import cg
+from .bicgstab import bicgstab, bicgstab_m
 from .direct import dense_from_csr, dense_solve, free_field_solve, pure_gauge_solve
 from .gradient import (
     dense_reference_gradient,
@@ -37,6 +41,8 @@ __all__ = [
     "adjoint_csr",
     "cg_m",
     "cg",
+    "bicgstab",
+    "bicgstab_m",
     "dense_from_csr",
     "dense_solve",
     "free_field_solve",

@@ -23,7 +23,7 @@ def dense_from_csr(rowptr, col, vals, n) -> np.ndarray:
 def dense_solve(kind, rowptr, col, vals, n, b, sigma) -> np.ndarray:
     """x_k = (A + sigma_k I)^{-1} b for every shift, dense FP64; returns (ns, n)."""
     m = dense_from_csr(rowptr, col, vals, n)
-    a = m.conj().T @ m if kind == "mhm" else m
+    a = m.conj().T @ m if kind == "mhm" else m  # "herm" and "general": A as given
     eye = np.eye(int(n))
     b = np.asarray(b, dtype=np.complex128)
     return np.stack([np.linalg.solve(a + float(sk) * eye, b) for sk in np.ravel(sigma)])

@@ -1,9 +1,10 @@
 """Sparse operators for the oracle (test infrastructure only).
 
-The problem is the family (A + sigma_i I) x_i = b (Section 2, eq. linprob).  Two operator
+The problem is the family (A + sigma_i I) x_i = b (Section 2, eq. linprob).  Three operator
 kinds are supported: ``"mhm"`` where the caller gives M and A = M^H M (the lattice case,
-where the fermion matrix enters through its normal operator), and ``"herm"`` where the
-caller gives a Hermitian positive-definite A directly.
+where the fermion matrix enters through its normal operator), ``"herm"`` where the
+caller gives a Hermitian positive-definite A directly, and ``"general"`` where A is any
+matrix given directly (the non-Hermitian systems of BiCGStab-M).
 """
 from __future__ import annotations
 
@@ -28,7 +29,7 @@ def adjoint_csr(m: sp.csr_matrix) -> sp.csr_matrix:
 def shifted_apply(kind: str, rowptr, col, vals, n):
     """Return ``apply(v, shift=0.0) = (A + shift I) v`` in FP64.
 
-    kind ``"mhm"``: A v = M^H (M v); kind ``"herm"``: A v = A v.
+    kind ``"mhm"``: A v = M^H (M v); kinds ``"herm"`` and ``"general"``: A v = A v.
     """
     m = csr_matrix_of(rowptr, col, vals, n)
     if kind == "mhm":
@@ -39,7 +40,7 @@ def shifted_apply(kind: str, rowptr, col, vals, n):
             if shift != 0.0:
                 out = out + shift * v
             return out
-    elif kind == "herm":
+    elif kind in ("herm", "general"):
         def apply(v, shift=0.0):
             out = m @ v
             if shift != 0.0:
