@@ -41,13 +41,18 @@ WORKLOAD_NAMES = {
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
 KERNEL_NAMES = {("mixed", "head"): "k1_fused<float, true>", ("mixed", "K2"): "k2_sell<float>",
                 ("fp64", "head"): "k1_fused<double, true>", ("fp64", "K2"): "k2_sell<double>"}
+# the same kernels on the matrix-free staggered operator (M and M^H from the links)
+KERNEL_NAMES_MF = {("mixed", "head"): "k1_fused<float, true, true>",
+                   ("mixed", "K2"): "k2_sell<float, true>",
+                   ("fp64", "head"): "k1_fused<double, true, true>",
+                   ("fp64", "K2"): "k2_sell<double, true>"}
 PHASE_NAMES = {"fp64": "FP64", "mixed": "complex64"}
 
 
-def measured_traffic(workload, prec, kernel):
+def measured_traffic(workload, prec, kernel, matrix_free=False):
     """(bytes per launch, kernel name) from the committed counter summary, or (None, name)."""
     import hashlib
-    name = KERNEL_NAMES.get((prec, kernel))
+    name = (KERNEL_NAMES_MF if matrix_free else KERNEL_NAMES).get((prec, kernel))
     try:
         with open(TRAFFIC_FILE) as fh:
             data = json.load(fh)
@@ -235,6 +240,11 @@ def main():
                          "core: 8 at 32^3x64, 420 at 16^4, all at 4^4)")
     ap.add_argument("--fp64-steps", type=int, default=5,
                     help="timed steps of the FP64 plain comparison line (after one warm-up)")
+    ap.add_argument("--no-matrix-free", action="store_true",
+                    help="skip the matrix-free staggered operator's lines (links instead of "
+                         "a stored matrix in the iteration)")
+    ap.add_argument("--headline-op", default="stored", choices=["stored", "matrix_free"],
+                    help="which operator the headline value is quoted on")
     ap.add_argument("--no-c1", action="store_true",
                     help="skip the cache-resident 16^4 line reported beside the 32^3x64 one")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -282,8 +292,8 @@ def main():
         log(f"copy probe: {args.copy_probe_mb} MiB read + {args.copy_probe_mb} MiB written")
         del src, dst
 
-    def run_path(prec, steps, warmup, prob=prob, op=op, b=b, x=x):
-        kw = dict(tol=prob["tol"], prec=prec, timing=args.timing)
+    def run_path(prec, steps, warmup, prob=prob, op=op, b=b, x=x, fmt="auto"):
+        kw = dict(tol=prob["tol"], prec=prec, timing=args.timing, format=fmt)
         for i in range(warmup):
             _, info = op.solve(b, out=x, **kw)
             log(f"{prec} warmup {i}: {info['status']} iters={info['iters']} {info['seconds']:.4f}s")
@@ -332,7 +342,7 @@ def main():
                     "gbs": round(kby[k] / (kms[k] * 1e-3) / 1e9, 1),
                     "launches_per_step": round(launches, 1),
                     "ms_per_step": round(1e-3 * avg_us * launches, 3)}
-        return dict(prec=prec, wall=wall, ok=ok, iters=iters, infos=infos,
+        return dict(prec=prec, wall=wall, ok=ok, iters=iters, infos=infos, fmt=fmt,
                     value=ns * steps / wall, ms_per_step=1e3 * wall / steps, steps=steps,
                     eff_gbs=alg_bytes / (wall / steps) / 1e9, kernels=kernels,
                     refine_iters=infos[-1]["refine_iters"], n_refined=infos[-1]["n_refined"],
@@ -340,13 +350,39 @@ def main():
 
     # the headline path takes --steps / --warmup; the FP64 plain comparison beside it takes
     # --fp64-steps after one warm-up
-    res = {}
-    if args.prec in ("mixed", "both"):
-        res["mixed"] = run_path("mixed", args.steps, args.warmup)
-    if args.prec in ("fp64", "both"):
-        fp64_only = args.prec == "fp64"
-        res["fp64"] = run_path("fp64", args.steps if fp64_only else args.fp64_steps,
-                               args.warmup if fp64_only else 1)
+    def run_op(op, fmt, headline):
+        """The mixed and FP64 paths on one operator; the headline one takes --steps /
+        --warmup, the other --fp64-steps (FP64) or up to 10 steps after one warm-up."""
+        out = {}
+        if args.prec in ("mixed", "both"):
+            st = args.steps if headline else min(args.steps, 10)
+            out["mixed"] = run_path("mixed", st, args.warmup if headline else 1, op=op, fmt=fmt)
+        if args.prec in ("fp64", "both"):
+            fp64_only = args.prec == "fp64"
+            out["fp64"] = run_path("fp64", args.steps if fp64_only and headline else args.fp64_steps,
+                                   args.warmup if fp64_only and headline else 1, op=op, fmt=fmt)
+        return out
+
+    # the stored matrix (CSR handed to msc_op_create_csr; the iteration reads its sliced
+    # ELLPACK copies) and, for the staggered workloads, the matrix-free operator built
+    # from the links (msc_op_create_staggered; the iteration reads the links)
+    want_mf = not args.no_matrix_free and "links" in prob
+    headline_mf = args.headline_op == "matrix_free" and want_mf
+    res_stored = run_op(op, "auto", not headline_mf)
+    op.close()
+    del op
+    res_mf, mf_setup_s = None, None
+    if want_mf:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        op_mf = Operator.staggered(prob["links"], prob["dims"], prob["mass"], device=dev)
+        op_mf.set_shifts(prob["sigma"])
+        torch.cuda.synchronize()
+        mf_setup_s = time.perf_counter() - t0
+        res_mf = run_op(op_mf, "stencil", headline_mf)
+        op_mf.close()
+        del op_mf
+    res = res_mf if headline_mf else res_stored
     paths = list(res)
     main_path = res["mixed"] if "mixed" in res else res[paths[0]]
     kernels = main_path["kernels"]
@@ -355,7 +391,7 @@ def main():
         dom = dominant_kernel(kernels)
         ach = kernels[dom]["gbs"]
         traffic, kname = measured_traffic(args.workload, kernels[dom]["phase"],
-                                          kernels[dom]["kernel"])
+                                          kernels[dom]["kernel"], matrix_free=headline_mf)
         roofline = {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                     "frac": round(ach / PEAK_HBM_GBS, 4),
                     "traffic": None if traffic is None else round(traffic),
@@ -405,6 +441,31 @@ def main():
         ref_iters = res["fp64"]["iters"] if "fp64" in res else iters
         cpu = cpu_baseline(prob, sample, ref_iters)
     fp64 = res.get("fp64")
+
+    def summary(rr):
+        """The mixed and FP64 lines of one operator form, beside the headline."""
+        if rr is None:
+            return None
+        out = {}
+        for pp, r in rr.items():
+            out[pp] = {"value": round(r["value"], 3), "ms_per_step": round(r["ms_per_step"], 3),
+                       "steps": r["steps"], "iters": r["iters"], "converged": r["ok"],
+                       "max_true_rel_res": r["max_res"], "effective_gbs": round(r["eff_gbs"], 1),
+                       "kernels": r["kernels"]}
+        if "mixed" in rr and "fp64" in rr:
+            out["mixed_speedup"] = round(rr["mixed"]["value"] / rr["fp64"]["value"], 3)
+        return out
+
+    other = res_stored if headline_mf else res_mf
+    other_line = summary(other)
+    if other_line is not None:
+        other_line["operator"] = ("stored matrix: CSR to msc_op_create_csr, iteration on its "
+                                  "sliced ELLPACK copies" if headline_mf else
+                                  "matrix-free: links to msc_op_create_staggered, iteration "
+                                  "applies M and M^H from the links")
+        other_line["setup_s"] = round(setup_s if headline_mf else mf_setup_s, 3)
+        other_line["vs_headline"] = round(other["mixed"]["value"] / main_path["value"], 3) \
+            if "mixed" in other and main_path["prec"] == "mixed" else None
     line = {
         "metric": METRIC,
         "value": round(main_path["value"], 3),
@@ -420,13 +481,14 @@ def main():
         "data": "synthetic (seeded Haar SU(3) links, complex Gaussian b)",
         "config": {"workload": f"{args.workload}: {WORKLOAD_NAMES[args.workload]}", "n": n,
                    "nnz_M": nnz, "ns": ns, "prec": main_path["prec"], "iters": iters,
+                   "operator": "matrix_free" if headline_mf else "stored",
                    "refine_iters": main_path["refine_iters"], "n_refined": main_path["n_refined"],
                    "parallelism": "single GPU"},
         "converged": main_path["ok"],
         "max_true_rel_res": main_path["max_res"],
         "effective_gbs": round(main_path["eff_gbs"], 1),
         "iters_per_s": round(iters * args.steps / main_path["wall"], 1),
-        "setup_s": round(setup_s, 3),
+        "setup_s": round(mf_setup_s if headline_mf else setup_s, 3),
         "kernels": kernels,
         "fp64_plain": None if fp64 is None or fp64 is main_path else {
             "value": round(fp64["value"], 3), "ms_per_step": round(fp64["ms_per_step"], 3),
@@ -435,13 +497,13 @@ def main():
             "effective_gbs": round(fp64["eff_gbs"], 1), "kernels": fp64["kernels"],
             "mixed_speedup": round(main_path["value"] / fp64["value"], 3)},
         "roofline": roofline,
+        ("stored_matrix" if headline_mf else "matrix_free"): other_line,
         "cpu_baseline": cpu,
         "c1_cache_resident": c1_line,
         "batched": None if args.no_batch else batched_line(args, dev),
         "paper_table1": None if args.no_paper_workload else paper_table1_line(args, dev),
     }
     print(json.dumps(line), flush=True)
-    op.close()
 
 
 if __name__ == "__main__":

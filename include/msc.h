@@ -45,7 +45,8 @@ typedef enum {
 
 typedef enum {
     MSC_A_MHM = 0,         /* the caller passes M; A = M^H M                           */
-    MSC_A_HERM = 1         /* the caller passes A itself (Hermitian positive definite) */
+    MSC_A_HERM = 1,        /* the caller passes A itself (Hermitian positive definite) */
+    MSC_A_GENERAL = 2      /* the caller passes any A (msc_solve_bicgstab only)        */
 } msc_op_kind;
 
 typedef enum {
@@ -67,7 +68,10 @@ typedef enum {
     MSC_FORMAT_AUTO = 0,
     MSC_FORMAT_CSR = 1,
     MSC_FORMAT_SELL = 2,
-    MSC_FORMAT_SELL32 = 3
+    MSC_FORMAT_SELL32 = 3,
+    MSC_FORMAT_STENCIL = 4   /* operators from msc_op_create_staggered only: the
+                                iteration's two operator halves read the links instead of
+                                a stored matrix (AUTO picks this for such operators)    */
 } msc_format;
 
 /* Solver parameters; fill with msc_params_default() and override fields. */
@@ -144,7 +148,8 @@ const char* msc_last_error(void);
  * Create an operator from a CSR matrix held in device memory (Fig. 1 of the paper
  * builds the matrix, copies it to the device, then calls the solver; here the CSR is
  * already resident).  For MSC_A_MHM the matrix is M and the library builds M^H
- * (conjugate transpose with sorted columns) on the device; for MSC_A_HERM it is A.
+ * (conjugate transpose with sorted columns) on the device; for MSC_A_HERM and
+ * MSC_A_GENERAL it is A.
  *   d_rowptr : int64[n+1], non-decreasing, d_rowptr[0] = 0, d_rowptr[n] = nnz
  *   d_col    : int32[nnz], each in [0, n)
  *   d_vals   : complex128[nnz] (2*nnz doubles)
@@ -157,8 +162,36 @@ msc_status msc_op_create_csr(msc_op* out, int32_t kind, int64_t n, int64_t nnz,
                              const double* d_vals, msc_stream stream);
 
 /* Replace the values of the operator's matrix (same pattern, same entry order as at
- * creation, complex128[nnz] on the device) -- for example after new gauge links. */
+ * creation, complex128[nnz] on the device) -- for example after new gauge links.
+ * Operators made by msc_op_create_staggered take msc_op_update_links instead
+ * (MSC_EINVAL here). */
 msc_status msc_op_update_values(msc_op op, const double* d_vals, msc_stream stream);
+
+/*
+ * Create the staggered fermion operator M = m I + D (A = M^H M) of a periodic 4-D
+ * lattice from its gauge links, for a matrix-free iteration (paper: Section 3 leaves
+ * room for a custom linear operator kernel in place of the library's stored matrix).
+ *   dims    : host int32[4], extents L0..L3, each >= 3, 75 * L0 L1 L2 L3 < 2^31
+ *   mass    : m
+ *   d_links : device complex128[4][V][3][3] (V = L0 L1 L2 L3): U_mu(x) for direction mu,
+ *             site x = x0 + L0 (x1 + L1 (x2 + L2 x3)), row-major 3x3
+ * Row 3 s + c is colour c of site s, and
+ *   D[x, y] = sum_mu eta_mu(x)/2 [ U_mu(x) delta(y, x+mu) - U_mu(x-mu)^H delta(y, x-mu) ],
+ *   eta_0 = 1, eta_mu(x) = (-1)^(x0 + ... + x_{mu-1}).
+ * The library keeps eta/2 U in complex128 and complex64 (the links are copied; the
+ * caller may free them) and also builds the equivalent scalar CSR of M (25 sorted
+ * entries per row) with every copy msc_op_create_csr makes, which the reliable
+ * updates, the verification, the refinement, the adjoint, msc_op_apply and the
+ * batched solve use.  The multishift iteration applies M and M^H from the links
+ * (msc_params.format AUTO or STENCIL).  MSC_EINVAL on an extent below 3, an oversized
+ * lattice, a non-finite mass or a null pointer.
+ */
+msc_status msc_op_create_staggered(msc_op* out, const int32_t* dims, double mass,
+                                   const double* d_links, msc_stream stream);
+
+/* New gauge links for an operator made by msc_op_create_staggered (same layout as at
+ * creation): the link copies and every stored copy of M are rebuilt. */
+msc_status msc_op_update_links(msc_op op, const double* d_links, msc_stream stream);
 
 /* Set the shifts sigma_k (host array, any order, duplicates allowed, 1 <= ns <= 64).
  * The smallest shift drives the Krylov sequence; A + sigma_min must be positive
@@ -209,6 +242,22 @@ msc_status msc_solve(msc_op op, const double* d_b, double* d_x, const msc_params
 msc_status msc_solve_adjoint(msc_op op, const double* d_g, const double* d_x,
                              double* d_grad_b, double* d_grad_vals,
                              const msc_params* params, msc_info* info, msc_stream stream);
+
+/*
+ * Multishift BiCGStab (BiCGStab-M, the paper's second shifted solver: Sections 1 and 3)
+ * for a general, possibly non-Hermitian A: (A + sigma_k I) x_k = b for every shift from
+ * one BiCGStab sequence of the smallest shift, shadow vector b.  The operator must be of
+ * kind MSC_A_GENERAL or MSC_A_HERM (A as given; MSC_EINVAL for MSC_A_MHM, whose A is
+ * Hermitian positive definite: use msc_solve).  FP64 only (params->prec must be
+ * MSC_PREC_FP64).  d_b, d_x as for msc_solve.  Each shift stops being advanced once its
+ * recursive residual (a multiple of the driving one) is below tol |b|; the sequence
+ * halts when every shift has stopped.  With verify on, the FP64 true residuals are
+ * reported and decide MSC_OK / MSC_ENOTCONV; MSC_EBREAKDOWN when w^H v, t^H t or rho
+ * vanishes, 1 + s omega = 0 for a shift, or a value is not finite.  info (may be NULL)
+ * reports iters, true_rel_res and freeze_iter; timing fields are zero.
+ */
+msc_status msc_solve_bicgstab(msc_op op, const double* d_b, double* d_x,
+                              const msc_params* params, msc_info* info, msc_stream stream);
 
 /*
  * Many independent multishift solves in one launch sequence: system s uses ops[s]

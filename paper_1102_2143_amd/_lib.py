@@ -14,17 +14,19 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("MSC_LIB", os.path.join(HERE, "libmsc.so"))
 
 MSC_OK, MSC_ENOTCONV, MSC_EINVAL, MSC_ENOMEM, MSC_EHIP, MSC_EBREAKDOWN = 0, 1, -1, -2, -3, -4
-MSC_A_MHM, MSC_A_HERM = 0, 1
+MSC_A_MHM, MSC_A_HERM, MSC_A_GENERAL = 0, 1, 2
 MSC_PREC_FP64, MSC_PREC_MIXED = 0, 1
-MSC_FORMAT_AUTO, MSC_FORMAT_CSR, MSC_FORMAT_SELL, MSC_FORMAT_SELL32 = 0, 1, 2, 3
+MSC_FORMAT_AUTO, MSC_FORMAT_CSR, MSC_FORMAT_SELL, MSC_FORMAT_SELL32, MSC_FORMAT_STENCIL = 0, 1, 2, 3, 4
 
 STATUS_NAMES = {0: "ok", 1: "notconv", -1: "einval", -2: "enomem", -3: "ehip", -4: "breakdown"}
 
 EXPORTED = (
     "msc_params_default", "msc_version", "msc_last_error", "msc_op_create_csr",
-    "msc_op_update_values", "msc_op_set_shifts", "msc_op_query", "msc_op_storage", "msc_op_apply",
-    "msc_solve",
-    "msc_solve_adjoint", "msc_solve_batched", "msc_op_destroy",
+    "msc_op_create_staggered", "msc_op_update_links", "msc_op_update_values",
+    "msc_op_set_shifts", "msc_op_query", "msc_op_storage", "msc_op_apply",
+    "msc_solve", "msc_solve_adjoint", "msc_solve_bicgstab",
+    "msc_solve_batched",
+    "msc_op_destroy",
 )
 
 
@@ -91,6 +93,10 @@ def load():
     lib.msc_last_error.restype = ctypes.c_char_p
     lib.msc_op_create_csr.argtypes = [ctypes.POINTER(vp), i32, i64, i64, vp, vp, vp, vp]
     lib.msc_op_create_csr.restype = i32
+    lib.msc_op_create_staggered.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(i32), dbl, vp, vp]
+    lib.msc_op_create_staggered.restype = i32
+    lib.msc_op_update_links.argtypes = [vp, vp, vp]
+    lib.msc_op_update_links.restype = i32
     lib.msc_op_update_values.argtypes = [vp, vp, vp]
     lib.msc_op_update_values.restype = i32
     lib.msc_op_set_shifts.argtypes = [vp, ctypes.POINTER(dbl), i32]
@@ -104,6 +110,8 @@ def load():
     lib.msc_op_apply.restype = i32
     lib.msc_solve.argtypes = [vp, vp, vp, ctypes.POINTER(Params), ctypes.POINTER(Info), vp]
     lib.msc_solve.restype = i32
+    lib.msc_solve_bicgstab.argtypes = [vp, vp, vp, ctypes.POINTER(Params), ctypes.POINTER(Info), vp]
+    lib.msc_solve_bicgstab.restype = i32
     lib.msc_solve_adjoint.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(Params),
                                       ctypes.POINTER(Info), vp]
     lib.msc_solve_adjoint.restype = i32

@@ -12,9 +12,9 @@ import torch
 from . import _lib as L
 
 _PREC = {"fp64": L.MSC_PREC_FP64, "mixed": L.MSC_PREC_MIXED}
-_KIND = {"mhm": L.MSC_A_MHM, "herm": L.MSC_A_HERM}
+_KIND = {"mhm": L.MSC_A_MHM, "herm": L.MSC_A_HERM, "general": L.MSC_A_GENERAL}
 _FORMAT = {"auto": L.MSC_FORMAT_AUTO, "csr": L.MSC_FORMAT_CSR, "sell": L.MSC_FORMAT_SELL,
-           "sell32": L.MSC_FORMAT_SELL32}
+           "sell32": L.MSC_FORMAT_SELL32, "stencil": L.MSC_FORMAT_STENCIL}
 
 
 def _stream(stream=None):
@@ -87,7 +87,8 @@ def make_params(tol=1e-10, prec="fp64", max_iter=10000, reliable_every=50, freez
 
 
 class Operator:
-    """A CSR operator resident on the GPU: A = M^H M (kind "mhm") or A itself ("herm")."""
+    """A CSR operator resident on the GPU: A = M^H M (kind "mhm"), a Hermitian positive
+    definite A itself ("herm"), or any A ("general", solved by solve_bicgstab)."""
 
     def __init__(self, rowptr, col, vals, n, kind="mhm", device="cuda:0", stream=None):
         self.n = int(n)
@@ -114,6 +115,48 @@ class Operator:
         if st != L.MSC_OK:
             raise L.MscError(st, "msc_op_create_csr")
         self.handle = h
+
+    @classmethod
+    def staggered(cls, links, dims, mass, device="cuda:0", stream=None):
+        """The staggered operator M = m + D from gauge links U (4, V, 3, 3) complex128:
+        A = M^H M with a matrix-free multishift iteration (msc_op_create_staggered)."""
+        dims = tuple(int(L) for L in dims)
+        _need(len(dims) == 4, "staggered: dims must have four extents")
+        _need(all(L >= 3 for L in dims), "staggered: every extent must be >= 3")
+        vol = int(np.prod(dims))
+        _need(_numel(links) == 4 * vol * 9,
+              f"staggered: links has {_numel(links)} entries, expected 4 * V * 9 = {36 * vol}")
+        self = cls.__new__(cls)
+        self.n = 3 * vol
+        self.kind = "mhm"
+        self.sigma = None
+        self.version = 0
+        self._autograd_vals = None
+        self.handle = None
+        self.lib = L.load()
+        self.device = torch.device(device)
+        lk = _dev_tensor(links, torch.complex128, self.device)
+        d = (ctypes.c_int32 * 4)(*dims)
+        h = ctypes.c_void_p()
+        st = self.lib.msc_op_create_staggered(ctypes.byref(h), d, float(mass), _ptr(lk),
+                                              _stream(stream))
+        if st != L.MSC_OK:
+            raise L.MscError(st, "msc_op_create_staggered")
+        self.handle = h
+        self.nnz = 25 * self.n
+        self.dims = dims
+        return self
+
+    def update_links(self, links, stream=None):
+        """New gauge links for an operator made by Operator.staggered."""
+        _need(_numel(links) == 12 * self.n,
+              f"update_links: links has {_numel(links)} entries, expected {12 * self.n}")
+        lk = _dev_tensor(links, torch.complex128, self.device)
+        st = self.lib.msc_op_update_links(self.handle, _ptr(lk), _stream(stream))
+        if st != L.MSC_OK:
+            raise L.MscError(st, "msc_op_update_links")
+        self.version += 1
+        self._autograd_vals = None
 
     def close(self):
         if getattr(self, "handle", None) is not None and self.handle.value:
@@ -184,6 +227,26 @@ class Operator:
         res = _info_dict(st, info, rel, fi)
         if check and st not in (L.MSC_OK, L.MSC_ENOTCONV):
             raise L.MscError(st, "msc_solve")
+        return x, res
+
+    def solve_bicgstab(self, b, out=None, stream=None, check=True, **kw):
+        """x (ns, n) complex128 for (A + sigma_k) x_k = b by multishift BiCGStab (general A);
+        returns (x, info dict)."""
+        if self.sigma is None:
+            raise ValueError("set_shifts first")
+        ns = self.sigma.size
+        _need(_numel(b) == self.n, f"solve_bicgstab: b has {_numel(b)} entries, expected n = {self.n}")
+        if out is not None:
+            _check_out(out, (ns, self.n), self.device, "solve_bicgstab")
+        bt = _dev_tensor(b, torch.complex128, self.device)
+        x = torch.empty((ns, self.n), dtype=torch.complex128, device=self.device) if out is None else out
+        prm = make_params(**kw)
+        info, rel, fi = _new_info(ns)
+        st = self.lib.msc_solve_bicgstab(self.handle, _ptr(bt), _ptr(x), ctypes.byref(prm),
+                                         ctypes.byref(info), _stream(stream))
+        res = _info_dict(st, info, rel, fi)
+        if check and st not in (L.MSC_OK, L.MSC_ENOTCONV):
+            raise L.MscError(st, "msc_solve_bicgstab")
         return x, res
 
     def solve_adjoint(self, g, x, stream=None, grad_vals=True, grad_b=True, check=True, **kw):

@@ -18,7 +18,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmsc.so")
 ARCH = os.environ.get("MSC_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["setup.hip", "multishift.hip", "batched_cg.hip", "batched_ms.hip", "grad.hip", "capi.cpp"]
+SOURCES = ["setup.hip", "multishift.hip", "batched_cg.hip", "batched_ms.hip", "grad.hip",
+           "bicgstab.hip", "capi.cpp"]
 
 FLAGS = [
     f"--offload-arch={ARCH}",

@@ -169,6 +169,9 @@ MsArgs make_args(msc_op op, int lanes, const double* d_b, double* d_x) {
       a.sh32 = sell_view(sh, sh.val32, sh.diag32, true);
     }
   }
+  a.stencil = 0;
+  a.w64 = op->w64;
+  a.w32 = op->w32;
   a.b = reinterpret_cast<const double2*>(d_b);
   a.x = reinterpret_cast<double2*>(d_x);
   a.r = op->ws.r;
@@ -199,12 +202,26 @@ struct KernelBytes {
 // operator's matrix and of M^H that the SpMVs read.
 // `kept`: residual vectors the head's update writes (a deferring head keeps r) or reads
 // back (an applying head after deferred steps).
-KernelBytes kernel_bytes(int kind, int prec, double n, double nnz, double nnz_h, double act,
-                         bool pending, double ib, double ibh, int kept) {
+// Matrix bytes of one application of M (or A) and of M^H in precision `prec`: the stored
+// copy (value + index per entry, 4-byte row pointers), or for the matrix-free staggered
+// operator the links, each read once: 4 links x 9 values per site = 12 values per row.
+struct MatBytes {
+  double m, mh;
+};
+MatBytes mat_bytes(int kind, int prec, double n, double nnz, double nnz_h, double ib, double ibh,
+                   bool stencil) {
+  const double w = prec == MSC_PREC_MIXED ? 8.0 : 16.0;
+  if (stencil) return MatBytes{12.0 * w * n, 12.0 * w * n};
+  return MatBytes{nnz * (w + ib) + 4.0 * (n + 1),
+                  kind == MSC_A_MHM ? nnz_h * (w + ibh) + 4.0 * (n + 1) : 0.0};
+}
+
+KernelBytes kernel_bytes(int kind, int prec, double n, const MatBytes& mb, double act,
+                         bool pending, int kept) {
   const double w = prec == MSC_PREC_MIXED ? 8.0 : 16.0;
   KernelBytes b{};
-  b.k1 = nnz * (w + ib) + 4.0 * (n + 1) + 2.0 * n * w;
-  b.k2 = (kind == MSC_A_MHM ? nnz_h * (w + ibh) + 4.0 * (n + 1) + n * w : n * w) + 3.0 * n * w;
+  b.k1 = mb.m + 2.0 * n * w;
+  b.k2 = (kind == MSC_A_MHM ? mb.mh + n * w : n * w) + 3.0 * n * w;
   b.upd = pending ? n * (3.0 * w + 32.0) + act * n * (32.0 + 2.0 * w) + kept * n * w : 0.0;
   b.head = b.k1 + (pending ? b.upd - n * w : 0.0);
   return b;
@@ -212,12 +229,10 @@ KernelBytes kernel_bytes(int kind, int prec, double n, double nnz, double nnz_h,
 
 // act_sum: x_j/p_j row-vector updates performed (shifts listed, summed over the heads);
 // kept: heads that kept r for a deferred step or read it back.
-double iter_bytes(int kind, int prec, double n, double nnz, double nnz_h, double act_sum,
-                  double iters, double ib, double ibh, double kept) {
+double iter_bytes(int kind, int prec, double n, const MatBytes& mb, double act_sum,
+                  double iters, double kept) {
   const double w = prec == MSC_PREC_MIXED ? 8.0 : 16.0;   // Krylov vector element
-  const double vb = prec == MSC_PREC_MIXED ? 8.0 : 16.0;  // matrix value
-  const double mat = (nnz * (vb + ib) + 4.0 * (n + 1)) +
-                     (kind == MSC_A_MHM ? nnz_h * (vb + ibh) + 4.0 * (n + 1) : 0.0);
+  const double mat = mb.m + mb.mh;
   double vec;
   if (kind == MSC_A_MHM)
     vec = n * (w + w) + n * (w + w + 2 * w);  // K1: p gather, t write; K2: t gather, p, r r/w
@@ -263,15 +278,23 @@ msc_status run_multishift(msc_op op, const double* d_b, double* d_x, const msc_p
   rc = ensure_workspace(op, prec, ns);
   if (rc != MSC_OK) return rc;
   const int lanes = choose_lanes(op, prm);
-  if (prm.format < MSC_FORMAT_AUTO || prm.format > MSC_FORMAT_SELL32 ||
+  if (prm.format < MSC_FORMAT_AUTO || prm.format > MSC_FORMAT_STENCIL ||
       ((prm.format == MSC_FORMAT_SELL || prm.format == MSC_FORMAT_SELL32) && !op->sell)) {
     set_error("msc_solve: format %d unavailable (sliced ELLPACK copy %s)", prm.format,
               op->sell ? "built" : "not built: padding too large");
     return MSC_EINVAL;
   }
+  if (prm.format == MSC_FORMAT_STENCIL && !(op->stencil && op->sell)) {
+    set_error("msc_solve: format stencil needs an operator made by msc_op_create_staggered");
+    return MSC_EINVAL;
+  }
   MsArgs a64 = make_args(op, lanes, d_b, d_x);
   if (prm.max_grid > 0) a64.grid = std::min(prm.max_grid, kMaxGrid);
   if (prm.format == MSC_FORMAT_CSR) a64.sell = 0;
+  // the iteration's two operator halves from the links: the default for staggered
+  // operators (the reliable update, verification and refinement keep the stored copies)
+  a64.stencil = op->stencil && a64.sell &&
+                (prm.format == MSC_FORMAT_AUTO || prm.format == MSC_FORMAT_STENCIL) ? 1 : 0;
   if (prm.format == MSC_FORMAT_SELL32 && op->sell) {
     const SellStore &sm = op->sell_m, &sh = op->sell_mh;
     a64.s64 = sell_view(sm, sm.val64, sm.diag64, false);
@@ -346,15 +369,17 @@ msc_status run_multishift(msc_op op, const double* d_b, double* d_x, const msc_p
         sample_launch.push_back(launched);
       }
       // iteration `launched` starts from the state rot[launched & 1]; in the complex64
-      // phase every reliable_every-th iteration recomputes r in FP64 after its head has
-      // brought x up to date
+      // phase the reliable update (r recomputed in FP64 after the head has brought x_0 up
+      // to date) is launched every kRuCheck-th iteration and on its period: it runs on
+      // the period, or at a check when the recursive residual has fallen fast
       cur->par = launched & 1;
       const int since = launched - launched_at_switch;
-      const bool ru = phase == MSC_PREC_MIXED && prm.reliable_every > 0 && since > 0 &&
-                      since % prm.reliable_every == 0;
-      // a head followed by a reliable update applies its own step (the update may halt
-      // the sequence before the next head)
-      cur->defer_ok = ru ? 0 : 1;
+      const bool ru_period = phase == MSC_PREC_MIXED && prm.reliable_every > 0 && since > 0 &&
+                             since % prm.reliable_every == 0;
+      const bool ru = ru_period || (phase == MSC_PREC_MIXED && prm.reliable_every > 0 &&
+                                    since > 0 && since % kRuCheck == 0);
+      cur->ru_force = ru_period ? 1 : 0;
+      cur->defer_ok = 1;
       cur->steps = prm.update_steps;
       HIP_TRY(launch_iteration(phase, *cur, s, ev, ru));
       ++launched;
@@ -418,8 +443,10 @@ msc_status run_multishift(msc_op op, const double* d_b, double* d_x, const msc_p
       const bool pending = !(L == 0 || (ph32 && L == launched_at_switch));
       const int act = h.smp_nact[q];
       const int kept = h.smp_mode[q] == 1 ? 1 : h.smp_m[q];
-      const KernelBytes kb = kernel_bytes(op->kind, ph32 ? MSC_PREC_MIXED : MSC_PREC_FP64, nn,
-                                          nz, nzh, double(act), pending, ib, ibh, kept);
+      const int phq = ph32 ? MSC_PREC_MIXED : MSC_PREC_FP64;
+      const KernelBytes kb =
+          kernel_bytes(op->kind, phq, nn, mat_bytes(op->kind, phq, nn, nz, nzh, ib, ibh, a64.stencil),
+                       double(act), pending, kept);
       kby[0] += a64.sell ? kb.head : kb.k1;
       kby[1] += kb.k2;
       if (!a64.sell) kby[2] += kb.upd;
@@ -443,10 +470,13 @@ msc_status run_multishift(msc_op op, const double* d_b, double* d_x, const msc_p
   const double act64 = h.n_shift_upd[0], act32 = h.n_shift_upd[1];
   const double kept64 = h.n_defer[0] + h.n_two[0], kept32 = h.n_defer[1] + h.n_two[1];
   const double nn = double(op->n), nz = double(op->nnz), nzh = double(op->nnz_h);
-  *bytes_out = iter_bytes(op->kind, MSC_PREC_FP64, nn, nz, nzh, act64, double(iters_fp64), ib, ibh,
-                          kept64) +
-               iter_bytes(op->kind, MSC_PREC_MIXED, nn, nz, nzh, act32,
-                          double(fin.iter - iters_fp64), ib, ibh, kept32) +
+  const bool stn = a64.stencil != 0;
+  *bytes_out = iter_bytes(op->kind, MSC_PREC_FP64, nn,
+                          mat_bytes(op->kind, MSC_PREC_FP64, nn, nz, nzh, ib, ibh, stn), act64,
+                          double(iters_fp64), kept64) +
+               iter_bytes(op->kind, MSC_PREC_MIXED, nn,
+                          mat_bytes(op->kind, MSC_PREC_MIXED, nn, nz, nzh, ib, ibh, stn), act32,
+                          double(fin.iter - iters_fp64), kept32) +
                double(h.n_reliable) * (nz * (16.0 + ib) + nzh * (16.0 + ibh) +
                                        4.0 * (nn + 1) * (op->kind == MSC_A_MHM ? 2.0 : 1.0) +
                                        nn * (16.0 * 3 + 8.0));
@@ -1187,10 +1217,12 @@ struct BatchRun {
           const double nn = double(n), nz = double(op->nnz), nzh = double(op->nnz_h);
           const double ib = index_bytes(sys[s].sell, sys[s].s64);
           const double ibh = index_bytes(sys[s].sell, sys[s].sh64);
-          I.alg_bytes = iter_bytes(op->kind, MSC_PREC_FP64, nn, nz, nzh, act64, i64, ib, ibh,
-                                   kept64) +
-                        iter_bytes(op->kind, MSC_PREC_MIXED, nn, nz, nzh, act32, it - i64, ib, ibh,
-                                   kept32) -
+          I.alg_bytes = iter_bytes(op->kind, MSC_PREC_FP64, nn,
+                                   mat_bytes(op->kind, MSC_PREC_FP64, nn, nz, nzh, ib, ibh, false),
+                                   act64, i64, kept64) +
+                        iter_bytes(op->kind, MSC_PREC_MIXED, nn,
+                                   mat_bytes(op->kind, MSC_PREC_MIXED, nn, nz, nzh, ib, ibh, false),
+                                   act32, it - i64, kept32) -
                         (double(nrhs[s]) - 1.0) / double(nrhs[s]) *
                             ((nz * (16.0 + ib) + nzh * (16.0 + ibh)) * i64 +
                              (nz * (8.0 + ib) + nzh * (8.0 + ibh)) * (it - i64));
@@ -1217,6 +1249,9 @@ msc_status check_op(msc_op op) {
 }
 
 }  // namespace
+
+// New values of the stored matrix (same pattern): copies, casts, M^H and sliced copies.
+msc_status update_values_impl(msc_op op, const double* d_vals, hipStream_t s);
 
 extern "C" {
 
@@ -1250,7 +1285,7 @@ msc_status msc_op_create_csr(msc_op* out, int32_t kind, int64_t n, int64_t nnz,
     return MSC_EINVAL;
   }
   *out = nullptr;
-  if (kind != MSC_A_MHM && kind != MSC_A_HERM) {
+  if (kind != MSC_A_MHM && kind != MSC_A_HERM && kind != MSC_A_GENERAL) {
     set_error("msc_op_create_csr: unknown kind %d", kind);
     return MSC_EINVAL;
   }
@@ -1346,7 +1381,17 @@ msc_status msc_op_update_values(msc_op op, const double* d_vals, msc_stream stre
     set_error("msc_op_update_values: null values");
     return MSC_EINVAL;
   }
-  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (op->stencil) {
+    set_error("msc_op_update_values: a staggered operator takes new links "
+              "(msc_op_update_links), not new matrix values");
+    return MSC_EINVAL;
+  }
+  return update_values_impl(op, d_vals, static_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"
+
+msc_status update_values_impl(msc_op op, const double* d_vals, hipStream_t s) {
   if (op->nnz > 0) {
     HIP_TRY(hipMemcpyAsync(op->val64, d_vals, sizeof(double2) * op->nnz, hipMemcpyDeviceToDevice, s));
     HIP_TRY(launch_cast_vals(op->val64, op->val32, op->nnz, s));
@@ -1360,6 +1405,142 @@ msc_status msc_op_update_values(msc_op op, const double* d_vals, msc_stream stre
   }
   HIP_TRY(hipStreamSynchronize(s));
   return MSC_OK;
+}
+
+namespace {
+
+// Geometry of a staggered operator (links pointer left null), or false with the error set.
+bool staggered_geometry(const char* who, const int32_t* dims, double mass, Stencil<double2>& g) {
+  if (!dims) {
+    set_error("%s: null dims", who);
+    return false;
+  }
+  int64_t vol = 1;
+  for (int mu = 0; mu < 4; ++mu) {
+    if (dims[mu] < 3) {
+      set_error("%s: every extent must be >= 3 (dims[%d] = %d)", who, mu, dims[mu]);
+      return false;
+    }
+    g.L[mu] = dims[mu];
+    g.stride[mu] = vol;
+    vol *= dims[mu];
+    if (vol > (int64_t(1) << 31)) break;
+  }
+  if (vol * 3 * 25 >= (int64_t(1) << 31)) {
+    set_error("%s: 25 * 3 * volume must stay below 2^31", who);
+    return false;
+  }
+  if (!std::isfinite(mass)) {
+    set_error("%s: mass is not finite", who);
+    return false;
+  }
+  g.vol = vol;
+  g.mass = mass;
+  return true;
+}
+
+// The op's links from the caller's U (w64, w32) and the CSR of M built from them
+// (device temporaries owned by the caller of this function).
+msc_status staggered_csr(const Stencil<double2>& w, int64_t** rowptr, int32_t** col,
+                         double2** vals, hipStream_t s) {
+  const int64_t n = 3 * w.vol;
+  HIP_TRY(dalloc(rowptr, size_t(n) + 1));
+  HIP_TRY(dalloc(col, size_t(25 * n)));
+  HIP_TRY(dalloc(vals, size_t(25 * n)));
+  HIP_TRY(launch_stencil_csr(w, *rowptr, *col, *vals, s));
+  return MSC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+msc_status msc_op_create_staggered(msc_op* out, const int32_t* dims, double mass,
+                                   const double* d_links, msc_stream stream) {
+  if (!out) {
+    set_error("msc_op_create_staggered: out is NULL");
+    return MSC_EINVAL;
+  }
+  *out = nullptr;
+  Stencil<double2> geo;
+  if (!staggered_geometry("msc_op_create_staggered", dims, mass, geo)) return MSC_EINVAL;
+  if (!d_links) {
+    set_error("msc_op_create_staggered: null links");
+    return MSC_EINVAL;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t nw = size_t(4 * 9) * size_t(geo.vol);
+  double2* w64 = nullptr;
+  float2* w32 = nullptr;
+  int64_t* rowptr = nullptr;
+  int32_t* col = nullptr;
+  double2* vals = nullptr;
+  auto cleanup = [&](bool keep_links) {
+    if (rowptr) (void)hipFree(rowptr);
+    if (col) (void)hipFree(col);
+    if (vals) (void)hipFree(vals);
+    if (!keep_links) {
+      dfree(w64);
+      dfree(w32);
+    }
+  };
+  hipError_t e = dalloc(&w64, nw);
+  if (e == hipSuccess) e = dalloc(&w32, nw);
+  if (e == hipSuccess) e = launch_stencil_links(reinterpret_cast<const double2*>(d_links), geo, w64, w32, s);
+  if (e != hipSuccess) {
+    set_error("msc_op_create_staggered: %s", hipGetErrorString(e));
+    cleanup(false);
+    return e == hipErrorOutOfMemory ? MSC_ENOMEM : MSC_EHIP;
+  }
+  Stencil<double2> w = geo;
+  w.w = w64;
+  msc_status rc = staggered_csr(w, &rowptr, &col, &vals, s);
+  const int64_t n = 3 * geo.vol;
+  msc_op op = nullptr;
+  if (rc == MSC_OK)
+    rc = msc_op_create_csr(&op, MSC_A_MHM, n, 25 * n, rowptr, col,
+                           reinterpret_cast<const double*>(vals), stream);
+  if (rc != MSC_OK) {
+    cleanup(false);
+    return rc;
+  }
+  cleanup(true);
+  op->stencil = true;
+  op->w64 = w;
+  op->w32 = Stencil<float2>{};
+  op->w32.w = w32;
+  for (int mu = 0; mu < 4; ++mu) {
+    op->w32.L[mu] = geo.L[mu];
+    op->w32.stride[mu] = geo.stride[mu];
+  }
+  op->w32.vol = geo.vol;
+  op->w32.mass = geo.mass;
+  *out = op;
+  return MSC_OK;
+}
+
+msc_status msc_op_update_links(msc_op op, const double* d_links, msc_stream stream) {
+  if (check_op(op) != MSC_OK) return MSC_EINVAL;
+  if (!op->stencil) {
+    set_error("msc_op_update_links: the operator was not made by msc_op_create_staggered");
+    return MSC_EINVAL;
+  }
+  if (!d_links) {
+    set_error("msc_op_update_links: null links");
+    return MSC_EINVAL;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  HIP_TRY(launch_stencil_links(reinterpret_cast<const double2*>(d_links), op->w64,
+                               const_cast<double2*>(op->w64.w), const_cast<float2*>(op->w32.w), s));
+  int64_t* rowptr = nullptr;
+  int32_t* col = nullptr;
+  double2* vals = nullptr;
+  msc_status rc = staggered_csr(op->w64, &rowptr, &col, &vals, s);
+  if (rc == MSC_OK) rc = update_values_impl(op, reinterpret_cast<const double*>(vals), s);
+  if (rowptr) (void)hipFree(rowptr);
+  if (col) (void)hipFree(col);
+  if (vals) (void)hipFree(vals);
+  return rc;
 }
 
 msc_status msc_op_set_shifts(msc_op op, const double* h_sigma, int32_t ns) {
@@ -1434,6 +1615,11 @@ msc_status msc_solve(msc_op op, const double* d_b, double* d_x, const msc_params
     set_error("msc_solve: no shifts set");
     return MSC_EINVAL;
   }
+  if (op->kind == MSC_A_GENERAL) {
+    set_error("msc_solve: CG-M needs a Hermitian positive-definite A; a general operator "
+              "takes msc_solve_bicgstab");
+    return MSC_EINVAL;
+  }
   msc_params prm;
   if (params)
     prm = *params;
@@ -1463,6 +1649,10 @@ msc_status msc_solve_adjoint(msc_op op, const double* d_g, const double* d_x, do
   }
   if (op->sigma.empty()) {
     set_error("msc_solve_adjoint: no shifts set");
+    return MSC_EINVAL;
+  }
+  if (op->kind == MSC_A_GENERAL) {
+    set_error("msc_solve_adjoint: not available for a general operator");
     return MSC_EINVAL;
   }
   msc_params prm;
@@ -1613,6 +1803,144 @@ msc_status msc_solve_adjoint(msc_op op, const double* d_g, const double* d_x, do
   return result;
 }
 
+msc_status msc_solve_bicgstab(msc_op op, const double* d_b, double* d_x,
+                              const msc_params* params, msc_info* info, msc_stream stream) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (check_op(op) != MSC_OK) return MSC_EINVAL;
+  if (!d_b || !d_x) {
+    set_error("msc_solve_bicgstab: null b or x");
+    return MSC_EINVAL;
+  }
+  if (op->sigma.empty()) {
+    set_error("msc_solve_bicgstab: no shifts set");
+    return MSC_EINVAL;
+  }
+  if (op->kind == MSC_A_MHM) {
+    set_error("msc_solve_bicgstab: A = M^H M is Hermitian positive definite: use msc_solve "
+              "(or create the operator of M itself with kind MSC_A_GENERAL)");
+    return MSC_EINVAL;
+  }
+  msc_params prm;
+  if (params)
+    prm = *params;
+  else
+    msc_params_default(&prm);
+  if (!(prm.tol >= 0.0) || prm.prec != MSC_PREC_FP64 || prm.reserved != 0) {
+    set_error("msc_solve_bicgstab: invalid tol, precision (FP64 only) or reserved");
+    return MSC_EINVAL;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int ns = int(op->sigma.size());
+  const int64_t n = op->n;
+  msc_status rc = ensure_scratch(op);
+  if (rc != MSC_OK) return rc;
+  // buffers: r[2], p, v, s, t (n each), ns directions, the state
+  const size_t vec = sizeof(double2) * size_t(n);
+  const size_t need = vec * (6 + size_t(ns)) + sizeof(BcgState) + 256;
+  if (op->bcg_bytes < need) {
+    if (op->bcg) (void)hipFree(op->bcg);
+    op->bcg = nullptr;
+    op->bcg_bytes = 0;
+    HIP_TRY(hipMalloc(&op->bcg, need));
+    op->bcg_bytes = need;
+  }
+  unsigned char* base = static_cast<unsigned char*>(op->bcg);
+  BcgArgs a{};
+  a.n = n;
+  a.ns = ns;
+  a.lanes = choose_lanes(op, prm);
+  a.m = Csr<double2>{op->rowptr, op->col, op->val64};
+  a.b = reinterpret_cast<const double2*>(d_b);
+  a.x = reinterpret_cast<double2*>(d_x);
+  double2* vbase = reinterpret_cast<double2*>(base);
+  a.r[0] = vbase;
+  a.r[1] = vbase + n;
+  a.p = vbase + 2 * n;
+  a.v = vbase + 3 * n;
+  a.s = vbase + 4 * n;
+  a.t = vbase + 5 * n;
+  a.pk = vbase + 6 * n;
+  a.st = reinterpret_cast<BcgState*>(base + vec * (6 + size_t(ns)));
+  a.partial = op->scratch.partial;
+  a.tickets = op->scratch.tickets + 12 * kTicketSite;
+
+  std::vector<int> order(ns);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int i, int j) { return op->sigma[i] < op->sigma[j]; });
+  BcgState h{};
+  h.sigma0 = op->sigma[order[0]];
+  h.eps2 = prm.tol * prm.tol;  // scaled by |b|^2 in the init kernel
+  h.al_prev = double2{1.0, 0.0};
+  h.be_prev = double2{0.0, 0.0};
+  h.max_iter = prm.max_iter;
+  h.ns = ns;
+  h.upd_launch = -1;
+  for (int j = 0; j < ns; ++j) {
+    h.s[j] = op->sigma[order[j]] - h.sigma0;
+    h.z[j] = h.z_old[j] = h.tau[j] = double2{1.0, 0.0};
+    h.active[j] = 1;
+    h.freeze_iter[j] = -1;
+    h.orig[j] = order[j];
+  }
+  HIP_TRY(hipMemcpyAsync(a.st, &h, sizeof h, hipMemcpyHostToDevice, s));
+  HIP_TRY(launch_bcg_init(a, s));
+  const int G = std::max(1, prm.poll_every);
+  int launched = 0;
+  bool done = prm.max_iter <= 0;
+  while (!done) {
+    for (int g = 0; g < G; ++g) {
+      HIP_TRY(launch_bcg_iteration(a, launched, s));
+      ++launched;
+    }
+    int halt = 0;
+    HIP_TRY(hipMemcpyAsync(&halt, &a.st->halt, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (halt || launched >= prm.max_iter + G) done = true;
+  }
+  HIP_TRY(hipMemcpyAsync(&h, a.st, sizeof h, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  std::vector<double> rel(ns, 0.0);
+  const double bn = std::sqrt(h.bnorm2);
+  if (prm.verify && h.status == 0 && bn > 0.0) {
+    MsArgs va = make_args(op, a.lanes, d_b, d_x);
+    for (int k0 = 0; k0 < ns; k0 += 8) {
+      const int kc = std::min(8, ns - k0);
+      HIP_TRY(launch_verify(va, op->sigma.data(), k0, kc, nullptr, s));
+    }
+    std::vector<double> r2(ns);
+    HIP_TRY(hipMemcpyAsync(r2.data(), op->scratch.res2, sizeof(double) * ns, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int k = 0; k < ns; ++k) rel[k] = std::sqrt(r2[k]) / bn;
+  }
+  bool all_ok = true;
+  for (int j = 0; j < ns; ++j)
+    if (h.iter > 0 && h.active_next[j]) all_ok = false;  // still advanced at the end
+  if (prm.verify)
+    for (int k = 0; k < ns; ++k)
+      if (!(rel[k] <= prm.tol)) all_ok = false;
+  if (info) {
+    clear_timing(*info);
+    info->iters = h.iter;
+    info->refine_iters = 0;
+    info->n_reliable = 0;
+    info->n_refined = 0;
+    info->iters_fp64 = h.iter;
+    info->alg_bytes = 0.0;
+    if (info->true_rel_res)
+      for (int k = 0; k < ns; ++k) info->true_rel_res[k] = rel[k];
+    if (info->freeze_iter)
+      for (int j = 0; j < ns; ++j) info->freeze_iter[order[j]] = h.freeze_iter[j];
+    info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  if (h.status != 0) {
+    set_error("msc_solve_bicgstab: breakdown (w^H v, t^H t or rho vanished, 1 + s om = 0, "
+              "or a non-finite value) at iteration %d", h.iter);
+    return MSC_EBREAKDOWN;
+  }
+  return all_ok ? MSC_OK : MSC_ENOTCONV;
+}
+
 msc_status msc_solve_batched(int32_t nsys, const msc_op* ops, const int32_t* nrhs,
                              const double* const* d_b, double* const* d_x,
                              const msc_params* params, msc_info* info, msc_stream stream) {
@@ -1637,10 +1965,11 @@ msc_status msc_solve_batched(int32_t nsys, const msc_op* ops, const int32_t* nrh
   int rr = 1, max_nrhs = 0;
   for (int s = 0; s < nsys; ++s) {
     const msc_op op = ops[s];
-    if (!op || op->sigma.empty() || int(op->sigma.size()) > kBatchMaxShifts || nrhs[s] < 1 ||
+    if (!op || op->kind == MSC_A_GENERAL || op->sigma.empty() ||
+        int(op->sigma.size()) > kBatchMaxShifts || nrhs[s] < 1 ||
         nrhs[s] > kBatchMaxRhs || !d_b[s] || !d_x[s]) {
-      set_error("msc_solve_batched: system %d: need an operator with 1..%d shifts, 1..%d "
-                "right-hand sides and non-null b and x", s, kBatchMaxShifts, kBatchMaxRhs);
+      set_error("msc_solve_batched: system %d: need a Hermitian operator with 1..%d shifts, "
+                "1..%d right-hand sides and non-null b and x", s, kBatchMaxShifts, kBatchMaxRhs);
       return MSC_EINVAL;
     }
     max_nrhs = std::max(max_nrhs, int(nrhs[s]));
@@ -1675,6 +2004,9 @@ void msc_op_destroy(msc_op op) {
   dfree(op->val32_h);
   free_sell(op->sell_m);
   free_sell(op->sell_mh);
+  if (op->bcg) (void)hipFree(op->bcg);
+  if (op->w64.w) (void)hipFree(const_cast<double2*>(op->w64.w));
+  if (op->w32.w) (void)hipFree(const_cast<float2*>(op->w32.w));
   delete op;
 }
 

@@ -44,6 +44,14 @@ struct RotState {
   int active[kMaxShifts];      // shift j still updated
 };
 
+// Reliable updates of the complex64 phase: the host launches the update kernels every
+// kRuCheck iterations; they run when the period (msc_params::reliable_every) is due, or
+// when the recursive |r|^2 has dropped below kRuDelta2 times its value at the last update
+// (a residual that falls fast would otherwise run far below what the complex64 operator
+// can certify before the next replacement).
+constexpr int kRuCheck = 10;
+constexpr double kRuDelta2 = 1e-2;
+
 // Head launches whose update mode is recorded for the byte model of sampled timings.
 constexpr int kMaxSamples = 256;
 
@@ -75,6 +83,7 @@ struct SolveState {
   int n_reliable;
   int kstatus;       // 1: a K2 found p^H (A + sigma0) p <= 0
   int pad_;
+  double R_ru;       // |r|^2 right after the last reliable update (or the precision switch)
   double s[kMaxShifts];         // sigma_j - sigma0
   double zeta_prev[kMaxShifts]; // zeta_j^(n-1)
   double zk[kMaxShifts];        // zeta_j^(n+1) of the current iteration (K2 -> head)
@@ -133,6 +142,19 @@ template <class V> struct Sell {
   // half, at col16[c kSlice + l].
   const uint32_t* col16 = nullptr;
   const int32_t* cbase = nullptr;
+};
+
+// Matrix-free staggered operator M = m + D on a periodic 4-D lattice (every extent >= 3):
+// w holds W_mu(x) = eta_mu(x)/2 U_mu(x) as [4][V][3][3] (direction-major, site x0
+// fastest, row-major 3x3), so that
+//   (D v)(x) = sum_mu [ W_mu(x) v(x + mu) - W_mu(x - mu)^H v(x - mu) ]
+// (eta_mu does not depend on x_mu).  Row 3 s + c of M is colour c of site s.
+template <class V> struct Stencil {
+  const V* w = nullptr;
+  int32_t L[4] = {0, 0, 0, 0};
+  int64_t stride[4] = {0, 0, 0, 0};  // 1, L0, L0 L1, L0 L1 L2
+  int64_t vol = 0;
+  double mass = 0.0;
 };
 
 // Device buffers of one sliced ELLPACK matrix (both value precisions share the columns).
@@ -208,10 +230,15 @@ struct msc_op_s {
   msc::Workspace ws;
   msc::BssWorkspace bws;
   msc::Scratch scratch;
+  void* bcg = nullptr;           // BiCGStab-M buffers (one allocation), bcg_ns shifts
+  size_t bcg_bytes = 0;
   double2* yadj = nullptr;       // adjoint solutions, ns * n complex128
   size_t yadj_count = 0;
   double* adj_small = nullptr;   // 256 doubles: Gram sums and shift factors
   int lanes64 = 0, lanes32 = 0;  // chosen lanes per row (0 = not yet tuned)
+  bool stencil = false;          // matrix-free staggered operator (links kept below)
+  msc::Stencil<double2> w64;     // W_mu(x) = eta_mu(x)/2 U_mu(x), complex128 and
+  msc::Stencil<float2> w32;      // complex64 copies (device memory owned by the op)
   bool sell = false;             // sliced ELLPACK copies built (M, and M^H for kind MHM)
   msc::SellStore sell_m, sell_mh;
 };
@@ -239,6 +266,14 @@ hipError_t build_sell(const int32_t* rowptr, const int32_t* col, const double2* 
 hipError_t refill_sell(const int32_t* rowptr, const int32_t* col, const double2* val64, int64_t n,
                        const SellStore& out, hipStream_t s);
 void free_sell(SellStore& out);
+// Matrix-free staggered operator set-up: w64 = eta/2 U from the caller's complex128
+// links [4][V][3][3], w32 = complex64 copy; and the scalar CSR of M = m + D built from
+// w64 (25 entries per row, columns sorted): rowptr int64[n+1], col int32[25n],
+// vals complex128[25n].
+hipError_t launch_stencil_links(const double2* links, const Stencil<double2>& geo,
+                                double2* w64, float2* w32, hipStream_t s);
+hipError_t launch_stencil_csr(const Stencil<double2>& op, int64_t* rowptr, int32_t* col,
+                              double2* vals, hipStream_t s);
 
 // multishift.hip
 struct MsArgs {
@@ -262,6 +297,10 @@ struct MsArgs {
   int* hflag;            // host-coherent word: halt | switch_req << 1 of the next state
   int steps;             // steps of the all-shift update folded into one pass (1..kMaxSteps)
   int defer_ok;          // 1: this launch's head may defer its all-shift update
+  int ru_force;          // reliable-update launch: 1 runs it whatever the residual
+  int stencil;           // the head and K2 apply M and M^H from links (kind MHM, sell = 1)
+  Stencil<double2> w64;
+  Stencil<float2> w32;
   int sample;            // slot of SolveState::smp_* for this head, -1: not sampled
   double2* t64;
   SolveState* st;
@@ -285,6 +324,38 @@ hipError_t launch_apply(int kind, int prec, int lanes, int64_t n, const Csr<doub
                         double shift, void* tmp_a, void* tmp_b, hipStream_t s);
 
 int default_grid(int64_t n, int lanes);
+
+// bicgstab.hip -- multishift BiCGStab for a general A (complex FP64 scalars)
+struct BcgCoef {
+  double2 xp, xs;          // x(s) += xp p(s) + xs s
+  double2 pr, pp, po, ps;  // p(s) <- pr r' + pp p(s) + po r + ps s
+};
+struct BcgState {
+  double sigma0, bnorm2, eps2, R;
+  double2 rho, alpha, omega, beta, al_prev, be_prev;
+  int iter, max_iter, halt, status, rotate, upd_launch, ns, pad_;
+  double s[kMaxShifts];              // sigma_j - sigma0, shifts sorted ascending
+  double2 z[kMaxShifts], z_old[kMaxShifts], z_new[kMaxShifts];
+  double2 tau[kMaxShifts], tau_new[kMaxShifts];
+  double2 al_s[kMaxShifts], om_s[kMaxShifts];
+  BcgCoef cf[kMaxShifts];
+  int active[kMaxShifts], active_next[kMaxShifts], freeze_iter[kMaxShifts], orig[kMaxShifts];
+};
+struct BcgArgs {
+  int64_t n;
+  int ns, lanes, par;
+  Csr<double2> m;
+  const double2* b;       // right-hand side, also the shadow vector
+  double2* x;             // caller's x, shift-major, caller order
+  double2* r[2];          // r_n and r_{n+1} alternate
+  double2 *p, *v, *s, *t;
+  double2* pk;            // ns directions, sorted order
+  BcgState* st;
+  double* partial;        // >= 4 kMaxGrid doubles
+  unsigned* tickets;      // one ticket site
+};
+hipError_t launch_bcg_init(const BcgArgs& a, hipStream_t s);
+hipError_t launch_bcg_iteration(const BcgArgs& a, int launch, hipStream_t s);
 
 // batched_cg.hip -- m <= kBssMax single-shift systems sharing one operator
 constexpr int kBssMax = 16;

@@ -29,6 +29,7 @@
 #include "dev_common.h"
 #include "msc_internal.h"
 #include "sell_load.h"
+#include "stencil.h"
 
 namespace msc {
 
@@ -44,6 +45,9 @@ template <> __device__ __forceinline__ Csr<double2> pick_mh<double>(const MsArgs
 template <class R> __device__ __forceinline__ Sell<cplx<R>> pick_sm(const MsArgs& a);
 template <> __device__ __forceinline__ Sell<float2> pick_sm<float>(const MsArgs& a) { return a.s32; }
 template <> __device__ __forceinline__ Sell<double2> pick_sm<double>(const MsArgs& a) { return a.s64; }
+template <class R> __device__ __forceinline__ Stencil<cplx<R>> pick_w(const MsArgs& a);
+template <> __device__ __forceinline__ Stencil<float2> pick_w<float>(const MsArgs& a) { return a.w32; }
+template <> __device__ __forceinline__ Stencil<double2> pick_w<double>(const MsArgs& a) { return a.w64; }
 template <class R> __device__ __forceinline__ Sell<cplx<R>> pick_shm(const MsArgs& a);
 template <> __device__ __forceinline__ Sell<float2> pick_shm<float>(const MsArgs& a) { return a.sh32; }
 template <> __device__ __forceinline__ Sell<double2> pick_shm<double>(const MsArgs& a) { return a.sh64; }
@@ -127,6 +131,15 @@ __device__ __forceinline__ cplx<R> next_dir(double b, const cplx<R>& r, const cp
   v.y = fma(b, pd.y, rd.y);
   return from_d<R>(v);
 }
+
+// Directions per round trip of the matrix-free staggered rows: the head (which gathers
+// r and p at every neighbour) and K2.
+#ifndef MSC_STENCIL_DPR_HEAD
+#define MSC_STENCIL_DPR_HEAD 1
+#endif
+#ifndef MSC_STENCIL_DPR_K2
+#define MSC_STENCIL_DPR_K2 2
+#endif
 
 // Pairs per round trip when each entry gathers two vectors (MSC_SELL_KPN32 / 64).
 #ifndef MSC_SELL_KPN32
@@ -697,7 +710,8 @@ __global__ __launch_bounds__(kBlock) void k_update(MsArgs a) {
 // its own row (x, p_j, and p' = r + b p stored in the other buffer), then t = M p' takes
 // p' at the gathered columns from r and the old p, rounded exactly as the owning lane
 // rounds it; P = |t|^2 + sigma0 |p'|^2 (A = M^H M) or Re p'^H t + sigma0 |p'|^2.
-template <class R, bool MHM>
+// ST: M is applied from the links (matrix-free staggered operator, A = M^H M).
+template <class R, bool MHM, bool ST = false>
 __global__ __launch_bounds__(kBlock) void k1_fused(MsArgs a) {
   const SolveState* st = a.st;
   const RotState& rs = st->rot[a.par];
@@ -749,10 +763,17 @@ __global__ __launch_bounds__(kBlock) void k1_fused(MsArgs a) {
         p_row = next_dir<R>(bn, r_i, p_i);
     }
     if (!pl.spmv) continue;
-    const cplx<R> d = m.diag[rr];
     // without a pending update p' = p: the same product with r := p and b = 0 (exact)
-    cplx<R> v = sell_row_next<R>(m, upd ? rv : pv, pv, bn, sl, lane);
-    cfma<R>(v, d, p_row);
+    cplx<R> v;
+    if constexpr (ST) {
+      const cplx<R>* __restrict__ rg = upd ? rv : pv;
+      v = stencil_row<R, MSC_STENCIL_DPR_HEAD>(pick_w<R>(a), rr, p_row, 1,
+                         [&](int64_t c) { return next_dir<R>(bn, rg[c], pv[c]); });
+    } else {
+      const cplx<R> d = m.diag[rr];
+      v = sell_row_next<R>(m, upd ? rv : pv, pv, bn, sl, lane);
+      cfma<R>(v, d, p_row);
+    }
     if (live) {
       t[row] = v;
       if (MHM)
@@ -846,7 +867,8 @@ __global__ __launch_bounds__(kBlock) void k2_mhm(MsArgs a) {
 }
 
 // ---- K2 on the sliced ELLPACK copy of M^H: one row per lane, one slice per wave ------
-template <class R>
+// ST: M^H = m - D applied from the links instead.
+template <class R, bool ST = false>
 __global__ __launch_bounds__(kBlock) void k2_sell(MsArgs a) {
   const SolveState* st = a.st;
   const RotState& ns = st->rot[a.par ^ 1];  // written by this iteration's head
@@ -873,12 +895,16 @@ __global__ __launch_bounds__(kBlock) void k2_sell(MsArgs a) {
     const int64_t row = sl * kSlice + lane;
     const int64_t rr = row < a.n ? row : a.n - 1;  // lanes past n read a valid row, unused
     const cplx<R> tr = t[rr];
-    const cplx<R> d = mh.diag[rr];
     Row o;
     o.p = p[rr];
     o.r = r[rr];
-    o.q = sell_row<R>(mh, t, sl, lane);
-    cfma<R>(o.q, d, tr);
+    if constexpr (ST) {
+      o.q = stencil_row<R, MSC_STENCIL_DPR_K2>(pick_w<R>(a), rr, tr, -1, [&](int64_t c) { return t[c]; });
+    } else {
+      const cplx<R> d = mh.diag[rr];
+      o.q = sell_row<R>(mh, t, sl, lane);
+      cfma<R>(o.q, d, tr);
+    }
     return o;
   };
   auto epilogue = [&](int64_t sl, const Row& o) {
@@ -999,12 +1025,24 @@ __global__ __launch_bounds__(kBlock) void k_switch(MsArgs a64, MsArgs a32, int n
       rs.halt = 0;
       rs.switch_req = 0;
       st->sw_eps2 = 0.0;
+      st->R_ru = rs.R;
     }
   }
 }
 
 // ---- reliable update: r = b - (A + sigma0) x_0 in FP64, between the head and K2 ----------
+// Launched at check points; runs (in every workgroup alike) when forced by the period or
+// when the recursive residual has dropped by kRuDelta2 in |r|^2 since the last one.
+__device__ __forceinline__ bool ru_due(const MsArgs& a) {
+  const SolveState* st = a.st;
+  const RotState& ns = st->rot[a.par ^ 1];  // written by this iteration's head
+  if (ns.halt) return false;
+  return a.ru_force || ns.R < kRuDelta2 * st->R_ru;
+}
+
 // After each workgroup's share of |r|^2 (acc per thread): the last workgroup replaces R.
+// The update never halts the sequence (K2 decides on the replaced residual), so heads
+// before it may defer their all-shift update; a non-finite residual is a breakdown.
 __device__ void ru_finish(const MsArgs& a, double acc) {
   SolveState* st = a.st;
   // region 2: the head's partials in region 0 still wait for K2
@@ -1016,12 +1054,10 @@ __device__ void ru_finish(const MsArgs& a, double acc) {
   if (threadIdx.x == 0) {
     RotState& rs = st->rot[a.par ^ 1];
     rs.R = Rt;
+    st->R_ru = Rt;
     st->n_reliable += 1;
     if (!isfinite(Rt)) {
       rs.status = 1;
-      rs.halt = 1;
-      store_host_flag(a.hflag, 1);
-    } else if (Rt <= st->eps2) {
       rs.halt = 1;
       store_host_flag(a.hflag, 1);
     }
@@ -1032,8 +1068,7 @@ template <int L, bool MHM>
 __global__ __launch_bounds__(kBlock) void k_ru_first(MsArgs a) {
   // t64 = M x_0 (A = M^H M) -- first half of the FP64 operator
   const SolveState* st = a.st;
-  const RotState& ns = st->rot[a.par ^ 1];  // written by this iteration's head
-  if (ns.halt) return;
+  if (!ru_due(a)) return;
   const double2* __restrict__ x0 = a.x + int64_t(st->orig[0]) * a.n;
   constexpr int GPB = kBlock / L;
   const int lane = threadIdx.x % L, grp = threadIdx.x / L;
@@ -1048,7 +1083,7 @@ __global__ __launch_bounds__(kBlock) void k_ru_first(MsArgs a) {
 template <class R, int L, bool MHM>
 __global__ __launch_bounds__(kBlock) void k_ru_second(MsArgs a) {
   SolveState* st = a.st;
-  if (st->rot[a.par ^ 1].halt) return;
+  if (!ru_due(a)) return;
   const double2* __restrict__ x0 = a.x + int64_t(st->orig[0]) * a.n;
   cplx<R>* __restrict__ r = static_cast<cplx<R>*>(a.r);
   const double sigma0 = st->sigma0;
@@ -1075,7 +1110,7 @@ __global__ __launch_bounds__(kBlock) void k_ru_second(MsArgs a) {
 // The same on the sliced ELLPACK copies: one row per lane, one slice per wavefront.
 __global__ __launch_bounds__(kBlock) void k_ru_first_s(MsArgs a) {
   const SolveState* st = a.st;
-  if (st->rot[a.par ^ 1].halt) return;
+  if (!ru_due(a)) return;
   const double2* __restrict__ x0 = a.x + int64_t(st->orig[0]) * a.n;
   constexpr int SPB = kBlock / kSlice;
   const int lane = threadIdx.x % kSlice;
@@ -1094,7 +1129,7 @@ __global__ __launch_bounds__(kBlock) void k_ru_first_s(MsArgs a) {
 template <class R, bool MHM>
 __global__ __launch_bounds__(kBlock) void k_ru_second_s(MsArgs a) {
   SolveState* st = a.st;
-  if (st->rot[a.par ^ 1].halt) return;
+  if (!ru_due(a)) return;
   const double2* __restrict__ x0 = a.x + int64_t(st->orig[0]) * a.n;
   cplx<R>* __restrict__ r = static_cast<cplx<R>*>(a.r);
   const double sigma0 = st->sigma0;
@@ -1381,8 +1416,11 @@ hipError_t iteration_impl(const MsArgs& args, hipStream_t s, hipEvent_t* ev, boo
     a.gk1 = g1;
     a.gk2 = a.kind == MSC_A_MHM ? g1 : g3;
   }
+  const bool st = a.sell && a.stencil && a.kind == MSC_A_MHM;
   if (a.sell) {
-    if (a.kind == MSC_A_MHM)
+    if (st)
+      launch_timed(k1_fused<R, true, true>, g3, s, ev, 0, a);
+    else if (a.kind == MSC_A_MHM)
       launch_timed(k1_fused<R, true>, g3, s, ev, 0, a);
     else
       launch_timed(k1_fused<R, false>, g3, s, ev, 0, a);
@@ -1399,7 +1437,9 @@ hipError_t iteration_impl(const MsArgs& args, hipStream_t s, hipEvent_t* ev, boo
     if (e != hipSuccess) return e;
   }
   if (a.kind == MSC_A_MHM) {
-    if (a.sell) {
+    if (st) {
+      launch_timed(k2_sell<R, true>, g3, s, ev, 1, a);
+    } else if (a.sell) {
       launch_timed(k2_sell<R>, g3, s, ev, 1, a);
     } else {
       MSC_LANES_SWITCH(a.lanes, (launch_timed(k2_mhm<R, LL>, g1, s, ev, 1, a)));

@@ -2,6 +2,7 @@
 // conjugate transpose M^H (counting sort by column, then a per-row sort so the result
 // is deterministic), and the sliced ELLPACK copies the iteration SpMVs read.  Runs once
 // per operator (the values again after an update); not on the iteration path.
+#include <algorithm>
 #include <vector>
 
 #include "dev_common.h"
@@ -425,6 +426,119 @@ hipError_t build_sell(const int32_t* rowptr, const int32_t* col, const double2* 
     m.cbase = nullptr;
   }
   return hipSuccess;
+}
+
+// ---- matrix-free staggered operator --------------------------------------------------
+namespace {
+
+// w = eta_mu(x)/2 U_mu(x) (complex128 and complex64), one thread per link entry.
+__global__ void k_stencil_links(const double2* __restrict__ links, Stencil<double2> geo,
+                                double2* __restrict__ w64, float2* __restrict__ w32) {
+  const int64_t total = 4 * geo.vol * 9;
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < total;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t link = i / 9;
+    const int mu = int(link / geo.vol);
+    int64_t rem = link - int64_t(mu) * geo.vol;
+    // eta_mu(x) = (-1)^(x_0 + ... + x_{mu-1})
+    int parity = 0;
+    for (int nu = 0; nu < mu; ++nu) {
+      parity += int(rem % geo.L[nu]);
+      rem /= geo.L[nu];
+    }
+    const double h = (parity & 1) ? -0.5 : 0.5;
+    const double2 u = links[i];
+    const double2 v{h * u.x, h * u.y};
+    w64[i] = v;
+    w32[i] = float2{float(v.x), float(v.y)};
+  }
+}
+
+// The scalar CSR of M = m + D from w, one thread per row: the row's own site (the mass
+// on the diagonal) and its eight neighbours (three columns each), in ascending site order,
+// so the columns come out sorted.
+__global__ void k_stencil_csr(Stencil<double2> op, int64_t* __restrict__ rowptr,
+                              int32_t* __restrict__ col, double2* __restrict__ vals) {
+  const int64_t n = 3 * op.vol;
+  for (int64_t row = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; row <= n;
+       row += int64_t(gridDim.x) * blockDim.x) {
+    rowptr[row] = 25 * row;
+    if (row == n) continue;
+    const int64_t s = row / 3;
+    const int c = int(row - 3 * s);
+    // site and kind of each of the nine blocks: -1 the diagonal, 2 mu forward, 2 mu + 1
+    // backward
+    int64_t site[9];
+    int kind[9];
+    site[0] = s;
+    kind[0] = -1;
+    int64_t rem = s;
+    for (int mu = 0; mu < 4; ++mu) {
+      const int64_t L = op.L[mu];
+      const int64_t xm = rem % L;
+      rem /= L;
+      const int64_t st = op.stride[mu];
+      site[1 + 2 * mu] = xm == L - 1 ? s - (L - 1) * st : s + st;
+      kind[1 + 2 * mu] = 2 * mu;
+      site[2 + 2 * mu] = xm == 0 ? s + (L - 1) * st : s - st;
+      kind[2 + 2 * mu] = 2 * mu + 1;
+    }
+    // insertion sort of the nine distinct sites (every extent >= 3)
+    for (int i = 1; i < 9; ++i) {
+      const int64_t ks = site[i];
+      const int kk = kind[i];
+      int j = i - 1;
+      while (j >= 0 && site[j] > ks) {
+        site[j + 1] = site[j];
+        kind[j + 1] = kind[j];
+        --j;
+      }
+      site[j + 1] = ks;
+      kind[j + 1] = kk;
+    }
+    int64_t e = 25 * row;
+    for (int i = 0; i < 9; ++i) {
+      const int64_t y = site[i];
+      if (kind[i] < 0) {
+        col[e] = int32_t(3 * y + c);
+        vals[e] = double2{op.mass, 0.0};
+        ++e;
+        continue;
+      }
+      const int mu = kind[i] >> 1;
+      const bool forward = (kind[i] & 1) == 0;
+      for (int j = 0; j < 3; ++j) {
+        double2 v;
+        if (forward) {
+          v = op.w[(int64_t(mu) * op.vol + s) * 9 + 3 * c + j];  // W_mu(s)[c][j]
+        } else {
+          const double2 u = op.w[(int64_t(mu) * op.vol + y) * 9 + 3 * j + c];
+          v = double2{-u.x, u.y};                                  // -conj(W_mu(s-mu)[j][c])
+        }
+        col[e] = int32_t(3 * y + j);
+        vals[e] = v;
+        ++e;
+      }
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_stencil_links(const double2* links, const Stencil<double2>& geo,
+                                double2* w64, float2* w32, hipStream_t s) {
+  const int64_t total = 4 * geo.vol * 9;
+  const int64_t g = std::min<int64_t>((total + 255) / 256, 8192);
+  k_stencil_links<<<dim3(unsigned(g)), 256, 0, s>>>(links, geo, w64, w32);
+  return hipGetLastError();
+}
+
+hipError_t launch_stencil_csr(const Stencil<double2>& op, int64_t* rowptr, int32_t* col,
+                              double2* vals, hipStream_t s) {
+  const int64_t rows = 3 * op.vol + 1;
+  const int64_t g = std::min<int64_t>((rows + 255) / 256, 8192);
+  k_stencil_csr<<<dim3(unsigned(g)), 256, 0, s>>>(op, rowptr, col, vals);
+  return hipGetLastError();
 }
 
 }  // namespace msc

@@ -1,0 +1,87 @@
+// Matrix-free staggered operator: the rows of M = m + D and M^H = m - D computed from the
+// link field (Stencil in msc_internal.h) instead of a stored matrix, one row per lane.
+//
+// D v at row 3 s + c reads row c of the four forward links W_mu(s) and column c of the
+// four backward links W_mu(s - mu): per row 12 + 12 link values and 24 gathered values,
+// like the 24 off-diagonal entries of a sliced ELLPACK row but with no column indices,
+// and each link is shared by the three rows of its site and by the neighbour that reads
+// it backwards (paper: Section 3, where the library leaves room for a custom linear
+// operator kernel in place of the stored matrix when an application warrants one).
+#pragma once
+
+#include "dev_common.h"
+#include "msc_internal.h"
+
+namespace msc {
+
+// acc += conj(a) * b
+template <class R>
+__device__ __forceinline__ void cfma_conj(cplx<R>& acc, const cplx<R>& a, const cplx<R>& b) {
+  acc.x = fma(a.x, b.x, acc.x);
+  acc.x = fma(a.y, b.y, acc.x);
+  acc.y = fma(a.x, b.y, acc.y);
+  acc.y = fma(-a.y, b.x, acc.y);
+}
+
+// Hopping part (D v) of row `row`, with v read through gather(col); the four directions
+// are taken DPR at a time, each group's link and vector loads issued before its first
+// multiply-add (DPR = 1 where the gather itself reads two vectors).
+template <class R, int DPR, class G>
+__device__ __forceinline__ cplx<R> stencil_hop(const Stencil<cplx<R>>& op, int64_t row, G gather) {
+  static_assert(DPR == 1 || DPR == 2 || DPR == 4, "directions per round trip");
+  const uint32_t s = uint32_t(row / 3);
+  const int c = int(row - 3 * int64_t(s));
+  uint32_t rem = s;
+  int64_t fwd[4], bwd[4];
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) {
+    const uint32_t L = uint32_t(op.L[mu]);
+    const uint32_t q = rem / L;
+    const uint32_t xm = rem - q * L;
+    rem = q;
+    const int64_t st = op.stride[mu];
+    fwd[mu] = xm == L - 1 ? int64_t(s) - int64_t(L - 1) * st : int64_t(s) + st;
+    bwd[mu] = xm == 0 ? int64_t(s) + int64_t(L - 1) * st : int64_t(s) - st;
+  }
+  cplx<R> fw = czero<R>(), bw = czero<R>();
+#pragma unroll
+  for (int h = 0; h < 4; h += DPR) {
+    cplx<R> uf[DPR][3], ub[DPR][3], gf[DPR][3], gb[DPR][3];
+#pragma unroll
+    for (int d = 0; d < DPR; ++d) {
+      const int mu = h + d;
+      const cplx<R>* __restrict__ wf = op.w + (int64_t(mu) * op.vol + s) * 9 + 3 * c;
+      const cplx<R>* __restrict__ wb = op.w + (int64_t(mu) * op.vol + bwd[mu]) * 9 + c;
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        uf[d][j] = wf[j];
+        ub[d][j] = wb[3 * j];
+        gf[d][j] = gather(3 * fwd[mu] + j);
+        gb[d][j] = gather(3 * bwd[mu] + j);
+      }
+    }
+#pragma unroll
+    for (int d = 0; d < DPR; ++d) {
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        cfma<R>(fw, uf[d][j], gf[d][j]);
+        cfma_conj<R>(bw, ub[d][j], gb[d][j]);
+      }
+    }
+  }
+  return cplx<R>{fw.x - bw.x, fw.y - bw.y};
+}
+
+// Row `row` of M v (sign = +1) or M^H v (sign = -1): m v_row + sign (D v)_row.
+template <class R, int DPR, class G>
+__device__ __forceinline__ cplx<R> stencil_row(const Stencil<cplx<R>>& op, int64_t row,
+                                               const cplx<R>& v_row, int sign, G gather) {
+  const cplx<R> h = stencil_hop<R, DPR>(op, row, gather);
+  const R m = R(op.mass);
+  cplx<R> o;
+  o.x = sign > 0 ? fma(m, v_row.x, h.x) : fma(m, v_row.x, -h.x);
+  o.y = sign > 0 ? fma(m, v_row.y, h.y) : fma(m, v_row.y, -h.y);
+  return o;
+}
+
+}  // namespace msc

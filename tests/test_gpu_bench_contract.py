@@ -32,6 +32,10 @@ def test_bench_line_keeps_the_contract(cuda):
     assert d["max_true_rel_res"] <= 1e-10
     assert d["config"]["workload"].startswith("c1:")
     assert d["fp64_plain"]["steps"] == 2
+    # the matrix-free operator's lines beside the headline
+    mf = d["matrix_free"]
+    assert mf["mixed"]["converged"] is True and mf["fp64"]["converged"] is True
+    assert mf["mixed"]["max_true_rel_res"] <= 1e-10
     rf = d["roofline"]
     assert rf["bound"] == "hbm" and rf["unit"] == "GB/s" and rf["peak"] == 8000.0
     assert rf["frac"] == pytest.approx(rf["achieved"] / rf["peak"], abs=1e-4)

@@ -65,6 +65,31 @@ def test_c1_fp64_every_shift_matches_oracle(c1, cuda):
 
 
 @pytest.mark.timeout(900)
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_c1_stencil_every_shift_matches_oracle(c1, cuda, prec):
+    # the matrix-free operator built from the same links as the recipe's CSR
+    from paper_1102_2143_amd import Operator
+    cfg = W.CONFIGS["c1"]
+    print(f"[gpu] c1 16^4 stencil {prec}: every shift vs oracle", flush=True)
+    links = W.random_su3_links(cfg["dims"], cfg["seed_links"])
+    op = Operator.staggered(links, cfg["dims"], cfg["mass"], device=cuda)
+    op.set_shifts(c1["sigma"])
+    tol, otol = (1e-10, 1e-10) if prec == "fp64" else (1e-12, 1e-13)
+    x, info = op.solve(c1["b"], tol=tol, prec=prec, format="stencil")
+    ref = _c1_oracle(c1, otol)
+    err = _rel(x.cpu().numpy(), ref["x"])
+    print(f"[gpu] c1 stencil {prec} iters gpu={info['iters']} oracle={ref['iters']} "
+          f"max err={err.max():.3e}", flush=True)
+    assert info["status"] == "ok"
+    assert np.all(info["true_rel_res"] <= tol)
+    assert np.all(err <= 1e-8), err
+    if prec == "fp64":
+        assert abs(info["iters"] - ref["iters"]) <= 2
+        assert np.all(np.abs(info["freeze_iter"] - ref["freeze_iter"]) <= 2)
+    op.close()
+
+
+@pytest.mark.timeout(900)
 def test_c1_mixed_every_shift_matches_tightened_oracle(c1, cuda):
     print("[gpu] c1 16^4 mixed at 1e-12: every shift vs oracle at 1e-13", flush=True)
     op = _op(c1, cuda)
@@ -89,24 +114,29 @@ def c2_pure_gauge():
     print("[gpu] c2 pure-gauge problem and FFT closed form", flush=True)
     links, g = W.pure_gauge_links(dims, cfg["seed_links"])
     rowptr, col, vals = W.staggered_csr(links, dims, mass)
-    del links
     n = 3 * W.lattice_volume(dims)
     b = W.gaussian_rhs(n, cfg["seed_b"])
     sigma = W.logspace_shifts(*cfg["shifts"])
     xs = O.pure_gauge_solve(dims, mass, g, b, sigma)
     # spectrum of A = M^H M is that of the free field: [m^2, m^2 + 4]
     kappa = (mass ** 2 + 4.0 + sigma) / (mass ** 2 + sigma)
-    return dict(n=n, rowptr=rowptr, col=col, vals=vals, b=b, sigma=sigma, x=xs, kappa=kappa)
+    return dict(n=n, rowptr=rowptr, col=col, vals=vals, b=b, sigma=sigma, x=xs, kappa=kappa,
+                links=links, dims=dims, mass=mass)
 
 
 @pytest.mark.timeout(900)
-@pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_c2_pure_gauge_every_shift_matches_closed_form(c2_pure_gauge, cuda, prec):
+@pytest.mark.parametrize("prec,fmt", [("fp64", "sell"), ("mixed", "sell"), ("fp64", "stencil"),
+                                      ("mixed", "stencil")])
+def test_c2_pure_gauge_every_shift_matches_closed_form(c2_pure_gauge, cuda, prec, fmt):
     p = c2_pure_gauge
-    print(f"[gpu] c2 32^3x64 pure gauge {prec} at 1e-12: every shift vs FFT", flush=True)
-    op = _op(p, cuda)
+    print(f"[gpu] c2 32^3x64 pure gauge {prec} {fmt} at 1e-12: every shift vs FFT", flush=True)
+    if fmt == "stencil":
+        from paper_1102_2143_amd import Operator
+        op = Operator.staggered(p["links"], p["dims"], p["mass"], device=cuda)
+    else:
+        op = _op(p, cuda)
     op.set_shifts(p["sigma"])
-    x, info = op.solve(p["b"], tol=1e-12, prec=prec)
+    x, info = op.solve(p["b"], tol=1e-12, prec=prec, format=fmt)
     assert info["status"] == "ok", info["status"]
     rho = info["true_rel_res"]
     err = np.array([_rel(x[k].cpu().numpy(), p["x"][k]) for k in range(p["sigma"].size)])

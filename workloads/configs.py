@@ -45,7 +45,7 @@ def staggered_problem(dims, mass, seed_links, seed_b, shifts, nrhs=None):
     n = 3 * lattice_volume(dims)
     b = gaussian_rhs(n, seed_b, nrhs)
     return dict(kind="mhm", dims=tuple(dims), mass=mass, n=n, rowptr=rowptr, col=col,
-                vals=vals, b=b, sigma=logspace_shifts(*shifts))
+                vals=vals, b=b, sigma=logspace_shifts(*shifts), links=links)
 
 
 def _batch_systems(cfg):
