@@ -13,6 +13,9 @@ Contents (each function cites the passage of the paper it follows):
 * :mod:`oracle.bicgstab` -- textbook BiCGStab and the multishift BiCGStab-M (the
                             paper's second shifted solver, Sections 1 and 3) for
                             non-Hermitian A, derived from the BiCG polynomials.
+* :mod:`oracle.osborn`   -- a different right-hand side per shift (Section 5, eq.
+                            linprobgen): initial guesses that leave every shifted system
+                            the same residual, then one CG-M.
 * :mod:`oracle.direct`   -- the plain definition x_k = (A + sigma_k I)^{-1} b: dense
                             solve, the free-field Fourier closed form and the pure-gauge
                             closed form.
@@ -25,6 +28,7 @@ from .operators import csr_matrix_of, shifted_apply, adjoint_csr
 from .cgm import cg_m
 from .cg import cg
 from .bicgstab import bicgstab, bicgstab_m
+from .osborn import common_residual_guesses, multi_rhs_solve
 from .direct import dense_from_csr, dense_solve, free_field_solve, pure_gauge_solve
 from .gradient import (
     dense_reference_gradient,
@@ -43,6 +47,8 @@ __all__ = [
     "cg",
     "bicgstab",
     "bicgstab_m",
+    "common_residual_guesses",
+    "multi_rhs_solve",
     "dense_from_csr",
     "dense_solve",
     "free_field_solve",
