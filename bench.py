@@ -108,8 +108,9 @@ def paper_table1_line(args, dev):
     """The paper's own benchmark workload (Table 1): the 2-D 5-point Poisson matrix on a
     1000 x 1000 grid with 15 shifts, b = 1 as in its Fig. 1 example, ms per CG-M iteration.
     The shifts are not given for Table 1; here they are 15 log-spaced in [1e-3, 1].  The
-    matrix is real but runs through the complex path (zero imaginary parts), so every
-    value moves twice the bytes of a real-valued solver."""
+    real-valued path (msc_solve_real: double, and float with FP64 reductions for the
+    paper's single-precision column) is the like-for-like comparison; the complex path on
+    the same matrix (zero imaginary parts, twice the bytes) is reported beside it."""
     import torch
     import workloads as W
     from paper_1102_2143_amd import Operator
@@ -140,6 +141,24 @@ def paper_table1_line(args, dev):
         ref = PAPER_T10_MS_PER_ITER["fp64" if name == "fp64" else "fp32"]
         out[name] = {"ms_per_iter": round(ms, 4), "iters": info["iters"],
                      "t10_over_mi355x": round(ref / ms, 1)}
+        log(f"paper workload {name}: {ms:.4f} ms per iteration ({info['iters']} iterations)")
+    br = torch.ones(n, dtype=torch.float64, device=dev)
+    xr = torch.empty((15, n), dtype=torch.float64, device=dev)
+    for name, prec in (("real_fp64", "fp64"), ("real_single", "mixed")):
+        kw = dict(tol=1e-5, max_iter=2000, verify=False, prec=prec)
+        op.solve_real(br, out=xr, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        iters = 0
+        for _ in range(max(1, args.steps)):
+            _, info = op.solve_real(br, out=xr, **kw)
+            iters += info["iters"]
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / iters
+        ref = PAPER_T10_MS_PER_ITER["fp64" if prec == "fp64" else "fp32"]
+        out[name] = {"ms_per_iter": round(ms, 4), "iters": info["iters"],
+                     "t10_over_mi355x": round(ref / ms, 1),
+                     "effective_gbs": round(info["alg_bytes"] / info["iters"] / (ms * 1e-3) / 1e9, 1)}
         log(f"paper workload {name}: {ms:.4f} ms per iteration ({info['iters']} iterations)")
     op.close()
     return out

@@ -260,6 +260,47 @@ msc_status msc_solve_bicgstab(msc_op op, const double* d_b, double* d_x,
                               const msc_params* params, msc_info* info, msc_stream stream);
 
 /*
+ * The multishift solve for a real symmetric positive-definite A (paper: Section 4,
+ * Table 1 -- the paper's benchmark matrix, the 2-D 5-point Poisson operator, is real):
+ * the same recurrences as msc_solve on real vectors and a real copy of the sliced ELLPACK
+ * matrix, half the bytes of the complex path.  The operator must be of kind MSC_A_HERM,
+ * have its sliced copy (msc_op_storage), and every stored imaginary part must be 0
+ * (checked on the first call; MSC_EINVAL otherwise).
+ *   d_b : device double[n] (real)
+ *   d_x : device double[ns*n], shift-major, caller's shift order
+ * params->prec: MSC_PREC_FP64 (double storage and arithmetic) or MSC_PREC_MIXED (float
+ * vectors and matrix, FP64 reductions and shift scalars; meant for moderate tolerances
+ * such as the paper's 1e-5: no reliable update or refinement).  x_k is kept in FP64.
+ * Returns MSC_OK when the driving residual reached tol and (with verify) every shift's
+ * FP64 true residual is below tol, MSC_ENOTCONV otherwise, MSC_EBREAKDOWN on a breakdown.
+ * info: iters, true_rel_res, freeze_iter, alg_bytes; timing fields are zero.
+ */
+msc_status msc_solve_real(msc_op op, const double* d_b, double* d_x, const msc_params* params,
+                          msc_info* info, msc_stream stream);
+
+/*
+ * A different right-hand side per shift, (A + sigma_k I) x_k = b_k (paper: Section 5,
+ * eq. linprobgen), for kinds MSC_A_MHM and MSC_A_HERM with distinct shifts.  The
+ * library forms, with ns - 1 products with A in FP64, initial guesses x0_k that leave
+ * every shifted system the same residual r0 (from the Newton interpolant of the b_k
+ * over the shifts), solves (A + sigma_k) d_k = r0 for all k with one multishift solve
+ * (params->prec as for msc_solve) stopped at tol min_k |b_k| / |r0|, sets
+ * x_k = x0_k + d_k, and checks every shift against its own b_k in FP64, continuing the
+ * ones above tol with the batched CG (up to refine_max_iter iterations).  The guesses
+ * grow with the spread of the shifts (the interpolant is evaluated far outside their
+ * interval); when tol min_k |b_k| / |r0| falls below 1e-14, or the shifts repeat, they
+ * are dropped and every shift is solved from zero by the batched CG.
+ *   d_B : complex128[ns*n], shift-major in the caller's shift order (b_k at 2*k*n)
+ *   d_x : complex128[ns*n], same layout
+ * info (may be NULL): iters = multishift iterations (0 when the guesses were dropped or
+ * already exact), refine_iters = batched CG iterations, true_rel_res = FP64
+ * |b_k - (A + sigma_k) x_k| / |b_k|.  Returns MSC_OK when every shift meets tol,
+ * MSC_ENOTCONV otherwise, MSC_EBREAKDOWN on a breakdown.
+ */
+msc_status msc_solve_multi_rhs(msc_op op, const double* d_B, double* d_x,
+                               const msc_params* params, msc_info* info, msc_stream stream);
+
+/*
  * Many independent multishift solves in one launch sequence: system s uses ops[s]
  * (each with its own shifts) and nrhs[s] right-hand sides at d_b[s]
  * (complex128[nrhs[s]*n_s], rhs-major); solutions go to d_x[s]

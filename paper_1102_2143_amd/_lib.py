@@ -25,7 +25,7 @@ EXPORTED = (
     "msc_op_create_staggered", "msc_op_update_links", "msc_op_update_values",
     "msc_op_set_shifts", "msc_op_query", "msc_op_storage", "msc_op_apply",
     "msc_solve", "msc_solve_adjoint", "msc_solve_bicgstab",
-    "msc_solve_batched",
+    "msc_solve_multi_rhs", "msc_solve_real", "msc_solve_batched",
     "msc_op_destroy",
 )
 
@@ -112,6 +112,10 @@ def load():
     lib.msc_solve.restype = i32
     lib.msc_solve_bicgstab.argtypes = [vp, vp, vp, ctypes.POINTER(Params), ctypes.POINTER(Info), vp]
     lib.msc_solve_bicgstab.restype = i32
+    lib.msc_solve_multi_rhs.argtypes = [vp, vp, vp, ctypes.POINTER(Params), ctypes.POINTER(Info), vp]
+    lib.msc_solve_multi_rhs.restype = i32
+    lib.msc_solve_real.argtypes = [vp, vp, vp, ctypes.POINTER(Params), ctypes.POINTER(Info), vp]
+    lib.msc_solve_real.restype = i32
     lib.msc_solve_adjoint.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(Params),
                                       ctypes.POINTER(Info), vp]
     lib.msc_solve_adjoint.restype = i32

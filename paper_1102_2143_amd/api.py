@@ -249,6 +249,54 @@ class Operator:
             raise L.MscError(st, "msc_solve_bicgstab")
         return x, res
 
+    def solve_real(self, b, out=None, stream=None, check=True, **kw):
+        """x (ns, n) float64 for a real symmetric A (kind "herm", real values): the real
+        multishift path; b real of length n.  Returns (x, info dict)."""
+        if self.sigma is None:
+            raise ValueError("set_shifts first")
+        ns = self.sigma.size
+        _need(_numel(b) == self.n, f"solve_real: b has {_numel(b)} entries, expected n = {self.n}")
+        if out is not None:
+            _need(isinstance(out, torch.Tensor) and tuple(out.shape) == (ns, self.n)
+                  and out.dtype == torch.float64 and out.device == self.device
+                  and out.is_contiguous(),
+                  "solve_real: out must be a contiguous float64 tensor (ns, n) on the device")
+        if isinstance(b, torch.Tensor):
+            _need(not b.is_complex(), "solve_real: b must be real")
+        else:
+            _need(not np.iscomplexobj(b), "solve_real: b must be real")
+        bt = _dev_tensor(b, torch.float64, self.device)
+        x = torch.empty((ns, self.n), dtype=torch.float64, device=self.device) if out is None else out
+        prm = make_params(**kw)
+        info, rel, fi = _new_info(ns)
+        st = self.lib.msc_solve_real(self.handle, _ptr(bt), _ptr(x), ctypes.byref(prm),
+                                     ctypes.byref(info), _stream(stream))
+        res = _info_dict(st, info, rel, fi)
+        if check and st not in (L.MSC_OK, L.MSC_ENOTCONV):
+            raise L.MscError(st, "msc_solve_real")
+        return x, res
+
+    def solve_multi_rhs(self, B, out=None, stream=None, check=True, **kw):
+        """x (ns, n) complex128 for (A + sigma_k) x_k = b_k with B (ns, n), one right-hand
+        side per shift in the caller's shift order; returns (x, info dict)."""
+        if self.sigma is None:
+            raise ValueError("set_shifts first")
+        ns = self.sigma.size
+        _need(_numel(B) == ns * self.n,
+              f"solve_multi_rhs: B has {_numel(B)} entries, expected ns * n = {ns * self.n}")
+        if out is not None:
+            _check_out(out, (ns, self.n), self.device, "solve_multi_rhs")
+        bt = _dev_tensor(B, torch.complex128, self.device).reshape(ns, self.n)
+        x = torch.empty((ns, self.n), dtype=torch.complex128, device=self.device) if out is None else out
+        prm = make_params(**kw)
+        info, rel, fi = _new_info(ns)
+        st = self.lib.msc_solve_multi_rhs(self.handle, _ptr(bt), _ptr(x), ctypes.byref(prm),
+                                          ctypes.byref(info), _stream(stream))
+        res = _info_dict(st, info, rel, fi)
+        if check and st not in (L.MSC_OK, L.MSC_ENOTCONV):
+            raise L.MscError(st, "msc_solve_multi_rhs")
+        return x, res
+
     def solve_adjoint(self, g, x, stream=None, grad_vals=True, grad_b=True, check=True, **kw):
         """(grad_b (n,), grad_vals (nnz,), info) of L with dL/dx = g."""
         if self.sigma is None:

@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "libmsc.so")
 ARCH = os.environ.get("MSC_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["setup.hip", "multishift.hip", "batched_cg.hip", "batched_ms.hip", "grad.hip",
-           "bicgstab.hip", "capi.cpp"]
+           "bicgstab.hip", "osborn.hip", "real_ms.hip", "capi.cpp"]
 
 FLAGS = [
     f"--offload-arch={ARCH}",

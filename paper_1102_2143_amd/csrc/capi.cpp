@@ -1397,6 +1397,11 @@ msc_status update_values_impl(msc_op op, const double* d_vals, hipStream_t s) {
     HIP_TRY(launch_cast_vals(op->val64, op->val32, op->nnz, s));
     if (op->kind == MSC_A_MHM)
       HIP_TRY(launch_adjoint_vals(op->perm_h, op->val64, op->val64_h, op->val32_h, op->nnz, s));
+    op->real_state = 0;  // the real copies are rebuilt by the next real solve
+    dfree(op->rval64);
+    dfree(op->rval32);
+    dfree(op->rdiag64);
+    dfree(op->rdiag32);
     if (op->sell) {
       HIP_TRY(refill_sell(op->rowptr, op->col, op->val64, op->n, op->sell_m, s));
       if (op->kind == MSC_A_MHM)
@@ -1941,6 +1946,401 @@ msc_status msc_solve_bicgstab(msc_op op, const double* d_b, double* d_x,
   return all_ok ? MSC_OK : MSC_ENOTCONV;
 }
 
+msc_status msc_solve_multi_rhs(msc_op op, const double* d_B, double* d_x,
+                               const msc_params* params, msc_info* info, msc_stream stream) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (check_op(op) != MSC_OK) return MSC_EINVAL;
+  if (!d_B || !d_x) {
+    set_error("msc_solve_multi_rhs: null B or x");
+    return MSC_EINVAL;
+  }
+  if (op->sigma.empty()) {
+    set_error("msc_solve_multi_rhs: no shifts set");
+    return MSC_EINVAL;
+  }
+  if (op->kind == MSC_A_GENERAL) {
+    set_error("msc_solve_multi_rhs: needs a Hermitian positive-definite A");
+    return MSC_EINVAL;
+  }
+  msc_params prm;
+  if (params)
+    prm = *params;
+  else
+    msc_params_default(&prm);
+  if (!(prm.tol >= 0.0) || (prm.prec != MSC_PREC_FP64 && prm.prec != MSC_PREC_MIXED) ||
+      !(prm.mixed_margin > 0.0 && prm.mixed_margin <= 1.0) ||
+      prm.update_steps < 1 || prm.update_steps > kMaxSteps || prm.reserved != 0) {
+    set_error("msc_solve_multi_rhs: invalid tol, precision, mixed_margin, update_steps or reserved");
+    return MSC_EINVAL;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int ns = int(op->sigma.size());
+  const int64_t n = op->n;
+  msc_status rc = ensure_scratch(op);
+  if (rc != MSC_OK) return rc;
+  rc = ensure_workspace(op, prm.prec, ns);
+  if (rc != MSC_OK) return rc;
+  // buffers: W (ns n), r0 (n), d (ns n), product (n); tables; norms, partials, tickets
+  auto align = [](size_t b) { return (b + 255) / 256 * 256; };
+  const size_t vec = sizeof(double2) * size_t(n);
+  const size_t tab = align(sizeof(double) * ns * ns);
+  const size_t need = align(vec * ns) + align(vec) + align(vec * ns) + align(vec) + 2 * tab +
+                      align(sizeof(int) * ns) + align(sizeof(double) * (ns + 1)) +
+                      align(sizeof(double) * (ns + 1) * kOsbSlices) +
+                      align(sizeof(unsigned) * (ns + 1) * kTicketSite);
+  if (op->osb_bytes < need) {
+    if (op->osb) (void)hipFree(op->osb);
+    op->osb = nullptr;
+    op->osb_bytes = 0;
+    HIP_TRY(hipMalloc(&op->osb, need));
+    op->osb_bytes = need;
+  }
+  unsigned char* cur = static_cast<unsigned char*>(op->osb);
+  auto carve = [&](size_t b) {
+    unsigned char* p = cur;
+    cur += align(b);
+    return p;
+  };
+  double2* W = reinterpret_cast<double2*>(carve(vec * ns));
+  double2* r0 = reinterpret_cast<double2*>(carve(vec));
+  double2* dl = reinterpret_cast<double2*>(carve(vec * ns));
+  double2* prod = reinterpret_cast<double2*>(carve(vec));
+  double* d_inv = reinterpret_cast<double*>(carve(sizeof(double) * ns * ns));
+  double* d_w = reinterpret_cast<double*>(carve(sizeof(double) * ns * ns));
+  int* d_orig = reinterpret_cast<int*>(carve(sizeof(int) * ns));
+  double* d_norm = reinterpret_cast<double*>(carve(sizeof(double) * (ns + 1)));
+  double* d_part = reinterpret_cast<double*>(carve(sizeof(double) * (ns + 1) * kOsbSlices));
+  unsigned* d_tick = reinterpret_cast<unsigned*>(carve(sizeof(unsigned) * (ns + 1) * kTicketSite));
+  HIP_TRY(hipMemsetAsync(d_tick, 0, sizeof(unsigned) * (ns + 1) * kTicketSite, s));
+
+  // sorted shifts, the divided-difference and Newton-weight tables
+  std::vector<int> order(ns);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int i, int j) { return op->sigma[i] < op->sigma[j]; });
+  std::vector<double> sv(ns), inv(size_t(ns) * ns, 0.0), w(size_t(ns) * ns, 0.0);
+  bool distinct = true;
+  for (int j = 0; j < ns; ++j) sv[j] = op->sigma[order[j]];
+  for (int j = 1; j < ns; ++j)
+    if (!(sv[j] > sv[j - 1])) distinct = false;
+  for (int k = 0; k < ns; ++k) {
+    for (int level = 1; level <= k; ++level) inv[size_t(k) * ns + level] = 1.0 / (sv[k] - sv[k - level]);
+    double wk = 1.0;
+    for (int j = 0; j <= std::min(k, ns - 2); ++j) {
+      w[size_t(k) * ns + j] = wk;
+      wk *= sv[k] - sv[j];
+    }
+  }
+  HIP_TRY(hipMemcpy(d_inv, inv.data(), sizeof(double) * ns * ns, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(d_w, w.data(), sizeof(double) * ns * ns, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(d_orig, order.data(), sizeof(int) * ns, hipMemcpyHostToDevice));
+
+  const double2* B = reinterpret_cast<const double2*>(d_B);
+  double2* X = reinterpret_cast<double2*>(d_x);
+  const int lanes = choose_lanes(op, prm);
+  auto apply = [&](const double2* in, double2* out, double shift) {
+    return launch_apply(op->kind, MSC_PREC_FP64, lanes, n,
+                        Csr<double2>{op->rowptr, op->col, op->val64},
+                        Csr<double2>{op->rowptr_h, op->col_h, op->val64_h},
+                        Csr<float2>{op->rowptr, op->col, op->val32},
+                        Csr<float2>{op->rowptr_h, op->col_h, op->val32_h}, in, out, shift,
+                        op->ws.t64, op->ws.u64, s);
+  };
+  // |b_k|^2 in the caller's order
+  std::vector<double> bn2(ns + 1, 0.0);
+  HIP_TRY(launch_osb_norms(B, ns, n, d_part, d_tick, d_norm, s));
+  HIP_TRY(hipMemcpyAsync(bn2.data(), d_norm, sizeof(double) * ns, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  double bmin = HUGE_VAL;
+  for (int k = 0; k < ns; ++k) bmin = std::min(bmin, std::sqrt(bn2[k]));
+
+  int iters = 0;
+  bool used = false;
+  if (distinct) {
+    // guesses x0 into x, common residual into r0
+    HIP_TRY(launch_osb_divdiff(B, d_orig, d_inv, W, ns, n, s));
+    for (int m = ns - 2; m >= 1; --m) {
+      HIP_TRY(apply(W + int64_t(m + 1) * n, prod, sv[m]));  // (A + s_m) Y_m
+      HIP_TRY(launch_osb_sub(W + int64_t(m) * n, prod, n, s));  // W[m] <- Y_{m-1}
+    }
+    if (ns >= 2) {
+      HIP_TRY(apply(W + n, prod, sv[0]));
+      HIP_TRY(launch_osb_sub(W, prod, n, s));
+    }
+    HIP_TRY(hipMemcpyAsync(r0, W, vec, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(launch_osb_combine(W, d_w, d_orig, X, ns, n, s));
+    double rr = 0.0;
+    HIP_TRY(launch_osb_norms(r0, 1, n, d_part, d_tick + size_t(ns) * kTicketSite, d_norm + ns, s));
+    HIP_TRY(hipMemcpyAsync(&rr, d_norm + ns, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const double rn = std::sqrt(rr);
+    // the multishift stop that gives every shift tol |b_k|; beyond FP64's reach the
+    // guesses are dropped and each shift is solved from zero by the batched CG
+    const double tol_inner = rn > 0.0 ? prm.tol * bmin / rn : 0.0;
+    if (rn == 0.0) {
+      used = true;
+    } else if (std::isfinite(rn) && tol_inner >= 1e-14) {
+      used = true;
+      msc_params p2 = prm;
+      p2.verify = 0;
+      std::vector<double> rel;
+      int st = 0;
+      double bytes = 0.0, bnorm = 0.0;
+      const double tol_stop = tol_inner * (prm.prec == MSC_PREC_MIXED ? prm.mixed_margin : 1.0);
+      rc = run_multishift(op, reinterpret_cast<const double*>(r0), reinterpret_cast<double*>(dl),
+                          p2, nullptr, s, tol_stop, prm.prec, &rel, &iters, &st, &bytes, &bnorm);
+      if (rc != MSC_OK) return rc;
+      if (st != 0) {
+        set_error("msc_solve_multi_rhs: breakdown in the multishift solve of the common residual");
+        return MSC_EBREAKDOWN;
+      }
+      HIP_TRY(launch_osb_add(X, dl, int64_t(ns) * n, s));
+    }
+  }
+  if (!used) HIP_TRY(hipMemsetAsync(X, 0, vec * ns, s));
+
+  // every shift against its own b_k in FP64; those above tol continue with the batched CG
+  std::vector<double> rel(ns, 0.0);
+  int refine_iters = 0, n_refined = 0;
+  bool breakdown = false;
+  for (int g0 = 0; g0 < ns; g0 += kBssMax) {
+    const int m = std::min(kBssMax, ns - g0);
+    std::vector<double> sig(m), tol_abs(m), res;
+    std::vector<const double2*> f(m);
+    std::vector<double2*> x(m);
+    for (int j = 0; j < m; ++j) {
+      const int k = g0 + j;
+      sig[j] = op->sigma[k];
+      tol_abs[j] = prm.tol * std::sqrt(bn2[k]);
+      f[j] = B + int64_t(k) * n;
+      x[j] = X + int64_t(k) * n;
+    }
+    int inner = 0;
+    bool bd = false;
+    double bytes = 0.0;
+    rc = run_batched_cg(op, MSC_PREC_FP64, m, sig.data(), f.data(), x.data(), tol_abs.data(), 0.0,
+                        prm, s, res, &inner, &bytes, &bd);
+    if (rc != MSC_OK) return rc;
+    refine_iters = std::max(refine_iters, inner);
+    for (int j = 0; j < m; ++j) {
+      const double bk = std::sqrt(bn2[g0 + j]);
+      rel[g0 + j] = bk > 0.0 ? res[j] / bk : 0.0;
+    }
+    if (inner > 0) n_refined += m;  // the group needed CG iterations
+    if (bd) breakdown = true;
+  }
+  if (info) {
+    clear_timing(*info);
+    info->iters = iters;
+    info->refine_iters = refine_iters;
+    info->n_reliable = 0;
+    info->n_refined = n_refined;
+    info->iters_fp64 = iters;
+    info->alg_bytes = 0.0;
+    if (info->true_rel_res)
+      for (int k = 0; k < ns; ++k) info->true_rel_res[k] = rel[k];
+    if (info->freeze_iter)
+      for (int k = 0; k < ns; ++k) info->freeze_iter[k] = -1;
+    info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  if (breakdown) {
+    set_error("msc_solve_multi_rhs: breakdown in the per-shift CG");
+    return MSC_EBREAKDOWN;
+  }
+  for (int k = 0; k < ns; ++k)
+    if (!(rel[k] <= prm.tol)) {
+      set_error("msc_solve_multi_rhs: some shift did not reach tol");
+      return MSC_ENOTCONV;
+    }
+  return MSC_OK;
+}
+
+msc_status msc_solve_real(msc_op op, const double* d_b, double* d_x, const msc_params* params,
+                          msc_info* info, msc_stream stream) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (check_op(op) != MSC_OK) return MSC_EINVAL;
+  if (!d_b || !d_x) {
+    set_error("msc_solve_real: null b or x");
+    return MSC_EINVAL;
+  }
+  if (op->sigma.empty()) {
+    set_error("msc_solve_real: no shifts set");
+    return MSC_EINVAL;
+  }
+  if (op->kind != MSC_A_HERM || !op->sell) {
+    set_error("msc_solve_real: needs an operator of kind MSC_A_HERM with its sliced ELLPACK "
+              "copy built");
+    return MSC_EINVAL;
+  }
+  msc_params prm;
+  if (params)
+    prm = *params;
+  else
+    msc_params_default(&prm);
+  if (!(prm.tol >= 0.0) || (prm.prec != MSC_PREC_FP64 && prm.prec != MSC_PREC_MIXED) ||
+      prm.reserved != 0) {
+    set_error("msc_solve_real: invalid tol, precision or reserved");
+    return MSC_EINVAL;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int ns = int(op->sigma.size());
+  const int64_t n = op->n;
+  msc_status rc = ensure_scratch(op);
+  if (rc != MSC_OK) return rc;
+  const SellStore& sm = op->sell_m;
+  const int64_t cells = sm.pairs * 2 * kSlice;
+  // real copies of the sliced values and diagonal, after checking every imaginary part is 0
+  if (op->real_state == 0) {
+    unsigned long long* d_imax = nullptr;
+    HIP_TRY(dalloc(&op->rval64, size_t(cells)));
+    HIP_TRY(dalloc(&op->rval32, size_t(cells)));
+    HIP_TRY(dalloc(&op->rdiag64, size_t(n)));
+    HIP_TRY(dalloc(&op->rdiag32, size_t(n)));
+    HIP_TRY(dalloc(&d_imax, 1));
+    HIP_TRY(hipMemsetAsync(d_imax, 0, sizeof(unsigned long long), s));
+    HIP_TRY(launch_real_extract(sm.val64, op->rval64, op->rval32, cells, d_imax, s));
+    HIP_TRY(launch_real_extract(sm.diag64, op->rdiag64, op->rdiag32, n, d_imax, s));
+    unsigned long long h_imax = 0;
+    HIP_TRY(hipMemcpyAsync(&h_imax, d_imax, sizeof(h_imax), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    (void)hipFree(d_imax);
+    op->real_state = h_imax == 0 ? 1 : -1;
+  }
+  if (op->real_state != 1) {
+    set_error("msc_solve_real: the operator has non-zero imaginary parts");
+    return MSC_EINVAL;
+  }
+  const int prec = prm.prec;
+  const size_t el = prec == MSC_PREC_MIXED ? sizeof(float) : sizeof(double);
+  auto align = [](size_t b) { return (b + 255) / 256 * 256; };
+  const size_t vec = align(el * size_t(n));
+  const size_t need = 3 * vec + align(el * size_t(n) * size_t(std::max(ns - 1, 1))) +
+                      align(sizeof(RealState)) + align(sizeof(double) * ns);
+  if (op->rws_bytes < need) {
+    if (op->rws) (void)hipFree(op->rws);
+    op->rws = nullptr;
+    op->rws_bytes = 0;
+    HIP_TRY(hipMalloc(&op->rws, need));
+    op->rws_bytes = need;
+  }
+  unsigned char* cur = static_cast<unsigned char*>(op->rws);
+  RealArgs a{};
+  a.n = n;
+  a.nslices = sm.nslices;
+  a.ns = ns;
+  a.m64 = SellReal<double>{sm.cptr, sm.col, sm.col16, sm.cbase, sm.wp, op->rval64, op->rdiag64};
+  a.m32 = SellReal<float>{sm.cptr, sm.col, sm.col16, sm.cbase, sm.wp, op->rval32, op->rdiag32};
+  a.b = d_b;
+  a.x = d_x;
+  a.r = cur;
+  cur += vec;
+  a.p = cur;
+  cur += vec;
+  a.t = cur;
+  cur += vec;
+  a.pk = cur;
+  cur += align(el * size_t(n) * size_t(std::max(ns - 1, 1)));
+  a.st = reinterpret_cast<RealState*>(cur);
+  cur += align(sizeof(RealState));
+  double* d_res2 = reinterpret_cast<double*>(cur);
+  a.partial = op->scratch.partial;
+  a.tickets = op->scratch.tickets + 13 * kTicketSite;
+
+  std::vector<int> order(ns);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int i, int j) { return op->sigma[i] < op->sigma[j]; });
+  RealState h{};
+  h.sigma0 = op->sigma[order[0]];
+  h.eps2 = prm.tol * prm.tol;
+  h.a_prev = 1.0;
+  h.b = 0.0;
+  h.max_iter = prm.max_iter;
+  h.ns = ns;
+  h.freeze = prm.freeze ? 1 : 0;
+  h.upd_launch = -1;
+  for (int j = 0; j < ns; ++j) {
+    h.s[j] = op->sigma[order[j]] - h.sigma0;
+    h.zeta[j] = h.zeta_prev[j] = 1.0;
+    h.active[j] = 1;
+    h.freeze_iter[j] = -1;
+    h.orig[j] = order[j];
+  }
+  HIP_TRY(hipMemcpyAsync(a.st, &h, sizeof h, hipMemcpyHostToDevice, s));
+  HIP_TRY(launch_real_init(prec, a, s));
+  const int G = std::max(1, prm.poll_every);
+  int launched = 0;
+  bool done = prm.max_iter <= 0;
+  while (!done) {
+    for (int g = 0; g < G; ++g) {
+      HIP_TRY(launch_real_iteration(prec, a, launched, s));
+      ++launched;
+    }
+    int halt = 0;
+    HIP_TRY(hipMemcpyAsync(&halt, &a.st->halt, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (halt || launched >= prm.max_iter + G) done = true;
+  }
+  HIP_TRY(hipMemcpyAsync(&h, a.st, sizeof h, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  std::vector<double> rel(ns, 0.0);
+  const double bn = std::sqrt(h.bnorm2);
+  if (prm.verify && h.status == 0 && bn > 0.0) {
+    for (int k = 0; k < ns; ++k)
+      HIP_TRY(launch_real_verify(a, d_x + int64_t(k) * n, op->sigma[k], d_res2 + k, s));
+    std::vector<double> r2(ns);
+    HIP_TRY(hipMemcpyAsync(r2.data(), d_res2, sizeof(double) * ns, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int k = 0; k < ns; ++k) rel[k] = std::sqrt(r2[k]) / bn;
+  }
+  if (info) {
+    clear_timing(*info);
+    info->iters = h.iter;
+    info->refine_iters = 0;
+    info->n_reliable = 0;
+    info->n_refined = 0;
+    info->iters_fp64 = prec == MSC_PREC_FP64 ? h.iter : 0;
+    const double w = double(el), nn = double(n);
+    // per iteration: matrix (value + index per stored entry, diagonal), p gather and t
+    // write (RK1); r r/w, t, p (RK2); r, p r/w, x_0 r/w (RK3); per live shift x_k r/w
+    // (FP64) and p_k r/w
+    const double ib = sm.col16 ? 2.0 : 4.0;
+    const double mat = double(op->nnz) * (w + ib) + 4.0 * (nn + 1);
+    double upd = 0.0;
+    for (int j = 1; j < ns; ++j) {
+      const int fi = h.freeze_iter[j] < 0 ? h.iter : h.freeze_iter[j];
+      upd += double(fi) * nn * (16.0 + 2 * w);
+    }
+    info->alg_bytes =
+        double(h.iter) * (mat + nn * (2 * w) + nn * (4 * w) + nn * (3 * w + 16.0)) + upd;
+    if (info->true_rel_res)
+      for (int k = 0; k < ns; ++k) info->true_rel_res[k] = rel[k];
+    if (info->freeze_iter)
+      for (int j = 0; j < ns; ++j) {
+        int fi = h.freeze_iter[j];
+        if (j == 0 || fi < 0) fi = h.R <= h.eps2 ? h.iter : -1;
+        info->freeze_iter[order[j]] = fi;
+      }
+    info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  if (h.status != 0) {
+    set_error("msc_solve_real: breakdown (p.(A + sigma_min) p <= 0 or not finite) at iteration %d",
+              h.iter);
+    return MSC_EBREAKDOWN;
+  }
+  if (!(h.R <= h.eps2)) {
+    set_error("msc_solve_real: the iteration limit was reached");
+    return MSC_ENOTCONV;
+  }
+  if (prm.verify)
+    for (int k = 0; k < ns; ++k)
+      if (!(rel[k] <= prm.tol)) {
+        set_error("msc_solve_real: shift %d misses tol in FP64 (%.3e)", k, rel[k]);
+        return MSC_ENOTCONV;
+      }
+  return MSC_OK;
+}
+
 msc_status msc_solve_batched(int32_t nsys, const msc_op* ops, const int32_t* nrhs,
                              const double* const* d_b, double* const* d_x,
                              const msc_params* params, msc_info* info, msc_stream stream) {
@@ -2005,6 +2405,12 @@ void msc_op_destroy(msc_op op) {
   free_sell(op->sell_m);
   free_sell(op->sell_mh);
   if (op->bcg) (void)hipFree(op->bcg);
+  if (op->osb) (void)hipFree(op->osb);
+  if (op->rws) (void)hipFree(op->rws);
+  dfree(op->rval64);
+  dfree(op->rval32);
+  dfree(op->rdiag64);
+  dfree(op->rdiag32);
   if (op->w64.w) (void)hipFree(const_cast<double2*>(op->w64.w));
   if (op->w32.w) (void)hipFree(const_cast<float2*>(op->w32.w));
   delete op;

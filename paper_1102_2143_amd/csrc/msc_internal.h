@@ -230,8 +230,18 @@ struct msc_op_s {
   msc::Workspace ws;
   msc::BssWorkspace bws;
   msc::Scratch scratch;
-  void* bcg = nullptr;           // BiCGStab-M buffers (one allocation), bcg_ns shifts
+  void* bcg = nullptr;           // BiCGStab-M buffers (one allocation)
   size_t bcg_bytes = 0;
+  void* osb = nullptr;           // per-shift right-hand sides: guesses and tables
+  size_t osb_bytes = 0;
+  // real copies of the sliced matrix (built on the first real solve of a real operator)
+  double* rval64 = nullptr;
+  float* rval32 = nullptr;
+  double* rdiag64 = nullptr;
+  float* rdiag32 = nullptr;
+  int real_state = 0;            // 0 not checked, 1 real (copies built), -1 not real
+  void* rws = nullptr;           // real solve buffers
+  size_t rws_bytes = 0;
   double2* yadj = nullptr;       // adjoint solutions, ns * n complex128
   size_t yadj_count = 0;
   double* adj_small = nullptr;   // 256 doubles: Gram sums and shift factors
@@ -356,6 +366,53 @@ struct BcgArgs {
 };
 hipError_t launch_bcg_init(const BcgArgs& a, hipStream_t s);
 hipError_t launch_bcg_iteration(const BcgArgs& a, int launch, hipStream_t s);
+
+// real_ms.hip -- multishift CG for a real symmetric positive-definite A
+template <class T> struct SellReal {
+  const int32_t* cptr = nullptr;
+  const int32_t* col = nullptr;
+  const uint32_t* col16 = nullptr;  // narrow columns (with cbase), or null: col is read
+  const int32_t* cbase = nullptr;
+  int32_t wp = 0;
+  const T* val = nullptr;           // real parts of the sliced copy's values
+  const T* diag = nullptr;
+};
+struct RealState {
+  double a, a_prev, b, b_new, P, R, sigma0, bnorm2, eps2;
+  int iter, max_iter, ns, halt, status, rotate, upd_launch, freeze;
+  double s[kMaxShifts], zeta[kMaxShifts], zeta_prev[kMaxShifts], zeta_new[kMaxShifts];
+  double ak[kMaxShifts], bk[kMaxShifts];
+  int active[kMaxShifts], active_next[kMaxShifts], freeze_iter[kMaxShifts], orig[kMaxShifts];
+};
+struct RealArgs {
+  int64_t n, nslices;
+  int ns;
+  SellReal<double> m64;
+  SellReal<float> m32;
+  const double* b;
+  double* x;               // caller's x, shift-major, caller order (FP64 always)
+  void *r, *p, *t, *pk;    // double or float by precision
+  RealState* st;
+  double* partial;
+  unsigned* tickets;       // one ticket site
+};
+hipError_t launch_real_extract(const double2* v64, double* r64, float* r32, int64_t count,
+                               unsigned long long* imax, hipStream_t s);
+hipError_t launch_real_init(int prec, const RealArgs& a, hipStream_t s);
+hipError_t launch_real_iteration(int prec, const RealArgs& a, int launch, hipStream_t s);
+hipError_t launch_real_verify(const RealArgs& a, const double* x, double sigma, double* out,
+                              hipStream_t s);
+
+// osborn.hip -- a right-hand side per shift through common-residual initial guesses
+constexpr int kOsbSlices = 256;  // workgroups per vector of the norm reduction
+hipError_t launch_osb_divdiff(const double2* B, const int* orig, const double* inv, double2* W,
+                              int m, int64_t n, hipStream_t s);
+hipError_t launch_osb_sub(double2* y, const double2* t, int64_t n, hipStream_t s);
+hipError_t launch_osb_combine(const double2* W, const double* w, const int* orig, double2* x,
+                              int m, int64_t n, hipStream_t s);
+hipError_t launch_osb_add(double2* x, const double2* d, int64_t count, hipStream_t s);
+hipError_t launch_osb_norms(const double2* v, int count, int64_t n, double* partial,
+                            unsigned* tickets, double* out, hipStream_t s);
 
 // batched_cg.hip -- m <= kBssMax single-shift systems sharing one operator
 constexpr int kBssMax = 16;

@@ -59,9 +59,11 @@ def test_small_batch_matches_oracle(cuda, prec, fmt):
             t += 1
             assert np.all(info["true_rel_res"] <= 1e-10), (s, q, info["true_rel_res"])
             assert np.all(_rel(xg, ref["x"]) <= 1e-8), (s, q)
-            # FP64: the oracle's Krylov path to +-2; mixed: the complex64 phase costs a few
-            # extra iterations (bounded at 3%)
-            bar = 2 if prec == "fp64" else max(2, int(0.03 * ref["iters"]))
+            # FP64: the oracle's Krylov path to +-2; mixed: against the oracle run to the
+            # same stopping rule (tol * mixed_margin), with one iteration per replacement
+            # of the residual by the true one on top (each reliable update perturbs the
+            # Krylov sequence, which takes about one step to absorb it)
+            bar = 2 if prec == "fp64" else info["n_reliable"] + 2
             assert abs(info["iters"] - ref["iters"]) <= bar, (s, q, info["iters"], ref["iters"])
             rho = np.array([np.linalg.norm(bs[q] - ap(xg[k], sk)) for k, sk in enumerate(p["sigma"])])
             assert np.all(rho / np.linalg.norm(bs[q]) <= 1e-10)

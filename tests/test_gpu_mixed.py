@@ -65,10 +65,12 @@ def test_mixed_switches_precision_and_keeps_shifts_close(c0, cuda):
     assert np.all(info["true_rel_res"] <= 1e-8)
     assert info["n_reliable"] >= 1
     assert info["n_refined"] == 0
-    # the complex64 phase costs a few iterations over the FP64 oracle's count (<= 3%);
-    # the FP64 path is held to +-2 (test_gpu_multishift)
+    # against the FP64 oracle run to the same stopping rule (tol * mixed_margin = tol
+    # here): +-2, plus one iteration per reliable update (each replacement of r by the
+    # true residual perturbs the Krylov sequence by about one step); the FP64 path is
+    # held to +-2 (test_gpu_multishift)
     ref = O.cg_m(c0["apply"], c0["b"], c0["sigma"], tol=1e-10)
-    assert abs(info["iters"] - ref["iters"]) <= max(2, int(0.03 * ref["iters"]))
+    assert abs(info["iters"] - ref["iters"]) <= info["n_reliable"] + 2
     op.close()
 
 

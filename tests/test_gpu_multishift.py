@@ -333,9 +333,10 @@ def test_c0_both_formats_match_oracle(c0, cuda, fmt, prec):
         assert abs(info["iters"] - ref["iters"]) <= 2
         assert np.all(_rel(x.cpu().numpy(), ref["x"]) <= 1e-8)
     else:
-        # the mixed sequence runs to 0.7 tol (default mixed_margin)
+        # the mixed sequence runs to 0.7 tol (default mixed_margin): the oracle at that
+        # tolerance, +-2 plus one iteration per reliable update
         ref7 = O.cg_m(c0["apply"], c0["b"], c0["sigma"], tol=0.7e-10)
-        assert info["iters"] <= 1.03 * ref7["iters"] + 2
+        assert abs(info["iters"] - ref7["iters"]) <= info["n_reliable"] + 2
         assert info["n_reliable"] > 0
     assert np.all(info["true_rel_res"] <= 1e-10)
     # the FP64 verification (on the format's own kernels) agrees with the oracle's residuals
