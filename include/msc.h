@@ -217,6 +217,22 @@ msc_status msc_op_apply(msc_op op, int32_t prec, const double* d_in, double* d_o
                         double shift, msc_stream stream);
 
 /*
+ * msc_op_apply for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same product,
+ * d_out = (A + shift I) d_in, computed by the same kernels, with its temporaries in a
+ * fixed device array of 64 MiB that the library keeps on each GPU it runs on until the
+ * process ends.  Nothing is allocated, not even on the first call.  Limits: n <= 2^21
+ * for MSC_PREC_FP64 with MSC_A_MHM, n <= 2^22 otherwise; larger operators get
+ * MSC_EINVAL (use msc_op_apply).  The operator's device must be the current device
+ * (MSC_EINVAL otherwise).  The call only queues work on `stream` and returns without
+ * synchronising; the result is ready when the stream reaches that point.  Every call on
+ * one GPU shares that GPU's array, so calls that may overlap on one GPU (different
+ * streams, or different threads) race and must be ordered by the caller.
+ */
+msc_status msc_op_apply_noalloc(msc_op op, int32_t prec, const double* d_in, double* d_out,
+                                double shift, msc_stream stream);
+
+/*
  * The multishift solve (Algorithm 1).  d_b: complex128[n]; d_x: complex128[ns*n],
  * shift-major (x_k occupies d_x[2*k*n .. 2*(k+1)*n)) in the caller's shift order.
  * x starts from zero (the method requires it).  Blocks until done.  Returns MSC_OK when

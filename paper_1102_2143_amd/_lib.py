@@ -24,7 +24,7 @@ EXPORTED = (
     "msc_params_default", "msc_version", "msc_last_error", "msc_op_create_csr",
     "msc_op_create_staggered", "msc_op_update_links", "msc_op_update_values",
     "msc_op_set_shifts", "msc_op_query", "msc_op_storage", "msc_op_apply",
-    "msc_solve", "msc_solve_adjoint", "msc_solve_bicgstab",
+    "msc_op_apply_noalloc", "msc_solve", "msc_solve_adjoint", "msc_solve_bicgstab",
     "msc_solve_multi_rhs", "msc_solve_real", "msc_solve_batched",
     "msc_op_destroy",
 )
@@ -108,6 +108,8 @@ def load():
     lib.msc_op_storage.restype = i32
     lib.msc_op_apply.argtypes = [vp, i32, vp, vp, dbl, vp]
     lib.msc_op_apply.restype = i32
+    lib.msc_op_apply_noalloc.argtypes = [vp, i32, vp, vp, dbl, vp]
+    lib.msc_op_apply_noalloc.restype = i32
     lib.msc_solve.argtypes = [vp, vp, vp, ctypes.POINTER(Params), ctypes.POINTER(Info), vp]
     lib.msc_solve.restype = i32
     lib.msc_solve_bicgstab.argtypes = [vp, vp, vp, ctypes.POINTER(Params), ctypes.POINTER(Info), vp]

@@ -210,6 +210,19 @@ class Operator:
             raise L.MscError(st, "msc_op_apply")
         return out
 
+    def apply_noalloc(self, v, out, shift=0.0, prec="fp64", stream=None):
+        """out = (A + shift) v through msc_op_apply_noalloc: the library allocates nothing
+        and only queues the work on the stream (the caller provides `out`)."""
+        _need(_numel(v) == self.n, f"apply_noalloc: v has {_numel(v)} entries, expected n = {self.n}")
+        _need(prec in _PREC, f"apply_noalloc: unknown precision {prec!r}")
+        _check_out(out, (self.n,), self.device, "apply_noalloc")
+        vin = _dev_tensor(v, torch.complex128, self.device).reshape(-1)
+        st = self.lib.msc_op_apply_noalloc(self.handle, _PREC[prec], _ptr(vin), _ptr(out),
+                                           float(shift), _stream(stream))
+        if st != L.MSC_OK:
+            raise L.MscError(st, "msc_op_apply_noalloc")
+        return out
+
     def solve(self, b, out=None, stream=None, check=True, **kw):
         """x (ns, n) complex128 for (A + sigma_k) x_k = b; returns (x, info dict)."""
         if self.sigma is None:

@@ -1608,6 +1608,42 @@ msc_status msc_op_apply(msc_op op, int32_t prec, const double* d_in, double* d_o
   return MSC_OK;
 }
 
+msc_status msc_op_apply_noalloc(msc_op op, int32_t prec, const double* d_in, double* d_out,
+                                double shift, msc_stream stream) {
+  if (check_op(op) != MSC_OK) return MSC_EINVAL;
+  if (!d_in || !d_out || (prec != MSC_PREC_FP64 && prec != MSC_PREC_MIXED)) {
+    set_error("msc_op_apply_noalloc: null vector or unknown precision");
+    return MSC_EINVAL;
+  }
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev != op->device) {
+    set_error("msc_op_apply_noalloc: device %d is current, the operator lives on device %d",
+              dev, op->device);
+    return MSC_EINVAL;
+  }
+  const size_t need = apply_scratch_bytes(op->kind, prec, op->n);
+  if (need > kNoAllocScratchBytes) {
+    set_error("msc_op_apply_noalloc: n = %lld needs %zu bytes of scratch, above the "
+              "%zu-byte limit (use msc_op_apply)",
+              (long long)op->n, need, kNoAllocScratchBytes);
+    return MSC_EINVAL;
+  }
+  void* base = nullptr;
+  HIP_TRY(noalloc_scratch(dev, &base));
+  msc_params prm;
+  msc_params_default(&prm);
+  HIP_TRY(launch_apply_noalloc(op->kind, prec, choose_lanes(op, prm), op->n,
+                               Csr<double2>{op->rowptr, op->col, op->val64},
+                               Csr<double2>{op->rowptr_h, op->col_h, op->val64_h},
+                               Csr<float2>{op->rowptr, op->col, op->val32},
+                               Csr<float2>{op->rowptr_h, op->col_h, op->val32_h},
+                               reinterpret_cast<const double2*>(d_in),
+                               reinterpret_cast<double2*>(d_out), shift, base,
+                               static_cast<hipStream_t>(stream)));
+  return MSC_OK;
+}
+
 msc_status msc_solve(msc_op op, const double* d_b, double* d_x, const msc_params* params,
                      msc_info* info, msc_stream stream) {
   const auto t0 = std::chrono::steady_clock::now();

@@ -333,6 +333,22 @@ hipError_t launch_apply(int kind, int prec, int lanes, int64_t n, const Csr<doub
                         const Csr<float2>& mh32, const double2* in, double2* out,
                         double shift, void* tmp_a, void* tmp_b, hipStream_t s);
 
+// No-allocation apply: temporaries in a file-scope device array of this many bytes per GPU
+// (FP64: n <= 2^21 rows for A = M^H M, 2^22 for A given; complex64: n <= 2^22).
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+// Bytes of that array one apply of n rows needs.
+size_t apply_scratch_bytes(int kind, int prec, int64_t n);
+// The array's address on `device`, which must be the current device; looked up with
+// hipGetSymbolAddress on the first call per device and kept.
+hipError_t noalloc_scratch(int device, void** ptr);
+// launch_apply with its temporaries carved from `base` (the address noalloc_scratch
+// returned); hipErrorInvalidValue when n exceeds the array.
+hipError_t launch_apply_noalloc(int kind, int prec, int lanes, int64_t n,
+                                const Csr<double2>& m64, const Csr<double2>& mh64,
+                                const Csr<float2>& m32, const Csr<float2>& mh32,
+                                const double2* in, double2* out, double shift, void* base,
+                                hipStream_t s);
+
 int default_grid(int64_t n, int lanes);
 
 // bicgstab.hip -- multishift BiCGStab for a general A (complex FP64 scalars)

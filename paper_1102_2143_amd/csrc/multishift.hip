@@ -24,6 +24,7 @@
 // arrive does).
 #include <hip/hip_ext.h>
 
+#include <mutex>
 #include <type_traits>
 
 #include "dev_common.h"
@@ -1543,6 +1544,57 @@ hipError_t launch_apply(int kind, int prec, int lanes, int64_t n, const Csr<doub
     }
   }
   return hipGetLastError();
+}
+
+// ---- operator application without allocation ------------------------------------------
+// The two temporaries of the no-allocation apply live in a file-scope device array: each
+// GPU the library runs on holds its own copy, until the process ends.  In host code the
+// name `scratch` is only a host-side stand-in, so it is never passed to a kernel: the
+// array's address on each device comes from hipGetSymbolAddress, looked up once per
+// device with that device current, and kept in scratch_addr.
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mutex;
+void* scratch_addr[kMaxDevices] = {};
+}  // namespace
+
+size_t apply_scratch_bytes(int kind, int prec, int64_t n) {
+  // mixed: the complex64 input and one complex64 product (both kinds);
+  // FP64: one complex128 product, two for A = M^H M; each temporary 256-byte aligned
+  const size_t elem = prec == MSC_PREC_MIXED ? sizeof(float2) : sizeof(double2);
+  const int count = (prec == MSC_PREC_MIXED || kind == MSC_A_MHM) ? 2 : 1;
+  const size_t one = (elem * size_t(n) + 255) / 256 * 256;
+  return one * count;
+}
+
+hipError_t noalloc_scratch(int device, void** ptr) {
+  *ptr = nullptr;
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(scratch_mutex);
+  if (!scratch_addr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    scratch_addr[device] = p;
+  }
+  *ptr = scratch_addr[device];
+  return hipSuccess;
+}
+
+hipError_t launch_apply_noalloc(int kind, int prec, int lanes, int64_t n,
+                                const Csr<double2>& m64, const Csr<double2>& mh64,
+                                const Csr<float2>& m32, const Csr<float2>& mh32,
+                                const double2* in, double2* out, double shift, void* base,
+                                hipStream_t s) {
+  const size_t need = apply_scratch_bytes(kind, prec, n);
+  if (need > kNoAllocScratchBytes) return hipErrorInvalidValue;
+  const size_t elem = prec == MSC_PREC_MIXED ? sizeof(float2) : sizeof(double2);
+  const size_t one = (elem * size_t(n) + 255) / 256 * 256;
+  unsigned char* b = static_cast<unsigned char*>(base);
+  return launch_apply(kind, prec, lanes, n, m64, mh64, m32, mh32, in, out, shift, b,
+                      b + one, s);
 }
 
 }  // namespace msc
