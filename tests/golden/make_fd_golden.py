@@ -5,10 +5,12 @@ second-order functional L~ = sum_k c_k Re(b^H x_k + x_k^H r_k) (x_k from the FP6
 oracle at tol 1e-14), for the real and imaginary part of 32 seeded stored entries of M;
 with the argument ``directional``, the 16^4 fixture: one central difference along a seeded
 direction over every stored entry; with ``entries16`` the 16^4 fixture of 32 seeded stored
-entries, real and imaginary part each (128 oracle solves, spread over worker processes).
+entries, real and imaginary part each (128 oracle solves, spread over worker processes);
+with ``loss`` the loss L~ at the unperturbed entries is added to the per-entry fixtures
+(the scale of the central differences' rounding error, u |L~| / h).
 The loss is the rational-approximation form sum_k c_k Re(b^H x_k) of the shifted family
 (Section 2 of the paper).
-Run:  python tests/golden/make_fd_golden.py [directional | entries16 [jobs]]
+Run:  python tests/golden/make_fd_golden.py [directional | entries16 [jobs] | loss]
 """
 import concurrent.futures
 import json
@@ -23,6 +25,25 @@ import oracle as O  # noqa: E402
 import workloads as W  # noqa: E402
 
 
+def base_loss(name):
+    """L~ at the unperturbed entries (one FP64 CG-M oracle solve at tol 1e-14)."""
+    p = W.make_config(name)
+    ap = O.shifted_apply("mhm", p["rowptr"], p["col"], p["vals"], p["n"])
+    sol = O.cg_m(ap, p["b"], p["sigma"], tol=1e-14, max_iter=100000)
+    return O.second_order_loss("mhm", p["rowptr"], p["col"], p["vals"], p["n"], p["b"],
+                               p["sigma"], p["c"], sol["x"])
+
+
+def main_loss():
+    for name, out in (("c3", "fd_c3_8x4.json"), ("c3_16", "fd_c3_16x4.json")):
+        path = os.path.join(HERE, out)
+        rec = json.load(open(path))
+        rec["loss"] = float(base_loss(name))
+        with open(path, "w") as f:
+            json.dump(rec, f, indent=1)
+        print(f"{out}: loss {rec['loss']:.6e}")
+
+
 def main(name="c3", out="fd_c3_8x4.json"):
     p = W.make_config(name)
     cfg = p["cfg"]
@@ -33,7 +54,7 @@ def main(name="c3", out="fd_c3_8x4.json"):
                seeds=dict(links=cfg["seed_links"], b=cfg["seed_b"], c=cfg["seed_c"], nz=cfg["seed_nz"]),
                h=cfg["fd_h"], solve_tol=1e-14, nz=[int(e) for e in p["fd_nz"]],
                grad_re=[float(v.real) for v in fd], grad_im=[float(v.imag) for v in fd],
-               seconds=round(time.time() - t0, 1),
+               loss=float(base_loss(name)), seconds=round(time.time() - t0, 1),
                source="oracle.fd_gradient (central differences of the second-order functional)")
     with open(os.path.join(HERE, out), "w") as f:
         json.dump(rec, f, indent=1)
@@ -85,7 +106,7 @@ def main_entries16(name="c3_16", out="fd_c3_16x4.json", jobs=8):
                seeds=dict(links=cfg["seed_links"], b=cfg["seed_b"], c=cfg["seed_c"], nz=cfg["seed_nz"]),
                h=cfg["fd_h"], solve_tol=1e-14, nz=nz,
                grad_re=[float(res[e].real) for e in nz], grad_im=[float(res[e].imag) for e in nz],
-               seconds=round(time.time() - t0, 1),
+               loss=float(base_loss(name)), seconds=round(time.time() - t0, 1),
                source="oracle.fd_gradient (central differences of the second-order functional)")
     with open(os.path.join(HERE, out), "w") as f:
         json.dump(rec, f, indent=1)
@@ -95,6 +116,8 @@ def main_entries16(name="c3_16", out="fd_c3_16x4.json", jobs=8):
 if __name__ == "__main__":
     if len(sys.argv) > 1 and sys.argv[1] == "directional":
         main_directional()
+    elif len(sys.argv) > 1 and sys.argv[1] == "loss":
+        main_loss()
     elif len(sys.argv) > 1 and sys.argv[1] == "entries16":
         main_entries16(jobs=int(sys.argv[2]) if len(sys.argv) > 2 else 8)
     else:

@@ -158,14 +158,15 @@ def test_fd_directional_fixture_16x4_matches_its_recipe():
     assert np.isfinite(rec["directional_derivative"])
 
 
-def test_closed_form_matches_fd_fixture_8x4():
-    """The oracle's closed-form gradient at 8^4 against the stored central differences
-    (tests/golden/fd_c3_8x4.json, written by make_fd_golden.py from the oracle's FD)."""
+@pytest.mark.parametrize("name,fixture", [("c3", "fd_c3_8x4.json"), ("c3_16", "fd_c3_16x4.json")])
+def test_closed_form_matches_fd_fixture(name, fixture):
+    """The oracle's closed-form gradient at 8^4 and 16^4 against the stored central
+    differences (tests/golden, written by make_fd_golden.py from the oracle's FD)."""
     import json
     import os
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "fd_c3_8x4.json")
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", fixture)
     rec = json.load(open(path))
-    p = W.make_config("c3")
+    p = W.make_config(name)
     assert rec["nz"] == [int(e) for e in p["fd_nz"]]
     ap = O.shifted_apply("mhm", p["rowptr"], p["col"], p["vals"], p["n"])
     sol = O.cg_m(ap, p["b"], p["sigma"], tol=1e-14, max_iter=100000)
@@ -174,4 +175,14 @@ def test_closed_form_matches_fd_fixture_8x4():
     got = gv[np.array(rec["nz"])]
     comp_got = np.concatenate([got.real, got.imag])
     comp_fd = np.concatenate([fd.real, fd.imag])
-    assert np.linalg.norm(comp_got - comp_fd) / np.linalg.norm(comp_fd) <= 1e-6
+    # Error of a central difference in floating point: each of the two loss values carries
+    # a rounding error of about u |L| (u = 2^-53), so their quotient carries u |L| / h:
+    # 9e-4 at 16^4, where |L| ~ 4e6, against gradients of order 1e2; the truncation error,
+    # of order h^2 times the third derivative, is far below it.  Each component may differ
+    # by 4 u |L| / h plus 1e-7 of the largest component.
+    L = O.second_order_loss("mhm", p["rowptr"], p["col"], p["vals"], p["n"], p["b"], p["sigma"],
+                            p["c"], sol["x"])
+    assert abs(L - rec["loss"]) <= 1e-12 * abs(L)
+    bound = 4 * 2.0 ** -53 * abs(L) / rec["h"] + 1e-7 * np.abs(comp_fd).max()
+    assert np.all(np.abs(comp_got - comp_fd) <= bound)
+    assert np.linalg.norm(comp_got - comp_fd) / np.linalg.norm(comp_fd) <= 2e-6
