@@ -103,7 +103,12 @@ typedef struct {
                                 into one pass over x_k and p_k (the heads between defer
                                 theirs); same recurrences, 1/update_steps of the traffic
                                 of those vectors. 1: one step per iteration    (4)    */
-    int32_t reserved;        /* must be 0                                        (0)    */
+    int32_t sweep;           /* order of the rows the iteration kernels visit: 0 (auto)
+                                follows the operator's lattice structure where one was
+                                found at creation (planes and slabs of the staggered
+                                lattice, from the links or from a stored matrix's
+                                columns), so that each XCD works on neighbouring rows
+                                at once; 1 = one contiguous range per workgroup   (0)    */
 } msc_params;
 
 /* Per-solve report.  Array members are caller-owned host arrays of length ns (or

@@ -48,7 +48,7 @@ class Params(ctypes.Structure):
         ("format", ctypes.c_int32),
         ("mixed_margin", ctypes.c_double),
         ("update_steps", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("sweep", ctypes.c_int32),
     ]
 
 

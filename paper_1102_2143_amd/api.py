@@ -57,10 +57,13 @@ def _check_out(out, shape, device, what):
     _need(out.is_contiguous(), f"{what}: out must be contiguous")
 
 
+_SWEEP = {"auto": 0, "contiguous": 1}
+
+
 def make_params(tol=1e-10, prec="fp64", max_iter=10000, reliable_every=50, freeze=True,
                 refine=True, poll_every=16, switch_tol=None, refine_max_iter=10000, lanes=0,
                 verify=True, timing=0, max_grid=0, format="auto", mixed_margin=None,
-                update_steps=None) -> L.Params:
+                update_steps=None, sweep="auto") -> L.Params:
     lib = L.load()
     p = L.Params()
     lib.msc_params_default(ctypes.byref(p))
@@ -83,6 +86,7 @@ def make_params(tol=1e-10, prec="fp64", max_iter=10000, reliable_every=50, freez
         p.mixed_margin = float(mixed_margin)
     if update_steps is not None:
         p.update_steps = int(update_steps)
+    p.sweep = _SWEEP[sweep] if isinstance(sweep, str) else int(sweep)
     return p
 
 

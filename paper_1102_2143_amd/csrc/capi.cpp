@@ -9,7 +9,9 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <iterator>
 #include <map>
 #include <mutex>
 #include <numeric>
@@ -68,13 +70,17 @@ void free_workspace(Workspace& w) {
   w = Workspace{};
 }
 
-msc_status ensure_scratch(msc_op op) {
+// Buffers are cleared on the stream that first uses them: a hipMemset would run on the
+// null stream, which does not order itself with the library's non-blocking streams (the
+// batched solve's internal stream), so the clearing could land after the first kernels
+// had already written the buffers.
+msc_status ensure_scratch(msc_op op, hipStream_t s) {
   Scratch& sc = op->scratch;
   if (sc.partial) return MSC_OK;
   HIP_TRY(dalloc(&sc.partial, size_t(kMaxGrid) * kMaxShifts));
   HIP_TRY(dalloc(&sc.tickets, 16 * kTicketSite));
   HIP_TRY(dalloc(&sc.res2, kMaxShifts));
-  HIP_TRY(hipMemset(sc.tickets, 0, sizeof(unsigned) * 16 * kTicketSite));
+  HIP_TRY(hipMemsetAsync(sc.tickets, 0, sizeof(unsigned) * 16 * kTicketSite, s));
   return MSC_OK;
 }
 
@@ -141,6 +147,70 @@ Sell<V> sell_view(const SellStore& m, const V* val, const V* diag, bool narrow) 
 // ELLPACK: 4, narrow sliced ELLPACK: 2, the per-column bases being negligible).
 template <class V> double index_bytes(bool sell, const Sell<V>& m) {
   return sell && m.col16 ? 2.0 : 4.0;
+}
+
+// Sweep order of a lattice whose neighbouring planes lie s1 slices and neighbouring slabs
+// s2 slices apart (s2 a multiple of s1): planes are cut into tiles of cs slices, the
+// largest divisor of s1 that keeps neighbouring planes (cs * slabs-per-XCD positions
+// apart in the sweep) within kTileSpan positions.  Zeros when the structure does not fit.
+constexpr int64_t kTileSpan = 96;
+SweepOrder lattice_order(int64_t nslices, int64_t s1, int64_t s2) {
+  SweepOrder o{0, 0, 0, 0};
+  if (s1 < 1 || s2 <= s1 || s2 % s1 != 0 || s2 > nslices / kXcds) return o;
+  const int64_t na = std::max<int64_t>(1, nslices / kXcds / s2);
+  int64_t cs = 1;
+  for (int64_t c = 1; c <= s1; ++c)
+    if (s1 % c == 0 && c * na <= kTileSpan) cs = c;
+  o.s1 = int32_t(s1);
+  o.s2 = int32_t(s2);
+  o.cs = int32_t(cs);
+  return o;
+}
+
+// Lattice structure of a stored matrix, read from its columns: in blocks of rows spread
+// over the matrix (at scattered offsets, so that they do not all sit on one lattice
+// boundary), the row-to-column distances (periodic: min(d, n - d)) that are whole slices
+// and occur in at least 3/4 of the sampled rows (a boundary row reaches one neighbour
+// the long way round); the two largest give the plane and slab distances.  A matrix
+// without such a structure gets zeros (contiguous sweeps).
+SweepOrder detect_order(const int64_t* d_rowptr, const int32_t* d_col, int64_t n, int64_t nnz,
+                        int64_t nslices, hipStream_t s) {
+  const SweepOrder none{0, 0, 0, 0};
+  constexpr int kBlocks = 8, kRows = 16, kMaxEntries = 64 * kRows;
+  if (nslices < 2 * kXcds || nnz == 0) return none;
+  std::map<int64_t, int> seen;  // distance in slices -> sampled rows having it
+  for (int bk = 0; bk < kBlocks; ++bk) {
+    const int64_t r0 = (n * (2 * bk + 1) / (2 * kBlocks) + 1009 * int64_t(bk * bk + 3 * bk + 1)) %
+                       std::max<int64_t>(1, n - kRows);
+    if (r0 + kRows > n) return none;
+    int64_t rp[kRows + 1];
+    if (hipMemcpyAsync(rp, d_rowptr + r0, sizeof rp, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return none;
+    const int64_t cnt = rp[kRows] - rp[0];
+    if (cnt <= 0 || cnt > kMaxEntries) return none;
+    std::vector<int32_t> cols(size_t(cnt), 0);
+    if (hipMemcpyAsync(cols.data(), d_col + rp[0], sizeof(int32_t) * cnt, hipMemcpyDeviceToHost, s) !=
+            hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return none;
+    for (int i = 0; i < kRows; ++i) {
+      std::vector<int64_t> ds;
+      for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
+        int64_t d = std::llabs(int64_t(cols[size_t(e - rp[0])]) - (r0 + i));
+        d = std::min(d, n - d);
+        if (d >= kSlice && d % kSlice == 0) ds.push_back(d / kSlice);
+      }
+      std::sort(ds.begin(), ds.end());
+      ds.erase(std::unique(ds.begin(), ds.end()), ds.end());
+      for (int64_t d : ds) ++seen[d];
+    }
+  }
+  std::vector<int64_t> common;
+  for (const auto& kv : seen)
+    if (4 * kv.second >= 3 * kBlocks * kRows) common.push_back(kv.first);
+  if (common.size() < 2) return none;
+  return lattice_order(nslices, common[common.size() - 2], common.back());
 }
 
 MsArgs make_args(msc_op op, int lanes, const double* d_b, double* d_x) {
@@ -273,7 +343,7 @@ msc_status run_multishift(msc_op op, const double* d_b, double* d_x, const msc_p
                           std::vector<double>* rel_out, int* iters_out, int* status_out,
                           double* bytes_out, double* bnorm_out) {
   const int ns = int(op->sigma.size());
-  msc_status rc = ensure_scratch(op);
+  msc_status rc = ensure_scratch(op, s);
   if (rc != MSC_OK) return rc;
   rc = ensure_workspace(op, prec, ns);
   if (rc != MSC_OK) return rc;
@@ -295,6 +365,8 @@ msc_status run_multishift(msc_op op, const double* d_b, double* d_x, const msc_p
   // operators (the reliable update, verification and refinement keep the stored copies)
   a64.stencil = op->stencil && a64.sell &&
                 (prm.format == MSC_FORMAT_AUTO || prm.format == MSC_FORMAT_STENCIL) ? 1 : 0;
+  a64.ord = op->order;
+  a64.ord.on = (prm.sweep == 0 && op->order.s1 > 0) ? 1 : 0;
   if (prm.format == MSC_FORMAT_SELL32 && op->sell) {
     const SellStore &sm = op->sell_m, &sh = op->sell_mh;
     a64.s64 = sell_view(sm, sm.val64, sm.diag64, false);
@@ -513,7 +585,7 @@ void free_bss(BssWorkspace& w) {
   w = BssWorkspace{};
 }
 
-msc_status ensure_bss(msc_op op, int prec, int mp) {
+msc_status ensure_bss(msc_op op, int prec, int mp, hipStream_t s) {
   BssWorkspace& w = op->bws;
   const size_t n = size_t(op->n);
   if (w.st && w.prec == prec && w.mp == mp && w.n == n) return MSC_OK;
@@ -521,7 +593,7 @@ msc_status ensure_bss(msc_op op, int prec, int mp) {
   const size_t bytes = (prec == MSC_PREC_MIXED ? sizeof(float2) : sizeof(double2)) * n * mp;
   for (void** q : {&w.p, &w.t, &w.r, &w.e}) {
     HIP_TRY(hipMalloc(q, bytes));
-    HIP_TRY(hipMemset(*q, 0, bytes));
+    HIP_TRY(hipMemsetAsync(*q, 0, bytes, s));
   }
   HIP_TRY(dalloc(&w.st, 1));
   HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&w.h_halt), 2 * sizeof(int),
@@ -600,11 +672,11 @@ msc_status run_batched_cg(msc_op op, int prec, int m, const double* sig, const d
     return MSC_EINVAL;
   }
   const int mp = m <= 4 ? 4 : (m <= 8 ? 8 : 16);
-  msc_status rc = ensure_scratch(op);
+  msc_status rc = ensure_scratch(op, s);
   if (rc != MSC_OK) return rc;
   rc = ensure_workspace(op, op->ws.prec >= 0 ? op->ws.prec : prec, std::max<int>(1, int(op->sigma.size())));
   if (rc != MSC_OK) return rc;
-  rc = ensure_bss(op, prec, mp);
+  rc = ensure_bss(op, prec, mp, s);
   if (rc != MSC_OK) return rc;
   const int lanes = choose_lanes(op, prm);
   BssArgs a{};
@@ -782,15 +854,51 @@ msc_status solve_impl(msc_op op, const double* d_b, double* d_x, const msc_param
 
 // ---- batched solves --------------------------------------------------------------------
 
-// Chosen lanes per row of a batch, keyed by (systems, total rows, total entries).
-struct TuneKey {
-  int64_t nsys, rows, nnz;
-  bool operator<(const TuneKey& o) const {
-    return std::tie(nsys, rows, nnz) < std::tie(o.nsys, o.rows, o.nnz);
-  }
+// Batch launch choices, measured once per batch shape and kept in process; with the
+// environment variable MSC_TUNE_CACHE naming a file, also on disk (read at the first
+// batched solve, one line appended per new shape: "<key> = <sell> <lanes> <grid>").
+// The key: systems, right-hand sides per system, total rows and entries, the requested
+// format and lanes, and the total row-length histogram (rows with 0, 1, 2-3, ..., >= 64
+// entries) of the batch.
+struct TuneChoice {
+  int sell, lanes, grid;
 };
 std::mutex g_tune_mu;
-std::map<TuneKey, int> g_tune_cache;
+std::map<std::string, TuneChoice> g_tune_cache;
+bool g_tune_loaded = false;
+
+void tune_cache_load_locked() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const char* path = std::getenv("MSC_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  char line[512];
+  while (std::fgets(line, sizeof line, f)) {
+    char* eq = std::strchr(line, '=');
+    if (!eq) continue;
+    TuneChoice c{};
+    if (std::sscanf(eq + 1, "%d %d %d", &c.sell, &c.lanes, &c.grid) != 3) continue;
+    if ((c.lanes != 4 && c.lanes != 8 && c.lanes != 16) || c.grid < 8 || c.grid > kMaxGrid ||
+        (c.sell != 0 && c.sell != 1))
+      continue;
+    std::string key(line, size_t(eq - line));
+    while (!key.empty() && key.back() == ' ') key.pop_back();
+    g_tune_cache[key] = c;
+  }
+  std::fclose(f);
+}
+
+void tune_cache_store_locked(const std::string& key, const TuneChoice& c) {
+  g_tune_cache[key] = c;
+  const char* path = std::getenv("MSC_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "%s = %d %d %d\n", key.c_str(), c.sell, c.lanes, c.grid);
+  std::fclose(f);
+}
 
 struct BatchRun {
   int nsys = 0, rr = 1, nchunks = 0, lanes = 8, grid = 8;
@@ -983,52 +1091,73 @@ struct BatchRun {
     return MSC_OK;
   }
 
-  // SpMV layout of the batch, measured on this batch over a few iterations of each
-  // candidate and cached per shape: the sliced ELLPACK copies (one row per lane, 64 rows
-  // per wavefront; systems without a copy use CSR) or CSR throughout with 4, 8 or 16
-  // lanes per row (16, 8 or 4 rows per wavefront).  msc_params.format / lanes narrow the
-  // candidates.
+  // Launch choices of the batch, measured on this batch over a few iterations of each
+  // candidate and cached per shape: the SpMV layout -- the sliced ELLPACK copies (one row
+  // per lane, 64 rows per wavefront; systems without a copy use CSR) or CSR throughout
+  // with 4, 8 or 16 lanes per row (16, 8 or 4 rows per wavefront) -- times the grid of
+  // the persistent kernels (all chunks' worth up to kMaxGrid, or half of it).
+  // msc_params.format / lanes / max_grid narrow the candidates.
   msc_status tune(const msc_params& prm) {
     const bool fixed_lanes = prm.lanes == 4 || prm.lanes == 8 || prm.lanes == 16;
     bool any_sell = false;
     for (int s = 0; s < nsys; ++s) any_sell = any_sell || ops[s]->sell;
-    std::vector<std::pair<bool, int>> cands;  // (sliced ELLPACK where built, lanes)
-    if (any_sell && prm.format != MSC_FORMAT_CSR) cands.push_back({true, fixed_lanes ? prm.lanes : 8});
+    std::vector<std::pair<bool, int>> layouts;  // (sliced ELLPACK where built, lanes)
+    if (any_sell && prm.format != MSC_FORMAT_CSR) layouts.push_back({true, fixed_lanes ? prm.lanes : 8});
     if ((prm.format != MSC_FORMAT_SELL && prm.format != MSC_FORMAT_SELL32) || !any_sell) {
       if (fixed_lanes)
-        cands.push_back({false, prm.lanes});
+        layouts.push_back({false, prm.lanes});
       else
-        for (int l : {4, 8, 16}) cands.push_back({false, l});
+        for (int l : {4, 8, 16}) layouts.push_back({false, l});
     }
-    auto apply = [&](bool sell, int l) {
-      lanes = l;
-      for (int s = 0; s < nsys; ++s) sys[s].sell = (sell && ops[s]->sell) ? 1 : 0;
+    const int full = grid;
+    std::vector<int> grids{full};
+    const int half = std::max(8, full / 2 / kXcds * kXcds);
+    if (prm.max_grid <= 0 && half < full) grids.push_back(half);
+    std::vector<TuneChoice> cands;
+    for (const auto& l : layouts)
+      for (int g : grids) cands.push_back(TuneChoice{l.first ? 1 : 0, l.second, g});
+    auto apply = [&](const TuneChoice& c) {
+      lanes = c.lanes;
+      grid = c.grid;
+      for (int s = 0; s < nsys; ++s) sys[s].sell = (c.sell && ops[s]->sell) ? 1 : 0;
     };
     if (cands.size() == 1) {
-      apply(cands[0].first, cands[0].second);
+      apply(cands[0]);
       return MSC_OK;
     }
-    TuneKey key{nsys, 0, 0};
+    int64_t rows = 0, nnz = 0, hist[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (int s = 0; s < nsys; ++s) {
-      key.rows += ops[s]->n;
-      key.nnz += ops[s]->nnz;
+      rows += ops[s]->n;
+      nnz += ops[s]->nnz;
+      for (int k = 0; k < 8; ++k) hist[k] += ops[s]->rowhist[k];
     }
-    key.nsys += int64_t(prm.format) << 32;
+    char kb[320];
+    std::snprintf(kb, sizeof kb, "batch sys %d rhs %d rows %lld nnz %lld format %d lanes %d grid %d hist",
+                  nsys, rr, (long long)rows, (long long)nnz, prm.format, prm.lanes, full);
+    std::string key(kb);
+    for (int k = 0; k < 8; ++k) key += " " + std::to_string(hist[k]);
     {
       std::lock_guard<std::mutex> lk(g_tune_mu);
+      tune_cache_load_locked();
       auto it = g_tune_cache.find(key);
       if (it != g_tune_cache.end()) {
-        apply((it->second & 256) != 0, it->second & 255);
-        return MSC_OK;
+        TuneChoice c = it->second;
+        // a cached layout is used only where it is still a candidate (the copies exist)
+        bool ok = false;
+        for (const auto& d : cands) ok = ok || (d.sell == c.sell && d.lanes == c.lanes && d.grid == c.grid);
+        if (ok) {
+          apply(c);
+          return MSC_OK;
+        }
       }
     }
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     float best = 1e30f;
-    std::pair<bool, int> best_c = cands[0];
+    TuneChoice best_c = cands[0];
     for (const auto& c : cands) {
-      apply(c.first, c.second);
+      apply(c);
       msc_status rc = reset(sint);
       if (rc != MSC_OK) return rc;
       HIP_TRY(launch_batch_iteration(args(), sint));  // warm-up
@@ -1045,14 +1174,15 @@ struct BatchRun {
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    apply(best_c.first, best_c.second);
+    apply(best_c);
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune_cache[key] = best_c.second | (best_c.first ? 256 : 0);
+    tune_cache_store_locked(key, best_c);
     return MSC_OK;
   }
 
   msc_status solve(const msc_params& prm, hipStream_t user) {
     grid = std::max(8, std::min(nchunks, kMaxGrid));
+    if (prm.max_grid > 0) grid = std::max(8, std::min(grid, prm.max_grid));
     // order the internal stream after the caller's prior work
     HIP_TRY(hipEventRecord(ev_sync, user));
     HIP_TRY(hipStreamWaitEvent(sint, ev_sync, 0));
@@ -1127,7 +1257,7 @@ struct BatchRun {
         const msc_op op = ops[s];
         const int ns = int(op->sigma.size());
         const int64_t n = op->n;
-        msc_status rc = ensure_scratch(op);
+        msc_status rc = ensure_scratch(op, sint);
         if (rc != MSC_OK) return rc;
         rc = ensure_workspace(op, MSC_PREC_FP64, ns);
         if (rc != MSC_OK) return rc;
@@ -1157,6 +1287,7 @@ struct BatchRun {
         const double bn = std::sqrt(h.bnorm2[q]);
         int refine_iters = 0, n_refined = 0;
         bool bd = h.status[q] != 0;
+        const bool bd_seq = bd;
         if (!bd && prm.verify) {
           const double* r2 = r2all.data() + size_t(t) * kMaxShifts;
           std::vector<int> todo;
@@ -1186,7 +1317,8 @@ struct BatchRun {
         }
         if (bd) {
           result = MSC_EBREAKDOWN;
-          set_error("msc_solve_batched: breakdown in system %d rhs %d", s, q);
+          set_error("msc_solve_batched: breakdown in system %d rhs %d (%s, iteration %d)", s, q,
+                    bd_seq ? "multishift sequence" : "refinement", h.iter[q]);
         } else if (prm.verify) {
           for (int k = 0; k < ns; ++k)
             if (!(rel[k] <= prm.tol) && result == MSC_OK) {
@@ -1350,6 +1482,17 @@ msc_status msc_op_create_csr(msc_op* out, int32_t kind, int64_t n, int64_t nnz,
     CREATE_TRY(hipMemcpyAsync(op->val64, d_vals, sizeof(double2) * nnz, hipMemcpyDeviceToDevice, s));
   }
   CREATE_TRY(launch_cast_vals(op->val64, op->val32, nnz, s));
+  {
+    unsigned long long* d_hist = nullptr;
+    unsigned long long h_hist[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    CREATE_TRY(dalloc(&d_hist, 8));
+    hipError_t e = launch_row_hist(op->rowptr, n, d_hist, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(h_hist, d_hist, sizeof h_hist, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(d_hist);
+    CREATE_TRY(e);
+    for (int k = 0; k < 8; ++k) op->rowhist[k] = int64_t(h_hist[k]);
+  }
   if (kind == MSC_A_MHM) {
     CREATE_TRY(dalloc(&op->rowptr_h, size_t(n) + 1));
     CREATE_TRY(dalloc(&op->col_h, size_t(nnz)));
@@ -1370,6 +1513,7 @@ msc_status msc_op_create_csr(msc_op* out, int32_t kind, int64_t n, int64_t nnz,
     free_sell(op->sell_mh);
   }
   CREATE_TRY(hipStreamSynchronize(s));
+  if (op->sell) op->order = detect_order(d_rowptr, d_col, n, nnz, op->sell_m.nslices, s);
 #undef CREATE_TRY
   *out = op;
   return MSC_OK;
@@ -1520,6 +1664,11 @@ msc_status msc_op_create_staggered(msc_op* out, const int32_t* dims, double mass
   }
   op->w32.vol = geo.vol;
   op->w32.mass = geo.mass;
+  // the lattice's planes (fixed x2, x3) and slabs (fixed x3), when they are whole slices
+  const int64_t plane = 3 * int64_t(geo.L[0]) * geo.L[1], slab = plane * geo.L[2];
+  op->order = (op->sell && plane % kSlice == 0)
+                  ? lattice_order(op->sell_m.nslices, plane / kSlice, slab / kSlice)
+                  : SweepOrder{0, 0, 0, 0};
   *out = op;
   return MSC_OK;
 }
@@ -1668,8 +1817,8 @@ msc_status msc_solve(msc_op op, const double* d_b, double* d_x, const msc_params
     msc_params_default(&prm);
   if (!(prm.tol >= 0.0) || (prm.prec != MSC_PREC_FP64 && prm.prec != MSC_PREC_MIXED) ||
       !(prm.mixed_margin > 0.0 && prm.mixed_margin <= 1.0) ||
-      prm.update_steps < 1 || prm.update_steps > kMaxSteps || prm.reserved != 0) {
-    set_error("msc_solve: invalid tol, precision, mixed_margin, update_steps or reserved");
+      prm.update_steps < 1 || prm.update_steps > kMaxSteps || (prm.sweep != 0 && prm.sweep != 1)) {
+    set_error("msc_solve: invalid tol, precision, mixed_margin, update_steps or sweep");
     return MSC_EINVAL;
   }
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -1703,15 +1852,15 @@ msc_status msc_solve_adjoint(msc_op op, const double* d_g, const double* d_x, do
     msc_params_default(&prm);
   if (!(prm.tol >= 0.0) || (prm.prec != MSC_PREC_FP64 && prm.prec != MSC_PREC_MIXED) ||
       !(prm.mixed_margin > 0.0 && prm.mixed_margin <= 1.0) ||
-      prm.update_steps < 1 || prm.update_steps > kMaxSteps || prm.reserved != 0) {
-    set_error("msc_solve_adjoint: invalid tol, precision, mixed_margin, update_steps or reserved");
+      prm.update_steps < 1 || prm.update_steps > kMaxSteps || (prm.sweep != 0 && prm.sweep != 1)) {
+    set_error("msc_solve_adjoint: invalid tol, precision, mixed_margin, update_steps or sweep");
     return MSC_EINVAL;
   }
   prm.verify = 1;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int ns = int(op->sigma.size());
   const int64_t n = op->n;
-  msc_status rc = ensure_scratch(op);
+  msc_status rc = ensure_scratch(op, s);
   if (rc != MSC_OK) return rc;
   rc = ensure_workspace(op, prm.prec, ns);
   if (rc != MSC_OK) return rc;
@@ -1866,14 +2015,14 @@ msc_status msc_solve_bicgstab(msc_op op, const double* d_b, double* d_x,
     prm = *params;
   else
     msc_params_default(&prm);
-  if (!(prm.tol >= 0.0) || prm.prec != MSC_PREC_FP64 || prm.reserved != 0) {
-    set_error("msc_solve_bicgstab: invalid tol, precision (FP64 only) or reserved");
+  if (!(prm.tol >= 0.0) || prm.prec != MSC_PREC_FP64 || (prm.sweep != 0 && prm.sweep != 1)) {
+    set_error("msc_solve_bicgstab: invalid tol, precision (FP64 only) or sweep");
     return MSC_EINVAL;
   }
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int ns = int(op->sigma.size());
   const int64_t n = op->n;
-  msc_status rc = ensure_scratch(op);
+  msc_status rc = ensure_scratch(op, s);
   if (rc != MSC_OK) return rc;
   // buffers: r[2], p, v, s, t (n each), ns directions, the state
   const size_t vec = sizeof(double2) * size_t(n);
@@ -2005,14 +2154,14 @@ msc_status msc_solve_multi_rhs(msc_op op, const double* d_B, double* d_x,
     msc_params_default(&prm);
   if (!(prm.tol >= 0.0) || (prm.prec != MSC_PREC_FP64 && prm.prec != MSC_PREC_MIXED) ||
       !(prm.mixed_margin > 0.0 && prm.mixed_margin <= 1.0) ||
-      prm.update_steps < 1 || prm.update_steps > kMaxSteps || prm.reserved != 0) {
-    set_error("msc_solve_multi_rhs: invalid tol, precision, mixed_margin, update_steps or reserved");
+      prm.update_steps < 1 || prm.update_steps > kMaxSteps || (prm.sweep != 0 && prm.sweep != 1)) {
+    set_error("msc_solve_multi_rhs: invalid tol, precision, mixed_margin, update_steps or sweep");
     return MSC_EINVAL;
   }
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int ns = int(op->sigma.size());
   const int64_t n = op->n;
-  msc_status rc = ensure_scratch(op);
+  msc_status rc = ensure_scratch(op, s);
   if (rc != MSC_OK) return rc;
   rc = ensure_workspace(op, prm.prec, ns);
   if (rc != MSC_OK) return rc;
@@ -2214,14 +2363,14 @@ msc_status msc_solve_real(msc_op op, const double* d_b, double* d_x, const msc_p
   else
     msc_params_default(&prm);
   if (!(prm.tol >= 0.0) || (prm.prec != MSC_PREC_FP64 && prm.prec != MSC_PREC_MIXED) ||
-      prm.reserved != 0) {
-    set_error("msc_solve_real: invalid tol, precision or reserved");
+      (prm.sweep != 0 && prm.sweep != 1)) {
+    set_error("msc_solve_real: invalid tol, precision or sweep");
     return MSC_EINVAL;
   }
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int ns = int(op->sigma.size());
   const int64_t n = op->n;
-  msc_status rc = ensure_scratch(op);
+  msc_status rc = ensure_scratch(op, s);
   if (rc != MSC_OK) return rc;
   const SellStore& sm = op->sell_m;
   const int64_t cells = sm.pairs * 2 * kSlice;
@@ -2393,9 +2542,9 @@ msc_status msc_solve_batched(int32_t nsys, const msc_op* ops, const int32_t* nrh
   if (!(prm.tol >= 0.0) || (prm.prec != MSC_PREC_FP64 && prm.prec != MSC_PREC_MIXED) ||
       !(prm.mixed_margin > 0.0 && prm.mixed_margin <= 1.0) ||
       prm.format < MSC_FORMAT_AUTO || prm.format > MSC_FORMAT_SELL32 ||
-      prm.update_steps < 1 || prm.update_steps > kMaxSteps || prm.reserved != 0) {
+      prm.update_steps < 1 || prm.update_steps > kMaxSteps || (prm.sweep != 0 && prm.sweep != 1)) {
     set_error("msc_solve_batched: invalid tol, precision, mixed_margin, format, update_steps "
-              "or reserved");
+              "or sweep");
     return MSC_EINVAL;
   }
   int rr = 1, max_nrhs = 0;

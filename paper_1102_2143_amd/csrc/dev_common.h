@@ -11,7 +11,6 @@
 namespace msc {
 
 constexpr int kWave = 64;   // CDNA wavefront width
-constexpr int kXcds = 8;    // MI355X: 8 accelerator complex dies, one L2 each
 
 template <class R> struct vec2;
 template <> struct vec2<float> { using type = float2; };
@@ -124,9 +123,10 @@ __device__ __forceinline__ void store_host_flag(int* p, int v) {
 // there before the increment that reports it.  The last arrival issues its loads only
 // after its increment has returned the final count, i.e. after every other increment,
 // hence after every partial store completed.  This is the ordering an agent-scope
-// release/acquire pair would give; the pair would add an L2 write-back in every
-// workgroup and an L2 invalidate in the last ones (what the compiler emits for
-// non-coherent data), which the partials do not need, and which evict the gathered
+// release/acquire pair would give (the release's wait on the memory counter, without
+// its L2 write-back, which only dirty lines written by plain stores need; the
+// acquire's L2 invalidate is for plain loads); the pair would add that write-back in
+// every workgroup and the invalidate in the last ones, which evict the gathered
 // vectors the kernels rely on (measured: the 64-system batch ran 296 ms per solve with
 // them against 182 ms without).  Compiler barriers keep the stores, the wait, the
 // increment and the loads in program order.
@@ -188,6 +188,67 @@ __device__ __forceinline__ void block_range(int64_t n, int step, int64_t& beg, i
   end = beg + per * step;
   if (end > n) end = n;
   if (beg > n) beg = n;
+}
+
+// The slices one wave of an iteration kernel visits, in order.  With a lattice order
+// (SweepOrder::on), XCD x (workgroups b with b % 8 == x under the round-robin dispatch)
+// owns slices [x N / 8, (x + 1) N / 8) of the N slices, and its U waves visit positions
+// j = u, u + U, u + 2U, ... of a permutation of that range (u: the wave's index among
+// them), so the slices in flight on an XCD at any moment are consecutive positions.  The
+// permutation walks the range's whole slabs tile by tile: position
+// j = ((cb nb + b) na + a) cs + cc names slice a s2 + b s1 + cb cs + cc (slab a of na,
+// plane b of nb, tile cb, slice cc), so the same tile of neighbouring slabs lies cs
+// positions away and that of neighbouring planes cs na positions away, within what the
+// XCD has in flight: its L2 then serves the neighbours' gathers and shared operands.
+// Without an order, workgroup b sweeps one contiguous range (block_range) with its waves
+// interleaved.  The position arithmetic is wave-uniform (scalar unit).
+struct Sweep {
+  int64_t lo;      // first slice of the range
+  uint32_t len;    // slices in the range
+  uint32_t j, step;
+  uint32_t na, nb, s1, s2, cs;  // na = 0: identity permutation
+  __device__ __forceinline__ bool more() const { return j < len; }
+  __device__ __forceinline__ void next() { j += step; }
+  __device__ __forceinline__ int64_t slice() const {
+    uint32_t k = j;
+    if (na > 0 && j < na * s2) {
+      const uint32_t cc = j % cs, r1 = j / cs;
+      const uint32_t sa = r1 % na, r2 = r1 / na;
+      const uint32_t pb = r2 % nb, cb = r2 / nb;
+      k = sa * s2 + pb * s1 + cb * cs + cc;
+    }
+    return lo + int64_t(k);
+  }
+};
+
+// wpb: waves per workgroup, each taking one slice at a time.
+__device__ __forceinline__ Sweep make_sweep(int64_t nslices, const SweepOrder& o, int wpb) {
+  Sweep w{};
+  const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x / kWave));
+  const int g = gridDim.x;
+  if (o.on && (g % kXcds) == 0) {
+    const int x = int(blockIdx.x % kXcds);
+    const int64_t lo = nslices * x / kXcds, hi = nslices * (x + 1) / kXcds;
+    w.lo = lo;
+    w.len = uint32_t(hi - lo);
+    w.j = uint32_t(int(blockIdx.x / kXcds) * wpb + wv);
+    w.step = uint32_t((g / kXcds) * wpb);
+    if (o.s1 > 0 && o.s2 > 0 && o.cs > 0) {
+      w.na = w.len / uint32_t(o.s2);
+      w.nb = uint32_t(o.s2 / o.s1);
+      w.s1 = uint32_t(o.s1);
+      w.s2 = uint32_t(o.s2);
+      w.cs = uint32_t(o.cs);
+    }
+  } else {
+    int64_t beg, end;
+    block_range(nslices, wpb, beg, end);
+    w.lo = beg;
+    w.len = uint32_t(end - beg);
+    w.j = uint32_t(wv);
+    w.step = uint32_t(wpb);
+  }
+  return w;
 }
 
 }  // namespace msc

@@ -14,6 +14,7 @@ namespace msc {
 constexpr int kMaxShifts = 64;
 constexpr int kBlock = 256;          // threads per workgroup for every solver kernel
 constexpr int kMaxGrid = 2048;       // 256 CUs x 8 resident workgroups
+constexpr int kXcds = 8;             // MI355X: 8 accelerator complex dies, one L2 each
 // A "last workgroup" ticket site: eight group counters 128 bytes apart and a final one.
 constexpr int kTicketStride = 32;
 constexpr int kTicketSite = 9 * kTicketStride;
@@ -157,6 +158,15 @@ template <class V> struct Stencil {
   double mass = 0.0;
 };
 
+// Order in which the waves of the iteration kernels (head and K2 on the sliced path) visit
+// the slices of 64 rows, for operators with a lattice structure: rows s1 slices apart are
+// neighbours in one direction (a plane), rows s2 slices apart in the slowest one (a slab),
+// and a plane is cut into tiles of cs slices.  on = 0: every workgroup sweeps one
+// contiguous range of slices.
+struct SweepOrder {
+  int32_t s1, s2, cs, on;
+};
+
 // Device buffers of one sliced ELLPACK matrix (both value precisions share the columns).
 struct SellStore {
   int64_t nslices = 0;
@@ -246,6 +256,8 @@ struct msc_op_s {
   size_t yadj_count = 0;
   double* adj_small = nullptr;   // 256 doubles: Gram sums and shift factors
   int lanes64 = 0, lanes32 = 0;  // chosen lanes per row (0 = not yet tuned)
+  msc::SweepOrder order{0, 0, 0, 0};  // lattice structure of the rows (zeros: none found)
+  int64_t rowhist[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // rows by length: 0, 1, 2-3, ..., >= 64
   bool stencil = false;          // matrix-free staggered operator (links kept below)
   msc::Stencil<double2> w64;     // W_mu(x) = eta_mu(x)/2 U_mu(x), complex128 and
   msc::Stencil<float2> w32;      // complex64 copies (device memory owned by the op)
@@ -262,6 +274,8 @@ namespace msc {
 hipError_t launch_validate_csr(const int64_t* rowptr, const int32_t* col, int64_t n, int64_t nnz,
                                int* d_err, hipStream_t s);
 hipError_t launch_rowptr_to32(const int64_t* in, int32_t* out, int64_t n, hipStream_t s);
+// Row-length histogram (8 power-of-two buckets: 0, 1, 2-3, ..., >= 64) into hist[8].
+hipError_t launch_row_hist(const int32_t* rowptr, int64_t n, unsigned long long* hist, hipStream_t s);
 hipError_t launch_cast_vals(const double2* in, float2* out, int64_t nnz, hipStream_t s);
 hipError_t build_adjoint(const int32_t* rowptr, const int32_t* col, int64_t n, int64_t nnz,
                          int32_t* rowptr_h, int32_t* col_h, int32_t* perm_h, hipStream_t s);
@@ -309,6 +323,7 @@ struct MsArgs {
   int defer_ok;          // 1: this launch's head may defer its all-shift update
   int ru_force;          // reliable-update launch: 1 runs it whatever the residual
   int stencil;           // the head and K2 apply M and M^H from links (kind MHM, sell = 1)
+  SweepOrder ord;        // slice order of the head and K2 on the sliced path
   Stencil<double2> w64;
   Stencil<float2> w32;
   int sample;            // slot of SolveState::smp_* for this head, -1: not sampled

@@ -24,8 +24,10 @@
 // arrive does).
 #include <hip/hip_ext.h>
 
+#include <map>
 #include <mutex>
 #include <type_traits>
+#include <utility>
 
 #include "dev_common.h"
 #include "msc_internal.h"
@@ -734,13 +736,12 @@ __global__ __launch_bounds__(kBlock) void k1_fused(MsArgs a) {
   const double step = st->a;
   constexpr int SPB = kBlock / kSlice;
   const int lane = threadIdx.x % kSlice;
-  const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x / kSlice));
-  int64_t beg, end;
-  block_range(a.nslices, SPB, beg, end);
+  Sweep sw = make_sweep(a.nslices, a.ord, SPB);
   // the first slice's own row is read while R' is being summed
-  const int64_t sl0 = beg + wv;
+  const bool has0 = sw.more();
+  const int64_t sl0 = has0 ? sw.slice() : 0;
   const int64_t row0 = sl0 * kSlice + lane;
-  const int64_t rc = (sl0 < end && row0 < a.n) ? row0 : a.n - 1;
+  const int64_t rc = (has0 && row0 < a.n) ? row0 : a.n - 1;
   const cplx<R> r_first = rv[rc], p_first = pv[rc];
   const double2 x_first = x0[rc];
   __shared__ Plan pl;
@@ -749,11 +750,11 @@ __global__ __launch_bounds__(kBlock) void k1_fused(MsArgs a) {
   const bool upd = pl.pending != 0;
   const double bn = pl.bn;
   double acc = 0.0;
-  for (int64_t sl = sl0; sl < end; sl += SPB) {
+  for (bool first = true; sw.more(); sw.next(), first = false) {
+    const int64_t sl = first ? sl0 : sw.slice();
     const int64_t row = sl * kSlice + lane;
     const bool live = row < a.n;
     const int64_t rr = live ? row : a.n - 1;  // lanes past n read a valid row, unused
-    const bool first = sl == sl0;
     const cplx<R> r_i = first ? r_first : rv[rr];
     const cplx<R> p_i = first ? p_first : pv[rr];
     cplx<R> p_row = p_i;
@@ -883,9 +884,7 @@ __global__ __launch_bounds__(kBlock) void k2_sell(MsArgs a) {
   const double sigma0 = st->sigma0;
   constexpr int SPB = kBlock / kSlice;
   const int lane = threadIdx.x % kSlice;
-  const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x / kSlice));
-  int64_t beg, end;
-  block_range(a.nslices, SPB, beg, end);
+  Sweep sw = make_sweep(a.nslices, a.ord, SPB);
   double acc = 0.0;
   double step = 0.0;
   // q = M^H t for one slice, with the row operands of the epilogue
@@ -922,13 +921,16 @@ __global__ __launch_bounds__(kBlock) void k2_sell(MsArgs a) {
     acc += norm2d<R>(st_r);
   };
   // the first slice's product runs while P's partials are on their way
-  int64_t sl = beg + wv;
-  const bool has0 = sl < end;
+  const bool has0 = sw.more();
+  const int64_t sl0 = has0 ? sw.slice() : 0;
   Row first{};
-  if (has0) first = product(sl);
+  if (has0) first = product(sl0);
   if (!k2_step(a, e, step)) return;  // breakdown: every workgroup sees the same P
-  if (has0) epilogue(sl, first);
-  for (sl += SPB; sl < end; sl += SPB) epilogue(sl, product(sl));
+  if (has0) epilogue(sl0, first);
+  for (sw.next(); sw.more(); sw.next()) {
+    const int64_t sl = sw.slice();
+    epilogue(sl, product(sl));
+  }
   store_partial(region(a, 1), acc);
 }
 
@@ -1359,6 +1361,30 @@ int grid_rows(int64_t n, int rows_per_pass, int cap = kMaxGrid) {
   return int(g);
 }
 
+// Workgroups of kernel `kern` (kBlock threads) that the device holds resident at once,
+// rounded down to a multiple of the XCD count: the grid of a launch whose waves sweep a
+// lattice order in step (a larger grid would leave the later workgroups' positions to a
+// second round).  Cached per device and kernel.
+int resident_grid(const void* kern, int cap) {
+  static std::mutex mu;
+  static std::map<std::pair<int, const void*>, int> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return cap;
+  std::lock_guard<std::mutex> lk(mu);
+  const auto key = std::make_pair(dev, kern);
+  auto it = cache.find(key);
+  if (it == cache.end()) {
+    int per_cu = 0, cus = 0;
+    int g = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kBlock, 0) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
+      g = per_cu * cus / kXcds * kXcds;
+    it = cache.emplace(key, g).first;
+  }
+  const int g = it->second;
+  return g >= kXcds && g < cap ? g : cap;
+}
+
 // Dispatch on lanes per row.
 #define MSC_LANES_SWITCH(LANES, CALL) \
   switch (LANES) {                    \
@@ -1410,21 +1436,27 @@ hipError_t iteration_impl(const MsArgs& args, hipStream_t s, hipEvent_t* ev, boo
   const int g1 = grid_rows(args.n, kBlock / args.lanes, args.grid);
   const int g3 = grid_rows(args.n, kBlock, args.grid);
   MsArgs a = args;
+  const bool st = a.sell && a.stencil && a.kind == MSC_A_MHM;
+  // the head and K2 on the sliced path, and their grids: with a lattice order, the
+  // resident workgroups only (their waves sweep the order in step)
+  auto head = st ? k1_fused<R, true, true>
+                 : (a.kind == MSC_A_MHM ? k1_fused<R, true> : k1_fused<R, false>);
+  auto k2s = st ? k2_sell<R, true> : k2_sell<R>;
+  int gh = g3, gk = g3;
+  if (a.sell && a.ord.on) {
+    gh = resident_grid(reinterpret_cast<const void*>(head), g3);
+    if (a.kind == MSC_A_MHM) gk = resident_grid(reinterpret_cast<const void*>(k2s), g3);
+  }
   // workgroups of K1 and K2, whose partials K2 and the next head add up
   if (a.sell) {
-    a.gk1 = a.gk2 = g3;
+    a.gk1 = gh;
+    a.gk2 = gk;
   } else {
     a.gk1 = g1;
     a.gk2 = a.kind == MSC_A_MHM ? g1 : g3;
   }
-  const bool st = a.sell && a.stencil && a.kind == MSC_A_MHM;
   if (a.sell) {
-    if (st)
-      launch_timed(k1_fused<R, true, true>, g3, s, ev, 0, a);
-    else if (a.kind == MSC_A_MHM)
-      launch_timed(k1_fused<R, true>, g3, s, ev, 0, a);
-    else
-      launch_timed(k1_fused<R, false>, g3, s, ev, 0, a);
+    launch_timed(head, gh, s, ev, 0, a);
   } else {
     launch_timed(k_update<R>, g3, s, ev, 2, a);
     if (a.kind == MSC_A_MHM) {
@@ -1438,10 +1470,8 @@ hipError_t iteration_impl(const MsArgs& args, hipStream_t s, hipEvent_t* ev, boo
     if (e != hipSuccess) return e;
   }
   if (a.kind == MSC_A_MHM) {
-    if (st) {
-      launch_timed(k2_sell<R, true>, g3, s, ev, 1, a);
-    } else if (a.sell) {
-      launch_timed(k2_sell<R>, g3, s, ev, 1, a);
+    if (a.sell) {
+      launch_timed(k2s, gk, s, ev, 1, a);
     } else {
       MSC_LANES_SWITCH(a.lanes, (launch_timed(k2_mhm<R, LL>, g1, s, ev, 1, a)));
     }

@@ -42,6 +42,24 @@ __global__ void k_validate_col(const int32_t* __restrict__ col, int64_t n, int64
   }
 }
 
+// Row lengths of a CSR matrix in 8 buckets (0, 1, 2-3, 4-7, ..., 32-63, >= 64 entries):
+// one LDS histogram per workgroup, added to hist[8].
+__global__ void k_row_hist(const int32_t* __restrict__ rowptr, int64_t n,
+                           unsigned long long* __restrict__ hist) {
+  __shared__ unsigned int h[8];
+  if (threadIdx.x < 8) h[threadIdx.x] = 0u;
+  __syncthreads();
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const int len = rowptr[i + 1] - rowptr[i];
+    const int bkt = len <= 0 ? 0 : min(7, 32 - __clz(len));
+    atomicAdd(&h[bkt], 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x < 8 && h[threadIdx.x] != 0u)
+    atomicAdd(&hist[threadIdx.x], static_cast<unsigned long long>(h[threadIdx.x]));
+}
+
 __global__ void k_rowptr_to32(const int64_t* __restrict__ in, int32_t* __restrict__ out,
                               int64_t count) {
   for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < count;
@@ -277,6 +295,13 @@ hipError_t launch_validate_csr(const int64_t* rowptr, const int32_t* col, int64_
                                int* d_err, hipStream_t s) {
   k_validate_rowptr<<<blocks_for(n), kSetupBlock, 0, s>>>(rowptr, n, nnz, d_err);
   if (nnz > 0) k_validate_col<<<blocks_for(nnz), kSetupBlock, 0, s>>>(col, n, nnz, d_err);
+  return hipGetLastError();
+}
+
+hipError_t launch_row_hist(const int32_t* rowptr, int64_t n, unsigned long long* hist, hipStream_t s) {
+  hipError_t e = hipMemsetAsync(hist, 0, 8 * sizeof(unsigned long long), s);
+  if (e != hipSuccess) return e;
+  k_row_hist<<<blocks_for(n), kSetupBlock, 0, s>>>(rowptr, n, hist);
   return hipGetLastError();
 }
 

@@ -71,6 +71,36 @@ def test_small_batch_matches_oracle(cuda, prec, fmt):
         op.close()
 
 
+@pytest.mark.parametrize("fmt", ["csr", "auto"])
+def test_batch_refinement_on_fresh_operators(cuda, fmt):
+    # complex64 from the first iterations and no margin: most shifts end above tol and
+    # the FP64 refinement (batched CG per operator) runs, as the first use of each
+    # operator's refinement buffers.  Those buffers are cleared on the batch's own stream:
+    # a clearing on the null stream could land after the first refinement kernels wrote
+    # them (seen under profiling as a breakdown of the Laplacian's refinement).
+    print(f"[gpu] batched refinement on fresh operators {fmt}", flush=True)
+    from paper_1102_2143_amd import solve_batched
+    systems = _small_batch()
+    ops = _ops(systems, cuda)
+    kw = dict(format="csr", lanes=4) if fmt == "csr" else {}
+    xs, infos, status = solve_batched(ops, [p["b"] for p in systems], tol=1e-10, prec="mixed",
+                                      switch_tol=1e-2, mixed_margin=1.0, **kw)
+    assert status == "ok"
+    assert sum(i["n_refined"] for i in infos) > 0
+    t = 0
+    for s, p in enumerate(systems):
+        bs = np.atleast_2d(p["b"])
+        for q in range(bs.shape[0]):
+            info = infos[t]
+            t += 1
+            assert np.all(info["true_rel_res"] <= 1e-10), (s, q)
+            dense = O.dense_solve(p["kind"], p["rowptr"], p["col"], p["vals"], p["n"], bs[q],
+                                  p["sigma"])
+            assert np.all(_rel(xs[s][q].cpu().numpy(), dense) <= 1e-8), (s, q)
+    for op in ops:
+        op.close()
+
+
 def test_batch_result_is_independent_of_companions(cuda):
     # each system's arithmetic depends only on its own rows: alone or with others, its
     # solution is bitwise the same
