@@ -39,8 +39,10 @@ WORKLOAD_NAMES = {
 # (FETCH_SIZE and WRITE_SIZE, KiB per dispatch, scaled by the calibration against a copy
 # kernel of known size); it is reported only while the kernel sources are unchanged since.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
-KERNEL_NAMES = {("mixed", "head"): "k1_fused<float, true>", ("mixed", "K2"): "k2_sell<float>",
-                ("fp64", "head"): "k1_fused<double, true>", ("fp64", "K2"): "k2_sell<double>"}
+KERNEL_NAMES = {("mixed", "head"): "k1_fused<float, true, false>",
+                ("mixed", "K2"): "k2_sell<float, false>",
+                ("fp64", "head"): "k1_fused<double, true, false>",
+                ("fp64", "K2"): "k2_sell<double, false>"}
 # the same kernels on the matrix-free staggered operator (M and M^H from the links)
 KERNEL_NAMES_MF = {("mixed", "head"): "k1_fused<float, true, true>",
                    ("mixed", "K2"): "k2_sell<float, true>",
@@ -262,7 +264,7 @@ def main():
     ap.add_argument("--no-matrix-free", action="store_true",
                     help="skip the matrix-free staggered operator's lines (links instead of "
                          "a stored matrix in the iteration)")
-    ap.add_argument("--headline-op", default="stored", choices=["stored", "matrix_free"],
+    ap.add_argument("--headline-op", default="matrix_free", choices=["stored", "matrix_free"],
                     help="which operator the headline value is quoted on")
     ap.add_argument("--no-c1", action="store_true",
                     help="skip the cache-resident 16^4 line reported beside the 32^3x64 one")

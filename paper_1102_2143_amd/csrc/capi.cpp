@@ -1385,6 +1385,14 @@ msc_status check_op(msc_op op) {
 // New values of the stored matrix (same pattern): copies, casts, M^H and sliced copies.
 msc_status update_values_impl(msc_op op, const double* d_vals, hipStream_t s);
 
+struct MultiRhsOut {
+  int iters = 0, refine_iters = 0, n_refined = 0;
+  bool breakdown = false;
+  std::vector<double> rel;  // per shift, caller's order
+};
+msc_status multi_rhs_impl(msc_op op, const double2* B, double2* X, const msc_params& prm,
+                          hipStream_t s, MultiRhsOut& out);
+
 extern "C" {
 
 void msc_params_default(msc_params* p) {
@@ -1534,6 +1542,180 @@ msc_status msc_op_update_values(msc_op op, const double* d_vals, msc_stream stre
 }
 
 }  // extern "C"
+
+// A different right-hand side per shift (Section 5, eq. linprobgen): B and X are ns x n
+// complex128 (caller's shift order).  Common-residual initial guesses, one multishift
+// solve of the common residual, then every shift checked against its own b_k in FP64
+// and completed by the batched CG; the guesses are dropped when the stop they need
+// falls below 1e-14 or the shifts repeat.
+msc_status multi_rhs_impl(msc_op op, const double2* B, double2* X, const msc_params& prm,
+                          hipStream_t s, MultiRhsOut& out) {
+  const int ns = int(op->sigma.size());
+  const int64_t n = op->n;
+  msc_status rc = ensure_scratch(op, s);
+  if (rc != MSC_OK) return rc;
+  rc = ensure_workspace(op, prm.prec, ns);
+  if (rc != MSC_OK) return rc;
+  // buffers: W (ns n), r0 (n), d (ns n), product (n); tables; norms, partials, tickets
+  auto align = [](size_t b) { return (b + 255) / 256 * 256; };
+  const size_t vec = sizeof(double2) * size_t(n);
+  const size_t tab = align(sizeof(double) * ns * ns);
+  const size_t need = align(vec * ns) + align(vec) + align(vec * ns) + align(vec) + 2 * tab +
+                      align(sizeof(int) * ns) + align(sizeof(double) * (ns + 1)) +
+                      align(sizeof(double) * (ns + 1) * kOsbSlices) +
+                      align(sizeof(unsigned) * (ns + 1) * kTicketSite);
+  if (op->osb_bytes < need) {
+    if (op->osb) (void)hipFree(op->osb);
+    op->osb = nullptr;
+    op->osb_bytes = 0;
+    HIP_TRY(hipMalloc(&op->osb, need));
+    op->osb_bytes = need;
+  }
+  unsigned char* cur = static_cast<unsigned char*>(op->osb);
+  auto carve = [&](size_t b) {
+    unsigned char* p = cur;
+    cur += align(b);
+    return p;
+  };
+  double2* W = reinterpret_cast<double2*>(carve(vec * ns));
+  double2* r0 = reinterpret_cast<double2*>(carve(vec));
+  double2* dl = reinterpret_cast<double2*>(carve(vec * ns));
+  double2* prod = reinterpret_cast<double2*>(carve(vec));
+  double* d_inv = reinterpret_cast<double*>(carve(sizeof(double) * ns * ns));
+  double* d_w = reinterpret_cast<double*>(carve(sizeof(double) * ns * ns));
+  int* d_orig = reinterpret_cast<int*>(carve(sizeof(int) * ns));
+  double* d_norm = reinterpret_cast<double*>(carve(sizeof(double) * (ns + 1)));
+  double* d_part = reinterpret_cast<double*>(carve(sizeof(double) * (ns + 1) * kOsbSlices));
+  unsigned* d_tick = reinterpret_cast<unsigned*>(carve(sizeof(unsigned) * (ns + 1) * kTicketSite));
+  HIP_TRY(hipMemsetAsync(d_tick, 0, sizeof(unsigned) * (ns + 1) * kTicketSite, s));
+
+  // sorted shifts, the divided-difference and Newton-weight tables
+  std::vector<int> order(ns);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int i, int j) { return op->sigma[i] < op->sigma[j]; });
+  std::vector<double> sv(ns), inv(size_t(ns) * ns, 0.0), w(size_t(ns) * ns, 0.0);
+  bool distinct = true;
+  for (int j = 0; j < ns; ++j) sv[j] = op->sigma[order[j]];
+  for (int j = 1; j < ns; ++j)
+    if (!(sv[j] > sv[j - 1])) distinct = false;
+  for (int k = 0; k < ns; ++k) {
+    for (int level = 1; level <= k; ++level) inv[size_t(k) * ns + level] = 1.0 / (sv[k] - sv[k - level]);
+    double wk = 1.0;
+    for (int j = 0; j <= std::min(k, ns - 2); ++j) {
+      w[size_t(k) * ns + j] = wk;
+      wk *= sv[k] - sv[j];
+    }
+  }
+  HIP_TRY(hipMemcpy(d_inv, inv.data(), sizeof(double) * ns * ns, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(d_w, w.data(), sizeof(double) * ns * ns, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(d_orig, order.data(), sizeof(int) * ns, hipMemcpyHostToDevice));
+
+  const int lanes = choose_lanes(op, prm);
+  auto apply = [&](const double2* in, double2* out, double shift) {
+    return launch_apply(op->kind, MSC_PREC_FP64, lanes, n,
+                        Csr<double2>{op->rowptr, op->col, op->val64},
+                        Csr<double2>{op->rowptr_h, op->col_h, op->val64_h},
+                        Csr<float2>{op->rowptr, op->col, op->val32},
+                        Csr<float2>{op->rowptr_h, op->col_h, op->val32_h}, in, out, shift,
+                        op->ws.t64, op->ws.u64, s);
+  };
+  // |b_k|^2 in the caller's order
+  std::vector<double> bn2(ns + 1, 0.0);
+  HIP_TRY(launch_osb_norms(B, ns, n, d_part, d_tick, d_norm, s));
+  HIP_TRY(hipMemcpyAsync(bn2.data(), d_norm, sizeof(double) * ns, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  // the smallest nonzero |b_k| sets the stop (a zero b_k gets x_k = 0 below)
+  double bmin = HUGE_VAL;
+  for (int k = 0; k < ns; ++k)
+    if (bn2[k] > 0.0) bmin = std::min(bmin, std::sqrt(bn2[k]));
+  if (!(bmin < HUGE_VAL)) bmin = 0.0;
+
+  int& iters = out.iters;
+  iters = 0;
+  bool used = false;
+  if (distinct) {
+    // guesses x0 into x, common residual into r0
+    HIP_TRY(launch_osb_divdiff(B, d_orig, d_inv, W, ns, n, s));
+    for (int m = ns - 2; m >= 1; --m) {
+      HIP_TRY(apply(W + int64_t(m + 1) * n, prod, sv[m]));  // (A + s_m) Y_m
+      HIP_TRY(launch_osb_sub(W + int64_t(m) * n, prod, n, s));  // W[m] <- Y_{m-1}
+    }
+    if (ns >= 2) {
+      HIP_TRY(apply(W + n, prod, sv[0]));
+      HIP_TRY(launch_osb_sub(W, prod, n, s));
+    }
+    HIP_TRY(hipMemcpyAsync(r0, W, vec, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(launch_osb_combine(W, d_w, d_orig, X, ns, n, s));
+    double rr = 0.0;
+    HIP_TRY(launch_osb_norms(r0, 1, n, d_part, d_tick + size_t(ns) * kTicketSite, d_norm + ns, s));
+    HIP_TRY(hipMemcpyAsync(&rr, d_norm + ns, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const double rn = std::sqrt(rr);
+    // the multishift stop that gives every shift tol |b_k|; beyond FP64's reach the
+    // guesses are dropped and each shift is solved from zero by the batched CG
+    const double tol_inner = rn > 0.0 ? prm.tol * bmin / rn : 0.0;
+    if (rn == 0.0) {
+      used = true;
+    } else if (std::isfinite(rn) && tol_inner >= 1e-14) {
+      used = true;
+      msc_params p2 = prm;
+      p2.verify = 0;
+      std::vector<double> rel;
+      int st = 0;
+      double bytes = 0.0, bnorm = 0.0;
+      const double tol_stop = tol_inner * (prm.prec == MSC_PREC_MIXED ? prm.mixed_margin : 1.0);
+      rc = run_multishift(op, reinterpret_cast<const double*>(r0), reinterpret_cast<double*>(dl),
+                          p2, nullptr, s, tol_stop, prm.prec, &rel, &iters, &st, &bytes, &bnorm);
+      if (rc != MSC_OK) return rc;
+      if (st != 0) {
+        set_error("breakdown in the multishift solve of the common residual");
+        out.breakdown = true;
+        return MSC_EBREAKDOWN;
+      }
+      HIP_TRY(launch_osb_add(X, dl, int64_t(ns) * n, s));
+    }
+  }
+  if (!used) HIP_TRY(hipMemsetAsync(X, 0, vec * ns, s));
+  for (int k = 0; k < ns; ++k)
+    if (!(bn2[k] > 0.0)) HIP_TRY(hipMemsetAsync(X + int64_t(k) * n, 0, vec, s));
+
+  // every shift against its own b_k in FP64; those above tol continue with the batched CG
+  std::vector<double>& rel = out.rel;
+  rel.assign(ns, 0.0);
+  int& refine_iters = out.refine_iters;
+  int& n_refined = out.n_refined;
+  bool& breakdown = out.breakdown;
+  refine_iters = n_refined = 0;
+  breakdown = false;
+  for (int g0 = 0; g0 < ns; g0 += kBssMax) {
+    const int m = std::min(kBssMax, ns - g0);
+    std::vector<double> sig(m), tol_abs(m), res;
+    std::vector<const double2*> f(m);
+    std::vector<double2*> x(m);
+    for (int j = 0; j < m; ++j) {
+      const int k = g0 + j;
+      sig[j] = op->sigma[k];
+      tol_abs[j] = prm.tol * std::sqrt(bn2[k]);
+      f[j] = B + int64_t(k) * n;
+      x[j] = X + int64_t(k) * n;
+    }
+    int inner = 0;
+    bool bd = false;
+    double bytes = 0.0;
+    rc = run_batched_cg(op, MSC_PREC_FP64, m, sig.data(), f.data(), x.data(), tol_abs.data(), 0.0,
+                        prm, s, res, &inner, &bytes, &bd);
+    if (rc != MSC_OK) return rc;
+    refine_iters = std::max(refine_iters, inner);
+    for (int j = 0; j < m; ++j) {
+      const double bk = std::sqrt(bn2[g0 + j]);
+      rel[g0 + j] = bk > 0.0 ? res[j] / bk : 0.0;
+    }
+    if (inner > 0) n_refined += m;  // the group needed CG iterations
+    if (bd) breakdown = true;
+  }
+  return MSC_OK;
+}
 
 msc_status update_values_impl(msc_op op, const double* d_vals, hipStream_t s) {
   if (op->nnz > 0) {
@@ -1931,35 +2113,16 @@ msc_status msc_solve_adjoint(msc_op op, const double* d_g, const double* d_x, do
     bytes = sub.alg_bytes;
     rel = sub_rel;
   } else {
-    HIP_TRY(hipMemsetAsync(y, 0, sizeof(double2) * size_t(ns) * size_t(n), s));
-    std::vector<int> todo;
-    for (int k = 0; k < ns; ++k)
-      if (gn2[k] > 0.0) todo.push_back(k);
-    const double delta = prm.prec == MSC_PREC_MIXED ? 1e-4 : 0.0;
-    bool bd = false;
-    for (size_t g0 = 0; g0 < todo.size(); g0 += kBssMax) {
-      const int m = int(std::min<size_t>(kBssMax, todo.size() - g0));
-      std::vector<double> sig(m), tol_abs(m), res;
-      std::vector<const double2*> f(m);
-      std::vector<double2*> xs(m);
-      for (int j = 0; j < m; ++j) {
-        const int k = todo[g0 + j];
-        sig[j] = op->sigma[k];
-        tol_abs[j] = prm.tol * std::sqrt(gn2[k]);
-        f[j] = g + int64_t(k) * n;
-        xs[j] = y + int64_t(k) * n;
-      }
-      int inner = 0;
-      bool b1 = false;
-      rc = run_batched_cg(op, prm.prec, m, sig.data(), f.data(), xs.data(), tol_abs.data(), delta, prm,
-                          s, res, &inner, &bytes, &b1);
-      if (rc != MSC_OK) return rc;
-      bd = bd || b1;
-      iters = std::max(iters, inner);
-      for (int j = 0; j < m; ++j) rel[todo[g0 + j]] = res[j] / std::sqrt(gn2[todo[g0 + j]]);
-    }
-    n_refined = int(todo.size());
-    if (bd) {
+    // a different g_k per shift: the common-residual guesses and one multishift solve
+    // where the shifts allow it, every shift completed by the batched CG (Section 5)
+    MultiRhsOut out;
+    rc = multi_rhs_impl(op, g, y, prm, s, out);
+    if (rc != MSC_OK && rc != MSC_EBREAKDOWN) return rc;
+    iters = out.iters;
+    refine_iters = out.refine_iters;
+    n_refined = out.n_refined;
+    rel = out.rel;
+    if (rc == MSC_EBREAKDOWN || out.breakdown) {
       set_error("msc_solve_adjoint: breakdown in an adjoint solve");
       result = MSC_EBREAKDOWN;
     } else {
@@ -2160,160 +2323,18 @@ msc_status msc_solve_multi_rhs(msc_op op, const double* d_B, double* d_x,
   }
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int ns = int(op->sigma.size());
-  const int64_t n = op->n;
-  msc_status rc = ensure_scratch(op, s);
+  MultiRhsOut out;
+  msc_status rc = multi_rhs_impl(op, reinterpret_cast<const double2*>(d_B),
+                                 reinterpret_cast<double2*>(d_x), prm, s, out);
+  if (rc == MSC_EBREAKDOWN) {
+    const std::string why = msc_last_error();
+    set_error("msc_solve_multi_rhs: %s", why.c_str());
+    return rc;
+  }
   if (rc != MSC_OK) return rc;
-  rc = ensure_workspace(op, prm.prec, ns);
-  if (rc != MSC_OK) return rc;
-  // buffers: W (ns n), r0 (n), d (ns n), product (n); tables; norms, partials, tickets
-  auto align = [](size_t b) { return (b + 255) / 256 * 256; };
-  const size_t vec = sizeof(double2) * size_t(n);
-  const size_t tab = align(sizeof(double) * ns * ns);
-  const size_t need = align(vec * ns) + align(vec) + align(vec * ns) + align(vec) + 2 * tab +
-                      align(sizeof(int) * ns) + align(sizeof(double) * (ns + 1)) +
-                      align(sizeof(double) * (ns + 1) * kOsbSlices) +
-                      align(sizeof(unsigned) * (ns + 1) * kTicketSite);
-  if (op->osb_bytes < need) {
-    if (op->osb) (void)hipFree(op->osb);
-    op->osb = nullptr;
-    op->osb_bytes = 0;
-    HIP_TRY(hipMalloc(&op->osb, need));
-    op->osb_bytes = need;
-  }
-  unsigned char* cur = static_cast<unsigned char*>(op->osb);
-  auto carve = [&](size_t b) {
-    unsigned char* p = cur;
-    cur += align(b);
-    return p;
-  };
-  double2* W = reinterpret_cast<double2*>(carve(vec * ns));
-  double2* r0 = reinterpret_cast<double2*>(carve(vec));
-  double2* dl = reinterpret_cast<double2*>(carve(vec * ns));
-  double2* prod = reinterpret_cast<double2*>(carve(vec));
-  double* d_inv = reinterpret_cast<double*>(carve(sizeof(double) * ns * ns));
-  double* d_w = reinterpret_cast<double*>(carve(sizeof(double) * ns * ns));
-  int* d_orig = reinterpret_cast<int*>(carve(sizeof(int) * ns));
-  double* d_norm = reinterpret_cast<double*>(carve(sizeof(double) * (ns + 1)));
-  double* d_part = reinterpret_cast<double*>(carve(sizeof(double) * (ns + 1) * kOsbSlices));
-  unsigned* d_tick = reinterpret_cast<unsigned*>(carve(sizeof(unsigned) * (ns + 1) * kTicketSite));
-  HIP_TRY(hipMemsetAsync(d_tick, 0, sizeof(unsigned) * (ns + 1) * kTicketSite, s));
-
-  // sorted shifts, the divided-difference and Newton-weight tables
-  std::vector<int> order(ns);
-  std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(),
-                   [&](int i, int j) { return op->sigma[i] < op->sigma[j]; });
-  std::vector<double> sv(ns), inv(size_t(ns) * ns, 0.0), w(size_t(ns) * ns, 0.0);
-  bool distinct = true;
-  for (int j = 0; j < ns; ++j) sv[j] = op->sigma[order[j]];
-  for (int j = 1; j < ns; ++j)
-    if (!(sv[j] > sv[j - 1])) distinct = false;
-  for (int k = 0; k < ns; ++k) {
-    for (int level = 1; level <= k; ++level) inv[size_t(k) * ns + level] = 1.0 / (sv[k] - sv[k - level]);
-    double wk = 1.0;
-    for (int j = 0; j <= std::min(k, ns - 2); ++j) {
-      w[size_t(k) * ns + j] = wk;
-      wk *= sv[k] - sv[j];
-    }
-  }
-  HIP_TRY(hipMemcpy(d_inv, inv.data(), sizeof(double) * ns * ns, hipMemcpyHostToDevice));
-  HIP_TRY(hipMemcpy(d_w, w.data(), sizeof(double) * ns * ns, hipMemcpyHostToDevice));
-  HIP_TRY(hipMemcpy(d_orig, order.data(), sizeof(int) * ns, hipMemcpyHostToDevice));
-
-  const double2* B = reinterpret_cast<const double2*>(d_B);
-  double2* X = reinterpret_cast<double2*>(d_x);
-  const int lanes = choose_lanes(op, prm);
-  auto apply = [&](const double2* in, double2* out, double shift) {
-    return launch_apply(op->kind, MSC_PREC_FP64, lanes, n,
-                        Csr<double2>{op->rowptr, op->col, op->val64},
-                        Csr<double2>{op->rowptr_h, op->col_h, op->val64_h},
-                        Csr<float2>{op->rowptr, op->col, op->val32},
-                        Csr<float2>{op->rowptr_h, op->col_h, op->val32_h}, in, out, shift,
-                        op->ws.t64, op->ws.u64, s);
-  };
-  // |b_k|^2 in the caller's order
-  std::vector<double> bn2(ns + 1, 0.0);
-  HIP_TRY(launch_osb_norms(B, ns, n, d_part, d_tick, d_norm, s));
-  HIP_TRY(hipMemcpyAsync(bn2.data(), d_norm, sizeof(double) * ns, hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
-  double bmin = HUGE_VAL;
-  for (int k = 0; k < ns; ++k) bmin = std::min(bmin, std::sqrt(bn2[k]));
-
-  int iters = 0;
-  bool used = false;
-  if (distinct) {
-    // guesses x0 into x, common residual into r0
-    HIP_TRY(launch_osb_divdiff(B, d_orig, d_inv, W, ns, n, s));
-    for (int m = ns - 2; m >= 1; --m) {
-      HIP_TRY(apply(W + int64_t(m + 1) * n, prod, sv[m]));  // (A + s_m) Y_m
-      HIP_TRY(launch_osb_sub(W + int64_t(m) * n, prod, n, s));  // W[m] <- Y_{m-1}
-    }
-    if (ns >= 2) {
-      HIP_TRY(apply(W + n, prod, sv[0]));
-      HIP_TRY(launch_osb_sub(W, prod, n, s));
-    }
-    HIP_TRY(hipMemcpyAsync(r0, W, vec, hipMemcpyDeviceToDevice, s));
-    HIP_TRY(launch_osb_combine(W, d_w, d_orig, X, ns, n, s));
-    double rr = 0.0;
-    HIP_TRY(launch_osb_norms(r0, 1, n, d_part, d_tick + size_t(ns) * kTicketSite, d_norm + ns, s));
-    HIP_TRY(hipMemcpyAsync(&rr, d_norm + ns, sizeof(double), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    const double rn = std::sqrt(rr);
-    // the multishift stop that gives every shift tol |b_k|; beyond FP64's reach the
-    // guesses are dropped and each shift is solved from zero by the batched CG
-    const double tol_inner = rn > 0.0 ? prm.tol * bmin / rn : 0.0;
-    if (rn == 0.0) {
-      used = true;
-    } else if (std::isfinite(rn) && tol_inner >= 1e-14) {
-      used = true;
-      msc_params p2 = prm;
-      p2.verify = 0;
-      std::vector<double> rel;
-      int st = 0;
-      double bytes = 0.0, bnorm = 0.0;
-      const double tol_stop = tol_inner * (prm.prec == MSC_PREC_MIXED ? prm.mixed_margin : 1.0);
-      rc = run_multishift(op, reinterpret_cast<const double*>(r0), reinterpret_cast<double*>(dl),
-                          p2, nullptr, s, tol_stop, prm.prec, &rel, &iters, &st, &bytes, &bnorm);
-      if (rc != MSC_OK) return rc;
-      if (st != 0) {
-        set_error("msc_solve_multi_rhs: breakdown in the multishift solve of the common residual");
-        return MSC_EBREAKDOWN;
-      }
-      HIP_TRY(launch_osb_add(X, dl, int64_t(ns) * n, s));
-    }
-  }
-  if (!used) HIP_TRY(hipMemsetAsync(X, 0, vec * ns, s));
-
-  // every shift against its own b_k in FP64; those above tol continue with the batched CG
-  std::vector<double> rel(ns, 0.0);
-  int refine_iters = 0, n_refined = 0;
-  bool breakdown = false;
-  for (int g0 = 0; g0 < ns; g0 += kBssMax) {
-    const int m = std::min(kBssMax, ns - g0);
-    std::vector<double> sig(m), tol_abs(m), res;
-    std::vector<const double2*> f(m);
-    std::vector<double2*> x(m);
-    for (int j = 0; j < m; ++j) {
-      const int k = g0 + j;
-      sig[j] = op->sigma[k];
-      tol_abs[j] = prm.tol * std::sqrt(bn2[k]);
-      f[j] = B + int64_t(k) * n;
-      x[j] = X + int64_t(k) * n;
-    }
-    int inner = 0;
-    bool bd = false;
-    double bytes = 0.0;
-    rc = run_batched_cg(op, MSC_PREC_FP64, m, sig.data(), f.data(), x.data(), tol_abs.data(), 0.0,
-                        prm, s, res, &inner, &bytes, &bd);
-    if (rc != MSC_OK) return rc;
-    refine_iters = std::max(refine_iters, inner);
-    for (int j = 0; j < m; ++j) {
-      const double bk = std::sqrt(bn2[g0 + j]);
-      rel[g0 + j] = bk > 0.0 ? res[j] / bk : 0.0;
-    }
-    if (inner > 0) n_refined += m;  // the group needed CG iterations
-    if (bd) breakdown = true;
-  }
+  const int iters = out.iters, refine_iters = out.refine_iters, n_refined = out.n_refined;
+  const bool breakdown = out.breakdown;
+  const std::vector<double>& rel = out.rel;
   if (info) {
     clear_timing(*info);
     info->iters = iters;

@@ -35,6 +35,29 @@ template <class R> __device__ __forceinline__ double norm2d(const cplx<R>& v) {
 
 __device__ __forceinline__ double2 to_d(const float2 v) { return double2{double(v.x), double(v.y)}; }
 __device__ __forceinline__ double2 to_d(const double2 v) { return v; }
+// Streaming accesses: data a launch touches once (the shifted solutions and directions,
+// kept residuals, rows no other wave of the launch gathers, outputs the next kernel reads
+// back) carry the non-temporal hint, so that they do not evict from L2 what the launch
+// gathers again (neighbouring rows, the links).
+typedef double vd2_t __attribute__((ext_vector_type(2)));
+typedef float vf2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ double2 ld_stream(const double2* p) {
+  const vd2_t v = __builtin_nontemporal_load(reinterpret_cast<const vd2_t*>(p));
+  return double2{v.x, v.y};
+}
+__device__ __forceinline__ float2 ld_stream(const float2* p) {
+  const vf2_t v = __builtin_nontemporal_load(reinterpret_cast<const vf2_t*>(p));
+  return float2{v.x, v.y};
+}
+__device__ __forceinline__ void st_stream(double2* p, const double2& v) {
+  const vd2_t w = {v.x, v.y};
+  __builtin_nontemporal_store(w, reinterpret_cast<vd2_t*>(p));
+}
+__device__ __forceinline__ void st_stream(float2* p, const float2& v) {
+  const vf2_t w = {v.x, v.y};
+  __builtin_nontemporal_store(w, reinterpret_cast<vf2_t*>(p));
+}
+
 template <class R> __device__ __forceinline__ cplx<R> from_d(const double2 v);
 template <> __device__ __forceinline__ float2 from_d<float>(const double2 v) {
   return float2{float(v.x), float(v.y)};

@@ -609,13 +609,13 @@ __device__ __forceinline__ cplx<R> update_row(const MsArgs& a, const Plan& pl, d
   const double2 rd = to_d(rr), pd = to_d(pp);
   x0v.x = fma(step, pd.x, x0v.x);
   x0v.y = fma(step, pd.y, x0v.y);
-  x0[i] = x0v;
-  if (pl.keep >= 0) static_cast<cplx<R>*>(a.rkeep[pl.keep])[i] = rr;
+  st_stream(&x0[i], x0v);
+  if (pl.keep >= 0) st_stream(&static_cast<cplx<R>*>(a.rkeep[pl.keep])[i], rr);
   // kept residuals (zero beyond m, where the coefficients are zero too)
   double2 rk[kMaxSteps - 1];
 #pragma unroll
   for (int k = 0; k < kMaxSteps - 1; ++k)
-    rk[k] = k < pl.m ? to_d(static_cast<const cplx<R>*>(a.rkeep[k])[i]) : double2{0.0, 0.0};
+    rk[k] = k < pl.m ? to_d(ld_stream(&static_cast<const cplx<R>*>(a.rkeep[k])[i])) : double2{0.0, 0.0};
   // shifts in groups of MSC_UPD_GROUP: a group's loads are all issued before its first
   // store; a last, partial group is masked.  With one step (m = 0) the fused
   // multiply-adds round exactly as x += a p and p <- zeta r + b p.
@@ -627,8 +627,8 @@ __device__ __forceinline__ cplx<R> update_row(const MsArgs& a, const Plan& pl, d
 #pragma unroll
     for (int u = 0; u < kUpdGroup; ++u) {
       if (decltype(full)::value || u < cnt) {
-        pj[u] = pk[pl.po[q + u] + i];
-        xj[u] = x[pl.xo[q + u] + i];
+        pj[u] = ld_stream(&pk[pl.po[q + u] + i]);
+        xj[u] = ld_stream(&x[pl.xo[q + u] + i]);
       }
     }
 #pragma unroll
@@ -646,7 +646,7 @@ __device__ __forceinline__ cplx<R> update_row(const MsArgs& a, const Plan& pl, d
         }
         xv.x = fma(pl.cx[0][c], pjd.x, xv.x);
         xv.y = fma(pl.cx[0][c], pjd.y, xv.y);
-        x[pl.xo[c] + i] = xv;
+        st_stream(&x[pl.xo[c] + i], xv);
         if (pl.pw[c]) {
           const double c0 = pl.cp[0][c];
           double2 np{c0 * pjd.x, c0 * pjd.y};
@@ -660,7 +660,7 @@ __device__ __forceinline__ cplx<R> update_row(const MsArgs& a, const Plan& pl, d
           const double cr = pl.cp[m + 1][c];
           np.x = fma(cr, rd.x, np.x);
           np.y = fma(cr, rd.y, np.y);
-          pk[pl.po[c] + i] = from_d<R>(np);
+          st_stream(&pk[pl.po[c] + i], from_d<R>(np));
         }
       }
     }
@@ -669,7 +669,7 @@ __device__ __forceinline__ cplx<R> update_row(const MsArgs& a, const Plan& pl, d
   for (; q + kUpdGroup <= nact; q += kUpdGroup) group(q, kUpdGroup, std::true_type{});
   if (q < nact) group(q, nact - q, std::false_type{});
   const cplx<R> np = next_dir<R>(pl.bn, rr, pp);
-  pnew[i] = np;
+  st_stream(&pnew[i], np);
   return np;
 }
 
@@ -743,7 +743,7 @@ __global__ __launch_bounds__(kBlock) void k1_fused(MsArgs a) {
   const int64_t row0 = sl0 * kSlice + lane;
   const int64_t rc = (has0 && row0 < a.n) ? row0 : a.n - 1;
   const cplx<R> r_first = rv[rc], p_first = pv[rc];
-  const double2 x_first = x0[rc];
+  const double2 x_first = ld_stream(&x0[rc]);
   __shared__ Plan pl;
   head_plan<R>(a, e, pl);
   if (!pl.ok) return;
@@ -760,7 +760,8 @@ __global__ __launch_bounds__(kBlock) void k1_fused(MsArgs a) {
     cplx<R> p_row = p_i;
     if (upd) {
       if (live)
-        p_row = update_row<R>(a, pl, step, row, r_i, p_i, first ? x_first : x0[rr], x0, pnew);
+        p_row = update_row<R>(a, pl, step, row, r_i, p_i, first ? x_first : ld_stream(&x0[rr]), x0,
+                                pnew);
       else
         p_row = next_dir<R>(bn, r_i, p_i);
     }
@@ -777,7 +778,7 @@ __global__ __launch_bounds__(kBlock) void k1_fused(MsArgs a) {
       cfma<R>(v, d, p_row);
     }
     if (live) {
-      t[row] = v;
+      st_stream(&t[row], v);
       if (MHM)
         acc += norm2d<R>(v) + sigma0 * norm2d<R>(p_row);
       else
@@ -896,8 +897,8 @@ __global__ __launch_bounds__(kBlock) void k2_sell(MsArgs a) {
     const int64_t rr = row < a.n ? row : a.n - 1;  // lanes past n read a valid row, unused
     const cplx<R> tr = t[rr];
     Row o;
-    o.p = p[rr];
-    o.r = r[rr];
+    o.p = ld_stream(&p[rr]);
+    o.r = ld_stream(&r[rr]);
     if constexpr (ST) {
       o.q = stencil_row<R, MSC_STENCIL_DPR_K2>(pick_w<R>(a), rr, tr, -1, [&](int64_t c) { return t[c]; });
     } else {
@@ -917,7 +918,7 @@ __global__ __launch_bounds__(kBlock) void k2_sell(MsArgs a) {
     nr.x = rr.x - step * (qd.x + sigma0 * pr.x);
     nr.y = rr.y - step * (qd.y + sigma0 * pr.y);
     const cplx<R> st_r = from_d<R>(nr);
-    r[row] = st_r;
+    st_stream(&r[row], st_r);
     acc += norm2d<R>(st_r);
   };
   // the first slice's product runs while P's partials are on their way

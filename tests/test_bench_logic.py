@@ -30,7 +30,9 @@ def test_traffic_is_reported_only_for_the_measured_sources(tmp_path, monkeypatch
     data = json.load(open(bench.TRAFFIC_FILE))
     wl = sorted(data["workloads"])[0]
     name = sorted(data["workloads"][wl])[0]
-    prec, kern = [k for k, v in bench.KERNEL_NAMES.items() if v == name][0]
+    names = [(k, False) for k, v in bench.KERNEL_NAMES.items() if v == name] + \
+            [(k, True) for k, v in bench.KERNEL_NAMES_MF.items() if v == name]
+    (prec, kern), mf = names[0]
     ent = data["workloads"][wl][name]
     want = 1024.0 * (ent["fetch_kib"] * data["fetch_scale"] + ent["write_kib"] * data["write_scale"])
     # a summary whose digest matches the kernel sources as they are gives the figure
@@ -41,14 +43,14 @@ def test_traffic_is_reported_only_for_the_measured_sources(tmp_path, monkeypatch
     fresh = tmp_path / "fresh.json"
     fresh.write_text(json.dumps(data))
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(fresh))
-    got, kname = bench.measured_traffic(wl, prec, kern)
+    got, kname = bench.measured_traffic(wl, prec, kern, matrix_free=mf)
     assert kname == name and got == pytest.approx(want)
     # a digest that no longer matches the kernel sources turns the figure off
     data["kernel_source_sha256"] = "0" * 64
     stale = tmp_path / "hbm_traffic.json"
     stale.write_text(json.dumps(data))
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(stale))
-    got, kname = bench.measured_traffic(wl, prec, kern)
+    got, kname = bench.measured_traffic(wl, prec, kern, matrix_free=mf)
     assert got is None and kname == name
 
 

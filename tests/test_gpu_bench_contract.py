@@ -32,10 +32,14 @@ def test_bench_line_keeps_the_contract(cuda):
     assert d["max_true_rel_res"] <= 1e-10
     assert d["config"]["workload"].startswith("c1:")
     assert d["fp64_plain"]["steps"] == 2
-    # the matrix-free operator's lines beside the headline
-    mf = d["matrix_free"]
-    assert mf["mixed"]["converged"] is True and mf["fp64"]["converged"] is True
-    assert mf["mixed"]["max_true_rel_res"] <= 1e-10
+    # the headline is quoted on the matrix-free operator; the stored matrix's lines
+    # stand beside it
+    assert d["config"]["operator"] == "matrix_free"
+    st = d["stored_matrix"]
+    assert st["mixed"]["converged"] is True and st["fp64"]["converged"] is True
+    assert st["mixed"]["max_true_rel_res"] <= 1e-10
+    assert d["roofline"]["kernel_name"].endswith("true, true>") or \
+        d["roofline"]["kernel_name"] in ("k2_sell<double, true>", "k2_sell<float, true>")
     rf = d["roofline"]
     assert rf["bound"] == "hbm" and rf["unit"] == "GB/s" and rf["peak"] == 8000.0
     assert rf["frac"] == pytest.approx(rf["achieved"] / rf["peak"], abs=1e-4)
