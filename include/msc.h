@@ -209,7 +209,9 @@ msc_status msc_op_query(msc_op op, int64_t* n, int64_t* nnz, int32_t* ns, int32_
 /* Storage the operator holds besides its CSR matrix (see msc_format): *sell = 1 when the
  * sliced ELLPACK copy was built; *narrow has bit 0 set when the copy of the operator's
  * matrix has 16-bit column offsets and, for MSC_A_MHM, bit 1 when the copy of M^H has
- * them.  Either pointer may be NULL. */
+ * them; bit 2 when an operator from msc_op_create_staggered found every link in SU(3)
+ * (|U U^H - I| and |det U - 1| <= 1e-12) and its iteration reads the links' first two
+ * rows, rebuilding the third (a third less link traffic).  Either pointer may be NULL. */
 msc_status msc_op_storage(msc_op op, int32_t* sell, int32_t* narrow);
 
 /*

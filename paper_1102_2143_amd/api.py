@@ -185,13 +185,15 @@ class Operator:
 
     def storage(self):
         """{"sell": sliced ELLPACK copy built, "narrow": (matrix, M^H) copies with 16-bit
-        column offsets}."""
+        column offsets, "two_rows": a staggered operator whose links are in SU(3), read by
+        the iteration as their first two rows}."""
         sell, narrow = ctypes.c_int32(), ctypes.c_int32()
         st = self.lib.msc_op_storage(self.handle, ctypes.byref(sell), ctypes.byref(narrow))
         if st != L.MSC_OK:
             raise L.MscError(st, "msc_op_storage")
         return {"sell": bool(sell.value),
-                "narrow": (bool(narrow.value & 1), bool(narrow.value & 2))}
+                "narrow": (bool(narrow.value & 1), bool(narrow.value & 2)),
+                "two_rows": bool(narrow.value & 4)}
 
     def update_values(self, vals, stream=None):
         _need(_numel(vals) == self.nnz,

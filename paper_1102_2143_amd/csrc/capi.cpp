@@ -153,7 +153,10 @@ template <class V> double index_bytes(bool sell, const Sell<V>& m) {
 // s2 slices apart (s2 a multiple of s1): planes are cut into tiles of cs slices, the
 // largest divisor of s1 that keeps neighbouring planes (cs * slabs-per-XCD positions
 // apart in the sweep) within kTileSpan positions.  Zeros when the structure does not fit.
-constexpr int64_t kTileSpan = 96;
+#ifndef MSC_TILE_SPAN
+#define MSC_TILE_SPAN 48
+#endif
+constexpr int64_t kTileSpan = MSC_TILE_SPAN;
 SweepOrder lattice_order(int64_t nslices, int64_t s1, int64_t s2) {
   SweepOrder o{0, 0, 0, 0};
   if (s1 < 1 || s2 <= s1 || s2 % s1 != 0 || s2 > nslices / kXcds) return o;
@@ -260,6 +263,16 @@ MsArgs make_args(msc_op op, int lanes, const double* d_b, double* d_x) {
   return a;
 }
 
+// Which FP64 heads on the links form their product by the recurrence: all but the first
+// launch and the launches kTrEvery / 2 mod kTrEvery (off the timing samples' positions,
+// which start at multiples of 128); and how many of the first n launches do.
+bool tr_launch(bool eligible, int launch) {
+  return eligible && launch != 0 && launch % kTrEvery != kTrEvery / 2;
+}
+int tr_launches(int n) {
+  return n <= 1 ? 0 : n - 1 - (n + kTrEvery / 2 - 1) / kTrEvery;
+}
+
 // Algorithmic HBM bytes of one multishift iteration (each array touched once, gathers
 // counted once), per row: see the byte model in the design notes of the repository.
 // Algorithmic bytes of one launch: K1 (t = M p), K2 (r <- r - a (M^H t + sigma0 p)), the
@@ -279,9 +292,11 @@ struct MatBytes {
   double m, mh;
 };
 MatBytes mat_bytes(int kind, int prec, double n, double nnz, double nnz_h, double ib, double ibh,
-                   bool stencil) {
+                   int stencil) {
   const double w = prec == MSC_PREC_MIXED ? 8.0 : 16.0;
-  if (stencil) return MatBytes{12.0 * w * n, 12.0 * w * n};
+  // links: each read once per site and direction, 3 or 2 rows of 3 values: 12 or 8
+  // values per row of the operator
+  if (stencil) return MatBytes{4.0 * stencil * w * n, 4.0 * stencil * w * n};
   return MatBytes{nnz * (w + ib) + 4.0 * (n + 1),
                   kind == MSC_A_MHM ? nnz_h * (w + ibh) + 4.0 * (n + 1) : 0.0};
 }
@@ -364,7 +379,9 @@ msc_status run_multishift(msc_op op, const double* d_b, double* d_x, const msc_p
   // the iteration's two operator halves from the links: the default for staggered
   // operators (the reliable update, verification and refinement keep the stored copies)
   a64.stencil = op->stencil && a64.sell &&
-                (prm.format == MSC_FORMAT_AUTO || prm.format == MSC_FORMAT_STENCIL) ? 1 : 0;
+                (prm.format == MSC_FORMAT_AUTO || prm.format == MSC_FORMAT_STENCIL)
+                    ? (op->two_rows ? 2 : 3) : 0;
+  if (a64.stencil == 2) a64.w64 = op->wc64;
   a64.ord = op->order;
   a64.ord.on = (prm.sweep == 0 && op->order.s1 > 0) ? 1 : 0;
   if (prm.format == MSC_FORMAT_SELL32 && op->sell) {
@@ -378,6 +395,11 @@ msc_status run_multishift(msc_op op, const double* d_b, double* d_x, const msc_p
   }
   const double ib = index_bytes(a64.sell, a64.s64), ibh = index_bytes(a64.sell, a64.sh64);
   MsArgs a32 = a64;
+  // the complex64 phase reads all nine values of each link: rebuilding the third row
+  // costs those kernels more in arithmetic and loads than the third less link traffic
+  // saves (measured at 32^3x64: head 386 -> 458 us, K2 212 -> 239 us), while the FP64
+  // ones gain (K2 466 -> 376 us)
+  if (a32.stencil != 0) a32.stencil = 3;
   const bool mixed = prec == MSC_PREC_MIXED;
   if (mixed) {
     a32.r = op->ws.r32;
@@ -451,6 +473,9 @@ msc_status run_multishift(msc_op op, const double* d_b, double* d_x, const msc_p
       const bool ru = ru_period || (phase == MSC_PREC_MIXED && prm.reliable_every > 0 &&
                                     since > 0 && since % kRuCheck == 0);
       cur->ru_force = ru_period ? 1 : 0;
+      // links, FP64: the head's product by the recurrence t' = M r + b t; a direct one in
+      // the first launch (no old t yet) and every kTrEvery launches
+      cur->t_rec = tr_launch(phase == MSC_PREC_FP64 && cur->stencil != 0, launched) ? 1 : 0;
       cur->defer_ok = 1;
       cur->steps = prm.update_steps;
       HIP_TRY(launch_iteration(phase, *cur, s, ev, ru));
@@ -517,9 +542,12 @@ msc_status run_multishift(msc_op op, const double* d_b, double* d_x, const msc_p
       const int kept = h.smp_mode[q] == 1 ? 1 : h.smp_m[q];
       const int phq = ph32 ? MSC_PREC_MIXED : MSC_PREC_FP64;
       const KernelBytes kb =
-          kernel_bytes(op->kind, phq, nn, mat_bytes(op->kind, phq, nn, nz, nzh, ib, ibh, a64.stencil),
+          kernel_bytes(op->kind, phq, nn, mat_bytes(op->kind, phq, nn, nz, nzh, ib, ibh,
+                                                   phq == MSC_PREC_FP64 ? a64.stencil : a32.stencil),
                        double(act), pending, kept);
-      kby[0] += a64.sell ? kb.head : kb.k1;
+      // a recurrence head also reads the old t (its own row)
+      const bool trq = tr_launch(phq == MSC_PREC_FP64 && a64.stencil != 0, L);
+      kby[0] += (a64.sell ? kb.head : kb.k1) + (trq ? 16.0 * nn : 0.0);
       kby[1] += kb.k2;
       if (!a64.sell) kby[2] += kb.upd;
       (apart ? info->fp64_kernel_samples : info->kernel_samples) += 1;
@@ -542,13 +570,13 @@ msc_status run_multishift(msc_op op, const double* d_b, double* d_x, const msc_p
   const double act64 = h.n_shift_upd[0], act32 = h.n_shift_upd[1];
   const double kept64 = h.n_defer[0] + h.n_two[0], kept32 = h.n_defer[1] + h.n_two[1];
   const double nn = double(op->n), nz = double(op->nnz), nzh = double(op->nnz_h);
-  const bool stn = a64.stencil != 0;
   *bytes_out = iter_bytes(op->kind, MSC_PREC_FP64, nn,
-                          mat_bytes(op->kind, MSC_PREC_FP64, nn, nz, nzh, ib, ibh, stn), act64,
+                          mat_bytes(op->kind, MSC_PREC_FP64, nn, nz, nzh, ib, ibh, a64.stencil), act64,
                           double(iters_fp64), kept64) +
                iter_bytes(op->kind, MSC_PREC_MIXED, nn,
-                          mat_bytes(op->kind, MSC_PREC_MIXED, nn, nz, nzh, ib, ibh, stn), act32,
+                          mat_bytes(op->kind, MSC_PREC_MIXED, nn, nz, nzh, ib, ibh, a32.stencil), act32,
                           double(fin.iter - iters_fp64), kept32) +
+               (a64.stencil != 0 ? 16.0 * nn * double(tr_launches(iters_fp64)) : 0.0) +
                double(h.n_reliable) * (nz * (16.0 + ib) + nzh * (16.0 + ibh) +
                                        4.0 * (nn + 1) * (op->kind == MSC_A_MHM ? 2.0 : 1.0) +
                                        nn * (16.0 * 3 + 8.0));
@@ -1385,6 +1413,50 @@ msc_status check_op(msc_op op) {
 // New values of the stored matrix (same pattern): copies, casts, M^H and sliced copies.
 msc_status update_values_impl(msc_op op, const double* d_vals, hipStream_t s);
 
+// Links of a staggered operator in SU(3) (to 1e-12) are also kept as their first two
+// rows, which the iteration reads (it rebuilds the third); otherwise that copy is off.
+constexpr double kSu3Tol = 1e-12;
+msc_status refresh_two_rows(msc_op op, const double2* d_links, hipStream_t s) {
+  const int64_t nlinks = 4 * op->w64.vol;
+  unsigned long long* d_dev = nullptr;
+  HIP_TRY(dalloc(&d_dev, 1));
+  unsigned long long bits = 0;
+  hipError_t e = hipMemsetAsync(d_dev, 0, sizeof(unsigned long long), s);
+  if (e == hipSuccess) e = launch_su3_deviation(d_links, nlinks, d_dev, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(&bits, d_dev, sizeof bits, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(d_dev);
+  if (e != hipSuccess) {
+    set_error("SU(3) check of the links: %s", hipGetErrorString(e));
+    return MSC_EHIP;
+  }
+  double dev = 0.0;
+  std::memcpy(&dev, &bits, sizeof dev);
+  op->two_rows = false;
+  if (!(dev <= kSu3Tol)) return MSC_OK;
+  if (!op->wc64.w) {
+    double2* w64 = nullptr;
+    float2* w32 = nullptr;
+    HIP_TRY(dalloc(&w64, size_t(6) * size_t(nlinks)));
+    e = dalloc(&w32, size_t(6) * size_t(nlinks));
+    if (e != hipSuccess) {
+      dfree(w64);
+      set_error("two-row links: %s", hipGetErrorString(e));
+      return e == hipErrorOutOfMemory ? MSC_ENOMEM : MSC_EHIP;
+    }
+    op->wc64 = op->w64;
+    op->wc64.w = w64;
+    op->wc64.rows = 2;
+    op->wc32 = op->w32;
+    op->wc32.w = w32;
+    op->wc32.rows = 2;
+  }
+  HIP_TRY(launch_two_rows(op->w64.w, nlinks, const_cast<double2*>(op->wc64.w),
+                          const_cast<float2*>(op->wc32.w), s));
+  op->two_rows = true;
+  return MSC_OK;
+}
+
 struct MultiRhsOut {
   int iters = 0, refine_iters = 0, n_refined = 0;
   bool breakdown = false;
@@ -1851,6 +1923,11 @@ msc_status msc_op_create_staggered(msc_op* out, const int32_t* dims, double mass
   op->order = (op->sell && plane % kSlice == 0)
                   ? lattice_order(op->sell_m.nslices, plane / kSlice, slab / kSlice)
                   : SweepOrder{0, 0, 0, 0};
+  rc = refresh_two_rows(op, reinterpret_cast<const double2*>(d_links), s);
+  if (rc != MSC_OK) {
+    msc_op_destroy(op);
+    return rc;
+  }
   *out = op;
   return MSC_OK;
 }
@@ -1876,6 +1953,7 @@ msc_status msc_op_update_links(msc_op op, const double* d_links, msc_stream stre
   if (rowptr) (void)hipFree(rowptr);
   if (col) (void)hipFree(col);
   if (vals) (void)hipFree(vals);
+  if (rc == MSC_OK) rc = refresh_two_rows(op, reinterpret_cast<const double2*>(d_links), s);
   return rc;
 }
 
@@ -1908,7 +1986,8 @@ msc_status msc_op_storage(msc_op op, int32_t* sell, int32_t* narrow) {
   if (sell) *sell = op->sell ? 1 : 0;
   if (narrow)
     *narrow = (op->sell && op->sell_m.col16 ? 1 : 0) |
-              (op->sell && op->kind == MSC_A_MHM && op->sell_mh.col16 ? 2 : 0);
+              (op->sell && op->kind == MSC_A_MHM && op->sell_mh.col16 ? 2 : 0) |
+              (op->stencil && op->two_rows ? 4 : 0);
   return MSC_OK;
 }
 
@@ -2619,6 +2698,8 @@ void msc_op_destroy(msc_op op) {
   dfree(op->rdiag32);
   if (op->w64.w) (void)hipFree(const_cast<double2*>(op->w64.w));
   if (op->w32.w) (void)hipFree(const_cast<float2*>(op->w32.w));
+  if (op->wc64.w) (void)hipFree(const_cast<double2*>(op->wc64.w));
+  if (op->wc32.w) (void)hipFree(const_cast<float2*>(op->wc32.w));
   delete op;
 }
 

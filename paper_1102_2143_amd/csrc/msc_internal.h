@@ -15,6 +15,7 @@ constexpr int kMaxShifts = 64;
 constexpr int kBlock = 256;          // threads per workgroup for every solver kernel
 constexpr int kMaxGrid = 2048;       // 256 CUs x 8 resident workgroups
 constexpr int kXcds = 8;             // MI355X: 8 accelerator complex dies, one L2 each
+constexpr int kTrEvery = 64;         // launches between two direct products t = M p
 // A "last workgroup" ticket site: eight group counters 128 bytes apart and a final one.
 constexpr int kTicketStride = 32;
 constexpr int kTicketSite = 9 * kTicketStride;
@@ -152,6 +153,7 @@ template <class V> struct Sell {
 // (eta_mu does not depend on x_mu).  Row 3 s + c of M is colour c of site s.
 template <class V> struct Stencil {
   const V* w = nullptr;
+  int32_t rows = 3;  // rows of each link stored: 3, or 2 (SU(3): the third is rebuilt)
   int32_t L[4] = {0, 0, 0, 0};
   int64_t stride[4] = {0, 0, 0, 0};  // 1, L0, L0 L1, L0 L1 L2
   int64_t vol = 0;
@@ -261,6 +263,9 @@ struct msc_op_s {
   bool stencil = false;          // matrix-free staggered operator (links kept below)
   msc::Stencil<double2> w64;     // W_mu(x) = eta_mu(x)/2 U_mu(x), complex128 and
   msc::Stencil<float2> w32;      // complex64 copies (device memory owned by the op)
+  bool two_rows = false;         // every link is in SU(3): the iteration reads wc64 / wc32,
+  msc::Stencil<double2> wc64;    // the first two rows of each W_mu(x) (6 values), and
+  msc::Stencil<float2> wc32;     // rebuilds the third from them
   bool sell = false;             // sliced ELLPACK copies built (M, and M^H for kind MHM)
   msc::SellStore sell_m, sell_mh;
 };
@@ -298,6 +303,15 @@ hipError_t launch_stencil_links(const double2* links, const Stencil<double2>& ge
                                 double2* w64, float2* w32, hipStream_t s);
 hipError_t launch_stencil_csr(const Stencil<double2>& op, int64_t* rowptr, int32_t* col,
                               double2* vals, hipStream_t s);
+// Largest deviation of the caller's links [4][V][3][3] from SU(3) over all links,
+// max(|U U^H - I|, |det U - 1|) entrywise, into *dev (as the bits of a double; the
+// caller zeroes it first).
+hipError_t launch_su3_deviation(const double2* links, int64_t nlinks, unsigned long long* dev,
+                                hipStream_t s);
+// The first two rows of every W_mu(x) of the full copy w64 [4][V][9] into wc64 / wc32
+// [4][V][6].
+hipError_t launch_two_rows(const double2* w64, int64_t nlinks, double2* wc64, float2* wc32,
+                           hipStream_t s);
 
 // multishift.hip
 struct MsArgs {
@@ -322,8 +336,10 @@ struct MsArgs {
   int steps;             // steps of the all-shift update folded into one pass (1..kMaxSteps)
   int defer_ok;          // 1: this launch's head may defer its all-shift update
   int ru_force;          // reliable-update launch: 1 runs it whatever the residual
-  int stencil;           // the head and K2 apply M and M^H from links (kind MHM, sell = 1)
+  int stencil;           // the head and K2 apply M and M^H from links (kind MHM, sell = 1):
+                         // 0 no, 3 full links, 2 two rows per link (w64 / w32 in that form)
   SweepOrder ord;        // slice order of the head and K2 on the sliced path
+  int t_rec;             // links, FP64: this head forms t' = M r + b t (the old t = M p)
   Stencil<double2> w64;
   Stencil<float2> w32;
   int sample;            // slot of SolveState::smp_* for this head, -1: not sampled

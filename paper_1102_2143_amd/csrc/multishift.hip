@@ -143,6 +143,12 @@ __device__ __forceinline__ cplx<R> next_dir(double b, const cplx<R>& r, const cp
 #ifndef MSC_STENCIL_DPR_K2
 #define MSC_STENCIL_DPR_K2 2
 #endif
+#ifndef MSC_STENCIL_DPR_K2_TWO
+#define MSC_STENCIL_DPR_K2_TWO 1
+#endif
+#ifndef MSC_STENCIL_DPR_HEAD_TR
+#define MSC_STENCIL_DPR_HEAD_TR 1
+#endif
 
 // Pairs per round trip when each entry gathers two vectors (MSC_SELL_KPN32 / 64).
 #ifndef MSC_SELL_KPN32
@@ -713,8 +719,13 @@ __global__ __launch_bounds__(kBlock) void k_update(MsArgs a) {
 // its own row (x, p_j, and p' = r + b p stored in the other buffer), then t = M p' takes
 // p' at the gathered columns from r and the old p, rounded exactly as the owning lane
 // rounds it; P = |t|^2 + sigma0 |p'|^2 (A = M^H M) or Re p'^H t + sigma0 |p'|^2.
-// ST: M is applied from the links (matrix-free staggered operator, A = M^H M).
-template <class R, bool MHM, bool ST = false>
+// LR: M is applied from the links (matrix-free staggered operator, A = M^H M), 3 or 2
+// rows stored per link; 0: the sliced ELLPACK copy.
+// TR (links, FP64): t' = M r + b t instead of M (r + b p), the old t being M p from the
+// previous head: one gathered vector instead of two.  The rounding of the recurrence
+// stays at the FP64 level over the launches between two direct products (the host
+// interleaves a direct one every kTrEvery launches).
+template <class R, bool MHM, int LR = 0, bool TR = false>
 __global__ __launch_bounds__(kBlock) void k1_fused(MsArgs a) {
   const SolveState* st = a.st;
   const RotState& rs = st->rot[a.par];
@@ -768,9 +779,17 @@ __global__ __launch_bounds__(kBlock) void k1_fused(MsArgs a) {
     if (!pl.spmv) continue;
     // without a pending update p' = p: the same product with r := p and b = 0 (exact)
     cplx<R> v;
-    if constexpr (ST) {
+    if constexpr (LR != 0 && TR) {
+      // without a pending update bn = 0 and the product is M p
       const cplx<R>* __restrict__ rg = upd ? rv : pv;
-      v = stencil_row<R, MSC_STENCIL_DPR_HEAD>(pick_w<R>(a), rr, p_row, 1,
+      const cplx<R> told = ld_stream(&t[rr]);
+      v = stencil_row<R, MSC_STENCIL_DPR_HEAD_TR, LR>(pick_w<R>(a), rr, upd ? r_i : p_i, 1,
+                                                       [&](int64_t c) { return rg[c]; });
+      v.x = fma(bn, told.x, v.x);
+      v.y = fma(bn, told.y, v.y);
+    } else if constexpr (LR != 0) {
+      const cplx<R>* __restrict__ rg = upd ? rv : pv;
+      v = stencil_row<R, MSC_STENCIL_DPR_HEAD, LR>(pick_w<R>(a), rr, p_row, 1,
                          [&](int64_t c) { return next_dir<R>(bn, rg[c], pv[c]); });
     } else {
       const cplx<R> d = m.diag[rr];
@@ -870,8 +889,8 @@ __global__ __launch_bounds__(kBlock) void k2_mhm(MsArgs a) {
 }
 
 // ---- K2 on the sliced ELLPACK copy of M^H: one row per lane, one slice per wave ------
-// ST: M^H = m - D applied from the links instead.
-template <class R, bool ST = false>
+// LR (3 or 2 rows per link): M^H = m - D applied from the links instead.
+template <class R, int LR = 0>
 __global__ __launch_bounds__(kBlock) void k2_sell(MsArgs a) {
   const SolveState* st = a.st;
   const RotState& ns = st->rot[a.par ^ 1];  // written by this iteration's head
@@ -899,8 +918,9 @@ __global__ __launch_bounds__(kBlock) void k2_sell(MsArgs a) {
     Row o;
     o.p = ld_stream(&p[rr]);
     o.r = ld_stream(&r[rr]);
-    if constexpr (ST) {
-      o.q = stencil_row<R, MSC_STENCIL_DPR_K2>(pick_w<R>(a), rr, tr, -1, [&](int64_t c) { return t[c]; });
+    if constexpr (LR != 0) {
+      o.q = stencil_row<R, LR == 3 ? MSC_STENCIL_DPR_K2 : MSC_STENCIL_DPR_K2_TWO, LR>(
+          pick_w<R>(a), rr, tr, -1, [&](int64_t c) { return t[c]; });
     } else {
       const cplx<R> d = mh.diag[rr];
       o.q = sell_row<R>(mh, t, sl, lane);
@@ -1437,12 +1457,14 @@ hipError_t iteration_impl(const MsArgs& args, hipStream_t s, hipEvent_t* ev, boo
   const int g1 = grid_rows(args.n, kBlock / args.lanes, args.grid);
   const int g3 = grid_rows(args.n, kBlock, args.grid);
   MsArgs a = args;
-  const bool st = a.sell && a.stencil && a.kind == MSC_A_MHM;
+  const int lr = (a.sell && a.kind == MSC_A_MHM) ? a.stencil : 0;  // links: rows per link
   // the head and K2 on the sliced path, and their grids: with a lattice order, the
   // resident workgroups only (their waves sweep the order in step)
-  auto head = st ? k1_fused<R, true, true>
-                 : (a.kind == MSC_A_MHM ? k1_fused<R, true> : k1_fused<R, false>);
-  auto k2s = st ? k2_sell<R, true> : k2_sell<R>;
+  const bool tr = a.t_rec && std::is_same<R, double>::value;
+  auto head = lr == 3 ? (tr ? k1_fused<R, true, 3, true> : k1_fused<R, true, 3>)
+              : lr == 2 ? (tr ? k1_fused<R, true, 2, true> : k1_fused<R, true, 2>)
+                        : (a.kind == MSC_A_MHM ? k1_fused<R, true> : k1_fused<R, false>);
+  auto k2s = lr == 3 ? k2_sell<R, 3> : lr == 2 ? k2_sell<R, 2> : k2_sell<R>;
   int gh = g3, gk = g3;
   if (a.sell && a.ord.on) {
     gh = resident_grid(reinterpret_cast<const void*>(head), g3);

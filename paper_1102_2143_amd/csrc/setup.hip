@@ -479,6 +479,56 @@ __global__ void k_stencil_links(const double2* __restrict__ links, Stencil<doubl
   }
 }
 
+// max over the links of |U U^H - I| and |det U - 1| (entrywise moduli), one link per
+// thread; non-negative doubles order like their bit patterns, so one atomicMax on the
+// bits keeps the largest.
+__global__ void k_su3_deviation(const double2* __restrict__ links, int64_t nlinks,
+                                unsigned long long* __restrict__ dev) {
+  double worst = 0.0;
+  for (int64_t l = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; l < nlinks;
+       l += int64_t(gridDim.x) * blockDim.x) {
+    double2 u[3][3];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) u[i][j] = links[l * 9 + 3 * i + j];
+    // U U^H - I
+    for (int i = 0; i < 3; ++i)
+      for (int k = 0; k < 3; ++k) {
+        double re = (i == k) ? -1.0 : 0.0, im = 0.0;
+        for (int j = 0; j < 3; ++j) {  // u[i][j] conj(u[k][j])
+          re += u[i][j].x * u[k][j].x + u[i][j].y * u[k][j].y;
+          im += u[i][j].y * u[k][j].x - u[i][j].x * u[k][j].y;
+        }
+        worst = fmax(worst, sqrt(re * re + im * im));
+      }
+    // det U = u0 . (u1 x u2)
+    double dre = 0.0, dim = 0.0;
+    for (int j = 0; j < 3; ++j) {
+      const int j1 = (j + 1) % 3, j2 = (j + 2) % 3;
+      const double cre = u[1][j1].x * u[2][j2].x - u[1][j1].y * u[2][j2].y -
+                         (u[1][j2].x * u[2][j1].x - u[1][j2].y * u[2][j1].y);
+      const double cim = u[1][j1].x * u[2][j2].y + u[1][j1].y * u[2][j2].x -
+                         (u[1][j2].x * u[2][j1].y + u[1][j2].y * u[2][j1].x);
+      dre += u[0][j].x * cre - u[0][j].y * cim;
+      dim += u[0][j].x * cim + u[0][j].y * cre;
+    }
+    const double dd = sqrt((dre - 1.0) * (dre - 1.0) + dim * dim);
+    worst = fmax(worst, isfinite(dd) ? dd : 1e300);
+  }
+  if (!(worst >= 0.0)) worst = 1e300;  // NaN entries
+  atomicMax(dev, static_cast<unsigned long long>(__double_as_longlong(worst)));
+}
+
+__global__ void k_two_rows(const double2* __restrict__ w64, int64_t nlinks,
+                           double2* __restrict__ wc64, float2* __restrict__ wc32) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < nlinks * 6;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t l = i / 6;
+    const double2 v = w64[l * 9 + (i - 6 * l)];
+    wc64[i] = v;
+    wc32[i] = float2{float(v.x), float(v.y)};
+  }
+}
+
 // The scalar CSR of M = m + D from w, one thread per row: the row's own site (the mass
 // on the diagonal) and its eight neighbours (three columns each), in ascending site order,
 // so the columns come out sorted.
@@ -555,6 +605,20 @@ hipError_t launch_stencil_links(const double2* links, const Stencil<double2>& ge
   const int64_t total = 4 * geo.vol * 9;
   const int64_t g = std::min<int64_t>((total + 255) / 256, 8192);
   k_stencil_links<<<dim3(unsigned(g)), 256, 0, s>>>(links, geo, w64, w32);
+  return hipGetLastError();
+}
+
+hipError_t launch_su3_deviation(const double2* links, int64_t nlinks, unsigned long long* dev,
+                                hipStream_t s) {
+  const int64_t g = std::min<int64_t>((nlinks + 255) / 256, 8192);
+  k_su3_deviation<<<dim3(unsigned(std::max<int64_t>(g, 1))), 256, 0, s>>>(links, nlinks, dev);
+  return hipGetLastError();
+}
+
+hipError_t launch_two_rows(const double2* w64, int64_t nlinks, double2* wc64, float2* wc32,
+                           hipStream_t s) {
+  const int64_t g = std::min<int64_t>((6 * nlinks + 255) / 256, 8192);
+  k_two_rows<<<dim3(unsigned(std::max<int64_t>(g, 1))), 256, 0, s>>>(w64, nlinks, wc64, wc32);
   return hipGetLastError();
 }
 

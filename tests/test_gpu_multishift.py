@@ -158,7 +158,7 @@ def test_paper_poisson_workload_small(cuda, prec):
     sigma = W.logspace_shifts(1e-3, 1.0, 15)
     b = np.ones(n, dtype=np.complex128)
     op = _op(dict(rowptr=rowptr, col=col, vals=vals, n=n, kind="herm"), cuda)
-    assert op.storage() == {"sell": True, "narrow": (True, False)}
+    assert op.storage() == {"sell": True, "narrow": (True, False), "two_rows": False}
     op.set_shifts(sigma)
     x, info = op.solve(b, tol=1e-10, prec=prec)
     ref = O.cg_m(O.shifted_apply("herm", rowptr, col, vals, n), b, sigma, tol=1e-10)
@@ -353,7 +353,7 @@ def test_narrow_and_wide_columns_agree_bitwise(c0, cuda, prec):
     # offsets; they name the same entries as the 32-bit columns, so the solves agree in
     # every bit, and the sampled kernels' byte counts differ by 2 bytes per entry read
     op = _op(c0, cuda)
-    assert op.storage() == {"sell": True, "narrow": (True, True)}
+    assert op.storage() == {"sell": True, "narrow": (True, True), "two_rows": False}
     op.set_shifts(c0["sigma"])
     x16, i16 = op.solve(c0["b"], tol=1e-10, prec=prec, format="sell", timing=8)
     x32, i32 = op.solve(c0["b"], tol=1e-10, prec=prec, format="sell32", timing=8)

@@ -11,6 +11,9 @@ stored matrix), while the library also builds the equivalent CSR for its other k
   <= 1e-8, iterations and freeze iterations within 2; mixed at 1e-12 against the oracle
   at 1e-13), and against the dense solve;
 * new links through msc_op_update_links give what a fresh operator gives;
+* SU(3) links are read as their first two rows (the third rebuilt in the kernels):
+  reported by storage(), and links off SU(3) (scaled, or a U(3) phase) keep all nine
+  values, through creation and through update_links, with the same parity;
 * the misuse cases are rejected.
 """
 import numpy as np
@@ -152,3 +155,40 @@ def test_misuse_is_rejected(c0, cuda):
         cs.update_links(c0["links"])
     op.close()
     cs.close()
+
+
+def test_two_row_links_and_their_fallback(c0, cuda):
+    from paper_1102_2143_amd import Operator
+    dims, mass = c0["dims"], c0["mass"]
+    op = Operator.staggered(c0["links"], dims, mass, device=cuda)
+    assert op.storage()["two_rows"] is True
+    op.set_shifts(c0["sigma"])
+    for prec in ("fp64", "mixed"):
+        x, info = op.solve(c0["b"], tol=1e-10, prec=prec)
+        assert info["status"] == "ok" and np.all(info["true_rel_res"] <= 1e-10)
+        assert np.all(_rel(x.cpu().numpy(), c0["ref"]["x"]) <= 1e-8)
+        if prec == "fp64":
+            assert abs(info["iters"] - c0["ref"]["iters"]) <= 2
+    # links off SU(3): a U(3) phase on one link, then every link scaled
+    for bad in ("phase", "scale"):
+        links = np.array(c0["links"], copy=True)
+        if bad == "phase":
+            links[2, 5] = links[2, 5] * np.exp(0.3j)
+        else:
+            links = links * 1.01
+        op.update_links(links)
+        assert op.storage()["two_rows"] is False
+        rowptr, col, vals = W.staggered_csr(links, dims, mass)
+        ap = O.shifted_apply("mhm", rowptr, col, vals, c0["n"])
+        ref = O.cg_m(ap, c0["b"], c0["sigma"], tol=1e-10)
+        x, info = op.solve(c0["b"], tol=1e-10, prec="fp64")
+        assert info["status"] == "ok"
+        assert np.all(_rel(x.cpu().numpy(), ref["x"]) <= 1e-8)
+        assert abs(info["iters"] - ref["iters"]) <= 2
+        fresh = Operator.staggered(links, dims, mass, device=cuda)
+        assert fresh.storage()["two_rows"] is False
+        fresh.close()
+    # back to SU(3) links: two rows again
+    op.update_links(c0["links"])
+    assert op.storage()["two_rows"] is True
+    op.close()
