@@ -808,6 +808,21 @@ msc_status run_batched_cg(msc_op op, int prec, int m, const double* sig, const d
   return MSC_OK;
 }
 
+// Inner precision of the per-shift refinement (defect correction: FP64 residuals outside,
+// batched CG inside).  Shifts that miss tol by a small factor (the usual case after a
+// mixed solve: well under one digit to gain) are refined in FP64 in one inner solve; when
+// some shift is more than kRefineMixedGap x tol away, the inner CG runs in complex64, each
+// cycle reducing its residual kRefineDelta times before the next FP64 residual.
+constexpr double kRefineMixedGap = 1e3;
+constexpr double kRefineDelta = 1e-4;
+int refine_precision(const std::vector<double>& rel, const std::vector<int>& todo,
+                     const msc_params& prm) {
+  if (prm.prec != MSC_PREC_MIXED) return MSC_PREC_FP64;
+  double worst = 0.0;
+  for (int k : todo) worst = std::max(worst, std::isfinite(rel[k]) ? rel[k] : HUGE_VAL);
+  return worst > kRefineMixedGap * prm.tol ? MSC_PREC_MIXED : MSC_PREC_FP64;
+}
+
 // The full solve: multishift sequence, FP64 verification of every shift, and batched
 // refinement of the shifts whose true residual is above tol.  With the mixed path and
 // refinement on, shifts that the complex64 phase left slightly above tol are refined in
@@ -835,9 +850,8 @@ msc_status solve_impl(msc_op op, const double* d_b, double* d_x, const msc_param
       if (!(rel[k] <= prm.tol)) todo.push_back(k);
     if (refine && !todo.empty() && bnorm > 0.0) {
       n_refined = int(todo.size());
-      // the shifts miss tol by a small factor at most: refine them in FP64
-      const int rprec = MSC_PREC_FP64;
-      const double delta = 0.0;
+      const int rprec = refine_precision(rel, todo, prm);
+      const double delta = rprec == MSC_PREC_MIXED ? kRefineDelta : 0.0;
       for (size_t g0 = 0; g0 < todo.size(); g0 += kBssMax) {
         const int m = int(std::min<size_t>(kBssMax, todo.size() - g0));
         std::vector<double> sig(m), tol_abs(m), res;
@@ -1336,8 +1350,10 @@ struct BatchRun {
             }
             double bytes = 0.0;
             bool b1 = false;
-            const msc_status rc = run_batched_cg(op, MSC_PREC_FP64, int(todo.size()), sig.data(), f.data(), xs.data(),
-                                tol_abs.data(), 0.0, prm, sint, res, &refine_iters, &bytes, &b1);
+            const int rprec = refine_precision(rel, todo, prm);
+            const msc_status rc = run_batched_cg(op, rprec, int(todo.size()), sig.data(), f.data(), xs.data(),
+                                tol_abs.data(), rprec == MSC_PREC_MIXED ? kRefineDelta : 0.0, prm,
+                                sint, res, &refine_iters, &bytes, &b1);
             if (rc != MSC_OK) return rc;
             bd = bd || b1;
             for (size_t j = 0; j < todo.size(); ++j) rel[todo[j]] = res[j] / bn;

@@ -100,8 +100,9 @@ def test_mixed_margin_trades_iterations_for_residual(c0, cuda):
 @pytest.mark.parametrize("fmt", ["auto", "csr"])
 @pytest.mark.parametrize("switch_tol", [1.0, 1e-3])
 def test_mixed_early_switch_is_refined_to_tol(c0, cuda, switch_tol, fmt):
-    # switching early leaves larger complex64 gaps; the FP64 refinement (a batched CG on
-    # the sliced ELLPACK copies, or on CSR) closes them
+    # switching early leaves larger complex64 gaps; the refinement (FP64 residuals, a
+    # batched CG on the sliced ELLPACK copies or on CSR, in complex64 cycles of 1e-4 when
+    # a shift is more than 1e3 tol away, else in FP64) closes them
     op = _op(c0, cuda)
     op.set_shifts(c0["sigma"])
     x, info = op.solve(c0["b"], tol=1e-10, prec="mixed", switch_tol=switch_tol, format=fmt)
@@ -117,8 +118,8 @@ def test_mixed_early_switch_is_refined_to_tol(c0, cuda, switch_tol, fmt):
 
 @pytest.mark.parametrize("lanes", [4, 16, 32])
 def test_refinement_on_csr_at_every_lane_width(c0, cuda, lanes):
-    # an early switch leaves every shift above tol, so the FP64 refinement (residuals and
-    # batched CG on CSR with the given lanes per row) does the rest
+    # an early switch leaves every shift far above tol, so the refinement (FP64 residuals,
+    # complex64 batched-CG cycles on CSR with the given lanes per row) does the rest
     op = _op(c0, cuda)
     op.set_shifts(c0["sigma"])
     x, info = op.solve(c0["b"], tol=1e-10, prec="mixed", switch_tol=1.0, format="csr",
