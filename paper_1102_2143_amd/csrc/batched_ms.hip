@@ -262,14 +262,14 @@ __device__ void bk2_chunk(const BatchSys& S, BatchState* st, const int4& ch, int
   // steps this rhs deferred in previous BK3s, composed (read before any lane writes the
   // state): x_k gained cx[0] p_k + sum_i cx[i+1] r_i, p_k now is cp[0] p_k + sum_i cp[i+1] r_i
   const int md = q < nrhs ? st->ndef[q] : 0;
-  double cx[kMaxSteps + 1], cp[kMaxSteps + 1];
+  double cx[kBatchMaxSteps + 1], cp[kBatchMaxSteps + 1];
 #pragma unroll
-  for (int i = 0; i <= kMaxSteps; ++i) cx[i] = cp[i] = 0.0;
+  for (int i = 0; i <= kBatchMaxSteps; ++i) cx[i] = cp[i] = 0.0;
   cp[0] = 1.0;
   bool dact = false, dupd = false;
   if (md > 0 && k >= 1 && k < ns) {
 #pragma unroll
-    for (int i = 0; i < kMaxSteps; ++i) {
+    for (int i = 0; i < kBatchMaxSteps; ++i) {
       if (i <= md) {
         cx[i] = st->dcx[i][lk];
         cp[i] = st->dcp[i][lk];
@@ -325,15 +325,15 @@ __device__ void bk2_chunk(const BatchSys& S, BatchState* st, const int4& ch, int
   // precision, fewer than `steps` - 1 steps pending) or applies every pending step
   if (act) {
 #pragma unroll
-    for (int i = 0; i < kMaxSteps; ++i)
+    for (int i = 0; i < kBatchMaxSteps; ++i)
       if (i <= md) cx[i] = fma(akq, cp[i], cx[i]);
   }
   if (act && keep_p) {
 #pragma unroll
-    for (int i = 0; i < kMaxSteps; ++i)
+    for (int i = 0; i < kBatchMaxSteps; ++i)
       if (i <= md) cp[i] *= bkq;
 #pragma unroll
-    for (int i = 1; i <= kMaxSteps; ++i)
+    for (int i = 1; i <= kBatchMaxSteps; ++i)
       if (i == md + 1) cp[i] = zn;
   }
   dact = dact || act;
@@ -343,12 +343,12 @@ __device__ void bk2_chunk(const BatchSys& S, BatchState* st, const int4& ch, int
   st->upd_x[lk] = listed ? 1 : 0;
   st->upd_p[lk] = (listed && dupd) ? 1 : 0;
 #pragma unroll
-  for (int i = 0; i < kMaxSteps; ++i) st->cx[i][lk] = i <= md ? cx[i] : 0.0;
+  for (int i = 0; i < kBatchMaxSteps; ++i) st->cx[i][lk] = i <= md ? cx[i] : 0.0;
 #pragma unroll
-  for (int i = 0; i <= kMaxSteps; ++i) st->cp[i][lk] = i <= md + 1 ? cp[i] : 0.0;
+  for (int i = 0; i <= kBatchMaxSteps; ++i) st->cp[i][lk] = i <= md + 1 ? cp[i] : 0.0;
   if (defer) {
 #pragma unroll
-    for (int i = 0; i < kMaxSteps; ++i) {
+    for (int i = 0; i < kBatchMaxSteps; ++i) {
       st->dcx[i][lk] = i <= md ? cx[i] : 0.0;
       st->dcp[i][lk] = i <= md + 1 ? cp[i] : 0.0;
     }
@@ -382,7 +382,7 @@ __device__ void bk2_chunk(const BatchSys& S, BatchState* st, const int4& ch, int
 // The update's per-(rhs, shift) coefficients, staged in LDS once per chunk so the loop
 // over shifts issues its vector loads without first waiting on the scalar state.
 struct K3Coef {
-  double cx[kMaxSteps][kQK], cp[kMaxSteps + 1][kQK];
+  double cx[kBatchMaxSteps][kQK], cp[kBatchMaxSteps + 1][kQK];
   int upd_x[kQK], upd_p[kQK];
   int orig[kBatchMaxShifts];
   double a[kBatchMaxRhs], bnew[kBatchMaxRhs];
@@ -397,9 +397,9 @@ __device__ void bk3_chunk(const BatchSys& S, const BatchState* st, const int4& c
   __syncthreads();  // the previous chunk of this workgroup is done with cf
   if (tid < kQK) {
 #pragma unroll
-    for (int i = 0; i < kMaxSteps; ++i) cf.cx[i][tid] = st->cx[i][tid];
+    for (int i = 0; i < kBatchMaxSteps; ++i) cf.cx[i][tid] = st->cx[i][tid];
 #pragma unroll
-    for (int i = 0; i <= kMaxSteps; ++i) cf.cp[i][tid] = st->cp[i][tid];
+    for (int i = 0; i <= kBatchMaxSteps; ++i) cf.cp[i][tid] = st->cp[i][tid];
     cf.upd_x[tid] = st->upd_x[tid];
     cf.upd_p[tid] = st->upd_p[tid];
   }
@@ -443,9 +443,9 @@ __device__ void bk3_chunk(const BatchSys& S, const BatchState* st, const int4& c
       // m = 0 the multiply-adds round exactly as one step)
       const int mq = cf.m[q], kq = cf.keep[q];
       if (kq >= 0) static_cast<cplx<R>*>(S.rkeep[kq])[idx] = r[idx];
-      double2 rk[kMaxSteps - 1];
+      double2 rk[kBatchMaxSteps - 1];
 #pragma unroll
-      for (int kk = 0; kk < kMaxSteps - 1; ++kk)
+      for (int kk = 0; kk < kBatchMaxSteps - 1; ++kk)
         rk[kk] = kk < mq ? to_d(static_cast<const cplx<R>*>(S.rkeep[kk])[idx]) : double2{0.0, 0.0};
       constexpr bool same = std::is_same<R, W>::value;
       // two shifts at a time, their loads issued before either store (x_k and p_k of
@@ -472,7 +472,7 @@ __device__ void bk3_chunk(const BatchSys& S, const BatchState* st, const int4& c
           if (ux[u]) {
             double2 xv = xk[u];
 #pragma unroll
-            for (int kk = kMaxSteps - 2; kk >= 0; --kk) {
+            for (int kk = kBatchMaxSteps - 2; kk >= 0; --kk) {
               if (kk < mq) {
                 xv.x = fma(cf.cx[kk + 1][lk], rk[kk].x, xv.x);
                 xv.y = fma(cf.cx[kk + 1][lk], rk[kk].y, xv.y);
@@ -486,7 +486,7 @@ __device__ void bk3_chunk(const BatchSys& S, const BatchState* st, const int4& c
             const double c0 = cf.cp[0][lk];
             double2 np{c0 * pj[u].x, c0 * pj[u].y};
 #pragma unroll
-            for (int kk = 0; kk < kMaxSteps - 1; ++kk) {
+            for (int kk = 0; kk < kBatchMaxSteps - 1; ++kk) {
               if (kk < mq) {
                 np.x = fma(cf.cp[kk + 1][lk], rk[kk].x, np.x);
                 np.y = fma(cf.cp[kk + 1][lk], rk[kk].y, np.y);

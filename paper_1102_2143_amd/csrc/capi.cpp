@@ -58,9 +58,12 @@ template <class T> void dfree(T*& p) {
 }
 
 void free_workspace(Workspace& w) {
-  for (void* q : {w.r, w.p[0], w.p[1], w.t, w.pk, w.r32, w.p32[0], w.p32[1], w.t32, w.pk32,
-                  w.rkeep[0], w.rkeep[1], w.rkeep[2]})
+  for (void* q : {w.r, w.p[0], w.p[1], w.t, w.pk, w.r32, w.p32[0], w.p32[1], w.t32, w.pk32})
     if (q) (void)hipFree(q);
+  for (void*& q : w.rkeep) {
+    if (q) (void)hipFree(q);
+    q = nullptr;
+  }
   dfree(w.t64);
   dfree(w.u64);
   dfree(w.st);
@@ -993,7 +996,7 @@ struct BatchRun {
       const size_t n = size_t(ops[s]->n), nk = std::max<size_t>(ops[s]->sigma.size() - 1, 1);
       const size_t nch = (n + kBatchChunkRows - 1) / kBatchChunkRows;
       off[s] = bytes;
-      bytes += (4 + kMaxSteps - 1) * align(sizeof(double2) * n * rr) +
+      bytes += (4 + kBatchMaxSteps - 1) * align(sizeof(double2) * n * rr) +
                align(sizeof(double2) * n * rr * nk) +
                3 * align(sizeof(float2) * n * rr) + align(sizeof(float2) * n * rr * nk) +
                align(sizeof(double) * nch * kBatchMaxRhs);
@@ -1239,8 +1242,9 @@ struct BatchRun {
       // BK3 may defer its shifted update except in the graph's last iteration (a reliable
       // update or the end of the solve may follow it)
       BatchArgs ga = args();
-      ga.defer_ok = (prm.update_steps > 1 && g < G - 1) ? 1 : 0;
-      ga.steps = prm.update_steps;
+      const int steps = std::min(prm.update_steps, kBatchMaxSteps);
+      ga.defer_ok = (steps > 1 && g < G - 1) ? 1 : 0;
+      ga.steps = steps;
       hipError_t e = launch_batch_iteration(ga, sint);
       if (e != hipSuccess) {
         hipGraph_t tmp = nullptr;
@@ -1498,7 +1502,7 @@ void msc_params_default(msc_params* p) {
   p->lanes = 0;
   p->verify = 1;
   p->mixed_margin = 0.7;
-  p->update_steps = 4;
+  p->update_steps = kMaxSteps;
 }
 
 const char* msc_version(void) { return "msc 0.1 (gfx950)"; }

@@ -57,8 +57,11 @@ constexpr double kRuDelta2 = 1e-2;
 // Head launches whose update mode is recorded for the byte model of sampled timings.
 constexpr int kMaxSamples = 256;
 
-// Steps of the all-shift update one pass over x_j and p_j may fold together.
-constexpr int kMaxSteps = 4;
+// Steps of the all-shift update one pass over x_j and p_j may fold together: up to 8 in
+// the single solve, up to 4 in the batched one (whose update kernel holds the kept
+// residuals of four right-hand sides).
+constexpr int kMaxSteps = 8;
+constexpr int kBatchMaxSteps = 4;
 
 // Deferred steps of shift j composed against the direction p_j at the first of them and
 // the residuals r_0..r_{m-1} the deferring heads kept: so far
@@ -197,7 +200,7 @@ struct Workspace {
   void* t32 = nullptr;
   void* pk32 = nullptr;
   double2* t64 = nullptr;   // n complex128 (reliable updates, verification)
-  void* rkeep[kMaxSteps - 1] = {nullptr, nullptr, nullptr};  // n complex128 each (complex64
+  void* rkeep[kMaxSteps - 1] = {};  // n complex128 each (complex64
                             // in the second phase): residuals kept by deferring heads
   double2* u64 = nullptr;   // 8 * n complex128 (verification SpMM chunk)
   SolveState* st = nullptr;
@@ -541,11 +544,11 @@ struct BatchState {
   // BK3's update of (q, k) (upd_x, upd_p): x += cx[0] p_k + sum_{i<m} cx[i+1] r_i and
   // p_k <- cp[0] p_k + sum_{i<m} cp[i+1] r_i + cp[m+1] r, the r_i being the residuals
   // kept by the m BK3s that deferred (one step: m = 0)
-  double cx[kMaxSteps][kBatchMaxRhs * kBatchMaxShifts];
-  double cp[kMaxSteps + 1][kBatchMaxRhs * kBatchMaxShifts];
+  double cx[kBatchMaxSteps][kBatchMaxRhs * kBatchMaxShifts];
+  double cp[kBatchMaxSteps + 1][kBatchMaxRhs * kBatchMaxShifts];
   // the deferred steps of (q, k) composed as in DeferState
-  double dcx[kMaxSteps][kBatchMaxRhs * kBatchMaxShifts];
-  double dcp[kMaxSteps][kBatchMaxRhs * kBatchMaxShifts];
+  double dcx[kBatchMaxSteps][kBatchMaxRhs * kBatchMaxShifts];
+  double dcp[kBatchMaxSteps][kBatchMaxRhs * kBatchMaxShifts];
   int dact[kBatchMaxRhs * kBatchMaxShifts], dupd[kBatchMaxRhs * kBatchMaxShifts];
   // per right-hand side: steps deferred so far, BK3's kept residuals to read (m) and the
   // slot it keeps r in (-1: none), and per phase (FP64, complex64) the shift-vector
@@ -572,7 +575,7 @@ struct BatchSys {
   double2* x;             // nrhs * ns * n (rhs-major, shift-major, caller order)
   double2 *r64, *p64, *t64, *pk64, *u64;   // rhs-interleaved n x RR; pk: (ns-1) blocks
   float2 *r32, *p32, *t32, *pk32;
-  void* rkeep[kMaxSteps - 1];  // n x RR each: residuals kept by deferring BK3s
+  void* rkeep[kBatchMaxSteps - 1];  // n x RR each: residuals kept by deferring BK3s
                                // (complex128, or complex64 in the second phase)
   BatchState* st;
   double* partial;
@@ -589,7 +592,7 @@ struct BatchArgs {
   int rr;                 // right-hand sides per system, padded (1, 2 or 4)
   int* active_systems;
   int defer_ok;           // 1: this iteration's BK3 may defer the shifted update
-  int steps;              // steps of the shifted update folded into one pass (1..kMaxSteps)
+  int steps;              // steps of the shifted update folded into one pass (1..kBatchMaxSteps)
 };
 
 hipError_t launch_batch_init(const BatchArgs& a, hipStream_t s);

@@ -123,12 +123,12 @@ def test_batch_result_is_independent_of_companions(cuda):
         op.close()
 
 
-@pytest.mark.parametrize("steps", [2, 4])
+@pytest.mark.parametrize("steps", [2, 4, 8])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_batch_folded_steps_match_one_step(cuda, prec, steps):
-    # the batch defers shifted updates and folds up to `steps` of them into one pass: the
-    # driving sequences, iteration counts and freezes are those of one step per
-    # iteration, the solutions agree to rounding, and fewer bytes move
+    # the batch defers shifted updates and folds up to `steps` of them (at most 4) into
+    # one pass: the driving sequences, iteration counts and freezes are those of one step
+    # per iteration, the solutions agree to rounding, and fewer bytes move
     print(f"[gpu] batched {steps} folded steps {prec}", flush=True)
     from paper_1102_2143_amd import solve_batched
     systems = _small_batch()

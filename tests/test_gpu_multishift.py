@@ -229,7 +229,8 @@ def test_iteration_limit_in_the_complex64_phase(c0, cuda, fmt, limit):
     op.close()
 
 
-@pytest.mark.parametrize("fmt,steps", [("sell", 2), ("sell", 3), ("sell", 4), ("csr", 2), ("csr", 3)])
+@pytest.mark.parametrize("fmt,steps", [("sell", 2), ("sell", 3), ("sell", 4), ("sell", 7), ("sell", 8),
+                                       ("csr", 2), ("csr", 5), ("csr", 8)])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_folded_update_steps_match_one_step(c0, cuda, fmt, steps, prec):
     # folding consecutive steps of the all-shift update into one pass (the heads between
@@ -257,7 +258,7 @@ def test_update_steps_out_of_range_rejected(c0, cuda):
     from paper_1102_2143_amd import MscError
     op = _op(c0, cuda)
     op.set_shifts(c0["sigma"])
-    for bad in (0, 5):
+    for bad in (0, 9):
         with pytest.raises(MscError):
             op.solve(c0["b"], update_steps=bad)
     op.close()

@@ -41,7 +41,7 @@ def test_params_default_and_struct_layout():
     lib.msc_params_default(ctypes.byref(p))
     assert p.tol == 1e-10 and p.max_iter == 10000 and p.reliable_every == 50
     assert p.poll_every == 16 and p.verify == 1
-    assert p.update_steps == 4 and p.sweep == 0
+    assert p.update_steps == 8 and p.sweep == 0
     assert ctypes.sizeof(_lib.Params) == 80  # update_steps and the sweep order appended
     assert ctypes.sizeof(_lib.Info) == 160  # FP64-phase timing fields appended
 
