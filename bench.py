@@ -39,18 +39,17 @@ WORKLOAD_NAMES = {
 # (FETCH_SIZE and WRITE_SIZE, KiB per dispatch, scaled by the calibration against a copy
 # kernel of known size); it is reported only while the kernel sources are unchanged since.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
-KERNEL_NAMES = {("mixed", "head"): "k1_fused<float, true, 0, false>",
-                ("mixed", "K2"): "k2_sell<float, 0>",
-                ("fp64", "head"): "k1_fused<double, true, 0, false>",
-                ("fp64", "K2"): "k2_sell<double, 0>"}
-# the same kernels on the matrix-free staggered operator (M and M^H from the links: the
-# FP64 ones read two rows per SU(3) link and the FP64 head forms its product by the
-# recurrence t' = M r + b t in all but one launch in 64; the complex64 ones read all nine
-# values)
-KERNEL_NAMES_MF = {("mixed", "head"): "k1_fused<float, true, 3, false>",
-                   ("mixed", "K2"): "k2_sell<float, 3>",
-                   ("fp64", "head"): "k1_fused<double, true, 2, true>",
-                   ("fp64", "K2"): "k2_sell<double, 2>"}
+KERNEL_NAMES = {("mixed", "head"): "k1_fused<float, true>",
+                ("mixed", "K2"): "k2_sell<float>",
+                ("fp64", "head"): "k1_fused<double, true>",
+                ("fp64", "K2"): "k2_sell<double>"}
+# the same kernels on the matrix-free staggered operator (M and M^H from the links, one
+# lattice site per lane; two rows per SU(3) link; the FP64 head forms its product by the
+# recurrence t' = M r + b t in all but one launch in 64)
+KERNEL_NAMES_MF = {("mixed", "head"): "k1_site<float, 2, false>",
+                   ("mixed", "K2"): "k2_site<float, 2>",
+                   ("fp64", "head"): "k1_site<double, 2, true>",
+                   ("fp64", "K2"): "k2_site<double, 2>"}
 PHASE_NAMES = {"fp64": "FP64", "mixed": "complex64"}
 
 

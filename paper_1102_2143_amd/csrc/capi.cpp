@@ -159,14 +159,23 @@ template <class V> double index_bytes(bool sell, const Sell<V>& m) {
 #ifndef MSC_TILE_SPAN
 #define MSC_TILE_SPAN 48
 #endif
+// The links' kernels sweep blocks of 64 sites (192 rows), with their own span.
+#ifndef MSC_TILE_SPAN_SITES
+#define MSC_TILE_SPAN_SITES 16
+#endif
+#ifndef MSC_C64_TWO_ROWS
+#define MSC_C64_TWO_ROWS 1
+#endif
 constexpr int64_t kTileSpan = MSC_TILE_SPAN;
-SweepOrder lattice_order(int64_t nslices, int64_t s1, int64_t s2) {
+constexpr int64_t kTileSpanSites = MSC_TILE_SPAN_SITES;
+constexpr bool kC64TwoRows = MSC_C64_TWO_ROWS != 0;
+SweepOrder lattice_order(int64_t nslices, int64_t s1, int64_t s2, int64_t span = kTileSpan) {
   SweepOrder o{0, 0, 0, 0};
   if (s1 < 1 || s2 <= s1 || s2 % s1 != 0 || s2 > nslices / kXcds) return o;
   const int64_t na = std::max<int64_t>(1, nslices / kXcds / s2);
   int64_t cs = 1;
   for (int64_t c = 1; c <= s1; ++c)
-    if (s1 % c == 0 && c * na <= kTileSpan) cs = c;
+    if (s1 % c == 0 && c * na <= span) cs = c;
   o.s1 = int32_t(s1);
   o.s2 = int32_t(s2);
   o.cs = int32_t(cs);
@@ -385,8 +394,8 @@ msc_status run_multishift(msc_op op, const double* d_b, double* d_x, const msc_p
                 (prm.format == MSC_FORMAT_AUTO || prm.format == MSC_FORMAT_STENCIL)
                     ? (op->two_rows ? 2 : 3) : 0;
   if (a64.stencil == 2) a64.w64 = op->wc64;
-  a64.ord = op->order;
-  a64.ord.on = (prm.sweep == 0 && op->order.s1 > 0) ? 1 : 0;
+  a64.ord = a64.stencil ? op->order_sites : op->order;
+  a64.ord.on = (prm.sweep == 0 && a64.ord.s1 > 0) ? 1 : 0;
   if (prm.format == MSC_FORMAT_SELL32 && op->sell) {
     const SellStore &sm = op->sell_m, &sh = op->sell_mh;
     a64.s64 = sell_view(sm, sm.val64, sm.diag64, false);
@@ -398,11 +407,13 @@ msc_status run_multishift(msc_op op, const double* d_b, double* d_x, const msc_p
   }
   const double ib = index_bytes(a64.sell, a64.s64), ibh = index_bytes(a64.sell, a64.sh64);
   MsArgs a32 = a64;
-  // the complex64 phase reads all nine values of each link: rebuilding the third row
-  // costs those kernels more in arithmetic and loads than the third less link traffic
-  // saves (measured at 32^3x64: head 386 -> 458 us, K2 212 -> 239 us), while the FP64
-  // ones gain (K2 466 -> 376 us)
-  if (a32.stencil != 0) a32.stencil = 3;
+  // the complex64 phase reads two rows per SU(3) link too, unless told otherwise
+  if (a32.stencil == 2) {
+    if (kC64TwoRows)
+      a32.w32 = op->wc32;
+    else
+      a32.stencil = 3;
+  }
   const bool mixed = prec == MSC_PREC_MIXED;
   if (mixed) {
     a32.r = op->ws.r32;
@@ -1943,6 +1954,11 @@ msc_status msc_op_create_staggered(msc_op* out, const int32_t* dims, double mass
   op->order = (op->sell && plane % kSlice == 0)
                   ? lattice_order(op->sell_m.nslices, plane / kSlice, slab / kSlice)
                   : SweepOrder{0, 0, 0, 0};
+  // the same structure in blocks of 64 sites, for the kernels that read the links
+  const int64_t splane = int64_t(geo.L[0]) * geo.L[1], sslab = splane * geo.L[2];
+  op->order_sites = splane % 64 == 0
+                        ? lattice_order((geo.vol + 63) / 64, splane / 64, sslab / 64, kTileSpanSites)
+                        : SweepOrder{0, 0, 0, 0};
   rc = refresh_two_rows(op, reinterpret_cast<const double2*>(d_links), s);
   if (rc != MSC_OK) {
     msc_op_destroy(op);

@@ -150,8 +150,8 @@ template <class V> struct Sell {
 };
 
 // Matrix-free staggered operator M = m + D on a periodic 4-D lattice (every extent >= 3):
-// w holds W_mu(x) = eta_mu(x)/2 U_mu(x) as [4][V][3][3] (direction-major, site x0
-// fastest, row-major 3x3), so that
+// w holds W_mu(x) = eta_mu(x)/2 U_mu(x) value-major as [4][K][V] (direction, entry of the
+// row-major 3x3 matrix, site with x0 fastest; K = 9, or 6 with rows = 2), so that
 //   (D v)(x) = sum_mu [ W_mu(x) v(x + mu) - W_mu(x - mu)^H v(x - mu) ]
 // (eta_mu does not depend on x_mu).  Row 3 s + c of M is colour c of site s.
 template <class V> struct Stencil {
@@ -262,6 +262,7 @@ struct msc_op_s {
   double* adj_small = nullptr;   // 256 doubles: Gram sums and shift factors
   int lanes64 = 0, lanes32 = 0;  // chosen lanes per row (0 = not yet tuned)
   msc::SweepOrder order{0, 0, 0, 0};  // lattice structure of the rows (zeros: none found)
+  msc::SweepOrder order_sites{0, 0, 0, 0};  // the same in blocks of 64 sites (links' kernels)
   int64_t rowhist[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // rows by length: 0, 1, 2-3, ..., >= 64
   bool stencil = false;          // matrix-free staggered operator (links kept below)
   msc::Stencil<double2> w64;     // W_mu(x) = eta_mu(x)/2 U_mu(x), complex128 and
@@ -299,7 +300,7 @@ hipError_t refill_sell(const int32_t* rowptr, const int32_t* col, const double2*
                        const SellStore& out, hipStream_t s);
 void free_sell(SellStore& out);
 // Matrix-free staggered operator set-up: w64 = eta/2 U from the caller's complex128
-// links [4][V][3][3], w32 = complex64 copy; and the scalar CSR of M = m + D built from
+// links [4][V][3][3], stored [4][9][V], w32 = complex64 copy; and the scalar CSR of M = m + D built from
 // w64 (25 entries per row, columns sorted): rowptr int64[n+1], col int32[25n],
 // vals complex128[25n].
 hipError_t launch_stencil_links(const double2* links, const Stencil<double2>& geo,
@@ -311,8 +312,8 @@ hipError_t launch_stencil_csr(const Stencil<double2>& op, int64_t* rowptr, int32
 // caller zeroes it first).
 hipError_t launch_su3_deviation(const double2* links, int64_t nlinks, unsigned long long* dev,
                                 hipStream_t s);
-// The first two rows of every W_mu(x) of the full copy w64 [4][V][9] into wc64 / wc32
-// [4][V][6].
+// The first two rows of every W_mu(x) of the full copy w64 [4][9][V] into wc64 / wc32
+// [4][6][V].
 hipError_t launch_two_rows(const double2* w64, int64_t nlinks, double2* wc64, float2* wc32,
                            hipStream_t s);
 

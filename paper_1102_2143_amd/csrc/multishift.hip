@@ -135,19 +135,13 @@ __device__ __forceinline__ cplx<R> next_dir(double b, const cplx<R>& r, const cp
   return from_d<R>(v);
 }
 
-// Directions per round trip of the matrix-free staggered rows: the head (which gathers
-// r and p at every neighbour) and K2.
-#ifndef MSC_STENCIL_DPR_HEAD
-#define MSC_STENCIL_DPR_HEAD 1
+// Minimum waves per SIMD asked of the compiler for the matrix-free head and K2 (1: no
+// constraint).
+#ifndef MSC_SITE_HEAD_WPE
+#define MSC_SITE_HEAD_WPE 1
 #endif
-#ifndef MSC_STENCIL_DPR_K2
-#define MSC_STENCIL_DPR_K2 2
-#endif
-#ifndef MSC_STENCIL_DPR_K2_TWO
-#define MSC_STENCIL_DPR_K2_TWO 1
-#endif
-#ifndef MSC_STENCIL_DPR_HEAD_TR
-#define MSC_STENCIL_DPR_HEAD_TR 1
+#ifndef MSC_SITE_K2_WPE
+#define MSC_SITE_K2_WPE 1
 #endif
 
 // Pairs per round trip when each entry gathers two vectors (MSC_SELL_KPN32 / 64).
@@ -719,13 +713,7 @@ __global__ __launch_bounds__(kBlock) void k_update(MsArgs a) {
 // its own row (x, p_j, and p' = r + b p stored in the other buffer), then t = M p' takes
 // p' at the gathered columns from r and the old p, rounded exactly as the owning lane
 // rounds it; P = |t|^2 + sigma0 |p'|^2 (A = M^H M) or Re p'^H t + sigma0 |p'|^2.
-// LR: M is applied from the links (matrix-free staggered operator, A = M^H M), 3 or 2
-// rows stored per link; 0: the sliced ELLPACK copy.
-// TR (links, FP64): t' = M r + b t instead of M (r + b p), the old t being M p from the
-// previous head: one gathered vector instead of two.  The rounding of the recurrence
-// stays at the FP64 level over the launches between two direct products (the host
-// interleaves a direct one every kTrEvery launches).
-template <class R, bool MHM, int LR = 0, bool TR = false>
+template <class R, bool MHM>
 __global__ __launch_bounds__(kBlock) void k1_fused(MsArgs a) {
   const SolveState* st = a.st;
   const RotState& rs = st->rot[a.par];
@@ -778,24 +766,9 @@ __global__ __launch_bounds__(kBlock) void k1_fused(MsArgs a) {
     }
     if (!pl.spmv) continue;
     // without a pending update p' = p: the same product with r := p and b = 0 (exact)
-    cplx<R> v;
-    if constexpr (LR != 0 && TR) {
-      // without a pending update bn = 0 and the product is M p
-      const cplx<R>* __restrict__ rg = upd ? rv : pv;
-      const cplx<R> told = ld_stream(&t[rr]);
-      v = stencil_row<R, MSC_STENCIL_DPR_HEAD_TR, LR>(pick_w<R>(a), rr, upd ? r_i : p_i, 1,
-                                                       [&](int64_t c) { return rg[c]; });
-      v.x = fma(bn, told.x, v.x);
-      v.y = fma(bn, told.y, v.y);
-    } else if constexpr (LR != 0) {
-      const cplx<R>* __restrict__ rg = upd ? rv : pv;
-      v = stencil_row<R, MSC_STENCIL_DPR_HEAD, LR>(pick_w<R>(a), rr, p_row, 1,
-                         [&](int64_t c) { return next_dir<R>(bn, rg[c], pv[c]); });
-    } else {
-      const cplx<R> d = m.diag[rr];
-      v = sell_row_next<R>(m, upd ? rv : pv, pv, bn, sl, lane);
-      cfma<R>(v, d, p_row);
-    }
+    const cplx<R> d = m.diag[rr];
+    cplx<R> v = sell_row_next<R>(m, upd ? rv : pv, pv, bn, sl, lane);
+    cfma<R>(v, d, p_row);
     if (live) {
       st_stream(&t[row], v);
       if (MHM)
@@ -889,8 +862,7 @@ __global__ __launch_bounds__(kBlock) void k2_mhm(MsArgs a) {
 }
 
 // ---- K2 on the sliced ELLPACK copy of M^H: one row per lane, one slice per wave ------
-// LR (3 or 2 rows per link): M^H = m - D applied from the links instead.
-template <class R, int LR = 0>
+template <class R>
 __global__ __launch_bounds__(kBlock) void k2_sell(MsArgs a) {
   const SolveState* st = a.st;
   const RotState& ns = st->rot[a.par ^ 1];  // written by this iteration's head
@@ -918,14 +890,9 @@ __global__ __launch_bounds__(kBlock) void k2_sell(MsArgs a) {
     Row o;
     o.p = ld_stream(&p[rr]);
     o.r = ld_stream(&r[rr]);
-    if constexpr (LR != 0) {
-      o.q = stencil_row<R, LR == 3 ? MSC_STENCIL_DPR_K2 : MSC_STENCIL_DPR_K2_TWO, LR>(
-          pick_w<R>(a), rr, tr, -1, [&](int64_t c) { return t[c]; });
-    } else {
-      const cplx<R> d = mh.diag[rr];
-      o.q = sell_row<R>(mh, t, sl, lane);
-      cfma<R>(o.q, d, tr);
-    }
+    const cplx<R> d = mh.diag[rr];
+    o.q = sell_row<R>(mh, t, sl, lane);
+    cfma<R>(o.q, d, tr);
     return o;
   };
   auto epilogue = [&](int64_t sl, const Row& o) {
@@ -951,6 +918,166 @@ __global__ __launch_bounds__(kBlock) void k2_sell(MsArgs a) {
   for (sw.next(); sw.more(); sw.next()) {
     const int64_t sl = sw.slice();
     epilogue(sl, product(sl));
+  }
+  store_partial(region(a, 1), acc);
+}
+
+// ---- matrix-free head and K2: one lattice site (three rows) per lane ------------------
+// The waves sweep blocks of 64 sites (192 rows).  The head first applies the pending
+// update to the block's rows, one row per lane in three passes (the same update_row as on
+// the sliced path), then computes t' = M p' for the block's sites, one site per lane,
+// forming p' = r + b p at its own and at every gathered neighbour's rows with next_dir,
+// so that all of them round exactly as the row's owner does; P = |t'|^2 + sigma0 |p'|^2.
+// LR: rows stored per link (3, or 2 for SU(3) links).
+// TR (FP64): t' = M r + b t instead of M (r + b p), the old t being M p from the previous
+// head: one gathered vector instead of two.  The recurrence's rounding stays at the FP64
+// level over the launches between two direct products (the host interleaves a direct
+// one every kTrEvery launches).
+// A lane's own rows (48 or 24 contiguous bytes, read or written by three instructions
+// whose lanes lie 48 or 24 bytes apart) take ordinary loads and stores: with streaming
+// hints a line could leave the cache between the three.
+constexpr int kSiteBlock = kWave;  // sites per wave pass
+
+template <class R, int LR, bool TR>
+__global__ __launch_bounds__(kBlock, MSC_SITE_HEAD_WPE) void k1_site(MsArgs a) {
+  const SolveState* st = a.st;
+  const RotState& rs = st->rot[a.par];
+  if (rs.halt) {
+    carry_state(a);
+    return;
+  }
+  const int pending = rs.pending;
+  Early e;
+  if (pending) load_early(region(a, 1), a.gk2, e);
+  const int pc = rs.pcur;
+  const cplx<R>* __restrict__ rv = static_cast<const cplx<R>*>(a.r);
+  const cplx<R>* __restrict__ pv = static_cast<const cplx<R>*>(a.pb[pc]);
+  cplx<R>* __restrict__ pnew = static_cast<cplx<R>*>(a.pb[pc ^ 1]);
+  cplx<R>* __restrict__ t = static_cast<cplx<R>*>(a.t);
+  double2* __restrict__ x0 = a.x + int64_t(st->orig[0]) * a.n;
+  const Stencil<cplx<R>> w = pick_w<R>(a);
+  const uint32_t vol = uint32_t(w.vol);
+  const int64_t nblk = (int64_t(vol) + kSiteBlock - 1) / kSiteBlock;
+  const double sigma0 = st->sigma0;
+  const double step = st->a;
+  constexpr int WPB = kBlock / kWave;
+  const int lane = threadIdx.x % kWave;
+  Sweep sw = make_sweep(nblk, a.ord, WPB);
+  __shared__ Plan pl;
+  head_plan<R>(a, e, pl);
+  if (!pl.ok) return;
+  const bool upd = pl.pending != 0;
+  const double bn = pl.bn;
+  double acc = 0.0;
+  for (; sw.more(); sw.next()) {
+    const int64_t blk = sw.slice();
+    if (upd) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const int64_t row = (3 * blk + k) * kWave + lane;
+        if (row < a.n) update_row<R>(a, pl, step, row, rv[row], pv[row], ld_stream(&x0[row]), x0, pnew);
+      }
+    }
+    if (!pl.spmv) continue;
+    const uint32_t site = uint32_t(blk * kSiteBlock) + uint32_t(lane);
+    const bool live = site < vol;
+    const uint32_t ss = live ? site : vol - 1;  // lanes past the volume compute a valid site, unused
+    const int64_t r0 = 3 * int64_t(ss);
+    cplx<R> pr[3], own[3], v[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const cplx<R> ri = rv[r0 + c], pi = pv[r0 + c];
+      pr[c] = upd ? next_dir<R>(bn, ri, pi) : pi;
+      own[c] = TR ? (upd ? ri : pi) : pr[c];
+    }
+    const cplx<R>* __restrict__ rg = upd ? rv : pv;
+    if constexpr (TR) {
+      // without a pending update bn = 0 and the product is M p
+      stencil_site<R, LR>(w, ss, own, 1, [&](int64_t c) { return rg[c]; }, v);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const cplx<R> told = t[r0 + c];
+        v[c].x = fma(bn, told.x, v[c].x);
+        v[c].y = fma(bn, told.y, v[c].y);
+      }
+    } else {
+      // without a pending update p' = p: the same product with r := p and b = 0 (exact)
+      stencil_site<R, LR>(w, ss, own, 1, [&](int64_t c) { return next_dir<R>(bn, rg[c], pv[c]); },
+                          v);
+    }
+    if (live) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        t[r0 + c] = v[c];
+        acc += norm2d<R>(v[c]) + sigma0 * norm2d<R>(pr[c]);
+      }
+    }
+  }
+  if (pl.spmv) store_partial(region(a, 0), acc);
+}
+
+// K2: q = M^H t = m t - D t for the block's sites, then r <- r - a (q + sigma0 p) and
+// R' = |r|^2 on their rows.
+template <class R, int LR>
+__global__ __launch_bounds__(kBlock, MSC_SITE_K2_WPE) void k2_site(MsArgs a) {
+  const SolveState* st = a.st;
+  const RotState& ns = st->rot[a.par ^ 1];  // written by this iteration's head
+  if (ns.halt) return;
+  Early e;
+  load_early(region(a, 0), a.gk1, e);
+  const cplx<R>* __restrict__ t = static_cast<const cplx<R>*>(a.t);
+  const cplx<R>* __restrict__ p = static_cast<const cplx<R>*>(a.pb[ns.pcur]);
+  cplx<R>* __restrict__ r = static_cast<cplx<R>*>(a.r);
+  const Stencil<cplx<R>> w = pick_w<R>(a);
+  const uint32_t vol = uint32_t(w.vol);
+  const int64_t nblk = (int64_t(vol) + kSiteBlock - 1) / kSiteBlock;
+  const double sigma0 = st->sigma0;
+  constexpr int WPB = kBlock / kWave;
+  const int lane = threadIdx.x % kWave;
+  Sweep sw = make_sweep(nblk, a.ord, WPB);
+  double acc = 0.0;
+  double step = 0.0;
+  struct Site {
+    cplx<R> q[3];
+  };
+  auto product = [&](int64_t blk) {
+    const uint32_t site = uint32_t(blk * kSiteBlock) + uint32_t(lane);
+    const uint32_t ss = site < vol ? site : vol - 1;  // lanes past the volume: unused
+    const int64_t r0 = 3 * int64_t(ss);
+    cplx<R> own[3];
+    Site o;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) own[c] = t[r0 + c];
+    stencil_site<R, LR>(w, ss, own, -1, [&](int64_t c) { return t[c]; }, o.q);
+    return o;
+  };
+  auto epilogue = [&](int64_t blk, const Site& o) {
+    const uint32_t site = uint32_t(blk * kSiteBlock) + uint32_t(lane);
+    if (site >= vol) return;
+    const int64_t r0 = 3 * int64_t(site);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const double2 pr = to_d(p[r0 + c]);
+      const double2 rr = to_d(r[r0 + c]);
+      const double2 qd = to_d(o.q[c]);
+      double2 nr;
+      nr.x = rr.x - step * (qd.x + sigma0 * pr.x);
+      nr.y = rr.y - step * (qd.y + sigma0 * pr.y);
+      const cplx<R> st_r = from_d<R>(nr);
+      r[r0 + c] = st_r;
+      acc += norm2d<R>(st_r);
+    }
+  };
+  // the first block's product runs while P's partials are on their way
+  const bool has0 = sw.more();
+  const int64_t b0 = has0 ? sw.slice() : 0;
+  Site first{};
+  if (has0) first = product(b0);
+  if (!k2_step(a, e, step)) return;  // breakdown: every workgroup sees the same P
+  if (has0) epilogue(b0, first);
+  for (sw.next(); sw.more(); sw.next()) {
+    const int64_t blk = sw.slice();
+    epilogue(blk, product(blk));
   }
   store_partial(region(a, 1), acc);
 }
@@ -1461,14 +1588,17 @@ hipError_t iteration_impl(const MsArgs& args, hipStream_t s, hipEvent_t* ev, boo
   // the head and K2 on the sliced path, and their grids: with a lattice order, the
   // resident workgroups only (their waves sweep the order in step)
   const bool tr = a.t_rec && std::is_same<R, double>::value;
-  auto head = lr == 3 ? (tr ? k1_fused<R, true, 3, true> : k1_fused<R, true, 3>)
-              : lr == 2 ? (tr ? k1_fused<R, true, 2, true> : k1_fused<R, true, 2>)
+  auto head = lr == 3 ? (tr ? k1_site<R, 3, true> : k1_site<R, 3, false>)
+              : lr == 2 ? (tr ? k1_site<R, 2, true> : k1_site<R, 2, false>)
                         : (a.kind == MSC_A_MHM ? k1_fused<R, true> : k1_fused<R, false>);
-  auto k2s = lr == 3 ? k2_sell<R, 3> : lr == 2 ? k2_sell<R, 2> : k2_sell<R>;
-  int gh = g3, gk = g3;
+  auto k2s = lr == 3 ? k2_site<R, 3> : lr == 2 ? k2_site<R, 2> : k2_sell<R>;
+  // the links' kernels take one block of 64 sites per wave pass
+  const int gsite = lr ? grid_rows((a.w64.vol + kSiteBlock - 1) / kSiteBlock, kBlock / kWave, a.grid)
+                       : g3;
+  int gh = lr ? gsite : g3, gk = gh;
   if (a.sell && a.ord.on) {
-    gh = resident_grid(reinterpret_cast<const void*>(head), g3);
-    if (a.kind == MSC_A_MHM) gk = resident_grid(reinterpret_cast<const void*>(k2s), g3);
+    gh = resident_grid(reinterpret_cast<const void*>(head), gh);
+    if (a.kind == MSC_A_MHM) gk = resident_grid(reinterpret_cast<const void*>(k2s), gk);
   }
   // workgroups of K1 and K2, whose partials K2 and the next head add up
   if (a.sell) {

@@ -456,23 +456,26 @@ hipError_t build_sell(const int32_t* rowptr, const int32_t* col, const double2* 
 // ---- matrix-free staggered operator --------------------------------------------------
 namespace {
 
-// w = eta_mu(x)/2 U_mu(x) (complex128 and complex64), one thread per link entry.
+// w = eta_mu(x)/2 U_mu(x) (complex128 and complex64), stored value-major: entry k of the
+// link at (mu, s), links[(mu vol + s) 9 + k], goes to w[(mu 9 + k) vol + s].  One thread
+// per stored value.
 __global__ void k_stencil_links(const double2* __restrict__ links, Stencil<double2> geo,
                                 double2* __restrict__ w64, float2* __restrict__ w32) {
-  const int64_t total = 4 * geo.vol * 9;
+  const int64_t vol = geo.vol, total = 4 * vol * 9;
   for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < total;
        i += int64_t(gridDim.x) * blockDim.x) {
-    const int64_t link = i / 9;
-    const int mu = int(link / geo.vol);
-    int64_t rem = link - int64_t(mu) * geo.vol;
+    const int64_t mk = i / vol;  // mu 9 + k
+    const int64_t site = i - mk * vol;
+    const int mu = int(mk / 9), k = int(mk - 9 * mu);
     // eta_mu(x) = (-1)^(x_0 + ... + x_{mu-1})
+    int64_t rem = site;
     int parity = 0;
     for (int nu = 0; nu < mu; ++nu) {
       parity += int(rem % geo.L[nu]);
       rem /= geo.L[nu];
     }
     const double h = (parity & 1) ? -0.5 : 0.5;
-    const double2 u = links[i];
+    const double2 u = links[(int64_t(mu) * vol + site) * 9 + k];
     const double2 v{h * u.x, h * u.y};
     w64[i] = v;
     w32[i] = float2{float(v.x), float(v.y)};
@@ -518,12 +521,13 @@ __global__ void k_su3_deviation(const double2* __restrict__ links, int64_t nlink
   atomicMax(dev, static_cast<unsigned long long>(__double_as_longlong(worst)));
 }
 
-__global__ void k_two_rows(const double2* __restrict__ w64, int64_t nlinks,
+// Rows 0 and 1 of every link (entries k < 6), value-major like w: wc[(mu 6 + k) vol + s].
+__global__ void k_two_rows(const double2* __restrict__ w64, int64_t vol,
                            double2* __restrict__ wc64, float2* __restrict__ wc32) {
-  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < nlinks * 6;
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < 4 * vol * 6;
        i += int64_t(gridDim.x) * blockDim.x) {
-    const int64_t l = i / 6;
-    const double2 v = w64[l * 9 + (i - 6 * l)];
+    const int64_t mu = i / (6 * vol);
+    const double2 v = w64[i + 3 * vol * mu];  // (mu 9 + k) vol + s = i + 3 vol mu
     wc64[i] = v;
     wc32[i] = float2{float(v.x), float(v.y)};
   }
@@ -585,9 +589,9 @@ __global__ void k_stencil_csr(Stencil<double2> op, int64_t* __restrict__ rowptr,
       for (int j = 0; j < 3; ++j) {
         double2 v;
         if (forward) {
-          v = op.w[(int64_t(mu) * op.vol + s) * 9 + 3 * c + j];  // W_mu(s)[c][j]
+          v = op.w[(int64_t(mu) * 9 + 3 * c + j) * op.vol + s];  // W_mu(s)[c][j]
         } else {
-          const double2 u = op.w[(int64_t(mu) * op.vol + y) * 9 + 3 * j + c];
+          const double2 u = op.w[(int64_t(mu) * 9 + 3 * j + c) * op.vol + y];
           v = double2{-u.x, u.y};                                  // -conj(W_mu(s-mu)[j][c])
         }
         col[e] = int32_t(3 * y + j);
@@ -618,7 +622,7 @@ hipError_t launch_su3_deviation(const double2* links, int64_t nlinks, unsigned l
 hipError_t launch_two_rows(const double2* w64, int64_t nlinks, double2* wc64, float2* wc32,
                            hipStream_t s) {
   const int64_t g = std::min<int64_t>((6 * nlinks + 255) / 256, 8192);
-  k_two_rows<<<dim3(unsigned(std::max<int64_t>(g, 1))), 256, 0, s>>>(w64, nlinks, wc64, wc32);
+  k_two_rows<<<dim3(unsigned(std::max<int64_t>(g, 1))), 256, 0, s>>>(w64, nlinks / 4, wc64, wc32);
   return hipGetLastError();
 }
 

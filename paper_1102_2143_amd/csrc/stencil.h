@@ -1,12 +1,17 @@
-// Matrix-free staggered operator: the rows of M = m + D and M^H = m - D computed from the
-// link field (Stencil in msc_internal.h) instead of a stored matrix, one row per lane.
+// Matrix-free staggered operator: M = m + D and M^H = m - D computed from the link field
+// (Stencil in msc_internal.h) instead of a stored matrix, one lattice site per lane.
 //
-// D v at row 3 s + c reads row c of the four forward links W_mu(s) and column c of the
-// four backward links W_mu(s - mu): per row 12 + 12 link values and 24 gathered values,
-// like the 24 off-diagonal entries of a sliced ELLPACK row but with no column indices,
-// and each link is shared by the three rows of its site and by the neighbour that reads
-// it backwards (paper: Section 3, where the library leaves room for a custom linear
-// operator kernel in place of the stored matrix when an application warrants one).
+// D v at site s, colour c, reads row c of the four forward links W_mu(s) and column c of
+// the four backward links W_mu(s - mu), and the three colours of the eight neighbours.  A
+// lane computes all three colours of its site, so it reads each of its eight links once,
+// whole, and each neighbour's three values once (paper: Section 3, where the library
+// leaves room for a custom linear operator kernel in place of the stored matrix when an
+// application warrants one).
+//
+// The links are stored value-major: entry k (row-major within the 3 x 3 matrix) of W_mu
+// at site s is w[(mu K + k) vol + s], K = 9, or K = 6 when only rows 0 and 1 are kept.
+// The 64 lanes of a wave hold 64 consecutive sites, so each of their link loads reads
+// one contiguous run of 64 values.
 #pragma once
 
 #include "dev_common.h"
@@ -32,22 +37,38 @@ __device__ __forceinline__ cplx<R> conj_diff(const cplx<R>& a, const cplx<R>& b,
   return cplx<R>{re, -im};
 }
 
-// Hopping part (D v) of row `row`, with v read through gather(col); the four directions
-// are taken DPR at a time, each group's link and vector loads issued before its first
-// multiply-add (DPR = 1 where the gather itself reads two vectors).
-// LR = 3: every link holds its 9 values.  LR = 2: it holds rows 0 and 1 of W = (eta/2) U
-// with U in SU(3), whose third row is conj(u0 x u1); for W that is conj(w0 x w1) / (eta/2)
-// = 2 eta conj(w0 x w1), eta = eta_mu(x) the link's sign (equal for the site and its
-// backward neighbour in direction mu, since eta_mu does not depend on x_mu).
-template <class R, int DPR, int LR, class G>
-__device__ __forceinline__ cplx<R> stencil_hop(const Stencil<cplx<R>>& op, int64_t row, G gather) {
-  static_assert(DPR == 1 || DPR == 2 || DPR == 4, "directions per round trip");
+// Row 2 of an SU(3) link W = (eta/2) U from its rows 0 and 1 (u[0..2], u[3..5]): the third
+// row of U is conj(u0 x u1), so that of W is conj(w0 x w1) / (eta/2) = 2 eta conj(w0 x w1).
+// te = 2 eta, equal for a site and its backward neighbour in direction mu (eta_mu does
+// not depend on x_mu).
+template <class R>
+__device__ __forceinline__ void third_row(cplx<R> (&u)[9], R te) {
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const int j1 = (j + 1) % 3, j2 = (j + 2) % 3;
+    cplx<R> r2 = conj_diff<R>(u[j1], u[3 + j2], u[j2], u[3 + j1]);
+    r2.x *= te;
+    r2.y *= te;
+    u[6 + j] = r2;
+  }
+}
+
+// out[c] = m own[c] + sign (D v)_(3 s + c), c = 0, 1, 2, with v read through gather(row)
+// and own[c] = v at the site's own rows.  LR: link rows stored (3, or 2 for SU(3) links).
+// The sums run over mu = 0..3 and, within a direction, over the neighbour's colours j,
+// forward and backward terms apart, in that order.
+template <class R, int LR, class G>
+__device__ __forceinline__ void stencil_site(const Stencil<cplx<R>>& op, uint32_t s,
+                                             const cplx<R> (&own)[3], int sign, G gather,
+                                             cplx<R> (&out)[3]) {
   static_assert(LR == 2 || LR == 3, "link rows");
-  const uint32_t s = uint32_t(row / 3);
-  const int c = int(row - 3 * int64_t(s));
+  constexpr int K = 3 * LR;
+  // neighbours and the sign mask in 32 bits (the volume is below 2^31, checked at
+  // creation)
+  const uint32_t vol = uint32_t(op.vol);
   uint32_t rem = s;
-  int64_t fwd[4], bwd[4];
-  R two_eta[4];
+  uint32_t fwd[4], bwd[4];
+  uint32_t neg = 0;  // bit mu: eta_mu(x) = -1
   uint32_t par = 0;
 #pragma unroll
   for (int mu = 0; mu < 4; ++mu) {
@@ -55,93 +76,50 @@ __device__ __forceinline__ cplx<R> stencil_hop(const Stencil<cplx<R>>& op, int64
     const uint32_t q = rem / L;
     const uint32_t xm = rem - q * L;
     rem = q;
-    two_eta[mu] = (par & 1u) ? R(-2) : R(2);
+    neg |= (par & 1u) << mu;
     par += xm;
-    const int64_t st = op.stride[mu];
-    fwd[mu] = xm == L - 1 ? int64_t(s) - int64_t(L - 1) * st : int64_t(s) + st;
-    bwd[mu] = xm == 0 ? int64_t(s) + int64_t(L - 1) * st : int64_t(s) - st;
+    const uint32_t st = uint32_t(op.stride[mu]);
+    fwd[mu] = xm == L - 1 ? s - (L - 1) * st : s + st;
+    bwd[mu] = xm == 0 ? s + (L - 1) * st : s - st;
   }
-  cplx<R> fw = czero<R>(), bw = czero<R>();
-  if constexpr (LR == 2) {
-    // per lane: the six link values it needs, at lane-dependent offsets.  Forward, row c
-    // of W_mu(x): rows 0 and 1 for c = 2 (whose row is rebuilt), row c twice otherwise.
-    // Backward, column c of W_mu(x - mu): (0, c), (1, c) and the four entries of rows 0
-    // and 1 in columns c + 1 and c + 2 that give (2, c).
-    const int c1 = c == 2 ? 0 : c + 1, c2 = c == 0 ? 2 : c - 1;
-    const int f0 = c < 2 ? 3 * c : 0, f1 = c < 2 ? 3 * c : 3;
+  cplx<R> fw[3], bw[3];
 #pragma unroll
-    for (int mu = 0; mu < 4; ++mu) {
-      const cplx<R>* __restrict__ wf = op.w + (int64_t(mu) * op.vol + s) * 6;
-      const cplx<R>* __restrict__ wb = op.w + (int64_t(mu) * op.vol + bwd[mu]) * 6;
-      cplx<R> F[6], gf[3], gb[3];
+  for (int c = 0; c < 3; ++c) fw[c] = bw[c] = czero<R>();
 #pragma unroll
-      for (int j = 0; j < 3; ++j) {
-        F[j] = wf[f0 + j];
-        F[3 + j] = wf[f1 + j];
-      }
-      const cplx<R> a0 = wb[c], a1 = wb[3 + c];
-      const cplx<R> b0 = wb[c1], b1 = wb[3 + c2], d0 = wb[c2], d1 = wb[3 + c1];
+  for (int mu = 0; mu < 4; ++mu) {
+    const cplx<R>* __restrict__ wm = op.w + int64_t(mu) * K * vol;
+    cplx<R> U[9], B[9], gf[3], gb[3];
 #pragma unroll
-      for (int j = 0; j < 3; ++j) {
-        gf[j] = gather(3 * fwd[mu] + j);
-        gb[j] = gather(3 * bwd[mu] + j);
-      }
-      const R te = two_eta[mu];
-#pragma unroll
-      for (int j = 0; j < 3; ++j) {
-        const int j1 = (j + 1) % 3, j2 = (j + 2) % 3;
-        cplx<R> r2 = conj_diff<R>(F[j1], F[3 + j2], F[j2], F[3 + j1]);
-        r2.x *= te;
-        r2.y *= te;
-        cfma<R>(fw, c < 2 ? F[j] : r2, gf[j]);
-      }
-      cplx<R> e2 = conj_diff<R>(b0, b1, d0, d1);
-      e2.x *= te;
-      e2.y *= te;
-      cfma_conj<R>(bw, a0, gb[0]);
-      cfma_conj<R>(bw, a1, gb[1]);
-      cfma_conj<R>(bw, e2, gb[2]);
+    for (int k = 0; k < K; ++k) {
+      U[k] = wm[int64_t(k) * vol + s];
+      B[k] = wm[int64_t(k) * vol + bwd[mu]];
     }
-  } else {
 #pragma unroll
-    for (int h = 0; h < 4; h += DPR) {
-      cplx<R> uf[DPR][3], ub[DPR][3], gf[DPR][3], gb[DPR][3];
+    for (int j = 0; j < 3; ++j) {
+      gf[j] = gather(3 * int64_t(fwd[mu]) + j);
+      gb[j] = gather(3 * int64_t(bwd[mu]) + j);
+    }
+    if constexpr (LR == 2) {
+      const R te = ((neg >> mu) & 1u) ? R(-2) : R(2);
+      third_row<R>(U, te);
+      third_row<R>(B, te);
+    }
 #pragma unroll
-      for (int d = 0; d < DPR; ++d) {
-        const int mu = h + d;
-        const cplx<R>* __restrict__ wf = op.w + (int64_t(mu) * op.vol + s) * 9 + 3 * c;
-        const cplx<R>* __restrict__ wb = op.w + (int64_t(mu) * op.vol + bwd[mu]) * 9 + c;
+    for (int c = 0; c < 3; ++c) {
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {
-          uf[d][j] = wf[j];
-          ub[d][j] = wb[3 * j];
-          gf[d][j] = gather(3 * fwd[mu] + j);
-          gb[d][j] = gather(3 * bwd[mu] + j);
-        }
-      }
-#pragma unroll
-      for (int d = 0; d < DPR; ++d) {
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-          cfma<R>(fw, uf[d][j], gf[d][j]);
-          cfma_conj<R>(bw, ub[d][j], gb[d][j]);
-        }
+      for (int j = 0; j < 3; ++j) {
+        cfma<R>(fw[c], U[3 * c + j], gf[j]);
+        cfma_conj<R>(bw[c], B[3 * j + c], gb[j]);
       }
     }
   }
-  return cplx<R>{fw.x - bw.x, fw.y - bw.y};
-}
-
-// Row `row` of M v (sign = +1) or M^H v (sign = -1): m v_row + sign (D v)_row.
-template <class R, int DPR, int LR, class G>
-__device__ __forceinline__ cplx<R> stencil_row(const Stencil<cplx<R>>& op, int64_t row,
-                                               const cplx<R>& v_row, int sign, G gather) {
-  const cplx<R> h = stencil_hop<R, DPR, LR>(op, row, gather);
   const R m = R(op.mass);
-  cplx<R> o;
-  o.x = sign > 0 ? fma(m, v_row.x, h.x) : fma(m, v_row.x, -h.x);
-  o.y = sign > 0 ? fma(m, v_row.y, h.y) : fma(m, v_row.y, -h.y);
-  return o;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const cplx<R> h{fw[c].x - bw[c].x, fw[c].y - bw[c].y};
+    out[c].x = sign > 0 ? fma(m, own[c].x, h.x) : fma(m, own[c].x, -h.x);
+    out[c].y = sign > 0 ? fma(m, own[c].y, h.y) : fma(m, own[c].y, -h.y);
+  }
 }
 
 }  // namespace msc
