@@ -14,7 +14,10 @@ stored matrix), while the library also builds the equivalent CSR for its other k
 * SU(3) links are read as their first two rows (the third rebuilt in the kernels):
   reported by storage(), and links off SU(3) (scaled, or a U(3) phase) keep all nine
   values, through creation and through update_links, with the same parity;
-* the misuse cases are rejected.
+* the misuse cases are rejected;
+* the site kernels on lattices whose volume leaves a partial block of 64 sites, on one
+  whose blocks follow the lattice order, and with nine-value links in both phases of a
+  mixed solve, against the oracle.
 """
 import numpy as np
 import pytest
@@ -191,4 +194,59 @@ def test_two_row_links_and_their_fallback(c0, cuda):
     # back to SU(3) links: two rows again
     op.update_links(c0["links"])
     assert op.storage()["two_rows"] is True
+    op.close()
+
+
+@pytest.mark.parametrize("dims", [(3, 4, 5, 6), (5, 5, 5, 7), (8, 8, 8, 8)])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_site_kernels_on_ragged_and_ordered_lattices(cuda, dims, prec):
+    # the iteration's kernels take blocks of 64 sites: 360 and 875 sites leave a partial
+    # last block, 8^4 (planes of exactly one block) sweeps its blocks in the lattice order;
+    # FP64 at tol 1e-10 against the oracle CG-M (per shift <= 1e-8, iterations within 2),
+    # mixed at 1e-12 against the oracle at 1e-13
+    from paper_1102_2143_amd import Operator
+    print(f"[gpu] stencil site kernels dims={dims} {prec}", flush=True)
+    mass = 0.1
+    links = W.random_su3_links(dims, 77)
+    rowptr, col, vals = W.staggered_csr(links, dims, mass)
+    n = 3 * W.lattice_volume(dims)
+    sigma = W.logspace_shifts(1e-4, 1.0, 6)
+    b = W.gaussian_rhs(n, 78)
+    ap = O.shifted_apply("mhm", rowptr, col, vals, n)
+    op = Operator.staggered(links, dims, mass, device=cuda)
+    assert op.storage()["two_rows"] is True
+    op.set_shifts(sigma)
+    if prec == "fp64":
+        ref = O.cg_m(ap, b, sigma, tol=1e-10)
+        x, info = op.solve(b, tol=1e-10, prec="fp64")
+        assert abs(info["iters"] - ref["iters"]) <= 2
+        assert np.all(info["true_rel_res"] <= 1e-10)
+    else:
+        ref = O.cg_m(ap, b, sigma, tol=1e-13)
+        x, info = op.solve(b, tol=1e-12, prec="mixed")
+        assert np.all(info["true_rel_res"] <= 1e-12)
+    assert info["status"] == "ok"
+    assert np.all(_rel(x.cpu().numpy(), ref["x"]) <= 1e-8)
+    op.close()
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (3, 4, 5, 6)])
+def test_nine_value_links_in_the_mixed_solve(cuda, dims):
+    # links off SU(3) keep all nine values in both phases of a mixed solve (the complex64
+    # kernels read them too): mixed at 1e-12 against the oracle at 1e-13
+    from paper_1102_2143_amd import Operator
+    print(f"[gpu] stencil nine-value links mixed dims={dims}", flush=True)
+    mass = 0.1
+    links = W.random_su3_links(dims, 79) * 1.01
+    rowptr, col, vals = W.staggered_csr(links, dims, mass)
+    n = 3 * W.lattice_volume(dims)
+    sigma = W.logspace_shifts(1e-4, 1.0, 6)
+    b = W.gaussian_rhs(n, 80)
+    op = Operator.staggered(links, dims, mass, device=cuda)
+    assert op.storage()["two_rows"] is False
+    op.set_shifts(sigma)
+    x, info = op.solve(b, tol=1e-12, prec="mixed")
+    ref = O.cg_m(O.shifted_apply("mhm", rowptr, col, vals, n), b, sigma, tol=1e-13)
+    assert info["status"] == "ok" and np.all(info["true_rel_res"] <= 1e-12)
+    assert np.all(_rel(x.cpu().numpy(), ref["x"]) <= 1e-8)
     op.close()
