@@ -389,7 +389,7 @@ msc_status run_multishift(msc_op op, const double* d_b, double* d_x, const msc_p
   if (prm.max_grid > 0) a64.grid = std::min(prm.max_grid, kMaxGrid);
   if (prm.format == MSC_FORMAT_CSR) a64.sell = 0;
   // the iteration's two operator halves from the links: the default for staggered
-  // operators (the reliable update, verification and refinement keep the stored copies)
+  // operators (verification and refinement keep the stored copies)
   a64.stencil = op->stencil && a64.sell &&
                 (prm.format == MSC_FORMAT_AUTO || prm.format == MSC_FORMAT_STENCIL)
                     ? (op->two_rows ? 2 : 3) : 0;
@@ -591,9 +591,17 @@ msc_status run_multishift(msc_op op, const double* d_b, double* d_x, const msc_p
                           mat_bytes(op->kind, MSC_PREC_MIXED, nn, nz, nzh, ib, ibh, a32.stencil), act32,
                           double(fin.iter - iters_fp64), kept32) +
                (a64.stencil != 0 ? 16.0 * nn * double(tr_launches(iters_fp64)) : 0.0) +
-               double(h.n_reliable) * (nz * (16.0 + ib) + nzh * (16.0 + ibh) +
-                                       4.0 * (nn + 1) * (op->kind == MSC_A_MHM ? 2.0 : 1.0) +
-                                       nn * (16.0 * 3 + 8.0));
+               double(h.n_reliable) *
+                   ((a32.stencil != 0
+                         ? [&] {
+                             // the reliable update reads the FP64 links
+                             const MatBytes rb = mat_bytes(op->kind, MSC_PREC_FP64, nn, nz, nzh, ib,
+                                                           ibh, a32.stencil);
+                             return rb.m + rb.mh;
+                           }()
+                         : nz * (16.0 + ib) + nzh * (16.0 + ibh) +
+                               4.0 * (nn + 1) * (op->kind == MSC_A_MHM ? 2.0 : 1.0)) +
+                    nn * (16.0 * 3 + 8.0));
   // the fused head reads the old direction once for the update and the product
   if (a64.sell) *bytes_out -= nn * (16.0 * iters_fp64 + 8.0 * (fin.iter - iters_fp64));
   if (info) info->iters_fp64 = iters_fp64;

@@ -1309,6 +1309,74 @@ __global__ __launch_bounds__(kBlock) void k_ru_second_s(MsArgs a) {
   ru_finish(a, acc);
 }
 
+// The same on the links (matrix-free staggered operator, LR rows per link), one site per
+// lane: t64 = M x_0, then r = b - M^H t64 - sigma0 x_0.
+template <int LR>
+__global__ __launch_bounds__(kBlock) void k_ru_first_site(MsArgs a) {
+  const SolveState* st = a.st;
+  if (!ru_due(a)) return;
+  const double2* __restrict__ x0 = a.x + int64_t(st->orig[0]) * a.n;
+  const Stencil<double2> w = a.w64;
+  const uint32_t vol = uint32_t(w.vol);
+  constexpr int WPB = kBlock / kWave;
+  const int lane = threadIdx.x % kWave;
+  const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x / kWave));
+  int64_t beg, end;
+  block_range((int64_t(vol) + kSiteBlock - 1) / kSiteBlock, WPB, beg, end);
+  for (int64_t blk = beg + wv; blk < end; blk += WPB) {
+    const uint32_t site = uint32_t(blk * kSiteBlock) + uint32_t(lane);
+    const uint32_t ss = site < vol ? site : vol - 1;  // lanes past the volume: unused
+    const int64_t r0 = 3 * int64_t(ss);
+    double2 own[3], v[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) own[c] = x0[r0 + c];
+    stencil_site<double, LR>(w, ss, own, 1, [&](int64_t c) { return x0[c]; }, v);
+    if (site < vol) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) a.t64[r0 + c] = v[c];
+    }
+  }
+}
+
+template <class R, int LR>
+__global__ __launch_bounds__(kBlock) void k_ru_second_site(MsArgs a) {
+  SolveState* st = a.st;
+  if (!ru_due(a)) return;
+  const double2* __restrict__ x0 = a.x + int64_t(st->orig[0]) * a.n;
+  const double2* __restrict__ u = a.t64;
+  cplx<R>* __restrict__ r = static_cast<cplx<R>*>(a.r);
+  const double sigma0 = st->sigma0;
+  const Stencil<double2> w = a.w64;
+  const uint32_t vol = uint32_t(w.vol);
+  constexpr int WPB = kBlock / kWave;
+  const int lane = threadIdx.x % kWave;
+  const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x / kWave));
+  int64_t beg, end;
+  block_range((int64_t(vol) + kSiteBlock - 1) / kSiteBlock, WPB, beg, end);
+  double acc = 0.0;
+  for (int64_t blk = beg + wv; blk < end; blk += WPB) {
+    const uint32_t site = uint32_t(blk * kSiteBlock) + uint32_t(lane);
+    const uint32_t ss = site < vol ? site : vol - 1;  // lanes past the volume: unused
+    const int64_t r0 = 3 * int64_t(ss);
+    double2 own[3], q[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) own[c] = u[r0 + c];
+    stencil_site<double, LR>(w, ss, own, -1, [&](int64_t c) { return u[c]; }, q);
+    if (site < vol) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const double2 bv = a.b[r0 + c], xv = x0[r0 + c];
+        double2 rt;
+        rt.x = bv.x - q[c].x - sigma0 * xv.x;
+        rt.y = bv.y - q[c].y - sigma0 * xv.y;
+        r[r0 + c] = from_d<R>(rt);
+        acc += fma(rt.x, rt.x, rt.y * rt.y);
+      }
+    }
+  }
+  ru_finish(a, acc);
+}
+
 // ---- verification: FP64 true residual norms of up to 8 solutions ---------------------
 constexpr int kVerifyChunk = 8;
 
@@ -1556,6 +1624,18 @@ void launch_timed(K kern, int grid, hipStream_t s, hipEvent_t* ev, int k, const 
 
 template <class R>
 hipError_t reliable_impl(const MsArgs& a, hipStream_t s) {
+  if (a.sell && a.kind == MSC_A_MHM && a.stencil != 0) {
+    // the links: the same FP64 operator as the stored copies, a third of their bytes
+    const int gs = grid_rows((a.w64.vol + kSiteBlock - 1) / kSiteBlock, kBlock / kWave);
+    if (a.stencil == 2) {
+      k_ru_first_site<2><<<gs, kBlock, 0, s>>>(a);
+      k_ru_second_site<R, 2><<<gs, kBlock, 0, s>>>(a);
+    } else {
+      k_ru_first_site<3><<<gs, kBlock, 0, s>>>(a);
+      k_ru_second_site<R, 3><<<gs, kBlock, 0, s>>>(a);
+    }
+    return hipGetLastError();
+  }
   if (a.sell) {
     const int gs = grid_rows(a.nslices, kBlock / kSlice);
     if (a.kind == MSC_A_MHM) {
