@@ -100,9 +100,9 @@ typedef struct {
                                 reach mixed_margin * tol (0 < margin <= 1), so that the
                                 complex64 drift leaves few shifts above tol     (0.7)  */
     int32_t update_steps;    /* 1..8: consecutive steps of the all-shift update folded
-                                into one pass over x_k and p_k (the heads between defer
-                                theirs); same recurrences, 1/update_steps of the traffic
-                                of those vectors. 1: one step per iteration. The
+                                into one pass over x_0, x_k and p_k (the heads between
+                                defer theirs); same recurrences, 1/update_steps of the
+                                traffic of those vectors. 1: one step per iteration. The
                                 batched solve folds at most 4 (larger values act
                                 as 4 there)                                     (8)    */
     int32_t sweep;           /* order of the rows the iteration kernels visit: 0 (auto)

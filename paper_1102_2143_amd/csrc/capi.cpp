@@ -58,7 +58,8 @@ template <class T> void dfree(T*& p) {
 }
 
 void free_workspace(Workspace& w) {
-  for (void* q : {w.r, w.p[0], w.p[1], w.t, w.pk, w.r32, w.p32[0], w.p32[1], w.t32, w.pk32})
+  for (void* q : {w.r, w.p[0], w.p[1], w.t, w.pk, w.r32, w.p32[0], w.p32[1], w.t32, w.pk32,
+                  w.pkeep0})
     if (q) (void)hipFree(q);
   for (void*& q : w.rkeep) {
     if (q) (void)hipFree(q);
@@ -103,6 +104,7 @@ msc_status ensure_workspace(msc_op op, int prec, int ns) {
     HIP_TRY(dalloc(&w.t64, n));
     HIP_TRY(dalloc(&w.u64, n * 8));
     for (auto& q : w.rkeep) HIP_TRY(hipMalloc(&q, sizeof(double2) * n));
+    HIP_TRY(hipMalloc(&w.pkeep0, sizeof(double2) * n));
     HIP_TRY(dalloc(&w.st, 1));
     HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&w.h_halt), 4 * sizeof(int),
                           hipHostMallocMapped | hipHostMallocCoherent));
@@ -265,6 +267,7 @@ MsArgs make_args(msc_op op, int lanes, const double* d_b, double* d_x) {
   a.t = op->ws.t;
   a.pk = op->ws.pk;
   for (int k = 0; k < kMaxSteps - 1; ++k) a.rkeep[k] = op->ws.rkeep[k];  // complex64 in phase 2
+  a.pkeep0 = op->ws.pkeep0;
   a.hflag = op->ws.d_halt;
   a.steps = 1;
   a.defer_ok = 0;
@@ -313,21 +316,26 @@ MatBytes mat_bytes(int kind, int prec, double n, double nnz, double nnz_h, doubl
                   kind == MSC_A_MHM ? nnz_h * (w + ibh) + 4.0 * (n + 1) : 0.0};
 }
 
+// x0b: bytes per row of x_0 and of its kept direction that the update moves (an applying
+// head reads and writes x_0, 32, and reads the kept direction after deferred steps; the
+// first deferring head of a cycle writes it).
 KernelBytes kernel_bytes(int kind, int prec, double n, const MatBytes& mb, double act,
-                         bool pending, int kept) {
+                         bool pending, int kept, double x0b) {
   const double w = prec == MSC_PREC_MIXED ? 8.0 : 16.0;
   KernelBytes b{};
   b.k1 = mb.m + 2.0 * n * w;
   b.k2 = (kind == MSC_A_MHM ? mb.mh + n * w : n * w) + 3.0 * n * w;
-  b.upd = pending ? n * (3.0 * w + 32.0) + act * n * (32.0 + 2.0 * w) + kept * n * w : 0.0;
+  b.upd = pending ? n * (3.0 * w + x0b) + act * n * (32.0 + 2.0 * w) + kept * n * w : 0.0;
   b.head = b.k1 + (pending ? b.upd - n * w : 0.0);
   return b;
 }
 
 // act_sum: x_j/p_j row-vector updates performed (shifts listed, summed over the heads);
 // kept: heads that kept r for a deferred step or read it back.
+// x0_total: bytes per row of x_0 and its kept direction summed over the heads (negative:
+// x_0 read and written in every iteration, 32 bytes per row each).
 double iter_bytes(int kind, int prec, double n, const MatBytes& mb, double act_sum,
-                  double iters, double kept) {
+                  double iters, double kept, double x0_total = -1.0) {
   const double w = prec == MSC_PREC_MIXED ? 8.0 : 16.0;   // Krylov vector element
   const double mat = mb.m + mb.mh;
   double vec;
@@ -335,9 +343,10 @@ double iter_bytes(int kind, int prec, double n, const MatBytes& mb, double act_s
     vec = n * (w + w) + n * (w + w + 2 * w);  // K1: p gather, t write; K2: t gather, p, r r/w
   else
     vec = n * (w + w) + n * (w + w + 2 * w);  // K1: p, t; K2: t, p, r r/w
-  vec += n * (w + 2 * w + 32.0);               // K3: r, p r/w, x_0 r/w
+  vec += n * (w + 2 * w);                      // K3: r, p r/w
+  const double x0 = x0_total < 0.0 ? 32.0 * n * iters : x0_total * n;
   const double per_shift = n * (32.0 + 2 * w); // x_j r/w (complex128) + p_j r/w
-  return iters * (mat + vec) + act_sum * per_shift + kept * n * w;
+  return iters * (mat + vec) + x0 + act_sum * per_shift + kept * n * w;
 }
 
 // Events for sampled per-kernel timing; destroyed with the pool.
@@ -487,6 +496,7 @@ msc_status run_multishift(msc_op op, const double* d_b, double* d_x, const msc_p
       const bool ru = ru_period || (phase == MSC_PREC_MIXED && prm.reliable_every > 0 &&
                                     since > 0 && since % kRuCheck == 0);
       cur->ru_force = ru_period ? 1 : 0;
+      cur->ru_check = ru ? 1 : 0;
       // links, FP64: the head's product by the recurrence t' = M r + b t; a direct one in
       // the first launch (no old t yet) and every kTrEvery launches
       cur->t_rec = tr_launch(phase == MSC_PREC_FP64 && cur->stencil != 0, launched) ? 1 : 0;
@@ -555,10 +565,13 @@ msc_status run_multishift(msc_op op, const double* d_b, double* d_x, const msc_p
       const int act = h.smp_nact[q];
       const int kept = h.smp_mode[q] == 1 ? 1 : h.smp_m[q];
       const int phq = ph32 ? MSC_PREC_MIXED : MSC_PREC_FP64;
+      const double wq = ph32 ? 8.0 : 16.0;
+      const double x0b = h.smp_mode[q] == 0 ? 32.0 + (h.smp_m[q] > 0 ? wq : 0.0)
+                                            : (h.smp_m[q] == 0 ? wq : 0.0);
       const KernelBytes kb =
           kernel_bytes(op->kind, phq, nn, mat_bytes(op->kind, phq, nn, nz, nzh, ib, ibh,
                                                    phq == MSC_PREC_FP64 ? a64.stencil : a32.stencil),
-                       double(act), pending, kept);
+                       double(act), pending, kept, x0b);
       // a recurrence head also reads the old t (its own row)
       const bool trq = tr_launch(phq == MSC_PREC_FP64 && a64.stencil != 0, L);
       kby[0] += (a64.sell ? kb.head : kb.k1) + (trq ? 16.0 * nn : 0.0);
@@ -584,12 +597,16 @@ msc_status run_multishift(msc_op op, const double* d_b, double* d_x, const msc_p
   const double act64 = h.n_shift_upd[0], act32 = h.n_shift_upd[1];
   const double kept64 = h.n_defer[0] + h.n_two[0], kept32 = h.n_defer[1] + h.n_two[1];
   const double nn = double(op->n), nz = double(op->nnz), nzh = double(op->nnz_h);
+  // x_0 (and its kept direction) per phase: applying heads read and write x_0, and each
+  // cycle with deferred steps writes and reads the kept direction once
+  const double x064 = 32.0 * h.n_apply[0] + 2.0 * 16.0 * h.n_keep0[0];
+  const double x032 = 32.0 * h.n_apply[1] + 2.0 * 8.0 * h.n_keep0[1];
   *bytes_out = iter_bytes(op->kind, MSC_PREC_FP64, nn,
                           mat_bytes(op->kind, MSC_PREC_FP64, nn, nz, nzh, ib, ibh, a64.stencil), act64,
-                          double(iters_fp64), kept64) +
+                          double(iters_fp64), kept64, x064) +
                iter_bytes(op->kind, MSC_PREC_MIXED, nn,
                           mat_bytes(op->kind, MSC_PREC_MIXED, nn, nz, nzh, ib, ibh, a32.stencil), act32,
-                          double(fin.iter - iters_fp64), kept32) +
+                          double(fin.iter - iters_fp64), kept32, x032) +
                (a64.stencil != 0 ? 16.0 * nn * double(tr_launches(iters_fp64)) : 0.0) +
                double(h.n_reliable) *
                    ((a32.stencil != 0

@@ -105,11 +105,15 @@ struct SolveState {
   int smp_nact[kMaxSamples];
   int smp_m[kMaxSamples];
   // per phase (0: FP64, 1: complex64): x_j/p_j row updates performed (in units of n
-  // rows), heads that deferred their update, and passes over kept residuals (a deferring
-  // head writes one, an applying head reads the ones pending)
+  // rows), heads that deferred their update, passes over kept residuals (a deferring
+  // head writes one, an applying head reads the ones pending), heads that applied the
+  // update (x_0 read and written), and heads that kept the direction for x_0's deferred
+  // steps (the applying head of that cycle reads it back)
   int n_shift_upd[2];
   int n_defer[2];
   int n_two[2];
+  int n_apply[2];
+  int n_keep0[2];
   int pad2_[2];
 };
 
@@ -200,6 +204,7 @@ struct Workspace {
   void* t32 = nullptr;
   void* pk32 = nullptr;
   double2* t64 = nullptr;   // n complex128 (reliable updates, verification)
+  void* pkeep0 = nullptr;           // n complex128 (complex64 in phase 2): x_0's first deferred direction
   void* rkeep[kMaxSteps - 1] = {};  // n complex128 each (complex64
                             // in the second phase): residuals kept by deferring heads
   double2* u64 = nullptr;   // 8 * n complex128 (verification SpMM chunk)
@@ -336,10 +341,13 @@ struct MsArgs {
   void* r; void* t; void* pk;
   void* pb[2];           // the two direction buffers (p of consecutive iterations)
   void* rkeep[kMaxSteps - 1];  // residuals kept by heads that defer the all-shift update
+  void* pkeep0;          // the direction p at the first deferred step (x_0's deferred update)
   int* hflag;            // host-coherent word: halt | switch_req << 1 of the next state
   int steps;             // steps of the all-shift update folded into one pass (1..kMaxSteps)
   int defer_ok;          // 1: this launch's head may defer its all-shift update
   int ru_force;          // reliable-update launch: 1 runs it whatever the residual
+  int ru_check;          // 1: the reliable-update kernels follow this head (x_0 must be
+                         // current when they run)
   int stencil;           // the head and K2 apply M and M^H from links (kind MHM, sell = 1):
                          // 0 no, 3 full links, 2 two rows per link (w64 / w32 in that form)
   SweepOrder ord;        // slice order of the head and K2 on the sliced path

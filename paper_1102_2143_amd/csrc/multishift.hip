@@ -136,12 +136,17 @@ __device__ __forceinline__ cplx<R> next_dir(double b, const cplx<R>& r, const cp
 }
 
 // Minimum waves per SIMD asked of the compiler for the matrix-free head and K2 (1: no
-// constraint).
+// constraint).  The FP64 heads need the bound and a scheduling barrier between their
+// update and stencil parts (MSC_SITE_SB): without them the compiler interleaves the two
+// into 256 VGPRs, one wave per SIMD.
 #ifndef MSC_SITE_HEAD_WPE
-#define MSC_SITE_HEAD_WPE 1
+#define MSC_SITE_HEAD_WPE 2
 #endif
 #ifndef MSC_SITE_K2_WPE
 #define MSC_SITE_K2_WPE 1
+#endif
+#ifndef MSC_SITE_SB
+#define MSC_SITE_SB 1
 #endif
 
 // Pairs per round trip when each entry gathers two vectors (MSC_SELL_KPN32 / 64).
@@ -403,6 +408,11 @@ struct Plan {
   int64_t xo[kMaxShifts];
   int64_t po[kMaxShifts];
   int pw[kMaxShifts];
+  // the driving system in the same form (zeta = 1): x_0 += x0c[0] p_1 + sum_{k<m}
+  // x0c[k+1] r_k, p_1 the direction at the first pending step (the current p when m = 0,
+  // else the one the first deferring head kept)
+  double x0c[kMaxSteps];
+  int keep0;                 // 1: this deferring head keeps p for x_0 (first of a cycle)
   int nact;
   int mode;                  // 0: apply (the current step and m deferred ones); 1: defer
   int m;                     // kept residuals read (mode 0)
@@ -415,9 +425,11 @@ struct Plan {
 // Consecutive steps of shift j compose: with p_j = cp[0] p + sum_k cp[k+1] r_k after the
 // deferred ones, the next step adds a_j p_j to x_j and turns p_j into
 // zeta_j' r + b_j p_j (r: that step's residual), unless j freezes there (p_j stays); a
-// frozen shift takes no further step.  A head defers (keeps its r, touches no x_j, p_j)
-// while fewer than `steps` - 1 steps are pending and its iteration continues; otherwise
-// it applies all of them in one pass.
+// frozen shift takes no further step.  The driving system (lane 0) composes the same way
+// with zeta = 1, a_0 = a and b_0 = b: its x is x_0, its direction p.  A head defers (keeps
+// its r, touches no x_j, p_j and not x_0) while fewer than `steps` - 1 steps are pending,
+// its iteration continues and no reliable update (which reads x_0) runs after it;
+// otherwise it applies all of them in one pass.
 template <class T>
 __device__ void head_plan(const MsArgs& a, const Early& e, Plan& pl) {
   constexpr int ph = sizeof(T) == 4 ? 1 : 0;  // phase: 0 FP64, 1 complex64
@@ -434,14 +446,15 @@ __device__ void head_plan(const MsArgs& a, const Early& e, Plan& pl) {
 #pragma unroll
   for (int i = 0; i <= kMaxSteps; ++i) cx[i] = cp[i] = 0.0;
   cp[0] = 1.0;
-  if (j >= 1 && j < kWave && j < st->ns) {
+  const bool drv = j == 0;  // lane 0: the driving system
+  if (j < kWave && j < st->ns) {
     if (pending) {
-      act0 = rs.active[j];
-      z = rs.zeta[j];
-      zn = st->zk[j];
-      akj = st->ak[j];
+      act0 = drv ? 1 : rs.active[j];
+      z = drv ? 1.0 : rs.zeta[j];
+      zn = drv ? 1.0 : st->zk[j];
+      akj = drv ? st->a : st->ak[j];
     }
-    if (pending || m > 0) origj = st->orig[j];
+    if (!drv && (pending || m > 0)) origj = st->orig[j];
     if (m > 0) {
       const DeferState& d = st->dfs[a.par];
 #pragma unroll
@@ -462,7 +475,7 @@ __device__ void head_plan(const MsArgs& a, const Early& e, Plan& pl) {
     const bool ok = !pending || (isfinite(Rn) && kst == 0);
     const double bn = pending ? Rn / R : 0.0;
     const bool act = pending && ok && act0;
-    const bool freeze_now = act && frz && zn * zn * Rn <= eps2;
+    const bool freeze_now = act && !drv && frz && zn * zn * Rn <= eps2;
     const double ratio = act ? zn / z : 0.0;
     const double bk = bn * ratio * ratio;
     const int it = pending ? rs.iter + 1 : rs.iter;
@@ -487,8 +500,11 @@ __device__ void head_plan(const MsArgs& a, const Early& e, Plan& pl) {
     }
     dact = dact || act;
     dupd = dupd || (act && !freeze_now);
-    const int mode = (pending && cont && a.defer_ok && m + 1 < a.steps) ? 1 : 0;
-    const bool listed = mode == 0 && dact;
+    // a reliable update after this head reads x_0: the same test as ru_due on the R this
+    // head writes
+    const bool ru_now = a.ru_check && (a.ru_force || Rn < kRuDelta2 * st->R_ru);
+    const int mode = (pending && cont && a.defer_ok && m + 1 < a.steps && !ru_now) ? 1 : 0;
+    const bool listed = mode == 0 && dact && !drv;
     const uint64_t mask = __ballot(listed);
     if (listed) {
       const int pos = __popcll(mask & ((uint64_t(1) << j) - 1));
@@ -501,7 +517,10 @@ __device__ void head_plan(const MsArgs& a, const Early& e, Plan& pl) {
       pl.pw[pos] = dupd ? 1 : 0;
     }
     const int nlist = __popcll(mask);
-    if (j == 0) {
+    if (drv) {
+#pragma unroll
+      for (int i = 0; i < kMaxSteps; ++i) pl.x0c[i] = (mode == 0 && i <= m) ? cx[i] : 0.0;
+      pl.keep0 = (mode == 1 && m == 0) ? 1 : 0;
       pl.bn = bn;
       pl.nact = nlist;
       pl.mode = mode;
@@ -513,9 +532,14 @@ __device__ void head_plan(const MsArgs& a, const Early& e, Plan& pl) {
     }
     if (blockIdx.x == 0) {
       if (j < st->ns) {
-        nx.zeta[j] = act ? zn : rs.zeta[j];
-        nx.active[j] = act ? (freeze_now ? 0 : 1) : rs.active[j];
-        if (mode == 1 && j >= 1) {
+        if (!drv) {
+          nx.zeta[j] = act ? zn : rs.zeta[j];
+          nx.active[j] = act ? (freeze_now ? 0 : 1) : rs.active[j];
+        } else {
+          nx.zeta[0] = rs.zeta[0];
+          nx.active[0] = rs.active[0];
+        }
+        if (mode == 1) {
           DeferState& d = st->dfs[a.par ^ 1];
 #pragma unroll
           for (int i = 0; i < kMaxSteps; ++i) {
@@ -526,22 +550,24 @@ __device__ void head_plan(const MsArgs& a, const Early& e, Plan& pl) {
           d.upd[j] = dupd ? 1 : 0;
         }
       }
-      if (act) {
+      if (act && !drv) {
         st->zeta_prev[j] = z;
         if (freeze_now) st->freeze_iter[j] = it;
       }
-      if (j == 0) {
+      if (drv) {
         nx.pending = 0;
         nx.ndef = (ok && mode == 1) ? m + 1 : 0;
         if (a.sample >= 0 && a.sample < kMaxSamples) {
           st->smp_mode[a.sample] = mode;
           st->smp_nact[a.sample] = nlist;
-          st->smp_m[a.sample] = mode == 0 ? m : 0;
+          st->smp_m[a.sample] = m;
         }
         if (pending && ok) {
           st->n_shift_upd[ph] += nlist;
           st->n_defer[ph] += mode == 1 ? 1 : 0;
           st->n_two[ph] += mode == 0 ? m : 0;
+          st->n_apply[ph] += mode == 0 ? 1 : 0;
+          st->n_keep0[ph] += (mode == 1 && m == 0) ? 1 : 0;
         }
         if (!ok) {
           nx.R = R;
@@ -594,33 +620,47 @@ __device__ void carry_state(const MsArgs& a) {
   }
 }
 
-// The pending update of row i: x_0 += a p, then the listed shifts' x_j and p_j as the
-// plan composes them (the current step and the m deferred ones, reading the m kept
-// residuals; a deferring head keeps r instead and touches no shift), then the new
-// direction r + b p, which is stored in the other direction buffer and returned.  rr,
-// pp, x0v: the row's r, p and x_0 (already loaded).
+// The pending update of row i: the listed shifts' x_j and p_j and x_0 as the plan
+// composes them (the current step and the m deferred ones, reading the m kept residuals;
+// a deferring head keeps r, and the first of a cycle p, instead and touches neither x_0
+// nor any shift), then the new direction r + b p, which is stored in the other direction
+// buffer and returned.  rr, pp: the row's r and p (already loaded).
 template <class R>
-__device__ __forceinline__ cplx<R> update_row(const MsArgs& a, const Plan& pl, double step,
-                                              int64_t i, const cplx<R>& rr, const cplx<R>& pp,
-                                              double2 x0v, double2* __restrict__ x0,
+__device__ __forceinline__ cplx<R> update_row(const MsArgs& a, const Plan& pl, int64_t i,
+                                              const cplx<R>& rr, const cplx<R>& pp,
+                                              double2* __restrict__ x0,
                                               cplx<R>* __restrict__ pnew) {
   cplx<R>* __restrict__ pk = static_cast<cplx<R>*>(a.pk);
+  cplx<R>* __restrict__ pkeep0 = static_cast<cplx<R>*>(a.pkeep0);
   double2* __restrict__ x = a.x;
   const double2 rd = to_d(rr), pd = to_d(pp);
-  x0v.x = fma(step, pd.x, x0v.x);
-  x0v.y = fma(step, pd.y, x0v.y);
-  st_stream(&x0[i], x0v);
   if (pl.keep >= 0) st_stream(&static_cast<cplx<R>*>(a.rkeep[pl.keep])[i], rr);
+  if (pl.keep0) st_stream(&pkeep0[i], pp);
   // kept residuals (zero beyond m, where the coefficients are zero too)
   double2 rk[kMaxSteps - 1];
 #pragma unroll
   for (int k = 0; k < kMaxSteps - 1; ++k)
     rk[k] = k < pl.m ? to_d(ld_stream(&static_cast<const cplx<R>*>(a.rkeep[k])[i])) : double2{0.0, 0.0};
+  const int m = pl.m;
+  if (pl.mode == 0) {
+    // x_0: with one step (m = 0) the fused multiply-add rounds exactly as x_0 += a p
+    double2 xv = ld_stream(&x0[i]);
+    const double2 p1 = m > 0 ? to_d(ld_stream(&pkeep0[i])) : pd;
+#pragma unroll
+    for (int k = kMaxSteps - 2; k >= 0; --k) {
+      if (k < m) {
+        xv.x = fma(pl.x0c[k + 1], rk[k].x, xv.x);
+        xv.y = fma(pl.x0c[k + 1], rk[k].y, xv.y);
+      }
+    }
+    xv.x = fma(pl.x0c[0], p1.x, xv.x);
+    xv.y = fma(pl.x0c[0], p1.y, xv.y);
+    st_stream(&x0[i], xv);
+  }
   // shifts in groups of MSC_UPD_GROUP: a group's loads are all issued before its first
   // store; a last, partial group is masked.  With one step (m = 0) the fused
   // multiply-adds round exactly as x += a p and p <- zeta r + b p.
   const int nact = pl.nact;
-  const int m = pl.m;
   auto group = [&](int q, int cnt, auto full) {
     cplx<R> pj[kUpdGroup];
     double2 xj[kUpdGroup];
@@ -696,15 +736,12 @@ __global__ __launch_bounds__(kBlock) void k_update(MsArgs a) {
   const int64_t i0 = beg + threadIdx.x;
   const int64_t ic = i0 < end ? i0 : n - 1;
   const cplx<R> r_first = rv[ic], p_first = pv[ic];
-  const double2 x_first = x0[ic];
-  const double step = st->a;
   __shared__ Plan pl;
   head_plan<R>(a, e, pl);
   if (!pl.ok || !pl.pending) return;
   for (int64_t i = i0; i < end; i += kBlock) {
     const bool first = i == i0;
-    update_row<R>(a, pl, step, i, first ? r_first : rv[i], first ? p_first : pv[i],
-                  first ? x_first : x0[i], x0, pnew);
+    update_row<R>(a, pl, i, first ? r_first : rv[i], first ? p_first : pv[i], x0, pnew);
   }
 }
 
@@ -732,7 +769,6 @@ __global__ __launch_bounds__(kBlock) void k1_fused(MsArgs a) {
   cplx<R>* __restrict__ t = static_cast<cplx<R>*>(a.t);
   double2* __restrict__ x0 = a.x + int64_t(st->orig[0]) * a.n;
   const double sigma0 = st->sigma0;
-  const double step = st->a;
   constexpr int SPB = kBlock / kSlice;
   const int lane = threadIdx.x % kSlice;
   Sweep sw = make_sweep(a.nslices, a.ord, SPB);
@@ -742,7 +778,6 @@ __global__ __launch_bounds__(kBlock) void k1_fused(MsArgs a) {
   const int64_t row0 = sl0 * kSlice + lane;
   const int64_t rc = (has0 && row0 < a.n) ? row0 : a.n - 1;
   const cplx<R> r_first = rv[rc], p_first = pv[rc];
-  const double2 x_first = ld_stream(&x0[rc]);
   __shared__ Plan pl;
   head_plan<R>(a, e, pl);
   if (!pl.ok) return;
@@ -759,8 +794,7 @@ __global__ __launch_bounds__(kBlock) void k1_fused(MsArgs a) {
     cplx<R> p_row = p_i;
     if (upd) {
       if (live)
-        p_row = update_row<R>(a, pl, step, row, r_i, p_i, first ? x_first : ld_stream(&x0[rr]), x0,
-                                pnew);
+        p_row = update_row<R>(a, pl, row, r_i, p_i, x0, pnew);
       else
         p_row = next_dir<R>(bn, r_i, p_i);
     }
@@ -959,7 +993,6 @@ __global__ __launch_bounds__(kBlock, MSC_SITE_HEAD_WPE) void k1_site(MsArgs a) {
   const uint32_t vol = uint32_t(w.vol);
   const int64_t nblk = (int64_t(vol) + kSiteBlock - 1) / kSiteBlock;
   const double sigma0 = st->sigma0;
-  const double step = st->a;
   constexpr int WPB = kBlock / kWave;
   const int lane = threadIdx.x % kWave;
   Sweep sw = make_sweep(nblk, a.ord, WPB);
@@ -975,9 +1008,12 @@ __global__ __launch_bounds__(kBlock, MSC_SITE_HEAD_WPE) void k1_site(MsArgs a) {
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
         const int64_t row = (3 * blk + k) * kWave + lane;
-        if (row < a.n) update_row<R>(a, pl, step, row, rv[row], pv[row], ld_stream(&x0[row]), x0, pnew);
+        if (row < a.n) update_row<R>(a, pl, row, rv[row], pv[row], x0, pnew);
       }
     }
+#if MSC_SITE_SB
+    __builtin_amdgcn_sched_barrier(0);
+#endif
     if (!pl.spmv) continue;
     const uint32_t site = uint32_t(blk * kSiteBlock) + uint32_t(lane);
     const bool live = site < vol;

@@ -234,19 +234,24 @@ def test_iteration_limit_in_the_complex64_phase(c0, cuda, fmt, limit):
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_folded_update_steps_match_one_step(c0, cuda, fmt, steps, prec):
     # folding consecutive steps of the all-shift update into one pass (the heads between
-    # defer theirs) follows the same recurrences: the driving sequence, the iteration count
-    # and every freeze are identical; the shifted solutions agree to rounding (FP64) or to
-    # the complex64 rounding of the shift directions (mixed), and fewer bytes move
+    # defer theirs, x_0's update included) follows the same recurrences: in FP64 the
+    # driving sequence, the iteration count and every freeze are identical; in a mixed
+    # solve the reliable updates recompute r from x_0, whose rounding depends on the
+    # folding, so the sequence after them agrees to rounding (iterations and freezes
+    # within 2); the solutions agree to rounding (FP64) or to the complex64 rounding of
+    # the directions (mixed), and fewer bytes move
     op = _op(c0, cuda)
     op.set_shifts(c0["sigma"])
     x1, i1 = op.solve(c0["b"], tol=1e-10, prec=prec, format=fmt, update_steps=1)
     x2, i2 = op.solve(c0["b"], tol=1e-10, prec=prec, format=fmt, update_steps=steps)
     assert i1["status"] == "ok" and i2["status"] == "ok"
-    assert i1["iters"] == i2["iters"] and i1["iters_fp64"] == i2["iters_fp64"]
-    assert np.array_equal(i1["freeze_iter"], i2["freeze_iter"])
+    assert i1["iters_fp64"] == i2["iters_fp64"]
     if prec == "fp64":
-        k0 = int(np.argmin(c0["sigma"]))
-        assert bool((x1[k0] == x2[k0]).all())  # the driving shift's x does not defer
+        assert i1["iters"] == i2["iters"]
+        assert np.array_equal(i1["freeze_iter"], i2["freeze_iter"])
+    else:
+        assert abs(i1["iters"] - i2["iters"]) <= 2
+        assert np.all(np.abs(i1["freeze_iter"] - i2["freeze_iter"]) <= 2)
     bar = 1e-11 if prec == "fp64" else 1e-6
     assert np.all(_rel(x2.cpu().numpy(), x1.cpu().numpy()) <= bar)
     assert np.all(i2["true_rel_res"] <= 1e-10)
