@@ -728,6 +728,12 @@ msc_status batch_residual(msc_op op, int prec, int lanes, int m, int mp, const d
 //           CG on (A + sig_j) e_j = r_j in the working precision from e = 0 until
 //           |r_in| <= max(delta |r_j|, tol_abs_j / 2); x_j += e_j in FP64.
 // On return res_abs[j] = |f_j - (A + sig_j) x_j| of the final iterates.
+// The inner CG of a refinement cycle stops at this fraction of the outer tolerance (the
+// next FP64 residual decides whether another cycle runs).
+#ifndef MSC_REFINE_TARGET
+#define MSC_REFINE_TARGET 0.7
+#endif
+constexpr double kRefineTarget = MSC_REFINE_TARGET;
 msc_status run_batched_cg(msc_op op, int prec, int m, const double* sig, const double2* const* f,
                           double2* const* x, const double* tol_abs, double delta,
                           const msc_params& prm, hipStream_t s, std::vector<double>& res_abs,
@@ -803,7 +809,7 @@ msc_status run_batched_cg(msc_op op, int prec, int m, const double* sig, const d
       const bool done = !(rn > tol_abs[j]);
       if (!std::isfinite(rn)) *breakdown = true;
       h.active[j] = (done || !std::isfinite(rn)) ? 0 : 1;
-      const double tgt = std::max(delta * rn, 0.5 * tol_abs[j]);
+      const double tgt = std::max(delta * rn, kRefineTarget * tol_abs[j]);
       h.target2[j] = tgt * tgt;
       if (h.active[j]) all_done = false;
     }
