@@ -256,9 +256,12 @@ __device__ void bk2_chunk(const BatchSys& S, BatchState* st, const int4& ch, int
   const double sw2q = q < nrhs ? st->sw_eps2[q] : 0.0;
   const int max_iter = st->max_iter;
   const int phase32 = st->phase32;
-  const bool act = live && k >= 1 && k < ns && st->active[lk];
-  const double z = act ? st->zeta[lk] : 1.0, zn = act ? st->zk[lk] : 1.0;
-  const double akq = act ? st->ak[lk] : 0.0;
+  // lane k = 0 of each rhs composes x_0's steps like a shift with zeta = 1 (step a_q,
+  // direction coefficient b): x_0 then takes them in the BK3 that applies
+  const bool drv = k == 0;
+  const bool act = live && (drv || (k >= 1 && k < ns && st->active[lk]));
+  const double z = (act && !drv) ? st->zeta[lk] : 1.0, zn = (act && !drv) ? st->zk[lk] : 1.0;
+  const double akq = act ? (drv ? aq : st->ak[lk]) : 0.0;
   // steps this rhs deferred in previous BK3s, composed (read before any lane writes the
   // state): x_k gained cx[0] p_k + sum_i cx[i+1] r_i, p_k now is cp[0] p_k + sum_i cp[i+1] r_i
   const int md = q < nrhs ? st->ndef[q] : 0;
@@ -267,7 +270,7 @@ __device__ void bk2_chunk(const BatchSys& S, BatchState* st, const int4& ch, int
   for (int i = 0; i <= kBatchMaxSteps; ++i) cx[i] = cp[i] = 0.0;
   cp[0] = 1.0;
   bool dact = false, dupd = false;
-  if (md > 0 && k >= 1 && k < ns) {
+  if (md > 0 && k < ns) {
 #pragma unroll
     for (int i = 0; i < kBatchMaxSteps; ++i) {
       if (i <= md) {
@@ -282,7 +285,10 @@ __device__ void bk2_chunk(const BatchSys& S, BatchState* st, const int4& ch, int
   const double bn = Rn / Rq;
   bool keep_p = false;
   double bkq = 0.0;
-  if (act) {
+  if (act && drv) {
+    bkq = bn;
+    keep_p = true;
+  } else if (act) {
     const double ratio = zn / z;
     bkq = bn * ratio * ratio;
     st->bk[lk] = bkq;
@@ -339,7 +345,7 @@ __device__ void bk2_chunk(const BatchSys& S, BatchState* st, const int4& ch, int
   dact = dact || act;
   dupd = dupd || (act && keep_p);
   const bool defer = live && !halt_q && !switching && defer_ok && md + 1 < steps;
-  const bool listed = !defer && dact;
+  const bool listed = !defer && dact && !drv;
   st->upd_x[lk] = listed ? 1 : 0;
   st->upd_p[lk] = (listed && dupd) ? 1 : 0;
 #pragma unroll
@@ -364,6 +370,8 @@ __device__ void bk2_chunk(const BatchSys& S, BatchState* st, const int4& ch, int
       const int ph = phase32 ? 1 : 0;
       st->n_upd[q][ph] += __popcll((lm >> (q * kBatchMaxShifts)) & 0xffffull);
       st->n_kept[q][ph] += defer ? 1 : md;
+      st->n_x0[q][ph] += defer ? 0 : 1;
+      st->n_k0[q][ph] += (defer && md == 0) ? 1 : 0;
     }
   }
   if (lk == 0) {
@@ -385,7 +393,7 @@ struct K3Coef {
   double cx[kBatchMaxSteps][kQK], cp[kBatchMaxSteps + 1][kQK];
   int upd_x[kQK], upd_p[kQK];
   int orig[kBatchMaxShifts];
-  double a[kBatchMaxRhs], bnew[kBatchMaxRhs];
+  double bnew[kBatchMaxRhs];
   int x0_upd[kBatchMaxRhs], m[kBatchMaxRhs], keep[kBatchMaxRhs];
   int nrhs, ns;
 };
@@ -405,7 +413,6 @@ __device__ void bk3_chunk(const BatchSys& S, const BatchState* st, const int4& c
   }
   if (tid < kBatchMaxShifts) cf.orig[tid] = st->orig[tid];
   if (tid < kBatchMaxRhs) {
-    cf.a[tid] = st->a[tid];
     cf.bnew[tid] = st->b_new[tid];
     cf.x0_upd[tid] = st->x0_upd[tid];
     cf.m[tid] = st->m[tid];
@@ -433,20 +440,33 @@ __device__ void bk3_chunk(const BatchSys& S, const BatchState* st, const int4& c
     const double2 rd = to_d(r[idx]);
     const double2 pd = to_d(p[idx]);
     if (q < cf.nrhs && cf.x0_upd[q]) {
-      double2* x0 = S.x + (int64_t(q) * ns + cf.orig[0]) * n + i;
-      const double a = cf.a[q];
-      double2 xv = *x0;
-      xv.x = fma(a, pd.x, xv.x);
-      xv.y = fma(a, pd.y, xv.y);
-      *x0 = xv;
-      // a deferring BK3 keeps r; the one that applies reads the m kept residuals (with
-      // m = 0 the multiply-adds round exactly as one step)
+      // a deferring BK3 keeps r (the first of a cycle p too); the one that applies reads
+      // the m kept residuals and updates x_0 and the shifts (with m = 0 the multiply-adds
+      // round exactly as one step)
       const int mq = cf.m[q], kq = cf.keep[q];
+      cplx<R>* __restrict__ pkeep0 = static_cast<cplx<R>*>(S.pkeep0);
       if (kq >= 0) static_cast<cplx<R>*>(S.rkeep[kq])[idx] = r[idx];
+      if (kq == 0) pkeep0[idx] = p[idx];
       double2 rk[kBatchMaxSteps - 1];
 #pragma unroll
       for (int kk = 0; kk < kBatchMaxSteps - 1; ++kk)
         rk[kk] = kk < mq ? to_d(static_cast<const cplx<R>*>(S.rkeep[kk])[idx]) : double2{0.0, 0.0};
+      if (kq < 0) {
+        double2* x0 = S.x + (int64_t(q) * ns + cf.orig[0]) * n + i;
+        const int l0 = q * kBatchMaxShifts;
+        const double2 p1 = mq > 0 ? to_d(pkeep0[idx]) : pd;
+        double2 xv = *x0;
+#pragma unroll
+        for (int kk = kBatchMaxSteps - 2; kk >= 0; --kk) {
+          if (kk < mq) {
+            xv.x = fma(cf.cx[kk + 1][l0], rk[kk].x, xv.x);
+            xv.y = fma(cf.cx[kk + 1][l0], rk[kk].y, xv.y);
+          }
+        }
+        xv.x = fma(cf.cx[0][l0], p1.x, xv.x);
+        xv.y = fma(cf.cx[0][l0], p1.y, xv.y);
+        *x0 = xv;
+      }
       constexpr bool same = std::is_same<R, W>::value;
       // two shifts at a time, their loads issued before either store (x_k and p_k of
       // different shifts share one array each, so the compiler cannot reorder); frozen

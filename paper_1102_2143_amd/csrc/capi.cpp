@@ -1038,7 +1038,7 @@ struct BatchRun {
       const size_t n = size_t(ops[s]->n), nk = std::max<size_t>(ops[s]->sigma.size() - 1, 1);
       const size_t nch = (n + kBatchChunkRows - 1) / kBatchChunkRows;
       off[s] = bytes;
-      bytes += (4 + kBatchMaxSteps - 1) * align(sizeof(double2) * n * rr) +
+      bytes += (5 + kBatchMaxSteps - 1) * align(sizeof(double2) * n * rr) +
                align(sizeof(double2) * n * rr * nk) +
                3 * align(sizeof(float2) * n * rr) + align(sizeof(float2) * n * rr * nk) +
                align(sizeof(double) * nch * kBatchMaxRhs);
@@ -1107,6 +1107,7 @@ struct BatchRun {
       S.t64 = reinterpret_cast<double2*>(take(sizeof(double2) * n * rr));
       S.u64 = reinterpret_cast<double2*>(take(sizeof(double2) * n * rr));
       for (auto& q : S.rkeep) q = take(sizeof(double2) * n * rr);
+      S.pkeep0 = take(sizeof(double2) * n * rr);
       S.pk64 = reinterpret_cast<double2*>(take(sizeof(double2) * n * rr * nk));
       S.r32 = reinterpret_cast<float2*>(take(sizeof(float2) * n * rr));
       S.p32 = reinterpret_cast<float2*>(take(sizeof(float2) * n * rr));
@@ -1436,15 +1437,19 @@ struct BatchRun {
           const int it = h.iter[q], i64 = std::min(I.iters_fp64, it);
           const double act64 = h.n_upd[q][0], act32 = h.n_upd[q][1];
           const double kept64 = h.n_kept[q][0], kept32 = h.n_kept[q][1];
+          // x_0 read and written by the BK3s that applied, p kept and read back once per
+          // cycle of deferred steps
+          const double x064 = 32.0 * h.n_x0[q][0] + 2.0 * 16.0 * h.n_k0[q][0];
+          const double x032 = 32.0 * h.n_x0[q][1] + 2.0 * 8.0 * h.n_k0[q][1];
           const double nn = double(n), nz = double(op->nnz), nzh = double(op->nnz_h);
           const double ib = index_bytes(sys[s].sell, sys[s].s64);
           const double ibh = index_bytes(sys[s].sell, sys[s].sh64);
           I.alg_bytes = iter_bytes(op->kind, MSC_PREC_FP64, nn,
                                    mat_bytes(op->kind, MSC_PREC_FP64, nn, nz, nzh, ib, ibh, false),
-                                   act64, i64, kept64) +
+                                   act64, i64, kept64, x064) +
                         iter_bytes(op->kind, MSC_PREC_MIXED, nn,
                                    mat_bytes(op->kind, MSC_PREC_MIXED, nn, nz, nzh, ib, ibh, false),
-                                   act32, it - i64, kept32) -
+                                   act32, it - i64, kept32, x032) -
                         (double(nrhs[s]) - 1.0) / double(nrhs[s]) *
                             ((nz * (16.0 + ib) + nzh * (16.0 + ibh)) * i64 +
                              (nz * (8.0 + ib) + nzh * (8.0 + ibh)) * (it - i64));

@@ -560,10 +560,12 @@ struct BatchState {
   double dcp[kBatchMaxSteps][kBatchMaxRhs * kBatchMaxShifts];
   int dact[kBatchMaxRhs * kBatchMaxShifts], dupd[kBatchMaxRhs * kBatchMaxShifts];
   // per right-hand side: steps deferred so far, BK3's kept residuals to read (m) and the
-  // slot it keeps r in (-1: none), and per phase (FP64, complex64) the shift-vector
-  // updates and kept-r passes
+  // slot it keeps r in (-1: none; slot 0 also keeps p, the direction x_0's deferred steps
+  // start from), and per phase (FP64, complex64) the shift-vector updates, kept-r
+  // passes, BK3s that updated x_0 and BK3s that kept p
   int ndef[kBatchMaxRhs], m[kBatchMaxRhs], keep[kBatchMaxRhs];
   int n_upd[kBatchMaxRhs][2], n_kept[kBatchMaxRhs][2];
+  int n_x0[kBatchMaxRhs][2], n_k0[kBatchMaxRhs][2];
   // per system
   double s[kBatchMaxShifts];
   int orig[kBatchMaxShifts];
@@ -586,6 +588,7 @@ struct BatchSys {
   float2 *r32, *p32, *t32, *pk32;
   void* rkeep[kBatchMaxSteps - 1];  // n x RR each: residuals kept by deferring BK3s
                                // (complex128, or complex64 in the second phase)
+  void* pkeep0;           // n x RR: p at the first deferred step (x_0's composition)
   BatchState* st;
   double* partial;
   unsigned* tickets;      // 8 counters

@@ -126,9 +126,11 @@ def test_batch_result_is_independent_of_companions(cuda):
 @pytest.mark.parametrize("steps", [2, 4, 8])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_batch_folded_steps_match_one_step(cuda, prec, steps):
-    # the batch defers shifted updates and folds up to `steps` of them (at most 4) into
-    # one pass: the driving sequences, iteration counts and freezes are those of one step
-    # per iteration, the solutions agree to rounding, and fewer bytes move
+    # the batch defers shifted updates (x_0's included) and folds up to `steps` of them (at
+    # most 4) into one pass: in FP64 the driving sequences, iteration counts and freezes
+    # are those of one step per iteration; in a mixed solve the reliable updates recompute
+    # r from x_0, whose rounding depends on the folding, so they agree within 2; the
+    # solutions agree to rounding, and fewer bytes move
     print(f"[gpu] batched {steps} folded steps {prec}", flush=True)
     from paper_1102_2143_amd import solve_batched
     systems = _small_batch()
@@ -138,8 +140,12 @@ def test_batch_folded_steps_match_one_step(cuda, prec, steps):
     x2, i2, s2 = solve_batched(ops, bs, tol=1e-10, prec=prec, update_steps=steps)
     assert s1 == "ok" and s2 == "ok"
     for a, b in zip(i1, i2):
-        assert a["iters"] == b["iters"]
-        assert np.array_equal(a["freeze_iter"], b["freeze_iter"])
+        if prec == "fp64":
+            assert a["iters"] == b["iters"]
+            assert np.array_equal(a["freeze_iter"], b["freeze_iter"])
+        else:
+            assert abs(a["iters"] - b["iters"]) <= 2
+            assert np.all(np.abs(a["freeze_iter"] - b["freeze_iter"]) <= 2)
         assert np.all(b["true_rel_res"] <= 1e-10)
     bar = 1e-11 if prec == "fp64" else 1e-6
     for a, b in zip(x1, x2):
