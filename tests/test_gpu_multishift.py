@@ -269,6 +269,25 @@ def test_update_steps_out_of_range_rejected(c0, cuda):
     op.close()
 
 
+@pytest.mark.parametrize("every", [3, 7])
+@pytest.mark.parametrize("fmt", ["sell", "csr"])
+def test_forced_reliable_updates_with_folded_steps(c0, cuda, every, fmt):
+    # reliable updates on a period that cuts the folding cycles (3, 7 against 8 steps):
+    # the head before each one applies the pending steps, x_0 included, so the update
+    # reads the current x_0; the solutions match the oracle run to 1e-13
+    print(f"[gpu] forced reliable updates every {every} {fmt}", flush=True)
+    op = _op(c0, cuda)
+    op.set_shifts(c0["sigma"])
+    x, info = op.solve(c0["b"], tol=1e-12, prec="mixed", format=fmt, update_steps=8,
+                       reliable_every=every, switch_tol=1e-2)
+    ref = O.cg_m(c0["apply"], c0["b"], c0["sigma"], tol=1e-13)
+    assert info["status"] == "ok"
+    assert info["n_reliable"] >= 3
+    assert np.all(info["true_rel_res"] <= 1e-12)
+    assert np.all(_rel(x.cpu().numpy(), ref["x"]) <= 1e-8)
+    op.close()
+
+
 def test_refinement_completes_a_truncated_sequence(c0, cuda):
     # three multishift iterations, then the FP64 batched refinement takes every shift
     # to tol from those iterates
