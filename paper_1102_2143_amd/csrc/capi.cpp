@@ -563,7 +563,9 @@ msc_status run_multishift(msc_op op, const double* d_b, double* d_x, const msc_p
       // the head's update mode and the shifts it listed, as recorded by the head itself
       const bool pending = !(L == 0 || (ph32 && L == launched_at_switch));
       const int act = h.smp_nact[q];
-      const int kept = h.smp_mode[q] == 1 ? 1 : h.smp_m[q];
+      // an applying head reads the m kept residuals (the deferring ones leave theirs in
+      // the ring)
+      const int kept = h.smp_mode[q] == 1 ? 0 : h.smp_m[q];
       const int phq = ph32 ? MSC_PREC_MIXED : MSC_PREC_FP64;
       const double wq = ph32 ? 8.0 : 16.0;
       const double x0b = h.smp_mode[q] == 0 ? 32.0 + (h.smp_m[q] > 0 ? wq : 0.0)
@@ -595,7 +597,7 @@ msc_status run_multishift(msc_op op, const double* d_b, double* d_x, const msc_p
 
   // shift-vector updates and kept-r passes counted by the heads, per phase
   const double act64 = h.n_shift_upd[0], act32 = h.n_shift_upd[1];
-  const double kept64 = h.n_defer[0] + h.n_two[0], kept32 = h.n_defer[1] + h.n_two[1];
+  const double kept64 = h.n_two[0], kept32 = h.n_two[1];
   const double nn = double(op->n), nz = double(op->nnz), nzh = double(op->nnz_h);
   // x_0 (and its kept direction) per phase: applying heads read and write x_0, and each
   // cycle with deferred steps writes and reads the kept direction once

@@ -87,7 +87,7 @@ struct SolveState {
   int freeze;
   int n_reliable;
   int kstatus;       // 1: a K2 found p^H (A + sigma0) p <= 0
-  int pad_;
+  int rslot;         // residual slot a halting head read (where r stays: no K2 follows it)
   double R_ru;       // |r|^2 right after the last reliable update (or the precision switch)
   double s[kMaxShifts];         // sigma_j - sigma0
   double zeta_prev[kMaxShifts]; // zeta_j^(n-1)
@@ -105,8 +105,8 @@ struct SolveState {
   int smp_nact[kMaxSamples];
   int smp_m[kMaxSamples];
   // per phase (0: FP64, 1: complex64): x_j/p_j row updates performed (in units of n
-  // rows), heads that deferred their update, passes over kept residuals (a deferring
-  // head writes one, an applying head reads the ones pending), heads that applied the
+  // rows), heads that deferred their update, passes over kept residuals (an applying head
+  // reads the ones pending from the ring), heads that applied the
   // update (x_0 read and written), and heads that kept the direction for x_0's deferred
   // steps (the applying head of that cycle reads it back)
   int n_shift_upd[2];
@@ -340,7 +340,11 @@ struct MsArgs {
   double2* x;            // caller's x, shift-major, caller order
   void* r; void* t; void* pk;
   void* pb[2];           // the two direction buffers (p of consecutive iterations)
-  void* rkeep[kMaxSteps - 1];  // residuals kept by heads that defer the all-shift update
+  // the residual lives in a ring of kMaxSteps slots: slot 0 is r, slot k >= 1 is
+  // rkeep[k - 1]; a head with m steps deferred reads r from slot m, so the m residuals of
+  // the heads that deferred stay in slots 0..m-1 without a copy, and K2 writes the next
+  // residual into the slot of the next head (0 after a head that applied)
+  void* rkeep[kMaxSteps - 1];
   void* pkeep0;          // the direction p at the first deferred step (x_0's deferred update)
   int* hflag;            // host-coherent word: halt | switch_req << 1 of the next state
   int steps;             // steps of the all-shift update folded into one pass (1..kMaxSteps)

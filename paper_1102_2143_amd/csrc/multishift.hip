@@ -66,6 +66,16 @@ template <> __device__ __forceinline__ Sell<double2> pick_shm<double>(const MsAr
 
 // Pairs per round trip of the sliced ELLPACK row product (register budget: complex64
 // keeps a 24-entry staggered row in flight at once, complex128 half of it).
+// Slot k of the residual ring (slot 0: a.r, slot k >= 1: a.rkeep[k - 1]); k is uniform.
+template <class R>
+__device__ __forceinline__ cplx<R>* rslot(const MsArgs& a, int k) {
+  void* q = a.r;
+#pragma unroll
+  for (int j = 1; j < kMaxSteps; ++j)
+    if (k == j) q = a.rkeep[j - 1];
+  return static_cast<cplx<R>*>(q);
+}
+
 template <class R> constexpr int sell_kp();
 template <> constexpr int sell_kp<float>() { return MSC_SELL_KP32; }
 template <> constexpr int sell_kp<double>() { return MSC_SELL_KP64; }
@@ -416,7 +426,6 @@ struct Plan {
   int nact;
   int mode;                  // 0: apply (the current step and m deferred ones); 1: defer
   int m;                     // kept residuals read (mode 0)
-  int keep;                  // slot the current residual is kept in (mode 1), -1: none
   int pending;               // the update runs in this head
   int ok;                    // 0: breakdown, the head stops
   int spmv;                  // 1: this head also computes t = M p
@@ -426,8 +435,9 @@ struct Plan {
 // deferred ones, the next step adds a_j p_j to x_j and turns p_j into
 // zeta_j' r + b_j p_j (r: that step's residual), unless j freezes there (p_j stays); a
 // frozen shift takes no further step.  The driving system (lane 0) composes the same way
-// with zeta = 1, a_0 = a and b_0 = b: its x is x_0, its direction p.  A head defers (keeps
-// its r, touches no x_j, p_j and not x_0) while fewer than `steps` - 1 steps are pending,
+// with zeta = 1, a_0 = a and b_0 = b: its x is x_0, its direction p.  A head defers (its r
+// stays in its ring slot; it touches no x_j, p_j and not x_0) while fewer than `steps` - 1
+// steps are pending,
 // its iteration continues and no reliable update (which reads x_0) runs after it;
 // otherwise it applies all of them in one pass.
 template <class T>
@@ -525,7 +535,6 @@ __device__ void head_plan(const MsArgs& a, const Early& e, Plan& pl) {
       pl.nact = nlist;
       pl.mode = mode;
       pl.m = mode == 0 ? m : 0;
-      pl.keep = mode == 1 ? m : -1;
       pl.pending = pending;
       pl.ok = ok ? 1 : 0;
       pl.spmv = cont ? 1 : 0;
@@ -582,6 +591,7 @@ __device__ void head_plan(const MsArgs& a, const Early& e, Plan& pl) {
           nx.iter = it;
           nx.status = 0;
           nx.halt = (done || sw) ? 1 : 0;
+          if (done || sw) st->rslot = m;  // no K2 follows: r stays in this head's slot
           nx.switch_req = sw ? 1 : 0;
           nx.pcur = pending ? rs.pcur ^ 1 : rs.pcur;
           store_host_flag(a.hflag, ((done || sw) ? 1 : 0) | (sw ? 2 : 0));
@@ -621,10 +631,11 @@ __device__ void carry_state(const MsArgs& a) {
 }
 
 // The pending update of row i: the listed shifts' x_j and p_j and x_0 as the plan
-// composes them (the current step and the m deferred ones, reading the m kept residuals;
-// a deferring head keeps r, and the first of a cycle p, instead and touches neither x_0
-// nor any shift), then the new direction r + b p, which is stored in the other direction
-// buffer and returned.  rr, pp: the row's r and p (already loaded).
+// composes them (the current step and the m deferred ones, reading the residuals of the
+// m deferring heads from ring slots 0..m-1; a deferring head touches neither x_0 nor any
+// shift, and the first of a cycle keeps p), then the new direction r + b p, which is
+// stored in the other direction buffer and returned.  rr, pp: the row's r and p (already
+// loaded).
 template <class R>
 __device__ __forceinline__ cplx<R> update_row(const MsArgs& a, const Plan& pl, int64_t i,
                                               const cplx<R>& rr, const cplx<R>& pp,
@@ -634,13 +645,13 @@ __device__ __forceinline__ cplx<R> update_row(const MsArgs& a, const Plan& pl, i
   cplx<R>* __restrict__ pkeep0 = static_cast<cplx<R>*>(a.pkeep0);
   double2* __restrict__ x = a.x;
   const double2 rd = to_d(rr), pd = to_d(pp);
-  if (pl.keep >= 0) st_stream(&static_cast<cplx<R>*>(a.rkeep[pl.keep])[i], rr);
   if (pl.keep0) st_stream(&pkeep0[i], pp);
-  // kept residuals (zero beyond m, where the coefficients are zero too)
+  // the residuals of the m heads that deferred, in ring slots 0..m-1 (zero beyond m,
+  // where the coefficients are zero too)
   double2 rk[kMaxSteps - 1];
 #pragma unroll
   for (int k = 0; k < kMaxSteps - 1; ++k)
-    rk[k] = k < pl.m ? to_d(ld_stream(&static_cast<const cplx<R>*>(a.rkeep[k])[i])) : double2{0.0, 0.0};
+    rk[k] = k < pl.m ? to_d(ld_stream(&rslot<R>(a, k)[i])) : double2{0.0, 0.0};
   const int m = pl.m;
   if (pl.mode == 0) {
     // x_0: with one step (m = 0) the fused multiply-add rounds exactly as x_0 += a p
@@ -726,7 +737,7 @@ __global__ __launch_bounds__(kBlock) void k_update(MsArgs a) {
   if (rs.pending) load_early(region(a, 1), a.gk2, e);
   const int pc = rs.pcur;
   const int64_t n = a.n;
-  const cplx<R>* __restrict__ rv = static_cast<const cplx<R>*>(a.r);
+  const cplx<R>* __restrict__ rv = rslot<R>(a, rs.ndef);
   const cplx<R>* __restrict__ pv = static_cast<const cplx<R>*>(a.pb[pc]);
   cplx<R>* __restrict__ pnew = static_cast<cplx<R>*>(a.pb[pc ^ 1]);
   double2* __restrict__ x0 = a.x + int64_t(st->orig[0]) * n;
@@ -763,7 +774,7 @@ __global__ __launch_bounds__(kBlock) void k1_fused(MsArgs a) {
   if (pending) load_early(region(a, 1), a.gk2, e);
   const int pc = rs.pcur;
   const Sell<cplx<R>> m = pick_sm<R>(a);
-  const cplx<R>* __restrict__ rv = static_cast<const cplx<R>*>(a.r);
+  const cplx<R>* __restrict__ rv = rslot<R>(a, rs.ndef);
   const cplx<R>* __restrict__ pv = static_cast<const cplx<R>*>(a.pb[pc]);
   cplx<R>* __restrict__ pnew = static_cast<cplx<R>*>(a.pb[pc ^ 1]);
   cplx<R>* __restrict__ t = static_cast<cplx<R>*>(a.t);
@@ -864,7 +875,9 @@ __global__ __launch_bounds__(kBlock) void k2_mhm(MsArgs a) {
   const Csr<cplx<R>> mh = pick_mh<R>(a);
   const cplx<R>* __restrict__ t = static_cast<const cplx<R>*>(a.t);
   const cplx<R>* __restrict__ p = static_cast<const cplx<R>*>(a.pb[ns.pcur]);
-  cplx<R>* __restrict__ r = static_cast<cplx<R>*>(a.r);
+  // the residual moves from this head's ring slot to the next one's (in place when equal)
+  const cplx<R>* rin = rslot<R>(a, st->rot[a.par].ndef);
+  cplx<R>* r = rslot<R>(a, ns.ndef);
   const double sigma0 = st->sigma0;
   constexpr int GPB = kBlock / L;
   const int lane = threadIdx.x % L, grp = threadIdx.x / L;
@@ -873,7 +886,7 @@ __global__ __launch_bounds__(kBlock) void k2_mhm(MsArgs a) {
   double acc = 0.0;
   auto epilogue = [&](int64_t row, const cplx<R>& q) {
     const double2 pr = to_d(p[row]);
-    const double2 rr = to_d(r[row]);
+    const double2 rr = to_d(rin[row]);
     const double2 qd = to_d(q);
     double2 nr;
     nr.x = rr.x - step * (qd.x + sigma0 * pr.x);
@@ -906,7 +919,9 @@ __global__ __launch_bounds__(kBlock) void k2_sell(MsArgs a) {
   const Sell<cplx<R>> mh = pick_shm<R>(a);
   const cplx<R>* __restrict__ t = static_cast<const cplx<R>*>(a.t);
   const cplx<R>* __restrict__ p = static_cast<const cplx<R>*>(a.pb[ns.pcur]);
-  cplx<R>* __restrict__ r = static_cast<cplx<R>*>(a.r);
+  // the residual moves from this head's ring slot to the next one's (in place when equal)
+  const cplx<R>* rin = rslot<R>(a, st->rot[a.par].ndef);
+  cplx<R>* r = rslot<R>(a, ns.ndef);
   const double sigma0 = st->sigma0;
   constexpr int SPB = kBlock / kSlice;
   const int lane = threadIdx.x % kSlice;
@@ -923,7 +938,7 @@ __global__ __launch_bounds__(kBlock) void k2_sell(MsArgs a) {
     const cplx<R> tr = t[rr];
     Row o;
     o.p = ld_stream(&p[rr]);
-    o.r = ld_stream(&r[rr]);
+    o.r = ld_stream(&rin[rr]);
     const cplx<R> d = mh.diag[rr];
     o.q = sell_row<R>(mh, t, sl, lane);
     cfma<R>(o.q, d, tr);
@@ -984,7 +999,7 @@ __global__ __launch_bounds__(kBlock, MSC_SITE_HEAD_WPE) void k1_site(MsArgs a) {
   Early e;
   if (pending) load_early(region(a, 1), a.gk2, e);
   const int pc = rs.pcur;
-  const cplx<R>* __restrict__ rv = static_cast<const cplx<R>*>(a.r);
+  const cplx<R>* __restrict__ rv = rslot<R>(a, rs.ndef);
   const cplx<R>* __restrict__ pv = static_cast<const cplx<R>*>(a.pb[pc]);
   cplx<R>* __restrict__ pnew = static_cast<cplx<R>*>(a.pb[pc ^ 1]);
   cplx<R>* __restrict__ t = static_cast<cplx<R>*>(a.t);
@@ -1063,7 +1078,9 @@ __global__ __launch_bounds__(kBlock, MSC_SITE_K2_WPE) void k2_site(MsArgs a) {
   load_early(region(a, 0), a.gk1, e);
   const cplx<R>* __restrict__ t = static_cast<const cplx<R>*>(a.t);
   const cplx<R>* __restrict__ p = static_cast<const cplx<R>*>(a.pb[ns.pcur]);
-  cplx<R>* __restrict__ r = static_cast<cplx<R>*>(a.r);
+  // the residual moves from this head's ring slot to the next one's (in place when equal)
+  const cplx<R>* rin = rslot<R>(a, st->rot[a.par].ndef);
+  cplx<R>* r = rslot<R>(a, ns.ndef);
   const Stencil<cplx<R>> w = pick_w<R>(a);
   const uint32_t vol = uint32_t(w.vol);
   const int64_t nblk = (int64_t(vol) + kSiteBlock - 1) / kSiteBlock;
@@ -1094,7 +1111,7 @@ __global__ __launch_bounds__(kBlock, MSC_SITE_K2_WPE) void k2_site(MsArgs a) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const double2 pr = to_d(p[r0 + c]);
-      const double2 rr = to_d(r[r0 + c]);
+      const double2 rr = to_d(rin[r0 + c]);
       const double2 qd = to_d(o.q[c]);
       double2 nr;
       nr.x = rr.x - step * (qd.x + sigma0 * pr.x);
@@ -1130,13 +1147,15 @@ __global__ __launch_bounds__(kBlock) void k2_herm(MsArgs a) {
   if (!k2_step(a, e, step)) return;  // breakdown: every workgroup sees the same P
   const cplx<R>* __restrict__ t = static_cast<const cplx<R>*>(a.t);
   const cplx<R>* __restrict__ p = static_cast<const cplx<R>*>(a.pb[ns.pcur]);
-  cplx<R>* __restrict__ r = static_cast<cplx<R>*>(a.r);
+  // the residual moves from this head's ring slot to the next one's (in place when equal)
+  const cplx<R>* rin = rslot<R>(a, st->rot[a.par].ndef);
+  cplx<R>* r = rslot<R>(a, ns.ndef);
   const double sigma0 = st->sigma0;
   int64_t beg, end;
   block_range(a.n, kBlock, beg, end);
   double acc = 0.0;
   for (int64_t i = beg + threadIdx.x; i < end; i += kBlock) {
-    const double2 pr = to_d(p[i]), rr = to_d(r[i]), td = to_d(t[i]);
+    const double2 pr = to_d(p[i]), rr = to_d(rin[i]), td = to_d(t[i]);
     double2 nr;
     nr.x = rr.x - step * (td.x + sigma0 * pr.x);
     nr.y = rr.y - step * (td.y + sigma0 * pr.y);
@@ -1189,7 +1208,8 @@ __global__ __launch_bounds__(kBlock) void k_init(MsArgs a) {
 __global__ __launch_bounds__(kBlock) void k_switch(MsArgs a64, MsArgs a32, int ns) {
   const int64_t n = a64.n;
   const int pc = a64.st->rot[a64.par].pcur;  // the direction buffer in use carries over
-  const double2* __restrict__ r = static_cast<const double2*>(a64.r);
+  // r stays in the ring slot the halting (switching) head read; slot 0 of complex64
+  const double2* __restrict__ r = rslot<double>(a64, a64.st->rslot);
   const double2* __restrict__ p = static_cast<const double2*>(a64.pb[pc]);
   const double2* __restrict__ pk = static_cast<const double2*>(a64.pk);
   float2* __restrict__ r32 = static_cast<float2*>(a32.r);
@@ -1272,7 +1292,7 @@ __global__ __launch_bounds__(kBlock) void k_ru_second(MsArgs a) {
   SolveState* st = a.st;
   if (!ru_due(a)) return;
   const double2* __restrict__ x0 = a.x + int64_t(st->orig[0]) * a.n;
-  cplx<R>* __restrict__ r = static_cast<cplx<R>*>(a.r);
+  cplx<R>* __restrict__ r = rslot<R>(a, st->rot[a.par].ndef);  // r_i's ring slot
   const double sigma0 = st->sigma0;
   constexpr int GPB = kBlock / L;
   const int lane = threadIdx.x % L, grp = threadIdx.x / L;
@@ -1318,7 +1338,7 @@ __global__ __launch_bounds__(kBlock) void k_ru_second_s(MsArgs a) {
   SolveState* st = a.st;
   if (!ru_due(a)) return;
   const double2* __restrict__ x0 = a.x + int64_t(st->orig[0]) * a.n;
-  cplx<R>* __restrict__ r = static_cast<cplx<R>*>(a.r);
+  cplx<R>* __restrict__ r = rslot<R>(a, st->rot[a.par].ndef);  // r_i's ring slot
   const double sigma0 = st->sigma0;
   constexpr int SPB = kBlock / kSlice;
   const int lane = threadIdx.x % kSlice;
@@ -1380,7 +1400,7 @@ __global__ __launch_bounds__(kBlock) void k_ru_second_site(MsArgs a) {
   if (!ru_due(a)) return;
   const double2* __restrict__ x0 = a.x + int64_t(st->orig[0]) * a.n;
   const double2* __restrict__ u = a.t64;
-  cplx<R>* __restrict__ r = static_cast<cplx<R>*>(a.r);
+  cplx<R>* __restrict__ r = rslot<R>(a, st->rot[a.par].ndef);  // r_i's ring slot
   const double sigma0 = st->sigma0;
   const Stencil<double2> w = a.w64;
   const uint32_t vol = uint32_t(w.vol);
