@@ -161,15 +161,20 @@ template <class V> double index_bytes(bool sell, const Sell<V>& m) {
 #ifndef MSC_TILE_SPAN
 #define MSC_TILE_SPAN 48
 #endif
-// The links' kernels sweep blocks of 64 sites (192 rows), with their own span.
+// The links' kernels sweep blocks of 64 sites (192 rows), with their own spans: the
+// complex64 ones, and the FP64 ones (twice the bytes per site in flight).
 #ifndef MSC_TILE_SPAN_SITES
 #define MSC_TILE_SPAN_SITES 16
+#endif
+#ifndef MSC_TILE_SPAN_SITES64
+#define MSC_TILE_SPAN_SITES64 32
 #endif
 #ifndef MSC_C64_TWO_ROWS
 #define MSC_C64_TWO_ROWS 1
 #endif
 constexpr int64_t kTileSpan = MSC_TILE_SPAN;
 constexpr int64_t kTileSpanSites = MSC_TILE_SPAN_SITES;
+constexpr int64_t kTileSpanSites64 = MSC_TILE_SPAN_SITES64;
 constexpr bool kC64TwoRows = MSC_C64_TWO_ROWS != 0;
 SweepOrder lattice_order(int64_t nslices, int64_t s1, int64_t s2, int64_t span = kTileSpan) {
   SweepOrder o{0, 0, 0, 0};
@@ -403,7 +408,7 @@ msc_status run_multishift(msc_op op, const double* d_b, double* d_x, const msc_p
                 (prm.format == MSC_FORMAT_AUTO || prm.format == MSC_FORMAT_STENCIL)
                     ? (op->two_rows ? 2 : 3) : 0;
   if (a64.stencil == 2) a64.w64 = op->wc64;
-  a64.ord = a64.stencil ? op->order_sites : op->order;
+  a64.ord = a64.stencil ? op->order_sites64 : op->order;
   a64.ord.on = (prm.sweep == 0 && a64.ord.s1 > 0) ? 1 : 0;
   if (prm.format == MSC_FORMAT_SELL32 && op->sell) {
     const SellStore &sm = op->sell_m, &sh = op->sell_mh;
@@ -416,6 +421,10 @@ msc_status run_multishift(msc_op op, const double* d_b, double* d_x, const msc_p
   }
   const double ib = index_bytes(a64.sell, a64.s64), ibh = index_bytes(a64.sell, a64.sh64);
   MsArgs a32 = a64;
+  if (a32.stencil != 0) {  // the complex64 kernels' tile span
+    a32.ord = op->order_sites;
+    a32.ord.on = a64.ord.on;
+  }
   // the complex64 phase reads two rows per SU(3) link too, unless told otherwise
   if (a32.stencil == 2) {
     if (kC64TwoRows)
@@ -1997,6 +2006,10 @@ msc_status msc_op_create_staggered(msc_op* out, const int32_t* dims, double mass
   op->order_sites = splane % 64 == 0
                         ? lattice_order((geo.vol + 63) / 64, splane / 64, sslab / 64, kTileSpanSites)
                         : SweepOrder{0, 0, 0, 0};
+  op->order_sites64 = splane % 64 == 0
+                          ? lattice_order((geo.vol + 63) / 64, splane / 64, sslab / 64,
+                                          kTileSpanSites64)
+                          : SweepOrder{0, 0, 0, 0};
   rc = refresh_two_rows(op, reinterpret_cast<const double2*>(d_links), s);
   if (rc != MSC_OK) {
     msc_op_destroy(op);

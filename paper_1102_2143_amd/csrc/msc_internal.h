@@ -267,7 +267,8 @@ struct msc_op_s {
   double* adj_small = nullptr;   // 256 doubles: Gram sums and shift factors
   int lanes64 = 0, lanes32 = 0;  // chosen lanes per row (0 = not yet tuned)
   msc::SweepOrder order{0, 0, 0, 0};  // lattice structure of the rows (zeros: none found)
-  msc::SweepOrder order_sites{0, 0, 0, 0};  // the same in blocks of 64 sites (links' kernels)
+  msc::SweepOrder order_sites{0, 0, 0, 0};    // the same in blocks of 64 sites (links'
+  msc::SweepOrder order_sites64{0, 0, 0, 0};  // kernels; complex64 and FP64 tile spans)
   int64_t rowhist[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // rows by length: 0, 1, 2-3, ..., >= 64
   bool stencil = false;          // matrix-free staggered operator (links kept below)
   msc::Stencil<double2> w64;     // W_mu(x) = eta_mu(x)/2 U_mu(x), complex128 and
