@@ -158,6 +158,9 @@ __device__ __forceinline__ cplx<R> next_dir(double b, const cplx<R>& r, const cp
 #ifndef MSC_SITE_SB
 #define MSC_SITE_SB 1
 #endif
+// Dynamic LDS of the complex64 site K2 (bytes per workgroup, within the 64 KB a
+// workgroup may hold): three workgroups fit a CU's 160 KB, four do not.
+constexpr size_t kC64K2Lds = size_t(48) << 10;
 
 // Pairs per round trip when each entry gathers two vectors (MSC_SELL_KPN32 / 64).
 #ifndef MSC_SELL_KPN32
@@ -1637,7 +1640,7 @@ int grid_rows(int64_t n, int rows_per_pass, int cap = kMaxGrid) {
 // rounded down to a multiple of the XCD count: the grid of a launch whose waves sweep a
 // lattice order in step (a larger grid would leave the later workgroups' positions to a
 // second round).  Cached per device and kernel.
-int resident_grid(const void* kern, int cap) {
+int resident_grid(const void* kern, int cap, size_t lds = 0) {
   static std::mutex mu;
   static std::map<std::pair<int, const void*>, int> cache;
   int dev = 0;
@@ -1648,7 +1651,7 @@ int resident_grid(const void* kern, int cap) {
   if (it == cache.end()) {
     int per_cu = 0, cus = 0;
     int g = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kBlock, 0) == hipSuccess &&
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kBlock, lds) == hipSuccess &&
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
       g = per_cu * cus / kXcds * kXcds;
     it = cache.emplace(key, g).first;
@@ -1671,11 +1674,12 @@ int resident_grid(const void* kern, int cap) {
 // attached to the dispatch itself (their timestamps are the kernel's own begin and
 // end), so the elapsed time excludes the queue gap between kernels.
 template <class K>
-void launch_timed(K kern, int grid, hipStream_t s, hipEvent_t* ev, int k, const MsArgs& a) {
+void launch_timed(K kern, int grid, hipStream_t s, hipEvent_t* ev, int k, const MsArgs& a,
+                  size_t lds = 0) {
   if (ev)
-    hipExtLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), 0, s, ev[2 * k], ev[2 * k + 1], 0, a);
+    hipExtLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), lds, s, ev[2 * k], ev[2 * k + 1], 0, a);
   else
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), lds, s, a);
 }
 
 template <class R>
@@ -1732,9 +1736,13 @@ hipError_t iteration_impl(const MsArgs& args, hipStream_t s, hipEvent_t* ev, boo
   const int gsite = lr ? grid_rows((a.w64.vol + kSiteBlock - 1) / kSiteBlock, kBlock / kWave, a.grid)
                        : g3;
   int gh = lr ? gsite : g3, gk = gh;
+  // the complex64 K2 on the links takes unused dynamic LDS that leaves room for three of
+  // its workgroups per CU (three waves per SIMD instead of the four its registers allow):
+  // fewer waves in flight keep more of the neighbours in L2
+  const size_t k2lds = (lr && std::is_same<R, float>::value) ? kC64K2Lds : 0;
   if (a.sell && a.ord.on) {
     gh = resident_grid(reinterpret_cast<const void*>(head), gh);
-    if (a.kind == MSC_A_MHM) gk = resident_grid(reinterpret_cast<const void*>(k2s), gk);
+    if (a.kind == MSC_A_MHM) gk = resident_grid(reinterpret_cast<const void*>(k2s), gk, k2lds);
   }
   // workgroups of K1 and K2, whose partials K2 and the next head add up
   if (a.sell) {
@@ -1760,7 +1768,7 @@ hipError_t iteration_impl(const MsArgs& args, hipStream_t s, hipEvent_t* ev, boo
   }
   if (a.kind == MSC_A_MHM) {
     if (a.sell) {
-      launch_timed(k2s, gk, s, ev, 1, a);
+      launch_timed(k2s, gk, s, ev, 1, a, k2lds);
     } else {
       MSC_LANES_SWITCH(a.lanes, (launch_timed(k2_mhm<R, LL>, g1, s, ev, 1, a)));
     }
