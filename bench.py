@@ -45,18 +45,21 @@ KERNEL_NAMES = {("mixed", "head"): "k1_fused<float, true>",
                 ("fp64", "K2"): "k2_sell<double>"}
 # the same kernels on the matrix-free staggered operator (M and M^H from the links, one
 # lattice site per lane; two rows per SU(3) link; the FP64 head forms its product by the
-# recurrence t' = M r + b t in all but one launch in 64)
-KERNEL_NAMES_MF = {("mixed", "head"): "k1_site<float, 2, false>",
-                   ("mixed", "K2"): "k2_site<float, 2>",
-                   ("fp64", "head"): "k1_site<double, 2, true>",
-                   ("fp64", "K2"): "k2_site<double, 2>"}
+# recurrence t' = M r + b t in all but one launch in 64; K2 marches along t where the
+# lattice has enough blocks of 64 sites for it, as at 32^3x64, and not at 16^4): the
+# first name that the counter summary holds for the workload
+KERNEL_NAMES_MF = {("mixed", "head"): ("k1_site<float, 2, false>",),
+                   ("mixed", "K2"): ("k2_site<float, 2, true>", "k2_site<float, 2, false>"),
+                   ("fp64", "head"): ("k1_site<double, 2, true>",),
+                   ("fp64", "K2"): ("k2_site<double, 2, true>", "k2_site<double, 2, false>")}
 PHASE_NAMES = {"fp64": "FP64", "mixed": "complex64"}
 
 
 def measured_traffic(workload, prec, kernel, matrix_free=False):
     """(bytes per launch, kernel name) from the committed counter summary, or (None, name)."""
     import hashlib
-    name = (KERNEL_NAMES_MF if matrix_free else KERNEL_NAMES).get((prec, kernel))
+    names = KERNEL_NAMES_MF.get((prec, kernel)) if matrix_free else (KERNEL_NAMES.get((prec, kernel)),)
+    name = names[0] if names else None
     try:
         with open(TRAFFIC_FILE) as fh:
             data = json.load(fh)
@@ -66,7 +69,9 @@ def measured_traffic(workload, prec, kernel, matrix_free=False):
                 h.update(fh.read())
         if h.hexdigest() != data["kernel_source_sha256"]:
             return None, name
-        ent = data["workloads"][workload][name]
+        wl = data["workloads"][workload]
+        name = next((nm for nm in names if nm in wl), name)
+        ent = wl[name]
         return 1024.0 * (ent["fetch_kib"] * data["fetch_scale"]
                          + ent["write_kib"] * data["write_scale"]), name
     except (OSError, KeyError, ValueError):

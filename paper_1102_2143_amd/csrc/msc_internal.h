@@ -356,6 +356,7 @@ struct MsArgs {
   int stencil;           // the head and K2 apply M and M^H from links (kind MHM, sell = 1):
                          // 0 no, 3 full links, 2 two rows per link (w64 / w32 in that form)
   SweepOrder ord;        // slice order of the head and K2 on the sliced path
+  int k2_march;          // links: t-slices per column of K2's march (set per launch; 1: none)
   int t_rec;             // links, FP64: this head forms t' = M r + b t (the old t = M p)
   Stencil<double2> w64;
   Stencil<float2> w32;

@@ -161,6 +161,18 @@ __device__ __forceinline__ cplx<R> next_dir(double b, const cplx<R>& r, const cp
 // Dynamic LDS of the complex64 site K2 (bytes per workgroup, within the 64 KB a
 // workgroup may hold): three workgroups fit a CU's 160 KB, four do not.
 constexpr size_t kC64K2Lds = size_t(48) << 10;
+// most t-slices per column of K2's march along t
+#ifndef MSC_K2_MARCH
+#define MSC_K2_MARCH 16
+#endif
+constexpr int kK2March = MSC_K2_MARCH;
+// waves per SIMD the marching K2 is compiled for (FP64, complex64)
+#ifndef MSC_K2_MARCH_WPE64
+#define MSC_K2_MARCH_WPE64 2
+#endif
+#ifndef MSC_K2_MARCH_WPE32
+#define MSC_K2_MARCH_WPE32 2
+#endif
 
 // Pairs per round trip when each entry gathers two vectors (MSC_SELL_KPN32 / 64).
 #ifndef MSC_SELL_KPN32
@@ -1070,10 +1082,36 @@ __global__ __launch_bounds__(kBlock, MSC_SITE_HEAD_WPE) void k1_site(MsArgs a) {
   if (pl.spmv) store_partial(region(a, 0), acc);
 }
 
+// The march positions [beg, end) of this wave: its XCD's share of [0, n) (workgroups are
+// dealt to the XCDs in turn), split evenly and contiguously over the XCD's waves.
+__device__ __forceinline__ void march_range(int64_t n, int wpb, int64_t& beg, int64_t& end) {
+  const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x / kWave));
+  const int g = gridDim.x;
+  int64_t lo = 0, hi = n, nw = int64_t(g) * wpb, w = int64_t(blockIdx.x) * wpb + wv;
+  if (g % kXcds == 0) {
+    const int x = int(blockIdx.x % kXcds);
+    lo = n * x / kXcds;
+    hi = n * (x + 1) / kXcds;
+    nw = int64_t(g / kXcds) * wpb;
+    w = int64_t(blockIdx.x / kXcds) * wpb + wv;
+  }
+  beg = lo + (hi - lo) * w / nw;
+  end = lo + (hi - lo) * (w + 1) / nw;
+}
+
 // K2: q = M^H t = m t - D t for the block's sites, then r <- r - a (q + sigma0 p) and
 // R' = |r|^2 on their rows.
-template <class R, int LR>
-__global__ __launch_bounds__(kBlock, MSC_SITE_K2_WPE) void k2_site(MsArgs a) {
+// MARCH (a.k2_march = tc >= 2; the host checks that a t-slice holds whole blocks of 64
+// sites and that tc divides L_t): the blocks are taken in columns of tc consecutive
+// t-slices (march position q: column q / tc, slice q % tc of it; the columns of one
+// chunk of tc slices first), each wave a contiguous run of positions, so that within a
+// column a lane's next site is its last one moved one slice along t: its t link and its
+// values stay in registers (TCarry), and the XCD's waves work through the same few
+// slices together, where the other neighbours lie.
+template <class R, int LR, bool MARCH>
+__global__ __launch_bounds__(kBlock, MARCH ? (sizeof(R) == 8 ? MSC_K2_MARCH_WPE64
+                                                               : MSC_K2_MARCH_WPE32)
+                                            : MSC_SITE_K2_WPE) void k2_site(MsArgs a) {
   const SolveState* st = a.st;
   const RotState& ns = st->rot[a.par ^ 1];  // written by this iteration's head
   if (ns.halt) return;
@@ -1124,6 +1162,67 @@ __global__ __launch_bounds__(kBlock, MSC_SITE_K2_WPE) void k2_site(MsArgs a) {
       acc += norm2d<R>(st_r);
     }
   };
+  if constexpr (MARCH) {
+    // positions and blocks in 32 bits (the volume is below 2^31)
+    const uint32_t tc = uint32_t(a.k2_march);
+    const uint32_t bs = vol / uint32_t(w.L[3]) / uint32_t(kSiteBlock);  // blocks per t-slice
+    auto block_at = [&](uint32_t q) {
+      const uint32_t col = q / tc, chunk = col / bs;
+      return int64_t((chunk * tc + (q - col * tc)) * bs + (col - chunk * bs));
+    };
+    TCarry<R, LR> car;
+    const uint32_t vol3 = vol / uint32_t(w.L[3]);  // sites per t-slice
+    constexpr int K = 3 * LR;
+    // the carry for a block whose previous site along t this wave did not just take: the
+    // backward t link and the values at the backward t neighbour and at the site
+    auto preload = [&](int64_t blk) {
+      const uint32_t site = uint32_t(blk * kSiteBlock) + uint32_t(lane);
+      const uint32_t sb = site >= vol3 ? site - vol3 : site + (vol - vol3);  // periodic
+      const cplx<R>* __restrict__ wt = w.w + int64_t(3) * K * vol;
+#pragma unroll
+      for (int k = 0; k < K; ++k) car.u[k] = wt[int64_t(k) * vol + sb];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        car.own[c] = t[3 * int64_t(sb) + c];
+        car.fw[c] = t[3 * int64_t(site) + c];
+      }
+    };
+    auto product_c = [&](int64_t blk) {
+      const uint32_t site = uint32_t(blk * kSiteBlock) + uint32_t(lane);  // below vol
+      cplx<R> own[3];
+      Site o;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) own[c] = car.fw[c];
+      stencil_site_c<R, LR, true>(w, site, own, -1, [&](int64_t c) { return t[c]; }, o.q, &car);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) car.own[c] = own[c];
+      return o;
+    };
+    int64_t qb, qe;
+    march_range(nblk, WPB, qb, qe);
+    uint32_t q = uint32_t(qb);
+    const uint32_t qend = uint32_t(qe);
+    const bool has0 = q < qend;
+    const int64_t b0 = has0 ? block_at(q) : 0;
+    Site first{};
+    if (has0) {
+      preload(b0);
+      first = product_c(b0);
+    }
+    if (!k2_step(a, e, step)) return;  // breakdown: every workgroup sees the same P
+    if (has0) {
+      epilogue(b0, first);
+      // within a column the carry moves on; a new column starts from memory
+#pragma nounroll
+      for (++q; q < qend; ++q) {
+        const int64_t blk = block_at(q);
+        if (q % tc == 0) preload(blk);
+        epilogue(blk, product_c(blk));
+      }
+    }
+    store_partial(region(a, 1), acc);
+    return;
+  }
   // the first block's product runs while P's partials are on their way
   const bool has0 = sw.more();
   const int64_t b0 = has0 ? sw.slice() : 0;
@@ -1731,9 +1830,19 @@ hipError_t iteration_impl(const MsArgs& args, hipStream_t s, hipEvent_t* ev, boo
   auto head = lr == 3 ? (tr ? k1_site<R, 3, true> : k1_site<R, 3, false>)
               : lr == 2 ? (tr ? k1_site<R, 2, true> : k1_site<R, 2, false>)
                         : (a.kind == MSC_A_MHM ? k1_fused<R, true> : k1_fused<R, false>);
-  auto k2s = lr == 3 ? k2_site<R, 3> : lr == 2 ? k2_site<R, 2> : k2_sell<R>;
+  // K2 on two-row links marches along t (k2_site<.., true>) when it runs on the resident
+  // grid, a t-slice holds whole blocks of 64 sites, some tc >= 2 (at most kK2March)
+  // divides L_t and every wave gets a run of at least 4 blocks
+  const int64_t lt = a.w64.L[3], vol = a.w64.vol;
+  int tc = 1;
+  if (lr == 2 && a.ord.on && lt > 0 && (vol / lt) % kSiteBlock == 0)
+    for (int c = kK2March; c >= 2 && tc == 1; c /= 2)
+      if (lt % c == 0) tc = c;
+  auto k2s = lr == 3   ? k2_site<R, 3, false>
+             : lr == 2 ? (tc > 1 ? k2_site<R, 2, true> : k2_site<R, 2, false>)
+                       : k2_sell<R>;
   // the links' kernels take one block of 64 sites per wave pass
-  const int gsite = lr ? grid_rows((a.w64.vol + kSiteBlock - 1) / kSiteBlock, kBlock / kWave, a.grid)
+  const int gsite = lr ? grid_rows((vol + kSiteBlock - 1) / kSiteBlock, kBlock / kWave, a.grid)
                        : g3;
   int gh = lr ? gsite : g3, gk = gh;
   // the complex64 K2 on the links takes unused dynamic LDS that leaves room for three of
@@ -1744,6 +1853,13 @@ hipError_t iteration_impl(const MsArgs& args, hipStream_t s, hipEvent_t* ev, boo
     gh = resident_grid(reinterpret_cast<const void*>(head), gh);
     if (a.kind == MSC_A_MHM) gk = resident_grid(reinterpret_cast<const void*>(k2s), gk, k2lds);
   }
+  if (tc > 1 && (vol / kSiteBlock) < int64_t(gk) * (kBlock / kWave) * 4) {
+    // runs too short to carry much: the plain order
+    tc = 1;
+    k2s = k2_site<R, 2, false>;
+    gk = resident_grid(reinterpret_cast<const void*>(k2s), gsite, k2lds);
+  }
+  a.k2_march = tc;
   // workgroups of K1 and K2, whose partials K2 and the next head add up
   if (a.sell) {
     a.gk1 = gh;

@@ -53,14 +53,29 @@ __device__ __forceinline__ void third_row(cplx<R> (&u)[9], R te) {
   }
 }
 
+// What a wave marching along t (one site per lane, the next site one t-slice further on)
+// keeps from one site to the next: the stored entries of the site's t link, which are
+// the next site's backward t link, and the values at the site and at its forward t
+// neighbour, which are the next site's backward t neighbour and its own values.
+template <class R, int LR> struct TCarry {
+  cplx<R> u[3 * LR];
+  cplx<R> own[3];
+  cplx<R> fw[3];
+};
+
 // out[c] = m own[c] + sign (D v)_(3 s + c), c = 0, 1, 2, with v read through gather(row)
 // and own[c] = v at the site's own rows.  LR: link rows stored (3, or 2 for SU(3) links).
 // The sums run over mu = 0..3 and, within a direction, over the neighbour's colours j,
 // forward and backward terms apart, in that order.
-template <class R, int LR, class G>
-__device__ __forceinline__ void stencil_site(const Stencil<cplx<R>>& op, uint32_t s,
-                                             const cplx<R> (&own)[3], int sign, G gather,
-                                             cplx<R> (&out)[3]) {
+// CAR: car->u and car->own stand in for the backward t link and the backward t
+// neighbour's values, and must hold exactly those (the previous site's t link and values
+// when the site lies one t-slice past it, else loaded for the site); on return car->u
+// holds this site's t link and car->fw the forward t neighbour's values (car->own is the
+// caller's to set).  The arithmetic is the same either way.
+template <class R, int LR, bool CAR, class G>
+__device__ __forceinline__ void stencil_site_c(const Stencil<cplx<R>>& op, uint32_t s,
+                                               const cplx<R> (&own)[3], int sign, G gather,
+                                               cplx<R> (&out)[3], TCarry<R, LR>* car) {
   static_assert(LR == 2 || LR == 3, "link rows");
   constexpr int K = 3 * LR;
   // neighbours and the sign mask in 32 bits (the volume is below 2^31, checked at
@@ -89,15 +104,30 @@ __device__ __forceinline__ void stencil_site(const Stencil<cplx<R>>& op, uint32_
   for (int mu = 0; mu < 4; ++mu) {
     const cplx<R>* __restrict__ wm = op.w + int64_t(mu) * K * vol;
     cplx<R> U[9], B[9], gf[3], gb[3];
+    const bool kept = CAR && mu == 3;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       U[k] = wm[int64_t(k) * vol + s];
-      B[k] = wm[int64_t(k) * vol + bwd[mu]];
+      if (kept)
+        B[k] = car->u[k];
+      else
+        B[k] = wm[int64_t(k) * vol + bwd[mu]];
     }
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
       gf[j] = gather(3 * int64_t(fwd[mu]) + j);
-      gb[j] = gather(3 * int64_t(bwd[mu]) + j);
+      if (kept)
+        gb[j] = car->own[j];
+      else
+        gb[j] = gather(3 * int64_t(bwd[mu]) + j);
+    }
+    if constexpr (CAR) {
+      if (mu == 3) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) car->u[k] = U[k];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) car->fw[j] = gf[j];
+      }
     }
     if constexpr (LR == 2) {
       const R te = ((neg >> mu) & 1u) ? R(-2) : R(2);
@@ -120,6 +150,14 @@ __device__ __forceinline__ void stencil_site(const Stencil<cplx<R>>& op, uint32_
     out[c].x = sign > 0 ? fma(m, own[c].x, h.x) : fma(m, own[c].x, -h.x);
     out[c].y = sign > 0 ? fma(m, own[c].y, h.y) : fma(m, own[c].y, -h.y);
   }
+}
+
+template <class R, int LR, class G>
+__device__ __forceinline__ void stencil_site(const Stencil<cplx<R>>& op, uint32_t s,
+                                             const cplx<R> (&own)[3], int sign, G gather,
+                                             cplx<R> (&out)[3]) {
+  stencil_site_c<R, LR, false>(op, s, own, sign, gather, out,
+                               static_cast<TCarry<R, LR>*>(nullptr));
 }
 
 }  // namespace msc

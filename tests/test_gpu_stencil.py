@@ -17,7 +17,9 @@ stored matrix), while the library also builds the equivalent CSR for its other k
 * the misuse cases are rejected;
 * the site kernels on lattices whose volume leaves a partial block of 64 sites, on one
   whose blocks follow the lattice order, and with nine-value links in both phases of a
-  mixed solve, against the oracle.
+  mixed solve, against the oracle;
+* K2 marching along t (columns of 16 or 8 t-slices, runs that start inside a column and
+  columns shared by several waves) against the oracle.
 """
 import numpy as np
 import pytest
@@ -248,5 +250,39 @@ def test_nine_value_links_in_the_mixed_solve(cuda, dims):
     x, info = op.solve(b, tol=1e-12, prec="mixed")
     ref = O.cg_m(O.shifted_apply("mhm", rowptr, col, vals, n), b, sigma, tol=1e-13)
     assert info["status"] == "ok" and np.all(info["true_rel_res"] <= 1e-12)
+    assert np.all(_rel(x.cpu().numpy(), ref["x"]) <= 1e-8)
+    op.close()
+
+
+@pytest.mark.parametrize("dims,grid", [((8, 8, 8, 32), 16), ((8, 8, 8, 24), 8)])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_k2_march_along_t(cuda, dims, grid, prec):
+    # with the grid capped at 16 (8) workgroups, 256 (192) blocks of 64 sites give every
+    # wave a run of 4 (6) blocks in columns of 16 (8) t-slices, the largest power of two
+    # up to 16 that divides L_t: runs start inside columns and cross into the next one.
+    # FP64 at tol 1e-10 against the oracle CG-M (per shift <= 1e-8, iterations within 2),
+    # mixed at 1e-12 against the oracle at 1e-13
+    from paper_1102_2143_amd import Operator
+    print(f"[gpu] stencil K2 march dims={dims} grid={grid} {prec}", flush=True)
+    mass = 0.1
+    links = W.random_su3_links(dims, 81)
+    rowptr, col, vals = W.staggered_csr(links, dims, mass)
+    n = 3 * W.lattice_volume(dims)
+    sigma = W.logspace_shifts(1e-4, 1.0, 6)
+    b = W.gaussian_rhs(n, 82)
+    ap = O.shifted_apply("mhm", rowptr, col, vals, n)
+    op = Operator.staggered(links, dims, mass, device=cuda)
+    assert op.storage()["two_rows"] is True
+    op.set_shifts(sigma)
+    if prec == "fp64":
+        ref = O.cg_m(ap, b, sigma, tol=1e-10)
+        x, info = op.solve(b, tol=1e-10, prec="fp64", max_grid=grid)
+        assert abs(info["iters"] - ref["iters"]) <= 2
+        assert np.all(info["true_rel_res"] <= 1e-10)
+    else:
+        ref = O.cg_m(ap, b, sigma, tol=1e-13)
+        x, info = op.solve(b, tol=1e-12, prec="mixed", max_grid=grid)
+        assert np.all(info["true_rel_res"] <= 1e-12)
+    assert info["status"] == "ok"
     assert np.all(_rel(x.cpu().numpy(), ref["x"]) <= 1e-8)
     op.close()
