@@ -18,8 +18,9 @@ stored matrix), while the library also builds the equivalent CSR for its other k
 * the site kernels on lattices whose volume leaves a partial block of 64 sites, on one
   whose blocks follow the lattice order, and with nine-value links in both phases of a
   mixed solve, against the oracle;
-* K2 marching along t (columns of 16 or 8 t-slices, runs that start inside a column and
-  columns shared by several waves) against the oracle.
+* K2 marching along t (columns of 16, 8 or 4 t-slices, runs that start inside a column,
+  columns shared by several waves, grids with and without the per-XCD split) against the
+  oracle.
 """
 import numpy as np
 import pytest
@@ -254,12 +255,15 @@ def test_nine_value_links_in_the_mixed_solve(cuda, dims):
     op.close()
 
 
-@pytest.mark.parametrize("dims,grid", [((8, 8, 8, 32), 16), ((8, 8, 8, 24), 8)])
+@pytest.mark.parametrize("dims,grid", [((8, 8, 8, 32), 16), ((8, 8, 8, 24), 8),
+                                       ((8, 8, 16, 12), 12)])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_k2_march_along_t(cuda, dims, grid, prec):
-    # with the grid capped at 16 (8) workgroups, 256 (192) blocks of 64 sites give every
-    # wave a run of 4 (6) blocks in columns of 16 (8) t-slices, the largest power of two
-    # up to 16 that divides L_t: runs start inside columns and cross into the next one.
+    # with the grid capped at 16 (8, 12) workgroups, 256 (192, 192) blocks of 64 sites give
+    # every wave a run of 4 (6, 4) blocks in columns of 16 (8, 4) t-slices, the largest
+    # power of two up to 16 that divides L_t: runs start inside columns and cross into the
+    # next one; 12 workgroups are not a multiple of the 8 XCDs, so the runs are dealt
+    # without the per-XCD split.
     # FP64 at tol 1e-10 against the oracle CG-M (per shift <= 1e-8, iterations within 2),
     # mixed at 1e-12 against the oracle at 1e-13
     from paper_1102_2143_amd import Operator
