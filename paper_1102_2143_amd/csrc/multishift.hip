@@ -166,6 +166,10 @@ constexpr size_t kC64K2Lds = size_t(48) << 10;
 #define MSC_K2_MARCH 16
 #endif
 constexpr int kK2March = MSC_K2_MARCH;
+#ifndef MSC_HEAD_MARCH
+#define MSC_HEAD_MARCH 1
+#endif
+constexpr bool kHeadMarch = MSC_HEAD_MARCH != 0;
 // waves per SIMD the marching K2 is compiled for (FP64, complex64)
 #ifndef MSC_K2_MARCH_WPE64
 #define MSC_K2_MARCH_WPE64 2
@@ -986,6 +990,23 @@ __global__ __launch_bounds__(kBlock) void k2_sell(MsArgs a) {
   store_partial(region(a, 1), acc);
 }
 
+// The march positions [beg, end) of this wave: its XCD's share of [0, n) (workgroups are
+// dealt to the XCDs in turn), split evenly and contiguously over the XCD's waves.
+__device__ __forceinline__ void march_range(int64_t n, int wpb, int64_t& beg, int64_t& end) {
+  const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x / kWave));
+  const int g = gridDim.x;
+  int64_t lo = 0, hi = n, nw = int64_t(g) * wpb, w = int64_t(blockIdx.x) * wpb + wv;
+  if (g % kXcds == 0) {
+    const int x = int(blockIdx.x % kXcds);
+    lo = n * x / kXcds;
+    hi = n * (x + 1) / kXcds;
+    nw = int64_t(g / kXcds) * wpb;
+    w = int64_t(blockIdx.x / kXcds) * wpb + wv;
+  }
+  beg = lo + (hi - lo) * w / nw;
+  end = lo + (hi - lo) * (w + 1) / nw;
+}
+
 // ---- matrix-free head and K2: one lattice site (three rows) per lane ------------------
 // The waves sweep blocks of 64 sites (192 rows).  The head first applies the pending
 // update to the block's rows, one row per lane in three passes (the same update_row as on
@@ -1002,8 +1023,12 @@ __global__ __launch_bounds__(kBlock) void k2_sell(MsArgs a) {
 // hints a line could leave the cache between the three.
 constexpr int kSiteBlock = kWave;  // sites per wave pass
 
-template <class R, int LR, bool TR>
+// MARCH (complex64, two-row links, TR = false; a.head_march = tc >= 2): K2's column order
+// along t, with the t link and the formed directions p' at the site and at its forward
+// t neighbour carried from one site of a column to the next (TCarry).
+template <class R, int LR, bool TR, bool MARCH = false>
 __global__ __launch_bounds__(kBlock, MSC_SITE_HEAD_WPE) void k1_site(MsArgs a) {
+  static_assert(!MARCH || (LR == 2 && !TR), "the head marches on two-row links without TR");
   const SolveState* st = a.st;
   const RotState& rs = st->rot[a.par];
   if (rs.halt) {
@@ -1032,6 +1057,59 @@ __global__ __launch_bounds__(kBlock, MSC_SITE_HEAD_WPE) void k1_site(MsArgs a) {
   const bool upd = pl.pending != 0;
   const double bn = pl.bn;
   double acc = 0.0;
+  if constexpr (MARCH) {
+    const uint32_t tc = uint32_t(a.head_march);
+    const uint32_t vol3 = vol / uint32_t(w.L[3]);  // sites per t-slice
+    const uint32_t bs = vol3 / uint32_t(kSiteBlock);
+    constexpr int K = 3 * LR;
+    const cplx<R>* __restrict__ rg = upd ? rv : pv;
+    // p' at row i (without a pending update bn = 0 and p' = p exactly)
+    auto nd = [&](int64_t i) { return next_dir<R>(bn, rg[i], pv[i]); };
+    TCarry<R, LR> car;
+    int64_t qb, qe;
+    march_range(nblk, WPB, qb, qe);
+    for (uint32_t q = uint32_t(qb); q < uint32_t(qe); ++q) {
+      const uint32_t col = q / tc, chunk = col / bs;
+      const int64_t blk = int64_t((chunk * tc + (q - col * tc)) * bs + (col - chunk * bs));
+      if (upd) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          const int64_t row = (3 * blk + k) * kWave + lane;
+          update_row<R>(a, pl, row, rv[row], pv[row], x0, pnew);  // below n
+        }
+      }
+#if MSC_SITE_SB
+      __builtin_amdgcn_sched_barrier(0);
+#endif
+      if (!pl.spmv) continue;
+      const uint32_t site = uint32_t(blk * kSiteBlock) + uint32_t(lane);  // below vol
+      if (q == uint32_t(qb) || q % tc == 0) {
+        // a run's first site or a column's: the carry from memory
+        const uint32_t sb = site >= vol3 ? site - vol3 : site + (vol - vol3);  // periodic
+        const cplx<R>* __restrict__ wt = w.w + int64_t(3) * K * vol;
+#pragma unroll
+        for (int k = 0; k < K; ++k) car.u[k] = wt[int64_t(k) * vol + sb];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          car.own[c] = nd(3 * int64_t(sb) + c);
+          car.fw[c] = nd(3 * int64_t(site) + c);
+        }
+      }
+      const int64_t r0 = 3 * int64_t(site);
+      cplx<R> pr[3], v[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) pr[c] = car.fw[c];
+      stencil_site_c<R, LR, true>(w, site, pr, 1, nd, v, &car);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        car.own[c] = pr[c];
+        t[r0 + c] = v[c];
+        acc += norm2d<R>(v[c]) + sigma0 * norm2d<R>(pr[c]);
+      }
+    }
+    if (pl.spmv) store_partial(region(a, 0), acc);
+    return;
+  }
   for (; sw.more(); sw.next()) {
     const int64_t blk = sw.slice();
     if (upd) {
@@ -1080,23 +1158,6 @@ __global__ __launch_bounds__(kBlock, MSC_SITE_HEAD_WPE) void k1_site(MsArgs a) {
     }
   }
   if (pl.spmv) store_partial(region(a, 0), acc);
-}
-
-// The march positions [beg, end) of this wave: its XCD's share of [0, n) (workgroups are
-// dealt to the XCDs in turn), split evenly and contiguously over the XCD's waves.
-__device__ __forceinline__ void march_range(int64_t n, int wpb, int64_t& beg, int64_t& end) {
-  const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x / kWave));
-  const int g = gridDim.x;
-  int64_t lo = 0, hi = n, nw = int64_t(g) * wpb, w = int64_t(blockIdx.x) * wpb + wv;
-  if (g % kXcds == 0) {
-    const int x = int(blockIdx.x % kXcds);
-    lo = n * x / kXcds;
-    hi = n * (x + 1) / kXcds;
-    nw = int64_t(g / kXcds) * wpb;
-    w = int64_t(blockIdx.x / kXcds) * wpb + wv;
-  }
-  beg = lo + (hi - lo) * w / nw;
-  end = lo + (hi - lo) * (w + 1) / nw;
 }
 
 // K2: q = M^H t = m t - D t for the block's sites, then r <- r - a (q + sigma0 p) and
@@ -1838,6 +1899,7 @@ hipError_t iteration_impl(const MsArgs& args, hipStream_t s, hipEvent_t* ev, boo
   if (lr == 2 && a.ord.on && lt > 0 && (vol / lt) % kSiteBlock == 0)
     for (int c = kK2March; c >= 2 && tc == 1; c /= 2)
       if (lt % c == 0) tc = c;
+  const int tc_lattice = tc;
   auto k2s = lr == 3   ? k2_site<R, 3, false>
              : lr == 2 ? (tc > 1 ? k2_site<R, 2, true> : k2_site<R, 2, false>)
                        : k2_sell<R>;
@@ -1860,6 +1922,20 @@ hipError_t iteration_impl(const MsArgs& args, hipStream_t s, hipEvent_t* ev, boo
     gk = resident_grid(reinterpret_cast<const void*>(k2s), gsite, k2lds);
   }
   a.k2_march = tc;
+  // the complex64 head on two-row links marches with K2's columns when every resident
+  // wave gets a run of at least 4 blocks
+  a.head_march = 1;
+  if constexpr (std::is_same<R, float>::value) {
+    if (kHeadMarch && lr == 2 && tc_lattice > 1) {
+      auto hm = k1_site<R, 2, false, true>;
+      const int gm = resident_grid(reinterpret_cast<const void*>(hm), gsite);
+      if (vol / kSiteBlock >= int64_t(gm) * (kBlock / kWave) * 4) {
+        head = hm;
+        gh = gm;
+        a.head_march = tc_lattice;
+      }
+    }
+  }
   // workgroups of K1 and K2, whose partials K2 and the next head add up
   if (a.sell) {
     a.gk1 = gh;
