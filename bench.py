@@ -45,13 +45,14 @@ KERNEL_NAMES = {("mixed", "head"): "k1_fused<float, true>",
                 ("fp64", "K2"): "k2_sell<double>"}
 # the same kernels on the matrix-free staggered operator (M and M^H from the links, one
 # lattice site per lane; two rows per SU(3) link; the FP64 head forms its product by the
-# recurrence t' = M r + b t in all but one launch in 64; K2 and the complex64 head march
-# along t where the lattice has enough blocks of 64 sites for it, as at 32^3x64, and not
-# at 16^4): the first name that the counter summary holds for the workload
+# recurrence t' = M r + b t in all but one launch in 64; K2 and the heads march along t
+# where the lattice has enough blocks of 64 sites for it, as at 32^3x64, and not at
+# 16^4): the first name that the counter summary holds for the workload
 KERNEL_NAMES_MF = {("mixed", "head"): ("k1_site<float, 2, false, true>",
                                        "k1_site<float, 2, false, false>"),
                    ("mixed", "K2"): ("k2_site<float, 2, true>", "k2_site<float, 2, false>"),
-                   ("fp64", "head"): ("k1_site<double, 2, true, false>",),
+                   ("fp64", "head"): ("k1_site<double, 2, true, true>",
+                                      "k1_site<double, 2, true, false>"),
                    ("fp64", "K2"): ("k2_site<double, 2, true>", "k2_site<double, 2, false>")}
 PHASE_NAMES = {"fp64": "FP64", "mixed": "complex64"}
 

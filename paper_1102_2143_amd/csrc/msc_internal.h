@@ -357,7 +357,7 @@ struct MsArgs {
                          // 0 no, 3 full links, 2 two rows per link (w64 / w32 in that form)
   SweepOrder ord;        // slice order of the head and K2 on the sliced path
   int k2_march;          // links: t-slices per column of K2's march (set per launch; 1: none)
-  int head_march;        // links: the same for the complex64 head (1: the sweep order)
+  int head_march;        // links: the same for the head (1: the sweep order)
   int t_rec;             // links, FP64: this head forms t' = M r + b t (the old t = M p)
   Stencil<double2> w64;
   Stencil<float2> w32;

@@ -1023,12 +1023,12 @@ __device__ __forceinline__ void march_range(int64_t n, int wpb, int64_t& beg, in
 // hints a line could leave the cache between the three.
 constexpr int kSiteBlock = kWave;  // sites per wave pass
 
-// MARCH (complex64, two-row links, TR = false; a.head_march = tc >= 2): K2's column order
-// along t, with the t link and the formed directions p' at the site and at its forward
-// t neighbour carried from one site of a column to the next (TCarry).
+// MARCH (two-row links; a.head_march = tc >= 2): K2's column order along t, with the t
+// link and the gathered values (p', or r with TR) at the site and at its forward t
+// neighbour carried from one site of a column to the next (TCarry).
 template <class R, int LR, bool TR, bool MARCH = false>
 __global__ __launch_bounds__(kBlock, MSC_SITE_HEAD_WPE) void k1_site(MsArgs a) {
-  static_assert(!MARCH || (LR == 2 && !TR), "the head marches on two-row links without TR");
+  static_assert(!MARCH || LR == 2, "the head marches on two-row links");
   const SolveState* st = a.st;
   const RotState& rs = st->rot[a.par];
   if (rs.halt) {
@@ -1063,8 +1063,14 @@ __global__ __launch_bounds__(kBlock, MSC_SITE_HEAD_WPE) void k1_site(MsArgs a) {
     const uint32_t bs = vol3 / uint32_t(kSiteBlock);
     constexpr int K = 3 * LR;
     const cplx<R>* __restrict__ rg = upd ? rv : pv;
-    // p' at row i (without a pending update bn = 0 and p' = p exactly)
-    auto nd = [&](int64_t i) { return next_dir<R>(bn, rg[i], pv[i]); };
+    // the gathered vector at row i: r with TR (p without a pending update), else p'
+    // (without a pending update bn = 0 and p' = p exactly)
+    auto gv = [&](int64_t i) {
+      if constexpr (TR)
+        return rg[i];
+      else
+        return next_dir<R>(bn, rg[i], pv[i]);
+    };
     TCarry<R, LR> car;
     int64_t qb, qe;
     march_range(nblk, WPB, qb, qe);
@@ -1091,18 +1097,27 @@ __global__ __launch_bounds__(kBlock, MSC_SITE_HEAD_WPE) void k1_site(MsArgs a) {
         for (int k = 0; k < K; ++k) car.u[k] = wt[int64_t(k) * vol + sb];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          car.own[c] = nd(3 * int64_t(sb) + c);
-          car.fw[c] = nd(3 * int64_t(site) + c);
+          car.own[c] = gv(3 * int64_t(sb) + c);
+          car.fw[c] = gv(3 * int64_t(site) + c);
         }
       }
       const int64_t r0 = 3 * int64_t(site);
-      cplx<R> pr[3], v[3];
-#pragma unroll
-      for (int c = 0; c < 3; ++c) pr[c] = car.fw[c];
-      stencil_site_c<R, LR, true>(w, site, pr, 1, nd, v, &car);
+      cplx<R> own[3], pr[3], v[3];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        car.own[c] = pr[c];
+        own[c] = car.fw[c];
+        // p' at the site: with TR own is r (p without a pending update), else p' itself
+        pr[c] = (TR && upd) ? next_dir<R>(bn, own[c], pv[r0 + c]) : own[c];
+      }
+      stencil_site_c<R, LR, true>(w, site, own, 1, gv, v, &car);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        car.own[c] = own[c];
+        if constexpr (TR) {
+          const cplx<R> told = t[r0 + c];
+          v[c].x = fma(bn, told.x, v[c].x);
+          v[c].y = fma(bn, told.y, v[c].y);
+        }
         t[r0 + c] = v[c];
         acc += norm2d<R>(v[c]) + sigma0 * norm2d<R>(pr[c]);
       }
@@ -1922,12 +1937,17 @@ hipError_t iteration_impl(const MsArgs& args, hipStream_t s, hipEvent_t* ev, boo
     gk = resident_grid(reinterpret_cast<const void*>(k2s), gsite, k2lds);
   }
   a.k2_march = tc;
-  // the complex64 head on two-row links marches with K2's columns when every resident
-  // wave gets a run of at least 4 blocks
+  // the heads on two-row links march with K2's columns (FP64: the recurrence's heads; the
+  // direct products keep the sweep order) when every resident wave gets a run of at
+  // least 4 blocks
   a.head_march = 1;
-  if constexpr (std::is_same<R, float>::value) {
-    if (kHeadMarch && lr == 2 && tc_lattice > 1) {
-      auto hm = k1_site<R, 2, false, true>;
+  if (kHeadMarch && lr == 2 && tc_lattice > 1) {
+    decltype(head) hm = nullptr;
+    if constexpr (std::is_same<R, float>::value)
+      hm = k1_site<R, 2, false, true>;
+    else if (tr)
+      hm = k1_site<R, 2, true, true>;
+    if (hm) {
       const int gm = resident_grid(reinterpret_cast<const void*>(hm), gsite);
       if (vol / kSiteBlock >= int64_t(gm) * (kBlock / kWave) * 4) {
         head = hm;

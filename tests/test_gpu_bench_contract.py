@@ -39,6 +39,7 @@ def test_bench_line_keeps_the_contract(cuda):
     assert st["mixed"]["converged"] is True and st["fp64"]["converged"] is True
     assert st["mixed"]["max_true_rel_res"] <= 1e-10
     assert d["roofline"]["kernel_name"] in ("k1_site<double, 2, true, false>",
+                                            "k1_site<double, 2, true, true>",
                                             "k2_site<double, 2, true>", "k2_site<double, 2, false>",
                                             "k1_site<float, 2, false, true>",
                                             "k1_site<float, 2, false, false>",
