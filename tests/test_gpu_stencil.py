@@ -18,9 +18,10 @@ stored matrix), while the library also builds the equivalent CSR for its other k
 * the site kernels on lattices whose volume leaves a partial block of 64 sites, on one
   whose blocks follow the lattice order, and with nine-value links in both phases of a
   mixed solve, against the oracle;
-* K2 marching along t (columns of 16, 8 or 4 t-slices, runs that start inside a column,
-  columns shared by several waves, grids with and without the per-XCD split) against the
-  oracle.
+* the heads and K2 marching along t (columns of 16, 8 or 4 t-slices, runs that start
+  inside a column, columns shared by several waves, grids with and without the per-XCD
+  split; the FP64 head with its recurrence t' = M r + b t, the complex64 head gathering
+  p') against the oracle.
 """
 import numpy as np
 import pytest
@@ -258,7 +259,7 @@ def test_nine_value_links_in_the_mixed_solve(cuda, dims):
 @pytest.mark.parametrize("dims,grid", [((8, 8, 8, 32), 16), ((8, 8, 8, 24), 8),
                                        ((8, 8, 16, 12), 12)])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_k2_march_along_t(cuda, dims, grid, prec):
+def test_march_along_t(cuda, dims, grid, prec):
     # with the grid capped at 16 (8, 12) workgroups, 256 (192, 192) blocks of 64 sites give
     # every wave a run of 4 (6, 4) blocks in columns of 16 (8, 4) t-slices, the largest
     # power of two up to 16 that divides L_t: runs start inside columns and cross into the
@@ -267,7 +268,8 @@ def test_k2_march_along_t(cuda, dims, grid, prec):
     # FP64 at tol 1e-10 against the oracle CG-M (per shift <= 1e-8, iterations within 2),
     # mixed at 1e-12 against the oracle at 1e-13
     from paper_1102_2143_amd import Operator
-    print(f"[gpu] stencil K2 march dims={dims} grid={grid} {prec}", flush=True)
+    # the heads take the same columns (the grid caps them alike)
+    print(f"[gpu] stencil march dims={dims} grid={grid} {prec}", flush=True)
     mass = 0.1
     links = W.random_su3_links(dims, 81)
     rowptr, col, vals = W.staggered_csr(links, dims, mass)
